@@ -1,0 +1,23 @@
+import os
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def pytest_configure(config):
+    config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
+    config.addinivalue_line("markers", "slow: large CPU-side case")
+
+
+@pytest.fixture(scope="session", autouse=True)
+def _built_host_libs():
+    """Build the CPU oracle and the input generators if they are missing."""
+    import gen
+    import oracle
+    gen.build(force=False)
+    oracle.build(force=False)
+    yield
