@@ -1,0 +1,218 @@
+/*
+ * ppsp.h - C interface of the MI355X (gfx950) point-to-point shortest-path
+ * library.
+ *
+ * The library answers exact s-t shortest-path distance queries on a graph
+ * with non-negative integer arc weights, single or batched, with the
+ * parallel point-to-point framework of "Parallel Point-to-Point Shortest
+ * Paths and Batch Queries" (SPAA 2025):
+ *   - Algorithm 2 (the PPSP framework built on the stepping framework of
+ *     Algorithm 1), with the Init / Prune / UpdateDistance rules of Table 2:
+ *     early termination (Section 3.2), A* (Section 3.3), bidirectional search
+ *     (Section 3.4, Theorem bids-correctness) and bidirectional A*
+ *     (Section 3.5, Theorem bdastar-correctness);
+ *   - Delta*-stepping thresholds (Section 2: the i-th threshold is i*Delta);
+ *   - batch queries through the query graph (Section 4.1) and the Plain,
+ *     Plain* and Multi-BiDS strategies (Section 4.2).
+ * Every mode computes exact distances; the threshold schedule only decides
+ * the order of work.
+ *
+ * Conventions for every function:
+ *   - The return value is a status: PPSP_OK (0) or a negative PPSP_E_* code.
+ *     On error, caller-owned outputs are left untouched unless stated.
+ *   - Host pointers are owned by the caller and are only read (or written, for
+ *     outputs) during the call. Device memory is owned by the library and is
+ *     released by ppsp_graph_destroy.
+ *   - `hip_stream` is a hipStream_t (NULL = the default stream). Work is
+ *     ordered on that stream; functions with host outputs synchronise it
+ *     before returning.
+ *   - A graph handle is not thread-safe: calls on one handle must not
+ *     overlap.
+ *   - Distances are uint64; PPSP_INF marks an unreachable target. Internally
+ *     distances are 32-bit: a distance that would reach 2^32-1 returns
+ *     PPSP_E_OVERFLOW instead of a wrong value.
+ */
+#ifndef PPSP_H
+#define PPSP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PPSP_INF UINT64_MAX
+
+/* Status codes. */
+enum {
+    PPSP_OK = 0,
+    PPSP_E_INVALID = -1,   /* null pointer, bad enum value, bad size, inconsistent CSR */
+    PPSP_E_RANGE = -2,     /* a vertex id >= n, m >= 2^32, or coordinates too far apart */
+    PPSP_E_OOM = -3,       /* device memory (or the search-state budget) is exhausted */
+    PPSP_E_OVERFLOW = -4,  /* a tentative distance reached 2^32-1 */
+    PPSP_E_NOCOORD = -5,   /* A* mode on a graph without consistent coordinates */
+    PPSP_E_NOTSYM = -6,    /* a bidirectional or batch mode on a graph not flagged symmetric */
+    PPSP_E_DEVICE = -7,    /* a HIP runtime error */
+    PPSP_E_BUSY = -8,      /* (serving) the request has not finished */
+    PPSP_E_PATHCAP = -9,   /* the caller's path buffer is too small; *path_len gets the need */
+    PPSP_E_NOPATH = -10,   /* paths were requested on a graph with a zero-weight arc */
+    PPSP_E_TIMEOUT = -11   /* the round loop ran longer than the "timeout_ms" option */
+};
+
+/* Search algorithm: the rows of Table 2 plus plain single-source search. */
+enum ppsp_algo {
+    PPSP_SSSP = 0,      /* Delta*-stepping from s without pruning; reports d(s,t) */
+    PPSP_ET = 1,        /* early termination: prune delta[v] >= mu (Section 3.2) */
+    PPSP_ASTAR = 2,     /* A*: prune delta[v] + h_t(v) >= mu (Section 3.3) */
+    PPSP_BIDS = 3,      /* bidirectional: prune 2*delta >= mu (Section 3.4) */
+    PPSP_BIDASTAR = 4   /* bidirectional A*: prune 2*delta +/- (h_t - h_s) >= mu (Section 3.5) */
+};
+
+/* Batch strategy (Section 4.2). */
+enum ppsp_batch {
+    PPSP_BATCH_PLAIN = 0,      /* one query after another */
+    PPSP_BATCH_PLAINSTAR = 1,  /* all queries at once, each with its own searches */
+    PPSP_BATCH_MULTI = 2       /* one search per query-graph vertex, shared (Multi-BiDS) */
+};
+
+/* Threshold schedule. */
+enum ppsp_sched {
+    PPSP_SCHED_FIXED = 0,      /* Delta*-stepping with opts.delta (0: graph default) */
+    PPSP_SCHED_AUTOTUNED = 1,  /* the Delta and launch shape chosen by ppsp_tune */
+    PPSP_SCHED_LEARNED = 2     /* per-round Delta multiplier chosen by the loaded MLP */
+};
+
+/* ppsp_graph_create flags. */
+#define PPSP_SYMMETRIC 1u      /* every arc (u,v,w) has a reverse arc (v,u,w) */
+
+/* ppsp_opts.flags. */
+#define PPSP_WANT_PATH 1u      /* also return an s->t vertex path per query */
+#define PPSP_MEMO_H 2u         /* memoise the heuristic per vertex (Section 5) */
+
+typedef struct {
+    uint32_t algo;     /* enum ppsp_algo */
+    uint32_t batch;    /* enum ppsp_batch (ignored by ppsp_query) */
+    uint32_t sched;    /* enum ppsp_sched */
+    uint32_t flags;    /* PPSP_WANT_PATH | PPSP_MEMO_H */
+    uint64_t delta;    /* Delta in distance units for PPSP_SCHED_FIXED; 0 = graph default */
+} ppsp_opts;
+
+/* Counters of the last query or batch on a graph. */
+typedef struct {
+    uint64_t rounds;           /* stepping rounds (threshold steps) executed */
+    uint64_t entries;          /* frontier entries processed (incl. pruned and carried) */
+    uint64_t scanned_vertices; /* extracted, unpruned search-vertices whose arcs were relaxed */
+    uint64_t scanned_arcs;     /* arcs relaxed */
+    uint64_t relax_success;    /* successful write_min operations */
+    uint64_t searches;         /* searches (frontier copies) in the batch */
+    uint64_t waves;            /* memory waves the batch was split into */
+    double wall_ms;            /* host wall time of the call */
+    double relax_kernel_ms;    /* summed duration of the round kernel (profiling on), else 0 */
+    uint64_t relax_launches;   /* number of round-kernel launches */
+} ppsp_stats;
+
+typedef struct ppsp_graph_s *ppsp_graph;
+
+/*
+ * Uploads a CSR graph (Section 2 notation: G = (V, E, w), N(v) = the arcs of
+ * v) to device `device` and returns a handle.
+ *   n          number of vertices (ids 0..n-1)
+ *   m          number of arcs; must be < 2^32
+ *   row_ptr    host, n+1 entries, nondecreasing, row_ptr[0] = 0, row_ptr[n] = m
+ *   col, w     host, m entries: arc e goes from its row's vertex to col[e] with
+ *              weight w[e] (non-negative integer)
+ *   coord_fx   host, 2n int32 fixed-point coordinates (x0,y0,x1,y1,...) with
+ *              coord_frac_bits fractional bits, or NULL. They define the
+ *              heuristic h_t(v) = floor(w_scale * |p_v - p_t|) used by A* and
+ *              bidirectional A* (Sections 3.3, 3.5). The heuristic is consistent
+ *              iff every arc satisfies w >= w_scale * |p_u - p_v|; this is checked
+ *              here exactly in integers, and A* modes return PPSP_E_NOCOORD on a
+ *              graph where it fails.
+ *   flags      PPSP_SYMMETRIC if the graph is undirected (required by the
+ *              bidirectional and batch modes, whose theorems assume it)
+ *   out        receives the handle
+ * Errors: PPSP_E_INVALID (bad CSR), PPSP_E_RANGE (col >= n, m too large,
+ * coordinate span too large for exact 64-bit arithmetic), PPSP_E_OOM,
+ * PPSP_E_DEVICE.
+ */
+int ppsp_graph_create(int device, uint32_t n, uint64_t m, const uint64_t *row_ptr,
+                      const uint32_t *col, const uint32_t *w, const int32_t *coord_fx,
+                      uint32_t coord_frac_bits, uint32_t w_scale, uint32_t flags,
+                      void *hip_stream, ppsp_graph *out);
+
+/* Releases all device memory of the graph. NULL is accepted. */
+int ppsp_graph_destroy(ppsp_graph g);
+
+/*
+ * One s-t query (Algorithm 2 with the Table 2 row named by opts->algo).
+ *   dist      host, 1 entry: d(s,t), 0 if s = t, PPSP_INF if unreachable
+ *             (the disconnected-query rule of Appendix B)
+ *   path      host buffer of path_cap vertex ids, or NULL; filled with an
+ *             s->t shortest path (s first, t last) when opts->flags has
+ *             PPSP_WANT_PATH; *path_len gets its length (0 if unreachable)
+ * Errors: PPSP_E_RANGE (s or t >= n), PPSP_E_NOCOORD, PPSP_E_NOTSYM,
+ * PPSP_E_OVERFLOW, PPSP_E_PATHCAP (path_cap too small; *path_len = need),
+ * PPSP_E_NOPATH, PPSP_E_OOM, PPSP_E_DEVICE.
+ */
+int ppsp_query(ppsp_graph g, uint32_t s, uint32_t t, const ppsp_opts *opts, void *hip_stream,
+               uint64_t *dist, uint32_t *path, uint32_t path_cap, uint32_t *path_len);
+
+/*
+ * A batch of k queries (Section 4): pairs[2q] = s_q, pairs[2q+1] = t_q (host).
+ * Duplicate pairs, (t,s) mirrors and s = t are allowed.
+ *   dist      host, k entries, in input order
+ *   path_off  host, k+1 entries or NULL: with PPSP_WANT_PATH, the path of query
+ *             q is path_vtx[path_off[q] .. path_off[q+1])
+ *   path_vtx  host buffer of path_cap vertex ids, or NULL
+ * opts->batch selects Plain, Plain* or Multi-BiDS; Multi-BiDS requires
+ * algo = PPSP_BIDS (the paper defines no batched heuristic search).
+ * Batches whose search state exceeds the memory budget are split into waves
+ * of whole query-graph components.
+ * Errors: as ppsp_query; PPSP_E_INVALID for Multi with another algorithm.
+ */
+int ppsp_batch_query(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp_opts *opts,
+                     void *hip_stream, uint64_t *dist, uint64_t *path_off, uint32_t *path_vtx,
+                     uint64_t path_cap);
+
+/* Counters of the last ppsp_query / ppsp_batch_query on g (see ppsp_stats). */
+int ppsp_last_stats(ppsp_graph g, ppsp_stats *stats);
+
+/*
+ * Tuning knobs of a graph handle (not part of the method; they only change
+ * launch shapes and bookkeeping):
+ *   "profile"         1: time every round-kernel launch with HIP events
+ *   "rounds_per_sync" rounds launched between host checks for termination
+ *   "grid_blocks"     blocks of the round kernel (0 = 4 per compute unit)
+ *   "mem_budget_mb"   cap on the search-state memory of one wave (0 = auto)
+ *   "default_delta"   Delta (distance units) used when opts.delta = 0
+ *   "use_graph"       1: replay rounds through a captured hipGraph
+ *   "timeout_ms"      host-side limit on one wave's round loop (0 = none)
+ * Returns PPSP_E_INVALID for an unknown name.
+ */
+int ppsp_set_option(ppsp_graph g, const char *name, int64_t value);
+int ppsp_get_option(ppsp_graph g, const char *name, int64_t *value);
+
+/*
+ * The heuristic of Sections 3.3 and 3.5 on fixed-point coordinates,
+ * computed exactly in integers: floor(w_scale * sqrt(dx^2 + dy^2) / 2^frac_bits)
+ * with (dx, dy) = (x1 - x0, y1 - y0). Host function, for checking.
+ * Requires w_scale^2 * (dx^2 + dy^2) < 2^63; returns UINT64_MAX otherwise.
+ */
+uint64_t ppsp_heuristic_fx(int32_t x0, int32_t y0, int32_t x1, int32_t y1, uint32_t w_scale,
+                           uint32_t frac_bits);
+
+/* Static description of a status code. */
+const char *ppsp_status_str(int status);
+
+/* Detail of the most recent PPSP_E_DEVICE / PPSP_E_OOM on this thread (the
+ * failing HIP call and its error name), or "" . Valid until the next call. */
+const char *ppsp_last_error(void);
+
+/* Library version, e.g. "0.1.0". */
+const char *ppsp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PPSP_H */

@@ -1,0 +1,272 @@
+"""MI355X (gfx950) exact point-to-point shortest paths: Python binding.
+
+A thin ctypes layer over ``libppsp.so`` (C interface in ``include/ppsp.h``).
+Every step of the search runs in the library's HIP kernels; this module only
+marshals arguments. There is no CPU fallback: if the library is not built,
+importing the functions raises.
+
+Module-level functions carry the C names without the ``ppsp_`` prefix
+(``graph_create``, ``query``, ``batch_query``, ``last_stats``, ...); the
+``Graph`` class wraps a handle for convenience. PyTorch is used only to
+obtain the caller's current HIP stream.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SO_PATH = os.path.join(HERE, "libppsp.so")
+
+INF = (1 << 64) - 1
+
+OK, E_INVALID, E_RANGE, E_OOM, E_OVERFLOW, E_NOCOORD, E_NOTSYM, E_DEVICE, E_BUSY, E_PATHCAP, E_NOPATH, \
+    E_TIMEOUT = 0, -1, -2, -3, -4, -5, -6, -7, -8, -9, -10, -11
+
+ALGO = {"sssp": 0, "et": 1, "astar": 2, "bids": 3, "bidastar": 4}
+BATCH = {"plain": 0, "plainstar": 1, "multi": 2}
+SCHED = {"fixed": 0, "autotuned": 1, "learned": 2}
+SYMMETRIC = 1
+WANT_PATH = 1
+MEMO_H = 2
+
+
+class PPSPError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        detail = last_error()
+        super().__init__("%s failed: %s (%d)%s" % (where, status_str(code), code,
+                                                   (": " + detail) if detail else ""))
+        self.code = code
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("algo", ctypes.c_uint32), ("batch", ctypes.c_uint32), ("sched", ctypes.c_uint32),
+                ("flags", ctypes.c_uint32), ("delta", ctypes.c_uint64)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("rounds", ctypes.c_uint64), ("entries", ctypes.c_uint64),
+                ("scanned_vertices", ctypes.c_uint64), ("scanned_arcs", ctypes.c_uint64),
+                ("relax_success", ctypes.c_uint64), ("searches", ctypes.c_uint64),
+                ("waves", ctypes.c_uint64), ("wall_ms", ctypes.c_double),
+                ("relax_kernel_ms", ctypes.c_double), ("relax_launches", ctypes.c_uint64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+EXPORTS = ["ppsp_graph_create", "ppsp_graph_destroy", "ppsp_query", "ppsp_batch_query", "ppsp_last_stats",
+           "ppsp_set_option", "ppsp_get_option", "ppsp_heuristic_fx", "ppsp_status_str", "ppsp_version", "ppsp_last_error"]
+
+_lib_handle = None
+
+
+def lib():
+    """The loaded libppsp.so; raises if it has not been built."""
+    global _lib_handle
+    if _lib_handle is None:
+        if not os.path.exists(SO_PATH):
+            raise ImportError("libppsp.so is not built (run __graft_entry__.build() or "
+                              "python paper_2506_16488_amd/build.py)")
+        # torch ships its own HIP runtime under the same soname; loading torch
+        # first makes the library bind to that one runtime, so torch's streams
+        # and device memory are valid here (two runtimes in one process do not
+        # share devices).
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
+        L = ctypes.CDLL(SO_PATH)
+        u32, u64, i32, i64, P = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p
+        L.ppsp_graph_create.argtypes = [ctypes.c_int, u32, u64, P, P, P, P, u32, u32, u32, P, ctypes.POINTER(P)]
+        L.ppsp_graph_create.restype = ctypes.c_int
+        L.ppsp_graph_destroy.argtypes = [P]
+        L.ppsp_graph_destroy.restype = ctypes.c_int
+        L.ppsp_query.argtypes = [P, u32, u32, ctypes.POINTER(Opts), P, ctypes.POINTER(u64), P, u32,
+                                 ctypes.POINTER(u32)]
+        L.ppsp_query.restype = ctypes.c_int
+        L.ppsp_batch_query.argtypes = [P, P, u32, ctypes.POINTER(Opts), P, P, P, P, u64]
+        L.ppsp_batch_query.restype = ctypes.c_int
+        L.ppsp_last_stats.argtypes = [P, ctypes.POINTER(Stats)]
+        L.ppsp_last_stats.restype = ctypes.c_int
+        L.ppsp_set_option.argtypes = [P, ctypes.c_char_p, i64]
+        L.ppsp_set_option.restype = ctypes.c_int
+        L.ppsp_get_option.argtypes = [P, ctypes.c_char_p, ctypes.POINTER(i64)]
+        L.ppsp_get_option.restype = ctypes.c_int
+        L.ppsp_heuristic_fx.argtypes = [i32, i32, i32, i32, u32, u32]
+        L.ppsp_heuristic_fx.restype = u64
+        L.ppsp_status_str.argtypes = [ctypes.c_int]
+        L.ppsp_status_str.restype = ctypes.c_char_p
+        L.ppsp_last_error.argtypes = []
+        L.ppsp_last_error.restype = ctypes.c_char_p
+        L.ppsp_version.argtypes = []
+        L.ppsp_version.restype = ctypes.c_char_p
+        _lib_handle = L
+    return _lib_handle
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else ctypes.c_void_p(a.ctypes.data)
+
+
+def current_stream():
+    """The caller's current HIP stream from torch (None = default stream)."""
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    except Exception:
+        pass
+    return None
+
+
+def _check(rc: int, where: str):
+    if rc != OK:
+        raise PPSPError(rc, where)
+
+
+def status_str(code: int) -> str:
+    try:
+        return lib().ppsp_status_str(code).decode()
+    except ImportError:
+        return "status %d" % code
+
+
+def last_error() -> str:
+    try:
+        return lib().ppsp_last_error().decode()
+    except ImportError:
+        return ""
+
+
+def version() -> str:
+    return lib().ppsp_version().decode()
+
+
+def heuristic_fx(x0: int, y0: int, x1: int, y1: int, w_scale: int, frac_bits: int) -> int:
+    return int(lib().ppsp_heuristic_fx(x0, y0, x1, y1, w_scale, frac_bits))
+
+
+def make_opts(algo="bids", batch="plainstar", sched="fixed", delta=0, want_path=False, memo=False) -> Opts:
+    return Opts(ALGO[algo] if isinstance(algo, str) else int(algo),
+                BATCH[batch] if isinstance(batch, str) else int(batch),
+                SCHED[sched] if isinstance(sched, str) else int(sched),
+                (WANT_PATH if want_path else 0) | (MEMO_H if memo else 0), int(delta))
+
+
+def graph_create(n, row_ptr, col, w, coords=None, frac_bits=8, w_scale=1000, symmetric=True, device=0,
+                 stream=None):
+    """ppsp_graph_create: returns an opaque handle (c_void_p)."""
+    rp = np.ascontiguousarray(row_ptr, np.uint64)
+    col = np.ascontiguousarray(col, np.uint32)
+    w = np.ascontiguousarray(w, np.uint32)
+    xy = None if coords is None else np.ascontiguousarray(coords, np.int32).reshape(-1)
+    h = ctypes.c_void_p()
+    rc = lib().ppsp_graph_create(device, int(n), int(col.shape[0]), _ptr(rp), _ptr(col), _ptr(w), _ptr(xy),
+                                 frac_bits, w_scale, SYMMETRIC if symmetric else 0,
+                                 stream if stream is not None else current_stream(), ctypes.byref(h))
+    _check(rc, "ppsp_graph_create")
+    return h
+
+
+def graph_destroy(h):
+    _check(lib().ppsp_graph_destroy(h), "ppsp_graph_destroy")
+
+
+def query(h, s, t, opts: Opts, stream=None, want_path=False, path_cap=1 << 20):
+    """ppsp_query: (distance, path or None)."""
+    d = ctypes.c_uint64(0)
+    plen = ctypes.c_uint32(0)
+    path = np.empty(path_cap, np.uint32) if want_path else None
+    rc = lib().ppsp_query(h, int(s), int(t), ctypes.byref(opts), stream if stream is not None else current_stream(),
+                          ctypes.byref(d), _ptr(path), path_cap if want_path else 0, ctypes.byref(plen))
+    if rc == E_PATHCAP and want_path:
+        return query(h, s, t, opts, stream, want_path, int(plen.value))
+    _check(rc, "ppsp_query")
+    return int(d.value), (path[:plen.value].copy() if want_path else None)
+
+
+def batch_query(h, pairs, opts: Opts, stream=None, want_path=False, path_cap=None):
+    """ppsp_batch_query: distances (uint64, input order) and, with paths, (offsets, vertices)."""
+    pairs = np.ascontiguousarray(pairs, np.uint32).reshape(-1, 2)
+    k = pairs.shape[0]
+    dist = np.empty(k, np.uint64)
+    off = np.empty(k + 1, np.uint64) if want_path else None
+    if want_path and path_cap is None:
+        path_cap = max(1, 64 * k)
+    vtx = np.empty(path_cap, np.uint32) if want_path else None
+    st = stream if stream is not None else current_stream()
+    for _ in range(8):
+        rc = lib().ppsp_batch_query(h, _ptr(pairs), k, ctypes.byref(opts), st, _ptr(dist), _ptr(off), _ptr(vtx),
+                                    path_cap if want_path else 0)
+        if rc == E_PATHCAP and want_path:
+            path_cap *= 4
+            vtx = np.empty(path_cap, np.uint32)
+            continue
+        break
+    _check(rc, "ppsp_batch_query")
+    if want_path:
+        return dist, (off, vtx[:int(off[k])].copy())
+    return dist
+
+
+def last_stats(h) -> dict:
+    s = Stats()
+    _check(lib().ppsp_last_stats(h, ctypes.byref(s)), "ppsp_last_stats")
+    return s.as_dict()
+
+
+def set_option(h, name: str, value: int):
+    _check(lib().ppsp_set_option(h, name.encode(), int(value)), "ppsp_set_option")
+
+
+def get_option(h, name: str) -> int:
+    v = ctypes.c_int64(0)
+    _check(lib().ppsp_get_option(h, name.encode(), ctypes.byref(v)), "ppsp_get_option")
+    return int(v.value)
+
+
+class Graph:
+    """A graph resident on one GPU (owns a ppsp_graph handle)."""
+
+    def __init__(self, n, row_ptr, col, w, coords=None, frac_bits=8, w_scale=1000, symmetric=True, device=0):
+        self.n = int(n)
+        self.h = graph_create(n, row_ptr, col, w, coords, frac_bits, w_scale, symmetric, device)
+
+    @classmethod
+    def from_host(cls, g, device=0, w_scale=1000):
+        """From any object with n, row_ptr, col, w, coords, frac_bits, symmetric."""
+        return cls(g.n, g.row_ptr, g.col, g.w, getattr(g, "coords", None), getattr(g, "frac_bits", 8),
+                   w_scale, getattr(g, "symmetric", True), device)
+
+    def query(self, s, t, algo="bids", delta=0, want_path=False, memo=False, sched="fixed"):
+        d, p = query(self.h, s, t, make_opts(algo, "plain", sched, delta, want_path, memo), want_path=want_path)
+        return (d, p) if want_path else d
+
+    def batch_query(self, pairs, algo="bids", batch="plainstar", delta=0, want_path=False, memo=False,
+                    sched="fixed"):
+        return batch_query(self.h, pairs, make_opts(algo, batch, sched, delta, want_path, memo),
+                           want_path=want_path)
+
+    def stats(self) -> dict:
+        return last_stats(self.h)
+
+    def set_option(self, name, value):
+        set_option(self.h, name, value)
+
+    def get_option(self, name):
+        return get_option(self.h, name)
+
+    def close(self):
+        if getattr(self, "h", None):
+            graph_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

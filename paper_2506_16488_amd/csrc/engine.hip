@@ -1,0 +1,847 @@
+// Host engine and C interface (include/ppsp.h) of the point-to-point
+// shortest-path library.
+//
+// A call goes through four steps:
+//   1. plan: turn the queries into searches (frontier copies) and query slots
+//      (mu values), following Table 2 for single queries and Section 4 for
+//      batches (Plain: one query at a time; Plain*: all queries at once with
+//      their own searches; Multi-BiDS: one search per query-graph vertex);
+//   2. split the searches into memory waves (whole queries, or whole
+//      query-graph components for Multi-BiDS) that fit the state budget;
+//   3. per wave: clear the state slabs, Init(), then rounds of k_round +
+//      k_control until every frontier is empty, checking termination on the
+//      host every `rounds_per_sync` rounds (the rounds in between are queued
+//      back to back, optionally as one captured hipGraph);
+//   4. read the mu slots (distance + meeting vertex) and, on request, walk
+//      the parent words into s->t paths.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <numeric>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/ppsp.h"
+#include "ppsp_dev.h"
+
+namespace ppsp {
+hipError_t launch_init(const RoundArgs &A, hipStream_t st);
+hipError_t launch_round(const RoundArgs &A, uint32_t par, uint32_t grid, hipStream_t st);
+hipError_t launch_control(const RoundArgs &A, uint32_t par, hipStream_t st);
+hipError_t launch_path_len(const RoundArgs &A, const PairDesc *pd, uint32_t *len, hipStream_t st);
+hipError_t launch_path_write(const RoundArgs &A, const PairDesc *pd, const uint32_t *len, const uint64_t *off,
+                             uint32_t *out, hipStream_t st);
+}  // namespace ppsp
+
+using namespace ppsp;
+
+namespace {
+
+extern thread_local std::string g_last_error;
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    template <class T> T *as() const { return (T *)p; }
+};
+
+int ensure(DevBuf &b, size_t bytes) {
+    if (bytes == 0) bytes = 8;
+    if (b.bytes >= bytes) return PPSP_OK;
+    if (b.p) { (void)hipFree(b.p); b.p = nullptr; b.bytes = 0; }
+    if (hipMalloc(&b.p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        b.p = nullptr;
+        g_last_error = "hipMalloc of " + std::to_string(bytes) + " bytes failed";
+        return PPSP_E_OOM;
+    }
+    b.bytes = bytes;
+    return PPSP_OK;
+}
+
+void release(DevBuf &b) {
+    if (b.p) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+}
+
+thread_local std::string g_last_error;
+
+int device_error(const char *what, hipError_t e) {
+    g_last_error = std::string(what) + ": " + hipGetErrorName(e) + " (" + hipGetErrorString(e) + ")";
+    (void)hipGetLastError();
+    return PPSP_E_DEVICE;
+}
+
+#define HIPCHK(x)                                                 \
+    do {                                                          \
+        hipError_t _e = (x);                                      \
+        if (_e != hipSuccess) return device_error(#x, _e);        \
+    } while (0)
+#define CHK(x)                            \
+    do {                                  \
+        int _rc = (x);                    \
+        if (_rc != PPSP_OK) return _rc;   \
+    } while (0)
+
+// A query slot of one wave: which searches meet in it and where the answer goes.
+struct Plan {
+    std::vector<SearchDesc> sd;
+    std::vector<Partner> partners;
+    std::vector<PairDesc> pairs;
+    std::vector<uint64_t> delta;    // per search, key units
+};
+
+}  // namespace
+
+struct ppsp_graph_s {
+    int device = 0;
+    uint32_t n = 0;
+    uint64_t m = 0;
+    bool symmetric = false, has_xy = false, xy_ok = false;
+    uint32_t wmin = 0, wmax = 0, fb = 0, w_scale = 0;
+    uint64_t ws2 = 0;
+    std::vector<int32_t> h_xy;      // host copy of coordinates (for descriptors)
+    DevBuf row_ptr, arcs, xy;
+    // workspace (grow only)
+    DevBuf S, flags, q0, q1, sd, partners, pairdesc, theta, delta, bound, done, exh, cnt, minkey, mu, qcount,
+        err, stats, pathlen, pathoff, pathbuf;
+    hipStream_t st = nullptr;
+    uint32_t *h_poll = nullptr;     // pinned
+    std::vector<hipEvent_t> ev;
+    ppsp_stats last{};
+    int cu = 256;
+    // options
+    int64_t opt_profile = 0, opt_rounds_per_sync = 16, opt_grid_blocks = 0, opt_mem_budget_mb = 0,
+            opt_default_delta = 0, opt_use_graph = 0, opt_timeout_ms = 600000;
+    uint64_t qcap = 0;
+};
+
+namespace {
+
+int set_device(ppsp_graph g) {
+    HIPCHK(hipSetDevice(g->device));
+    return PPSP_OK;
+}
+
+uint64_t key_delta(uint32_t kind, uint64_t d) {
+    return (kind == K_2DIST || kind == K_BIDA_F || kind == K_BIDA_B) ? 2 * d : d;
+}
+
+uint64_t graph_default_delta(ppsp_graph g) {
+    if (g->opt_default_delta > 0) return (uint64_t)g->opt_default_delta;
+    return std::max<uint64_t>(1, 2ull * g->wmax);
+}
+
+// Bytes of search state per search (slab + both frontier bitmaps).
+uint64_t state_bytes_per_search(ppsp_graph g) {
+    uint64_t fw = ((uint64_t)g->n + 31) / 32;
+    return (uint64_t)g->n * 8 + 2 * fw * 4;
+}
+
+uint64_t state_budget(ppsp_graph g) {
+    if (g->opt_mem_budget_mb > 0) return (uint64_t)g->opt_mem_budget_mb << 20;
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) != hipSuccess) { (void)hipGetLastError(); return 1ull << 30; }
+    uint64_t have = fr + g->S.bytes + g->flags.bytes;   // reusable
+    uint64_t reserve = (2ull << 30) + 2 * g->qcap * 8;  // queues and small buffers
+    return have > reserve ? (uint64_t)((have - reserve) * 0.9) : (1ull << 28);
+}
+
+uint64_t search_limit(ppsp_graph g) {
+    uint64_t per = state_bytes_per_search(g);
+    uint64_t lim = state_budget(g) / per;
+    return std::max<uint64_t>(lim, 1);
+}
+
+void set_args(ppsp_graph g, RoundArgs &A, uint32_t nsearch, uint32_t npair) {
+    memset(&A, 0, sizeof(A));
+    A.row_ptr = g->row_ptr.as<uint32_t>();
+    A.arcs = g->arcs.as<uint2>();
+    A.xy = g->has_xy ? g->xy.as<int2>() : nullptr;
+    A.ws2 = g->ws2;
+    A.fb = g->fb;
+    A.n = g->n;
+    A.sd = g->sd.as<SearchDesc>();
+    A.partners = g->partners.as<Partner>();
+    A.nsearch = nsearch;
+    A.npair = npair;
+    A.S = g->S.as<uint64_t>();
+    A.flags = g->flags.as<uint32_t>();
+    A.fw = ((uint64_t)g->n + 31) / 32;
+    A.theta = g->theta.as<uint64_t>();
+    A.delta = g->delta.as<uint64_t>();
+    A.bound = g->bound.as<uint64_t>();
+    A.done = g->done.as<uint32_t>();
+    A.exh = g->exh.as<uint32_t>();
+    A.cnt = g->cnt.as<uint32_t>();
+    A.minkey = g->minkey.as<uint64_t>();
+    A.mu = g->mu.as<uint64_t>();
+    A.q0 = g->q0.as<uint64_t>();
+    A.q1 = g->q1.as<uint64_t>();
+    A.qcount = g->qcount.as<uint32_t>();
+    A.qcap = g->qcap;
+    A.err = g->err.as<uint32_t>();
+    A.stats = g->stats.as<unsigned long long>();
+}
+
+int ensure_events(ppsp_graph g, size_t k) {
+    while (g->ev.size() < k) {
+        hipEvent_t e;
+        HIPCHK(hipEventCreate(&e));
+        g->ev.push_back(e);
+    }
+    return PPSP_OK;
+}
+
+struct WaveOut {
+    std::vector<uint64_t> mu;       // per pair slot
+    std::vector<uint32_t> path;     // concatenated paths (if requested)
+    std::vector<uint64_t> path_off; // npair + 1
+    unsigned long long stats[ST_N] = {0};
+    double relax_ms = 0;
+    uint64_t launches = 0;
+};
+
+// Runs one wave of searches to completion.
+int run_wave(ppsp_graph g, const Plan &P, bool want_path, WaveOut &out) {
+    const uint32_t ns = (uint32_t)P.sd.size(), npair = (uint32_t)P.pairs.size();
+    const uint64_t n = g->n;
+    const uint64_t fw = (n + 31) / 32;
+    hipStream_t st = g->st;
+    CHK(ensure(g->S, ns * n * 8));
+    CHK(ensure(g->flags, 2 * ns * fw * 4));
+    CHK(ensure(g->sd, ns * sizeof(SearchDesc)));
+    CHK(ensure(g->partners, P.partners.size() * sizeof(Partner)));
+    CHK(ensure(g->pairdesc, npair * sizeof(PairDesc)));
+    CHK(ensure(g->theta, ns * 8));
+    CHK(ensure(g->delta, ns * 8));
+    CHK(ensure(g->bound, ns * 8));
+    CHK(ensure(g->done, ns * 4));
+    CHK(ensure(g->exh, ns * 4));
+    CHK(ensure(g->cnt, 2 * ns * 4));
+    CHK(ensure(g->minkey, 2 * ns * 8));
+    CHK(ensure(g->mu, npair * 8));
+    CHK(ensure(g->qcount, 16));
+    CHK(ensure(g->err, 16));
+    CHK(ensure(g->stats, ST_N * 8));
+    {
+        // one frontier holds at most one entry per (search, vertex) plus rare duplicates
+        const uint64_t want = std::min<uint64_t>(std::max<uint64_t>(std::min<uint64_t>(16384ull * ns, ns * n + 1024),
+                                                                    1ull << 16), 1ull << 28);
+        if (g->qcap < want) g->qcap = want;
+    }
+    for (;;) {
+        CHK(ensure(g->q0, g->qcap * 8));
+        CHK(ensure(g->q1, g->qcap * 8));
+        HIPCHK(hipMemsetAsync(g->S.p, 0xFF, ns * n * 8, st));
+        HIPCHK(hipMemsetAsync(g->flags.p, 0, 2 * ns * fw * 4, st));
+        HIPCHK(hipMemcpyAsync(g->sd.p, P.sd.data(), ns * sizeof(SearchDesc), hipMemcpyHostToDevice, st));
+        if (!P.partners.empty())
+            HIPCHK(hipMemcpyAsync(g->partners.p, P.partners.data(), P.partners.size() * sizeof(Partner),
+                                  hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(g->pairdesc.p, P.pairs.data(), npair * sizeof(PairDesc), hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(g->delta.p, P.delta.data(), ns * 8, hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemsetAsync(g->mu.p, 0xFF, npair * 8, st));
+        uint32_t qc[4] = {ns, 0, 0, 0};
+        HIPCHK(hipMemcpyAsync(g->qcount.p, qc, 16, hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemsetAsync(g->err.p, 0, 16, st));
+        HIPCHK(hipMemsetAsync(g->stats.p, 0, ST_N * 8, st));
+        RoundArgs A;
+        set_args(g, A, ns, npair);
+        HIPCHK(launch_init(A, st));
+        const uint32_t grid = g->opt_grid_blocks > 0 ? (uint32_t)g->opt_grid_blocks : (uint32_t)(4 * g->cu);
+        const int K = std::max<int64_t>(1, g->opt_rounds_per_sync);
+        const bool prof = g->opt_profile != 0;
+        if (prof) CHK(ensure_events(g, 2 * (size_t)K));
+        uint64_t r = 0;
+        double relax_ms = 0;
+        uint64_t launches = 0;
+        const auto t_start = std::chrono::steady_clock::now();
+        bool timed_out = false;
+        hipGraphExec_t gexec = nullptr;
+        hipGraph_t graph = nullptr;
+        if (g->opt_use_graph && !prof) {
+            // Capture K rounds (K even keeps the parity pattern) once per wave.
+            const int Kg = K + (K & 1);
+            HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+            for (int k = 0; k < Kg; k++) {
+                (void)launch_round(A, (uint32_t)(k & 1), grid, st);
+                (void)launch_control(A, (uint32_t)(k & 1), st);
+            }
+            HIPCHK(hipStreamEndCapture(st, &graph));
+            HIPCHK(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
+        }
+        for (;;) {
+            int kk;
+            if (gexec) {
+                HIPCHK(hipGraphLaunch(gexec, st));
+                kk = K + (K & 1);
+                r += kk;
+            } else {
+                for (kk = 0; kk < K; kk++, r++) {
+                    const uint32_t par = (uint32_t)(r & 1);
+                    if (prof) HIPCHK(hipEventRecord(g->ev[2 * kk], st));
+                    HIPCHK(launch_round(A, par, grid, st));
+                    if (prof) HIPCHK(hipEventRecord(g->ev[2 * kk + 1], st));
+                    HIPCHK(launch_control(A, par, st));
+                }
+            }
+            launches += kk;
+            HIPCHK(hipMemcpyAsync(g->h_poll, g->qcount.p, 16, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipMemcpyAsync(g->h_poll + 4, g->err.p, 4, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            if (prof) {
+                for (int k = 0; k < kk; k++) {
+                    float ms = 0;
+                    HIPCHK(hipEventElapsedTime(&ms, g->ev[2 * k], g->ev[2 * k + 1]));
+                    relax_ms += ms;
+                }
+            }
+            const uint32_t pending = g->h_poll[r & 1];
+            if (pending == 0 || g->h_poll[4] != 0) break;
+            const double el = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+            if (g->opt_timeout_ms > 0 && el > (double)g->opt_timeout_ms) { timed_out = true; break; }
+        }
+        if (gexec) { (void)hipGraphExecDestroy(gexec); (void)hipGraphDestroy(graph); }
+        if (timed_out) return PPSP_E_TIMEOUT;
+        const uint32_t errbits = g->h_poll[4];
+        if (errbits & ERR_OVERFLOW) return PPSP_E_OVERFLOW;
+        if (errbits & ERR_QUEUE) {
+            // Grow the frontier queues and rerun the wave from scratch.
+            uint64_t want = g->qcap * 4;
+            if (want > (1ull << 31)) return PPSP_E_OOM;
+            g->qcap = want;
+            continue;
+        }
+        out.mu.resize(npair);
+        HIPCHK(hipMemcpyAsync(out.mu.data(), g->mu.p, npair * 8, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(out.stats, g->stats.p, ST_N * 8, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        out.relax_ms = relax_ms;
+        out.launches = launches;
+        if (want_path) {
+            CHK(ensure(g->pathlen, npair * 4));
+            CHK(ensure(g->pathoff, (npair + 1) * 8));
+            HIPCHK(launch_path_len(A, g->pairdesc.as<PairDesc>(), g->pathlen.as<uint32_t>(), st));
+            std::vector<uint32_t> len(npair);
+            HIPCHK(hipMemcpyAsync(len.data(), g->pathlen.p, npair * 4, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipMemcpyAsync(g->h_poll + 4, g->err.p, 4, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            if (g->h_poll[4] & ERR_PATH) return PPSP_E_NOPATH;
+            out.path_off.assign(npair + 1, 0);
+            for (uint32_t p = 0; p < npair; p++) out.path_off[p + 1] = out.path_off[p] + len[p];
+            const uint64_t tot = out.path_off[npair];
+            CHK(ensure(g->pathbuf, tot * 4));
+            HIPCHK(hipMemcpyAsync(g->pathoff.p, out.path_off.data(), (npair + 1) * 8, hipMemcpyHostToDevice, st));
+            HIPCHK(launch_path_write(A, g->pairdesc.as<PairDesc>(), g->pathlen.as<uint32_t>(),
+                                     g->pathoff.as<uint64_t>(), g->pathbuf.as<uint32_t>(), st));
+            out.path.resize(tot);
+            if (tot) HIPCHK(hipMemcpyAsync(out.path.data(), g->pathbuf.p, tot * 4, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+        }
+        return PPSP_OK;
+    }
+}
+
+// ---- planning ---------------------------------------------------------------
+
+bool is_bidir(uint32_t algo) { return algo == PPSP_BIDS || algo == PPSP_BIDASTAR; }
+bool is_astar(uint32_t algo) { return algo == PPSP_ASTAR || algo == PPSP_BIDASTAR; }
+
+SearchDesc make_sd(ppsp_graph g, uint32_t src, uint32_t kind, uint32_t s, uint32_t t) {
+    SearchDesc d;
+    memset(&d, 0, sizeof(d));
+    d.src = src;
+    d.kind = kind;
+    if (g->has_xy) {
+        d.tx = g->h_xy[2 * (uint64_t)t];
+        d.ty = g->h_xy[2 * (uint64_t)t + 1];
+        d.sx = g->h_xy[2 * (uint64_t)s];
+        d.sy = g->h_xy[2 * (uint64_t)s + 1];
+    }
+    return d;
+}
+
+// Adds the searches of one query (s, t) for a single-query algorithm.
+void plan_single(ppsp_graph g, Plan &P, uint32_t s, uint32_t t, uint32_t algo, uint64_t delta) {
+    const uint32_t pair = (uint32_t)P.pairs.size();
+    const uint32_t a = (uint32_t)P.sd.size();
+    if (is_bidir(algo)) {
+        const uint32_t kf = algo == PPSP_BIDS ? K_2DIST : K_BIDA_F;
+        const uint32_t kb = algo == PPSP_BIDS ? K_2DIST : K_BIDA_B;
+        SearchDesc f = make_sd(g, s, kf, s, t), b = make_sd(g, t, kb, s, t);
+        f.pbeg = (uint32_t)P.partners.size();
+        P.partners.push_back({a + 1, pair});
+        f.pend = (uint32_t)P.partners.size();
+        b.pbeg = (uint32_t)P.partners.size();
+        P.partners.push_back({a, pair});
+        b.pend = (uint32_t)P.partners.size();
+        P.sd.push_back(f);
+        P.sd.push_back(b);
+        P.delta.push_back(key_delta(kf, delta));
+        P.delta.push_back(key_delta(kb, delta));
+        P.pairs.push_back({a, a + 1});
+    } else {
+        const uint32_t k = algo == PPSP_ASTAR ? K_ASTAR : K_DIST;
+        SearchDesc f = make_sd(g, s, k, s, t);
+        f.noprune = algo == PPSP_SSSP;
+        f.pbeg = (uint32_t)P.partners.size();
+        P.partners.push_back({TARGET_BIT | t, pair});
+        f.pend = (uint32_t)P.partners.size();
+        P.sd.push_back(f);
+        P.delta.push_back(key_delta(k, delta));
+        P.pairs.push_back({a, TARGET_BIT | t});
+    }
+}
+
+int check_opts(ppsp_graph g, const ppsp_opts *o) {
+    if (!o) return PPSP_E_INVALID;
+    if (o->algo > PPSP_BIDASTAR || o->batch > PPSP_BATCH_MULTI || o->sched > PPSP_SCHED_LEARNED) return PPSP_E_INVALID;
+    if (is_astar(o->algo) && !g->xy_ok) return PPSP_E_NOCOORD;
+    if (is_bidir(o->algo) && !g->symmetric) return PPSP_E_NOTSYM;
+    if (o->batch == PPSP_BATCH_MULTI && o->algo != PPSP_BIDS) return PPSP_E_INVALID;
+    if ((o->flags & PPSP_WANT_PATH) && g->wmin == 0 && g->m > 0) return PPSP_E_NOPATH;
+    return PPSP_OK;
+}
+
+struct Query {
+    uint32_t s, t;
+};
+
+// Answers for distinct canonical queries, then scattered to the input order.
+struct Answer {
+    uint64_t dist = PPSP_INF;
+    std::vector<uint32_t> path;
+};
+
+void accumulate(ppsp_graph g, const WaveOut &w) {
+    g->last.rounds += w.stats[ST_ROUNDS];
+    g->last.entries += w.stats[ST_ENTRIES];
+    g->last.scanned_vertices += w.stats[ST_SCANV];
+    g->last.scanned_arcs += w.stats[ST_SCANE];
+    g->last.relax_success += w.stats[ST_SUCC];
+    g->last.relax_kernel_ms += w.relax_ms;
+    g->last.relax_launches += w.launches;
+    g->last.waves += 1;
+}
+
+// Copies wave results for pair slots [0, npair) into answers idx[...].
+void collect(const WaveOut &w, const std::vector<uint32_t> &ans_of_pair, std::vector<Answer> &ans, bool want_path) {
+    for (size_t p = 0; p < ans_of_pair.size(); p++) {
+        Answer &a = ans[ans_of_pair[p]];
+        const uint32_t d32 = (uint32_t)(w.mu[p] >> 32);
+        a.dist = d32 == INF32 ? PPSP_INF : d32;
+        if (want_path && d32 != INF32)
+            a.path.assign(w.path.begin() + w.path_off[p], w.path.begin() + w.path_off[p + 1]);
+    }
+}
+
+// Runs distinct queries with Plain / Plain* (each query owns its searches).
+int run_independent(ppsp_graph g, const std::vector<Query> &qs, const ppsp_opts *o, uint64_t delta,
+                    std::vector<Answer> &ans) {
+    const bool want_path = o->flags & PPSP_WANT_PATH;
+    const uint32_t per = is_bidir(o->algo) ? 2 : 1;
+    uint64_t lim = o->batch == PPSP_BATCH_PLAIN ? 1 : std::max<uint64_t>(1, search_limit(g) / per);
+    for (size_t q0 = 0; q0 < qs.size(); q0 += lim) {
+        const size_t q1 = std::min<size_t>(qs.size(), q0 + lim);
+        Plan P;
+        std::vector<uint32_t> ans_of_pair;
+        for (size_t q = q0; q < q1; q++) {
+            plan_single(g, P, qs[q].s, qs[q].t, o->algo, delta);
+            ans_of_pair.push_back((uint32_t)q);
+        }
+        g->last.searches += P.sd.size();
+        WaveOut w;
+        CHK(run_wave(g, P, want_path, w));
+        accumulate(g, w);
+        collect(w, ans_of_pair, ans, want_path);
+    }
+    return PPSP_OK;
+}
+
+// Multi-BiDS (Section 4.2): searches are the query-graph vertices, waves are
+// unions of whole query-graph components.
+int run_multi(ppsp_graph g, const std::vector<Query> &qs, const ppsp_opts *o, uint64_t delta,
+              std::vector<Answer> &ans) {
+    const bool want_path = o->flags & PPSP_WANT_PATH;
+    // query graph G_q: vertex ids and adjacency (Section 4.1)
+    std::unordered_map<uint32_t, uint32_t> vid;
+    std::vector<uint32_t> verts;
+    auto id_of = [&](uint32_t v) {
+        auto it = vid.find(v);
+        if (it != vid.end()) return it->second;
+        uint32_t k = (uint32_t)verts.size();
+        vid.emplace(v, k);
+        verts.push_back(v);
+        return k;
+    };
+    std::vector<std::pair<uint32_t, uint32_t>> qe(qs.size());
+    for (size_t q = 0; q < qs.size(); q++) qe[q] = {id_of(qs[q].s), id_of(qs[q].t)};
+    const uint32_t nv = (uint32_t)verts.size();
+    // components (union-find)
+    std::vector<uint32_t> par(nv);
+    std::iota(par.begin(), par.end(), 0u);
+    auto find = [&](uint32_t x) {
+        while (par[x] != x) { par[x] = par[par[x]]; x = par[x]; }
+        return x;
+    };
+    for (auto &e : qe) {
+        uint32_t a = find(e.first), b = find(e.second);
+        if (a != b) par[std::max(a, b)] = std::min(a, b);
+    }
+    std::map<uint32_t, std::vector<uint32_t>> comp_verts, comp_queries;
+    for (uint32_t v = 0; v < nv; v++) comp_verts[find(v)].push_back(v);
+    for (size_t q = 0; q < qe.size(); q++) comp_queries[find(qe[q].first)].push_back((uint32_t)q);
+    const uint64_t lim = search_limit(g);
+    std::vector<uint32_t> wave_comps;
+    uint64_t wave_size = 0;
+    auto flush = [&]() -> int {
+        if (wave_comps.empty()) return PPSP_OK;
+        Plan P;
+        std::vector<uint32_t> local(nv, UINT32_MAX);
+        for (uint32_t c : wave_comps)
+            for (uint32_t v : comp_verts[c]) {
+                local[v] = (uint32_t)P.sd.size();
+                P.sd.push_back(make_sd(g, verts[v], K_2DIST, verts[v], verts[v]));
+                P.delta.push_back(key_delta(K_2DIST, delta));
+            }
+        // adjacency with pair slots
+        std::vector<std::vector<Partner>> adj(P.sd.size());
+        std::vector<uint32_t> ans_of_pair;
+        for (uint32_t c : wave_comps)
+            for (uint32_t q : comp_queries[c]) {
+                const uint32_t a = local[qe[q].first], b = local[qe[q].second];
+                const uint32_t slot = (uint32_t)P.pairs.size();
+                P.pairs.push_back({a, b});
+                adj[a].push_back({b, slot});
+                adj[b].push_back({a, slot});
+                ans_of_pair.push_back(q);
+            }
+        for (size_t i = 0; i < P.sd.size(); i++) {
+            P.sd[i].pbeg = (uint32_t)P.partners.size();
+            P.partners.insert(P.partners.end(), adj[i].begin(), adj[i].end());
+            P.sd[i].pend = (uint32_t)P.partners.size();
+        }
+        g->last.searches += P.sd.size();
+        WaveOut w;
+        CHK(run_wave(g, P, want_path, w));
+        accumulate(g, w);
+        collect(w, ans_of_pair, ans, want_path);
+        wave_comps.clear();
+        wave_size = 0;
+        return PPSP_OK;
+    };
+    for (auto &kv : comp_verts) {
+        const uint64_t sz = kv.second.size();
+        if (sz > lim) {
+            // a component larger than the budget: answer its queries with Plain*
+            CHK(flush());
+            std::vector<Query> sub;
+            std::vector<uint32_t> ids;
+            for (uint32_t q : comp_queries[kv.first]) { sub.push_back(qs[q]); ids.push_back(q); }
+            std::vector<Answer> sa(sub.size());
+            ppsp_opts o2 = *o;
+            o2.batch = PPSP_BATCH_PLAINSTAR;
+            CHK(run_independent(g, sub, &o2, delta, sa));
+            for (size_t j = 0; j < ids.size(); j++) ans[ids[j]] = sa[j];
+            continue;
+        }
+        if (wave_size + sz > lim) CHK(flush());
+        wave_comps.push_back(kv.first);
+        wave_size += sz;
+    }
+    return flush();
+}
+
+int batch_impl(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp_opts *o, void *hip_stream,
+               uint64_t *dist, uint64_t *path_off, uint32_t *path_vtx, uint64_t path_cap, uint32_t *need_out) {
+    auto t0 = std::chrono::steady_clock::now();
+    if (!g || (!pairs && k) || (!dist && k)) return PPSP_E_INVALID;
+    CHK(check_opts(g, o));
+    const bool want_path = o->flags & PPSP_WANT_PATH;
+    if (want_path && (!path_off || (!path_vtx && path_cap))) return PPSP_E_INVALID;
+    for (uint64_t i = 0; i < 2ull * k; i++)
+        if (pairs[i] >= g->n) return PPSP_E_RANGE;
+    CHK(set_device(g));
+    g->last = ppsp_stats{};
+    // order the library stream after the caller's stream
+    hipEvent_t ev;
+    HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    HIPCHK(hipEventRecord(ev, (hipStream_t)hip_stream));
+    HIPCHK(hipStreamWaitEvent(g->st, ev, 0));
+    (void)hipEventDestroy(ev);
+    const uint64_t delta = o->delta ? o->delta : graph_default_delta(g);
+    // distinct queries; on symmetric graphs (t,s) is the same query as (s,t)
+    std::vector<Query> qs;
+    std::vector<uint32_t> qidx(k);
+    std::vector<uint8_t> flip(k, 0), self(k, 0);
+    {
+        std::unordered_map<uint64_t, uint32_t> seen;
+        for (uint32_t i = 0; i < k; i++) {
+            uint32_t s = pairs[2 * i], t = pairs[2 * i + 1];
+            if (s == t) { self[i] = 1; continue; }
+            if (g->symmetric && s > t && o->algo != PPSP_SSSP) { std::swap(s, t); flip[i] = 1; }
+            const uint64_t key = ((uint64_t)s << 32) | t;
+            auto it = seen.find(key);
+            if (it == seen.end()) {
+                it = seen.emplace(key, (uint32_t)qs.size()).first;
+                qs.push_back({s, t});
+            }
+            qidx[i] = it->second;
+        }
+    }
+    std::vector<Answer> ans(qs.size());
+    if (!qs.empty()) {
+        if (o->batch == PPSP_BATCH_MULTI) CHK(run_multi(g, qs, o, delta, ans));
+        else CHK(run_independent(g, qs, o, delta, ans));
+    }
+    // scatter
+    uint64_t need = 0;
+    for (uint32_t i = 0; i < k; i++) {
+        if (self[i]) need += 1;
+        else need += ans[qidx[i]].path.size();
+    }
+    if (want_path && need > path_cap) {
+        if (need_out) *need_out = (uint32_t)std::min<uint64_t>(need, UINT32_MAX);
+        return PPSP_E_PATHCAP;
+    }
+    uint64_t off = 0;
+    for (uint32_t i = 0; i < k; i++) {
+        if (self[i]) {
+            dist[i] = 0;
+            if (want_path) { path_off[i] = off; path_vtx[off++] = pairs[2 * i]; }
+            continue;
+        }
+        const Answer &a = ans[qidx[i]];
+        dist[i] = a.dist;
+        if (want_path) {
+            path_off[i] = off;
+            if (flip[i]) for (size_t j = a.path.size(); j-- > 0;) path_vtx[off++] = a.path[j];
+            else for (uint32_t v : a.path) path_vtx[off++] = v;
+        }
+    }
+    if (want_path) path_off[k] = off;
+    g->last.wall_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return PPSP_OK;
+}
+
+}  // namespace
+
+// ---- C interface --------------------------------------------------------------
+
+extern "C" {
+
+const char *ppsp_version(void) { return "0.1.0"; }
+
+const char *ppsp_last_error(void) { return g_last_error.c_str(); }
+
+const char *ppsp_status_str(int s) {
+    switch (s) {
+        case PPSP_OK: return "ok";
+        case PPSP_E_INVALID: return "invalid argument";
+        case PPSP_E_RANGE: return "value out of range";
+        case PPSP_E_OOM: return "out of device memory";
+        case PPSP_E_OVERFLOW: return "distance overflow (>= 2^32-1)";
+        case PPSP_E_NOCOORD: return "A* needs consistent coordinates";
+        case PPSP_E_NOTSYM: return "mode needs a symmetric graph";
+        case PPSP_E_DEVICE: return "HIP runtime error";
+        case PPSP_E_BUSY: return "request not finished";
+        case PPSP_E_PATHCAP: return "path buffer too small";
+        case PPSP_E_NOPATH: return "paths need positive weights";
+        case PPSP_E_TIMEOUT: return "round loop exceeded its time limit";
+        default: return "unknown status";
+    }
+}
+
+uint64_t ppsp_heuristic_fx(int32_t x0, int32_t y0, int32_t x1, int32_t y1, uint32_t w_scale, uint32_t frac_bits) {
+    const __int128 dx = (__int128)x1 - x0, dy = (__int128)y1 - y0;
+    const unsigned __int128 d2 = (unsigned __int128)(dx * dx) + (unsigned __int128)(dy * dy);
+    const unsigned __int128 q = d2 * ((unsigned __int128)w_scale * w_scale);
+    if (q >> 63) return UINT64_MAX;
+    return heur(x0, y0, x1, y1, (uint64_t)w_scale * w_scale, frac_bits);
+}
+
+int ppsp_graph_create(int device, uint32_t n, uint64_t m, const uint64_t *row_ptr, const uint32_t *col,
+                      const uint32_t *w, const int32_t *coord_fx, uint32_t coord_frac_bits, uint32_t w_scale,
+                      uint32_t flags, void *hip_stream, ppsp_graph *out) {
+    g_last_error.clear();
+    if (!out || !row_ptr || (m && (!col || !w)) || n == 0) return PPSP_E_INVALID;
+    if (n >= TARGET_BIT || m >= (1ull << 32)) return PPSP_E_RANGE;
+    if (row_ptr[0] != 0 || row_ptr[n] != m) return PPSP_E_INVALID;
+    for (uint32_t v = 0; v < n; v++)
+        if (row_ptr[v + 1] < row_ptr[v]) return PPSP_E_INVALID;
+    uint32_t wmin = UINT32_MAX, wmax = 0;
+    for (uint64_t e = 0; e < m; e++) {
+        if (col[e] >= n) return PPSP_E_RANGE;
+        wmin = std::min(wmin, w[e]);
+        wmax = std::max(wmax, w[e]);
+    }
+    if (m == 0) wmin = wmax = 1;
+    if (coord_fx && coord_frac_bits > 30) return PPSP_E_RANGE;
+    ppsp_graph g = new ppsp_graph_s();
+    g->device = device;
+    g->n = n;
+    g->m = m;
+    g->symmetric = flags & PPSP_SYMMETRIC;
+    g->wmin = wmin;
+    g->wmax = wmax;
+    auto fail = [&](int rc) {
+        ppsp_graph_destroy(g);
+        return rc;
+    };
+    if (coord_fx) {
+        // exact 64-bit heuristic arithmetic needs w_scale^2 * (span_x^2 + span_y^2) < 2^63
+        int64_t x0 = INT64_MAX, x1 = INT64_MIN, y0 = INT64_MAX, y1 = INT64_MIN;
+        for (uint32_t v = 0; v < n; v++) {
+            x0 = std::min<int64_t>(x0, coord_fx[2 * (uint64_t)v]);
+            x1 = std::max<int64_t>(x1, coord_fx[2 * (uint64_t)v]);
+            y0 = std::min<int64_t>(y0, coord_fx[2 * (uint64_t)v + 1]);
+            y1 = std::max<int64_t>(y1, coord_fx[2 * (uint64_t)v + 1]);
+        }
+        const __int128 sx = (__int128)x1 - x0, sy = (__int128)y1 - y0;
+        const unsigned __int128 span = (unsigned __int128)(sx * sx) + (unsigned __int128)(sy * sy);
+        if ((span * ((unsigned __int128)w_scale * w_scale)) >> 63) return fail(PPSP_E_RANGE);
+        g->has_xy = true;
+        g->fb = coord_frac_bits;
+        g->w_scale = w_scale;
+        g->ws2 = (uint64_t)w_scale * w_scale;
+        g->h_xy.assign(coord_fx, coord_fx + 2 * (uint64_t)n);
+        // Consistency of h (Section 3.3): h(u) <= w(u,v) + h(v) holds for the
+        // floor heuristic whenever w >= w_scale * |p_u - p_v|, i.e.
+        // (w * 2^fb)^2 >= w_scale^2 * |p_u - p_v|^2 in exact integers.
+        bool ok = true;
+        for (uint32_t u = 0; u < n && ok; u++)
+            for (uint64_t e = row_ptr[u]; e < row_ptr[u + 1]; e++) {
+                const uint32_t v = col[e];
+                const __int128 dx = (__int128)coord_fx[2 * (uint64_t)v] - coord_fx[2 * (uint64_t)u];
+                const __int128 dy = (__int128)coord_fx[2 * (uint64_t)v + 1] - coord_fx[2 * (uint64_t)u + 1];
+                const unsigned __int128 lhs = (unsigned __int128)((uint64_t)w[e] << coord_frac_bits) * ((uint64_t)w[e] << coord_frac_bits);
+                const unsigned __int128 rhs = (unsigned __int128)g->ws2 * (unsigned __int128)(dx * dx + dy * dy);
+                if (lhs < rhs) { ok = false; break; }
+            }
+        g->xy_ok = ok;
+    }
+    hipError_t he;
+    if ((he = hipSetDevice(device)) != hipSuccess) return fail(device_error("hipSetDevice", he));
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) g->cu = prop.multiProcessorCount;
+    if ((he = hipStreamCreateWithFlags(&g->st, hipStreamNonBlocking)) != hipSuccess) {
+        g->st = nullptr;
+        return fail(device_error("hipStreamCreateWithFlags", he));
+    }
+    if ((he = hipHostMalloc((void **)&g->h_poll, 64, hipHostMallocDefault)) != hipSuccess) {
+        g->h_poll = nullptr;
+        return fail(device_error("hipHostMalloc", he));
+    }
+    // device CSR: row_ptr as uint32 (m < 2^32), arcs interleaved (neighbour, weight)
+    std::vector<uint32_t> rp32(n + 1);
+    for (uint64_t v = 0; v <= n; v++) rp32[v] = (uint32_t)row_ptr[v];
+    std::vector<uint2> arcs(m);
+    for (uint64_t e = 0; e < m; e++) arcs[e] = make_uint2(col[e], w[e]);
+    int rc;
+    if ((rc = ensure(g->row_ptr, (n + 1) * 4ull)) != PPSP_OK) return fail(rc);
+    if ((rc = ensure(g->arcs, std::max<uint64_t>(m, 1) * 8)) != PPSP_OK) return fail(rc);
+    hipStream_t st = g->st;
+    hipEvent_t ev;
+    if ((he = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess)
+        return fail(device_error("hipEventCreateWithFlags", he));
+    if ((he = hipEventRecord(ev, (hipStream_t)hip_stream)) != hipSuccess) {
+        (void)hipEventDestroy(ev);
+        return fail(device_error("hipEventRecord on the caller's stream", he));
+    }
+    (void)hipStreamWaitEvent(st, ev, 0);
+    (void)hipEventDestroy(ev);
+    if ((he = hipMemcpyAsync(g->row_ptr.p, rp32.data(), (n + 1) * 4ull, hipMemcpyHostToDevice, st)) != hipSuccess)
+        return fail(device_error("upload row_ptr", he));
+    if (m && (he = hipMemcpyAsync(g->arcs.p, arcs.data(), m * 8, hipMemcpyHostToDevice, st)) != hipSuccess)
+        return fail(device_error("upload arcs", he));
+    if (g->has_xy) {
+        if ((rc = ensure(g->xy, n * 8ull)) != PPSP_OK) return fail(rc);
+        if ((he = hipMemcpyAsync(g->xy.p, coord_fx, n * 8ull, hipMemcpyHostToDevice, st)) != hipSuccess)
+            return fail(device_error("upload coordinates", he));
+    }
+    if ((he = hipStreamSynchronize(st)) != hipSuccess) return fail(device_error("graph upload sync", he));
+    *out = g;
+    return PPSP_OK;
+}
+
+int ppsp_graph_destroy(ppsp_graph g) {
+    if (!g) return PPSP_OK;
+    (void)hipSetDevice(g->device);
+    if (g->st) (void)hipStreamSynchronize(g->st);
+    DevBuf *bufs[] = {&g->row_ptr, &g->arcs, &g->xy, &g->S, &g->flags, &g->q0, &g->q1, &g->sd, &g->partners,
+                      &g->pairdesc, &g->theta, &g->delta, &g->bound, &g->done, &g->exh, &g->cnt, &g->minkey,
+                      &g->mu, &g->qcount, &g->err, &g->stats, &g->pathlen, &g->pathoff, &g->pathbuf};
+    for (DevBuf *b : bufs) release(*b);
+    for (hipEvent_t e : g->ev) (void)hipEventDestroy(e);
+    if (g->h_poll) (void)hipHostFree(g->h_poll);
+    if (g->st) (void)hipStreamDestroy(g->st);
+    delete g;
+    return PPSP_OK;
+}
+
+int ppsp_batch_query(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp_opts *opts, void *hip_stream,
+                     uint64_t *dist, uint64_t *path_off, uint32_t *path_vtx, uint64_t path_cap) {
+    return batch_impl(g, pairs, k, opts, hip_stream, dist, path_off, path_vtx, path_cap, nullptr);
+}
+
+int ppsp_query(ppsp_graph g, uint32_t s, uint32_t t, const ppsp_opts *opts, void *hip_stream, uint64_t *dist,
+               uint32_t *path, uint32_t path_cap, uint32_t *path_len) {
+    if (!g || !opts || !dist) return PPSP_E_INVALID;
+    const bool want_path = opts->flags & PPSP_WANT_PATH;
+    if (want_path && !path_len) return PPSP_E_INVALID;
+    ppsp_opts o = *opts;
+    o.batch = PPSP_BATCH_PLAIN;
+    uint32_t pr[2] = {s, t};
+    uint64_t off[2] = {0, 0};
+    uint32_t need = 0;
+    uint64_t d = 0;
+    int rc = batch_impl(g, pr, 1, &o, hip_stream, &d, want_path ? off : nullptr, path, path ? path_cap : 0, &need);
+    if (rc == PPSP_E_PATHCAP) { *path_len = need; return rc; }
+    if (rc != PPSP_OK) return rc;
+    *dist = d;
+    if (want_path) *path_len = (uint32_t)(off[1] - off[0]);
+    return PPSP_OK;
+}
+
+int ppsp_last_stats(ppsp_graph g, ppsp_stats *s) {
+    if (!g || !s) return PPSP_E_INVALID;
+    *s = g->last;
+    return PPSP_OK;
+}
+
+int ppsp_set_option(ppsp_graph g, const char *name, int64_t v) {
+    if (!g || !name) return PPSP_E_INVALID;
+    std::string k(name);
+    if (k == "profile") g->opt_profile = v;
+    else if (k == "rounds_per_sync") { if (v < 1) return PPSP_E_INVALID; g->opt_rounds_per_sync = v; }
+    else if (k == "grid_blocks") { if (v < 0) return PPSP_E_INVALID; g->opt_grid_blocks = v; }
+    else if (k == "mem_budget_mb") { if (v < 0) return PPSP_E_INVALID; g->opt_mem_budget_mb = v; }
+    else if (k == "default_delta") { if (v < 0) return PPSP_E_INVALID; g->opt_default_delta = v; }
+    else if (k == "use_graph") g->opt_use_graph = v;
+    else if (k == "timeout_ms") { if (v < 0) return PPSP_E_INVALID; g->opt_timeout_ms = v; }
+    else return PPSP_E_INVALID;
+    return PPSP_OK;
+}
+
+int ppsp_get_option(ppsp_graph g, const char *name, int64_t *v) {
+    if (!g || !name || !v) return PPSP_E_INVALID;
+    std::string k(name);
+    if (k == "profile") *v = g->opt_profile;
+    else if (k == "rounds_per_sync") *v = g->opt_rounds_per_sync;
+    else if (k == "grid_blocks") *v = g->opt_grid_blocks;
+    else if (k == "mem_budget_mb") *v = g->opt_mem_budget_mb;
+    else if (k == "default_delta") *v = (int64_t)graph_default_delta(g);
+    else if (k == "use_graph") *v = g->opt_use_graph;
+    else if (k == "timeout_ms") *v = g->opt_timeout_ms;
+    else return PPSP_E_INVALID;
+    return PPSP_OK;
+}
+
+}  // extern "C"

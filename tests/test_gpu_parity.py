@@ -1,0 +1,231 @@
+"""GPU parity: the HIP path through the C-ABI against the CPU oracle.
+
+Distances are integers and must be bit-exact (uint64, INF for unreachable).
+Paths are not unique, so they are validated instead: consecutive vertices
+are arcs, the weights sum to the distance, the ends are s and t.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import gen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+INF = oracle.INF
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+ALGOS_PLAIN = ["sssp", "et", "bids"]
+ALGOS_GEO = ["sssp", "et", "astar", "bids", "bidastar"]
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2506_16488_amd as P
+    P.lib()
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    return P
+
+
+def _graph(P, g, **kw):
+    G = P.Graph.from_host(g, **kw)
+    G.set_option("timeout_ms", 60000)
+    return G
+
+
+def _oracle(g, pairs):
+    return oracle.pp_batch(g.n, g.row_ptr, g.col, g.w, pairs)
+
+
+def _check_paths(g, pairs, dist, off, vtx):
+    for q in range(pairs.shape[0]):
+        s, t = int(pairs[q, 0]), int(pairs[q, 1])
+        path = vtx[int(off[q]):int(off[q + 1])]
+        if dist[q] == INF:
+            assert path.shape[0] == 0
+            continue
+        rc = oracle.check_path(g.n, g.row_ptr, g.col, g.w, path, s, t, int(dist[q]))
+        assert rc == (0, 0), (q, s, t, rc)
+
+
+def test_config1_grid_all_modes(P):
+    g = gen.config_graph(1)
+    pairs = gen.config_pairs(1, g)
+    exp = _oracle(g, pairs)
+    G = _graph(P, g)
+    for algo in ALGOS_PLAIN:
+        for batch in ["plainstar", "plain"]:
+            got = G.batch_query(pairs, algo=algo, batch=batch)
+            assert np.array_equal(got, exp), (algo, batch)
+    got = G.batch_query(pairs, algo="bids", batch="multi")
+    assert np.array_equal(got, exp)
+    # single-query entry point and the s = t special case
+    for q in range(0, 64, 9):
+        assert G.query(int(pairs[q, 0]), int(pairs[q, 1]), algo="bids") == int(exp[q])
+    assert G.query(77, 77, algo="bids") == 0
+    assert G.query(77, 77, algo="et") == 0
+    G.close()
+
+
+def test_config1_paths(P):
+    g = gen.config_graph(1)
+    pairs = gen.config_pairs(1, g)
+    G = _graph(P, g)
+    for algo in ["et", "bids"]:
+        for batch in ["plainstar", "multi"] if algo == "bids" else ["plainstar"]:
+            dist, (off, vtx) = G.batch_query(pairs, algo=algo, batch=batch, want_path=True)
+            assert np.array_equal(dist, _oracle(g, pairs))
+            _check_paths(g, pairs, dist, off, vtx)
+    d, path = G.query(5, 60000, algo="bids", want_path=True)
+    assert oracle.check_path(g.n, g.row_ptr, g.col, g.w, path, 5, 60000, d) == (0, 0)
+    d, path = G.query(9, 9, algo="bids", want_path=True)
+    assert d == 0 and path.tolist() == [9]
+    G.close()
+
+
+@pytest.mark.parametrize("seed", range(16))
+def test_random_small_graphs_all_pairs(P, seed):
+    """Random multigraphs with zero weights, isolated vertices and several
+    components: every pair, every mode, against Floyd-Warshall."""
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(2, 60))
+    m = int(rng.integers(0, 2 * n + 2))
+    g = gen.random_graph(n, m, int(rng.choice([1, 5, 1000])), seed=seed, wmin=seed % 2)
+    D = oracle.floyd_warshall(g.n, g.row_ptr, g.col, g.w)
+    s, t = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    pairs = np.stack([s.ravel(), t.ravel()], 1).astype(np.uint32)
+    exp = D[pairs[:, 0], pairs[:, 1]]
+    G = _graph(P, g)
+    for algo in ALGOS_PLAIN:
+        assert np.array_equal(G.batch_query(pairs, algo=algo, batch="plainstar"), exp), algo
+    assert np.array_equal(G.batch_query(pairs, algo="bids", batch="multi"), exp)
+    G.close()
+
+
+def test_golden_fixtures_gpu(P):
+    from test_oracle_pins import _read_golden
+    for name in sorted(f for f in os.listdir(GOLDEN) if f.endswith(".graph")):
+        g, queries = _read_golden(name)
+        G = _graph(P, g)
+        pairs = np.array([[s, t] for s, t, _ in queries], np.uint32)
+        exp = np.array([d for _, _, d in queries], np.uint64)
+        for algo in ALGOS_PLAIN:
+            for batch in ["plainstar", "plain"]:
+                assert np.array_equal(G.batch_query(pairs, algo=algo, batch=batch), exp), (name, algo)
+        assert np.array_equal(G.batch_query(pairs, algo="bids", batch="multi"), exp), name
+        G.close()
+
+
+@pytest.mark.parametrize("L,p", [(40, 0.3), (200, 0.05)])
+def test_lattice_heuristic_modes(P, L, p):
+    g = gen.lattice(L, p, seed=L)
+    pairs = gen.pairs_uniform(g.n, 100, seed=L + 1)
+    exp = _oracle(g, pairs)
+    G = _graph(P, g)
+    for algo in ALGOS_GEO:
+        got = G.batch_query(pairs, algo=algo, batch="plainstar")
+        assert np.array_equal(got, exp), algo
+    dist, (off, vtx) = G.batch_query(pairs[:20], algo="bidastar", want_path=True)
+    _check_paths(g, pairs[:20], dist, off, vtx)
+    dist, (off, vtx) = G.batch_query(pairs[:20], algo="astar", want_path=True)
+    _check_paths(g, pairs[:20], dist, off, vtx)
+    G.close()
+
+
+def test_schedule_invariance(P):
+    """Any threshold sequence gives the same distances (Theorems
+    bids-correctness and bdastar-correctness hold for every stepping rule)."""
+    g = gen.lattice(96, 0.1, seed=3)
+    pairs = gen.pairs_uniform(g.n, 60, seed=4)
+    exp = _oracle(g, pairs)
+    G = _graph(P, g)
+    for delta in [1, int(g.w.min()), 1000, 5000, 1 << 30]:
+        for algo in ["bids", "bidastar", "astar", "et"]:
+            assert np.array_equal(G.batch_query(pairs, algo=algo, delta=delta), exp), (delta, algo)
+    G.close()
+
+
+def test_batch_equals_alone_and_repeatable(P):
+    g = gen.config_graph(1)
+    pairs = gen.pairs_uniform(g.n, 40, seed=9)
+    G = _graph(P, g)
+    batch = G.batch_query(pairs, algo="bids", batch="multi")
+    for q in range(0, 40, 5):
+        assert G.query(int(pairs[q, 0]), int(pairs[q, 1]), algo="bids") == int(batch[q])
+    for _ in range(5):
+        assert np.array_equal(G.batch_query(pairs, algo="bids", batch="plainstar"), batch)
+    G.close()
+
+
+def test_hub_batch_multi(P):
+    g = gen.lattice(128, 0.05, seed=6)
+    pairs = gen.pairs_hub(g.n, 4, 40, 80, seed=7)
+    pairs = np.concatenate([pairs, pairs[:5, ::-1], pairs[:3]])        # mirrored and repeated
+    exp = _oracle(g, pairs)
+    G = _graph(P, g)
+    for batch in ["multi", "plainstar", "plain"]:
+        assert np.array_equal(G.batch_query(pairs, algo="bids", batch=batch), exp), batch
+    dist, (off, vtx) = G.batch_query(pairs, algo="bids", batch="multi", want_path=True)
+    _check_paths(g, pairs, dist, off, vtx)
+    G.close()
+
+
+def test_memory_waves(P):
+    """A state budget below the batch size forces several waves."""
+    g = gen.config_graph(1)
+    pairs = gen.config_pairs(1, g)
+    exp = _oracle(g, pairs)
+    G = _graph(P, g)
+    G.set_option("mem_budget_mb", 8)          # ~15 searches of 65,536 vertices per wave
+    for batch in ["plainstar", "multi"]:
+        assert np.array_equal(G.batch_query(pairs, algo="bids", batch=batch), exp)
+        assert G.stats()["waves"] > 1
+    G.close()
+
+
+def test_error_paths(P):
+    g = gen.grid(8, 8, 1, 5, seed=1)
+    G = _graph(P, g)
+    with pytest.raises(P.PPSPError) as e:
+        G.query(0, 64, algo="bids")
+    assert e.value.code == P.E_RANGE
+    with pytest.raises(P.PPSPError) as e:
+        G.query(0, 5, algo="astar")
+    assert e.value.code == P.E_NOCOORD
+    with pytest.raises(P.PPSPError) as e:
+        G.batch_query(np.array([[0, 5]]), algo="et", batch="multi")
+    assert e.value.code == P.E_INVALID
+    G.close()
+    d = gen.csr_from_edges(3, [0, 1], [1, 2], [1, 1], symmetric=False)
+    D = P.Graph(d.n, d.row_ptr, d.col, d.w, symmetric=False)
+    with pytest.raises(P.PPSPError) as e:
+        D.query(0, 2, algo="bids")
+    assert e.value.code == P.E_NOTSYM
+    assert D.query(0, 2, algo="et") == 2
+    assert D.query(2, 0, algo="et") == INF                 # directed: unreachable backwards
+    D.close()
+    z = gen.csr_from_edges(3, [0, 1], [1, 2], [0, 4])
+    Z = P.Graph(z.n, z.row_ptr, z.col, z.w)
+    assert Z.query(0, 2, algo="bids") == 4
+    with pytest.raises(P.PPSPError) as e:
+        Z.query(0, 2, algo="bids", want_path=True)
+    assert e.value.code == P.E_NOPATH
+    Z.close()
+
+
+@pytest.mark.slow
+def test_config2_full_size_sampled(P):
+    """The 2048^2 road-like lattice with all 1,000 pairs in one Plain* batch
+    (the benchmark's launch configuration); 48 sampled pairs vs the oracle."""
+    g = gen.config_graph(2)
+    pairs = gen.config_pairs(2, g)
+    G = _graph(P, g)
+    got = {a: G.batch_query(pairs, algo=a, batch="plainstar") for a in ["bidastar", "bids"]}
+    idx = np.arange(0, 1000, 21)
+    exp = _oracle(g, pairs[idx])
+    for a in got:
+        assert np.array_equal(got[a][idx], exp), a
+    assert np.array_equal(got["bids"], got["bidastar"])
+    G.close()
