@@ -109,6 +109,7 @@ typedef struct {
     double wall_ms;            /* host wall time of the call */
     double relax_kernel_ms;    /* summed duration of the round kernel (profiling on), else 0 */
     uint64_t relax_launches;   /* number of round-kernel launches */
+    uint64_t carried;          /* entries kept for a later round (key above the threshold) */
 } ppsp_stats;
 
 typedef struct ppsp_graph_s *ppsp_graph;
@@ -182,9 +183,14 @@ int ppsp_last_stats(ppsp_graph g, ppsp_stats *stats);
  * launch shapes and bookkeeping):
  *   "profile"         1: time every round-kernel launch with HIP events
  *   "rounds_per_sync" rounds launched between host checks for termination
- *   "grid_blocks"     blocks of the round kernel (0 = 4 per compute unit)
+ *   "grid_blocks"     single-wave workgroups of the round kernel (0 = 24 per compute unit)
  *   "mem_budget_mb"   cap on the search-state memory of one wave (0 = auto)
- *   "default_delta"   Delta (distance units) used when opts.delta = 0
+ *   "default_delta"   Delta (distance units) used when opts.delta = 0 (0 = 2 x mean arc weight)
+ *   "theta_mode"      0: Delta*-stepping, the threshold grows by Delta every round
+ *                     (raised to the smallest frontier key when a step would be
+ *                     empty); 1: the threshold is the end of the Delta-wide bucket
+ *                     holding the smallest frontier key (Delta-stepping buckets);
+ *                     2 (default): the smallest frontier key + Delta - 1
  *   "use_graph"       1: replay rounds through a captured hipGraph
  *   "timeout_ms"      host-side limit on one wave's round loop (0 = none)
  * Returns PPSP_E_INVALID for an unknown name.

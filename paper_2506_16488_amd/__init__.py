@@ -52,7 +52,8 @@ class Stats(ctypes.Structure):
                 ("scanned_vertices", ctypes.c_uint64), ("scanned_arcs", ctypes.c_uint64),
                 ("relax_success", ctypes.c_uint64), ("searches", ctypes.c_uint64),
                 ("waves", ctypes.c_uint64), ("wall_ms", ctypes.c_double),
-                ("relax_kernel_ms", ctypes.c_double), ("relax_launches", ctypes.c_uint64)]
+                ("relax_kernel_ms", ctypes.c_double), ("relax_launches", ctypes.c_uint64),
+                ("carried", ctypes.c_uint64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

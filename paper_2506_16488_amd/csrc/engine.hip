@@ -31,8 +31,8 @@
 
 namespace ppsp {
 hipError_t launch_init(const RoundArgs &A, hipStream_t st);
-hipError_t launch_round(const RoundArgs &A, uint32_t par, uint32_t grid, hipStream_t st);
-hipError_t launch_control(const RoundArgs &A, uint32_t par, hipStream_t st);
+hipError_t launch_round(const RoundArgs &A, uint32_t grid, hipStream_t st);
+hipError_t launch_control(const RoundArgs &A, hipStream_t st);
 hipError_t launch_path_len(const RoundArgs &A, const PairDesc *pd, uint32_t *len, hipStream_t st);
 hipError_t launch_path_write(const RoundArgs &A, const PairDesc *pd, const uint32_t *len, const uint64_t *off,
                              uint32_t *out, hipStream_t st);
@@ -91,6 +91,7 @@ int device_error(const char *what, hipError_t e) {
 
 // A query slot of one wave: which searches meet in it and where the answer goes.
 struct Plan {
+    uint32_t G = 1;                 // searches per interleaved state group
     std::vector<SearchDesc> sd;
     std::vector<Partner> partners;
     std::vector<PairDesc> pairs;
@@ -107,10 +108,10 @@ struct ppsp_graph_s {
     uint32_t wmin = 0, wmax = 0, fb = 0, w_scale = 0;
     uint64_t ws2 = 0;
     std::vector<int32_t> h_xy;      // host copy of coordinates (for descriptors)
-    DevBuf row_ptr, arcs, xy;
+    DevBuf row_ptr, arcs, xy, in_row_ptr, in_arcs;   // transpose only for a directed graph
     // workspace (grow only)
-    DevBuf S, flags, q0, q1, sd, partners, pairdesc, theta, delta, bound, done, exh, cnt, minkey, mu, qcount,
-        err, stats, pathlen, pathoff, pathbuf;
+    DevBuf S, q0, q1, sd, partners, pairdesc, ctl, delta, done, exh, alive, minkey, mu, qcount, cpre, round, err,
+        stats, wstats, pathlen, pathoff, pathbuf;
     hipStream_t st = nullptr;
     uint32_t *h_poll = nullptr;     // pinned
     std::vector<hipEvent_t> ev;
@@ -118,7 +119,8 @@ struct ppsp_graph_s {
     int cu = 256;
     // options
     int64_t opt_profile = 0, opt_rounds_per_sync = 16, opt_grid_blocks = 0, opt_mem_budget_mb = 0,
-            opt_default_delta = 0, opt_use_graph = 0, opt_timeout_ms = 600000;
+            opt_default_delta = 0, opt_use_graph = 0, opt_timeout_ms = 600000, opt_theta_mode = 2;
+    uint64_t wmean = 1;             // mean arc weight (rounded up)
     uint64_t qcap = 0;
 };
 
@@ -135,21 +137,18 @@ uint64_t key_delta(uint32_t kind, uint64_t d) {
 
 uint64_t graph_default_delta(ppsp_graph g) {
     if (g->opt_default_delta > 0) return (uint64_t)g->opt_default_delta;
-    return std::max<uint64_t>(1, 2ull * g->wmax);
+    return std::max<uint64_t>(1, 2 * g->wmean);
 }
 
-// Bytes of search state per search (slab + both frontier bitmaps).
-uint64_t state_bytes_per_search(ppsp_graph g) {
-    uint64_t fw = ((uint64_t)g->n + 31) / 32;
-    return (uint64_t)g->n * 8 + 2 * fw * 4;
-}
+// Bytes of search state per search.
+uint64_t state_bytes_per_search(ppsp_graph g) { return (uint64_t)g->n * 8; }
 
 uint64_t state_budget(ppsp_graph g) {
     if (g->opt_mem_budget_mb > 0) return (uint64_t)g->opt_mem_budget_mb << 20;
     size_t fr = 0, tot = 0;
     if (hipMemGetInfo(&fr, &tot) != hipSuccess) { (void)hipGetLastError(); return 1ull << 30; }
-    uint64_t have = fr + g->S.bytes + g->flags.bytes;   // reusable
-    uint64_t reserve = (2ull << 30) + 2 * g->qcap * 8;  // queues and small buffers
+    uint64_t have = fr + g->S.bytes;   // reusable
+    uint64_t reserve = (2ull << 30) + 2 * g->qcap * 16;  // queues and small buffers
     return have > reserve ? (uint64_t)((have - reserve) * 0.9) : (1ull << 28);
 }
 
@@ -159,10 +158,12 @@ uint64_t search_limit(ppsp_graph g) {
     return std::max<uint64_t>(lim, 1);
 }
 
-void set_args(ppsp_graph g, RoundArgs &A, uint32_t nsearch, uint32_t npair) {
+void set_args(ppsp_graph g, RoundArgs &A, uint32_t nsearch, uint32_t npair, uint32_t G) {
     memset(&A, 0, sizeof(A));
     A.row_ptr = g->row_ptr.as<uint32_t>();
     A.arcs = g->arcs.as<uint2>();
+    A.in_row_ptr = g->symmetric ? A.row_ptr : g->in_row_ptr.as<uint32_t>();
+    A.in_arcs = g->symmetric ? A.arcs : g->in_arcs.as<uint2>();
     A.xy = g->has_xy ? g->xy.as<int2>() : nullptr;
     A.ws2 = g->ws2;
     A.fb = g->fb;
@@ -171,23 +172,25 @@ void set_args(ppsp_graph g, RoundArgs &A, uint32_t nsearch, uint32_t npair) {
     A.partners = g->partners.as<Partner>();
     A.nsearch = nsearch;
     A.npair = npair;
+    A.G = G;
     A.S = g->S.as<uint64_t>();
-    A.flags = g->flags.as<uint32_t>();
-    A.fw = ((uint64_t)g->n + 31) / 32;
-    A.theta = g->theta.as<uint64_t>();
+    A.ctl = g->ctl.as<ulonglong2>();
     A.delta = g->delta.as<uint64_t>();
-    A.bound = g->bound.as<uint64_t>();
     A.done = g->done.as<uint32_t>();
     A.exh = g->exh.as<uint32_t>();
-    A.cnt = g->cnt.as<uint32_t>();
+    A.alive = g->alive.as<uint32_t>();
     A.minkey = g->minkey.as<uint64_t>();
     A.mu = g->mu.as<uint64_t>();
-    A.q0 = g->q0.as<uint64_t>();
-    A.q1 = g->q1.as<uint64_t>();
+    A.q0 = g->q0.as<uint4>();
+    A.q1 = g->q1.as<uint4>();
     A.qcount = g->qcount.as<uint32_t>();
-    A.qcap = g->qcap;
+    A.cpre = g->cpre.as<uint32_t>();
+    A.qseg = g->qcap / NSEG;
+    A.round = g->round.as<uint32_t>();
     A.err = g->err.as<uint32_t>();
     A.stats = g->stats.as<unsigned long long>();
+    A.wstats = g->wstats.as<unsigned long long>();
+    A.theta_mode = (uint32_t)g->opt_theta_mode;
 }
 
 int ensure_events(ppsp_graph g, size_t k) {
@@ -212,22 +215,21 @@ struct WaveOut {
 int run_wave(ppsp_graph g, const Plan &P, bool want_path, WaveOut &out) {
     const uint32_t ns = (uint32_t)P.sd.size(), npair = (uint32_t)P.pairs.size();
     const uint64_t n = g->n;
-    const uint64_t fw = (n + 31) / 32;
     hipStream_t st = g->st;
     CHK(ensure(g->S, ns * n * 8));
-    CHK(ensure(g->flags, 2 * ns * fw * 4));
+    CHK(ensure(g->round, 16));
     CHK(ensure(g->sd, ns * sizeof(SearchDesc)));
     CHK(ensure(g->partners, P.partners.size() * sizeof(Partner)));
     CHK(ensure(g->pairdesc, npair * sizeof(PairDesc)));
-    CHK(ensure(g->theta, ns * 8));
+    CHK(ensure(g->ctl, ns * 16));
     CHK(ensure(g->delta, ns * 8));
-    CHK(ensure(g->bound, ns * 8));
     CHK(ensure(g->done, ns * 4));
     CHK(ensure(g->exh, ns * 4));
-    CHK(ensure(g->cnt, 2 * ns * 4));
+    CHK(ensure(g->alive, 2 * ns * 4));
     CHK(ensure(g->minkey, 2 * ns * 8));
     CHK(ensure(g->mu, npair * 8));
-    CHK(ensure(g->qcount, 16));
+    CHK(ensure(g->qcount, 2 * NSEG * 4));
+    CHK(ensure(g->cpre, 2 * (NSEG + 1) * 4));
     CHK(ensure(g->err, 16));
     CHK(ensure(g->stats, ST_N * 8));
     {
@@ -236,11 +238,12 @@ int run_wave(ppsp_graph g, const Plan &P, bool want_path, WaveOut &out) {
                                                                     1ull << 16), 1ull << 28);
         if (g->qcap < want) g->qcap = want;
     }
+    const uint32_t grid = g->opt_grid_blocks > 0 ? (uint32_t)g->opt_grid_blocks : (uint32_t)(24 * g->cu);
+    CHK(ensure(g->wstats, (uint64_t)grid * ST_N * 8));
     for (;;) {
-        CHK(ensure(g->q0, g->qcap * 8));
-        CHK(ensure(g->q1, g->qcap * 8));
+        CHK(ensure(g->q0, g->qcap * 16));
+        CHK(ensure(g->q1, g->qcap * 16));
         HIPCHK(hipMemsetAsync(g->S.p, 0xFF, ns * n * 8, st));
-        HIPCHK(hipMemsetAsync(g->flags.p, 0, 2 * ns * fw * 4, st));
         HIPCHK(hipMemcpyAsync(g->sd.p, P.sd.data(), ns * sizeof(SearchDesc), hipMemcpyHostToDevice, st));
         if (!P.partners.empty())
             HIPCHK(hipMemcpyAsync(g->partners.p, P.partners.data(), P.partners.size() * sizeof(Partner),
@@ -248,14 +251,14 @@ int run_wave(ppsp_graph g, const Plan &P, bool want_path, WaveOut &out) {
         HIPCHK(hipMemcpyAsync(g->pairdesc.p, P.pairs.data(), npair * sizeof(PairDesc), hipMemcpyHostToDevice, st));
         HIPCHK(hipMemcpyAsync(g->delta.p, P.delta.data(), ns * 8, hipMemcpyHostToDevice, st));
         HIPCHK(hipMemsetAsync(g->mu.p, 0xFF, npair * 8, st));
-        uint32_t qc[4] = {ns, 0, 0, 0};
-        HIPCHK(hipMemcpyAsync(g->qcount.p, qc, 16, hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemsetAsync(g->qcount.p, 0, 2 * NSEG * 4, st));
+        HIPCHK(hipMemsetAsync(g->wstats.p, 0, (uint64_t)grid * ST_N * 8, st));
+        HIPCHK(hipMemsetAsync(g->round.p, 0, 16, st));
         HIPCHK(hipMemsetAsync(g->err.p, 0, 16, st));
         HIPCHK(hipMemsetAsync(g->stats.p, 0, ST_N * 8, st));
         RoundArgs A;
-        set_args(g, A, ns, npair);
+        set_args(g, A, ns, npair, P.G);
         HIPCHK(launch_init(A, st));
-        const uint32_t grid = g->opt_grid_blocks > 0 ? (uint32_t)g->opt_grid_blocks : (uint32_t)(4 * g->cu);
         const int K = std::max<int64_t>(1, g->opt_rounds_per_sync);
         const bool prof = g->opt_profile != 0;
         if (prof) CHK(ensure_events(g, 2 * (size_t)K));
@@ -271,8 +274,8 @@ int run_wave(ppsp_graph g, const Plan &P, bool want_path, WaveOut &out) {
             const int Kg = K + (K & 1);
             HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
             for (int k = 0; k < Kg; k++) {
-                (void)launch_round(A, (uint32_t)(k & 1), grid, st);
-                (void)launch_control(A, (uint32_t)(k & 1), st);
+                (void)launch_round(A, grid, st);
+                (void)launch_control(A, st);
             }
             HIPCHK(hipStreamEndCapture(st, &graph));
             HIPCHK(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
@@ -285,16 +288,16 @@ int run_wave(ppsp_graph g, const Plan &P, bool want_path, WaveOut &out) {
                 r += kk;
             } else {
                 for (kk = 0; kk < K; kk++, r++) {
-                    const uint32_t par = (uint32_t)(r & 1);
                     if (prof) HIPCHK(hipEventRecord(g->ev[2 * kk], st));
-                    HIPCHK(launch_round(A, par, grid, st));
+                    HIPCHK(launch_round(A, grid, st));
                     if (prof) HIPCHK(hipEventRecord(g->ev[2 * kk + 1], st));
-                    HIPCHK(launch_control(A, par, st));
+                    HIPCHK(launch_control(A, st));
                 }
             }
             launches += kk;
-            HIPCHK(hipMemcpyAsync(g->h_poll, g->qcount.p, 16, hipMemcpyDeviceToHost, st));
-            HIPCHK(hipMemcpyAsync(g->h_poll + 4, g->err.p, 4, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipMemcpyAsync(g->h_poll, g->qcount.p, 2 * NSEG * 4, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipMemcpyAsync(g->h_poll + 2 * NSEG, g->err.p, 4, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipMemcpyAsync(g->h_poll + 2 * NSEG + 1, g->round.p, 4, hipMemcpyDeviceToHost, st));
             HIPCHK(hipStreamSynchronize(st));
             if (prof) {
                 for (int k = 0; k < kk; k++) {
@@ -303,14 +306,16 @@ int run_wave(ppsp_graph g, const Plan &P, bool want_path, WaveOut &out) {
                     relax_ms += ms;
                 }
             }
-            const uint32_t pending = g->h_poll[r & 1];
-            if (pending == 0 || g->h_poll[4] != 0) break;
+            uint64_t pending = 0;
+            const uint32_t next = g->h_poll[2 * NSEG + 1];   // round to run next
+            for (uint32_t x = 0; x < (uint32_t)NSEG; x++) pending += g->h_poll[(next & 1) * NSEG + x];
+            if (pending == 0 || g->h_poll[2 * NSEG] != 0) break;
             const double el = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
             if (g->opt_timeout_ms > 0 && el > (double)g->opt_timeout_ms) { timed_out = true; break; }
         }
         if (gexec) { (void)hipGraphExecDestroy(gexec); (void)hipGraphDestroy(graph); }
         if (timed_out) return PPSP_E_TIMEOUT;
-        const uint32_t errbits = g->h_poll[4];
+        const uint32_t errbits = g->h_poll[2 * NSEG];
         if (errbits & ERR_OVERFLOW) return PPSP_E_OVERFLOW;
         if (errbits & ERR_QUEUE) {
             // Grow the frontier queues and rerun the wave from scratch.
@@ -322,7 +327,11 @@ int run_wave(ppsp_graph g, const Plan &P, bool want_path, WaveOut &out) {
         out.mu.resize(npair);
         HIPCHK(hipMemcpyAsync(out.mu.data(), g->mu.p, npair * 8, hipMemcpyDeviceToHost, st));
         HIPCHK(hipMemcpyAsync(out.stats, g->stats.p, ST_N * 8, hipMemcpyDeviceToHost, st));
+        std::vector<unsigned long long> ws((uint64_t)grid * ST_N);
+        HIPCHK(hipMemcpyAsync(ws.data(), g->wstats.p, ws.size() * 8, hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
+        for (uint64_t b = 0; b < grid; b++)
+            for (int k = 1; k < ST_N; k++) out.stats[k] += ws[b * ST_N + k];
         out.relax_ms = relax_ms;
         out.launches = launches;
         if (want_path) {
@@ -331,9 +340,9 @@ int run_wave(ppsp_graph g, const Plan &P, bool want_path, WaveOut &out) {
             HIPCHK(launch_path_len(A, g->pairdesc.as<PairDesc>(), g->pathlen.as<uint32_t>(), st));
             std::vector<uint32_t> len(npair);
             HIPCHK(hipMemcpyAsync(len.data(), g->pathlen.p, npair * 4, hipMemcpyDeviceToHost, st));
-            HIPCHK(hipMemcpyAsync(g->h_poll + 4, g->err.p, 4, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipMemcpyAsync(g->h_poll + 2 * NSEG, g->err.p, 4, hipMemcpyDeviceToHost, st));
             HIPCHK(hipStreamSynchronize(st));
-            if (g->h_poll[4] & ERR_PATH) return PPSP_E_NOPATH;
+            if (g->h_poll[2 * NSEG] & ERR_PATH) return PPSP_E_NOPATH;
             out.path_off.assign(npair + 1, 0);
             for (uint32_t p = 0; p < npair; p++) out.path_off[p + 1] = out.path_off[p] + len[p];
             const uint64_t tot = out.path_off[npair];
@@ -426,6 +435,7 @@ void accumulate(ppsp_graph g, const WaveOut &w) {
     g->last.scanned_vertices += w.stats[ST_SCANV];
     g->last.scanned_arcs += w.stats[ST_SCANE];
     g->last.relax_success += w.stats[ST_SUCC];
+    g->last.carried += w.stats[ST_CARRY];
     g->last.relax_kernel_ms += w.relax_ms;
     g->last.relax_launches += w.launches;
     g->last.waves += 1;
@@ -451,6 +461,7 @@ int run_independent(ppsp_graph g, const std::vector<Query> &qs, const ppsp_opts 
     for (size_t q0 = 0; q0 < qs.size(); q0 += lim) {
         const size_t q1 = std::min<size_t>(qs.size(), q0 + lim);
         Plan P;
+        P.G = is_bidir(o->algo) ? 2 : 1;
         std::vector<uint32_t> ans_of_pair;
         for (size_t q = q0; q < q1; q++) {
             plan_single(g, P, qs[q].s, qs[q].t, o->algo, delta);
@@ -677,10 +688,12 @@ int ppsp_graph_create(int device, uint32_t n, uint64_t m, const uint64_t *row_pt
     for (uint32_t v = 0; v < n; v++)
         if (row_ptr[v + 1] < row_ptr[v]) return PPSP_E_INVALID;
     uint32_t wmin = UINT32_MAX, wmax = 0;
+    uint64_t wsum = 0;
     for (uint64_t e = 0; e < m; e++) {
         if (col[e] >= n) return PPSP_E_RANGE;
         wmin = std::min(wmin, w[e]);
         wmax = std::max(wmax, w[e]);
+        wsum += w[e];
     }
     if (m == 0) wmin = wmax = 1;
     if (coord_fx && coord_frac_bits > 30) return PPSP_E_RANGE;
@@ -691,6 +704,7 @@ int ppsp_graph_create(int device, uint32_t n, uint64_t m, const uint64_t *row_pt
     g->symmetric = flags & PPSP_SYMMETRIC;
     g->wmin = wmin;
     g->wmax = wmax;
+    g->wmean = m ? std::max<uint64_t>(1, (wsum + m - 1) / m) : 1;
     auto fail = [&](int rc) {
         ppsp_graph_destroy(g);
         return rc;
@@ -735,7 +749,7 @@ int ppsp_graph_create(int device, uint32_t n, uint64_t m, const uint64_t *row_pt
         g->st = nullptr;
         return fail(device_error("hipStreamCreateWithFlags", he));
     }
-    if ((he = hipHostMalloc((void **)&g->h_poll, 64, hipHostMallocDefault)) != hipSuccess) {
+    if ((he = hipHostMalloc((void **)&g->h_poll, 4096, hipHostMallocDefault)) != hipSuccess) {
         g->h_poll = nullptr;
         return fail(device_error("hipHostMalloc", he));
     }
@@ -761,6 +775,24 @@ int ppsp_graph_create(int device, uint32_t n, uint64_t m, const uint64_t *row_pt
         return fail(device_error("upload row_ptr", he));
     if (m && (he = hipMemcpyAsync(g->arcs.p, arcs.data(), m * 8, hipMemcpyHostToDevice, st)) != hipSuccess)
         return fail(device_error("upload arcs", he));
+    std::vector<uint32_t> trp;
+    std::vector<uint2> tarcs;
+    if (!g->symmetric) {
+        // transpose (in-arcs) for the tight-arc path walk
+        trp.assign(n + 1, 0);
+        for (uint64_t e = 0; e < m; e++) trp[col[e] + 1]++;
+        for (uint32_t v = 0; v < n; v++) trp[v + 1] += trp[v];
+        std::vector<uint32_t> pos(trp.begin(), trp.end() - 1);
+        tarcs.resize(m);
+        for (uint32_t u = 0; u < n; u++)
+            for (uint64_t e = row_ptr[u]; e < row_ptr[u + 1]; e++) tarcs[pos[col[e]]++] = make_uint2(u, w[e]);
+        if ((rc = ensure(g->in_row_ptr, (n + 1) * 4ull)) != PPSP_OK) return fail(rc);
+        if ((rc = ensure(g->in_arcs, std::max<uint64_t>(m, 1) * 8)) != PPSP_OK) return fail(rc);
+        if ((he = hipMemcpyAsync(g->in_row_ptr.p, trp.data(), (n + 1) * 4ull, hipMemcpyHostToDevice, st)) != hipSuccess)
+            return fail(device_error("upload transpose", he));
+        if (m && (he = hipMemcpyAsync(g->in_arcs.p, tarcs.data(), m * 8, hipMemcpyHostToDevice, st)) != hipSuccess)
+            return fail(device_error("upload transpose", he));
+    }
     if (g->has_xy) {
         if ((rc = ensure(g->xy, n * 8ull)) != PPSP_OK) return fail(rc);
         if ((he = hipMemcpyAsync(g->xy.p, coord_fx, n * 8ull, hipMemcpyHostToDevice, st)) != hipSuccess)
@@ -775,9 +807,10 @@ int ppsp_graph_destroy(ppsp_graph g) {
     if (!g) return PPSP_OK;
     (void)hipSetDevice(g->device);
     if (g->st) (void)hipStreamSynchronize(g->st);
-    DevBuf *bufs[] = {&g->row_ptr, &g->arcs, &g->xy, &g->S, &g->flags, &g->q0, &g->q1, &g->sd, &g->partners,
-                      &g->pairdesc, &g->theta, &g->delta, &g->bound, &g->done, &g->exh, &g->cnt, &g->minkey,
-                      &g->mu, &g->qcount, &g->err, &g->stats, &g->pathlen, &g->pathoff, &g->pathbuf};
+    DevBuf *bufs[] = {&g->row_ptr, &g->arcs, &g->xy, &g->in_row_ptr, &g->in_arcs, &g->S, &g->q0, &g->q1,
+                      &g->sd, &g->partners, &g->pairdesc, &g->ctl, &g->delta, &g->done, &g->exh, &g->alive,
+                      &g->minkey, &g->mu, &g->qcount, &g->cpre, &g->round, &g->err, &g->stats, &g->wstats, &g->pathlen, &g->pathoff,
+                      &g->pathbuf};
     for (DevBuf *b : bufs) release(*b);
     for (hipEvent_t e : g->ev) (void)hipEventDestroy(e);
     if (g->h_poll) (void)hipHostFree(g->h_poll);
@@ -826,6 +859,8 @@ int ppsp_set_option(ppsp_graph g, const char *name, int64_t v) {
     else if (k == "default_delta") { if (v < 0) return PPSP_E_INVALID; g->opt_default_delta = v; }
     else if (k == "use_graph") g->opt_use_graph = v;
     else if (k == "timeout_ms") { if (v < 0) return PPSP_E_INVALID; g->opt_timeout_ms = v; }
+    else if (k == "theta_mode") { if (v < 0 || v > 2) return PPSP_E_INVALID; g->opt_theta_mode = v; }
+
     else return PPSP_E_INVALID;
     return PPSP_OK;
 }
@@ -840,6 +875,8 @@ int ppsp_get_option(ppsp_graph g, const char *name, int64_t *v) {
     else if (k == "default_delta") *v = (int64_t)graph_default_delta(g);
     else if (k == "use_graph") *v = g->opt_use_graph;
     else if (k == "timeout_ms") *v = g->opt_timeout_ms;
+    else if (k == "theta_mode") *v = g->opt_theta_mode;
+
     else return PPSP_E_INVALID;
     return PPSP_OK;
 }

@@ -4,37 +4,55 @@
 // k_round followed by one launch of k_control:
 //
 //   k_round     for every frontier entry u^(i):
-//                 - UpdateDistance for u^(i) against the other copies of u
-//                   (the deferred meeting check, see below);
-//                 - Prune(u^(i)): key >= bound  -> drop;
-//                 - Extract(theta): key > theta -> keep for a later round;
-//                 - otherwise relax every arc (u, v, w) with a 64-bit
-//                   atomicMin on the packed (distance, parent) word; on a
-//                   strict decrease run UpdateDistance for v^(i) at once,
-//                   then Prune(v^(i)) and Add(v^(i)) to the next frontier.
-//   k_control   per search: next threshold theta += Delta (Delta*-stepping,
-//               Section 2), raised to the smallest key in the next frontier
-//               when steps would be empty; mumax bound over the search's
-//               queries (Table 2); termination when the frontier is empty;
-//               the disconnected-query rule of Appendix B.
+//                 - read delta[u^(i)] (and, for an interleaved bidirectional
+//                   pair, delta of the other copy in the same 16-byte load);
+//                   the key is scale * delta + the entry's stored heuristic
+//                   term, so no coordinates are read here;
+//                 - Extract(theta): key above theta -> keep for a later round;
+//                 - otherwise run UpdateDistance for u (the deferred meeting
+//                   check, see below) and Prune(u^(i)): key >= bound;
+//                 - relax every arc (u, v, w) with a 64-bit atomicMin on the
+//                   packed (distance, parent) word; on a strict decrease run
+//                   UpdateDistance for v^(i) at once, then Prune(v^(i)) and
+//                   Add(v^(i)) to the next frontier.
+//   k_control   per search: the next threshold (Delta*-stepping of Section 2:
+//               theta grows by Delta per round, raised to the smallest key of
+//               the next frontier when a step would be empty; or, in the
+//               bucketed variant, the end of the Delta bucket holding that
+//               key); the mumax bound over the search's queries (Table 2);
+//               termination when the frontier is empty; the disconnected-
+//               query rule of Appendix B.
 //
 // Meeting checks. UpdateDistance(v) needs delta of the other copies of v.
 // A value written by another wave in the same launch may not be visible
 // (per-XCD L2s are only coherent at kernel boundaries), so the check runs
 // twice: immediately after a successful relaxation (sees every earlier
-// round) and again when the entry is processed in the next round (sees the
+// round) and again when the entry is extracted in a later round (sees the
 // whole previous round). For the meeting vertex of the correctness proofs
 // (Theorems bids-correctness and bdastar-correctness) one of its two copies
 // is unpruned when it becomes exact, so that copy is added to the frontier
-// and the next-round check covers the case where both copies became exact
-// in the same round.
+// and the later check covers the case where both copies became exact in the
+// same round.
 //
-// Frontier building. Appends are aggregated per wave (ballot + mbcnt prefix,
-// one LDS atomic per wave), staged in LDS, and written to the global queue
-// with one global atomic per block and coalesced stores. Per-search counts
-// and minimum keys are reduced across the wave before their atomics.
-// Vertices of degree > HEAVY_DEG are relaxed by a whole wave (coalesced arc
-// reads), lower degrees by one lane each.
+// Frontier building. The round kernel runs one wave per workgroup and the
+// waves never wait for each other. A wave appends with a ballot + mbcnt
+// prefix into its own LDS buffer and flushes it to its queue segment with
+// one global atomic and coalesced 16-byte stores. Atomics on shared counters
+// are kept rare, because atomics on one address serialise at the memory
+// side: appends spread over NSEG segment counters, the per-search liveness
+// flag is a plain store, the per-search minimum key is only atomically
+// lowered when a plain read shows it would change, and the round kernel's
+// counters go to per-workgroup slots. Duplicate Adds are avoided with the
+// round stamp in the low half of each state word (see ppsp_dev.h). Per-search
+// counts and minimum keys are reduced across the wave before their atomics.
+// The arcs of the vertices extracted from a chunk are relaxed arc-parallel:
+// a wave scan of their degrees turns them into one list that all lanes walk,
+// so there is no per-vertex loop and no idle lane behind a vertex that was
+// only kept for a later round.
+//
+// The round number lives in device memory (written by the kernel that does
+// not read it in the same launch), so a fixed sequence of launches can be
+// captured once in a hipGraph and replayed.
 #include "ppsp_dev.h"
 
 namespace ppsp {
@@ -63,261 +81,343 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long x)
     return x;
 }
 
-__device__ __forceinline__ uint32_t *flag_word(const RoundArgs &A, uint32_t par, uint32_t i, uint32_t v) {
-    return A.flags + ((uint64_t)par * A.nsearch + i) * A.fw + (v >> 5);
+// key = scale * delta + hk (see ppsp_dev.h); never negative for a consistent heuristic.
+__device__ __forceinline__ uint64_t key_of(uint32_t kind, uint64_t d, int32_t hk) {
+    const int64_t k = (int64_t)((kind >= K_2DIST ? 2 : 1) * d) + hk;
+    return k < 0 ? 0 : (uint64_t)k;
 }
 
-// Key of vertex v at tentative distance d for a search (see ppsp_dev.h).
-__device__ __forceinline__ uint64_t make_key(const RoundArgs &A, const SearchDesc &sd, uint64_t d, uint32_t v) {
-    switch (sd.kind) {
-        case K_DIST: return d;
-        case K_2DIST: return 2 * d;
-        case K_ASTAR: {
-            int2 p = A.xy[v];
-            return d + heur(p.x, p.y, sd.tx, sd.ty, A.ws2, A.fb);
-        }
-        default: {
-            int2 p = A.xy[v];
-            int64_t h2 = (int64_t)heur(p.x, p.y, sd.tx, sd.ty, A.ws2, A.fb) -
-                         (int64_t)heur(p.x, p.y, sd.sx, sd.sy, A.ws2, A.fb);
-            int64_t k = (int64_t)(2 * d) + (sd.kind == K_BIDA_F ? h2 : -h2);
-            return k < 0 ? 0 : (uint64_t)k;   // never negative for a consistent heuristic
-        }
-    }
+// Heuristic term of vertex v for a search: 0, h_t(v), h_t(v) - h_s(v) or h_s(v) - h_t(v).
+__device__ __forceinline__ int32_t hterm(const RoundArgs &A, const SearchDesc &sd, uint32_t v) {
+    if (sd.kind == K_DIST || sd.kind == K_2DIST) return 0;
+    const int2 p = A.xy[v];
+    const int64_t ht = (int64_t)heur(p.x, p.y, sd.tx, sd.ty, A.ws2, A.fb);
+    if (sd.kind == K_ASTAR) return (int32_t)ht;
+    const int64_t hs = (int64_t)heur(p.x, p.y, sd.sx, sd.sy, A.ws2, A.fb);
+    return (int32_t)(sd.kind == K_BIDA_F ? ht - hs : hs - ht);
 }
 
-// UpdateDistance (Table 2) of copy v^(i) at distance d.
-__device__ __forceinline__ void meet_check(const RoundArgs &A, const SearchDesc &sd, uint32_t d, uint32_t v) {
+__device__ __forceinline__ void mu_update(const RoundArgs &A, uint32_t pair, uint64_t sum, uint32_t v) {
+    if (sum >= INF32) { atomicOr(A.err, ERR_OVERFLOW); return; }
+    unsigned long long *mp = (unsigned long long *)(A.mu + pair);
+    if (sum < (*mp >> 32)) atomicMin(mp, (sum << 32) | v);
+}
+
+// UpdateDistance (Table 2) of copy v^(i) at distance d against every query
+// of the search (one-sided searches meet their target, others the copies
+// of their query-graph neighbours).
+__device__ __forceinline__ void meet_list(const RoundArgs &A, const SearchDesc &sd, uint32_t d, uint32_t v) {
     for (uint32_t p = sd.pbeg; p < sd.pend; p++) {
-        Partner pt = A.partners[p];
-        uint64_t sum;
+        const Partner pt = A.partners[p];
         if (pt.other & TARGET_BIT) {
-            if (v != (pt.other & ~TARGET_BIT)) continue;
-            sum = d;
+            if (v == (pt.other & ~TARGET_BIT)) mu_update(A, pt.pair, d, v);
         } else {
-            uint32_t dj = (uint32_t)(A.S[(uint64_t)pt.other * A.n + v] >> 32);
-            if (dj == INF32) continue;
-            sum = (uint64_t)d + dj;
-        }
-        if (sum >= INF32) { atomicOr(A.err, ERR_OVERFLOW); continue; }
-        unsigned long long *mp = (unsigned long long *)(A.mu + pt.pair);
-        if (sum < (*mp >> 32)) atomicMin(mp, (sum << 32) | v);
-    }
-}
-
-// LDS staging area of one block.
-struct Stage {
-    uint64_t buf[STAGE_CAP];
-    uint32_t count;   // slots handed out
-    uint32_t fail;    // first slot of a wave that did not fit (valid prefix length)
-    uint32_t base;    // global position of this flush
-};
-
-// Wave-aggregated append of the lanes with pred set. Must be reached by
-// every lane of the wave.
-__device__ __forceinline__ void stage_push(Stage &st, bool pred, uint64_t entry, uint64_t *qout,
-                                           uint32_t *qcout, uint64_t qcap, uint32_t *err) {
-    uint64_t mask = __ballot(pred);
-    if (mask == 0) return;
-    uint32_t c = __popcll(mask);
-    uint32_t off = mbcnt64(mask);
-    int leader = __ffsll((unsigned long long)mask) - 1;
-    uint32_t pos = 0;
-    if ((int)lane_id() == leader) pos = atomicAdd(&st.count, c);
-    pos = __shfl(pos, leader);
-    if (pos + c <= (uint32_t)STAGE_CAP) {
-        if (pred) st.buf[pos + off] = entry;
-    } else {
-        uint32_t g = 0;
-        if ((int)lane_id() == leader) {
-            atomicMin(&st.fail, pos);
-            g = atomicAdd(qcout, c);
-        }
-        g = __shfl(g, leader);
-        if (pred) {
-            uint64_t at = (uint64_t)g + off;
-            if (at < qcap) qout[at] = entry; else atomicOr(err, ERR_QUEUE);
+            const uint32_t dj = (uint32_t)(A.S[state_index(A.G, A.n, pt.other, v)] >> 32);
+            if (dj != INF32) mu_update(A, pt.pair, (uint64_t)d + dj, v);
         }
     }
 }
 
-// Block-wide flush of the staged entries. Every thread of the block calls it.
-__device__ __forceinline__ void stage_flush(Stage &st, uint64_t *qout, uint32_t *qcout, uint64_t qcap,
-                                            uint32_t *err) {
-    __syncthreads();
-    uint32_t c = min(st.count, st.fail);
-    if (threadIdx.x == 0) st.base = c ? atomicAdd(qcout, c) : 0u;
-    __syncthreads();
-    uint64_t b = st.base;
-    for (uint32_t j = threadIdx.x; j < c; j += BLOCK) {
-        if (b + j < qcap) qout[b + j] = st.buf[j]; else atomicOr(err, ERR_QUEUE);
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) { st.count = 0; st.fail = STAGE_CAP; }
-    __syncthreads();
-}
-
-// Per-search frontier statistics of the appends of this wave: one atomic
-// per wave when the appending lanes share a search.
+// Per-search frontier statistics of this wave: whether the search added
+// anything (a plain store of 1) and the smallest key seen (an atomicMin only
+// when a plain read shows it would lower the value). The lanes of a wave
+// usually share one search, so the reduction is per wave.
 __device__ __forceinline__ void search_stats(const RoundArgs &A, uint32_t np, uint32_t i, uint32_t cnt,
                                              uint64_t mink) {
-    bool has = cnt > 0;
-    uint64_t mask = __ballot(has);
+    const bool has = cnt > 0 || mink != INF64;
+    const uint64_t mask = __ballot(has);
     if (mask == 0) return;
-    int leader = __ffsll((unsigned long long)mask) - 1;
-    uint32_t i0 = __shfl(i, leader);
+    const int leader = __ffsll((unsigned long long)mask) - 1;
+    const uint32_t i0 = __shfl(i, leader);
     if (__all(!has || i == i0)) {
-        uint32_t tot = wave_sum_u32(cnt);
-        uint64_t mn = wave_min_u64(has ? mink : INF64);
+        const uint32_t tot = wave_sum_u32(has ? cnt : 0u);
+        const uint64_t mn = wave_min_u64(has ? mink : INF64);
         if ((int)lane_id() == leader) {
-            atomicAdd(&A.cnt[(uint64_t)np * A.nsearch + i0], tot);
-            atomicMin((unsigned long long *)&A.minkey[(uint64_t)np * A.nsearch + i0], mn);
+            uint32_t *al = &A.alive[(uint64_t)np * A.nsearch + i0];
+            if (tot && *al == 0) *al = 1;
+            unsigned long long *mp = (unsigned long long *)&A.minkey[(uint64_t)np * A.nsearch + i0];
+            if (mn < *mp) atomicMin(mp, mn);
         }
     } else if (has) {
-        atomicAdd(&A.cnt[(uint64_t)np * A.nsearch + i], cnt);
-        atomicMin((unsigned long long *)&A.minkey[(uint64_t)np * A.nsearch + i], mink);
+        uint32_t *al = &A.alive[(uint64_t)np * A.nsearch + i];
+        if (cnt && *al == 0) *al = 1;
+        unsigned long long *mp = (unsigned long long *)&A.minkey[(uint64_t)np * A.nsearch + i];
+        if (mink < *mp) atomicMin(mp, mink);
     }
 }
 
-// Relaxation of arc e out of u^(i) (Algorithm 2, inner loop). Returns true
-// if v^(i) must be added to the next frontier (*vout, key folded into *lmin).
+// Relaxation of arc e out of u^(i) (Algorithm 2, inner loop) in the round
+// whose stamp is `stamp`. Returns true if v^(i) must be added to the next
+// frontier; *out is that entry. *lmin takes the key of every unpruned
+// decrease (added now or by an earlier decrease of this round).
 __device__ __forceinline__ bool relax_arc(const RoundArgs &A, const SearchDesc &sd, uint32_t i, uint32_t u,
-                                          uint32_t du, uint64_t bnd, uint32_t e, uint32_t np,
-                                          uint32_t *vout, uint64_t *lmin, unsigned long long *succ) {
-    uint2 a = A.arcs[e];
-    uint32_t v = a.x;
-    uint64_t cand = (uint64_t)du + a.y;
+                                          uint32_t du, uint64_t bnd, uint32_t e, uint32_t stamp, uint4 *out,
+                                          uint64_t *lmin, unsigned long long *succ) {
+    const uint2 a = A.arcs[e];
+    const uint32_t v = a.x;
+    const uint64_t cand = (uint64_t)du + a.y;
     if (cand >= INF32) { atomicOr(A.err, ERR_OVERFLOW); return false; }
-    unsigned long long *sv = (unsigned long long *)(A.S + (uint64_t)i * A.n + v);
-    uint64_t cur = *sv;                 // possibly stale, never below the true value
-    if (cand >= (cur >> 32)) return false;
-    uint64_t old = atomicMin(sv, (cand << 32) | u);
+    unsigned long long *p;
+    uint64_t own, other = INF64;
+    if (A.G == 2) {
+        const uint64_t base = state_index(2, A.n, i & ~1u, v);
+        const ulonglong2 w = *(const ulonglong2 *)(A.S + base);   // possibly stale: never below the truth
+        own = (i & 1) ? w.y : w.x;
+        other = (i & 1) ? w.x : w.y;
+        p = (unsigned long long *)(A.S + base + (i & 1));
+    } else {
+        p = (unsigned long long *)(A.S + state_index(1, A.n, i, v));
+        own = *p;
+    }
+    if (cand >= (own >> 32)) return false;
+    const uint64_t old = atomicMin(p, (cand << 32) | stamp);
     if (cand >= (old >> 32)) return false;
     (*succ)++;
-    meet_check(A, sd, (uint32_t)cand, v);
-    uint64_t kv = make_key(A, sd, cand, v);
+    if (A.G == 2) {
+        const uint32_t dp = (uint32_t)(other >> 32);
+        if (dp != INF32) mu_update(A, A.partners[sd.pbeg].pair, cand + dp, v);
+    } else {
+        meet_list(A, sd, (uint32_t)cand, v);
+    }
+    const int32_t hk = hterm(A, sd, v);
+    const uint64_t kv = key_of(sd.kind, cand, hk);
     if (kv >= bnd) return false;        // Prune(v) before Add(v)
-    uint32_t bit = 1u << (v & 31);
-    uint32_t ob = atomicOr(flag_word(A, np, i, v), bit);
-    if (ob & bit) return false;         // already in the next frontier
-    *vout = v;
     if (kv < *lmin) *lmin = kv;
+    // Lowered before in this round: that lowering added v unless it was pruned.
+    if ((uint32_t)old == stamp && key_of(sd.kind, old >> 32, hk) < bnd) return false;
+    *out = make_uint4(i, v, stamp, (uint32_t)hk);
     return true;
 }
 
-__global__ __launch_bounds__(BLOCK) void k_round(RoundArgs A, uint32_t par) {
-    __shared__ Stage st;
-    if (threadIdx.x == 0) { st.count = 0; st.fail = STAGE_CAP; }
-    __syncthreads();
-    // entries past the capacity were never stored (the overflow is reported)
-    const uint32_t nent = (uint32_t)min((uint64_t)A.qcount[par], A.qcap);
-    const uint64_t *qin = par ? A.q1 : A.q0;
-    uint64_t *qout = par ? A.q0 : A.q1;
-    uint32_t *qcout = &A.qcount[par ^ 1];
-    const uint32_t np = par ^ 1;
-    if (blockIdx.x == 0 && threadIdx.x == 0 && nent > 0) atomicAdd(&A.stats[ST_ROUNDS], 1ull);
-    unsigned long long c_ent = 0, c_sv = 0, c_se = 0, c_succ = 0;
+// LDS staging of one wave's frontier adds. The wave appends with a ballot
+// + mbcnt prefix (no atomics: the count is wave-uniform) and flushes to the
+// global queue with one atomic and coalesced 16-byte stores.
+struct WaveStage {
+    uint4 buf[WSTAGE];
+};
 
-    for (uint64_t base = (uint64_t)blockIdx.x * BLOCK; base < nent; base += (uint64_t)gridDim.x * BLOCK) {
-        const uint64_t idx = base + threadIdx.x;
-        uint32_t i = 0, u = 0, du = 0, rb = 0, re = 0;
+__device__ __forceinline__ void wstage_flush(WaveStage &st, uint32_t &cnt, uint4 *qout, uint32_t *qcout,
+                                             uint64_t qseg, uint32_t *err) {
+    if (cnt == 0) return;
+    __syncthreads();                       // one wave per block: orders the LDS writes before the reads
+    uint32_t base = 0;
+    if (lane_id() == 0) base = atomicAdd(qcout, cnt);
+    base = __shfl(base, 0);
+    for (uint32_t j = lane_id(); j < cnt; j += WAVE) {
+        if ((uint64_t)base + j < qseg) qout[(uint64_t)base + j] = st.buf[j]; else atomicOr(err, ERR_QUEUE);
+    }
+    __syncthreads();
+    cnt = 0;
+}
+
+// Appends the entries of the lanes with pred set; flushes first if the
+// buffer could overflow. Every lane of the wave calls it.
+__device__ __forceinline__ void wstage_push(WaveStage &st, uint32_t &cnt, bool pred, uint4 entry, uint4 *qout,
+                                            uint32_t *qcout, uint64_t qseg, uint32_t *err) {
+    const uint64_t mask = __ballot(pred);
+    if (mask == 0) return;
+    if (cnt + WAVE > (uint32_t)WSTAGE) wstage_flush(st, cnt, qout, qcout, qseg, err);
+    if (pred) st.buf[cnt + mbcnt64(mask)] = entry;
+    cnt += __popcll(mask);
+}
+
+// Wave-wide exclusive prefix sum; *total receives the sum.
+__device__ __forceinline__ uint32_t wave_exscan(uint32_t v, uint32_t *total) {
+    const uint32_t lane = lane_id();
+    uint32_t x = v;
+    for (int o = 1; o < WAVE; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o);
+        if (lane >= (uint32_t)o) x += y;
+    }
+    *total = __shfl(x, WAVE - 1);
+    return x - v;
+}
+
+// Extracted vertices of one wave chunk, for the arc-parallel relaxation.
+struct Advance {
+    uint32_t off[WAVE + 1];   // exclusive prefix of the extracted degrees (0 for other lanes)
+    uint32_t i[WAVE], u[WAVE], du[WAVE], rb[WAVE];
+    uint64_t bnd[WAVE];
+};
+
+// One round. Workgroups are single waves that work independently (no
+// barriers between waves): each takes WAVE-entry chunks of its sub-queue.
+__global__ __launch_bounds__(WAVE) void k_round(RoundArgs A) {
+    __shared__ WaveStage st;
+    __shared__ Advance adv;
+    uint32_t scnt = 0;
+    const uint32_t r = A.round[0];
+    const uint32_t par = r & 1, np = par ^ 1, stamp = r + 1;
+    const uint32_t sego = blockIdx.x % NSEG;                // segment this wave appends to
+    const uint4 *qin = par ? A.q1 : A.q0;
+    uint4 *qout = (par ? A.q0 : A.q1) + (uint64_t)sego * A.qseg;
+    uint32_t *qcout = &A.qcount[np * NSEG + sego];
+    const uint32_t *cpre = A.cpre + par * (NSEG + 1);
+    const uint32_t nchunks = cpre[NSEG];
+    if (blockIdx.x == 0 && lane_id() == 0) {
+        A.round[1] = r;                                    // for k_control
+        if (nchunks) atomicAdd(&A.stats[ST_ROUNDS], 1ull);
+    }
+    unsigned long long c_ent = 0, c_sv = 0, c_se = 0, c_succ = 0, c_keep = 0;
+
+    for (uint32_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+        uint32_t lo = 0, hi = NSEG;                        // cpre[lo] <= ch < cpre[hi]
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (cpre[mid] <= ch) lo = mid; else hi = mid;
+        }
+        const uint64_t nseg = min((uint64_t)A.qcount[par * NSEG + lo], A.qseg);
+        const uint64_t base = (uint64_t)(ch - cpre[lo]) * WAVE;
+        const uint64_t pos = base + lane_id();
+        const uint64_t idx = (uint64_t)lo * A.qseg + pos;
+        const bool valid = pos < nseg;
+
+        // 1. One entry per lane: stale, kept for later, pruned or extracted.
+        uint4 ent = make_uint4(0, 0, 0, 0);
+        uint32_t du = 0, rb = 0, re = 0;
         uint64_t key = 0, bnd = 0;
         int action = 0;  // 0 nothing, 1 keep for a later round, 2 relax
-        SearchDesc sd = {};
-        if (idx < nent) {
-            const uint64_t ent = qin[idx];
-            i = (uint32_t)(ent >> 32);
-            u = (uint32_t)ent;
+        if (valid) {
+            ent = qin[idx];
+            const uint32_t i = ent.x, u = ent.y;
             c_ent++;
-            atomicAnd(flag_word(A, par, i, u), ~(1u << (u & 31)));
-            if (!A.done[i]) {
-                sd = A.sd[i];
-                du = (uint32_t)(A.S[(uint64_t)i * A.n + u] >> 32);
-                meet_check(A, sd, du, u);
-                key = make_key(A, sd, du, u);
-                bnd = A.bound[i];
-                if (key < bnd) action = (key > A.theta[i]) ? 1 : 2;
-                if (action == 2) {
-                    rb = A.row_ptr[u];
-                    re = A.row_ptr[u + 1];
-                    c_sv++;
-                    c_se += re - rb;
+            const ulonglong2 c = A.ctl[i];
+            bnd = c.y;
+            if (bnd != 0) {
+                const SearchDesc sd = A.sd[i];
+                const int32_t hk = (int32_t)ent.w;
+                uint64_t word;
+                uint32_t dp = INF32;
+                if (A.G == 2) {
+                    const ulonglong2 w = *(const ulonglong2 *)(A.S + state_index(2, A.n, i & ~1u, u));
+                    word = (i & 1) ? w.y : w.x;
+                    dp = (uint32_t)(((i & 1) ? w.x : w.y) >> 32);
+                } else {
+                    word = A.S[state_index(1, A.n, i, u)];
+                }
+                du = (uint32_t)(word >> 32);
+                key = key_of(sd.kind, du, hk);
+                if ((uint32_t)word != ent.z && (uint32_t)word != INF32) {
+                    // lowered after this entry was added: a fresher entry exists
+                } else if (key > c.x && key < bnd) {
+                    action = 1;                     // above the threshold: later round
+                } else {
+                    if (A.G == 2) {
+                        if (dp != INF32) mu_update(A, A.partners[sd.pbeg].pair, (uint64_t)du + dp, u);
+                    } else {
+                        meet_list(A, sd, du, u);
+                    }
+                    if (key < bnd) {
+                        action = 2;
+                        rb = A.row_ptr[u];
+                        re = A.row_ptr[u + 1];
+                        c_sv++;
+                        c_se += re - rb;
+                    }
                 }
             }
         }
-        // Entries above the threshold stay in the frontier.
-        bool keep = false;
-        if (action == 1) {
-            uint32_t bit = 1u << (u & 31);
-            keep = !(atomicOr(flag_word(A, np, i, u), bit) & bit);
-        }
-        uint32_t lcnt = keep ? 1u : 0u;
-        uint64_t lmin = keep ? key : INF64;
-        stage_push(st, keep, ((uint64_t)i << 32) | u, qout, qcout, A.qcap, A.err);
+        // Entries above the threshold stay in the frontier unchanged (a
+        // lowering of the vertex in this round adds a fresher entry, which
+        // makes this one stale next round).
+        const bool keep = action == 1;
+        c_keep += keep;
+        wstage_push(st, scnt, keep, ent, qout, qcout, A.qseg, A.err);
+        search_stats(A, np, ent.x, keep ? 1u : 0u, keep ? key : INF64);
 
-        // Light vertices: one lane per vertex.
-        const uint32_t deg = (action == 2) ? re - rb : 0u;
-        const uint32_t ldeg = deg <= HEAVY_DEG ? deg : 0u;
-        for (uint32_t k = 0; __any(k < ldeg); k++) {
+        // 2. Arc-parallel relaxation of the extracted vertices: a wave scan of
+        // their degrees lays their arcs out as one list, and each lane takes
+        // one arc per step (its vertex found by binary search).
+        const uint32_t deg = action == 2 ? re - rb : 0u;
+        uint32_t T;
+        const uint32_t pre = wave_exscan(deg, &T);
+        if (T == 0) continue;
+        adv.off[lane_id()] = pre;
+        if (lane_id() == WAVE - 1) adv.off[WAVE] = pre + deg;
+        adv.i[lane_id()] = ent.x;
+        adv.u[lane_id()] = ent.y;
+        adv.du[lane_id()] = du;
+        adv.rb[lane_id()] = rb;
+        adv.bnd[lane_id()] = bnd;
+        __syncthreads();
+        for (uint32_t a0 = 0; a0 < T; a0 += WAVE) {
+            const uint32_t a = a0 + lane_id();
             bool app = false;
-            uint32_t v = 0;
-            if (k < ldeg) app = relax_arc(A, sd, i, u, du, bnd, rb + k, np, &v, &lmin, &c_succ);
-            lcnt += app;
-            stage_push(st, app, ((uint64_t)i << 32) | v, qout, qcout, A.qcap, A.err);
-        }
-        search_stats(A, np, i, lcnt, lmin);
-
-        // Heavy vertices: the whole wave walks one arc list at a time.
-        uint64_t hmask = __ballot(deg > HEAVY_DEG);
-        while (hmask) {
-            const int L = __ffsll((unsigned long long)hmask) - 1;
-            hmask &= hmask - 1;
-            const uint32_t hi = __shfl(i, L), hu = __shfl(u, L), hdu = __shfl(du, L);
-            const uint32_t hrb = __shfl(rb, L), hre = __shfl(re, L);
-            const uint64_t hbnd = __shfl(bnd, L);
-            const SearchDesc hsd = A.sd[hi];
-            uint32_t hcnt = 0;
-            uint64_t hmin = INF64;
-            for (uint32_t e0 = hrb; e0 < hre; e0 += WAVE) {
-                const uint32_t e = e0 + lane_id();
-                bool app = false;
-                uint32_t v = 0;
-                if (e < hre) app = relax_arc(A, hsd, hi, hu, hdu, hbnd, e, np, &v, &hmin, &c_succ);
-                hcnt += app;
-                stage_push(st, app, ((uint64_t)hi << 32) | v, qout, qcout, A.qcap, A.err);
+            uint4 ne = make_uint4(0, 0, 0, 0);
+            uint64_t lmin = INF64;
+            uint32_t ai = 0;
+            if (a < T) {
+                uint32_t lo = 0, hi = WAVE;               // off[lo] <= a < off[hi]
+                while (hi - lo > 1) {
+                    const uint32_t mid = (lo + hi) >> 1;
+                    if (adv.off[mid] <= a) lo = mid; else hi = mid;
+                }
+                ai = adv.i[lo];
+                const SearchDesc sd = A.sd[ai];
+                app = relax_arc(A, sd, ai, adv.u[lo], adv.du[lo], adv.bnd[lo], adv.rb[lo] + (a - adv.off[lo]), stamp,
+                                &ne, &lmin, &c_succ);
             }
-            search_stats(A, np, hi, hcnt, hmin);
+            wstage_push(st, scnt, app, ne, qout, qcout, A.qseg, A.err);
+            search_stats(A, np, ai, app ? 1u : 0u, lmin);
         }
-        stage_flush(st, qout, qcout, A.qcap, A.err);
+        __syncthreads();                          // adv is rewritten by the next chunk
     }
+    wstage_flush(st, scnt, qout, qcout, A.qseg, A.err);
     c_ent = wave_sum_u64(c_ent);
     c_sv = wave_sum_u64(c_sv);
     c_se = wave_sum_u64(c_se);
     c_succ = wave_sum_u64(c_succ);
+    c_keep = wave_sum_u64(c_keep);
     if (lane_id() == 0 && c_ent) {
-        atomicAdd(&A.stats[ST_ENTRIES], c_ent);
-        atomicAdd(&A.stats[ST_SCANV], c_sv);
-        atomicAdd(&A.stats[ST_SCANE], c_se);
-        atomicAdd(&A.stats[ST_SUCC], c_succ);
+        // this workgroup's own slot: no atomics, summed by the host
+        unsigned long long *ws = A.wstats + (uint64_t)blockIdx.x * ST_N;
+        ws[ST_CARRY] += c_keep;
+        ws[ST_ENTRIES] += c_ent;
+        ws[ST_SCANV] += c_sv;
+        ws[ST_SCANE] += c_se;
+        ws[ST_SUCC] += c_succ;
     }
 }
 
+// Prefix sum of the chunk counts of the NSEG segments of queue `q` (one
+// wave of 64 = NSEG lanes).
+__device__ __forceinline__ void chunk_prefix(const RoundArgs &A, uint32_t q) {
+    const uint32_t k = lane_id();
+    const uint32_t n = (uint32_t)min((uint64_t)A.qcount[q * NSEG + k], A.qseg);
+    const uint32_t c = (n + WAVE - 1) / WAVE;
+    uint32_t x = c;
+    for (int o = 1; o < WAVE; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o);
+        if (k >= (uint32_t)o) x += y;
+    }
+    A.cpre[q * (NSEG + 1) + k + 1] = x;
+    if (k == 0) A.cpre[q * (NSEG + 1)] = 0;
+}
+
+__global__ __launch_bounds__(WAVE) void k_seed_prefix(RoundArgs A) { chunk_prefix(A, 0); }
+
 // Per-search step control after a round (see the file comment).
-__global__ __launch_bounds__(BLOCK) void k_control(RoundArgs A, uint32_t par) {
+__global__ __launch_bounds__(BLOCK) void k_control(RoundArgs A) {
     const uint32_t i = blockIdx.x * BLOCK + threadIdx.x;
-    if (i == 0) A.qcount[par] = 0;           // the queue just consumed becomes the next output
+    const uint32_t r = A.round[1];
+    const uint32_t par = r & 1, np = par ^ 1;
+    if (blockIdx.x == 0 && threadIdx.x < WAVE) {
+        chunk_prefix(A, np);                      // chunk layout of the queue the next round reads
+        A.qcount[par * NSEG + threadIdx.x] = 0;   // the queue just consumed becomes the next output
+    }
+    if (i == 0) A.round[0] = r + 1;
     if (i >= A.nsearch) return;
-    const uint32_t np = par ^ 1;
-    const uint32_t c = A.cnt[(uint64_t)np * A.nsearch + i];
+    const uint32_t c = A.alive[(uint64_t)np * A.nsearch + i];
     const uint64_t mk = A.minkey[(uint64_t)np * A.nsearch + i];
-    A.cnt[(uint64_t)par * A.nsearch + i] = 0;
+    A.alive[(uint64_t)par * A.nsearch + i] = 0;
     A.minkey[(uint64_t)par * A.nsearch + i] = INF64;
     if (A.done[i]) return;
     const SearchDesc sd = A.sd[i];
+    const ulonglong2 c0 = A.ctl[i];
     // A frontier that ran dry while nothing could be pruned has covered the
     // whole component of its root (Appendix B, disconnected queries).
     uint32_t ex = A.exh[i];
-    if (c == 0 && A.bound[i] == INF64 && !ex) { ex = 1; A.exh[i] = 1; }
+    if (c == 0 && c0.y == INF64 && !ex) { ex = 1; A.exh[i] = 1; }
     uint64_t mx = 0;
     bool open = false;
     for (uint32_t p = sd.pbeg; p < sd.pend; p++) {
@@ -332,43 +432,84 @@ __global__ __launch_bounds__(BLOCK) void k_control(RoundArgs A, uint32_t par) {
         }
         open = true;
     }
-    A.bound[i] = sd.noprune ? INF64 : (open ? mx : 0);
-    if (c == 0 || !open) { A.done[i] = 1; return; }
-    uint64_t th = A.theta[i] + A.delta[i];
-    if (th < A.theta[i]) th = INF64;
-    if (mk != INF64 && mk > th) th = mk;
-    A.theta[i] = th;
+    const uint64_t nb = sd.noprune ? INF64 : (open ? mx : 0);
+    if (c == 0 || !open) {
+        A.done[i] = 1;
+        A.ctl[i] = make_ulonglong2(c0.x, 0);
+        return;
+    }
+    const uint64_t d = A.delta[i], th0 = c0.x;
+    uint64_t th;
+    if (A.theta_mode == 0 || mk == INF64) {
+        // Delta*-stepping: the i-th threshold is i * Delta; steps that would
+        // extract nothing are skipped by raising it to the smallest key.
+        th = th0 + d;
+        if (th < th0) th = INF64;
+        if (mk != INF64 && mk > th) th = mk;
+    } else if (A.theta_mode == 1) {
+        // Bucketed variant: extract the Delta-wide bucket that holds the
+        // smallest key; the threshold stays while that bucket refills.
+        const uint64_t b = mk / d;
+        th = (b + 1 > INF64 / d) ? INF64 : (b + 1) * d - 1;
+        if (th < th0) th = th0;
+    } else {
+        // Sliding window: everything within Delta of the smallest key.
+        th = mk + d - 1;
+        if (th < mk) th = INF64;
+        if (th < th0) th = th0;
+    }
+    A.ctl[i] = make_ulonglong2(th, nb);
 }
 
 // Init() of Table 2 for every search: delta[root] = 0, root in the frontier.
+// The host has cleared the state, the queue counters and the round counter.
 __global__ __launch_bounds__(BLOCK) void k_init(RoundArgs A) {
     const uint32_t i = blockIdx.x * BLOCK + threadIdx.x;
     if (i >= A.nsearch) return;
     const SearchDesc sd = A.sd[i];
     const uint32_t s = sd.src;
-    A.S[(uint64_t)i * A.n + s] = (uint64_t)s;             // distance 0, parent = itself
-    *flag_word(A, 0, i, s) = 1u << (s & 31);             // bitmaps were cleared; one word per search
-    A.q0[i] = ((uint64_t)i << 32) | s;
-    const uint64_t k = make_key(A, sd, 0, s);
-    A.theta[i] = k;
-    A.cnt[i] = 1;
-    A.cnt[(uint64_t)A.nsearch + i] = 0;
+    A.S[state_index(A.G, A.n, i, s)] = 0;                   // distance 0, stamp 0
+    const int32_t hk = hterm(A, sd, s);
+    const uint32_t x = i % NSEG;
+    const uint32_t pos = atomicAdd(&A.qcount[x], 1u);
+    if (pos < A.qseg) A.q0[(uint64_t)x * A.qseg + pos] = make_uint4(i, s, 0u, (uint32_t)hk);
+    else atomicOr(A.err, ERR_QUEUE);
+    const uint64_t k = key_of(sd.kind, 0, hk);
+    A.ctl[i] = make_ulonglong2(k, INF64);
+    A.alive[i] = 1;
+    A.alive[(uint64_t)A.nsearch + i] = 0;
     A.minkey[i] = k;
     A.minkey[(uint64_t)A.nsearch + i] = INF64;
     A.done[i] = 0;
     A.exh[i] = 0;
-    A.bound[i] = INF64;
 }
 
-// Length of the parent walk from v back to the root of search i (vertices
-// counted, both ends included), or 0 if the walk does not reach the root
-// within n steps.
+__device__ __forceinline__ uint32_t dist_of(const RoundArgs &A, uint32_t i, uint32_t v) {
+    return (uint32_t)(A.S[state_index(A.G, A.n, i, v)] >> 32);
+}
+
+// A predecessor of v on a shortest path from the root of search i: an
+// in-neighbour p with delta[p] + w(p,v) = delta[v] (exists for every exact
+// v != root; see ppsp_dev.h), or INF32.
+__device__ uint32_t tight_pred(const RoundArgs &A, uint32_t i, uint32_t v) {
+    const uint32_t dv = dist_of(A, i, v);
+    for (uint32_t e = A.in_row_ptr[v]; e < A.in_row_ptr[v + 1]; e++) {
+        const uint2 a = A.in_arcs[e];
+        const uint32_t dp = dist_of(A, i, a.x);
+        if (dp != INF32 && (uint64_t)dp + a.y == dv) return a.x;
+    }
+    return INF32;
+}
+
+// Length of the tight-arc walk from v back to the root of search i (vertices
+// counted, both ends included), or 0 if it does not reach the root within n
+// steps.
 __device__ uint32_t walk_len(const RoundArgs &A, uint32_t i, uint32_t v) {
     const uint32_t root = A.sd[i].src;
     uint32_t len = 1;
     while (v != root) {
-        v = (uint32_t)A.S[(uint64_t)i * A.n + v];
-        if (++len > A.n) return 0;
+        v = tight_pred(A, i, v);
+        if (v == INF32 || ++len > A.n) return 0;
     }
     return len;
 }
@@ -381,8 +522,8 @@ __global__ void k_path_len(RoundArgs A, const PairDesc *pd, uint32_t *len) {
     if ((mu >> 32) == INF32) { len[p] = 0; return; }
     const uint32_t m = (uint32_t)mu;
     const PairDesc d = pd[p];
-    uint32_t la = walk_len(A, d.a, m);
-    uint32_t lb = (d.b & TARGET_BIT) ? 1u : walk_len(A, d.b, m);
+    const uint32_t la = walk_len(A, d.a, m);
+    const uint32_t lb = (d.b & TARGET_BIT) ? 1u : walk_len(A, d.b, m);
     if (la == 0 || lb == 0) { atomicOr(A.err, ERR_PATH); len[p] = 0; return; }
     len[p] = la + lb - 1;
 }
@@ -396,20 +537,19 @@ __global__ void k_path_write(RoundArgs A, const PairDesc *pd, const uint32_t *le
     const PairDesc d = pd[p];
     uint32_t *o = out + off[p];
     const uint32_t la = walk_len(A, d.a, m);
-    // forward half, written back to front
     uint32_t v = m;
     const uint32_t ra = A.sd[d.a].src;
-    for (uint32_t k = la; k-- > 0;) {
+    for (uint32_t k = la; k-- > 0;) {        // forward half, written back to front
         o[k] = v;
         if (v == ra) break;
-        v = (uint32_t)A.S[(uint64_t)d.a * A.n + v];
+        v = tight_pred(A, d.a, v);
     }
     if (d.b & TARGET_BIT) return;
     const uint32_t rb = A.sd[d.b].src;
     v = m;
     uint32_t k = la;
     while (v != rb) {
-        v = (uint32_t)A.S[(uint64_t)d.b * A.n + v];
+        v = tight_pred(A, d.b, v);
         o[k++] = v;
     }
 }
@@ -418,16 +558,18 @@ __global__ void k_path_write(RoundArgs A, const PairDesc *pd, const uint32_t *le
 
 hipError_t launch_init(const RoundArgs &A, hipStream_t st) {
     k_init<<<(A.nsearch + BLOCK - 1) / BLOCK, BLOCK, 0, st>>>(A);
+    k_seed_prefix<<<1, WAVE, 0, st>>>(A);
     return hipGetLastError();
 }
 
-hipError_t launch_round(const RoundArgs &A, uint32_t par, uint32_t grid, hipStream_t st) {
-    k_round<<<grid, BLOCK, 0, st>>>(A, par);
+hipError_t launch_round(const RoundArgs &A, uint32_t grid, hipStream_t st) {
+    k_round<<<grid, WAVE, 0, st>>>(A);
     return hipGetLastError();
 }
 
-hipError_t launch_control(const RoundArgs &A, uint32_t par, hipStream_t st) {
-    k_control<<<(A.nsearch + BLOCK - 1) / BLOCK, BLOCK, 0, st>>>(A, par);
+hipError_t launch_control(const RoundArgs &A, hipStream_t st) {
+    const uint32_t nb = (A.nsearch + BLOCK - 1) / BLOCK;
+    k_control<<<nb, BLOCK, 0, st>>>(A);
     return hipGetLastError();
 }
 

@@ -3,16 +3,34 @@
 //
 // Search state. Every search (one frontier copy v^(i) in the notation of
 // Section 3.1: the forward or backward copy of a bidirectional query, or the
-// copy rooted at query-graph vertex q_i in Multi-BiDS, Section 4.2) owns a
-// slab of n 64-bit words laid out search-major, S[i*n + v]:
+// copy rooted at query-graph vertex q_i in Multi-BiDS, Section 4.2) owns n
+// 64-bit words:
 //     bits 63..32  tentative distance delta[v^(i)] (0xFFFFFFFF = +infinity)
-//     bits 31..0   the vertex whose relaxation last lowered it (parent)
+//     bits 31..0   stamp: 1 + the round in which the word last changed
 // so WriteMin of Section 2 (write if smaller, report success) is one 64-bit
-// atomicMin; success is a strict decrease of the distance field.
+// atomicMin of (candidate << 32 | stamp); success is a strict decrease of the
+// distance field, and the returned old word tells whether the vertex was
+// already lowered, and so already added to the next frontier, in this round.
+// Add (Algorithm 1: add v unless already present) therefore needs no extra
+// memory. Every frontier entry records the stamp of the round that added it;
+// an entry whose vertex has been lowered in a later round (word stamp newer
+// than the entry's) is stale, because that later lowering added a fresh
+// entry (or pruned the vertex), and is dropped. So an entry kept for a later
+// round is simply added again, with no atomic and no duplicate work.
+// Parents are not stored: every vertex of an exact
+// path has a tight in-arc (delta[p] + w(p,v) = delta[v]) to an exact vertex,
+// so paths are recovered by walking tight arcs back to the root.
+// Words are grouped G searches at a time, vertex-major inside a group:
+//     S[((i / G) * n + v) * G + i % G]
+// G = 2 puts the forward and backward copies of a bidirectional query side by
+// side, so one 16-byte load returns both delta[v+] and delta[v-] (the two
+// terms of UpdateDistance); G = 1 is plain search-major.
 //
-// Frontier. A flat queue of 64-bit entries (search << 32 | vertex) per round
-// parity; membership of (i, v) in the next frontier is one bit in a per-parity
-// bitmap, so Add (Algorithm 1: add v unless already present) is one atomicOr.
+// Frontier. Queues of 16-byte entries (search, vertex, stamp when added,
+// heuristic term) per round parity. A queue is NSEG segments; a wave appends
+// to segment (workgroup id mod NSEG), which spreads the append counters over
+// NSEG addresses, and the next round walks the segments as one list of
+// WAVE-entry chunks through a prefix sum of their chunk counts.
 //
 // Keys. Extraction and pruning compare integer keys (Table 2), doubled where
 // the paper halves mu so that everything stays exact:
@@ -21,9 +39,11 @@
 //     K_2DIST   key = 2 delta                    (BiDS, Multi-BiDS: delta >= mu/2)
 //     K_BIDA_F  key = 2 delta + h_t(v) - h_s(v)  (BiD-A* forward:  delta + h_F >= mu/2)
 //     K_BIDA_B  key = 2 delta - h_t(v) + h_s(v)  (BiD-A* backward: delta + h_B >= mu/2)
-// with h_F = (h_t - h_s)/2 = -h_B (Section 3.5). A search prunes a vertex when
+// with h_F = (h_t - h_s)/2 = -h_B (Section 3.5). The vertex-only term
+// (0, h_t, h_t - h_s or h_s - h_t) is the entry's heuristic term hk, so a key
+// is scale * delta + hk with scale 1 or 2. A search prunes a vertex when
 // key >= bound, bound being mu of its query (or mumax[i] of Table 2's
-// Multi-PPSP row).
+// Multi-PPSP row); bound = 0 marks a finished search.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -36,12 +56,12 @@ constexpr uint64_t INF64 = ~0ull;
 constexpr uint32_t TARGET_BIT = 0x80000000u;  // Partner.other: a target vertex, not a search
 constexpr int BLOCK = 256;                     // threads per block (four wave64s)
 constexpr int WAVE = 64;
-constexpr int STAGE_CAP = 2048;                // LDS staging slots per block
-constexpr uint32_t HEAVY_DEG = 32;             // above this a whole wave relaxes the arc list
+constexpr int WSTAGE = 256;                    // LDS staging slots per wave (round kernel)
+constexpr int NSEG = 64;                       // append segments of a frontier queue
 
 constexpr uint32_t ERR_OVERFLOW = 1u;          // a distance reached 2^32-1
 constexpr uint32_t ERR_QUEUE = 2u;             // the frontier queue overflowed
-constexpr uint32_t ERR_PATH = 4u;              // a parent walk did not reach its root
+constexpr uint32_t ERR_PATH = 4u;              // a tight-arc walk did not reach its root
 
 enum KeyKind : uint32_t { K_DIST = 0, K_ASTAR = 1, K_2DIST = 2, K_BIDA_F = 3, K_BIDA_B = 4 };
 
@@ -93,6 +113,8 @@ struct RoundArgs {
     // graph
     const uint32_t *row_ptr;   // n+1
     const uint2 *arcs;         // m: (neighbour, weight)
+    const uint32_t *in_row_ptr;  // transpose (same arrays on a symmetric graph), for path walks
+    const uint2 *in_arcs;
     const int2 *xy;            // n fixed-point coordinates or null
     uint64_t ws2;              // w_scale^2
     uint32_t fb;               // coordinate fractional bits
@@ -102,24 +124,30 @@ struct RoundArgs {
     const Partner *partners;
     uint32_t nsearch;
     uint32_t npair;
-    uint64_t *S;               // [nsearch][n] packed (dist, parent)
-    uint32_t *flags;           // [2][nsearch][fw] frontier membership bits
-    uint64_t fw;               // 32-bit words per search per parity
-    uint64_t *theta;           // [nsearch] current threshold (key units)
+    uint32_t G;                // searches per interleaved group (1 or 2)
+    uint64_t *S;               // packed (distance, stamp) words, layout above
+    ulonglong2 *ctl;           // [nsearch] (theta, bound) in key units; bound 0 = finished
     const uint64_t *delta;     // [nsearch] threshold increment (key units)
-    uint64_t *bound;           // [nsearch] prune bound (key units), INF64 = none
     uint32_t *done;            // [nsearch]
     uint32_t *exh;             // [nsearch] frontier ran dry while the bound was infinite
-    uint32_t *cnt;             // [2][nsearch] entries added to the next frontier
+    uint32_t *alive;           // [2][nsearch] 1 if the search added anything to that frontier
     uint64_t *minkey;          // [2][nsearch] smallest key added to the next frontier
     uint64_t *mu;              // [npair] packed (distance, meeting vertex)
-    uint64_t *q0, *q1;         // frontier queues by round parity
-    uint32_t *qcount;          // [2] queue lengths
-    uint64_t qcap;             // queue capacity (entries)
+    uint4 *q0, *q1;            // frontier queues by round parity, NSEG segments of qseg entries
+    uint32_t *qcount;          // [2][NSEG] segment lengths
+    uint32_t *cpre;            // [2][NSEG + 1] prefix sums of the segments' WAVE-entry chunk counts
+    uint64_t qseg;             // capacity of one segment (entries)
+    uint32_t *round;           // [0] round to run next (read by k_round), [1] round just run (k_control)
     uint32_t *err;             // ERR_* bits
-    unsigned long long *stats; // counters, see StatIdx
+    unsigned long long *stats; // [ST_ROUNDS] rounds run
+    unsigned long long *wstats; // [grid][ST_N] per-workgroup counters of the round kernel
+    uint32_t theta_mode;       // 0: theta += Delta; 1: end of the smallest key's Delta bucket; 2: smallest key + Delta
 };
 
-enum StatIdx { ST_ROUNDS = 0, ST_ENTRIES = 1, ST_SCANV = 2, ST_SCANE = 3, ST_SUCC = 4, ST_N = 8 };
+__host__ __device__ inline uint64_t state_index(uint32_t G, uint32_t n, uint32_t i, uint32_t v) {
+    return G == 2 ? ((((uint64_t)(i >> 1) * n) + v) << 1) | (i & 1u) : (uint64_t)i * n + v;
+}
+
+enum StatIdx { ST_ROUNDS = 0, ST_ENTRIES = 1, ST_SCANV = 2, ST_SCANE = 3, ST_SUCC = 4, ST_CARRY = 5, ST_N = 8 };
 
 }  // namespace ppsp
