@@ -110,6 +110,7 @@ typedef struct {
     double relax_kernel_ms;    /* summed duration of the round kernel (profiling on), else 0 */
     uint64_t relax_launches;   /* number of round-kernel launches */
     uint64_t carried;          /* entries kept for a later round (key above the threshold) */
+    uint64_t retries;          /* waves rerun after growing an overflowed frontier queue */
 } ppsp_stats;
 
 typedef struct ppsp_graph_s *ppsp_graph;
@@ -193,6 +194,9 @@ int ppsp_last_stats(ppsp_graph g, ppsp_stats *stats);
  *                     2 (default): the smallest frontier key + Delta - 1
  *   "use_graph"       1: replay rounds through a captured hipGraph
  *   "timeout_ms"      host-side limit on one wave's round loop (0 = none)
+ *   "queue_cap"       frontier queue capacity in entries (grows x4, with a rerun of
+ *                     the wave, whenever a round overflows it)
+ *   "heavy_cap"       heavy-list capacity in arc chunks (grows the same way)
  * Returns PPSP_E_INVALID for an unknown name.
  */
 int ppsp_set_option(ppsp_graph g, const char *name, int64_t value);

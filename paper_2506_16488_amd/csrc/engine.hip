@@ -33,6 +33,7 @@ namespace ppsp {
 hipError_t launch_init(const RoundArgs &A, hipStream_t st);
 hipError_t launch_round(const RoundArgs &A, uint32_t grid, hipStream_t st);
 hipError_t launch_control(const RoundArgs &A, hipStream_t st);
+hipError_t launch_heavy(const RoundArgs &A, uint32_t grid, hipStream_t st);
 hipError_t launch_path_len(const RoundArgs &A, const PairDesc *pd, uint32_t *len, hipStream_t st);
 hipError_t launch_path_write(const RoundArgs &A, const PairDesc *pd, const uint32_t *len, const uint64_t *off,
                              uint32_t *out, hipStream_t st);
@@ -111,7 +112,9 @@ struct ppsp_graph_s {
     DevBuf row_ptr, arcs, xy, in_row_ptr, in_arcs;   // transpose only for a directed graph
     // workspace (grow only)
     DevBuf S, q0, q1, sd, partners, pairdesc, ctl, delta, done, exh, alive, minkey, mu, qcount, cpre, round, err,
-        stats, wstats, pathlen, pathoff, pathbuf;
+        stats, wstats, pathlen, pathoff, pathbuf, heavy, hcount;
+    uint32_t maxdeg = 0;
+    uint32_t hcap = 0;              // heavy list capacity (0 while no vertex exceeds HEAVY_DEG)
     hipStream_t st = nullptr;
     uint32_t *h_poll = nullptr;     // pinned
     std::vector<hipEvent_t> ev;
@@ -119,7 +122,7 @@ struct ppsp_graph_s {
     int cu = 256;
     // options
     int64_t opt_profile = 0, opt_rounds_per_sync = 16, opt_grid_blocks = 0, opt_mem_budget_mb = 0,
-            opt_default_delta = 0, opt_use_graph = 0, opt_timeout_ms = 600000, opt_theta_mode = 2;
+            opt_default_delta = 0, opt_use_graph = 0, opt_timeout_ms = 600000, opt_theta_mode = 2, opt_queue_cap = 0;
     uint64_t wmean = 1;             // mean arc weight (rounded up)
     uint64_t qcap = 0;
 };
@@ -190,6 +193,9 @@ void set_args(ppsp_graph g, RoundArgs &A, uint32_t nsearch, uint32_t npair, uint
     A.err = g->err.as<uint32_t>();
     A.stats = g->stats.as<unsigned long long>();
     A.wstats = g->wstats.as<unsigned long long>();
+    A.heavy = g->heavy.as<uint4>();
+    A.hcount = g->hcount.as<unsigned long long>();
+    A.hcap = g->maxdeg > HEAVY_DEG ? g->hcap : 0;
     A.theta_mode = (uint32_t)g->opt_theta_mode;
 }
 
@@ -218,6 +224,11 @@ int run_wave(ppsp_graph g, const Plan &P, bool want_path, WaveOut &out) {
     hipStream_t st = g->st;
     CHK(ensure(g->S, ns * n * 8));
     CHK(ensure(g->round, 16));
+    CHK(ensure(g->hcount, 16));
+    if (g->maxdeg > HEAVY_DEG) {
+        if (g->hcap == 0) g->hcap = 1u << 20;
+        CHK(ensure(g->heavy, (uint64_t)g->hcap * 32));
+    }
     CHK(ensure(g->sd, ns * sizeof(SearchDesc)));
     CHK(ensure(g->partners, P.partners.size() * sizeof(Partner)));
     CHK(ensure(g->pairdesc, npair * sizeof(PairDesc)));
@@ -236,7 +247,7 @@ int run_wave(ppsp_graph g, const Plan &P, bool want_path, WaveOut &out) {
         // one frontier holds at most one entry per (search, vertex) plus rare duplicates
         const uint64_t want = std::min<uint64_t>(std::max<uint64_t>(std::min<uint64_t>(16384ull * ns, ns * n + 1024),
                                                                     1ull << 16), 1ull << 28);
-        if (g->qcap < want) g->qcap = want;
+        if (g->qcap < want && g->opt_queue_cap == 0) g->qcap = want;
     }
     const uint32_t grid = g->opt_grid_blocks > 0 ? (uint32_t)g->opt_grid_blocks : (uint32_t)(24 * g->cu);
     CHK(ensure(g->wstats, (uint64_t)grid * ST_N * 8));
@@ -254,6 +265,7 @@ int run_wave(ppsp_graph g, const Plan &P, bool want_path, WaveOut &out) {
         HIPCHK(hipMemsetAsync(g->qcount.p, 0, 2 * NSEG * 4, st));
         HIPCHK(hipMemsetAsync(g->wstats.p, 0, (uint64_t)grid * ST_N * 8, st));
         HIPCHK(hipMemsetAsync(g->round.p, 0, 16, st));
+        HIPCHK(hipMemsetAsync(g->hcount.p, 0, 16, st));
         HIPCHK(hipMemsetAsync(g->err.p, 0, 16, st));
         HIPCHK(hipMemsetAsync(g->stats.p, 0, ST_N * 8, st));
         RoundArgs A;
@@ -275,6 +287,7 @@ int run_wave(ppsp_graph g, const Plan &P, bool want_path, WaveOut &out) {
             HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
             for (int k = 0; k < Kg; k++) {
                 (void)launch_round(A, grid, st);
+                if (A.hcap) (void)launch_heavy(A, grid, st);
                 (void)launch_control(A, st);
             }
             HIPCHK(hipStreamEndCapture(st, &graph));
@@ -290,6 +303,7 @@ int run_wave(ppsp_graph g, const Plan &P, bool want_path, WaveOut &out) {
                 for (kk = 0; kk < K; kk++, r++) {
                     if (prof) HIPCHK(hipEventRecord(g->ev[2 * kk], st));
                     HIPCHK(launch_round(A, grid, st));
+                    if (A.hcap) HIPCHK(launch_heavy(A, grid, st));
                     if (prof) HIPCHK(hipEventRecord(g->ev[2 * kk + 1], st));
                     HIPCHK(launch_control(A, st));
                 }
@@ -317,11 +331,19 @@ int run_wave(ppsp_graph g, const Plan &P, bool want_path, WaveOut &out) {
         if (timed_out) return PPSP_E_TIMEOUT;
         const uint32_t errbits = g->h_poll[2 * NSEG];
         if (errbits & ERR_OVERFLOW) return PPSP_E_OVERFLOW;
-        if (errbits & ERR_QUEUE) {
-            // Grow the frontier queues and rerun the wave from scratch.
-            uint64_t want = g->qcap * 4;
-            if (want > (1ull << 31)) return PPSP_E_OOM;
-            g->qcap = want;
+        if (errbits & (ERR_QUEUE | ERR_HEAVY)) {
+            g->last.retries++;
+            // Grow the frontier queues (or the heavy list) and rerun the wave from scratch.
+            if (errbits & ERR_QUEUE) {
+                uint64_t want = g->qcap * 4;
+                if (want > (1ull << 31)) return PPSP_E_OOM;
+                g->qcap = want;
+            }
+            if (errbits & ERR_HEAVY) {
+                if (g->hcap >= (1u << 28)) return PPSP_E_OOM;
+                g->hcap *= 4;
+                CHK(ensure(g->heavy, (uint64_t)g->hcap * 32));
+            }
             continue;
         }
         out.mu.resize(npair);
@@ -696,6 +718,8 @@ int ppsp_graph_create(int device, uint32_t n, uint64_t m, const uint64_t *row_pt
         wsum += w[e];
     }
     if (m == 0) wmin = wmax = 1;
+    uint32_t maxdeg = 0;
+    for (uint32_t v = 0; v < n; v++) maxdeg = std::max<uint32_t>(maxdeg, (uint32_t)(row_ptr[v + 1] - row_ptr[v]));
     if (coord_fx && coord_frac_bits > 30) return PPSP_E_RANGE;
     ppsp_graph g = new ppsp_graph_s();
     g->device = device;
@@ -705,6 +729,7 @@ int ppsp_graph_create(int device, uint32_t n, uint64_t m, const uint64_t *row_pt
     g->wmin = wmin;
     g->wmax = wmax;
     g->wmean = m ? std::max<uint64_t>(1, (wsum + m - 1) / m) : 1;
+    g->maxdeg = maxdeg;
     auto fail = [&](int rc) {
         ppsp_graph_destroy(g);
         return rc;
@@ -809,7 +834,7 @@ int ppsp_graph_destroy(ppsp_graph g) {
     if (g->st) (void)hipStreamSynchronize(g->st);
     DevBuf *bufs[] = {&g->row_ptr, &g->arcs, &g->xy, &g->in_row_ptr, &g->in_arcs, &g->S, &g->q0, &g->q1,
                       &g->sd, &g->partners, &g->pairdesc, &g->ctl, &g->delta, &g->done, &g->exh, &g->alive,
-                      &g->minkey, &g->mu, &g->qcount, &g->cpre, &g->round, &g->err, &g->stats, &g->wstats, &g->pathlen, &g->pathoff,
+                      &g->minkey, &g->mu, &g->qcount, &g->cpre, &g->round, &g->err, &g->stats, &g->wstats, &g->heavy, &g->hcount, &g->pathlen, &g->pathoff,
                       &g->pathbuf};
     for (DevBuf *b : bufs) release(*b);
     for (hipEvent_t e : g->ev) (void)hipEventDestroy(e);
@@ -860,6 +885,8 @@ int ppsp_set_option(ppsp_graph g, const char *name, int64_t v) {
     else if (k == "use_graph") g->opt_use_graph = v;
     else if (k == "timeout_ms") { if (v < 0) return PPSP_E_INVALID; g->opt_timeout_ms = v; }
     else if (k == "theta_mode") { if (v < 0 || v > 2) return PPSP_E_INVALID; g->opt_theta_mode = v; }
+    else if (k == "queue_cap") { if (v < (int64_t)NSEG || v > (1ll << 31)) return PPSP_E_INVALID; g->qcap = (uint64_t)v; g->opt_queue_cap = v; }
+    else if (k == "heavy_cap") { if (v < 1 || v > (1ll << 28)) return PPSP_E_INVALID; g->hcap = (uint32_t)v; }
 
     else return PPSP_E_INVALID;
     return PPSP_OK;
@@ -876,6 +903,8 @@ int ppsp_get_option(ppsp_graph g, const char *name, int64_t *v) {
     else if (k == "use_graph") *v = g->opt_use_graph;
     else if (k == "timeout_ms") *v = g->opt_timeout_ms;
     else if (k == "theta_mode") *v = g->opt_theta_mode;
+    else if (k == "queue_cap") *v = (int64_t)g->qcap;
+    else if (k == "heavy_cap") *v = g->hcap;
 
     else return PPSP_E_INVALID;
     return PPSP_OK;

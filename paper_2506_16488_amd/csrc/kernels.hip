@@ -325,10 +325,34 @@ __global__ __launch_bounds__(WAVE) void k_round(RoundArgs A) {
         wstage_push(st, scnt, keep, ent, qout, qcout, A.qseg, A.err);
         search_stats(A, np, ent.x, keep ? 1u : 0u, keep ? key : INF64);
 
+        // High-degree vertices go to the heavy list as chunks of at most
+        // HEAVY_CHUNK arcs, which all waves of k_heavy share; one atomic per
+        // wave reserves the wave's chunks.
+        const bool heavy = action == 2 && A.hcap && re - rb > HEAVY_DEG;
+        if (__ballot(heavy)) {
+            const uint32_t nck = heavy ? (re - rb + HEAVY_CHUNK - 1) / HEAVY_CHUNK : 0u;
+            uint32_t tot;
+            const uint32_t pre = wave_exscan(nck, &tot);
+            unsigned long long b0 = 0;
+            if (lane_id() == 0) b0 = atomicAdd(A.hcount, (unsigned long long)tot);
+            b0 = __shfl(b0, 0);
+            for (uint32_t k = 0; k < nck; k++) {
+                const uint64_t slot = b0 + pre + k;
+                const uint32_t eb = rb + k * HEAVY_CHUNK;
+                const uint32_t ee = min(re, eb + HEAVY_CHUNK);
+                if (slot < A.hcap) {
+                    A.heavy[2 * slot] = make_uint4(ent.x, ent.y, du, eb);
+                    A.heavy[2 * slot + 1] = make_uint4(ee, 0u, 0u, 0u);
+                } else {
+                    atomicOr(A.err, ERR_HEAVY);
+                }
+            }
+        }
+
         // 2. Arc-parallel relaxation of the extracted vertices: a wave scan of
         // their degrees lays their arcs out as one list, and each lane takes
         // one arc per step (its vertex found by binary search).
-        const uint32_t deg = action == 2 ? re - rb : 0u;
+        const uint32_t deg = (action == 2 && !heavy) ? re - rb : 0u;
         uint32_t T;
         const uint32_t pre = wave_exscan(deg, &T);
         if (T == 0) continue;
@@ -379,6 +403,41 @@ __global__ __launch_bounds__(WAVE) void k_round(RoundArgs A) {
     }
 }
 
+// The heavy list, relaxed by every wave of the grid: each wave takes whole
+// chunks (at most HEAVY_CHUNK arcs of one vertex), 64 arcs per step. Runs
+// after k_round in the same round.
+__global__ __launch_bounds__(WAVE) void k_heavy(RoundArgs A) {
+    __shared__ WaveStage st;
+    uint32_t scnt = 0;
+    const uint32_t r = A.round[1];                          // set by this round's k_round
+    const uint32_t np = (r & 1) ^ 1, stamp = r + 1;
+    const uint64_t nh = min((uint64_t)*A.hcount, (uint64_t)A.hcap);
+    if (nh == 0) return;
+    const uint32_t sego = blockIdx.x % NSEG;
+    uint4 *qout = ((r & 1) ? A.q0 : A.q1) + (uint64_t)sego * A.qseg;
+    uint32_t *qcout = &A.qcount[np * NSEG + sego];
+    unsigned long long c_succ = 0;
+    for (uint64_t slot = blockIdx.x; slot < nh; slot += gridDim.x) {
+        const uint4 h1 = A.heavy[2 * slot];
+        const uint32_t ee = A.heavy[2 * slot + 1].x;
+        const uint32_t ai = h1.x;
+        const SearchDesc sd = A.sd[ai];
+        const uint64_t bnd = A.ctl[ai].y;
+        for (uint32_t e0 = h1.w; e0 < ee; e0 += WAVE) {
+            const uint32_t e = e0 + lane_id();
+            bool app = false;
+            uint4 ne = make_uint4(0, 0, 0, 0);
+            uint64_t lmin = INF64;
+            if (e < ee) app = relax_arc(A, sd, ai, h1.y, h1.z, bnd, e, stamp, &ne, &lmin, &c_succ);
+            wstage_push(st, scnt, app, ne, qout, qcout, A.qseg, A.err);
+            search_stats(A, np, ai, app ? 1u : 0u, lmin);
+        }
+    }
+    wstage_flush(st, scnt, qout, qcout, A.qseg, A.err);
+    c_succ = wave_sum_u64(c_succ);
+    if (lane_id() == 0 && c_succ) A.wstats[(uint64_t)blockIdx.x * ST_N + ST_SUCC] += c_succ;
+}
+
 // Prefix sum of the chunk counts of the NSEG segments of queue `q` (one
 // wave of 64 = NSEG lanes).
 __device__ __forceinline__ void chunk_prefix(const RoundArgs &A, uint32_t q) {
@@ -405,7 +464,10 @@ __global__ __launch_bounds__(BLOCK) void k_control(RoundArgs A) {
         chunk_prefix(A, np);                      // chunk layout of the queue the next round reads
         A.qcount[par * NSEG + threadIdx.x] = 0;   // the queue just consumed becomes the next output
     }
-    if (i == 0) A.round[0] = r + 1;
+    if (i == 0) {
+        A.round[0] = r + 1;
+        *A.hcount = 0;
+    }
     if (i >= A.nsearch) return;
     const uint32_t c = A.alive[(uint64_t)np * A.nsearch + i];
     const uint64_t mk = A.minkey[(uint64_t)np * A.nsearch + i];
@@ -564,6 +626,11 @@ hipError_t launch_init(const RoundArgs &A, hipStream_t st) {
 
 hipError_t launch_round(const RoundArgs &A, uint32_t grid, hipStream_t st) {
     k_round<<<grid, WAVE, 0, st>>>(A);
+    return hipGetLastError();
+}
+
+hipError_t launch_heavy(const RoundArgs &A, uint32_t grid, hipStream_t st) {
+    k_heavy<<<grid, WAVE, 0, st>>>(A);
     return hipGetLastError();
 }
 

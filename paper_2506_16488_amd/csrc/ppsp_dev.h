@@ -57,11 +57,14 @@ constexpr uint32_t TARGET_BIT = 0x80000000u;  // Partner.other: a target vertex,
 constexpr int BLOCK = 256;                     // threads per block (four wave64s)
 constexpr int WAVE = 64;
 constexpr int WSTAGE = 256;                    // LDS staging slots per wave (round kernel)
+constexpr uint32_t HEAVY_DEG = 512;            // extracted vertices above this go to the heavy list
+constexpr uint32_t HEAVY_CHUNK = 2048;         // arcs per heavy-list chunk
 constexpr int NSEG = 64;                       // append segments of a frontier queue
 
 constexpr uint32_t ERR_OVERFLOW = 1u;          // a distance reached 2^32-1
 constexpr uint32_t ERR_QUEUE = 2u;             // the frontier queue overflowed
 constexpr uint32_t ERR_PATH = 4u;              // a tight-arc walk did not reach its root
+constexpr uint32_t ERR_HEAVY = 8u;             // the heavy list overflowed
 
 enum KeyKind : uint32_t { K_DIST = 0, K_ASTAR = 1, K_2DIST = 2, K_BIDA_F = 3, K_BIDA_B = 4 };
 
@@ -138,6 +141,10 @@ struct RoundArgs {
     uint32_t *cpre;            // [2][NSEG + 1] prefix sums of the segments' WAVE-entry chunk counts
     uint64_t qseg;             // capacity of one segment (entries)
     uint32_t *round;           // [0] round to run next (read by k_round), [1] round just run (k_control)
+    uint4 *heavy;              // [hcap][2] arc chunks of this round's extracted high-degree vertices:
+                               //   (search, vertex, distance, first arc), (end arc, 0, 0, 0)
+    unsigned long long *hcount;  // chunks written this round
+    uint32_t hcap;             // heavy list capacity (chunks); 0 = no heavy path
     uint32_t *err;             // ERR_* bits
     unsigned long long *stats; // [ST_ROUNDS] rounds run
     unsigned long long *wstats; // [grid][ST_N] per-workgroup counters of the round kernel

@@ -229,3 +229,70 @@ def test_config2_full_size_sampled(P):
         assert np.array_equal(got[a][idx], exp), a
     assert np.array_equal(got["bids"], got["bidastar"])
     G.close()
+
+
+@pytest.mark.parametrize("scale", [12, 16])
+def test_rmat_heavy_vertices(P, scale):
+    """Power-law graphs: hub vertices (degree > 512) take the heavy-list path;
+    pairs from the largest component plus a few from outside it."""
+    g = gen.rmat(scale, 16, seed=40 + scale)
+    lcc = gen.lcc(g)
+    pairs = np.concatenate([gen.pairs_uniform(lcc, 120, seed=scale), gen.pairs_uniform(g.n, 20, seed=scale + 1)])
+    exp = _oracle(g, pairs)
+    G = _graph(P, g)
+    for algo in ["bids", "et", "sssp"]:
+        assert np.array_equal(G.batch_query(pairs, algo=algo, batch="plainstar"), exp), algo
+    assert np.array_equal(G.batch_query(pairs, algo="bids", batch="multi"), exp)
+    dist, (off, vtx) = G.batch_query(pairs[:30], algo="bids", batch="multi", want_path=True)
+    _check_paths(g, pairs[:30], dist, off, vtx)
+    G.close()
+
+
+def test_overflow_retries_keep_results_exact(P):
+    """Tiny frontier-queue and heavy-list capacities force overflow: the wave
+    is rerun with larger buffers and the answers are unchanged."""
+    g = gen.rmat(14, 16, seed=77)
+    lcc = gen.lcc(g)
+    pairs = gen.pairs_uniform(lcc, 200, seed=78)
+    exp = _oracle(g, pairs)
+    G = _graph(P, g)
+    for batch in ["plainstar", "multi"]:
+        G.set_option("queue_cap", 4096)
+        G.set_option("heavy_cap", 4)
+        assert np.array_equal(G.batch_query(pairs, algo="bids", batch=batch), exp), batch
+        assert G.stats()["retries"] > 0
+        assert G.get_option("queue_cap") > 4096 and G.get_option("heavy_cap") > 4
+    G.close()
+
+
+@pytest.mark.slow
+def test_config3_hub_batch_sampled(P):
+    """The 4096^2 lattice with a 1,024-pair hub batch (512 pairs from 32 hub
+    sources, 512 uniform) as one Multi-BiDS wave of ~1,568 searches, and as
+    Plain* bidirectional A*; sampled pairs against the oracle."""
+    g = gen.config_graph(3)
+    pairs = gen.config_pairs(3, g)
+    idx = np.arange(0, 1024, 64)
+    exp = _oracle(g, pairs[idx])
+    G = _graph(P, g)
+    got = G.batch_query(pairs, algo="bids", batch="multi")
+    assert np.array_equal(got[idx], exp)
+    assert G.stats()["searches"] < 1700                 # shared sources: fewer searches than 2 x 1,024
+    assert np.array_equal(G.batch_query(pairs, algo="bidastar", batch="plainstar"), got)
+    G.close()
+
+
+@pytest.mark.slow
+def test_config4_rmat_sampled(P):
+    """R-MAT scale 24 (power law, hubs of degree ~400K) with 256 pairs from the
+    largest component, Multi-BiDS; sampled pairs against the oracle."""
+    g = gen.config_graph(4)
+    lcc = gen.lcc(g)
+    pairs = gen.config_pairs(4, g, cand=lcc)
+    idx = np.arange(0, 256, 32)
+    exp = _oracle(g, pairs[idx])
+    G = _graph(P, g)
+    G.set_option("timeout_ms", 240000)
+    got = G.batch_query(pairs, algo="bids", batch="multi")
+    assert np.array_equal(got[idx], exp)
+    G.close()
