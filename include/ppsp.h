@@ -53,7 +53,7 @@ enum {
     PPSP_E_NOCOORD = -5,   /* A* mode on a graph without consistent coordinates */
     PPSP_E_NOTSYM = -6,    /* a bidirectional or batch mode on a graph not flagged symmetric */
     PPSP_E_DEVICE = -7,    /* a HIP runtime error */
-    PPSP_E_BUSY = -8,      /* (serving) the request has not finished */
+    PPSP_E_BUSY = -8,      /* (serving) the request has not finished, or the graph belongs to a server */
     PPSP_E_PATHCAP = -9,   /* the caller's path buffer is too small; *path_len gets the need */
     PPSP_E_NOPATH = -10,   /* paths were requested on a graph with a zero-weight arc */
     PPSP_E_TIMEOUT = -11   /* the round loop ran longer than the "timeout_ms" option */
@@ -78,7 +78,7 @@ enum ppsp_batch {
 /* Threshold schedule. */
 enum ppsp_sched {
     PPSP_SCHED_FIXED = 0,      /* Delta*-stepping with opts.delta (0: graph default) */
-    PPSP_SCHED_AUTOTUNED = 1,  /* the Delta and launch shape chosen by ppsp_tune */
+    PPSP_SCHED_AUTOTUNED = 1,  /* the Delta and launch shape chosen by ppsp_tune (defaults until then) */
     PPSP_SCHED_LEARNED = 2     /* per-round Delta multiplier chosen by the loaded MLP */
 };
 
@@ -175,6 +175,72 @@ int ppsp_query(ppsp_graph g, uint32_t s, uint32_t t, const ppsp_opts *opts, void
 int ppsp_batch_query(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp_opts *opts,
                      void *hip_stream, uint64_t *dist, uint64_t *path_off, uint32_t *path_vtx,
                      uint64_t path_cap);
+
+/* Result of ppsp_tune. */
+typedef struct {
+    uint64_t delta;        /* chosen Delta (distance units) */
+    uint32_t theta_mode;   /* chosen threshold rule (see "theta_mode") */
+    uint32_t grid_blocks;  /* chosen round-kernel workgroups (0 = default) */
+    double ms;             /* wall time of the sample batch with the choice */
+    double default_ms;     /* wall time of the sample batch with the defaults */
+    uint32_t trials;       /* configurations timed */
+    uint32_t from_cache;   /* 1 if read from cache_path */
+} ppsp_tune_result;
+
+/*
+ * Chooses the threshold schedule and launch shape for (opts->algo,
+ * opts->batch) by timing the sample batch `pairs` (k pairs, host). Delta is
+ * first swept by doubling from a small start while the time improves (the
+ * tuning procedure of Section 6.1), then the threshold rule, Delta between the
+ * doublings and the number of round-kernel workgroups are refined. The choice
+ * is kept in the handle and used by PPSP_SCHED_AUTOTUNED. With cache_path
+ * (or NULL) the choice is read from / appended to a text file keyed by a hash
+ * of the graph, so a later process can skip the timing. Results of queries are
+ * identical under every choice; only their speed differs.
+ */
+int ppsp_tune(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp_opts *opts, const char *cache_path,
+              ppsp_tune_result *out);
+
+/*
+ * Serving (continuous batching). A server owns one or more resident graphs
+ * (all on one device) and a worker thread that keeps their round loops
+ * running. Each graph gets a fixed pool of query slots (one forward and one
+ * backward search each) sized from state_budget (bytes of search state,
+ * shared in proportion to the graphs' vertex counts). Submitted queries wait
+ * in FIFO order and are admitted into free slots between rounds, so requests
+ * that arrive while others run join them on the device; results are the same
+ * distances ppsp_batch_query returns. A graph attached to a server is
+ * reserved: ppsp_query / ppsp_batch_query on it return PPSP_E_BUSY until
+ * ppsp_server_destroy.
+ *   opts->algo    PPSP_BIDS or PPSP_BIDASTAR (one query = two searches)
+ *   opts->delta   Delta (0 = each graph's default)
+ * ppsp_server_submit copies the pairs and returns a request id.
+ * ppsp_server_poll returns PPSP_E_BUSY until every query of the request has
+ * finished; then it copies the k distances (input order) and the latency
+ * (submit to last result, ms) and forgets the request. ppsp_server_wait blocks
+ * up to timeout_ms. Errors: PPSP_E_RANGE (vertex id), PPSP_E_INVALID
+ * (unknown request), PPSP_E_OOM (a frontier queue overflowed; the server
+ * stops).
+ */
+typedef struct ppsp_server_s *ppsp_server;
+
+typedef struct {
+    uint64_t admitted;    /* queries admitted into slots */
+    uint64_t completed;   /* requests completed */
+    uint64_t chunks;      /* worker iterations (admit, rounds, collect) */
+    uint64_t rounds;      /* rounds run, summed over graphs */
+    uint64_t running;     /* queries on the device now */
+    uint64_t slots;       /* query slots, summed over graphs */
+    uint64_t pending;     /* requests with queries not yet admitted */
+} ppsp_server_counters;
+
+int ppsp_server_create(const ppsp_graph *graphs, uint32_t ngraphs, const ppsp_opts *opts, uint64_t state_budget,
+                       ppsp_server *out);
+int ppsp_server_submit(ppsp_server srv, uint32_t graph_id, const uint32_t *pairs, uint32_t k, uint64_t *req_id);
+int ppsp_server_poll(ppsp_server srv, uint64_t req_id, uint64_t *dist, double *latency_ms);
+int ppsp_server_wait(ppsp_server srv, uint64_t req_id, uint64_t *dist, double *latency_ms, uint32_t timeout_ms);
+int ppsp_server_stats(ppsp_server srv, ppsp_server_counters *out);
+int ppsp_server_destroy(ppsp_server srv);
 
 /* Counters of the last ppsp_query / ppsp_batch_query on g (see ppsp_stats). */
 int ppsp_last_stats(ppsp_graph g, ppsp_stats *stats);

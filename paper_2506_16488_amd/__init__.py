@@ -59,8 +59,27 @@ class Stats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class TuneResult(ctypes.Structure):
+    _fields_ = [("delta", ctypes.c_uint64), ("theta_mode", ctypes.c_uint32), ("grid_blocks", ctypes.c_uint32),
+                ("ms", ctypes.c_double), ("default_ms", ctypes.c_double), ("trials", ctypes.c_uint32),
+                ("from_cache", ctypes.c_uint32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class ServerCounters(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_uint64) for k in ("admitted", "completed", "chunks", "rounds", "running", "slots",
+                                               "pending")]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
 EXPORTS = ["ppsp_graph_create", "ppsp_graph_destroy", "ppsp_query", "ppsp_batch_query", "ppsp_last_stats",
-           "ppsp_set_option", "ppsp_get_option", "ppsp_heuristic_fx", "ppsp_status_str", "ppsp_version", "ppsp_last_error"]
+           "ppsp_set_option", "ppsp_get_option", "ppsp_heuristic_fx", "ppsp_status_str", "ppsp_version",
+           "ppsp_last_error", "ppsp_tune", "ppsp_server_create", "ppsp_server_submit", "ppsp_server_poll",
+           "ppsp_server_wait", "ppsp_server_stats", "ppsp_server_destroy"]
 
 _lib_handle = None
 
@@ -101,10 +120,20 @@ def lib():
         L.ppsp_heuristic_fx.restype = u64
         L.ppsp_status_str.argtypes = [ctypes.c_int]
         L.ppsp_status_str.restype = ctypes.c_char_p
+        L.ppsp_tune.argtypes = [P, P, u32, ctypes.POINTER(Opts), ctypes.c_char_p, ctypes.POINTER(TuneResult)]
+        L.ppsp_tune.restype = ctypes.c_int
         L.ppsp_last_error.argtypes = []
         L.ppsp_last_error.restype = ctypes.c_char_p
         L.ppsp_version.argtypes = []
         L.ppsp_version.restype = ctypes.c_char_p
+        L.ppsp_server_create.argtypes = [P, u32, ctypes.POINTER(Opts), u64, ctypes.POINTER(P)]
+        L.ppsp_server_submit.argtypes = [P, u32, P, u32, ctypes.POINTER(u64)]
+        L.ppsp_server_poll.argtypes = [P, u64, P, ctypes.POINTER(ctypes.c_double)]
+        L.ppsp_server_wait.argtypes = [P, u64, P, ctypes.POINTER(ctypes.c_double), u32]
+        L.ppsp_server_stats.argtypes = [P, ctypes.POINTER(ServerCounters)]
+        L.ppsp_server_destroy.argtypes = [P]
+        for f in ("create", "submit", "poll", "wait", "stats", "destroy"):
+            getattr(L, "ppsp_server_" + f).restype = ctypes.c_int
         _lib_handle = L
     return _lib_handle
 
@@ -214,6 +243,15 @@ def batch_query(h, pairs, opts: Opts, stream=None, want_path=False, path_cap=Non
     return dist
 
 
+def tune(h, pairs, opts: Opts, cache_path=None) -> dict:
+    """ppsp_tune: choose Delta, threshold rule and launch shape on a sample batch."""
+    pairs = np.ascontiguousarray(pairs, np.uint32).reshape(-1, 2)
+    r = TuneResult()
+    _check(lib().ppsp_tune(h, _ptr(pairs), pairs.shape[0], ctypes.byref(opts),
+                           cache_path.encode() if cache_path else None, ctypes.byref(r)), "ppsp_tune")
+    return r.as_dict()
+
+
 def last_stats(h) -> dict:
     s = Stats()
     _check(lib().ppsp_last_stats(h, ctypes.byref(s)), "ppsp_last_stats")
@@ -255,6 +293,9 @@ class Graph:
     def stats(self) -> dict:
         return last_stats(self.h)
 
+    def tune(self, pairs, algo="bids", batch="plainstar", cache_path=None) -> dict:
+        return tune(self.h, pairs, make_opts(algo, batch), cache_path)
+
     def set_option(self, name, value):
         set_option(self.h, name, value)
 
@@ -264,6 +305,64 @@ class Graph:
     def close(self):
         if getattr(self, "h", None):
             graph_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+
+
+class Server:
+    """Continuous-batching server over resident graphs (ppsp_server_*): queries
+    submitted while others run are admitted between rounds into free slots."""
+
+    def __init__(self, graphs, algo="bidastar", delta=0, state_budget_bytes=1 << 30):
+        self.graphs = list(graphs)
+        hs = (ctypes.c_void_p * len(self.graphs))(*[g.h for g in self.graphs])
+        h = ctypes.c_void_p()
+        _check(lib().ppsp_server_create(hs, len(self.graphs), ctypes.byref(make_opts(algo, "plainstar", delta=delta)),
+                                        int(state_budget_bytes), ctypes.byref(h)), "ppsp_server_create")
+        self.h = h
+        self.k = {}
+
+    def submit(self, graph_id, pairs) -> int:
+        pairs = np.ascontiguousarray(pairs, np.uint32).reshape(-1, 2)
+        rid = ctypes.c_uint64(0)
+        _check(lib().ppsp_server_submit(self.h, int(graph_id), _ptr(pairs), pairs.shape[0], ctypes.byref(rid)),
+               "ppsp_server_submit")
+        self.k[rid.value] = pairs.shape[0]
+        return int(rid.value)
+
+    def poll(self, rid):
+        """(distances, latency_ms) once the request finished, else None."""
+        d = np.empty(self.k[rid], np.uint64)
+        lat = ctypes.c_double(0)
+        rc = lib().ppsp_server_poll(self.h, rid, _ptr(d), ctypes.byref(lat))
+        if rc == E_BUSY:
+            return None
+        _check(rc, "ppsp_server_poll")
+        del self.k[rid]
+        return d, lat.value
+
+    def wait(self, rid, timeout_ms=60000):
+        d = np.empty(self.k[rid], np.uint64)
+        lat = ctypes.c_double(0)
+        _check(lib().ppsp_server_wait(self.h, rid, _ptr(d), ctypes.byref(lat), int(timeout_ms)), "ppsp_server_wait")
+        del self.k[rid]
+        return d, lat.value
+
+    def stats(self) -> dict:
+        c = ServerCounters()
+        _check(lib().ppsp_server_stats(self.h, ctypes.byref(c)), "ppsp_server_stats")
+        return c.as_dict()
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().ppsp_server_destroy(self.h)
             self.h = None
 
     def __del__(self):

@@ -18,7 +18,11 @@
 
 #include <algorithm>
 #include <chrono>
+#include <condition_variable>
 #include <cstdio>
+#include <deque>
+#include <mutex>
+#include <thread>
 #include <cstring>
 #include <map>
 #include <numeric>
@@ -34,6 +38,8 @@ hipError_t launch_init(const RoundArgs &A, hipStream_t st);
 hipError_t launch_round(const RoundArgs &A, uint32_t grid, hipStream_t st);
 hipError_t launch_control(const RoundArgs &A, hipStream_t st);
 hipError_t launch_heavy(const RoundArgs &A, uint32_t grid, hipStream_t st);
+hipError_t launch_admit(const RoundArgs &A, const uint32_t *ids, uint32_t k, hipStream_t st);
+hipError_t launch_idle(const RoundArgs &A, hipStream_t st);
 hipError_t launch_path_len(const RoundArgs &A, const PairDesc *pd, uint32_t *len, hipStream_t st);
 hipError_t launch_path_write(const RoundArgs &A, const PairDesc *pd, const uint32_t *len, const uint64_t *off,
                              uint32_t *out, hipStream_t st);
@@ -124,7 +130,15 @@ struct ppsp_graph_s {
     int64_t opt_profile = 0, opt_rounds_per_sync = 16, opt_grid_blocks = 0, opt_mem_budget_mb = 0,
             opt_default_delta = 0, opt_use_graph = 0, opt_timeout_ms = 600000, opt_theta_mode = 2, opt_queue_cap = 0;
     uint64_t wmean = 1;             // mean arc weight (rounded up)
+    uint64_t fingerprint = 0;       // hash of the CSR, keys the tuning cache
+    struct Tuned {
+        bool valid = false;
+        uint64_t delta = 0;
+        int64_t theta_mode = 2, grid = 0;
+        double ms = 0;
+    } tuned[5][3];                  // per (algo, batch strategy)
     uint64_t qcap = 0;
+    bool served = false;            // attached to a server, which owns the workspace
 };
 
 namespace {
@@ -596,6 +610,7 @@ int batch_impl(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp_opts 
                uint64_t *dist, uint64_t *path_off, uint32_t *path_vtx, uint64_t path_cap, uint32_t *need_out) {
     auto t0 = std::chrono::steady_clock::now();
     if (!g || (!pairs && k) || (!dist && k)) return PPSP_E_INVALID;
+    if (g->served) return PPSP_E_BUSY;
     CHK(check_opts(g, o));
     const bool want_path = o->flags & PPSP_WANT_PATH;
     if (want_path && (!path_off || (!path_vtx && path_cap))) return PPSP_E_INVALID;
@@ -609,7 +624,20 @@ int batch_impl(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp_opts 
     HIPCHK(hipEventRecord(ev, (hipStream_t)hip_stream));
     HIPCHK(hipStreamWaitEvent(g->st, ev, 0));
     (void)hipEventDestroy(ev);
-    const uint64_t delta = o->delta ? o->delta : graph_default_delta(g);
+    uint64_t delta = o->delta ? o->delta : graph_default_delta(g);
+    // PPSP_SCHED_AUTOTUNED: the threshold rule, Delta and launch shape that
+    // ppsp_tune chose for this algorithm and batch strategy.
+    struct Restore {
+        ppsp_graph g;
+        int64_t mode, grid;
+        ~Restore() { g->opt_theta_mode = mode; g->opt_grid_blocks = grid; }
+    } restore{g, g->opt_theta_mode, g->opt_grid_blocks};
+    if (o->sched == PPSP_SCHED_AUTOTUNED && g->tuned[o->algo][o->batch].valid) {
+        const auto &t = g->tuned[o->algo][o->batch];
+        delta = t.delta;
+        g->opt_theta_mode = t.theta_mode;
+        g->opt_grid_blocks = t.grid;
+    }
     // distinct queries; on symmetric graphs (t,s) is the same query as (s,t)
     std::vector<Query> qs;
     std::vector<uint32_t> qidx(k);
@@ -662,6 +690,272 @@ int batch_impl(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp_opts 
     if (want_path) path_off[k] = off;
     g->last.wall_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     return PPSP_OK;
+}
+
+}  // namespace
+
+// ---- serving: continuous batching --------------------------------------------
+//
+// Each resident graph has a fixed pool of query slots (a forward and a
+// backward search in one interleaved state group each), sized by the memory
+// budget. A worker thread drives the device round loop without ever
+// resetting it. Between chunks of rounds it
+//   - admits waiting queries into free slots (clears their state slabs,
+//     k_admit seeds their roots into the frontier the next round reads),
+//   - reads the per-search done flags and the mu slots, and retires finished
+//     queries (a slot is reused only one chunk after its query finished, so
+//     no frontier entry of the old query is still queued),
+// so requests that arrive while others run join them on the device.
+
+namespace {
+
+struct SrvRequest {
+    uint32_t graph = 0;
+    std::vector<uint32_t> pairs;
+    std::vector<uint64_t> dist;
+    uint32_t next = 0;              // next query to admit
+    uint32_t remaining = 0;         // queries not finished
+    std::chrono::steady_clock::time_point t_submit, t_done;
+    bool done = false;
+};
+
+struct SrvGraph {
+    ppsp_graph g = nullptr;
+    uint32_t C = 0;                 // query slots
+    std::vector<SearchDesc> sd;
+    std::vector<Partner> partners;
+    std::vector<PairDesc> pairs;
+    std::vector<uint64_t> delta;
+    std::vector<int> state;         // 0 free, 1 running, 2 finished (reusable next chunk)
+    std::vector<uint64_t> slot_req;
+    std::vector<uint32_t> slot_q;
+    RoundArgs A;
+    uint32_t grid = 0;
+    uint32_t *h_done = nullptr;     // pinned: 2C done flags, then err
+    uint64_t *h_mu = nullptr;       // pinned: C mu slots
+    DevBuf ids;
+    std::vector<uint32_t> h_ids;    // admitted search ids (kept until the chunk's sync)
+    uint32_t running = 0;           // slots in state 1
+    uint32_t draining = 0;          // slots in state 2
+};
+
+}  // namespace
+
+struct ppsp_server_s {
+    std::vector<SrvGraph> gs;
+    ppsp_opts opts{};
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<uint64_t> pending;
+    std::unordered_map<uint64_t, SrvRequest> reqs;
+    uint64_t next_id = 1;
+    std::thread worker;
+    bool stop = false;
+    int err = PPSP_OK;
+    uint64_t admitted = 0, completed = 0, chunks = 0, rounds = 0;
+    uint32_t rounds_per_chunk = 16;
+};
+
+namespace {
+
+int srv_setup_graph(ppsp_server srv, SrvGraph &G, uint64_t budget) {
+    ppsp_graph g = G.g;
+    const uint64_t n = g->n;
+    const uint64_t per_query = 2 * n * 8;
+    G.C = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(budget / per_query, 1), 1u << 20);
+    const uint32_t ns = 2 * G.C, npair = G.C;
+    const uint32_t algo = srv->opts.algo;
+    const uint32_t kf = algo == PPSP_BIDS ? K_2DIST : K_BIDA_F, kb = algo == PPSP_BIDS ? K_2DIST : K_BIDA_B;
+    const uint64_t delta = srv->opts.delta ? srv->opts.delta : graph_default_delta(g);
+    G.sd.assign(ns, SearchDesc{});
+    G.partners.resize(ns);
+    G.pairs.resize(npair);
+    G.delta.resize(ns);
+    for (uint32_t q = 0; q < G.C; q++) {
+        G.sd[2 * q].kind = kf;
+        G.sd[2 * q + 1].kind = kb;
+        G.sd[2 * q].pbeg = 2 * q;
+        G.sd[2 * q].pend = 2 * q + 1;
+        G.sd[2 * q + 1].pbeg = 2 * q + 1;
+        G.sd[2 * q + 1].pend = 2 * q + 2;
+        G.partners[2 * q] = {2 * q + 1, q};
+        G.partners[2 * q + 1] = {2 * q, q};
+        G.pairs[q] = {2 * q, 2 * q + 1};
+        G.delta[2 * q] = key_delta(kf, delta);
+        G.delta[2 * q + 1] = key_delta(kb, delta);
+    }
+    G.state.assign(G.C, 0);
+    G.slot_req.assign(G.C, 0);
+    G.slot_q.assign(G.C, 0);
+    hipStream_t st = g->st;
+    CHK(set_device(g));
+    CHK(ensure(g->S, (uint64_t)ns * n * 8));
+    CHK(ensure(g->round, 16));
+    CHK(ensure(g->hcount, 16));
+    if (g->maxdeg > HEAVY_DEG) {
+        if (g->hcap == 0) g->hcap = 1u << 22;
+        CHK(ensure(g->heavy, (uint64_t)g->hcap * 32));
+    }
+    CHK(ensure(g->sd, ns * sizeof(SearchDesc)));
+    CHK(ensure(g->partners, ns * sizeof(Partner)));
+    CHK(ensure(g->pairdesc, npair * sizeof(PairDesc)));
+    CHK(ensure(g->ctl, (uint64_t)ns * 16));
+    CHK(ensure(g->delta, (uint64_t)ns * 8));
+    CHK(ensure(g->done, (uint64_t)ns * 4));
+    CHK(ensure(g->exh, (uint64_t)ns * 4));
+    CHK(ensure(g->alive, 2ull * ns * 4));
+    CHK(ensure(g->minkey, 2ull * ns * 8));
+    CHK(ensure(g->mu, (uint64_t)npair * 8));
+    CHK(ensure(g->qcount, 2 * NSEG * 4));
+    CHK(ensure(g->cpre, 2 * (NSEG + 1) * 4));
+    CHK(ensure(g->err, 16));
+    CHK(ensure(g->stats, ST_N * 8));
+    G.grid = g->opt_grid_blocks > 0 ? (uint32_t)g->opt_grid_blocks : (uint32_t)(24 * g->cu);
+    CHK(ensure(g->wstats, (uint64_t)G.grid * ST_N * 8));
+    g->qcap = std::max<uint64_t>(g->qcap, std::min<uint64_t>(std::max<uint64_t>(16384ull * ns, 1ull << 22), 1ull << 29));
+    CHK(ensure(g->q0, g->qcap * 16));
+    CHK(ensure(g->q1, g->qcap * 16));
+    CHK(ensure(G.ids, (uint64_t)ns * 4));
+    HIPCHK(hipHostMalloc((void **)&G.h_done, ((uint64_t)ns + 4) * 4, hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void **)&G.h_mu, (uint64_t)npair * 8, hipHostMallocDefault));
+    HIPCHK(hipMemcpyAsync(g->sd.p, G.sd.data(), ns * sizeof(SearchDesc), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(g->partners.p, G.partners.data(), ns * sizeof(Partner), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(g->pairdesc.p, G.pairs.data(), npair * sizeof(PairDesc), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(g->delta.p, G.delta.data(), (uint64_t)ns * 8, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemsetAsync(g->qcount.p, 0, 2 * NSEG * 4, st));
+    HIPCHK(hipMemsetAsync(g->cpre.p, 0, 2 * (NSEG + 1) * 4, st));
+    HIPCHK(hipMemsetAsync(g->round.p, 0, 16, st));
+    HIPCHK(hipMemsetAsync(g->hcount.p, 0, 16, st));
+    HIPCHK(hipMemsetAsync(g->err.p, 0, 16, st));
+    HIPCHK(hipMemsetAsync(g->stats.p, 0, ST_N * 8, st));
+    HIPCHK(hipMemsetAsync(g->wstats.p, 0, (uint64_t)G.grid * ST_N * 8, st));
+    HIPCHK(hipMemsetAsync(g->mu.p, 0xFF, (uint64_t)npair * 8, st));
+    set_args(g, G.A, ns, npair, 2);
+    HIPCHK(launch_idle(G.A, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return PPSP_OK;
+}
+
+// One chunk of the worker: admit, run rounds, collect. Called without the lock.
+int srv_chunk(ppsp_server srv, bool &any_running) {
+    std::vector<std::vector<uint32_t>> admit(srv->gs.size());
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        for (size_t gi = 0; gi < srv->gs.size(); gi++) {
+            SrvGraph &G = srv->gs[gi];
+            uint32_t slot = 0;
+            for (auto it = srv->pending.begin(); it != srv->pending.end();) {
+                SrvRequest &rq = srv->reqs[*it];
+                if (rq.graph != gi) { ++it; continue; }
+                const uint32_t k = (uint32_t)(rq.pairs.size() / 2);
+                while (rq.next < k) {
+                    const uint32_t s = rq.pairs[2 * rq.next], t = rq.pairs[2 * rq.next + 1];
+                    if (s == t) {                              // d(s,s) = 0 needs no search
+                        rq.dist[rq.next++] = 0;
+                        if (--rq.remaining == 0) { rq.done = true; rq.t_done = std::chrono::steady_clock::now(); srv->completed++; }
+                        continue;
+                    }
+                    while (slot < G.C && G.state[slot] != 0) slot++;
+                    if (slot == G.C) break;
+                    G.state[slot] = 1;
+                    G.slot_req[slot] = *it;
+                    G.slot_q[slot] = rq.next++;
+                    G.sd[2 * slot].src = s;
+                    G.sd[2 * slot + 1].src = t;
+                    SearchDesc f = make_sd(G.g, s, G.sd[2 * slot].kind, s, t);
+                    SearchDesc b = make_sd(G.g, t, G.sd[2 * slot + 1].kind, s, t);
+                    f.pbeg = G.sd[2 * slot].pbeg; f.pend = G.sd[2 * slot].pend;
+                    b.pbeg = G.sd[2 * slot + 1].pbeg; b.pend = G.sd[2 * slot + 1].pend;
+                    G.sd[2 * slot] = f;
+                    G.sd[2 * slot + 1] = b;
+                    admit[gi].push_back(slot);
+                    srv->admitted++;
+                }
+                if (rq.done) srv->cv_done.notify_all();
+                if (rq.next == k) it = srv->pending.erase(it); else ++it;
+                if (slot == G.C) break;
+            }
+        }
+    }
+    any_running = false;
+    for (size_t gi = 0; gi < srv->gs.size(); gi++) {
+        SrvGraph &G = srv->gs[gi];
+        ppsp_graph g = G.g;
+        hipStream_t st = g->st;
+        if (!admit[gi].empty()) {
+            std::vector<uint32_t> &ids = G.h_ids;
+            ids.clear();
+            for (uint32_t q : admit[gi]) {
+                ids.push_back(2 * q);
+                ids.push_back(2 * q + 1);
+                HIPCHK(hipMemsetAsync(g->S.as<uint64_t>() + (uint64_t)q * g->n * 2, 0xFF, (uint64_t)g->n * 16, st));
+            }
+            HIPCHK(hipMemcpyAsync(g->sd.p, G.sd.data(), G.sd.size() * sizeof(SearchDesc), hipMemcpyHostToDevice, st));
+            HIPCHK(hipMemcpyAsync(G.ids.p, ids.data(), ids.size() * 4, hipMemcpyHostToDevice, st));
+            HIPCHK(launch_admit(G.A, G.ids.as<uint32_t>(), (uint32_t)ids.size(), st));
+            G.running += (uint32_t)admit[gi].size();
+        }
+        // Rounds also run while slots drain: a finished search's last frontier
+        // entries are dropped by the round after the one that finished it.
+        if (G.running == 0 && G.draining == 0) continue;
+        any_running = true;
+        for (uint32_t k = 0; k < srv->rounds_per_chunk; k++) {
+            HIPCHK(launch_round(G.A, G.grid, st));
+            if (G.A.hcap) HIPCHK(launch_heavy(G.A, G.grid, st));
+            HIPCHK(launch_control(G.A, st));
+        }
+        HIPCHK(hipMemcpyAsync(G.h_done, g->done.p, (uint64_t)2 * G.C * 4, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(G.h_done + 2 * G.C, g->err.p, 4, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(G.h_mu, g->mu.p, (uint64_t)G.C * 8, hipMemcpyDeviceToHost, st));
+    }
+    for (auto &G : srv->gs) HIPCHK(hipStreamSynchronize(G.g->st));
+    std::lock_guard<std::mutex> lk(srv->mu);
+    srv->chunks++;
+    for (auto &G : srv->gs) {
+        if (G.running == 0 && G.draining == 0) continue;
+        srv->rounds += srv->rounds_per_chunk;
+        if (G.h_done[2 * G.C] & (ERR_QUEUE | ERR_HEAVY)) return PPSP_E_OOM;
+        if (G.h_done[2 * G.C] & ERR_OVERFLOW) return PPSP_E_OVERFLOW;
+        for (uint32_t q = 0; q < G.C; q++) {
+            if (G.state[q] == 2) { G.state[q] = 0; G.draining--; continue; }
+            if (G.state[q] != 1 || !G.h_done[2 * q] || !G.h_done[2 * q + 1]) continue;
+            SrvRequest &rq = srv->reqs[G.slot_req[q]];
+            const uint32_t d32 = (uint32_t)(G.h_mu[q] >> 32);
+            rq.dist[G.slot_q[q]] = d32 == INF32 ? PPSP_INF : d32;
+            G.state[q] = 2;
+            G.draining++;
+            G.running--;
+            if (--rq.remaining == 0) {
+                rq.done = true;
+                rq.t_done = std::chrono::steady_clock::now();
+                srv->completed++;
+            }
+        }
+    }
+    srv->cv_done.notify_all();
+    return PPSP_OK;
+}
+
+void srv_worker(ppsp_server srv) {
+    (void)hipSetDevice(srv->gs[0].g->device);
+    for (;;) {
+        {
+            std::unique_lock<std::mutex> lk(srv->mu);
+            bool idle = srv->pending.empty();
+            for (auto &G : srv->gs) idle = idle && G.running == 0 && G.draining == 0;
+            if (idle && !srv->stop)
+                srv->cv_work.wait_for(lk, std::chrono::milliseconds(20));
+            if (srv->stop) return;
+        }
+        bool any = false;
+        const int rc = srv_chunk(srv, any);
+        if (rc != PPSP_OK) {
+            std::lock_guard<std::mutex> lk(srv->mu);
+            srv->err = rc;
+            srv->cv_done.notify_all();
+            return;
+        }
+    }
 }
 
 }  // namespace
@@ -729,6 +1023,17 @@ int ppsp_graph_create(int device, uint32_t n, uint64_t m, const uint64_t *row_pt
     g->wmin = wmin;
     g->wmax = wmax;
     g->wmean = m ? std::max<uint64_t>(1, (wsum + m - 1) / m) : 1;
+    {
+        // FNV-1a over n, m and a stride sample of the arcs
+        uint64_t h = 1469598103934665603ull;
+        auto mix = [&](uint64_t x) { h = (h ^ x) * 1099511628211ull; };
+        mix(n);
+        mix(m);
+        const uint64_t step = std::max<uint64_t>(1, m / 4096);
+        for (uint64_t e = 0; e < m; e += step) { mix(col[e]); mix(w[e]); }
+        for (uint64_t v = 0; v <= n; v += std::max<uint64_t>(1, n / 1024)) mix(row_ptr[v]);
+        g->fingerprint = h;
+    }
     g->maxdeg = maxdeg;
     auto fail = [&](int rc) {
         ppsp_graph_destroy(g);
@@ -868,6 +1173,101 @@ int ppsp_query(ppsp_graph g, uint32_t s, uint32_t t, const ppsp_opts *opts, void
     return PPSP_OK;
 }
 
+int ppsp_tune(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp_opts *opts, const char *cache_path,
+              ppsp_tune_result *out) {
+    if (!g || !pairs || k == 0 || !opts || !out) return PPSP_E_INVALID;
+    CHK(check_opts(g, opts));
+    auto &slot = g->tuned[opts->algo][opts->batch];
+    char key[128];
+    snprintf(key, sizeof key, "ppsp-tune-v1 %016llx %u %u", (unsigned long long)g->fingerprint, opts->algo, opts->batch);
+    if (cache_path) {
+        if (FILE *f = fopen(cache_path, "r")) {
+            char line[256];
+            while (fgets(line, sizeof line, f)) {
+                unsigned long long d;
+                long long mode, grid;
+                double ms;
+                if (strncmp(line, key, strlen(key)) == 0 &&
+                    sscanf(line + strlen(key), " %llu %lld %lld %lf", &d, &mode, &grid, &ms) == 4) {
+                    slot.valid = true;
+                    slot.delta = d;
+                    slot.theta_mode = mode;
+                    slot.grid = grid;
+                    slot.ms = ms;
+                }
+            }
+            fclose(f);
+            if (slot.valid) {
+                *out = ppsp_tune_result{slot.delta, (uint32_t)slot.theta_mode, (uint32_t)slot.grid, slot.ms, 0, 0, 1};
+                return PPSP_OK;
+            }
+        }
+    }
+    std::vector<uint64_t> dist(k);
+    ppsp_opts o = *opts;
+    o.sched = PPSP_SCHED_FIXED;
+    o.flags &= ~PPSP_WANT_PATH;
+    const int64_t mode0 = g->opt_theta_mode, grid0 = g->opt_grid_blocks;
+    uint32_t trials = 0;
+    // wall time of one configuration (best of two runs; the first may allocate)
+    auto trial = [&](uint64_t delta, int64_t mode, int64_t grid) -> double {
+        g->opt_theta_mode = mode;
+        g->opt_grid_blocks = grid;
+        o.delta = delta;
+        double best = 1e300;
+        for (int rep = 0; rep < 2; rep++) {
+            if (batch_impl(g, pairs, k, &o, nullptr, dist.data(), nullptr, nullptr, 0, nullptr) != PPSP_OK) return 1e300;
+            best = std::min(best, g->last.wall_ms);
+        }
+        trials++;
+        return best;
+    };
+    const double default_ms = trial(graph_default_delta(g), 2, 0);
+    // 1. Delta by doubling (Section 6.1: start small, double while the time improves).
+    uint64_t d = std::max<uint64_t>(g->wmin ? g->wmin : 1, g->wmean / 16);
+    uint64_t best_d = d;
+    double best_ms = trial(d, 2, 0);
+    int worse = 0;
+    while (worse < 2 && d < 64 * g->wmean) {
+        d *= 2;
+        const double ms = trial(d, 2, 0);
+        if (ms < best_ms) { best_ms = ms; best_d = d; worse = 0; } else worse++;
+    }
+    int64_t best_mode = 2, best_grid = 0;
+    // 2. Refinement: threshold rule, Delta between the doublings, launch shape.
+    for (int64_t mode : {0, 1}) {
+        const double ms = trial(best_d, mode, 0);
+        if (ms < best_ms) { best_ms = ms; best_mode = mode; }
+    }
+    const uint64_t base_d = best_d;
+    for (double f : {0.7, 1.4}) {
+        const uint64_t dd = std::max<uint64_t>(1, (uint64_t)(base_d * f));
+        const double ms = trial(dd, best_mode, 0);
+        if (ms < best_ms) { best_ms = ms; best_d = dd; }
+    }
+    for (int64_t per_cu : {12, 32}) {
+        const double ms = trial(best_d, best_mode, per_cu * g->cu);
+        if (ms < best_ms) { best_ms = ms; best_grid = per_cu * g->cu; }
+    }
+    g->opt_theta_mode = mode0;
+    g->opt_grid_blocks = grid0;
+    if (best_ms >= 1e300) return PPSP_E_DEVICE;
+    slot.valid = true;
+    slot.delta = best_d;
+    slot.theta_mode = best_mode;
+    slot.grid = best_grid;
+    slot.ms = best_ms;
+    if (cache_path) {
+        if (FILE *f = fopen(cache_path, "a")) {
+            fprintf(f, "%s %llu %lld %lld %.3f\n", key, (unsigned long long)best_d, (long long)best_mode,
+                    (long long)best_grid, best_ms);
+            fclose(f);
+        }
+    }
+    *out = ppsp_tune_result{best_d, (uint32_t)best_mode, (uint32_t)best_grid, best_ms, default_ms, trials, 0};
+    return PPSP_OK;
+}
+
 int ppsp_last_stats(ppsp_graph g, ppsp_stats *s) {
     if (!g || !s) return PPSP_E_INVALID;
     *s = g->last;
@@ -907,6 +1307,127 @@ int ppsp_get_option(ppsp_graph g, const char *name, int64_t *v) {
     else if (k == "heavy_cap") *v = g->hcap;
 
     else return PPSP_E_INVALID;
+    return PPSP_OK;
+}
+
+
+int ppsp_server_create(const ppsp_graph *graphs, uint32_t ngraphs, const ppsp_opts *opts, uint64_t state_budget,
+                       ppsp_server *out) {
+    if (!graphs || ngraphs == 0 || !opts || !out) return PPSP_E_INVALID;
+    if (opts->algo != PPSP_BIDS && opts->algo != PPSP_BIDASTAR) return PPSP_E_INVALID;
+    for (uint32_t i = 0; i < ngraphs; i++) {
+        if (!graphs[i] || graphs[i]->served) return PPSP_E_INVALID;
+        if (!graphs[i]->symmetric) return PPSP_E_NOTSYM;
+        if (opts->algo == PPSP_BIDASTAR && !graphs[i]->xy_ok) return PPSP_E_NOCOORD;
+        if (graphs[i]->device != graphs[0]->device) return PPSP_E_INVALID;
+    }
+    ppsp_server srv = new ppsp_server_s();
+    srv->opts = *opts;
+    // rounds between admission points: the first graph's rounds_per_sync, at least 2
+    // (a finished slot must see one more round before it is reused)
+    srv->rounds_per_chunk = (uint32_t)std::min<int64_t>(std::max<int64_t>(graphs[0]->opt_rounds_per_sync, 2), 1024);
+    srv->gs.resize(ngraphs);
+    uint64_t total_n = 0;
+    for (uint32_t i = 0; i < ngraphs; i++) total_n += graphs[i]->n;
+    for (uint32_t i = 0; i < ngraphs; i++) {
+        srv->gs[i].g = graphs[i];
+        // the budget is shared in proportion to the graphs' sizes: equal slots per vertex
+        const uint64_t b = (uint64_t)((double)state_budget * graphs[i]->n / total_n);
+        int rc = srv_setup_graph(srv, srv->gs[i], b);
+        if (rc != PPSP_OK) {
+            for (uint32_t j = 0; j <= i; j++) {
+                if (srv->gs[j].h_done) (void)hipHostFree(srv->gs[j].h_done);
+                if (srv->gs[j].h_mu) (void)hipHostFree(srv->gs[j].h_mu);
+                release(srv->gs[j].ids);
+            }
+            delete srv;
+            return rc;
+        }
+        graphs[i]->served = true;
+    }
+    srv->worker = std::thread(srv_worker, srv);
+    *out = srv;
+    return PPSP_OK;
+}
+
+int ppsp_server_submit(ppsp_server srv, uint32_t graph_id, const uint32_t *pairs, uint32_t k, uint64_t *req_id) {
+    if (!srv || !req_id || (k && !pairs) || graph_id >= srv->gs.size()) return PPSP_E_INVALID;
+    const uint32_t n = srv->gs[graph_id].g->n;
+    for (uint64_t i = 0; i < 2ull * k; i++)
+        if (pairs[i] >= n) return PPSP_E_RANGE;
+    std::lock_guard<std::mutex> lk(srv->mu);
+    if (srv->err != PPSP_OK) return srv->err;
+    const uint64_t id = srv->next_id++;
+    SrvRequest &rq = srv->reqs[id];
+    rq.graph = graph_id;
+    rq.pairs.assign(pairs, pairs + 2ull * k);
+    rq.dist.assign(k, PPSP_INF);
+    rq.remaining = k;
+    rq.t_submit = std::chrono::steady_clock::now();
+    if (k == 0) { rq.done = true; rq.t_done = rq.t_submit; srv->completed++; }
+    else srv->pending.push_back(id);
+    *req_id = id;
+    srv->cv_work.notify_all();
+    return PPSP_OK;
+}
+
+static int server_take(ppsp_server srv, uint64_t req_id, uint64_t *dist, double *latency_ms) {
+    auto it = srv->reqs.find(req_id);
+    if (it == srv->reqs.end()) return PPSP_E_INVALID;
+    if (!it->second.done) return srv->err != PPSP_OK ? srv->err : PPSP_E_BUSY;
+    if (dist) std::copy(it->second.dist.begin(), it->second.dist.end(), dist);
+    if (latency_ms)
+        *latency_ms = std::chrono::duration<double, std::milli>(it->second.t_done - it->second.t_submit).count();
+    srv->reqs.erase(it);
+    return PPSP_OK;
+}
+
+int ppsp_server_poll(ppsp_server srv, uint64_t req_id, uint64_t *dist, double *latency_ms) {
+    if (!srv) return PPSP_E_INVALID;
+    std::lock_guard<std::mutex> lk(srv->mu);
+    return server_take(srv, req_id, dist, latency_ms);
+}
+
+int ppsp_server_wait(ppsp_server srv, uint64_t req_id, uint64_t *dist, double *latency_ms, uint32_t timeout_ms) {
+    if (!srv) return PPSP_E_INVALID;
+    std::unique_lock<std::mutex> lk(srv->mu);
+    const auto until = std::chrono::steady_clock::now() + std::chrono::milliseconds(timeout_ms);
+    for (;;) {
+        const int rc = server_take(srv, req_id, dist, latency_ms);
+        if (rc != PPSP_E_BUSY) return rc;
+        if (srv->cv_done.wait_until(lk, until) == std::cv_status::timeout) return server_take(srv, req_id, dist, latency_ms);
+    }
+}
+
+int ppsp_server_stats(ppsp_server srv, ppsp_server_counters *out) {
+    if (!srv || !out) return PPSP_E_INVALID;
+    std::lock_guard<std::mutex> lk(srv->mu);
+    *out = ppsp_server_counters{};
+    out->admitted = srv->admitted;
+    out->completed = srv->completed;
+    out->chunks = srv->chunks;
+    out->rounds = srv->rounds;
+    for (auto &G : srv->gs) { out->running += G.running; out->slots += G.C; }
+    out->pending = srv->pending.size();
+    return PPSP_OK;
+}
+
+int ppsp_server_destroy(ppsp_server srv) {
+    if (!srv) return PPSP_OK;
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        srv->stop = true;
+        srv->cv_work.notify_all();
+    }
+    if (srv->worker.joinable()) srv->worker.join();
+    for (auto &G : srv->gs) {
+        (void)hipStreamSynchronize(G.g->st);
+        if (G.h_done) (void)hipHostFree(G.h_done);
+        if (G.h_mu) (void)hipHostFree(G.h_mu);
+        release(G.ids);
+        G.g->served = false;
+    }
+    delete srv;
     return PPSP_OK;
 }
 

@@ -546,6 +546,51 @@ __global__ __launch_bounds__(BLOCK) void k_init(RoundArgs A) {
     A.exh[i] = 0;
 }
 
+// Serving: Init() for the searches listed in ids[0..k), inserted between
+// rounds into a running round loop. Their state slabs were cleared by the
+// host; their roots join the frontier the next round reads, and their
+// per-search control words are set for that round's parity.
+__global__ __launch_bounds__(BLOCK) void k_admit(RoundArgs A, const uint32_t *ids, uint32_t k) {
+    const uint32_t j = blockIdx.x * BLOCK + threadIdx.x;
+    if (j >= k) return;
+    const uint32_t i = ids[j];
+    const uint32_t r = A.round[0];
+    const uint32_t par = r & 1, np = par ^ 1;
+    const SearchDesc sd = A.sd[i];
+    const uint32_t s = sd.src;
+    A.S[state_index(A.G, A.n, i, s)] = 0;                   // distance 0, stamp 0
+    const int32_t hk = hterm(A, sd, s);
+    const uint32_t x = i % NSEG;
+    const uint32_t pos = atomicAdd(&A.qcount[par * NSEG + x], 1u);
+    uint4 *q = par ? A.q1 : A.q0;
+    if (pos < A.qseg) q[(uint64_t)x * A.qseg + pos] = make_uint4(i, s, 0u, (uint32_t)hk);
+    else atomicOr(A.err, ERR_QUEUE);
+    A.ctl[i] = make_ulonglong2(key_of(sd.kind, 0, hk), INF64);
+    A.alive[(uint64_t)par * A.nsearch + i] = 0;
+    A.alive[(uint64_t)np * A.nsearch + i] = 0;
+    A.minkey[(uint64_t)par * A.nsearch + i] = INF64;
+    A.minkey[(uint64_t)np * A.nsearch + i] = INF64;
+    A.done[i] = 0;
+    A.exh[i] = 0;
+    for (uint32_t p = sd.pbeg; p < sd.pend; p++) A.mu[A.partners[p].pair] = INF64;
+}
+
+// Serving: chunk layout of the queue the next round reads, after admissions.
+__global__ __launch_bounds__(WAVE) void k_reprefix(RoundArgs A) { chunk_prefix(A, A.round[0] & 1); }
+
+// Serving: every search idle (finished, nothing to prune against).
+__global__ __launch_bounds__(BLOCK) void k_idle(RoundArgs A) {
+    const uint32_t i = blockIdx.x * BLOCK + threadIdx.x;
+    if (i >= A.nsearch) return;
+    A.ctl[i] = make_ulonglong2(0, 0);
+    A.done[i] = 1;
+    A.exh[i] = 0;
+    A.alive[i] = 0;
+    A.alive[(uint64_t)A.nsearch + i] = 0;
+    A.minkey[i] = INF64;
+    A.minkey[(uint64_t)A.nsearch + i] = INF64;
+}
+
 __device__ __forceinline__ uint32_t dist_of(const RoundArgs &A, uint32_t i, uint32_t v) {
     return (uint32_t)(A.S[state_index(A.G, A.n, i, v)] >> 32);
 }
@@ -621,6 +666,17 @@ __global__ void k_path_write(RoundArgs A, const PairDesc *pd, const uint32_t *le
 hipError_t launch_init(const RoundArgs &A, hipStream_t st) {
     k_init<<<(A.nsearch + BLOCK - 1) / BLOCK, BLOCK, 0, st>>>(A);
     k_seed_prefix<<<1, WAVE, 0, st>>>(A);
+    return hipGetLastError();
+}
+
+hipError_t launch_admit(const RoundArgs &A, const uint32_t *ids, uint32_t k, hipStream_t st) {
+    if (k) k_admit<<<(k + BLOCK - 1) / BLOCK, BLOCK, 0, st>>>(A, ids, k);
+    k_reprefix<<<1, WAVE, 0, st>>>(A);
+    return hipGetLastError();
+}
+
+hipError_t launch_idle(const RoundArgs &A, hipStream_t st) {
+    k_idle<<<(A.nsearch + BLOCK - 1) / BLOCK, BLOCK, 0, st>>>(A);
     return hipGetLastError();
 }
 

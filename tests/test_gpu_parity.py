@@ -296,3 +296,22 @@ def test_config4_rmat_sampled(P):
     got = G.batch_query(pairs, algo="bids", batch="multi")
     assert np.array_equal(got[idx], exp)
     G.close()
+
+
+def test_autotune_changes_speed_not_results(P, tmp_path):
+    g = gen.lattice(160, 0.05, seed=21)
+    pairs = gen.pairs_uniform(g.n, 64, seed=22)
+    exp = _oracle(g, pairs)
+    G = _graph(P, g)
+    cache = str(tmp_path / "tune.txt")
+    r = G.tune(pairs[:32], algo="bidastar", batch="plainstar", cache_path=cache)
+    assert r["delta"] > 0 and r["trials"] >= 6 and r["from_cache"] == 0
+    got = G.batch_query(pairs, algo="bidastar", batch="plainstar", sched="autotuned")
+    assert np.array_equal(got, exp)
+    G.close()
+    # a new handle on the same graph reads the choice back from the cache
+    G2 = _graph(P, g)
+    r2 = G2.tune(pairs[:32], algo="bidastar", batch="plainstar", cache_path=cache)
+    assert r2["from_cache"] == 1 and r2["delta"] == r["delta"] and r2["theta_mode"] == r["theta_mode"]
+    assert np.array_equal(G2.batch_query(pairs, algo="bidastar", sched="autotuned"), exp)
+    G2.close()

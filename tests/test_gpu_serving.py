@@ -1,0 +1,129 @@
+"""GPU tests of the continuous-batching server (ppsp_server_* through the C-ABI).
+
+Every request's distances must equal the oracle's and the same library's
+answer for that request run alone (ppsp_batch_query before the server took
+the graph), whatever else shares the device with it: queries are admitted
+into a running round loop between rounds, and slots are reused.
+"""
+import time
+
+import numpy as np
+import pytest
+
+import gen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2506_16488_amd as P
+    P.lib()
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    return P
+
+
+def _oracle(g, pairs):
+    return oracle.pp_batch(g.n, g.row_ptr, g.col, g.w, pairs)
+
+
+def _requests(graphs, sizes, seed):
+    """Request i goes to graph i % len(graphs); a few self pairs mixed in."""
+    out = []
+    for i, k in enumerate(sizes):
+        gi = i % len(graphs)
+        p = gen.pairs_uniform(graphs[gi].n, k, seed=seed + i)
+        if k > 2:
+            p[1, 1] = p[1, 0]
+        out.append((gi, p))
+    return out
+
+
+def _serve(P, hosts, algo, reqs, slots, stagger_s):
+    Gs = [P.Graph.from_host(g) for g in hosts]
+    alone = [Gs[gi].batch_query(p, algo=algo, batch="plainstar") for gi, p in reqs]
+    budget = 16 * sum(g.n for g in hosts) * slots        # `slots` query slots per graph
+    S = P.Server(Gs, algo=algo, state_budget_bytes=budget)
+    assert S.stats()["slots"] == slots * len(hosts)
+    ids = []
+    for gi, p in reqs:
+        ids.append(S.submit(gi, p))
+        time.sleep(stagger_s)
+    res = [S.wait(r, timeout_ms=120000) for r in ids]
+    st = S.stats()
+    S.close()
+    for G in Gs:
+        G.close()
+    return alone, res, st
+
+
+def test_server_isolation_and_admission(P):
+    """Two resident lattices, BiD-A*, 4 slots each, 14 requests of 1..37
+    queries submitted while earlier ones run: each request equals the oracle
+    and its own run alone."""
+    hosts = [gen.lattice(200, 0.05, seed=5), gen.lattice(120, 0.1, seed=6)]
+    sizes = [1, 9, 37, 3, 16, 2, 25, 5, 12, 1, 30, 7, 4, 20]
+    reqs = _requests(hosts, sizes, seed=500)
+    alone, res, st = _serve(P, hosts, "bidastar", reqs, slots=4, stagger_s=0.002)
+    for (gi, p), a, (d, lat) in zip(reqs, alone, res):
+        exp = _oracle(hosts[gi], p)
+        assert np.array_equal(a, exp)
+        assert np.array_equal(d, exp)
+        assert lat > 0
+    nself = sum(int(np.sum(p[:, 0] == p[:, 1])) for _, p in reqs)
+    assert st["admitted"] == sum(sizes) - nself
+    assert st["completed"] == len(reqs)
+    assert st["running"] == 0 and st["pending"] == 0
+
+
+def test_server_bids_unreachable_and_hubs(P):
+    """BiDS over a disconnected random graph and an R-MAT graph with hub
+    vertices (heavy-list path): unreachable pairs return INF in the mix."""
+    hosts = [gen.random_graph(3000, 2400, 100, seed=21), gen.rmat(12, 16, seed=52)]
+    sizes = [8, 40, 3, 17, 1, 29, 11, 6]
+    reqs = _requests(hosts, sizes, seed=700)
+    alone, res, st = _serve(P, hosts, "bids", reqs, slots=6, stagger_s=0.0)
+    n_inf = 0
+    for (gi, p), a, (d, _) in zip(reqs, alone, res):
+        exp = _oracle(hosts[gi], p)
+        assert np.array_equal(a, exp)
+        assert np.array_equal(d, exp)
+        n_inf += int(np.sum(exp == oracle.INF))
+    assert n_inf > 0, "the random graph should leave some pairs unreachable"
+
+
+def test_server_single_slot_reuse(P):
+    """One slot: every query reuses the slot its predecessor just left."""
+    hosts = [gen.lattice(64, 0.2, seed=8)]
+    reqs = _requests(hosts, [5, 1, 7, 3], seed=900)
+    alone, res, _ = _serve(P, hosts, "bidastar", reqs, slots=1, stagger_s=0.0)
+    for (gi, p), a, (d, _) in zip(reqs, alone, res):
+        assert np.array_equal(d, _oracle(hosts[gi], p))
+        assert np.array_equal(d, a)
+
+
+def test_server_errors_and_release(P):
+    g = gen.lattice(40, 0.3, seed=9)
+    G = P.Graph.from_host(g)
+    with pytest.raises(P.PPSPError):
+        P.Server([G], algo="et")                        # one-directional modes are not served
+    S = P.Server([G], algo="bids", state_budget_bytes=1 << 24)
+    with pytest.raises(P.PPSPError) as e:
+        G.query(0, 1, algo="bids")                      # reserved while served
+    assert e.value.code == P.E_BUSY
+    with pytest.raises(P.PPSPError) as e:
+        S.submit(0, np.array([[0, g.n]], np.uint32))
+    assert e.value.code == P.E_RANGE
+    with pytest.raises(P.PPSPError):
+        S.submit(1, np.array([[0, 1]], np.uint32))      # no graph 1
+    r = S.submit(0, np.zeros((0, 2), np.uint32))        # empty request completes at once
+    d, _ = S.wait(r)
+    assert d.shape == (0,)
+    r = S.submit(0, np.array([[3, 3]], np.uint32))
+    assert S.wait(r)[0].tolist() == [0]
+    S.close()
+    p = gen.pairs_uniform(g.n, 10, seed=1)
+    assert np.array_equal(G.batch_query(p, algo="bids"), _oracle(g, p))  # usable again
+    G.close()
