@@ -235,3 +235,34 @@ def config_pairs(k: int, g: Graph, batch: int = 0, cand: Optional[np.ndarray] = 
             cand = lcc(g)
         return pairs_uniform(cand, 256, seed, stream=batch * 16)
     raise ValueError(k)
+
+
+# ---- learned-schedule network: initial parameters and synthetic rows ----------
+
+MLP_SHAPES = [(64, 12), (64,), (64, 64), (64,), (8, 64), (8,)]
+
+
+def mlp_init(seed: int) -> np.ndarray:
+    """Initial parameters of the 12-64-64-8 network (flat float32, W1 b1 W2 b2
+    W3 b3): weights uniform in +-sqrt(6 / fan_in), biases 0."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for shp in MLP_SHAPES:
+        if len(shp) == 2:
+            lim = np.sqrt(6.0 / shp[1])
+            out.append(rng.uniform(-lim, lim, shp).reshape(-1))
+        else:
+            out.append(np.zeros(shp))
+    return np.concatenate(out).astype(np.float32)
+
+
+def mlp_rows(n: int, seed: int, learnable: bool = True):
+    """n synthetic feature rows in [-1, 1) and labels in 0..7; with
+    learnable=True the label is a fixed function of the first two features."""
+    rng = np.random.default_rng(seed)
+    X = rng.uniform(-1.0, 1.0, (n, 12)).astype(np.float32)
+    if learnable:
+        y = np.clip(np.floor(4.0 + 2.0 * X[:, 0] + 1.5 * X[:, 1]), 0, 7).astype(np.uint32)
+    else:
+        y = rng.integers(0, 8, n).astype(np.uint32)
+    return X, y

@@ -202,6 +202,74 @@ int ppsp_tune(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp_opts *
               ppsp_tune_result *out);
 
 /*
+ * Learned step schedule (PPSP_SCHED_LEARNED). The stepping framework of
+ * Section 2 lets any threshold sequence through (Theorems bids-correctness
+ * and bdastar-correctness hold for every stepping rule), and the best Delta
+ * depends on the query (Section 2's discussion of Delta and rho). With a
+ * network loaded on the graph, every search picks its own step each round:
+ * a 12 -> 64 -> 64 -> 8 perceptron (ReLU; parameters in bf16 on the device,
+ * fp32 arithmetic) maps 12 features of the search's state to one of 8
+ * multipliers 2^(b-4) of the base Delta; the threshold rule stays the
+ * graph's "theta_mode". Distances are exact whatever the network says.
+ *
+ * Parameters: PPSP_MLP_PARAMS floats, row-major, in this order:
+ *   W1 [64][12], b1 [64], W2 [64][64], b2 [64], W3 [8][64], b3 [8].
+ * Features (per search after each round; Delta = its base Delta, in key units):
+ *   0 log2(1+extracted)/16  1 log2(1+arcs scanned)/16  2 log2(1+next frontier)/16
+ *   3 (log2(1+next) - log2(1+partner's next))/8   4 log2(1+(bound-minkey)/Delta)/16 (0 if bound infinite)
+ *   5 bound infinite (1/0)  6 log2(1+(minkey-theta)/Delta)/8  7 log2(1+(theta-root key)/Delta)/16
+ *   8 log2(1+heuristic s-t distance/Delta)/16  9 log2(1+round)/16  10 (previous bin-4)/4  11 log2(m/n)/4
+ *
+ * ppsp_mlp_forward  logits [n][8] of feature rows x [n][12] (device `device`).
+ * ppsp_mlp_grad     mean cross-entropy loss of labels y (< 8) and its gradient
+ *                   with respect to the parameters (grad: PPSP_MLP_PARAMS).
+ * ppsp_mlp_train    Adam (lr, beta 0.9/0.999) on mini-batches of `batch` rows,
+ *                   reshuffled every epoch from `seed`; params is the initial
+ *                   value on entry and the result on return; losses are the
+ *                   full-data mean before and after.
+ * ppsp_mlp_load     installs params on g (rounded to bf16); enables
+ *                   PPSP_SCHED_LEARNED there.
+ * ppsp_sched_trace  runs a Plain or Plain* batch with the multiplier bin of
+ *                   each pair fixed (bins[k], NULL = 4, i.e. the base Delta),
+ *                   records up to cap feature rows (feat [cap][12], row_pair:
+ *                   the pair each row belongs to; *nrows = rows produced,
+ *                   possibly more than cap) and per pair the rounds its
+ *                   searches ran and the arcs they scanned.
+ * ppsp_mlp_fit      the whole training recipe on sample pairs: labels by
+ *                   timing every pair alone under each of the 8 fixed
+ *                   multipliers (the fastest wins), feature rows traced along
+ *                   the labelled and the default trajectories, training from
+ *                   `init` (caller-drawn), then ppsp_mlp_load.
+ * Errors: PPSP_E_INVALID (null pointers, label >= 8, a non-finite
+ * parameter, Multi-BiDS for tracing), the errors of ppsp_batch_query.
+ */
+#define PPSP_MLP_FEATURES 12
+#define PPSP_MLP_BINS 8
+#define PPSP_MLP_PARAMS 5512
+
+typedef struct {
+    uint32_t label_hist[8];   /* pairs per label bin */
+    uint64_t rows;            /* training rows */
+    double loss_first;        /* mean loss before training */
+    double loss_last;         /* after */
+    double train_acc;         /* fraction of rows whose argmax is the label */
+    double label_ms;          /* time spent labelling */
+    double train_ms;          /* time spent training */
+} ppsp_fit_report;
+
+int ppsp_mlp_forward(int device, const float *params, const float *x, uint32_t n, float *logits);
+int ppsp_mlp_grad(int device, const float *params, const float *x, const uint32_t *y, uint32_t n, float *grad,
+                  double *loss);
+int ppsp_mlp_train(int device, float *params, const float *x, const uint32_t *y, uint32_t n, uint32_t epochs,
+                   uint32_t batch, float lr, uint64_t seed, double *loss_first, double *loss_last);
+int ppsp_mlp_load(ppsp_graph g, const float *params);
+int ppsp_sched_trace(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp_opts *opts, const uint8_t *bins,
+                     float *feat, uint32_t *row_pair, uint64_t cap, uint64_t *nrows, uint32_t *pair_rounds,
+                     uint64_t *pair_arcs);
+int ppsp_mlp_fit(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp_opts *opts, const float *init,
+                 uint32_t epochs, uint64_t seed, float *params_out, ppsp_fit_report *rep);
+
+/*
  * Serving (continuous batching). A server owns one or more resident graphs
  * (all on one device) and a worker thread that keeps their round loops
  * running. Each graph gets a fixed pool of query slots (one forward and one

@@ -76,10 +76,24 @@ class ServerCounters(ctypes.Structure):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
 
 
+class FitReport(ctypes.Structure):
+    _fields_ = [("label_hist", ctypes.c_uint32 * 8), ("rows", ctypes.c_uint64), ("loss_first", ctypes.c_double),
+                ("loss_last", ctypes.c_double), ("train_acc", ctypes.c_double), ("label_ms", ctypes.c_double),
+                ("train_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["label_hist"] = list(self.label_hist)
+        return d
+
+
+MLP_FEATURES, MLP_BINS, MLP_PARAMS = 12, 8, 5512
+
 EXPORTS = ["ppsp_graph_create", "ppsp_graph_destroy", "ppsp_query", "ppsp_batch_query", "ppsp_last_stats",
            "ppsp_set_option", "ppsp_get_option", "ppsp_heuristic_fx", "ppsp_status_str", "ppsp_version",
            "ppsp_last_error", "ppsp_tune", "ppsp_server_create", "ppsp_server_submit", "ppsp_server_poll",
-           "ppsp_server_wait", "ppsp_server_stats", "ppsp_server_destroy"]
+           "ppsp_server_wait", "ppsp_server_stats", "ppsp_server_destroy", "ppsp_mlp_forward", "ppsp_mlp_grad",
+           "ppsp_mlp_train", "ppsp_mlp_load", "ppsp_sched_trace", "ppsp_mlp_fit"]
 
 _lib_handle = None
 
@@ -134,6 +148,16 @@ def lib():
         L.ppsp_server_destroy.argtypes = [P]
         for f in ("create", "submit", "poll", "wait", "stats", "destroy"):
             getattr(L, "ppsp_server_" + f).restype = ctypes.c_int
+        L.ppsp_mlp_forward.argtypes = [ctypes.c_int, P, P, u32, P]
+        L.ppsp_mlp_grad.argtypes = [ctypes.c_int, P, P, P, u32, P, ctypes.POINTER(ctypes.c_double)]
+        L.ppsp_mlp_train.argtypes = [ctypes.c_int, P, P, P, u32, u32, u32, ctypes.c_float, u64,
+                                     ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+        L.ppsp_mlp_load.argtypes = [P, P]
+        L.ppsp_sched_trace.argtypes = [P, P, u32, ctypes.POINTER(Opts), P, P, P, u64, ctypes.POINTER(u64), P, P]
+        L.ppsp_mlp_fit.argtypes = [P, P, u32, ctypes.POINTER(Opts), P, u32, u64, P, ctypes.POINTER(FitReport)]
+        for f in ("forward", "grad", "train", "load", "fit"):
+            getattr(L, "ppsp_mlp_" + f).restype = ctypes.c_int
+        L.ppsp_sched_trace.restype = ctypes.c_int
         _lib_handle = L
     return _lib_handle
 
@@ -252,6 +276,45 @@ def tune(h, pairs, opts: Opts, cache_path=None) -> dict:
     return r.as_dict()
 
 
+def _f32(a, shape=None):
+    a = np.ascontiguousarray(a, np.float32)
+    if shape is not None:
+        a = a.reshape(shape)
+    return a
+
+
+def mlp_forward(params, X, device=0) -> np.ndarray:
+    """Logits [n][8] of feature rows X [n][12] (ppsp_mlp_forward)."""
+    p = _f32(params, (MLP_PARAMS,))
+    X = _f32(X, (-1, MLP_FEATURES))
+    out = np.empty((X.shape[0], MLP_BINS), np.float32)
+    _check(lib().ppsp_mlp_forward(device, _ptr(p), _ptr(X), X.shape[0], _ptr(out)), "ppsp_mlp_forward")
+    return out
+
+
+def mlp_grad(params, X, y, device=0):
+    """(mean cross-entropy loss, gradient) (ppsp_mlp_grad)."""
+    p = _f32(params, (MLP_PARAMS,))
+    X = _f32(X, (-1, MLP_FEATURES))
+    y = np.ascontiguousarray(y, np.uint32)
+    g = np.empty(MLP_PARAMS, np.float32)
+    L = ctypes.c_double(0)
+    _check(lib().ppsp_mlp_grad(device, _ptr(p), _ptr(X), _ptr(y), X.shape[0], _ptr(g), ctypes.byref(L)),
+           "ppsp_mlp_grad")
+    return L.value, g
+
+
+def mlp_train(params, X, y, epochs, batch=512, lr=2e-3, seed=0, device=0):
+    """(trained parameters, loss before, loss after) (ppsp_mlp_train)."""
+    p = _f32(params, (MLP_PARAMS,)).copy()
+    X = _f32(X, (-1, MLP_FEATURES))
+    y = np.ascontiguousarray(y, np.uint32)
+    l0, l1 = ctypes.c_double(0), ctypes.c_double(0)
+    _check(lib().ppsp_mlp_train(device, _ptr(p), _ptr(X), _ptr(y), X.shape[0], int(epochs), int(batch), float(lr),
+                                int(seed), ctypes.byref(l0), ctypes.byref(l1)), "ppsp_mlp_train")
+    return p, l0.value, l1.value
+
+
 def last_stats(h) -> dict:
     s = Stats()
     _check(lib().ppsp_last_stats(h, ctypes.byref(s)), "ppsp_last_stats")
@@ -295,6 +358,38 @@ class Graph:
 
     def tune(self, pairs, algo="bids", batch="plainstar", cache_path=None) -> dict:
         return tune(self.h, pairs, make_opts(algo, batch), cache_path)
+
+    def mlp_load(self, params):
+        p = _f32(params, (MLP_PARAMS,))
+        _check(lib().ppsp_mlp_load(self.h, _ptr(p)), "ppsp_mlp_load")
+
+    def sched_trace(self, pairs, algo="bids", batch="plainstar", bins=None, cap=0, delta=0):
+        """Fixed per-pair multiplier bins; returns (features [rows][12],
+        row_pair, rows produced, pair_rounds, pair_arcs)."""
+        pairs = np.ascontiguousarray(pairs, np.uint32).reshape(-1, 2)
+        k = pairs.shape[0]
+        b = None if bins is None else np.ascontiguousarray(np.broadcast_to(bins, (k,)), np.uint8)
+        feat = np.empty((cap, MLP_FEATURES), np.float32)
+        rowp = np.empty(cap, np.uint32)
+        nrows = ctypes.c_uint64(0)
+        pr = np.empty(k, np.uint32)
+        pa = np.empty(k, np.uint64)
+        _check(lib().ppsp_sched_trace(self.h, _ptr(pairs), k, ctypes.byref(make_opts(algo, batch, delta=delta)),
+                                      _ptr(b), _ptr(feat) if cap else None, _ptr(rowp) if cap else None, int(cap),
+                                      ctypes.byref(nrows), _ptr(pr), _ptr(pa)), "ppsp_sched_trace")
+        kept = min(int(nrows.value), cap)
+        return feat[:kept], rowp[:kept], int(nrows.value), pr, pa
+
+    def mlp_fit(self, pairs, init, algo="bids", batch="plainstar", epochs=20, seed=0, delta=0):
+        """Labels, traces, trains and loads the learned schedule; returns
+        (parameters, report dict)."""
+        pairs = np.ascontiguousarray(pairs, np.uint32).reshape(-1, 2)
+        p0 = _f32(init, (MLP_PARAMS,))
+        out = np.empty(MLP_PARAMS, np.float32)
+        rep = FitReport()
+        _check(lib().ppsp_mlp_fit(self.h, _ptr(pairs), pairs.shape[0], ctypes.byref(make_opts(algo, batch, delta=delta)),
+                                  _ptr(p0), int(epochs), int(seed), _ptr(out), ctypes.byref(rep)), "ppsp_mlp_fit")
+        return out, rep.as_dict()
 
     def set_option(self, name, value):
         set_option(self.h, name, value)

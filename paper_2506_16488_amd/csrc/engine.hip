@@ -18,6 +18,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <condition_variable>
 #include <cstdio>
 #include <deque>
@@ -31,6 +32,7 @@
 #include <vector>
 
 #include "../../include/ppsp.h"
+#include "mlp_dev.h"
 #include "ppsp_dev.h"
 
 namespace ppsp {
@@ -40,6 +42,13 @@ hipError_t launch_control(const RoundArgs &A, hipStream_t st);
 hipError_t launch_heavy(const RoundArgs &A, uint32_t grid, hipStream_t st);
 hipError_t launch_admit(const RoundArgs &A, const uint32_t *ids, uint32_t k, hipStream_t st);
 hipError_t launch_idle(const RoundArgs &A, hipStream_t st);
+hipError_t launch_mlp_forward(const float *P, const float *X, uint32_t n, float *logits, hipStream_t st);
+hipError_t launch_mlp_grad(const float *P, const float *X, const uint32_t *Y, const uint32_t *idx, uint32_t beg,
+                           uint32_t end, uint32_t per, uint32_t nw, float scale, float *partial, double *loss,
+                           hipStream_t st);
+hipError_t launch_mlp_reduce(const float *partial, uint32_t nw, float *grad, hipStream_t st);
+hipError_t launch_mlp_adam(float *P, float *m, float *v, const float *partial, uint32_t nw, float lr, uint32_t t,
+                           hipStream_t st);
 hipError_t launch_path_len(const RoundArgs &A, const PairDesc *pd, uint32_t *len, hipStream_t st);
 hipError_t launch_path_write(const RoundArgs &A, const PairDesc *pd, const uint32_t *len, const uint64_t *off,
                              uint32_t *out, hipStream_t st);
@@ -103,6 +112,22 @@ struct Plan {
     std::vector<Partner> partners;
     std::vector<PairDesc> pairs;
     std::vector<uint64_t> delta;    // per search, key units
+    std::vector<uint8_t> bin;       // per search: Delta-multiplier bin (learned / traced schedule)
+    std::vector<uint32_t> qid;      // per search: index of its query among the call's distinct queries
+};
+
+// Learned or traced step schedule of the current call.
+struct MlCtx {
+    int mode = 0;                        // 0 off, 1 trace with fixed bins, 2 learned
+    const std::vector<uint8_t> *qbin = nullptr;  // trace: bin per distinct query
+    bool rows = false;                   // trace: record feature rows
+    uint64_t cap = 0;                    // row capacity
+    // outputs per distinct query / per row (trace)
+    std::vector<uint32_t> q_rounds;
+    std::vector<uint64_t> q_arcs;
+    std::vector<float> feat;
+    std::vector<uint32_t> row_q;
+    uint64_t rows_total = 0;             // rows produced (may exceed cap)
 };
 
 }  // namespace
@@ -139,6 +164,10 @@ struct ppsp_graph_s {
     } tuned[5][3];                  // per (algo, batch strategy)
     uint64_t qcap = 0;
     bool served = false;            // attached to a server, which owns the workspace
+    // learned schedule
+    DevBuf sc, bin, done_round, tot_arcs, trace, trace_s, trace_n, mlpw;
+    bool mlp_loaded = false;
+    MlCtx *ml = nullptr;            // set for the duration of a learned or traced call
 };
 
 namespace {
@@ -211,6 +240,21 @@ void set_args(ppsp_graph g, RoundArgs &A, uint32_t nsearch, uint32_t npair, uint
     A.hcount = g->hcount.as<unsigned long long>();
     A.hcap = g->maxdeg > HEAVY_DEG ? g->hcap : 0;
     A.theta_mode = (uint32_t)g->opt_theta_mode;
+    if (g->ml && g->ml->mode) {
+        A.sc = g->sc.as<unsigned long long>();
+        A.ml_mode = (uint32_t)g->ml->mode;
+        A.mlp = g->ml->mode == 2 ? g->mlpw.as<uint16_t>() : nullptr;
+        A.bin = g->bin.as<uint8_t>();
+        A.done_round = g->done_round.as<uint32_t>();
+        A.tot_arcs = g->tot_arcs.as<unsigned long long>();
+        if (g->ml->rows && g->ml->cap) {
+            A.trace = g->trace.as<float>();
+            A.trace_s = g->trace_s.as<uint32_t>();
+            A.trace_cap = g->ml->cap;
+        }
+        A.trace_n = g->trace_n.as<unsigned long long>();
+        A.deg_feat = g->n ? (float)(std::log2(std::max(1.0, (double)g->m / g->n)) / 4.0) : 0.f;
+    }
 }
 
 int ensure_events(ppsp_graph g, size_t k) {
@@ -229,6 +273,12 @@ struct WaveOut {
     unsigned long long stats[ST_N] = {0};
     double relax_ms = 0;
     uint64_t launches = 0;
+    // learned / traced schedule: per search
+    std::vector<uint32_t> done_round;
+    std::vector<unsigned long long> tot_arcs;
+    std::vector<float> feat;        // trace rows
+    std::vector<uint32_t> row_s;
+    uint64_t rows_total = 0;
 };
 
 // Runs one wave of searches to completion.
@@ -282,6 +332,22 @@ int run_wave(ppsp_graph g, const Plan &P, bool want_path, WaveOut &out) {
         HIPCHK(hipMemsetAsync(g->hcount.p, 0, 16, st));
         HIPCHK(hipMemsetAsync(g->err.p, 0, 16, st));
         HIPCHK(hipMemsetAsync(g->stats.p, 0, ST_N * 8, st));
+        if (g->ml && g->ml->mode) {
+            CHK(ensure(g->sc, 2ull * ns * 16));
+            CHK(ensure(g->bin, ns));
+            CHK(ensure(g->done_round, (uint64_t)ns * 4));
+            CHK(ensure(g->tot_arcs, (uint64_t)ns * 8));
+            CHK(ensure(g->trace_n, 8));
+            if (g->ml->rows && g->ml->cap) {
+                CHK(ensure(g->trace, g->ml->cap * MLP_F * 4));
+                CHK(ensure(g->trace_s, g->ml->cap * 4));
+            }
+            HIPCHK(hipMemsetAsync(g->sc.p, 0, 2ull * ns * 16, st));
+            HIPCHK(hipMemcpyAsync(g->bin.p, P.bin.data(), ns, hipMemcpyHostToDevice, st));
+            HIPCHK(hipMemsetAsync(g->done_round.p, 0, (uint64_t)ns * 4, st));
+            HIPCHK(hipMemsetAsync(g->tot_arcs.p, 0, (uint64_t)ns * 8, st));
+            HIPCHK(hipMemsetAsync(g->trace_n.p, 0, 8, st));
+        }
         RoundArgs A;
         set_args(g, A, ns, npair, P.G);
         HIPCHK(launch_init(A, st));
@@ -368,6 +434,26 @@ int run_wave(ppsp_graph g, const Plan &P, bool want_path, WaveOut &out) {
         HIPCHK(hipStreamSynchronize(st));
         for (uint64_t b = 0; b < grid; b++)
             for (int k = 1; k < ST_N; k++) out.stats[k] += ws[b * ST_N + k];
+        if (g->ml && g->ml->mode == 1) {
+            out.done_round.resize(ns);
+            out.tot_arcs.resize(ns);
+            HIPCHK(hipMemcpyAsync(out.done_round.data(), g->done_round.p, (uint64_t)ns * 4, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipMemcpyAsync(out.tot_arcs.data(), g->tot_arcs.p, (uint64_t)ns * 8, hipMemcpyDeviceToHost, st));
+            unsigned long long nrow = 0;
+            HIPCHK(hipMemcpyAsync(&nrow, g->trace_n.p, 8, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            out.rows_total = nrow;
+            if (g->ml->rows && g->ml->cap) {
+                const uint64_t keep = std::min<uint64_t>(nrow, g->ml->cap);
+                out.feat.resize(keep * MLP_F);
+                out.row_s.resize(keep);
+                if (keep) {
+                    HIPCHK(hipMemcpyAsync(out.feat.data(), g->trace.p, keep * MLP_F * 4, hipMemcpyDeviceToHost, st));
+                    HIPCHK(hipMemcpyAsync(out.row_s.data(), g->trace_s.p, keep * 4, hipMemcpyDeviceToHost, st));
+                    HIPCHK(hipStreamSynchronize(st));
+                }
+            }
+        }
         out.relax_ms = relax_ms;
         out.launches = launches;
         if (want_path) {
@@ -452,6 +538,7 @@ int check_opts(ppsp_graph g, const ppsp_opts *o) {
     if (is_bidir(o->algo) && !g->symmetric) return PPSP_E_NOTSYM;
     if (o->batch == PPSP_BATCH_MULTI && o->algo != PPSP_BIDS) return PPSP_E_INVALID;
     if ((o->flags & PPSP_WANT_PATH) && g->wmin == 0 && g->m > 0) return PPSP_E_NOPATH;
+    if (o->sched == PPSP_SCHED_LEARNED && !g->mlp_loaded) return PPSP_E_INVALID;
     return PPSP_OK;
 }
 
@@ -500,14 +587,33 @@ int run_independent(ppsp_graph g, const std::vector<Query> &qs, const ppsp_opts 
         P.G = is_bidir(o->algo) ? 2 : 1;
         std::vector<uint32_t> ans_of_pair;
         for (size_t q = q0; q < q1; q++) {
+            const size_t a = P.sd.size();
             plan_single(g, P, qs[q].s, qs[q].t, o->algo, delta);
             ans_of_pair.push_back((uint32_t)q);
+            const uint8_t b = (g->ml && g->ml->mode == 1) ? (*g->ml->qbin)[q] : (uint8_t)(MLP_K / 2);
+            for (size_t i = a; i < P.sd.size(); i++) {
+                P.bin.push_back(b);
+                P.qid.push_back((uint32_t)q);
+            }
         }
         g->last.searches += P.sd.size();
         WaveOut w;
         CHK(run_wave(g, P, want_path, w));
         accumulate(g, w);
         collect(w, ans_of_pair, ans, want_path);
+        if (g->ml && g->ml->mode == 1) {
+            MlCtx &c = *g->ml;
+            for (size_t i = 0; i < P.sd.size(); i++) {
+                const uint32_t q = P.qid[i];
+                c.q_rounds[q] = std::max(c.q_rounds[q], w.done_round[i]);
+                c.q_arcs[q] += w.tot_arcs[i];
+            }
+            c.rows_total += w.rows_total;
+            for (size_t r = 0; r < w.row_s.size() && c.row_q.size() < c.cap; r++) {
+                c.row_q.push_back(P.qid[w.row_s[r]]);
+                c.feat.insert(c.feat.end(), w.feat.begin() + r * MLP_F, w.feat.begin() + (r + 1) * MLP_F);
+            }
+        }
     }
     return PPSP_OK;
 }
@@ -557,6 +663,7 @@ int run_multi(ppsp_graph g, const std::vector<Query> &qs, const ppsp_opts *o, ui
                 local[v] = (uint32_t)P.sd.size();
                 P.sd.push_back(make_sd(g, verts[v], K_2DIST, verts[v], verts[v]));
                 P.delta.push_back(key_delta(K_2DIST, delta));
+                P.bin.push_back((uint8_t)(MLP_K / 2));
             }
         // adjacency with pair slots
         std::vector<std::vector<Partner>> adj(P.sd.size());
@@ -638,6 +745,19 @@ int batch_impl(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp_opts 
         g->opt_theta_mode = t.theta_mode;
         g->opt_grid_blocks = t.grid;
     }
+    // PPSP_SCHED_LEARNED: the loaded network picks each search's step
+    // (a trace call has set its own context already).
+    MlCtx learned;
+    struct MlRestore {
+        ppsp_graph g;
+        bool set;
+        ~MlRestore() { if (set) g->ml = nullptr; }
+    } mlrestore{g, false};
+    if (o->sched == PPSP_SCHED_LEARNED && !g->ml) {
+        learned.mode = 2;
+        g->ml = &learned;
+        mlrestore.set = true;
+    }
     // distinct queries; on symmetric graphs (t,s) is the same query as (s,t)
     std::vector<Query> qs;
     std::vector<uint32_t> qidx(k);
@@ -693,6 +813,187 @@ int batch_impl(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp_opts 
 }
 
 }  // namespace
+
+// ---- learned schedule: tracing, training, fitting ------------------------------
+
+// Runs the batch with a fixed Delta-multiplier bin per pair (ml mode 1) and
+// collects, per pair, the rounds and arcs of its searches and, optionally,
+// the feature rows of its step decisions.
+int trace_impl(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp_opts *o, const uint8_t *bins,
+               bool rows, uint64_t cap, MlCtx &c, std::vector<uint32_t> &row_pair, std::vector<uint32_t> &pair_rounds,
+               std::vector<uint64_t> &pair_arcs) {
+    if (o->batch == PPSP_BATCH_MULTI) return PPSP_E_INVALID;
+    for (uint32_t i = 0; i < k; i++)
+        if (bins && bins[i] >= MLP_K) return PPSP_E_INVALID;
+    // distinct queries in first-occurrence order, as batch_impl forms them
+    std::unordered_map<uint64_t, uint32_t> seen;
+    std::vector<uint32_t> first, qof(k, UINT32_MAX);
+    std::vector<uint8_t> qbin;
+    for (uint32_t i = 0; i < k; i++) {
+        uint32_t s = pairs[2 * i], t = pairs[2 * i + 1];
+        if (s >= g->n || t >= g->n) return PPSP_E_RANGE;
+        if (s == t) continue;
+        if (g->symmetric && s > t && o->algo != PPSP_SSSP) std::swap(s, t);
+        auto it = seen.find(((uint64_t)s << 32) | t);
+        if (it == seen.end()) {
+            it = seen.emplace(((uint64_t)s << 32) | t, (uint32_t)first.size()).first;
+            first.push_back(i);
+            qbin.push_back(bins ? bins[i] : (uint8_t)(MLP_K / 2));
+        }
+        qof[i] = it->second;
+    }
+    c = MlCtx{};
+    c.mode = 1;
+    c.qbin = &qbin;
+    c.rows = rows;
+    c.cap = rows ? cap : 0;
+    c.q_rounds.assign(first.size(), 0);
+    c.q_arcs.assign(first.size(), 0);
+    g->ml = &c;
+    std::vector<uint64_t> dist(k);
+    ppsp_opts oo = *o;
+    oo.sched = PPSP_SCHED_FIXED;
+    oo.flags &= ~PPSP_WANT_PATH;
+    const int rc = batch_impl(g, pairs, k, &oo, nullptr, dist.data(), nullptr, nullptr, 0, nullptr);
+    g->ml = nullptr;
+    CHK(rc);
+    row_pair.resize(c.row_q.size());
+    for (size_t r = 0; r < c.row_q.size(); r++) row_pair[r] = first[c.row_q[r]];
+    pair_rounds.assign(k, 0);
+    pair_arcs.assign(k, 0);
+    for (uint32_t i = 0; i < k; i++)
+        if (qof[i] != UINT32_MAX) {
+            pair_rounds[i] = c.q_rounds[qof[i]];
+            pair_arcs[i] = c.q_arcs[qof[i]];
+        }
+    return PPSP_OK;
+}
+
+uint64_t splitmix64(uint64_t &x) {
+    uint64_t z = (x += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Device buffers of one training or evaluation call.
+struct MlpDev {
+    DevBuf P, X, Y, idx, partial, loss, m, v, grad, logits;
+    hipStream_t st = nullptr;
+    ~MlpDev() {
+        if (st) (void)hipStreamDestroy(st);
+    }
+};
+
+int mlp_setup(int device, MlpDev &d, const float *params, const float *x, const uint32_t *y, uint32_t n) {
+    HIPCHK(hipSetDevice(device));
+    HIPCHK(hipStreamCreateWithFlags(&d.st, hipStreamNonBlocking));
+    CHK(ensure(d.P, MLP_NPARAM * 4));
+    HIPCHK(hipMemcpyAsync(d.P.p, params, MLP_NPARAM * 4, hipMemcpyHostToDevice, d.st));
+    if (n) {
+        CHK(ensure(d.X, (uint64_t)n * MLP_F * 4));
+        HIPCHK(hipMemcpyAsync(d.X.p, x, (uint64_t)n * MLP_F * 4, hipMemcpyHostToDevice, d.st));
+        if (y) {
+            CHK(ensure(d.Y, (uint64_t)n * 4));
+            HIPCHK(hipMemcpyAsync(d.Y.p, y, (uint64_t)n * 4, hipMemcpyHostToDevice, d.st));
+        }
+    }
+    return PPSP_OK;
+}
+
+// Full-batch gradient (mean cross-entropy) and loss of the parameters in d.P.
+int mlp_full_grad(MlpDev &d, uint32_t n, float *grad, double *loss) {
+    const uint32_t nw = std::max<uint32_t>(1, std::min<uint32_t>(1024, (n + 15) / 16));
+    const uint32_t per = (n + nw - 1) / nw;
+    CHK(ensure(d.partial, (uint64_t)nw * MLP_NPARAM * 4));
+    CHK(ensure(d.loss, (uint64_t)nw * 8));
+    CHK(ensure(d.grad, MLP_NPARAM * 4));
+    HIPCHK(launch_mlp_grad(d.P.as<float>(), d.X.as<float>(), d.Y.as<uint32_t>(), nullptr, 0, n, per, nw,
+                           1.f / (float)std::max<uint32_t>(n, 1), d.partial.as<float>(), d.loss.as<double>(), d.st));
+    HIPCHK(launch_mlp_reduce(d.partial.as<float>(), nw, d.grad.as<float>(), d.st));
+    std::vector<double> l(nw);
+    HIPCHK(hipMemcpyAsync(l.data(), d.loss.p, (uint64_t)nw * 8, hipMemcpyDeviceToHost, d.st));
+    if (grad) HIPCHK(hipMemcpyAsync(grad, d.grad.p, MLP_NPARAM * 4, hipMemcpyDeviceToHost, d.st));
+    HIPCHK(hipStreamSynchronize(d.st));
+    double s = 0;
+    for (double v : l) s += v;
+    if (loss) *loss = n ? s / n : 0.0;
+    return PPSP_OK;
+}
+
+int mlp_train_impl(int device, float *params, const float *x, const uint32_t *y, uint32_t n, uint32_t epochs,
+                   uint32_t batch, float lr, uint64_t seed, double *loss_first, double *loss_last) {
+    if (!params || (n && (!x || !y)) || batch == 0 || !(lr > 0.f)) return PPSP_E_INVALID;
+    for (uint32_t i = 0; i < n; i++)
+        if (y[i] >= (uint32_t)MLP_K) return PPSP_E_INVALID;
+    MlpDev d;
+    CHK(mlp_setup(device, d, params, x, y, n));
+    if (loss_first) CHK(mlp_full_grad(d, n, nullptr, loss_first));
+    const uint32_t per = 16;
+    const uint32_t nwmax = (batch + per - 1) / per;
+    CHK(ensure(d.partial, (uint64_t)nwmax * MLP_NPARAM * 4));
+    CHK(ensure(d.loss, (uint64_t)std::max<uint32_t>(nwmax, 1024) * 8));
+    CHK(ensure(d.m, MLP_NPARAM * 4));
+    CHK(ensure(d.v, MLP_NPARAM * 4));
+    CHK(ensure(d.idx, (uint64_t)std::max<uint32_t>(n, 1) * 4));
+    HIPCHK(hipMemsetAsync(d.m.p, 0, MLP_NPARAM * 4, d.st));
+    HIPCHK(hipMemsetAsync(d.v.p, 0, MLP_NPARAM * 4, d.st));
+    std::vector<uint32_t> perm(n);
+    std::iota(perm.begin(), perm.end(), 0u);
+    uint64_t rs = seed;
+    uint32_t t = 0;
+    for (uint32_t e = 0; e < epochs && n; e++) {
+        for (uint32_t i = n - 1; i > 0; i--) std::swap(perm[i], perm[splitmix64(rs) % (i + 1)]);
+        HIPCHK(hipMemcpyAsync(d.idx.p, perm.data(), (uint64_t)n * 4, hipMemcpyHostToDevice, d.st));
+        HIPCHK(hipStreamSynchronize(d.st));    // perm is rewritten next epoch
+        for (uint32_t b = 0; b < n; b += batch) {
+            const uint32_t end = std::min<uint32_t>(n, b + batch);
+            const uint32_t nw = (end - b + per - 1) / per;
+            HIPCHK(launch_mlp_grad(d.P.as<float>(), d.X.as<float>(), d.Y.as<uint32_t>(), d.idx.as<uint32_t>(), b, end,
+                                   per, nw, 1.f / (float)(end - b), d.partial.as<float>(), d.loss.as<double>(), d.st));
+            HIPCHK(launch_mlp_adam(d.P.as<float>(), d.m.as<float>(), d.v.as<float>(), d.partial.as<float>(), nw, lr,
+                                   ++t, d.st));
+        }
+    }
+    if (loss_last) CHK(mlp_full_grad(d, n, nullptr, loss_last));
+    HIPCHK(hipMemcpyAsync(params, d.P.p, MLP_NPARAM * 4, hipMemcpyDeviceToHost, d.st));
+    HIPCHK(hipStreamSynchronize(d.st));
+    return PPSP_OK;
+}
+
+int mlp_forward_impl(int device, const float *params, const float *x, uint32_t n, float *logits) {
+    if (!params || (n && (!x || !logits))) return PPSP_E_INVALID;
+    MlpDev d;
+    CHK(mlp_setup(device, d, params, x, nullptr, n));
+    if (n == 0) return PPSP_OK;
+    CHK(ensure(d.logits, (uint64_t)n * MLP_K * 4));
+    HIPCHK(launch_mlp_forward(d.P.as<float>(), d.X.as<float>(), n, d.logits.as<float>(), d.st));
+    HIPCHK(hipMemcpyAsync(logits, d.logits.p, (uint64_t)n * MLP_K * 4, hipMemcpyDeviceToHost, d.st));
+    HIPCHK(hipStreamSynchronize(d.st));
+    return PPSP_OK;
+}
+
+uint16_t f32_to_bf16(float f) {
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    if ((u & 0x7F800000u) == 0x7F800000u && (u & 0x7FFFFFu)) return (uint16_t)((u >> 16) | 0x40);  // NaN stays NaN
+    u += 0x7FFFu + ((u >> 16) & 1u);                                                                 // nearest even
+    return (uint16_t)(u >> 16);
+}
+
+int mlp_load_impl(ppsp_graph g, const float *params) {
+    if (!g || !params) return PPSP_E_INVALID;
+    for (int i = 0; i < MLP_NPARAM; i++)
+        if (!std::isfinite(params[i])) return PPSP_E_INVALID;
+    CHK(set_device(g));
+    std::vector<uint16_t> h(MLP_NPARAM);
+    for (int i = 0; i < MLP_NPARAM; i++) h[i] = f32_to_bf16(params[i]);
+    CHK(ensure(g->mlpw, MLP_NPARAM * 2));
+    HIPCHK(hipMemcpyAsync(g->mlpw.p, h.data(), MLP_NPARAM * 2, hipMemcpyHostToDevice, g->st));
+    HIPCHK(hipStreamSynchronize(g->st));
+    g->mlp_loaded = true;
+    return PPSP_OK;
+}
 
 // ---- serving: continuous batching --------------------------------------------
 //
@@ -1428,6 +1729,115 @@ int ppsp_server_destroy(ppsp_server srv) {
         G.g->served = false;
     }
     delete srv;
+    return PPSP_OK;
+}
+
+
+int ppsp_mlp_forward(int device, const float *params, const float *x, uint32_t n, float *logits) {
+    return mlp_forward_impl(device, params, x, n, logits);
+}
+
+int ppsp_mlp_grad(int device, const float *params, const float *x, const uint32_t *y, uint32_t n, float *grad,
+                  double *loss) {
+    if (!params || (n && (!x || !y)) || !grad) return PPSP_E_INVALID;
+    for (uint32_t i = 0; i < n; i++)
+        if (y[i] >= (uint32_t)MLP_K) return PPSP_E_INVALID;
+    MlpDev d;
+    CHK(mlp_setup(device, d, params, x, y, n));
+    return mlp_full_grad(d, n, grad, loss);
+}
+
+int ppsp_mlp_train(int device, float *params, const float *x, const uint32_t *y, uint32_t n, uint32_t epochs,
+                   uint32_t batch, float lr, uint64_t seed, double *loss_first, double *loss_last) {
+    return mlp_train_impl(device, params, x, y, n, epochs, batch, lr, seed, loss_first, loss_last);
+}
+
+int ppsp_mlp_load(ppsp_graph g, const float *params) { return mlp_load_impl(g, params); }
+
+int ppsp_sched_trace(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp_opts *opts, const uint8_t *bins,
+                     float *feat, uint32_t *row_pair, uint64_t cap, uint64_t *nrows, uint32_t *pair_rounds,
+                     uint64_t *pair_arcs) {
+    if (!g || !opts || (k && !pairs) || (cap && (!feat || !row_pair))) return PPSP_E_INVALID;
+    if (g->served) return PPSP_E_BUSY;
+    MlCtx c;
+    std::vector<uint32_t> rp, pr;
+    std::vector<uint64_t> pa;
+    CHK(trace_impl(g, pairs, k, opts, bins, cap > 0, cap, c, rp, pr, pa));
+    if (cap) {
+        memcpy(feat, c.feat.data(), c.feat.size() * 4);
+        memcpy(row_pair, rp.data(), rp.size() * 4);
+    }
+    if (nrows) *nrows = c.rows_total;
+    if (pair_rounds) memcpy(pair_rounds, pr.data(), (uint64_t)k * 4);
+    if (pair_arcs) memcpy(pair_arcs, pa.data(), (uint64_t)k * 8);
+    return PPSP_OK;
+}
+
+int ppsp_mlp_fit(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp_opts *opts, const float *init,
+                 uint32_t epochs, uint64_t seed, float *params_out, ppsp_fit_report *rep) {
+    if (!g || !opts || !pairs || k == 0 || !init || !params_out) return PPSP_E_INVALID;
+    if (g->served) return PPSP_E_BUSY;
+    if (opts->batch == PPSP_BATCH_MULTI) return PPSP_E_INVALID;
+    CHK(check_opts(g, opts));
+    ppsp_fit_report R{};
+    // 1. Labels: each pair alone under every fixed multiplier; the label is
+    //    the bin that finished it fastest (best of two runs).
+    auto t0 = std::chrono::steady_clock::now();
+    std::vector<uint8_t> y(k, (uint8_t)(MLP_K / 2));
+    ppsp_opts one = *opts;
+    one.batch = PPSP_BATCH_PLAIN;
+    for (uint32_t i = 0; i < k; i++) {
+        if (pairs[2 * i] == pairs[2 * i + 1]) continue;
+        double best = 1e300;
+        for (uint8_t b = 0; b < MLP_K; b++) {
+            double tb = 1e300;
+            for (int rep2 = 0; rep2 < 2; rep2++) {
+                MlCtx c;
+                std::vector<uint32_t> rp, pr;
+                std::vector<uint64_t> pa;
+                const auto a = std::chrono::steady_clock::now();
+                CHK(trace_impl(g, pairs + 2ull * i, 1, &one, &b, false, 0, c, rp, pr, pa));
+                tb = std::min(tb, std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - a).count());
+            }
+            if (tb < best) { best = tb; y[i] = b; }
+        }
+    }
+    for (uint32_t i = 0; i < k; i++) R.label_hist[y[i]]++;
+    R.label_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    // 2. Feature rows along the labelled trajectories and the default one.
+    std::vector<float> X;
+    std::vector<uint32_t> Y;
+    const uint64_t cap = 1ull << 21;
+    for (int pass = 0; pass < 2; pass++) {
+        std::vector<uint8_t> bins(k, (uint8_t)(MLP_K / 2));
+        if (pass == 0) bins = y;
+        MlCtx c;
+        std::vector<uint32_t> rp, pr;
+        std::vector<uint64_t> pa;
+        CHK(trace_impl(g, pairs, k, opts, bins.data(), true, cap, c, rp, pr, pa));
+        X.insert(X.end(), c.feat.begin(), c.feat.end());
+        for (uint32_t q : rp) Y.push_back(y[q]);
+    }
+    R.rows = Y.size();
+    // 3. Training on the GPU.
+    t0 = std::chrono::steady_clock::now();
+    memcpy(params_out, init, MLP_NPARAM * 4);
+    CHK(mlp_train_impl(g->device, params_out, X.data(), Y.data(), (uint32_t)Y.size(), epochs, 512, 2e-3f, seed,
+                       &R.loss_first, &R.loss_last));
+    R.train_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    // 4. Training accuracy and loading.
+    std::vector<float> lg((uint64_t)Y.size() * MLP_K);
+    CHK(mlp_forward_impl(g->device, params_out, X.data(), (uint32_t)Y.size(), lg.data()));
+    uint64_t hit = 0;
+    for (size_t r = 0; r < Y.size(); r++) {
+        uint32_t best = 0;
+        for (uint32_t b = 1; b < (uint32_t)MLP_K; b++)
+            if (lg[r * MLP_K + b] > lg[r * MLP_K + best]) best = b;
+        hit += best == Y[r];
+    }
+    R.train_acc = Y.empty() ? 0.0 : (double)hit / Y.size();
+    CHK(mlp_load_impl(g, params_out));
+    if (rep) *rep = R;
     return PPSP_OK;
 }
 

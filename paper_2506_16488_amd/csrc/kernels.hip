@@ -53,6 +53,7 @@
 // The round number lives in device memory (written by the kernel that does
 // not read it in the same launch), so a fixed sequence of launches can be
 // captured once in a hipGraph and replayed.
+#include "mlp_dev.h"
 #include "ppsp_dev.h"
 
 namespace ppsp {
@@ -137,13 +138,32 @@ __device__ __forceinline__ void search_stats(const RoundArgs &A, uint32_t np, ui
             if (tot && *al == 0) *al = 1;
             unsigned long long *mp = (unsigned long long *)&A.minkey[(uint64_t)np * A.nsearch + i0];
             if (mn < *mp) atomicMin(mp, mn);
+            if (A.sc && tot) atomicAdd(&A.sc[((uint64_t)(np ^ 1) * A.nsearch + i0) * 2 + 1], (unsigned long long)tot);
         }
     } else if (has) {
         uint32_t *al = &A.alive[(uint64_t)np * A.nsearch + i];
         if (cnt && *al == 0) *al = 1;
         unsigned long long *mp = (unsigned long long *)&A.minkey[(uint64_t)np * A.nsearch + i];
         if (mink < *mp) atomicMin(mp, mink);
+        if (A.sc && cnt) atomicAdd(&A.sc[((uint64_t)(np ^ 1) * A.nsearch + i) * 2 + 1], (unsigned long long)cnt);
     }
+}
+
+// ctr[2 * key + field] += val for every active lane: one atomic per distinct
+// key for the first few keys of the wave, then one per lane.
+__device__ __forceinline__ void wave_add_keyed(unsigned long long *ctr, uint32_t key, uint32_t field,
+                                               unsigned long long val, bool active) {
+    for (int it = 0; it < 4; it++) {
+        const uint64_t m = __ballot(active);
+        if (m == 0) return;
+        const int leader = __ffsll((unsigned long long)m) - 1;
+        const uint32_t k0 = __shfl(key, leader);
+        const bool mine = active && key == k0;
+        const unsigned long long s = wave_sum_u64(mine ? val : 0ull);
+        if ((int)lane_id() == leader) atomicAdd(&ctr[(uint64_t)k0 * 2 + field], s);
+        active = active && !mine;
+    }
+    if (active) atomicAdd(&ctr[(uint64_t)key * 2 + field], val);
 }
 
 // Relaxation of arc e out of u^(i) (Algorithm 2, inner loop) in the round
@@ -317,6 +337,9 @@ __global__ __launch_bounds__(WAVE) void k_round(RoundArgs A) {
                 }
             }
         }
+        if (A.sc)
+            wave_add_keyed(A.sc + (uint64_t)par * A.nsearch * 2, ent.x, 0,
+                           ((unsigned long long)(re - rb) << 32) + 1ull, action == 2);
         // Entries above the threshold stay in the frontier unchanged (a
         // lowering of the vertex in this round adds a fresher entry, which
         // makes this one stale next round).
@@ -455,31 +478,29 @@ __device__ __forceinline__ void chunk_prefix(const RoundArgs &A, uint32_t q) {
 
 __global__ __launch_bounds__(WAVE) void k_seed_prefix(RoundArgs A) { chunk_prefix(A, 0); }
 
-// Per-search step control after a round (see the file comment).
-__global__ __launch_bounds__(BLOCK) void k_control(RoundArgs A) {
-    const uint32_t i = blockIdx.x * BLOCK + threadIdx.x;
-    const uint32_t r = A.round[1];
-    const uint32_t par = r & 1, np = par ^ 1;
-    if (blockIdx.x == 0 && threadIdx.x < WAVE) {
-        chunk_prefix(A, np);                      // chunk layout of the queue the next round reads
-        A.qcount[par * NSEG + threadIdx.x] = 0;   // the queue just consumed becomes the next output
-    }
-    if (i == 0) {
-        A.round[0] = r + 1;
-        *A.hcount = 0;
-    }
-    if (i >= A.nsearch) return;
+// Liveness, termination and the bound of search i after round r: the part
+// of the step control that does not depend on the step rule. Returns 0 if
+// the search had already finished, 1 if it finished now, 2 if it goes on;
+// then *mk is the smallest key of its next frontier and *nb its new bound.
+// Only the writer lane stores.
+__device__ __forceinline__ int control_search(const RoundArgs &A, uint32_t i, uint32_t par, uint32_t np, bool writer,
+                                              uint64_t *mk_out, uint64_t *nb_out) {
     const uint32_t c = A.alive[(uint64_t)np * A.nsearch + i];
     const uint64_t mk = A.minkey[(uint64_t)np * A.nsearch + i];
-    A.alive[(uint64_t)par * A.nsearch + i] = 0;
-    A.minkey[(uint64_t)par * A.nsearch + i] = INF64;
-    if (A.done[i]) return;
+    if (writer) {
+        A.alive[(uint64_t)par * A.nsearch + i] = 0;
+        A.minkey[(uint64_t)par * A.nsearch + i] = INF64;
+    }
+    if (A.done[i]) return 0;
     const SearchDesc sd = A.sd[i];
     const ulonglong2 c0 = A.ctl[i];
     // A frontier that ran dry while nothing could be pruned has covered the
     // whole component of its root (Appendix B, disconnected queries).
     uint32_t ex = A.exh[i];
-    if (c == 0 && c0.y == INF64 && !ex) { ex = 1; A.exh[i] = 1; }
+    if (c == 0 && c0.y == INF64 && !ex) {
+        ex = 1;
+        if (writer) A.exh[i] = 1;
+    }
     uint64_t mx = 0;
     bool open = false;
     for (uint32_t p = sd.pbeg; p < sd.pend; p++) {
@@ -496,19 +517,28 @@ __global__ __launch_bounds__(BLOCK) void k_control(RoundArgs A) {
     }
     const uint64_t nb = sd.noprune ? INF64 : (open ? mx : 0);
     if (c == 0 || !open) {
-        A.done[i] = 1;
-        A.ctl[i] = make_ulonglong2(c0.x, 0);
-        return;
+        if (writer) {
+            A.done[i] = 1;
+            A.ctl[i] = make_ulonglong2(c0.x, 0);
+        }
+        return 1;
     }
-    const uint64_t d = A.delta[i], th0 = c0.x;
+    *mk_out = mk;
+    *nb_out = nb;
+    return 2;
+}
+
+// The next threshold from the current one, the smallest key of the next
+// frontier and the step Delta d (key units).
+__device__ __forceinline__ uint64_t step_threshold(uint32_t mode, uint64_t th0, uint64_t mk, uint64_t d) {
     uint64_t th;
-    if (A.theta_mode == 0 || mk == INF64) {
+    if (mode == 0 || mk == INF64) {
         // Delta*-stepping: the i-th threshold is i * Delta; steps that would
         // extract nothing are skipped by raising it to the smallest key.
         th = th0 + d;
         if (th < th0) th = INF64;
         if (mk != INF64 && mk > th) th = mk;
-    } else if (A.theta_mode == 1) {
+    } else if (mode == 1) {
         // Bucketed variant: extract the Delta-wide bucket that holds the
         // smallest key; the threshold stays while that bucket refills.
         const uint64_t b = mk / d;
@@ -520,7 +550,142 @@ __global__ __launch_bounds__(BLOCK) void k_control(RoundArgs A) {
         if (th < mk) th = INF64;
         if (th < th0) th = th0;
     }
+    return th;
+}
+
+// Per-search step control after a round (see the file comment).
+__global__ __launch_bounds__(BLOCK) void k_control(RoundArgs A) {
+    const uint32_t i = blockIdx.x * BLOCK + threadIdx.x;
+    const uint32_t r = A.round[1];
+    const uint32_t par = r & 1, np = par ^ 1;
+    if (blockIdx.x == 0 && threadIdx.x < WAVE) {
+        chunk_prefix(A, np);                      // chunk layout of the queue the next round reads
+        A.qcount[par * NSEG + threadIdx.x] = 0;   // the queue just consumed becomes the next output
+    }
+    if (i == 0) {
+        A.round[0] = r + 1;
+        *A.hcount = 0;
+    }
+    if (i >= A.nsearch) return;
+    uint64_t mk = 0, nb = 0;
+    if (control_search(A, i, par, np, true, &mk, &nb) != 2) return;
+    const uint64_t th = step_threshold(A.theta_mode, A.ctl[i].x, mk, A.delta[i]);
     A.ctl[i] = make_ulonglong2(th, nb);
+}
+
+__device__ __forceinline__ float lg2p(double x) { return log2f((float)(1.0 + x)); }
+
+// Features of search i for the step after round r (all roughly in [-2, 2]):
+//   0  log2(1 + vertices extracted in the round) / 16
+//   1  log2(1 + arcs scanned in the round) / 16
+//   2  log2(1 + entries of the next frontier) / 16
+//   3  (log2(1 + next frontier) - log2(1 + the partner search's)) / 8; 0 without a partner search
+//   4  log2(1 + (bound - smallest key) / Delta) / 16; 0 while the bound is infinite
+//   5  1 while the bound is infinite, else 0
+//   6  log2(1 + (smallest key - threshold) / Delta) / 8
+//   7  log2(1 + (threshold - root key) / Delta) / 16   (progress)
+//   8  log2(1 + heuristic distance of the query / Delta) / 16; 0 without coordinates
+//   9  log2(1 + round) / 16
+//  10  (previous bin - 4) / 4
+//  11  log2(m / n) / 4
+// Delta is the search's base Delta in key units.
+__device__ __forceinline__ void ml_features(const RoundArgs &A, uint32_t i, const SearchDesc &sd, uint32_t r,
+                                            uint32_t par, unsigned long long c0, unsigned long long nxt, uint64_t th0,
+                                            uint64_t mk, uint64_t nb, uint64_t db, uint32_t bin, float *f) {
+    const double d = (double)db;
+    const double near = (double)(c0 & 0xFFFFFFFFull), arcs = (double)(c0 >> 32);
+    f[0] = lg2p(near) / 16.f;
+    f[1] = lg2p(arcs) / 16.f;
+    f[2] = lg2p((double)nxt) / 16.f;
+    uint32_t pj = INF32;
+    if (A.G == 2) {
+        pj = i ^ 1u;
+    } else if (sd.pend > sd.pbeg) {
+        const uint32_t o = A.partners[sd.pbeg].other;
+        if (!(o & TARGET_BIT)) pj = o;
+    }
+    f[3] = 0.f;
+    if (pj != INF32 && pj < A.nsearch)
+        f[3] = (lg2p((double)nxt) - lg2p((double)A.sc[((uint64_t)par * A.nsearch + pj) * 2 + 1])) / 8.f;
+    f[4] = nb == INF64 ? 0.f : lg2p((double)(nb > mk ? nb - mk : 0) / d) / 16.f;
+    f[5] = nb == INF64 ? 1.f : 0.f;
+    f[6] = mk == INF64 ? 1.f : lg2p((double)(mk > th0 ? mk - th0 : 0) / d) / 8.f;
+    const uint64_t key0 = key_of(sd.kind, 0, hterm(A, sd, sd.src));
+    f[7] = lg2p((double)(th0 > key0 ? th0 - key0 : 0) / d) / 16.f;
+    double est = 0.0;
+    if (A.xy && sd.kind != K_DIST && sd.kind != K_2DIST) {
+        const int2 p = A.xy[sd.src];
+        const bool to_s = sd.kind == K_BIDA_B;
+        const uint64_t h = heur(p.x, p.y, to_s ? sd.sx : sd.tx, to_s ? sd.sy : sd.ty, A.ws2, A.fb);
+        est = (double)h * (sd.kind == K_ASTAR ? 1.0 : 2.0);
+    }
+    f[8] = lg2p(est / d) / 16.f;
+    f[9] = lg2p((double)r) / 16.f;
+    f[10] = ((float)bin - 4.f) / 4.f;
+    f[11] = A.deg_feat;
+}
+
+// Step control of the learned or traced schedule: one wave per search (the
+// waves of the grid stride over the searches). Termination and bounds as in
+// k_control; the step Delta is the base Delta times 2^(bin - 4), the bin
+// chosen by the network (ml_mode 2) or fixed per search (ml_mode 1). With a
+// trace buffer every step decision appends its feature row.
+__global__ __launch_bounds__(WAVE) void k_control_ml(RoundArgs A) {
+    const uint32_t r = A.round[1];
+    const uint32_t par = r & 1, np = par ^ 1;
+    const uint32_t lane = lane_id();
+    const bool w = lane == 0;
+    if (blockIdx.x == 0) {
+        chunk_prefix(A, np);
+        A.qcount[par * NSEG + lane] = 0;
+        if (w) {
+            A.round[0] = r + 1;
+            *A.hcount = 0;
+        }
+    }
+    MlpLane L;
+    if (A.ml_mode == 2) mlp_load_lane(A.mlp, L);
+    for (uint32_t i = blockIdx.x; i < A.nsearch; i += gridDim.x) {
+        const unsigned long long *sc = A.sc + ((uint64_t)par * A.nsearch + i) * 2;
+        const unsigned long long c0 = sc[0], nxt = sc[1];
+        uint64_t mk = 0, nb = 0;
+        const int st = control_search(A, i, par, np, w, &mk, &nb);
+        if (w) {
+            unsigned long long *sn = A.sc + ((uint64_t)np * A.nsearch + i) * 2;   // next round's counters
+            sn[0] = 0;
+            sn[1] = 0;
+        }
+        if (st == 0) continue;
+        if (w) A.tot_arcs[i] += c0 >> 32;
+        if (st == 1) {
+            if (w) A.done_round[i] = r + 1;
+            continue;
+        }
+        const SearchDesc sd = A.sd[i];
+        const uint64_t th0 = A.ctl[i].x;
+        const uint64_t db = A.delta[i];
+        uint32_t bin = A.bin[i];
+        float f[MLP_F];
+        ml_features(A, i, sd, r, par, c0, nxt, th0, mk, nb, db, bin, f);
+        if (A.ml_mode == 2) {
+            float z1, h1, z2, h2, lg[MLP_K];
+            mlp_forward(L, f, z1, h1, z2, h2, lg);
+            bin = mlp_argmax(lg);
+        }
+        if (w) {
+            if (A.trace) {
+                const unsigned long long row = atomicAdd(A.trace_n, 1ull);
+                if (row < A.trace_cap) {
+                    for (int k = 0; k < MLP_F; k++) A.trace[row * MLP_F + k] = f[k];
+                    A.trace_s[row] = i;
+                }
+            }
+            A.bin[i] = (uint8_t)bin;
+            uint64_t d = (db << bin) >> 4;
+            if (d == 0) d = 1;
+            A.ctl[i] = make_ulonglong2(step_threshold(A.theta_mode, th0, mk, d), nb);
+        }
+    }
 }
 
 // Init() of Table 2 for every search: delta[root] = 0, root in the frontier.
@@ -691,8 +856,13 @@ hipError_t launch_heavy(const RoundArgs &A, uint32_t grid, hipStream_t st) {
 }
 
 hipError_t launch_control(const RoundArgs &A, hipStream_t st) {
-    const uint32_t nb = (A.nsearch + BLOCK - 1) / BLOCK;
-    k_control<<<nb, BLOCK, 0, st>>>(A);
+    if (A.sc) {
+        const uint32_t nb = A.nsearch < 4096 ? A.nsearch : 4096;
+        k_control_ml<<<nb ? nb : 1, WAVE, 0, st>>>(A);
+    } else {
+        const uint32_t nb = (A.nsearch + BLOCK - 1) / BLOCK;
+        k_control<<<nb, BLOCK, 0, st>>>(A);
+    }
     return hipGetLastError();
 }
 

@@ -149,6 +149,20 @@ struct RoundArgs {
     unsigned long long *stats; // [ST_ROUNDS] rounds run
     unsigned long long *wstats; // [grid][ST_N] per-workgroup counters of the round kernel
     uint32_t theta_mode;       // 0: theta += Delta; 1: end of the smallest key's Delta bucket; 2: smallest key + Delta
+    // Learned or traced step schedule (sc = null: off). Delta of search i in
+    // a round is its base Delta times 2^(bin[i] - 4).
+    unsigned long long *sc;    // [2][nsearch][2] per-search counters of a round, by round parity:
+                               //   (arcs of extracted vertices << 32) + extracted vertices; entries for the next frontier
+    uint32_t ml_mode;          // 1: bins fixed per search (tracing), 2: the network picks them
+    const uint16_t *mlp;       // network parameters in bf16 (layout in mlp_dev.h)
+    uint8_t *bin;              // [nsearch] multiplier bin of the search's next round
+    uint32_t *done_round;      // [nsearch] rounds the search ran
+    unsigned long long *tot_arcs;  // [nsearch] arcs it scanned
+    float *trace;              // [trace_cap][12] feature rows, or null
+    uint32_t *trace_s;         // [trace_cap] search of each row
+    unsigned long long *trace_n;
+    uint64_t trace_cap;
+    float deg_feat;            // log2(m / n) / 4
 };
 
 __host__ __device__ inline uint64_t state_index(uint32_t G, uint32_t n, uint32_t i, uint32_t v) {

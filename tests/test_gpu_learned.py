@@ -1,0 +1,166 @@
+"""GPU tests of the learned step schedule: inference and training kernels
+against the FP64 reference (oracle.mlp), exactness of searches under any
+network, tracing, and the fit recipe."""
+import numpy as np
+import pytest
+
+import gen
+import oracle
+from oracle import mlp
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2506_16488_amd as P
+    P.lib()
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    return P
+
+
+def _params(seed, noise=0.05):
+    p = gen.mlp_init(seed).astype(np.float64)
+    p += np.random.default_rng(seed + 1).normal(0, noise, p.shape)
+    return p.astype(np.float32)
+
+
+def test_forward_matches_fp64_reference(P):
+    for seed in (1, 2):
+        p = _params(seed)
+        X, _ = gen.mlp_rows(3000, seed + 10, learnable=False)
+        got = P.mlp_forward(p, X)
+        exp = mlp.forward(p.astype(np.float64), X)
+        assert np.max(np.abs(got - exp)) <= 1e-5 * (1 + np.max(np.abs(exp))), seed
+    assert P.mlp_forward(_params(3), np.zeros((0, 12), np.float32)).shape == (0, 8)
+
+
+@pytest.mark.parametrize("n", [1, 37, 5000])
+def test_gradient_matches_fp64_reference(P, n):
+    p = _params(4)
+    X, y = gen.mlp_rows(n, 20 + n, learnable=False)
+    L, g = P.mlp_grad(p, X, y)
+    Le, ge = mlp.grad(p.astype(np.float64), X, y)
+    assert abs(L - Le) <= 1e-5 * (1 + abs(Le))
+    scale = np.max(np.abs(ge))
+    assert np.max(np.abs(g - ge)) <= 1e-4 * scale + 1e-7, n
+
+
+def test_adam_step_matches_reference(P):
+    """One full-batch step (batch = n, one epoch: the shuffle cannot matter)."""
+    p = _params(5)
+    X, y = gen.mlp_rows(512, 30, learnable=False)
+    lr = 1e-3
+    got, l0, l1 = P.mlp_train(p, X, y, epochs=1, batch=512, lr=lr, seed=3)
+    _, g = mlp.grad(p.astype(np.float64), X, y)
+    exp, _, _ = mlp.adam_step(p.astype(np.float64), np.zeros_like(g), np.zeros_like(g), g, 1, lr)
+    # parameters whose gradient is far from zero (where fp32 and fp64 agree on its sign)
+    big = np.abs(g) > 1e-3 * np.max(np.abs(g))
+    assert big.sum() > 1000
+    assert np.max(np.abs(got[big] - exp[big])) <= 2e-6
+    assert np.max(np.abs(got - p)) <= lr * 1.0001          # a first Adam step never exceeds lr
+    assert abs(l0 - mlp.loss(p.astype(np.float64), X, y)) < 1e-5
+    assert abs(l1 - mlp.loss(got.astype(np.float64), X, y)) < 1e-5
+
+
+def test_training_learns_a_rule(P):
+    X, y = gen.mlp_rows(20000, 40, learnable=True)
+    p, l0, l1 = P.mlp_train(gen.mlp_init(41), X, y, epochs=15, batch=256, lr=3e-3, seed=42)
+    assert l1 < 0.5 * l0, (l0, l1)
+    acc = np.mean(np.argmax(P.mlp_forward(p, X), axis=1) == y)
+    assert acc > 0.85, acc
+    Xt, yt = gen.mlp_rows(4000, 43, learnable=True)
+    assert np.mean(np.argmax(mlp.forward(p.astype(np.float64), Xt), axis=1) == yt) > 0.8
+    # same seed, same result
+    p2, _, _ = P.mlp_train(gen.mlp_init(41), X, y, epochs=15, batch=256, lr=3e-3, seed=42)
+    assert np.array_equal(p, p2)
+
+
+def _bias_only(b):
+    """A network that always picks bin b."""
+    p = np.zeros(P_PARAMS, np.float32)
+    p[-8:] = -5.0
+    p[-8 + b] = 5.0
+    return p
+
+
+P_PARAMS = 5512
+
+
+def test_learned_schedule_is_exact(P):
+    g = gen.lattice(96, 0.1, seed=50)
+    pairs = np.concatenate([gen.pairs_uniform(g.n, 60, seed=51), np.array([[5, 5], [7, 9000]], np.uint32)])
+    exp = oracle.pp_batch(g.n, g.row_ptr, g.col, g.w, pairs)
+    G = P.Graph.from_host(g)
+    with pytest.raises(P.PPSPError) as e:
+        G.batch_query(pairs, algo="bids", sched="learned")      # no network loaded
+    assert e.value.code == P.E_INVALID
+    for params in [_params(60), _params(61, noise=0.5), _bias_only(0), _bias_only(7)]:
+        G.mlp_load(params)
+        for algo in ["sssp", "et", "astar", "bids", "bidastar"]:
+            for batch in ["plainstar", "plain"]:
+                got = G.batch_query(pairs, algo=algo, batch=batch, sched="learned")
+                assert np.array_equal(got, exp), (algo, batch)
+        assert np.array_equal(G.batch_query(pairs, algo="bids", batch="multi", sched="learned"), exp)
+        d, (off, vtx) = G.batch_query(pairs[:10], algo="bidastar", sched="learned", want_path=True)
+        for q in range(10):
+            s, t = int(pairs[q, 0]), int(pairs[q, 1])
+            assert oracle.check_path(g.n, g.row_ptr, g.col, g.w, vtx[off[q]:off[q + 1]], s, t, int(d[q])) == (0, 0)
+    bad = _params(62)
+    bad[100] = np.nan
+    with pytest.raises(P.PPSPError):
+        G.mlp_load(bad)
+    G.close()
+
+
+def test_learned_schedule_unreachable_and_hubs(P):
+    g = gen.rmat(12, 16, seed=52)
+    pairs = gen.pairs_uniform(g.n, 80, seed=53)
+    exp = oracle.pp_batch(g.n, g.row_ptr, g.col, g.w, pairs)
+    assert np.any(exp == oracle.INF)
+    G = P.Graph.from_host(g)
+    G.mlp_load(_params(63, noise=0.3))
+    for algo in ["bids", "et"]:
+        assert np.array_equal(G.batch_query(pairs, algo=algo, sched="learned"), exp), algo
+    G.close()
+
+
+def test_trace_rows_and_costs(P):
+    g = gen.lattice(128, 0.05, seed=70)
+    pairs = gen.pairs_uniform(g.n, 40, seed=71)
+    G = P.Graph.from_host(g)
+    tot = {}
+    for b in (0, 4, 7):
+        feat, rowp, nrows, pr, pa = G.sched_trace(pairs, algo="bidastar", bins=b, cap=200000)
+        assert nrows == feat.shape[0] > 0
+        assert np.all(np.isfinite(feat)) and np.max(np.abs(feat)) < 4
+        assert np.all(rowp < pairs.shape[0])
+        assert np.all(pr > 0) and np.all(pa > 0)
+        # each pair's rows: about one per search and round
+        cnt = np.bincount(rowp, minlength=pairs.shape[0])
+        assert np.all(cnt <= 2 * pr)
+        tot[b] = (int(pr.sum()), int(pa.sum()))
+    # A larger step needs no more rounds (one hop per round bounds them from
+    # below, so they stop falling once Delta covers a hop) and scans more arcs.
+    assert tot[0][0] > tot[4][0] >= tot[7][0], tot
+    assert tot[0][1] < tot[4][1] < tot[7][1], tot
+    # the fixed-bin run computes the same distances
+    exp = oracle.pp_batch(g.n, g.row_ptr, g.col, g.w, pairs)
+    assert np.array_equal(G.batch_query(pairs, algo="bidastar"), exp)
+    G.close()
+
+
+def test_fit_recipe(P):
+    g = gen.lattice(128, 0.05, seed=80)
+    train = gen.pairs_uniform(g.n, 24, seed=81)
+    G = P.Graph.from_host(g)
+    params, rep = G.mlp_fit(train, gen.mlp_init(82), algo="bidastar", epochs=5, seed=83)
+    assert sum(rep["label_hist"]) == 24
+    assert rep["rows"] > 0 and rep["loss_last"] <= rep["loss_first"]
+    assert 0.0 <= rep["train_acc"] <= 1.0
+    test = gen.pairs_uniform(g.n, 50, seed=84)
+    exp = oracle.pp_batch(g.n, g.row_ptr, g.col, g.w, test)
+    assert np.array_equal(G.batch_query(test, algo="bidastar", sched="learned"), exp)
+    assert np.array_equal(G.batch_query(test, algo="bids", sched="learned"), exp)
+    G.close()
