@@ -331,6 +331,8 @@ int ppsp_last_stats(ppsp_graph g, ppsp_stats *stats);
  *   "queue_cap"       frontier queue capacity in entries (grows x4, with a rerun of
  *                     the wave, whenever a round overflows it)
  *   "heavy_cap"       heavy-list capacity in arc chunks (grows the same way)
+ *   "ml_every"        rounds between evaluations of the learned schedule's network (default 4;
+ *                     a search keeps its multiplier in between)
  * Returns PPSP_E_INVALID for an unknown name.
  */
 int ppsp_set_option(ppsp_graph g, const char *name, int64_t value);

@@ -153,7 +153,8 @@ struct ppsp_graph_s {
     int cu = 256;
     // options
     int64_t opt_profile = 0, opt_rounds_per_sync = 16, opt_grid_blocks = 0, opt_mem_budget_mb = 0,
-            opt_default_delta = 0, opt_use_graph = 0, opt_timeout_ms = 600000, opt_theta_mode = 2, opt_queue_cap = 0;
+            opt_default_delta = 0, opt_use_graph = 0, opt_timeout_ms = 600000, opt_theta_mode = 2, opt_queue_cap = 0,
+            opt_ml_every = 4;
     uint64_t wmean = 1;             // mean arc weight (rounded up)
     uint64_t fingerprint = 0;       // hash of the CSR, keys the tuning cache
     struct Tuned {
@@ -254,7 +255,9 @@ void set_args(ppsp_graph g, RoundArgs &A, uint32_t nsearch, uint32_t npair, uint
         }
         A.trace_n = g->trace_n.as<unsigned long long>();
         A.deg_feat = g->n ? (float)(std::log2(std::max(1.0, (double)g->m / g->n)) / 4.0) : 0.f;
+        A.ml_every = (uint32_t)std::max<int64_t>(1, g->opt_ml_every);
     }
+    A.grid = g->opt_grid_blocks > 0 ? (uint32_t)g->opt_grid_blocks : (uint32_t)(24 * g->cu);
 }
 
 int ensure_events(ppsp_graph g, size_t k) {
@@ -1588,6 +1591,7 @@ int ppsp_set_option(ppsp_graph g, const char *name, int64_t v) {
     else if (k == "theta_mode") { if (v < 0 || v > 2) return PPSP_E_INVALID; g->opt_theta_mode = v; }
     else if (k == "queue_cap") { if (v < (int64_t)NSEG || v > (1ll << 31)) return PPSP_E_INVALID; g->qcap = (uint64_t)v; g->opt_queue_cap = v; }
     else if (k == "heavy_cap") { if (v < 1 || v > (1ll << 28)) return PPSP_E_INVALID; g->hcap = (uint32_t)v; }
+    else if (k == "ml_every") { if (v < 1 || v > 1024) return PPSP_E_INVALID; g->opt_ml_every = v; }
 
     else return PPSP_E_INVALID;
     return PPSP_OK;
@@ -1606,6 +1610,7 @@ int ppsp_get_option(ppsp_graph g, const char *name, int64_t *v) {
     else if (k == "theta_mode") *v = g->opt_theta_mode;
     else if (k == "queue_cap") *v = (int64_t)g->qcap;
     else if (k == "heavy_cap") *v = g->hcap;
+    else if (k == "ml_every") *v = g->opt_ml_every;
 
     else return PPSP_E_INVALID;
     return PPSP_OK;

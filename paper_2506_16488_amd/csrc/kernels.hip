@@ -124,7 +124,7 @@ __device__ __forceinline__ void meet_list(const RoundArgs &A, const SearchDesc &
 // when a plain read shows it would lower the value). The lanes of a wave
 // usually share one search, so the reduction is per wave.
 __device__ __forceinline__ void search_stats(const RoundArgs &A, uint32_t np, uint32_t i, uint32_t cnt,
-                                             uint64_t mink) {
+                                             uint64_t mink, bool count) {
     const bool has = cnt > 0 || mink != INF64;
     const uint64_t mask = __ballot(has);
     if (mask == 0) return;
@@ -138,14 +138,14 @@ __device__ __forceinline__ void search_stats(const RoundArgs &A, uint32_t np, ui
             if (tot && *al == 0) *al = 1;
             unsigned long long *mp = (unsigned long long *)&A.minkey[(uint64_t)np * A.nsearch + i0];
             if (mn < *mp) atomicMin(mp, mn);
-            if (A.sc && tot) atomicAdd(&A.sc[((uint64_t)(np ^ 1) * A.nsearch + i0) * 2 + 1], (unsigned long long)tot);
+            if (count && tot) atomicAdd(&A.sc[((uint64_t)(np ^ 1) * A.nsearch + i0) * 2 + 1], (unsigned long long)tot);
         }
     } else if (has) {
         uint32_t *al = &A.alive[(uint64_t)np * A.nsearch + i];
         if (cnt && *al == 0) *al = 1;
         unsigned long long *mp = (unsigned long long *)&A.minkey[(uint64_t)np * A.nsearch + i];
         if (mink < *mp) atomicMin(mp, mink);
-        if (A.sc && cnt) atomicAdd(&A.sc[((uint64_t)(np ^ 1) * A.nsearch + i) * 2 + 1], (unsigned long long)cnt);
+        if (count && cnt) atomicAdd(&A.sc[((uint64_t)(np ^ 1) * A.nsearch + i) * 2 + 1], (unsigned long long)cnt);
     }
 }
 
@@ -279,6 +279,7 @@ __global__ __launch_bounds__(WAVE) void k_round(RoundArgs A) {
         if (nchunks) atomicAdd(&A.stats[ST_ROUNDS], 1ull);
     }
     unsigned long long c_ent = 0, c_sv = 0, c_se = 0, c_succ = 0, c_keep = 0;
+    const bool count = A.sc && blockIdx.x < ML_SAMPLE;
 
     for (uint32_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
         uint32_t lo = 0, hi = NSEG;                        // cpre[lo] <= ch < cpre[hi]
@@ -337,7 +338,7 @@ __global__ __launch_bounds__(WAVE) void k_round(RoundArgs A) {
                 }
             }
         }
-        if (A.sc)
+        if (count)
             wave_add_keyed(A.sc + (uint64_t)par * A.nsearch * 2, ent.x, 0,
                            ((unsigned long long)(re - rb) << 32) + 1ull, action == 2);
         // Entries above the threshold stay in the frontier unchanged (a
@@ -346,7 +347,7 @@ __global__ __launch_bounds__(WAVE) void k_round(RoundArgs A) {
         const bool keep = action == 1;
         c_keep += keep;
         wstage_push(st, scnt, keep, ent, qout, qcout, A.qseg, A.err);
-        search_stats(A, np, ent.x, keep ? 1u : 0u, keep ? key : INF64);
+        search_stats(A, np, ent.x, keep ? 1u : 0u, keep ? key : INF64, count);
 
         // High-degree vertices go to the heavy list as chunks of at most
         // HEAVY_CHUNK arcs, which all waves of k_heavy share; one atomic per
@@ -405,7 +406,7 @@ __global__ __launch_bounds__(WAVE) void k_round(RoundArgs A) {
                                 &ne, &lmin, &c_succ);
             }
             wstage_push(st, scnt, app, ne, qout, qcout, A.qseg, A.err);
-            search_stats(A, np, ai, app ? 1u : 0u, lmin);
+            search_stats(A, np, ai, app ? 1u : 0u, lmin, count);
         }
         __syncthreads();                          // adv is rewritten by the next chunk
     }
@@ -436,6 +437,7 @@ __global__ __launch_bounds__(WAVE) void k_heavy(RoundArgs A) {
     const uint32_t np = (r & 1) ^ 1, stamp = r + 1;
     const uint64_t nh = min((uint64_t)*A.hcount, (uint64_t)A.hcap);
     if (nh == 0) return;
+    const bool count = A.sc && blockIdx.x < ML_SAMPLE;   // scaled like the round kernel's counts
     const uint32_t sego = blockIdx.x % NSEG;
     uint4 *qout = ((r & 1) ? A.q0 : A.q1) + (uint64_t)sego * A.qseg;
     uint32_t *qcout = &A.qcount[np * NSEG + sego];
@@ -453,7 +455,7 @@ __global__ __launch_bounds__(WAVE) void k_heavy(RoundArgs A) {
             uint64_t lmin = INF64;
             if (e < ee) app = relax_arc(A, sd, ai, h1.y, h1.z, bnd, e, stamp, &ne, &lmin, &c_succ);
             wstage_push(st, scnt, app, ne, qout, qcout, A.qseg, A.err);
-            search_stats(A, np, ai, app ? 1u : 0u, lmin);
+            search_stats(A, np, ai, app ? 1u : 0u, lmin, count);
         }
     }
     wstage_flush(st, scnt, qout, qcout, A.qseg, A.err);
@@ -590,13 +592,14 @@ __device__ __forceinline__ float lg2p(double x) { return log2f((float)(1.0 + x))
 //  11  log2(m / n) / 4
 // Delta is the search's base Delta in key units.
 __device__ __forceinline__ void ml_features(const RoundArgs &A, uint32_t i, const SearchDesc &sd, uint32_t r,
-                                            uint32_t par, unsigned long long c0, unsigned long long nxt, uint64_t th0,
-                                            uint64_t mk, uint64_t nb, uint64_t db, uint32_t bin, float *f) {
+                                            uint32_t par, unsigned long long c0, unsigned long long nxt, double scale,
+                                            uint64_t th0, uint64_t mk, uint64_t nb, uint64_t db, uint32_t bin,
+                                            float *f) {
     const double d = (double)db;
-    const double near = (double)(c0 & 0xFFFFFFFFull), arcs = (double)(c0 >> 32);
+    const double near = scale * (double)(c0 & 0xFFFFFFFFull), arcs = scale * (double)(c0 >> 32);
     f[0] = lg2p(near) / 16.f;
     f[1] = lg2p(arcs) / 16.f;
-    f[2] = lg2p((double)nxt) / 16.f;
+    f[2] = lg2p(scale * (double)nxt) / 16.f;
     uint32_t pj = INF32;
     if (A.G == 2) {
         pj = i ^ 1u;
@@ -606,7 +609,7 @@ __device__ __forceinline__ void ml_features(const RoundArgs &A, uint32_t i, cons
     }
     f[3] = 0.f;
     if (pj != INF32 && pj < A.nsearch)
-        f[3] = (lg2p((double)nxt) - lg2p((double)A.sc[((uint64_t)par * A.nsearch + pj) * 2 + 1])) / 8.f;
+        f[3] = (lg2p(scale * (double)nxt) - lg2p(scale * (double)A.sc[((uint64_t)par * A.nsearch + pj) * 2 + 1])) / 8.f;
     f[4] = nb == INF64 ? 0.f : lg2p((double)(nb > mk ? nb - mk : 0) / d) / 16.f;
     f[5] = nb == INF64 ? 1.f : 0.f;
     f[6] = mk == INF64 ? 1.f : lg2p((double)(mk > th0 ? mk - th0 : 0) / d) / 8.f;
@@ -643,8 +646,14 @@ __global__ __launch_bounds__(WAVE) void k_control_ml(RoundArgs A) {
             *A.hcount = 0;
         }
     }
+    // share of this round's chunks that the counting workgroups processed
+    const uint32_t nch = A.cpre[par * (NSEG + 1) + NSEG];
+    const uint32_t q = nch / A.grid, rem = nch % A.grid;
+    const uint32_t sampled = A.grid <= ML_SAMPLE ? nch : q * ML_SAMPLE + min(rem, ML_SAMPLE);
+    const double scale = sampled ? (double)nch / sampled : 1.0;
+    const bool net = A.ml_mode == 2 && r % A.ml_every == 0;
     MlpLane L;
-    if (A.ml_mode == 2) mlp_load_lane(A.mlp, L);
+    if (net) mlp_load_lane(A.mlp, L);
     for (uint32_t i = blockIdx.x; i < A.nsearch; i += gridDim.x) {
         const unsigned long long *sc = A.sc + ((uint64_t)par * A.nsearch + i) * 2;
         const unsigned long long c0 = sc[0], nxt = sc[1];
@@ -656,18 +665,20 @@ __global__ __launch_bounds__(WAVE) void k_control_ml(RoundArgs A) {
             sn[1] = 0;
         }
         if (st == 0) continue;
-        if (w) A.tot_arcs[i] += c0 >> 32;
+        if (w) A.tot_arcs[i] += (unsigned long long)(scale * (double)(c0 >> 32) + 0.5);
         if (st == 1) {
             if (w) A.done_round[i] = r + 1;
             continue;
         }
-        const SearchDesc sd = A.sd[i];
         const uint64_t th0 = A.ctl[i].x;
         const uint64_t db = A.delta[i];
         uint32_t bin = A.bin[i];
         float f[MLP_F];
-        ml_features(A, i, sd, r, par, c0, nxt, th0, mk, nb, db, bin, f);
-        if (A.ml_mode == 2) {
+        if (net || A.trace) {
+            const SearchDesc sd = A.sd[i];
+            ml_features(A, i, sd, r, par, c0, nxt, scale, th0, mk, nb, db, bin, f);
+        }
+        if (net) {
             float z1, h1, z2, h2, lg[MLP_K];
             mlp_forward(L, f, z1, h1, z2, h2, lg);
             bin = mlp_argmax(lg);

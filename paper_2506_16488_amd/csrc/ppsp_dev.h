@@ -163,7 +163,15 @@ struct RoundArgs {
     unsigned long long *trace_n;
     uint64_t trace_cap;
     float deg_feat;            // log2(m / n) / 4
+    uint32_t grid;             // workgroups of the round kernel
+    uint32_t ml_every;         // the network runs every ml_every rounds (bins are kept in between)
 };
+
+// Only the first ML_SAMPLE workgroups of the round kernels update the
+// per-search counters; the control kernel scales their counts by the share
+// of chunks those workgroups processed (all of them when a round has at most
+// ML_SAMPLE chunks). Counter atomics on one search's address stay few.
+constexpr uint32_t ML_SAMPLE = 64;
 
 __host__ __device__ inline uint64_t state_index(uint32_t G, uint32_t n, uint32_t i, uint32_t v) {
     return G == 2 ? ((((uint64_t)(i >> 1) * n) + v) << 1) | (i & 1u) : (uint64_t)i * n + v;
