@@ -76,14 +76,19 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=64)
     ap.add_argument("--latency-sample", type=int, default=40)
     ap.add_argument("--copy-kernel", action="store_true", help="run the 1 GiB copy used to calibrate counters")
+    ap.add_argument("--workload", default="lattice2048", choices=["lattice2048", "lattice4096hub", "rmat24", "serve"],
+                    help="lattice2048: the headline line; the others are the further measured workloads")
     args = ap.parse_args()
     if args.copy_kernel:
         copy_kernel()
         return
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU only (queries shard across GPUs with no exchange; "
-              "see DESIGN.md); run with --gpus 1", file=sys.stderr)
+        print("bench.py: one GPU only (queries shard across GPUs with no exchange, so a multi-GPU run "
+              "is N independent copies of this one); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.workload != "lattice2048":
+        OTHER_WORKLOADS[args.workload](args)
+        return
 
     import numpy as np
     import torch
@@ -198,6 +203,215 @@ def main():
         }
     G.close()
     print(json.dumps(out), flush=True)
+
+
+# ---- further workloads (one JSON line each; not the headline) -----------------
+
+def _timed(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - a) / steps
+
+
+def _cpu_baseline(g, sample, label):
+    import oracle
+    threads = min(16, os.cpu_count() or 1)
+    a = time.perf_counter()
+    exp = oracle.pp_batch(g.n, g.row_ptr, g.col, g.w, sample, nthreads=threads)
+    cpu_s = time.perf_counter() - a
+    return exp, {"value": round(sample.shape[0] / cpu_s, 3), "unit": "queries/s", "cores": threads, "kind": "oracle",
+                 "sample": "%d pairs of %s, one binary-heap Dijkstra per pair (stops at t), %d host threads, %.1f s"
+                           % (sample.shape[0], label, threads, cpu_s)}
+
+
+def _line(args, workload, value, ms, dtype="u32", **extra):
+    out = {"metric": "exact s-t queries/sec", "value": round(value, 2), "unit": "queries/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": dtype, "data": "synthetic",
+           "config": {"workload": workload}}
+    out.update(extra)
+    print(json.dumps(out), flush=True)
+
+
+def workload_lattice4096hub(args):
+    """4096 x 4096 jittered lattice; batches of 1,024 pairs, half from 32
+    hubs (Multi-BiDS shares one search per hub), half uniform."""
+    import numpy as np
+    import torch
+    import gen
+    import paper_2506_16488_amd as P
+    torch.cuda.set_device(0)
+    g = gen.config_graph(3)
+    G = P.Graph.from_host(g, device=0)
+    G.set_option("timeout_ms", 600000)
+    batches = [gen.config_pairs(3, g, batch=b) for b in range(args.steps + args.warmup)]
+    it = iter(batches)
+    res = {}
+    dist = None
+    for algo, batch in [("bids", "multi"), ("bidastar", "plainstar"), ("bids", "plainstar")]:
+        n = args.steps if (algo, batch) == ("bids", "multi") else 1
+        bb = batches[args.warmup:args.warmup + n]
+        G.batch_query(batches[0], algo=algo, batch=batch)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        for p in bb:
+            d = G.batch_query(p, algo=algo, batch=batch)
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - a) / n
+        st = G.stats()
+        res["%s_%s" % (algo, batch)] = {"queries_per_s": round(1024 / t, 2), "ms_per_batch": round(1000 * t, 1),
+                                        "searches": st["searches"], "waves": st["waves"], "rounds": st["rounds"]}
+        if dist is None:
+            dist = (bb[-1], d)
+        else:
+            assert np.array_equal(G.batch_query(dist[0], algo=algo, batch=batch), dist[1])
+        print("# %s %s: %.1f q/s" % (algo, batch, 1024 / t), file=sys.stderr, flush=True)
+    main_ = res["bids_multi"]
+    extra = {"strategies": res}
+    if not args.no_cpu:
+        exp, cb = _cpu_baseline(g, dist[0][:8], "the last timed batch")
+        assert np.array_equal(exp, dist[1][:8])
+        extra["cpu_baseline"] = cb
+    G.close()
+    _line(args, "jittered lattice 4096x4096 (16,777,216 vertices, %d arcs), batches of 1,024 pairs "
+                "(512 from 32 hubs, 512 uniform), Multi-BiDS; Plain* BiD-A* and Plain* BiDS beside it" % g.m,
+          main_["queries_per_s"], main_["ms_per_batch"], **extra)
+
+
+def workload_rmat24(args):
+    """R-MAT scale 24, edge factor 16, weights U[1, 65535]: 256 pairs from the
+    largest component, BiDS Plain*, with the graph's default Delta, the
+    autotuned setting and the learned schedule."""
+    import numpy as np
+    import torch
+    import gen
+    import paper_2506_16488_amd as P
+    torch.cuda.set_device(0)
+    g = gen.config_graph(4)
+    lcc = gen.lcc(g)
+    pairs = gen.config_pairs(4, g, cand=lcc)
+    G = P.Graph.from_host(g, device=0)
+    G.set_option("timeout_ms", 900000)
+    res = {}
+    t = _timed(lambda: G.batch_query(pairs, algo="bids"), 1, 0)
+    res["fixed_default_delta"] = {"queries_per_s": round(len(pairs) / t, 2), "delta": G.get_option("default_delta"),
+                                  "scanned_arcs_per_query": int(G.stats()["scanned_arcs"] / len(pairs))}
+    print("# fixed: %.2f q/s" % (len(pairs) / t), file=sys.stderr, flush=True)
+    tr = G.tune(pairs[:32], algo="bids", batch="plainstar")
+    t = _timed(lambda: G.batch_query(pairs, algo="bids", sched="autotuned"), max(1, args.steps), 0)
+    res["autotuned"] = {"queries_per_s": round(len(pairs) / t, 2), "tune": {k: (round(v, 3) if isinstance(v, float) else v)
+                                                                              for k, v in tr.items()},
+                        "scanned_arcs_per_query": int(G.stats()["scanned_arcs"] / len(pairs))}
+    d_auto = G.batch_query(pairs, algo="bids", sched="autotuned")
+    print("# autotuned: %.2f q/s" % (len(pairs) / t), file=sys.stderr, flush=True)
+    train = gen.pairs_uniform(lcc, 16, seed=1104)
+    params, rep = G.mlp_fit(train, gen.mlp_init(4), algo="bids", epochs=20, seed=4, delta=int(tr["delta"]))
+    t = _timed(lambda: G.batch_query(pairs, algo="bids", sched="learned", delta=int(tr["delta"])), 1, 0)
+    assert np.array_equal(G.batch_query(pairs[:32], algo="bids", sched="learned", delta=int(tr["delta"])), d_auto[:32])
+    res["learned"] = {"queries_per_s": round(len(pairs) / t, 2), "fit": {k: (round(v, 3) if isinstance(v, float) else v)
+                                                                          for k, v in rep.items()}}
+    print("# learned: %.2f q/s" % (len(pairs) / t), file=sys.stderr, flush=True)
+    extra = {"schedules": res}
+    if not args.no_cpu:
+        exp, cb = _cpu_baseline(g, pairs[:8], "the 256")
+        assert np.array_equal(exp, d_auto[:8])
+        extra["cpu_baseline"] = cb
+    G.close()
+    best = max(v["queries_per_s"] for v in res.values())
+    _line(args, "R-MAT scale 24 (16,777,216 vertices, %d arcs, weights U[1,65535]), 256 pairs from the largest "
+                "component, BiDS Plain*; value = best of default-Delta, autotuned and learned schedules" % g.m,
+          best, 1000.0 * len(pairs) / best, **extra)
+
+
+def workload_serve(args):
+    """Serving: the 4096^2 lattice (BiD-A*) and R-MAT 24 (BiDS) resident in one
+    server; requests of log-uniform size in [1, 64] pairs on either graph
+    (50/50), Poisson arrivals at 50% and 80% of the measured saturation rate."""
+    import numpy as np
+    import torch
+    import gen
+    import paper_2506_16488_amd as P
+    torch.cuda.set_device(0)
+    hosts = [gen.config_graph(3), gen.config_graph(4)]
+    lcc = gen.lcc(hosts[1])
+    Gs = [P.Graph.from_host(h, device=0) for h in hosts]
+    # the R-MAT graph runs with its autotuned Delta
+    tr = Gs[1].tune(gen.config_pairs(4, hosts[1], cand=lcc)[:16], algo="bids", batch="plainstar")
+    rng = np.random.default_rng(105)
+
+    def make_requests(k, seed):
+        r = np.random.default_rng(seed)
+        out = []
+        for j in range(k):
+            gi = int(r.integers(0, 2))
+            size = int(np.floor(np.exp(r.uniform(0, np.log(65)))))
+            size = max(1, min(64, size))
+            cand = None if gi == 0 else lcc
+            p = gen.pairs_uniform(hosts[gi].n if cand is None else cand, size, seed=seed * 1000 + j)
+            out.append((gi, p))
+        return out
+
+    S = P.Server(Gs, algo=["bidastar", "bids"], delta=[0, int(tr["delta"])], state_budget_bytes=48 << 30)
+    # saturation: everything submitted at once
+    reqs = make_requests(60, 1)
+    a = time.perf_counter()
+    ids = [S.submit(gi, p) for gi, p in reqs]
+    for r in ids:
+        S.wait(r, timeout_ms=600000)
+    sat_s = time.perf_counter() - a
+    nq = sum(p.shape[0] for _, p in reqs)
+    sat_rps = len(reqs) / sat_s
+    print("# saturation: %.1f requests/s, %.1f queries/s" % (sat_rps, nq / sat_s), file=sys.stderr, flush=True)
+    out = {"saturation_requests_per_s": round(sat_rps, 2), "saturation_queries_per_s": round(nq / sat_s, 2),
+           "slots": S.stats()["slots"]}
+    check = None
+    for frac in (0.5, 0.8):
+        lam = frac * sat_rps
+        reqs = make_requests(120, 2 if frac == 0.5 else 3)
+        gaps = rng.exponential(1.0 / lam, len(reqs))
+        a = time.perf_counter()
+        t_next = a
+        ids = []
+        for (gi, p), gap in zip(reqs, gaps):
+            t_next += gap
+            while time.perf_counter() < t_next:
+                time.sleep(0.0005)
+            ids.append(S.submit(gi, p))
+        lats = []
+        res = []
+        for r in ids:
+            d, lat = S.wait(r, timeout_ms=600000)
+            lats.append(lat)
+            res.append(d)
+        wall = time.perf_counter() - a
+        lats = np.array(lats)
+        q = sum(p.shape[0] for _, p in reqs)
+        out["load_%d" % int(frac * 100)] = {"offered_requests_per_s": round(lam, 2), "queries_per_s": round(q / wall, 2),
+                                             "p50_ms": round(float(np.percentile(lats, 50)), 2),
+                                             "p99_ms": round(float(np.percentile(lats, 99)), 2), "requests": len(reqs)}
+        print("# load %.0f%%: p50 %.1f ms p99 %.1f ms" % (100 * frac, np.percentile(lats, 50), np.percentile(lats, 99)),
+              file=sys.stderr, flush=True)
+        check = (reqs, res)
+    S.close()
+    # results in the mix equal each request run alone
+    for (gi, p), d in list(zip(*check))[:10]:
+        alone = Gs[gi].batch_query(p, algo="bidastar" if gi == 0 else "bids",
+                                   delta=0 if gi == 0 else int(tr["delta"]))
+        assert np.array_equal(alone, d)
+    for G in Gs:
+        G.close()
+    _line(args, "serving: lattice 4096x4096 (BiD-A*) + R-MAT 24 (BiDS, autotuned Delta) resident together, requests "
+                "of log-uniform 1..64 pairs on either graph, Poisson arrivals at 50%% and 80%% of saturation",
+          out["load_80"]["queries_per_s"], out["load_80"]["p50_ms"], serving=out)
+
+
+OTHER_WORKLOADS = {"lattice4096hub": workload_lattice4096hub, "rmat24": workload_rmat24, "serve": workload_serve}
 
 
 if __name__ == "__main__":

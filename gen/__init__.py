@@ -266,3 +266,49 @@ def mlp_rows(n: int, seed: int, learnable: bool = True):
     else:
         y = rng.integers(0, 8, n).astype(np.uint32)
     return X, y
+
+
+# ---- batch patterns (query graphs of Section 4.1 and the batch experiments) ----
+
+PATTERNS = ["star", "fork", "chain", "cycle", "bipartite", "clique", "separate", "random"]
+
+
+def pattern_edges(kind: str, m: int = 6, k: int = 0, seed: int = 0):
+    """Query-graph edges over vertices 0..m-1: star (one hub), fork (two hubs
+    joined, each with leaves), chain (multi-stop), cycle, bipartite (halves,
+    pairwise), clique (subset APSP), separate (disjoint pairs), random (k
+    distinct pairs, k = 8 by default)."""
+    if kind == "star":
+        return [(0, j) for j in range(1, m)]
+    if kind == "fork":
+        h = m // 2
+        return [(0, 1)] + [(0, j) for j in range(2, h + 1)] + [(1, j) for j in range(h + 1, m)]
+    if kind == "chain":
+        return [(j, j + 1) for j in range(m - 1)]
+    if kind == "cycle":
+        return [(j, (j + 1) % m) for j in range(m)]
+    if kind == "bipartite":
+        h = m // 2
+        return [(a, b) for a in range(h) for b in range(h, m)]
+    if kind == "clique":
+        return [(a, b) for a in range(m) for b in range(a + 1, m)]
+    if kind == "separate":
+        return [(2 * j, 2 * j + 1) for j in range(m // 2)]
+    if kind == "random":
+        rng = np.random.default_rng(seed)
+        allp = [(a, b) for a in range(m) for b in range(a + 1, m)]
+        k = k or min(8, len(allp))
+        return [allp[i] for i in sorted(rng.choice(len(allp), min(k, len(allp)), replace=False))]
+    raise ValueError(kind)
+
+
+def batch_pattern(kind: str, n_or_cand, seed: int, m: int = 6, k: int = 0) -> np.ndarray:
+    """s-t pairs whose query graph is the pattern `kind` on m distinct
+    vertices drawn uniformly (from range(n) or from the candidate array)."""
+    rng = np.random.default_rng(seed)
+    if isinstance(n_or_cand, (int, np.integer)):
+        verts = rng.choice(int(n_or_cand), m, replace=False)
+    else:
+        verts = np.asarray(n_or_cand)[rng.choice(len(n_or_cand), m, replace=False)]
+    e = pattern_edges(kind, m, k, seed + 1)
+    return np.array([[verts[a], verts[b]] for a, b in e], np.uint32).reshape(-1, 2)

@@ -72,7 +72,10 @@ enum ppsp_algo {
 enum ppsp_batch {
     PPSP_BATCH_PLAIN = 0,      /* one query after another */
     PPSP_BATCH_PLAINSTAR = 1,  /* all queries at once, each with its own searches */
-    PPSP_BATCH_MULTI = 2       /* one search per query-graph vertex, shared (Multi-BiDS) */
+    PPSP_BATCH_MULTI = 2,      /* one search per query-graph vertex, shared (Multi-BiDS) */
+    PPSP_BATCH_SSSP = 3,       /* Plain-SSSP: one full SSSP per distinct source */
+    PPSP_BATCH_VC = 4,         /* VC-SSSP: one full SSSP per vertex of a vertex cover of the query graph */
+    PPSP_BATCH_AUTO = 5        /* VC-SSSP when a cover is small against the query graph, else Multi-BiDS */
 };
 
 /* Threshold schedule. */
@@ -168,6 +171,16 @@ int ppsp_query(ppsp_graph g, uint32_t s, uint32_t t, const ppsp_opts *opts, void
  *   path_vtx  host buffer of path_cap vertex ids, or NULL
  * opts->batch selects Plain, Plain* or Multi-BiDS; Multi-BiDS requires
  * algo = PPSP_BIDS (the paper defines no batched heuristic search).
+ * The SSSP-based strategies of Section 4.2 run one search without pruning per
+ * root and read every query's distance off its root's search: Plain-SSSP
+ * (PPSP_BATCH_SSSP) roots one search at every distinct source; VC-SSSP
+ * (PPSP_BATCH_VC, symmetric graphs) at the vertices of a vertex cover of the
+ * query graph (exact minimum per component of at most 16 query-graph
+ * vertices, greedy by uncovered degree above that), each query answered by a
+ * cover endpoint. Both take algo = PPSP_SSSP. PPSP_BATCH_AUTO (algo =
+ * PPSP_BIDS) runs VC-SSSP when the cover has at most a quarter of the
+ * query-graph vertices (star- and fork-like batches, where one search
+ * answers many queries), else Multi-BiDS.
  * Batches whose search state exceeds the memory budget are split into waves
  * of whole query-graph components.
  * Errors: as ppsp_query; PPSP_E_INVALID for Multi with another algorithm.
@@ -241,7 +254,8 @@ int ppsp_tune(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp_opts *
  *                   the labelled and the default trajectories, training from
  *                   `init` (caller-drawn), then ppsp_mlp_load.
  * Errors: PPSP_E_INVALID (null pointers, label >= 8, a non-finite
- * parameter, Multi-BiDS for tracing), the errors of ppsp_batch_query.
+ * parameter, a strategy other than Plain / Plain* for tracing or fitting),
+ * the errors of ppsp_batch_query.
  */
 #define PPSP_MLP_FEATURES 12
 #define PPSP_MLP_BINS 8
@@ -280,8 +294,9 @@ int ppsp_mlp_fit(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp_opt
  * distances ppsp_batch_query returns. A graph attached to a server is
  * reserved: ppsp_query / ppsp_batch_query on it return PPSP_E_BUSY until
  * ppsp_server_destroy.
- *   opts->algo    PPSP_BIDS or PPSP_BIDASTAR (one query = two searches)
- *   opts->delta   Delta (0 = each graph's default)
+ *   opts          one per graph: opts[i].algo is PPSP_BIDS or PPSP_BIDASTAR
+ *                 (one query = two searches), opts[i].delta its Delta (0 = the
+ *                 graph's default); other fields are ignored
  * ppsp_server_submit copies the pairs and returns a request id.
  * ppsp_server_poll returns PPSP_E_BUSY until every query of the request has
  * finished; then it copies the k distances (input order) and the latency

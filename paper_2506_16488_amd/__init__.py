@@ -27,7 +27,7 @@ OK, E_INVALID, E_RANGE, E_OOM, E_OVERFLOW, E_NOCOORD, E_NOTSYM, E_DEVICE, E_BUSY
     E_TIMEOUT = 0, -1, -2, -3, -4, -5, -6, -7, -8, -9, -10, -11
 
 ALGO = {"sssp": 0, "et": 1, "astar": 2, "bids": 3, "bidastar": 4}
-BATCH = {"plain": 0, "plainstar": 1, "multi": 2}
+BATCH = {"plain": 0, "plainstar": 1, "multi": 2, "sssp": 3, "vc": 4, "auto": 5}
 SCHED = {"fixed": 0, "autotuned": 1, "learned": 2}
 SYMMETRIC = 1
 WANT_PATH = 1
@@ -416,11 +416,15 @@ class Server:
     submitted while others run are admitted between rounds into free slots."""
 
     def __init__(self, graphs, algo="bidastar", delta=0, state_budget_bytes=1 << 30):
+        """algo and delta: one value for every graph, or a list with one per graph."""
         self.graphs = list(graphs)
-        hs = (ctypes.c_void_p * len(self.graphs))(*[g.h for g in self.graphs])
+        k = len(self.graphs)
+        algos = list(algo) if isinstance(algo, (list, tuple)) else [algo] * k
+        deltas = list(delta) if isinstance(delta, (list, tuple)) else [delta] * k
+        hs = (ctypes.c_void_p * k)(*[g.h for g in self.graphs])
+        opts = (Opts * k)(*[make_opts(a, "plainstar", delta=d) for a, d in zip(algos, deltas)])
         h = ctypes.c_void_p()
-        _check(lib().ppsp_server_create(hs, len(self.graphs), ctypes.byref(make_opts(algo, "plainstar", delta=delta)),
-                                        int(state_budget_bytes), ctypes.byref(h)), "ppsp_server_create")
+        _check(lib().ppsp_server_create(hs, k, opts, int(state_budget_bytes), ctypes.byref(h)), "ppsp_server_create")
         self.h = h
         self.k = {}
 

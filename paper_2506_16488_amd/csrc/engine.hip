@@ -49,6 +49,7 @@ hipError_t launch_mlp_grad(const float *P, const float *X, const uint32_t *Y, co
 hipError_t launch_mlp_reduce(const float *partial, uint32_t nw, float *grad, hipStream_t st);
 hipError_t launch_mlp_adam(float *P, float *m, float *v, const float *partial, uint32_t nw, float lr, uint32_t t,
                            hipStream_t st);
+hipError_t launch_gather(const RoundArgs &A, const PairDesc *pd, hipStream_t st);
 hipError_t launch_path_len(const RoundArgs &A, const PairDesc *pd, uint32_t *len, hipStream_t st);
 hipError_t launch_path_write(const RoundArgs &A, const PairDesc *pd, const uint32_t *len, const uint64_t *off,
                              uint32_t *out, hipStream_t st);
@@ -112,6 +113,7 @@ struct Plan {
     std::vector<Partner> partners;
     std::vector<PairDesc> pairs;
     std::vector<uint64_t> delta;    // per search, key units
+    bool gather = false;            // read each query's distance off its root's search after the rounds
     std::vector<uint8_t> bin;       // per search: Delta-multiplier bin (learned / traced schedule)
     std::vector<uint32_t> qid;      // per search: index of its query among the call's distinct queries
 };
@@ -162,7 +164,7 @@ struct ppsp_graph_s {
         uint64_t delta = 0;
         int64_t theta_mode = 2, grid = 0;
         double ms = 0;
-    } tuned[5][3];                  // per (algo, batch strategy)
+    } tuned[5][6];                  // per (algo, batch strategy)
     uint64_t qcap = 0;
     bool served = false;            // attached to a server, which owns the workspace
     // learned schedule
@@ -429,6 +431,7 @@ int run_wave(ppsp_graph g, const Plan &P, bool want_path, WaveOut &out) {
             }
             continue;
         }
+        if (P.gather) HIPCHK(launch_gather(A, g->pairdesc.as<PairDesc>(), st));
         out.mu.resize(npair);
         HIPCHK(hipMemcpyAsync(out.mu.data(), g->mu.p, npair * 8, hipMemcpyDeviceToHost, st));
         HIPCHK(hipMemcpyAsync(out.stats, g->stats.p, ST_N * 8, hipMemcpyDeviceToHost, st));
@@ -536,10 +539,12 @@ void plan_single(ppsp_graph g, Plan &P, uint32_t s, uint32_t t, uint32_t algo, u
 
 int check_opts(ppsp_graph g, const ppsp_opts *o) {
     if (!o) return PPSP_E_INVALID;
-    if (o->algo > PPSP_BIDASTAR || o->batch > PPSP_BATCH_MULTI || o->sched > PPSP_SCHED_LEARNED) return PPSP_E_INVALID;
+    if (o->algo > PPSP_BIDASTAR || o->batch > PPSP_BATCH_AUTO || o->sched > PPSP_SCHED_LEARNED) return PPSP_E_INVALID;
     if (is_astar(o->algo) && !g->xy_ok) return PPSP_E_NOCOORD;
     if (is_bidir(o->algo) && !g->symmetric) return PPSP_E_NOTSYM;
-    if (o->batch == PPSP_BATCH_MULTI && o->algo != PPSP_BIDS) return PPSP_E_INVALID;
+    if ((o->batch == PPSP_BATCH_MULTI || o->batch == PPSP_BATCH_AUTO) && o->algo != PPSP_BIDS) return PPSP_E_INVALID;
+    if ((o->batch == PPSP_BATCH_SSSP || o->batch == PPSP_BATCH_VC) && o->algo != PPSP_SSSP) return PPSP_E_INVALID;
+    if (o->batch == PPSP_BATCH_VC && !g->symmetric) return PPSP_E_NOTSYM;
     if ((o->flags & PPSP_WANT_PATH) && g->wmin == 0 && g->m > 0) return PPSP_E_NOPATH;
     if (o->sched == PPSP_SCHED_LEARNED && !g->mlp_loaded) return PPSP_E_INVALID;
     return PPSP_OK;
@@ -716,6 +721,126 @@ int run_multi(ppsp_graph g, const std::vector<Query> &qs, const ppsp_opts *o, ui
     return flush();
 }
 
+// A vertex cover of the query graph (edges = queries): exact minimum per
+// connected component of at most 16 vertices (smallest mask among the
+// minimum ones), greedy by uncovered degree otherwise. Returns, per query,
+// the cover endpoint that answers it.
+std::vector<uint32_t> query_cover(const std::vector<Query> &qs) {
+    std::unordered_map<uint32_t, uint32_t> vid;
+    std::vector<uint32_t> verts;
+    auto id_of = [&](uint32_t v) {
+        auto it = vid.find(v);
+        if (it != vid.end()) return it->second;
+        vid.emplace(v, (uint32_t)verts.size());
+        verts.push_back(v);
+        return (uint32_t)verts.size() - 1;
+    };
+    const size_t nq = qs.size();
+    std::vector<std::pair<uint32_t, uint32_t>> e(nq);
+    for (size_t q = 0; q < nq; q++) e[q] = {id_of(qs[q].s), id_of(qs[q].t)};
+    const uint32_t nv = (uint32_t)verts.size();
+    std::vector<std::vector<uint32_t>> adj(nv);
+    for (size_t q = 0; q < nq; q++) {
+        adj[e[q].first].push_back((uint32_t)q);
+        adj[e[q].second].push_back((uint32_t)q);
+    }
+    std::vector<uint32_t> by(nq, UINT32_MAX);
+    std::vector<int> comp(nv, -1);
+    for (uint32_t r = 0; r < nv; r++) {
+        if (comp[r] >= 0) continue;
+        std::vector<uint32_t> cv{r}, cq;
+        comp[r] = (int)r;
+        for (size_t h = 0; h < cv.size(); h++)
+            for (uint32_t q : adj[cv[h]]) {
+                const uint32_t o = e[q].first == cv[h] ? e[q].second : e[q].first;
+                if (comp[o] < 0) { comp[o] = (int)r; cv.push_back(o); }
+            }
+        for (uint32_t v : cv)
+            for (uint32_t q : adj[v])
+                if (e[q].first == v) cq.push_back(q);
+        if (cv.size() <= 16) {
+            std::unordered_map<uint32_t, uint32_t> loc;
+            for (uint32_t j = 0; j < cv.size(); j++) loc[cv[j]] = j;
+            uint32_t best = 0, bestc = 99;
+            for (uint32_t m = 0; m < (1u << cv.size()); m++) {
+                const uint32_t c = (uint32_t)__builtin_popcount(m);
+                if (c >= bestc) continue;
+                bool ok = true;
+                for (uint32_t q : cq)
+                    if (!((m >> loc[e[q].first]) & 1) && !((m >> loc[e[q].second]) & 1)) { ok = false; break; }
+                if (ok) { best = m; bestc = c; }
+            }
+            for (uint32_t q : cq)
+                by[q] = ((best >> loc[e[q].first]) & 1) ? verts[e[q].first] : verts[e[q].second];
+        } else {
+            std::map<std::pair<uint32_t, uint32_t>, uint32_t> heap;   // (-degree, vertex)
+            std::unordered_map<uint32_t, uint32_t> deg;
+            for (uint32_t v : cv) {
+                deg[v] = (uint32_t)adj[v].size();
+                heap[{UINT32_MAX - deg[v], v}] = v;
+            }
+            while (!heap.empty()) {
+                const uint32_t v = heap.begin()->second;
+                heap.erase(heap.begin());
+                if (deg[v] == 0) continue;
+                for (uint32_t q : adj[v]) {
+                    if (by[q] != UINT32_MAX) continue;
+                    by[q] = verts[v];
+                    const uint32_t o = e[q].first == v ? e[q].second : e[q].first;
+                    heap.erase({UINT32_MAX - deg[o], o});
+                    deg[o]--;
+                    heap[{UINT32_MAX - deg[o], o}] = o;
+                }
+                deg[v] = 0;
+            }
+        }
+    }
+    return by;
+}
+
+// Plain-SSSP and VC-SSSP (Section 4.2): one search without pruning per root,
+// each query read off its root's search (a gather after the rounds).
+int run_cover(ppsp_graph g, const std::vector<Query> &qs, const ppsp_opts *o, uint64_t delta,
+              std::vector<Answer> &ans, const std::vector<uint32_t> &root_of) {
+    const bool want_path = o->flags & PPSP_WANT_PATH;
+    std::map<uint32_t, std::vector<uint32_t>> by_root;
+    for (size_t q = 0; q < qs.size(); q++) by_root[root_of[q]].push_back((uint32_t)q);
+    std::vector<uint32_t> roots;
+    for (auto &kv : by_root) roots.push_back(kv.first);
+    const uint64_t lim = std::max<uint64_t>(1, search_limit(g));
+    for (size_t r0 = 0; r0 < roots.size(); r0 += lim) {
+        const size_t r1 = std::min<size_t>(roots.size(), r0 + lim);
+        Plan P;
+        P.G = 1;
+        P.gather = true;
+        std::vector<uint32_t> ans_of_pair;
+        for (size_t r = r0; r < r1; r++) {
+            const uint32_t root = roots[r];
+            const uint32_t a = (uint32_t)P.sd.size();
+            SearchDesc sd = make_sd(g, root, K_DIST, root, root);
+            sd.noprune = 1;
+            sd.pbeg = sd.pend = 0;
+            P.sd.push_back(sd);
+            P.delta.push_back(key_delta(K_DIST, delta));
+            P.bin.push_back((uint8_t)(MLP_K / 2));
+            for (uint32_t q : by_root[root]) {
+                const uint32_t other = qs[q].s == root ? qs[q].t : qs[q].s;
+                P.pairs.push_back({a, TARGET_BIT | other});
+                ans_of_pair.push_back(q);
+            }
+        }
+        g->last.searches += P.sd.size();
+        WaveOut w;
+        CHK(run_wave(g, P, want_path, w));
+        accumulate(g, w);
+        collect(w, ans_of_pair, ans, want_path);
+        if (want_path)
+            for (uint32_t q : ans_of_pair)
+                if (root_of[q] != qs[q].s) std::reverse(ans[q].path.begin(), ans[q].path.end());
+    }
+    return PPSP_OK;
+}
+
 int batch_impl(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp_opts *o, void *hip_stream,
                uint64_t *dist, uint64_t *path_off, uint32_t *path_vtx, uint64_t path_cap, uint32_t *need_out) {
     auto t0 = std::chrono::steady_clock::now();
@@ -782,8 +907,32 @@ int batch_impl(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp_opts 
     }
     std::vector<Answer> ans(qs.size());
     if (!qs.empty()) {
-        if (o->batch == PPSP_BATCH_MULTI) CHK(run_multi(g, qs, o, delta, ans));
-        else CHK(run_independent(g, qs, o, delta, ans));
+        if (o->batch == PPSP_BATCH_SSSP) {
+            std::vector<uint32_t> root_of(qs.size());
+            for (size_t q = 0; q < qs.size(); q++) root_of[q] = qs[q].s;
+            CHK(run_cover(g, qs, o, delta, ans, root_of));
+        } else if (o->batch == PPSP_BATCH_VC || o->batch == PPSP_BATCH_AUTO) {
+            const std::vector<uint32_t> root_of = query_cover(qs);
+            std::unordered_map<uint32_t, char> cover, vq;
+            for (size_t q = 0; q < qs.size(); q++) {
+                cover[root_of[q]] = 1;
+                vq[qs[q].s] = 1;
+                vq[qs[q].t] = 1;
+            }
+            if (o->batch == PPSP_BATCH_VC || 4 * cover.size() <= vq.size()) {
+                ppsp_opts oo = *o;
+                oo.algo = PPSP_SSSP;
+                CHK(run_cover(g, qs, &oo, delta, ans, root_of));
+            } else {
+                ppsp_opts oo = *o;
+                oo.batch = PPSP_BATCH_MULTI;
+                CHK(run_multi(g, qs, &oo, delta, ans));
+            }
+        } else if (o->batch == PPSP_BATCH_MULTI) {
+            CHK(run_multi(g, qs, o, delta, ans));
+        } else {
+            CHK(run_independent(g, qs, o, delta, ans));
+        }
     }
     // scatter
     uint64_t need = 0;
@@ -825,7 +974,7 @@ int batch_impl(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp_opts 
 int trace_impl(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp_opts *o, const uint8_t *bins,
                bool rows, uint64_t cap, MlCtx &c, std::vector<uint32_t> &row_pair, std::vector<uint32_t> &pair_rounds,
                std::vector<uint64_t> &pair_arcs) {
-    if (o->batch == PPSP_BATCH_MULTI) return PPSP_E_INVALID;
+    if (o->batch != PPSP_BATCH_PLAIN && o->batch != PPSP_BATCH_PLAINSTAR) return PPSP_E_INVALID;
     for (uint32_t i = 0; i < k; i++)
         if (bins && bins[i] >= MLP_K) return PPSP_E_INVALID;
     // distinct queries in first-occurrence order, as batch_impl forms them
@@ -1047,7 +1196,7 @@ struct SrvGraph {
 
 struct ppsp_server_s {
     std::vector<SrvGraph> gs;
-    ppsp_opts opts{};
+    std::vector<ppsp_opts> opts;    // per graph
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
     std::deque<uint64_t> pending;
@@ -1062,15 +1211,15 @@ struct ppsp_server_s {
 
 namespace {
 
-int srv_setup_graph(ppsp_server srv, SrvGraph &G, uint64_t budget) {
+int srv_setup_graph(ppsp_server srv, SrvGraph &G, const ppsp_opts &o, uint64_t budget) {
     ppsp_graph g = G.g;
     const uint64_t n = g->n;
     const uint64_t per_query = 2 * n * 8;
     G.C = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(budget / per_query, 1), 1u << 20);
     const uint32_t ns = 2 * G.C, npair = G.C;
-    const uint32_t algo = srv->opts.algo;
+    const uint32_t algo = o.algo;
     const uint32_t kf = algo == PPSP_BIDS ? K_2DIST : K_BIDA_F, kb = algo == PPSP_BIDS ? K_2DIST : K_BIDA_B;
-    const uint64_t delta = srv->opts.delta ? srv->opts.delta : graph_default_delta(g);
+    const uint64_t delta = o.delta ? o.delta : graph_default_delta(g);
     G.sd.assign(ns, SearchDesc{});
     G.partners.resize(ns);
     G.pairs.resize(npair);
@@ -1620,15 +1769,17 @@ int ppsp_get_option(ppsp_graph g, const char *name, int64_t *v) {
 int ppsp_server_create(const ppsp_graph *graphs, uint32_t ngraphs, const ppsp_opts *opts, uint64_t state_budget,
                        ppsp_server *out) {
     if (!graphs || ngraphs == 0 || !opts || !out) return PPSP_E_INVALID;
-    if (opts->algo != PPSP_BIDS && opts->algo != PPSP_BIDASTAR) return PPSP_E_INVALID;
     for (uint32_t i = 0; i < ngraphs; i++) {
+        if (opts[i].algo != PPSP_BIDS && opts[i].algo != PPSP_BIDASTAR) return PPSP_E_INVALID;
         if (!graphs[i] || graphs[i]->served) return PPSP_E_INVALID;
+        for (uint32_t j = 0; j < i; j++)
+            if (graphs[j] == graphs[i]) return PPSP_E_INVALID;
         if (!graphs[i]->symmetric) return PPSP_E_NOTSYM;
-        if (opts->algo == PPSP_BIDASTAR && !graphs[i]->xy_ok) return PPSP_E_NOCOORD;
+        if (opts[i].algo == PPSP_BIDASTAR && !graphs[i]->xy_ok) return PPSP_E_NOCOORD;
         if (graphs[i]->device != graphs[0]->device) return PPSP_E_INVALID;
     }
     ppsp_server srv = new ppsp_server_s();
-    srv->opts = *opts;
+    srv->opts.assign(opts, opts + ngraphs);
     // rounds between admission points: the first graph's rounds_per_sync, at least 2
     // (a finished slot must see one more round before it is reused)
     srv->rounds_per_chunk = (uint32_t)std::min<int64_t>(std::max<int64_t>(graphs[0]->opt_rounds_per_sync, 2), 1024);
@@ -1639,7 +1790,7 @@ int ppsp_server_create(const ppsp_graph *graphs, uint32_t ngraphs, const ppsp_op
         srv->gs[i].g = graphs[i];
         // the budget is shared in proportion to the graphs' sizes: equal slots per vertex
         const uint64_t b = (uint64_t)((double)state_budget * graphs[i]->n / total_n);
-        int rc = srv_setup_graph(srv, srv->gs[i], b);
+        int rc = srv_setup_graph(srv, srv->gs[i], srv->opts[i], b);
         if (rc != PPSP_OK) {
             for (uint32_t j = 0; j <= i; j++) {
                 if (srv->gs[j].h_done) (void)hipHostFree(srv->gs[j].h_done);
@@ -1782,7 +1933,7 @@ int ppsp_mlp_fit(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp_opt
                  uint32_t epochs, uint64_t seed, float *params_out, ppsp_fit_report *rep) {
     if (!g || !opts || !pairs || k == 0 || !init || !params_out) return PPSP_E_INVALID;
     if (g->served) return PPSP_E_BUSY;
-    if (opts->batch == PPSP_BATCH_MULTI) return PPSP_E_INVALID;
+    if (opts->batch != PPSP_BATCH_PLAIN && opts->batch != PPSP_BATCH_PLAINSTAR) return PPSP_E_INVALID;
     CHK(check_opts(g, opts));
     ppsp_fit_report R{};
     // 1. Labels: each pair alone under every fixed multiplier; the label is

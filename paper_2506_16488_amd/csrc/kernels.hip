@@ -504,7 +504,7 @@ __device__ __forceinline__ int control_search(const RoundArgs &A, uint32_t i, ui
         if (writer) A.exh[i] = 1;
     }
     uint64_t mx = 0;
-    bool open = false;
+    bool open = sd.noprune != 0;     // a search without pruning runs until its frontier is empty
     for (uint32_t p = sd.pbeg; p < sd.pend; p++) {
         const Partner pt = A.partners[p];
         const uint32_t m32 = (uint32_t)(A.mu[pt.pair] >> 32);
@@ -837,6 +837,18 @@ __global__ void k_path_write(RoundArgs A, const PairDesc *pd, const uint32_t *le
     }
 }
 
+// A query answered by a search without pruning: its distance and meeting
+// vertex (the target) are read off the root's state after the rounds.
+__global__ void k_gather(RoundArgs A, const PairDesc *pd) {
+    const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= A.npair) return;
+    const PairDesc d = pd[p];
+    if (!(d.b & TARGET_BIT)) return;
+    const uint32_t t = d.b & ~TARGET_BIT;
+    const uint32_t dt = dist_of(A, d.a, t);
+    A.mu[p] = dt == INF32 ? INF64 : (((uint64_t)dt << 32) | t);
+}
+
 // ---- host-side launchers (the engine lives in another translation unit) ----
 
 hipError_t launch_init(const RoundArgs &A, hipStream_t st) {
@@ -874,6 +886,11 @@ hipError_t launch_control(const RoundArgs &A, hipStream_t st) {
         const uint32_t nb = (A.nsearch + BLOCK - 1) / BLOCK;
         k_control<<<nb, BLOCK, 0, st>>>(A);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_gather(const RoundArgs &A, const PairDesc *pd, hipStream_t st) {
+    if (A.npair) k_gather<<<(A.npair + 255) / 256, 256, 0, st>>>(A, pd);
     return hipGetLastError();
 }
 

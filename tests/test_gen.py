@@ -126,3 +126,26 @@ def test_hub_pairs():
     assert p.shape == (1024, 2)
     assert np.unique(p[:512, 0]).shape[0] <= 32
     assert np.unique(p[512:, 0]).shape[0] > 400
+
+
+def test_batch_patterns():
+    import itertools
+    for kind in gen.PATTERNS:
+        e = gen.pattern_edges(kind)
+        assert all(0 <= a < 6 and 0 <= b < 6 and a != b for a, b in e), kind
+        assert len(set(tuple(sorted(x)) for x in e)) == len(e), kind
+        p = gen.batch_pattern(kind, 10_000, seed=1)
+        assert p.shape == (len(e), 2) and len(set(p.reshape(-1).tolist())) <= 6
+    sizes = {k: len(gen.pattern_edges(k)) for k in gen.PATTERNS}
+    assert sizes == {"star": 5, "fork": 5, "chain": 5, "cycle": 6, "bipartite": 9, "clique": 15, "separate": 3,
+                     "random": 8}
+    # brute-force minimum vertex covers of the fixed patterns
+    def min_cover(e):
+        for c in range(7):
+            for s in itertools.combinations(range(6), c):
+                if all(a in s or b in s for a, b in e):
+                    return c
+    assert {k: min_cover(gen.pattern_edges(k)) for k in gen.PATTERNS if k != "random"} == \
+        {"star": 1, "fork": 2, "chain": 3, "cycle": 3, "bipartite": 3, "clique": 5, "separate": 3}
+    big = gen.batch_pattern("random", 10_000, seed=2, m=30, k=200)
+    assert big.shape == (200, 2) and len(set(big.reshape(-1).tolist())) <= 30

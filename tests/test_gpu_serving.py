@@ -78,6 +78,26 @@ def test_server_isolation_and_admission(P):
     assert st["running"] == 0 and st["pending"] == 0
 
 
+def test_server_mixed_algorithms(P):
+    """One server, BiD-A* on a lattice and BiDS on an R-MAT graph (one
+    algorithm per graph)."""
+    hosts = [gen.lattice(150, 0.05, seed=11), gen.rmat(11, 16, seed=12)]
+    Gs = [P.Graph.from_host(g) for g in hosts]
+    reqs = _requests(hosts, [6, 20, 9, 13, 2, 30], seed=800)
+    S = P.Server(Gs, algo=["bidastar", "bids"], state_budget_bytes=16 * sum(g.n for g in hosts) * 5)
+    ids = [S.submit(gi, p) for gi, p in reqs]
+    for (gi, p), r in zip(reqs, ids):
+        d, _ = S.wait(r, timeout_ms=120000)
+        assert np.array_equal(d, _oracle(hosts[gi], p))
+    S.close()
+    with pytest.raises(P.PPSPError):
+        P.Server(Gs, algo=["bids", "bidastar"])             # no coordinates on the R-MAT graph
+    with pytest.raises(P.PPSPError):
+        P.Server([Gs[0], Gs[0]], algo="bids")               # a graph twice
+    for G in Gs:
+        G.close()
+
+
 def test_server_bids_unreachable_and_hubs(P):
     """BiDS over a disconnected random graph and an R-MAT graph with hub
     vertices (heavy-list path): unreachable pairs return INF in the mix."""
