@@ -346,6 +346,10 @@ int ppsp_last_stats(ppsp_graph g, ppsp_stats *stats);
  *   "queue_cap"       frontier queue capacity in entries (grows x4, with a rerun of
  *                     the wave, whenever a round overflows it)
  *   "heavy_cap"       heavy-list capacity in arc chunks (grows the same way)
+ *   "heavy_window"    vertices of degree > 512 are extracted only from the low 1/heavy_window
+ *                     of the step window (smallest key + Delta/heavy_window), where their
+ *                     distance is close to final, so their long arc lists are pushed fewer
+ *                     times (default 8; 1 = the whole window)
  *   "ml_every"        rounds between evaluations of the learned schedule's network (default 4;
  *                     a search keeps its multiplier in between)
  * Returns PPSP_E_INVALID for an unknown name.

@@ -145,7 +145,7 @@ struct ppsp_graph_s {
     DevBuf row_ptr, arcs, xy, in_row_ptr, in_arcs;   // transpose only for a directed graph
     // workspace (grow only)
     DevBuf S, q0, q1, sd, partners, pairdesc, ctl, delta, done, exh, alive, minkey, mu, qcount, cpre, round, err,
-        stats, wstats, pathlen, pathoff, pathbuf, heavy, hcount;
+        stats, wstats, pathlen, pathoff, pathbuf, heavy, hcount, hlim;
     uint32_t maxdeg = 0;
     uint32_t hcap = 0;              // heavy list capacity (0 while no vertex exceeds HEAVY_DEG)
     hipStream_t st = nullptr;
@@ -156,7 +156,7 @@ struct ppsp_graph_s {
     // options
     int64_t opt_profile = 0, opt_rounds_per_sync = 16, opt_grid_blocks = 0, opt_mem_budget_mb = 0,
             opt_default_delta = 0, opt_use_graph = 0, opt_timeout_ms = 600000, opt_theta_mode = 2, opt_queue_cap = 0,
-            opt_ml_every = 4;
+            opt_ml_every = 4, opt_heavy_window = 8;
     uint64_t wmean = 1;             // mean arc weight (rounded up)
     uint64_t fingerprint = 0;       // hash of the CSR, keys the tuning cache
     struct Tuned {
@@ -242,6 +242,8 @@ void set_args(ppsp_graph g, RoundArgs &A, uint32_t nsearch, uint32_t npair, uint
     A.heavy = g->heavy.as<uint4>();
     A.hcount = g->hcount.as<unsigned long long>();
     A.hcap = g->maxdeg > HEAVY_DEG ? g->hcap : 0;
+    A.hlim = g->hlim.as<uint64_t>();
+    A.hwin = (uint32_t)g->opt_heavy_window;
     A.theta_mode = (uint32_t)g->opt_theta_mode;
     if (g->ml && g->ml->mode) {
         A.sc = g->sc.as<unsigned long long>();
@@ -302,6 +304,7 @@ int run_wave(ppsp_graph g, const Plan &P, bool want_path, WaveOut &out) {
     CHK(ensure(g->partners, P.partners.size() * sizeof(Partner)));
     CHK(ensure(g->pairdesc, npair * sizeof(PairDesc)));
     CHK(ensure(g->ctl, ns * 16));
+    CHK(ensure(g->hlim, ns * 8));
     CHK(ensure(g->delta, ns * 8));
     CHK(ensure(g->done, ns * 4));
     CHK(ensure(g->exh, ns * 4));
@@ -1253,6 +1256,7 @@ int srv_setup_graph(ppsp_server srv, SrvGraph &G, const ppsp_opts &o, uint64_t b
     CHK(ensure(g->partners, ns * sizeof(Partner)));
     CHK(ensure(g->pairdesc, npair * sizeof(PairDesc)));
     CHK(ensure(g->ctl, (uint64_t)ns * 16));
+    CHK(ensure(g->hlim, (uint64_t)ns * 8));
     CHK(ensure(g->delta, (uint64_t)ns * 8));
     CHK(ensure(g->done, (uint64_t)ns * 4));
     CHK(ensure(g->exh, (uint64_t)ns * 4));
@@ -1741,6 +1745,7 @@ int ppsp_set_option(ppsp_graph g, const char *name, int64_t v) {
     else if (k == "queue_cap") { if (v < (int64_t)NSEG || v > (1ll << 31)) return PPSP_E_INVALID; g->qcap = (uint64_t)v; g->opt_queue_cap = v; }
     else if (k == "heavy_cap") { if (v < 1 || v > (1ll << 28)) return PPSP_E_INVALID; g->hcap = (uint32_t)v; }
     else if (k == "ml_every") { if (v < 1 || v > 1024) return PPSP_E_INVALID; g->opt_ml_every = v; }
+    else if (k == "heavy_window") { if (v < 1 || v > 4096) return PPSP_E_INVALID; g->opt_heavy_window = v; }
 
     else return PPSP_E_INVALID;
     return PPSP_OK;
@@ -1760,6 +1765,7 @@ int ppsp_get_option(ppsp_graph g, const char *name, int64_t *v) {
     else if (k == "queue_cap") *v = (int64_t)g->qcap;
     else if (k == "heavy_cap") *v = g->hcap;
     else if (k == "ml_every") *v = g->opt_ml_every;
+    else if (k == "heavy_window") *v = g->opt_heavy_window;
 
     else return PPSP_E_INVALID;
     return PPSP_OK;

@@ -323,17 +323,27 @@ __global__ __launch_bounds__(WAVE) void k_round(RoundArgs A) {
                 } else if (key > c.x && key < bnd) {
                     action = 1;                     // above the threshold: later round
                 } else {
-                    if (A.G == 2) {
-                        if (dp != INF32) mu_update(A, A.partners[sd.pbeg].pair, (uint64_t)du + dp, u);
-                    } else {
-                        meet_list(A, sd, du, u);
-                    }
-                    if (key < bnd) {
-                        action = 2;
+                    bool wait = false;
+                    if (A.hcap && key < bnd && key > A.hlim[i]) {
                         rb = A.row_ptr[u];
                         re = A.row_ptr[u + 1];
-                        c_sv++;
-                        c_se += re - rb;
+                        wait = re - rb > HEAVY_DEG;   // a hub above the low end of the window
+                    }
+                    if (wait) {
+                        action = 1;
+                    } else {
+                        if (A.G == 2) {
+                            if (dp != INF32) mu_update(A, A.partners[sd.pbeg].pair, (uint64_t)du + dp, u);
+                        } else {
+                            meet_list(A, sd, du, u);
+                        }
+                        if (key < bnd) {
+                            action = 2;
+                            rb = A.row_ptr[u];
+                            re = A.row_ptr[u + 1];
+                            c_sv++;
+                            c_se += re - rb;
+                        }
                     }
                 }
             }
@@ -555,6 +565,15 @@ __device__ __forceinline__ uint64_t step_threshold(uint32_t mode, uint64_t th0, 
     return th;
 }
 
+// Upper end of the extraction window of heavy vertices (see RoundArgs::hlim).
+__device__ __forceinline__ uint64_t heavy_limit(uint64_t mk, uint64_t d, uint32_t hwin) {
+    if (mk == INF64) return INF64;
+    uint64_t w = d / (hwin ? hwin : 1u);
+    if (w == 0) w = 1;
+    const uint64_t h = mk + w - 1;
+    return h < mk ? INF64 : h;
+}
+
 // Per-search step control after a round (see the file comment).
 __global__ __launch_bounds__(BLOCK) void k_control(RoundArgs A) {
     const uint32_t i = blockIdx.x * BLOCK + threadIdx.x;
@@ -573,6 +592,7 @@ __global__ __launch_bounds__(BLOCK) void k_control(RoundArgs A) {
     if (control_search(A, i, par, np, true, &mk, &nb) != 2) return;
     const uint64_t th = step_threshold(A.theta_mode, A.ctl[i].x, mk, A.delta[i]);
     A.ctl[i] = make_ulonglong2(th, nb);
+    if (A.hcap) A.hlim[i] = heavy_limit(mk, A.delta[i], A.hwin);
 }
 
 __device__ __forceinline__ float lg2p(double x) { return log2f((float)(1.0 + x)); }
@@ -695,6 +715,7 @@ __global__ __launch_bounds__(WAVE) void k_control_ml(RoundArgs A) {
             uint64_t d = (db << bin) >> 4;
             if (d == 0) d = 1;
             A.ctl[i] = make_ulonglong2(step_threshold(A.theta_mode, th0, mk, d), nb);
+            if (A.hcap) A.hlim[i] = heavy_limit(mk, d, A.hwin);
         }
     }
 }
@@ -714,6 +735,7 @@ __global__ __launch_bounds__(BLOCK) void k_init(RoundArgs A) {
     else atomicOr(A.err, ERR_QUEUE);
     const uint64_t k = key_of(sd.kind, 0, hk);
     A.ctl[i] = make_ulonglong2(k, INF64);
+    if (A.hcap) A.hlim[i] = k;
     A.alive[i] = 1;
     A.alive[(uint64_t)A.nsearch + i] = 0;
     A.minkey[i] = k;
@@ -742,6 +764,7 @@ __global__ __launch_bounds__(BLOCK) void k_admit(RoundArgs A, const uint32_t *id
     if (pos < A.qseg) q[(uint64_t)x * A.qseg + pos] = make_uint4(i, s, 0u, (uint32_t)hk);
     else atomicOr(A.err, ERR_QUEUE);
     A.ctl[i] = make_ulonglong2(key_of(sd.kind, 0, hk), INF64);
+    if (A.hcap) A.hlim[i] = key_of(sd.kind, 0, hk);
     A.alive[(uint64_t)par * A.nsearch + i] = 0;
     A.alive[(uint64_t)np * A.nsearch + i] = 0;
     A.minkey[(uint64_t)par * A.nsearch + i] = INF64;

@@ -165,6 +165,13 @@ struct RoundArgs {
     float deg_feat;            // log2(m / n) / 4
     uint32_t grid;             // workgroups of the round kernel
     uint32_t ml_every;         // the network runs every ml_every rounds (bins are kept in between)
+    // Degree-aware extraction: a vertex of degree > HEAVY_DEG is extracted
+    // only while its key <= hlim[i] = smallest key + max(1, Delta / hwin) - 1,
+    // i.e. from the low end of the window, where its distance is close to
+    // final, so its long arc list is pushed fewer times. The smallest key
+    // always qualifies, so every round makes progress.
+    uint64_t *hlim;            // [nsearch]
+    uint32_t hwin;             // window divisor for heavy vertices (1 = the whole window)
 };
 
 // Only the first ML_SAMPLE workgroups of the round kernels update the
