@@ -145,7 +145,7 @@ def main():
         dd = G.query(s, t, algo=args.algo, delta=delta)
         lat.append(1000.0 * (time.perf_counter() - a))
         assert dd == int(dist0[i]), "single query disagrees with the batch"
-    lat = np.array(lat)
+    lat = np.array(lat) if lat else None
 
     out = {
         "metric": "exact s-t queries/sec",
@@ -169,8 +169,8 @@ def main():
         "gteps": round(gteps, 4),
         "scanned_arcs_per_query": int(agg["scanned_arcs"] / (K * q)),
         "rounds_per_step": int(agg["rounds"] / K),
-        "single_query_p50_ms": round(float(np.percentile(lat, 50)), 3),
-        "single_query_p99_ms": round(float(np.percentile(lat, 99)), 3),
+        "single_query_p50_ms": None if lat is None else round(float(np.percentile(lat, 50)), 3),
+        "single_query_p99_ms": None if lat is None else round(float(np.percentile(lat, 99)), 3),
         "roofline": {
             "bound": "hbm",
             "kernel": "k_round",

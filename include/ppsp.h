@@ -198,13 +198,15 @@ typedef struct {
     double default_ms;     /* wall time of the sample batch with the defaults */
     uint32_t trials;       /* configurations timed */
     uint32_t from_cache;   /* 1 if read from cache_path */
+    uint32_t heavy_window; /* chosen "heavy_window" (graphs with vertices of degree > 512) */
 } ppsp_tune_result;
 
 /*
  * Chooses the threshold schedule and launch shape for (opts->algo,
  * opts->batch) by timing the sample batch `pairs` (k pairs, host). Delta is
  * first swept by doubling from a small start while the time improves (the
- * tuning procedure of Section 6.1), then the threshold rule, Delta between the
+ * tuning procedure of Section 6.1), then the hub window ("heavy_window", on
+ * graphs with vertices of degree > 512), the threshold rule, Delta between the
  * doublings and the number of round-kernel workgroups are refined. The choice
  * is kept in the handle and used by PPSP_SCHED_AUTOTUNED. With cache_path
  * (or NULL) the choice is read from / appended to a text file keyed by a hash

@@ -156,13 +156,13 @@ struct ppsp_graph_s {
     // options
     int64_t opt_profile = 0, opt_rounds_per_sync = 16, opt_grid_blocks = 0, opt_mem_budget_mb = 0,
             opt_default_delta = 0, opt_use_graph = 0, opt_timeout_ms = 600000, opt_theta_mode = 2, opt_queue_cap = 0,
-            opt_ml_every = 4, opt_heavy_window = 8;
+            opt_ml_every = 4, opt_heavy_window = 64;
     uint64_t wmean = 1;             // mean arc weight (rounded up)
     uint64_t fingerprint = 0;       // hash of the CSR, keys the tuning cache
     struct Tuned {
         bool valid = false;
         uint64_t delta = 0;
-        int64_t theta_mode = 2, grid = 0;
+        int64_t theta_mode = 2, grid = 0, hwin = 64;
         double ms = 0;
     } tuned[5][6];                  // per (algo, batch strategy)
     uint64_t qcap = 0;
@@ -867,14 +867,15 @@ int batch_impl(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp_opts 
     // ppsp_tune chose for this algorithm and batch strategy.
     struct Restore {
         ppsp_graph g;
-        int64_t mode, grid;
-        ~Restore() { g->opt_theta_mode = mode; g->opt_grid_blocks = grid; }
-    } restore{g, g->opt_theta_mode, g->opt_grid_blocks};
+        int64_t mode, grid, hwin;
+        ~Restore() { g->opt_theta_mode = mode; g->opt_grid_blocks = grid; g->opt_heavy_window = hwin; }
+    } restore{g, g->opt_theta_mode, g->opt_grid_blocks, g->opt_heavy_window};
     if (o->sched == PPSP_SCHED_AUTOTUNED && g->tuned[o->algo][o->batch].valid) {
         const auto &t = g->tuned[o->algo][o->batch];
         delta = t.delta;
         g->opt_theta_mode = t.theta_mode;
         g->opt_grid_blocks = t.grid;
+        g->opt_heavy_window = t.hwin;
     }
     // PPSP_SCHED_LEARNED: the loaded network picks each search's step
     // (a trace call has set its own context already).
@@ -1636,26 +1637,28 @@ int ppsp_tune(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp_opts *
     CHK(check_opts(g, opts));
     auto &slot = g->tuned[opts->algo][opts->batch];
     char key[128];
-    snprintf(key, sizeof key, "ppsp-tune-v1 %016llx %u %u", (unsigned long long)g->fingerprint, opts->algo, opts->batch);
+    snprintf(key, sizeof key, "ppsp-tune-v2 %016llx %u %u", (unsigned long long)g->fingerprint, opts->algo, opts->batch);
     if (cache_path) {
         if (FILE *f = fopen(cache_path, "r")) {
             char line[256];
             while (fgets(line, sizeof line, f)) {
                 unsigned long long d;
-                long long mode, grid;
+                long long mode, grid, hw;
                 double ms;
                 if (strncmp(line, key, strlen(key)) == 0 &&
-                    sscanf(line + strlen(key), " %llu %lld %lld %lf", &d, &mode, &grid, &ms) == 4) {
+                    sscanf(line + strlen(key), " %llu %lld %lld %lld %lf", &d, &mode, &grid, &hw, &ms) == 5) {
                     slot.valid = true;
                     slot.delta = d;
                     slot.theta_mode = mode;
                     slot.grid = grid;
+                    slot.hwin = hw;
                     slot.ms = ms;
                 }
             }
             fclose(f);
             if (slot.valid) {
-                *out = ppsp_tune_result{slot.delta, (uint32_t)slot.theta_mode, (uint32_t)slot.grid, slot.ms, 0, 0, 1};
+                *out = ppsp_tune_result{slot.delta, (uint32_t)slot.theta_mode, (uint32_t)slot.grid, slot.ms, 0, 0, 1,
+                                        (uint32_t)slot.hwin};
                 return PPSP_OK;
             }
         }
@@ -1664,12 +1667,14 @@ int ppsp_tune(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp_opts *
     ppsp_opts o = *opts;
     o.sched = PPSP_SCHED_FIXED;
     o.flags &= ~PPSP_WANT_PATH;
-    const int64_t mode0 = g->opt_theta_mode, grid0 = g->opt_grid_blocks;
+    const int64_t mode0 = g->opt_theta_mode, grid0 = g->opt_grid_blocks, hwin0 = g->opt_heavy_window;
     uint32_t trials = 0;
+    int64_t best_hw = hwin0;
     // wall time of one configuration (best of two runs; the first may allocate)
     auto trial = [&](uint64_t delta, int64_t mode, int64_t grid) -> double {
         g->opt_theta_mode = mode;
         g->opt_grid_blocks = grid;
+        g->opt_heavy_window = best_hw;
         o.delta = delta;
         double best = 1e300;
         for (int rep = 0; rep < 2; rep++) {
@@ -1691,7 +1696,18 @@ int ppsp_tune(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp_opts *
         if (ms < best_ms) { best_ms = ms; best_d = d; worse = 0; } else worse++;
     }
     int64_t best_mode = 2, best_grid = 0;
-    // 2. Refinement: threshold rule, Delta between the doublings, launch shape.
+    // 2. Refinement: the hub window (graphs with hubs), threshold rule,
+    //    Delta between the doublings, launch shape.
+    if (g->maxdeg > HEAVY_DEG) {
+        const int64_t hw_start = best_hw;
+        for (int64_t hw : {8, 64, 512}) {
+            if (hw == hw_start) continue;
+            const int64_t keep = best_hw;
+            best_hw = hw;
+            const double ms = trial(best_d, 2, 0);
+            if (ms < best_ms) best_ms = ms; else best_hw = keep;
+        }
+    }
     for (int64_t mode : {0, 1}) {
         const double ms = trial(best_d, mode, 0);
         if (ms < best_ms) { best_ms = ms; best_mode = mode; }
@@ -1708,20 +1724,23 @@ int ppsp_tune(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp_opts *
     }
     g->opt_theta_mode = mode0;
     g->opt_grid_blocks = grid0;
+    g->opt_heavy_window = hwin0;
     if (best_ms >= 1e300) return PPSP_E_DEVICE;
     slot.valid = true;
     slot.delta = best_d;
     slot.theta_mode = best_mode;
     slot.grid = best_grid;
+    slot.hwin = best_hw;
     slot.ms = best_ms;
     if (cache_path) {
         if (FILE *f = fopen(cache_path, "a")) {
-            fprintf(f, "%s %llu %lld %lld %.3f\n", key, (unsigned long long)best_d, (long long)best_mode,
-                    (long long)best_grid, best_ms);
+            fprintf(f, "%s %llu %lld %lld %lld %.3f\n", key, (unsigned long long)best_d, (long long)best_mode,
+                    (long long)best_grid, (long long)best_hw, best_ms);
             fclose(f);
         }
     }
-    *out = ppsp_tune_result{best_d, (uint32_t)best_mode, (uint32_t)best_grid, best_ms, default_ms, trials, 0};
+    *out = ppsp_tune_result{best_d, (uint32_t)best_mode, (uint32_t)best_grid, best_ms, default_ms, trials, 0,
+                            (uint32_t)best_hw};
     return PPSP_OK;
 }
 
