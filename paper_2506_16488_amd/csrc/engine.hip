@@ -201,10 +201,12 @@ uint64_t state_budget(ppsp_graph g) {
     return have > reserve ? (uint64_t)((have - reserve) * 0.9) : (1ull << 28);
 }
 
+// Searches per wave: what the state budget holds, below 2^30 (frontier
+// entries flag carried entries in bit 31 of the search index).
 uint64_t search_limit(ppsp_graph g) {
     uint64_t per = state_bytes_per_search(g);
     uint64_t lim = state_budget(g) / per;
-    return std::max<uint64_t>(lim, 1);
+    return std::min<uint64_t>(std::max<uint64_t>(lim, 1), 1ull << 30);
 }
 
 void set_args(ppsp_graph g, RoundArgs &A, uint32_t nsearch, uint32_t npair, uint32_t G) {

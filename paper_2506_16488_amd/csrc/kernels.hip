@@ -82,6 +82,8 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long x)
     return x;
 }
 
+__device__ __forceinline__ uint32_t key_scale(uint32_t kind) { return kind >= K_2DIST ? 2u : 1u; }
+
 // key = scale * delta + hk (see ppsp_dev.h); never negative for a consistent heuristic.
 __device__ __forceinline__ uint64_t key_of(uint32_t kind, uint64_t d, int32_t hk) {
     const int64_t k = (int64_t)((kind >= K_2DIST ? 2 : 1) * d) + hk;
@@ -253,6 +255,10 @@ __device__ __forceinline__ uint32_t wave_exscan(uint32_t v, uint32_t *total) {
     return x - v;
 }
 
+#ifndef CARRY_CHECK
+#define CARRY_CHECK 2   // rounds between state checks of a carried entry (a power of two; 1 = every round)
+#endif
+
 // Extracted vertices of one wave chunk, for the arc-parallel relaxation.
 struct Advance {
     uint32_t off[WAVE + 1];   // exclusive prefix of the extracted degrees (0 for other lanes)
@@ -294,19 +300,30 @@ __global__ __launch_bounds__(WAVE) void k_round(RoundArgs A) {
         const bool valid = pos < nseg;
 
         // 1. One entry per lane: stale, kept for later, pruned or extracted.
+        // A carried entry stores its exact key (CARRY_BIT set in .x, the key in
+        // .w instead of the heuristic term): while that key lies between the
+        // threshold and the bound it is carried again without reading the
+        // state, except every CARRY_CHECK-th round (staggered by vertex),
+        // which drops it if the vertex was lowered since (then a fresher
+        // entry exists).
         uint4 ent = make_uint4(0, 0, 0, 0);
-        uint32_t du = 0, rb = 0, re = 0;
+        uint32_t si = 0, du = 0, rb = 0, re = 0;
         uint64_t key = 0, bnd = 0;
         int action = 0;  // 0 nothing, 1 keep for a later round, 2 relax
         if (valid) {
             ent = qin[idx];
-            const uint32_t i = ent.x, u = ent.y;
+            const bool carried = (ent.x & CARRY_BIT) != 0;
+            si = ent.x & ~CARRY_BIT;
+            const uint32_t i = si, u = ent.y;
             c_ent++;
             const ulonglong2 c = A.ctl[i];
             bnd = c.y;
-            if (bnd != 0) {
+            if (bnd != 0 && carried && ent.w != KEY_UNKNOWN && ent.w > c.x && ent.w < bnd &&
+                ((r + u) & (CARRY_CHECK - 1)) != 0) {
+                key = ent.w;
+                action = 1;
+            } else if (bnd != 0) {
                 const SearchDesc sd = A.sd[i];
-                const int32_t hk = (int32_t)ent.w;
                 uint64_t word;
                 uint32_t dp = INF32;
                 if (A.G == 2) {
@@ -317,47 +334,56 @@ __global__ __launch_bounds__(WAVE) void k_round(RoundArgs A) {
                     word = A.S[state_index(1, A.n, i, u)];
                 }
                 du = (uint32_t)(word >> 32);
-                key = key_of(sd.kind, du, hk);
                 if ((uint32_t)word != ent.z && (uint32_t)word != INF32) {
                     // lowered after this entry was added: a fresher entry exists
-                } else if (key > c.x && key < bnd) {
-                    action = 1;                     // above the threshold: later round
                 } else {
-                    bool wait = false;
-                    if (A.hcap && key < bnd && key > A.hlim[i]) {
-                        rb = A.row_ptr[u];
-                        re = A.row_ptr[u + 1];
-                        wait = re - rb > HEAVY_DEG;   // a hub above the low end of the window
-                    }
-                    if (wait) {
-                        action = 1;
+                    // the heuristic term: stored, or (unchanged distance) the stored key minus scale * delta
+                    int32_t hk;
+                    if (!carried) hk = (int32_t)ent.w;
+                    else if (ent.w != KEY_UNKNOWN) hk = (int32_t)((int64_t)ent.w - (int64_t)key_scale(sd.kind) * du);
+                    else hk = hterm(A, sd, u);
+                    key = key_of(sd.kind, du, hk);
+                    if (key > c.x && key < bnd) {
+                        action = 1;                     // above the threshold: later round
                     } else {
-                        if (A.G == 2) {
-                            if (dp != INF32) mu_update(A, A.partners[sd.pbeg].pair, (uint64_t)du + dp, u);
-                        } else {
-                            meet_list(A, sd, du, u);
-                        }
-                        if (key < bnd) {
-                            action = 2;
+                        bool wait = false;
+                        if (A.hcap && key < bnd && key > A.hlim[i]) {
                             rb = A.row_ptr[u];
                             re = A.row_ptr[u + 1];
-                            c_sv++;
-                            c_se += re - rb;
+                            wait = re - rb > HEAVY_DEG;   // a hub above the low end of the window
+                        }
+                        if (wait) {
+                            action = 1;
+                        } else {
+                            if (A.G == 2) {
+                                if (dp != INF32) mu_update(A, A.partners[sd.pbeg].pair, (uint64_t)du + dp, u);
+                            } else {
+                                meet_list(A, sd, du, u);
+                            }
+                            if (key < bnd) {
+                                action = 2;
+                                rb = A.row_ptr[u];
+                                re = A.row_ptr[u + 1];
+                                c_sv++;
+                                c_se += re - rb;
+                            }
                         }
                     }
+                    if (action == 1)
+                        ent = make_uint4(i | CARRY_BIT, u, ent.z, key < KEY_UNKNOWN ? (uint32_t)key : KEY_UNKNOWN);
                 }
             }
         }
         if (count)
-            wave_add_keyed(A.sc + (uint64_t)par * A.nsearch * 2, ent.x, 0,
+            wave_add_keyed(A.sc + (uint64_t)par * A.nsearch * 2, si, 0,
                            ((unsigned long long)(re - rb) << 32) + 1ull, action == 2);
-        // Entries above the threshold stay in the frontier unchanged (a
-        // lowering of the vertex in this round adds a fresher entry, which
-        // makes this one stale next round).
+        // Entries above the threshold stay in the frontier (a lowering of the
+        // vertex in this round adds a fresher entry, which makes this one
+        // stale).
         const bool keep = action == 1;
         c_keep += keep;
         wstage_push(st, scnt, keep, ent, qout, qcout, A.qseg, A.err);
-        search_stats(A, np, ent.x, keep ? 1u : 0u, keep ? key : INF64, count);
+        search_stats(A, np, si, keep ? 1u : 0u, keep ? key : INF64, count);
 
         // High-degree vertices go to the heavy list as chunks of at most
         // HEAVY_CHUNK arcs, which all waves of k_heavy share; one atomic per
@@ -375,7 +401,7 @@ __global__ __launch_bounds__(WAVE) void k_round(RoundArgs A) {
                 const uint32_t eb = rb + k * HEAVY_CHUNK;
                 const uint32_t ee = min(re, eb + HEAVY_CHUNK);
                 if (slot < A.hcap) {
-                    A.heavy[2 * slot] = make_uint4(ent.x, ent.y, du, eb);
+                    A.heavy[2 * slot] = make_uint4(si, ent.y, du, eb);
                     A.heavy[2 * slot + 1] = make_uint4(ee, 0u, 0u, 0u);
                 } else {
                     atomicOr(A.err, ERR_HEAVY);
@@ -392,7 +418,7 @@ __global__ __launch_bounds__(WAVE) void k_round(RoundArgs A) {
         if (T == 0) continue;
         adv.off[lane_id()] = pre;
         if (lane_id() == WAVE - 1) adv.off[WAVE] = pre + deg;
-        adv.i[lane_id()] = ent.x;
+        adv.i[lane_id()] = si;
         adv.u[lane_id()] = ent.y;
         adv.du[lane_id()] = du;
         adv.rb[lane_id()] = rb;

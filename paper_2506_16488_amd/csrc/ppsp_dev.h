@@ -27,7 +27,8 @@
 // terms of UpdateDistance); G = 1 is plain search-major.
 //
 // Frontier. Queues of 16-byte entries (search, vertex, stamp when added,
-// heuristic term) per round parity. A queue is NSEG segments; a wave appends
+// heuristic term) per round parity. An entry kept for a later round holds
+// its key instead of the heuristic term (CARRY_BIT in the search field). A queue is NSEG segments; a wave appends
 // to segment (workgroup id mod NSEG), which spreads the append counters over
 // NSEG addresses, and the next round walks the segments as one list of
 // WAVE-entry chunks through a prefix sum of their chunk counts.
@@ -54,6 +55,8 @@ namespace ppsp {
 constexpr uint32_t INF32 = 0xFFFFFFFFu;
 constexpr uint64_t INF64 = ~0ull;
 constexpr uint32_t TARGET_BIT = 0x80000000u;  // Partner.other: a target vertex, not a search
+constexpr uint32_t CARRY_BIT = 0x80000000u;   // frontier entry .x: carried entry, .w holds its key
+constexpr uint32_t KEY_UNKNOWN = 0xFFFFFFFFu; // carried key too large for 32 bits
 constexpr int BLOCK = 256;                     // threads per block (four wave64s)
 constexpr int WAVE = 64;
 constexpr int WSTAGE = 256;                    // LDS staging slots per wave (round kernel)
