@@ -303,9 +303,11 @@ int ppsp_mlp_fit(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp_opt
  * ppsp_server_poll returns PPSP_E_BUSY until every query of the request has
  * finished; then it copies the k distances (input order) and the latency
  * (submit to last result, ms) and forgets the request. ppsp_server_wait blocks
- * up to timeout_ms. Errors: PPSP_E_RANGE (vertex id), PPSP_E_INVALID
- * (unknown request), PPSP_E_OOM (a frontier queue overflowed; the server
- * stops).
+ * up to timeout_ms. When a frontier queue or the heavy list overflows, the
+ * queries on the device start again with twice (four times) the capacity; a
+ * graph's explicit "queue_cap" option is the queue's starting size. Errors:
+ * PPSP_E_RANGE (vertex id), PPSP_E_INVALID (unknown request), PPSP_E_OOM
+ * (buffers can grow no further; the server stops).
  */
 typedef struct ppsp_server_s *ppsp_server;
 
@@ -317,6 +319,8 @@ typedef struct {
     uint64_t running;     /* queries on the device now */
     uint64_t slots;       /* query slots, summed over graphs */
     uint64_t pending;     /* requests with queries not yet admitted */
+    uint64_t restarts;    /* frontier-buffer overflows: the queries on the device were restarted
+                             with larger buffers (and count again in `admitted`) */
 } ppsp_server_counters;
 
 int ppsp_server_create(const ppsp_graph *graphs, uint32_t ngraphs, const ppsp_opts *opts, uint64_t state_budget,
@@ -352,6 +356,9 @@ int ppsp_last_stats(ppsp_graph g, ppsp_stats *stats);
  *                     of the step window (smallest key + Delta/heavy_window), where their
  *                     distance is close to final, so their long arc lists are pushed fewer
  *                     times (default 8; 1 = the whole window)
+ *   "multi_group"     Multi-BiDS state layout: this many consecutive query-graph vertices
+ *                     keep their words of a vertex side by side (a power of two up to 64;
+ *                     default 32; 1 = search-major)
  *   "ml_every"        rounds between evaluations of the learned schedule's network (default 4;
  *                     a search keeps its multiplier in between)
  * Returns PPSP_E_INVALID for an unknown name.

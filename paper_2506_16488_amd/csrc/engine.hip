@@ -147,6 +147,7 @@ struct ppsp_graph_s {
     DevBuf S, q0, q1, sd, partners, pairdesc, ctl, delta, done, exh, alive, minkey, mu, qcount, cpre, round, err,
         stats, wstats, pathlen, pathoff, pathbuf, heavy, hcount, hlim;
     uint32_t maxdeg = 0;
+    uint64_t hchunks = 0;           // heavy-list chunks of all vertices of degree > HEAVY_DEG
     uint32_t hcap = 0;              // heavy list capacity (0 while no vertex exceeds HEAVY_DEG)
     hipStream_t st = nullptr;
     uint32_t *h_poll = nullptr;     // pinned
@@ -156,7 +157,7 @@ struct ppsp_graph_s {
     // options
     int64_t opt_profile = 0, opt_rounds_per_sync = 16, opt_grid_blocks = 0, opt_mem_budget_mb = 0,
             opt_default_delta = 0, opt_use_graph = 0, opt_timeout_ms = 600000, opt_theta_mode = 2, opt_queue_cap = 0,
-            opt_ml_every = 4, opt_heavy_window = 64;
+            opt_ml_every = 4, opt_heavy_window = 64, opt_multi_group = 32;
     uint64_t wmean = 1;             // mean arc weight (rounded up)
     uint64_t fingerprint = 0;       // hash of the CSR, keys the tuning cache
     struct Tuned {
@@ -294,12 +295,15 @@ struct WaveOut {
 int run_wave(ppsp_graph g, const Plan &P, bool want_path, WaveOut &out) {
     const uint32_t ns = (uint32_t)P.sd.size(), npair = (uint32_t)P.pairs.size();
     const uint64_t n = g->n;
+    const uint64_t ns_words = ((uint64_t)ns + P.G - 1) / P.G * P.G;   // whole groups of G searches
     hipStream_t st = g->st;
-    CHK(ensure(g->S, ns * n * 8));
+    CHK(ensure(g->S, ns_words * n * 8));
     CHK(ensure(g->round, 16));
     CHK(ensure(g->hcount, 16));
     if (g->maxdeg > HEAVY_DEG) {
-        if (g->hcap == 0) g->hcap = 1u << 20;
+        // a round can extract each hub once per search; a quarter of that at once is ample
+        const uint64_t want = std::min<uint64_t>(1u << 26, std::max<uint64_t>(1u << 20, (uint64_t)ns * g->hchunks / 4));
+        if (g->hcap < want) g->hcap = (uint32_t)want;
         CHK(ensure(g->heavy, (uint64_t)g->hcap * 32));
     }
     CHK(ensure(g->sd, ns * sizeof(SearchDesc)));
@@ -328,7 +332,7 @@ int run_wave(ppsp_graph g, const Plan &P, bool want_path, WaveOut &out) {
     for (;;) {
         CHK(ensure(g->q0, g->qcap * 16));
         CHK(ensure(g->q1, g->qcap * 16));
-        HIPCHK(hipMemsetAsync(g->S.p, 0xFF, ns * n * 8, st));
+        HIPCHK(hipMemsetAsync(g->S.p, 0xFF, ns_words * n * 8, st));
         HIPCHK(hipMemcpyAsync(g->sd.p, P.sd.data(), ns * sizeof(SearchDesc), hipMemcpyHostToDevice, st));
         if (!P.partners.empty())
             HIPCHK(hipMemcpyAsync(g->partners.p, P.partners.data(), P.partners.size() * sizeof(Partner),
@@ -670,6 +674,7 @@ int run_multi(ppsp_graph g, const std::vector<Query> &qs, const ppsp_opts *o, ui
     auto flush = [&]() -> int {
         if (wave_comps.empty()) return PPSP_OK;
         Plan P;
+        P.G = (uint32_t)g->opt_multi_group;
         std::vector<uint32_t> local(nv, UINT32_MAX);
         for (uint32_t c : wave_comps)
             for (uint32_t v : comp_verts[c]) {
@@ -1196,6 +1201,7 @@ struct SrvGraph {
     std::vector<uint32_t> h_ids;    // admitted search ids (kept until the chunk's sync)
     uint32_t running = 0;           // slots in state 1
     uint32_t draining = 0;          // slots in state 2
+    std::deque<std::pair<uint64_t, uint32_t>> redo;   // (request, query) to admit first, after an overflow
 };
 
 }  // namespace
@@ -1211,7 +1217,7 @@ struct ppsp_server_s {
     std::thread worker;
     bool stop = false;
     int err = PPSP_OK;
-    uint64_t admitted = 0, completed = 0, chunks = 0, rounds = 0;
+    uint64_t admitted = 0, completed = 0, chunks = 0, rounds = 0, restarts = 0;
     uint32_t rounds_per_chunk = 16;
 };
 
@@ -1221,7 +1227,8 @@ int srv_setup_graph(ppsp_server srv, SrvGraph &G, const ppsp_opts &o, uint64_t b
     ppsp_graph g = G.g;
     const uint64_t n = g->n;
     const uint64_t per_query = 2 * n * 8;
-    G.C = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(budget / per_query, 1), 1u << 20);
+    // two thirds of the budget for search state, one third for the two frontier queues
+    G.C = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(budget / 3 * 2 / per_query, 1), 1u << 20);
     const uint32_t ns = 2 * G.C, npair = G.C;
     const uint32_t algo = o.algo;
     const uint32_t kf = algo == PPSP_BIDS ? K_2DIST : K_BIDA_F, kb = algo == PPSP_BIDS ? K_2DIST : K_BIDA_B;
@@ -1252,7 +1259,8 @@ int srv_setup_graph(ppsp_server srv, SrvGraph &G, const ppsp_opts &o, uint64_t b
     CHK(ensure(g->round, 16));
     CHK(ensure(g->hcount, 16));
     if (g->maxdeg > HEAVY_DEG) {
-        if (g->hcap == 0) g->hcap = 1u << 22;
+        const uint64_t want = std::min<uint64_t>(1u << 26, std::max<uint64_t>(1u << 20, (uint64_t)ns * g->hchunks / 4));
+        if (g->hcap < want) g->hcap = (uint32_t)want;
         CHK(ensure(g->heavy, (uint64_t)g->hcap * 32));
     }
     CHK(ensure(g->sd, ns * sizeof(SearchDesc)));
@@ -1272,7 +1280,8 @@ int srv_setup_graph(ppsp_server srv, SrvGraph &G, const ppsp_opts &o, uint64_t b
     CHK(ensure(g->stats, ST_N * 8));
     G.grid = g->opt_grid_blocks > 0 ? (uint32_t)g->opt_grid_blocks : (uint32_t)(24 * g->cu);
     CHK(ensure(g->wstats, (uint64_t)G.grid * ST_N * 8));
-    g->qcap = std::max<uint64_t>(g->qcap, std::min<uint64_t>(std::max<uint64_t>(16384ull * ns, 1ull << 22), 1ull << 29));
+    if (g->opt_queue_cap == 0)   // an explicit "queue_cap" stands (and grows on overflow)
+        g->qcap = std::max<uint64_t>(g->qcap, std::min<uint64_t>(std::max<uint64_t>(budget / 3 / 32, 1ull << 22), 1ull << 31));
     CHK(ensure(g->q0, g->qcap * 16));
     CHK(ensure(g->q1, g->qcap * 16));
     CHK(ensure(G.ids, (uint64_t)ns * 4));
@@ -1296,6 +1305,44 @@ int srv_setup_graph(ppsp_server srv, SrvGraph &G, const ppsp_opts &o, uint64_t b
     return PPSP_OK;
 }
 
+// Grows the buffer that overflowed, resets the graph's round loop to idle and
+// puts every running query back in front of the admission order. Called with
+// the lock held, after the stream is idle.
+int srv_restart(ppsp_server srv, SrvGraph &G, uint32_t errbits) {
+    ppsp_graph g = G.g;
+    hipStream_t st = g->st;
+    if (errbits & ERR_QUEUE) {
+        if (g->qcap >= (1ull << 31)) return PPSP_E_OOM;
+        g->qcap *= 2;
+        CHK(ensure(g->q0, g->qcap * 16));
+        CHK(ensure(g->q1, g->qcap * 16));
+    }
+    if (errbits & ERR_HEAVY) {
+        if (g->hcap >= (1u << 28)) return PPSP_E_OOM;
+        g->hcap *= 4;
+        CHK(ensure(g->heavy, (uint64_t)g->hcap * 32));
+    }
+    for (uint32_t q = G.C; q-- > 0;) {
+        if (G.state[q] == 1) {
+            G.redo.emplace_front(G.slot_req[q], G.slot_q[q]);
+            G.running--;
+        } else if (G.state[q] == 2) {
+            G.draining--;
+        }
+        G.state[q] = 0;
+    }
+    const uint32_t ns = 2 * G.C;
+    HIPCHK(hipMemsetAsync(g->qcount.p, 0, 2 * NSEG * 4, st));
+    HIPCHK(hipMemsetAsync(g->cpre.p, 0, 2 * (NSEG + 1) * 4, st));
+    HIPCHK(hipMemsetAsync(g->hcount.p, 0, 16, st));
+    HIPCHK(hipMemsetAsync(g->err.p, 0, 16, st));
+    set_args(g, G.A, ns, G.C, 2);
+    HIPCHK(launch_idle(G.A, st));
+    HIPCHK(hipStreamSynchronize(st));
+    srv->restarts++;
+    return PPSP_OK;
+}
+
 // One chunk of the worker: admit, run rounds, collect. Called without the lock.
 int srv_chunk(ppsp_server srv, bool &any_running) {
     std::vector<std::vector<uint32_t>> admit(srv->gs.size());
@@ -1304,36 +1351,45 @@ int srv_chunk(ppsp_server srv, bool &any_running) {
         for (size_t gi = 0; gi < srv->gs.size(); gi++) {
             SrvGraph &G = srv->gs[gi];
             uint32_t slot = 0;
+            // puts query q of request id into the next free slot; false when none is free
+            auto place = [&](uint64_t id, uint32_t q) -> bool {
+                while (slot < G.C && G.state[slot] != 0) slot++;
+                if (slot == G.C) return false;
+                SrvRequest &rq = srv->reqs[id];
+                const uint32_t s0 = rq.pairs[2 * q], t0 = rq.pairs[2 * q + 1];
+                G.state[slot] = 1;
+                G.slot_req[slot] = id;
+                G.slot_q[slot] = q;
+                SearchDesc f = make_sd(G.g, s0, G.sd[2 * slot].kind, s0, t0);
+                SearchDesc b = make_sd(G.g, t0, G.sd[2 * slot + 1].kind, s0, t0);
+                f.pbeg = G.sd[2 * slot].pbeg; f.pend = G.sd[2 * slot].pend;
+                b.pbeg = G.sd[2 * slot + 1].pbeg; b.pend = G.sd[2 * slot + 1].pend;
+                G.sd[2 * slot] = f;
+                G.sd[2 * slot + 1] = b;
+                admit[gi].push_back(slot);
+                srv->admitted++;
+                return true;
+            };
+            while (!G.redo.empty() && place(G.redo.front().first, G.redo.front().second)) G.redo.pop_front();
+            if (!G.redo.empty()) continue;
             for (auto it = srv->pending.begin(); it != srv->pending.end();) {
                 SrvRequest &rq = srv->reqs[*it];
                 if (rq.graph != gi) { ++it; continue; }
                 const uint32_t k = (uint32_t)(rq.pairs.size() / 2);
+                bool full = false;
                 while (rq.next < k) {
-                    const uint32_t s = rq.pairs[2 * rq.next], t = rq.pairs[2 * rq.next + 1];
-                    if (s == t) {                              // d(s,s) = 0 needs no search
+                    const uint32_t s0 = rq.pairs[2 * rq.next], t0 = rq.pairs[2 * rq.next + 1];
+                    if (s0 == t0) {                              // d(s,s) = 0 needs no search
                         rq.dist[rq.next++] = 0;
                         if (--rq.remaining == 0) { rq.done = true; rq.t_done = std::chrono::steady_clock::now(); srv->completed++; }
                         continue;
                     }
-                    while (slot < G.C && G.state[slot] != 0) slot++;
-                    if (slot == G.C) break;
-                    G.state[slot] = 1;
-                    G.slot_req[slot] = *it;
-                    G.slot_q[slot] = rq.next++;
-                    G.sd[2 * slot].src = s;
-                    G.sd[2 * slot + 1].src = t;
-                    SearchDesc f = make_sd(G.g, s, G.sd[2 * slot].kind, s, t);
-                    SearchDesc b = make_sd(G.g, t, G.sd[2 * slot + 1].kind, s, t);
-                    f.pbeg = G.sd[2 * slot].pbeg; f.pend = G.sd[2 * slot].pend;
-                    b.pbeg = G.sd[2 * slot + 1].pbeg; b.pend = G.sd[2 * slot + 1].pend;
-                    G.sd[2 * slot] = f;
-                    G.sd[2 * slot + 1] = b;
-                    admit[gi].push_back(slot);
-                    srv->admitted++;
+                    if (!place(*it, rq.next)) { full = true; break; }
+                    rq.next++;
                 }
                 if (rq.done) srv->cv_done.notify_all();
                 if (rq.next == k) it = srv->pending.erase(it); else ++it;
-                if (slot == G.C) break;
+                if (full) break;
             }
         }
     }
@@ -1374,8 +1430,14 @@ int srv_chunk(ppsp_server srv, bool &any_running) {
     for (auto &G : srv->gs) {
         if (G.running == 0 && G.draining == 0) continue;
         srv->rounds += srv->rounds_per_chunk;
-        if (G.h_done[2 * G.C] & (ERR_QUEUE | ERR_HEAVY)) return PPSP_E_OOM;
         if (G.h_done[2 * G.C] & ERR_OVERFLOW) return PPSP_E_OVERFLOW;
+        if (G.h_done[2 * G.C] & (ERR_QUEUE | ERR_HEAVY)) {
+            // A queue or the heavy list overflowed in this chunk: frontier
+            // entries were lost, so every query on the device starts again
+            // with larger buffers (results of earlier chunks stand).
+            CHK(srv_restart(srv, G, G.h_done[2 * G.C]));
+            continue;
+        }
         for (uint32_t q = 0; q < G.C; q++) {
             if (G.state[q] == 2) { G.state[q] = 0; G.draining--; continue; }
             if (G.state[q] != 1 || !G.h_done[2 * q] || !G.h_done[2 * q + 1]) continue;
@@ -1473,7 +1535,12 @@ int ppsp_graph_create(int device, uint32_t n, uint64_t m, const uint64_t *row_pt
     }
     if (m == 0) wmin = wmax = 1;
     uint32_t maxdeg = 0;
-    for (uint32_t v = 0; v < n; v++) maxdeg = std::max<uint32_t>(maxdeg, (uint32_t)(row_ptr[v + 1] - row_ptr[v]));
+    uint64_t hchunks = 0;
+    for (uint32_t v = 0; v < n; v++) {
+        const uint64_t d = row_ptr[v + 1] - row_ptr[v];
+        maxdeg = std::max<uint32_t>(maxdeg, (uint32_t)d);
+        if (d > HEAVY_DEG) hchunks += (d + HEAVY_CHUNK - 1) / HEAVY_CHUNK;
+    }
     if (coord_fx && coord_frac_bits > 30) return PPSP_E_RANGE;
     ppsp_graph g = new ppsp_graph_s();
     g->device = device;
@@ -1495,6 +1562,7 @@ int ppsp_graph_create(int device, uint32_t n, uint64_t m, const uint64_t *row_pt
         g->fingerprint = h;
     }
     g->maxdeg = maxdeg;
+    g->hchunks = hchunks;
     auto fail = [&](int rc) {
         ppsp_graph_destroy(g);
         return rc;
@@ -1767,6 +1835,10 @@ int ppsp_set_option(ppsp_graph g, const char *name, int64_t v) {
     else if (k == "heavy_cap") { if (v < 1 || v > (1ll << 28)) return PPSP_E_INVALID; g->hcap = (uint32_t)v; }
     else if (k == "ml_every") { if (v < 1 || v > 1024) return PPSP_E_INVALID; g->opt_ml_every = v; }
     else if (k == "heavy_window") { if (v < 1 || v > 4096) return PPSP_E_INVALID; g->opt_heavy_window = v; }
+    else if (k == "multi_group") {
+        if (v < 1 || v > 64 || (v & (v - 1))) return PPSP_E_INVALID;
+        g->opt_multi_group = v;
+    }
 
     else return PPSP_E_INVALID;
     return PPSP_OK;
@@ -1787,6 +1859,7 @@ int ppsp_get_option(ppsp_graph g, const char *name, int64_t *v) {
     else if (k == "heavy_cap") *v = g->hcap;
     else if (k == "ml_every") *v = g->opt_ml_every;
     else if (k == "heavy_window") *v = g->opt_heavy_window;
+    else if (k == "multi_group") *v = g->opt_multi_group;
 
     else return PPSP_E_INVALID;
     return PPSP_OK;
@@ -1893,6 +1966,7 @@ int ppsp_server_stats(ppsp_server srv, ppsp_server_counters *out) {
     out->rounds = srv->rounds;
     for (auto &G : srv->gs) { out->running += G.running; out->slots += G.C; }
     out->pending = srv->pending.size();
+    out->restarts = srv->restarts;
     return PPSP_OK;
 }
 

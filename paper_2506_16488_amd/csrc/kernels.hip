@@ -188,7 +188,7 @@ __device__ __forceinline__ bool relax_arc(const RoundArgs &A, const SearchDesc &
         other = (i & 1) ? w.x : w.y;
         p = (unsigned long long *)(A.S + base + (i & 1));
     } else {
-        p = (unsigned long long *)(A.S + state_index(1, A.n, i, v));
+        p = (unsigned long long *)(A.S + state_index(A.G, A.n, i, v));
         own = *p;
     }
     if (cand >= (own >> 32)) return false;
@@ -331,7 +331,7 @@ __global__ __launch_bounds__(WAVE) void k_round(RoundArgs A) {
                     word = (i & 1) ? w.y : w.x;
                     dp = (uint32_t)(((i & 1) ? w.x : w.y) >> 32);
                 } else {
-                    word = A.S[state_index(1, A.n, i, u)];
+                    word = A.S[state_index(A.G, A.n, i, u)];
                 }
                 du = (uint32_t)(word >> 32);
                 if ((uint32_t)word != ent.z && (uint32_t)word != INF32) {

@@ -24,7 +24,11 @@
 //     S[((i / G) * n + v) * G + i % G]
 // G = 2 puts the forward and backward copies of a bidirectional query side by
 // side, so one 16-byte load returns both delta[v+] and delta[v-] (the two
-// terms of UpdateDistance); G = 1 is plain search-major.
+// terms of UpdateDistance); G = 1 is plain search-major. Multi-BiDS groups
+// G consecutive query-graph vertices (by default 32: the copies of v for the
+// searches of one component share a few cache lines, the vertex-major layout
+// of Section 4.2), so its UpdateDistance over the neighbours in the query
+// graph reads few lines.
 //
 // Frontier. Queues of 16-byte entries (search, vertex, stamp when added,
 // heuristic term) per round parity. An entry kept for a later round holds
@@ -183,8 +187,11 @@ struct RoundArgs {
 // ML_SAMPLE chunks). Counter atomics on one search's address stay few.
 constexpr uint32_t ML_SAMPLE = 64;
 
+// G is a power of two: searches i and i^1.. of one group of G keep their
+// words of vertex v side by side (G = 1: search-major).
 __host__ __device__ inline uint64_t state_index(uint32_t G, uint32_t n, uint32_t i, uint32_t v) {
-    return G == 2 ? ((((uint64_t)(i >> 1) * n) + v) << 1) | (i & 1u) : (uint64_t)i * n + v;
+    const uint32_t s = (uint32_t)__builtin_ctz(G);
+    return ((((uint64_t)(i >> s) * n) + v) << s) | (i & (G - 1u));
 }
 
 enum StatIdx { ST_ROUNDS = 0, ST_ENTRIES = 1, ST_SCANV = 2, ST_SCANE = 3, ST_SUCC = 4, ST_CARRY = 5, ST_N = 8 };

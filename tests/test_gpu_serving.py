@@ -44,7 +44,7 @@ def _requests(graphs, sizes, seed):
 def _serve(P, hosts, algo, reqs, slots, stagger_s):
     Gs = [P.Graph.from_host(g) for g in hosts]
     alone = [Gs[gi].batch_query(p, algo=algo, batch="plainstar") for gi, p in reqs]
-    budget = 16 * sum(g.n for g in hosts) * slots        # `slots` query slots per graph
+    budget = 24 * sum(g.n for g in hosts) * slots        # `slots` query slots per graph (2/3 of it is state)
     S = P.Server(Gs, algo=algo, state_budget_bytes=budget)
     assert S.stats()["slots"] == slots * len(hosts)
     ids = []
@@ -122,6 +122,24 @@ def test_server_single_slot_reuse(P):
     for (gi, p), a, (d, _) in zip(reqs, alone, res):
         assert np.array_equal(d, _oracle(hosts[gi], p))
         assert np.array_equal(d, a)
+
+
+def test_server_overflow_restarts_keep_results(P):
+    """A queue far too small for the frontier: the server grows it and
+    restarts the queries on the device; every result still equals the oracle."""
+    hosts = [gen.lattice(120, 0.1, seed=14)]
+    G = P.Graph.from_host(hosts[0])
+    G.set_option("queue_cap", 256)
+    reqs = _requests(hosts, [12, 5, 30, 8], seed=950)
+    S = P.Server([G], algo="bidastar", state_budget_bytes=16 * hosts[0].n * 3 * 8)
+    ids = [S.submit(0, p) for _, p in reqs]
+    for (_, p), r in zip(reqs, ids):
+        d, _ = S.wait(r, timeout_ms=120000)
+        assert np.array_equal(d, _oracle(hosts[0], p))
+    st = S.stats()
+    assert st["restarts"] > 0 and st["completed"] == len(reqs)
+    S.close()
+    G.close()
 
 
 def test_server_errors_and_release(P):
