@@ -90,13 +90,18 @@ enum ppsp_sched {
 
 /* ppsp_opts.flags. */
 #define PPSP_WANT_PATH 1u      /* also return an s->t vertex path per query */
-#define PPSP_MEMO_H 2u         /* memoise the heuristic per vertex (Section 5) */
+#define PPSP_PULL 4u           /* pull relaxation (Appendix B): before an extracted vertex u pushes,
+                                  delta[u] <- min over its arcs (v, u) of delta[v] + w; symmetric graphs
+                                  only (ignored otherwise). Results are identical with or without it. */
+#define PPSP_MEMO_H 2u         /* memoise the heuristic per query and vertex (Section 5): A* and BiD-A*,
+                                  Plain / Plain*; one 8-byte word per query and vertex, shared by the
+                                  query's two searches. Results are identical with or without it. */
 
 typedef struct {
     uint32_t algo;     /* enum ppsp_algo */
     uint32_t batch;    /* enum ppsp_batch (ignored by ppsp_query) */
     uint32_t sched;    /* enum ppsp_sched */
-    uint32_t flags;    /* PPSP_WANT_PATH | PPSP_MEMO_H */
+    uint32_t flags;    /* PPSP_WANT_PATH | PPSP_MEMO_H | PPSP_PULL */
     uint64_t delta;    /* Delta in distance units for PPSP_SCHED_FIXED; 0 = graph default */
 } ppsp_opts;
 

@@ -32,6 +32,7 @@ SCHED = {"fixed": 0, "autotuned": 1, "learned": 2}
 SYMMETRIC = 1
 WANT_PATH = 1
 MEMO_H = 2
+PULL = 4
 
 
 class PPSPError(RuntimeError):
@@ -204,11 +205,12 @@ def heuristic_fx(x0: int, y0: int, x1: int, y1: int, w_scale: int, frac_bits: in
     return int(lib().ppsp_heuristic_fx(x0, y0, x1, y1, w_scale, frac_bits))
 
 
-def make_opts(algo="bids", batch="plainstar", sched="fixed", delta=0, want_path=False, memo=False) -> Opts:
+def make_opts(algo="bids", batch="plainstar", sched="fixed", delta=0, want_path=False, memo=False,
+              pull=False) -> Opts:
     return Opts(ALGO[algo] if isinstance(algo, str) else int(algo),
                 BATCH[batch] if isinstance(batch, str) else int(batch),
                 SCHED[sched] if isinstance(sched, str) else int(sched),
-                (WANT_PATH if want_path else 0) | (MEMO_H if memo else 0), int(delta))
+                (WANT_PATH if want_path else 0) | (MEMO_H if memo else 0) | (PULL if pull else 0), int(delta))
 
 
 def graph_create(n, row_ptr, col, w, coords=None, frac_bits=8, w_scale=1000, symmetric=True, device=0,
@@ -344,13 +346,13 @@ class Graph:
         return cls(g.n, g.row_ptr, g.col, g.w, getattr(g, "coords", None), getattr(g, "frac_bits", 8),
                    w_scale, getattr(g, "symmetric", True), device)
 
-    def query(self, s, t, algo="bids", delta=0, want_path=False, memo=False, sched="fixed"):
-        d, p = query(self.h, s, t, make_opts(algo, "plain", sched, delta, want_path, memo), want_path=want_path)
+    def query(self, s, t, algo="bids", delta=0, want_path=False, memo=False, sched="fixed", pull=False):
+        d, p = query(self.h, s, t, make_opts(algo, "plain", sched, delta, want_path, memo, pull), want_path=want_path)
         return (d, p) if want_path else d
 
     def batch_query(self, pairs, algo="bids", batch="plainstar", delta=0, want_path=False, memo=False,
-                    sched="fixed"):
-        return batch_query(self.h, pairs, make_opts(algo, batch, sched, delta, want_path, memo),
+                    sched="fixed", pull=False):
+        return batch_query(self.h, pairs, make_opts(algo, batch, sched, delta, want_path, memo, pull),
                            want_path=want_path)
 
     def stats(self) -> dict:

@@ -145,7 +145,7 @@ struct ppsp_graph_s {
     DevBuf row_ptr, arcs, xy, in_row_ptr, in_arcs;   // transpose only for a directed graph
     // workspace (grow only)
     DevBuf S, q0, q1, sd, partners, pairdesc, ctl, delta, done, exh, alive, minkey, mu, qcount, cpre, round, err,
-        stats, wstats, pathlen, pathoff, pathbuf, heavy, hcount, hlim;
+        stats, wstats, pathlen, pathoff, pathbuf, heavy, hcount, hlim, memo;
     uint32_t maxdeg = 0;
     uint64_t hchunks = 0;           // heavy-list chunks of all vertices of degree > HEAVY_DEG
     uint32_t hcap = 0;              // heavy list capacity (0 while no vertex exceeds HEAVY_DEG)
@@ -168,6 +168,9 @@ struct ppsp_graph_s {
     } tuned[5][6];                  // per (algo, batch strategy)
     uint64_t qcap = 0;
     bool served = false;            // attached to a server, which owns the workspace
+    uint32_t memo_epoch = 0;        // epoch of the last wave that used the heuristic memo
+    bool memo_call = false;         // the current call memoises the heuristic (PPSP_MEMO_H)
+    bool pull_call = false;         // the current call pulls before pushing (PPSP_PULL)
     // learned schedule
     DevBuf sc, bin, done_round, tot_arcs, trace, trace_s, trace_n, mlpw;
     bool mlp_loaded = false;
@@ -247,6 +250,11 @@ void set_args(ppsp_graph g, RoundArgs &A, uint32_t nsearch, uint32_t npair, uint
     A.hcap = g->maxdeg > HEAVY_DEG ? g->hcap : 0;
     A.hlim = g->hlim.as<uint64_t>();
     A.hwin = (uint32_t)g->opt_heavy_window;
+    A.pull = g->pull_call && g->symmetric ? 1u : 0u;
+    if (g->memo_call && g->has_xy && (G == 2 || G == 1)) {
+        A.memo = g->memo.as<uint64_t>();
+        A.epoch = g->memo_epoch;
+    }
     A.theta_mode = (uint32_t)g->opt_theta_mode;
     if (g->ml && g->ml->mode) {
         A.sc = g->sc.as<unsigned long long>();
@@ -361,6 +369,19 @@ int run_wave(ppsp_graph g, const Plan &P, bool want_path, WaveOut &out) {
             HIPCHK(hipMemsetAsync(g->done_round.p, 0, (uint64_t)ns * 4, st));
             HIPCHK(hipMemsetAsync(g->tot_arcs.p, 0, (uint64_t)ns * 8, st));
             HIPCHK(hipMemsetAsync(g->trace_n.p, 0, 8, st));
+        }
+        if (g->memo_call) {
+            // one word per query slot and vertex; a new epoch per wave invalidates the old words
+            const uint64_t slots = P.G == 2 ? (ns + 1) / 2 : ns;
+            if (g->memo.bytes < slots * n * 8) {
+                CHK(ensure(g->memo, slots * n * 8));
+                HIPCHK(hipMemsetAsync(g->memo.p, 0, g->memo.bytes, st));
+                g->memo_epoch = 0;
+            }
+            if (++g->memo_epoch == 0) {
+                HIPCHK(hipMemsetAsync(g->memo.p, 0, g->memo.bytes, st));
+                g->memo_epoch = 1;
+            }
         }
         RoundArgs A;
         set_args(g, A, ns, npair, P.G);
@@ -597,7 +618,9 @@ int run_independent(ppsp_graph g, const std::vector<Query> &qs, const ppsp_opts 
                     std::vector<Answer> &ans) {
     const bool want_path = o->flags & PPSP_WANT_PATH;
     const uint32_t per = is_bidir(o->algo) ? 2 : 1;
-    uint64_t lim = o->batch == PPSP_BATCH_PLAIN ? 1 : std::max<uint64_t>(1, search_limit(g) / per);
+    // queries per wave; the heuristic memo adds one 8-byte word per query and vertex (one search's worth)
+    uint64_t lim = o->batch == PPSP_BATCH_PLAIN ? 1
+                   : std::max<uint64_t>(1, search_limit(g) / (per + (g->memo_call ? 1 : 0)));
     for (size_t q0 = 0; q0 < qs.size(); q0 += lim) {
         const size_t q1 = std::min<size_t>(qs.size(), q0 + lim);
         Plan P;
@@ -884,6 +907,13 @@ int batch_impl(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp_opts 
         g->opt_grid_blocks = t.grid;
         g->opt_heavy_window = t.hwin;
     }
+    struct MemoRestore {
+        ppsp_graph g;
+        ~MemoRestore() { g->memo_call = false; g->pull_call = false; }
+    } memorestore{g};
+    g->pull_call = (o->flags & PPSP_PULL) != 0;
+    g->memo_call = (o->flags & PPSP_MEMO_H) && is_astar(o->algo) &&
+                   (o->batch == PPSP_BATCH_PLAIN || o->batch == PPSP_BATCH_PLAINSTAR);
     // PPSP_SCHED_LEARNED: the loaded network picks each search's step
     // (a trace call has set its own context already).
     MlCtx learned;

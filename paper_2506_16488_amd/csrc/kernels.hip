@@ -100,6 +100,27 @@ __device__ __forceinline__ int32_t hterm(const RoundArgs &A, const SearchDesc &s
     return (int32_t)(sd.kind == K_BIDA_F ? ht - hs : hs - ht);
 }
 
+// hterm through the memo: the query's forward term is read when this wave's
+// epoch wrote it, else computed from the coordinates and stored. The two
+// searches of a query share the word (the backward term is its negation);
+// a racing write stores the same value, and a write not yet visible is a miss.
+__device__ __forceinline__ int32_t hterm_memo(const RoundArgs &A, const SearchDesc &sd, uint32_t i, uint32_t v) {
+    if (sd.kind == K_DIST || sd.kind == K_2DIST) return 0;
+    if (!A.memo) return hterm(A, sd, v);
+    uint64_t *m = A.memo + (uint64_t)(A.G == 2 ? (i >> 1) : i) * A.n + v;
+    const uint64_t w = *m;
+    int32_t h;
+    if ((uint32_t)(w >> 32) == A.epoch) {
+        h = (int32_t)(uint32_t)w;
+    } else {
+        const int2 p = A.xy[v];
+        const int64_t ht = (int64_t)heur(p.x, p.y, sd.tx, sd.ty, A.ws2, A.fb);
+        h = sd.kind == K_ASTAR ? (int32_t)ht : (int32_t)(ht - (int64_t)heur(p.x, p.y, sd.sx, sd.sy, A.ws2, A.fb));
+        *m = ((uint64_t)A.epoch << 32) | (uint32_t)h;
+    }
+    return sd.kind == K_BIDA_B ? -h : h;
+}
+
 __device__ __forceinline__ void mu_update(const RoundArgs &A, uint32_t pair, uint64_t sum, uint32_t v) {
     if (sum >= INF32) { atomicOr(A.err, ERR_OVERFLOW); return; }
     unsigned long long *mp = (unsigned long long *)(A.mu + pair);
@@ -201,7 +222,7 @@ __device__ __forceinline__ bool relax_arc(const RoundArgs &A, const SearchDesc &
     } else {
         meet_list(A, sd, (uint32_t)cand, v);
     }
-    const int32_t hk = hterm(A, sd, v);
+    const int32_t hk = hterm_memo(A, sd, i, v);
     const uint64_t kv = key_of(sd.kind, cand, hk);
     if (kv >= bnd) return false;        // Prune(v) before Add(v)
     if (kv < *lmin) *lmin = kv;
@@ -424,6 +445,48 @@ __global__ __launch_bounds__(WAVE) void k_round(RoundArgs A) {
         adv.rb[lane_id()] = rb;
         adv.bnd[lane_id()] = bnd;
         __syncthreads();
+        if (A.pull) {
+            // Pull (Appendix B, undirected graphs): delta[u] <- min over the
+            // arcs (v, u) of delta[v] + w before u pushes, as an LDS minimum
+            // per extracted vertex; a lower value is written back (WriteMin)
+            // and met against the partner copies, then pushed.
+            for (uint32_t a0 = 0; a0 < T; a0 += WAVE) {
+                const uint32_t a = a0 + lane_id();
+                if (a < T) {
+                    uint32_t lo = 0, hi = WAVE;
+                    while (hi - lo > 1) {
+                        const uint32_t mid = (lo + hi) >> 1;
+                        if (adv.off[mid] <= a) lo = mid; else hi = mid;
+                    }
+                    const uint2 e = A.arcs[adv.rb[lo] + (a - adv.off[lo])];
+                    const uint32_t dv = (uint32_t)(A.S[state_index(A.G, A.n, adv.i[lo], e.x)] >> 32);
+                    if (dv != INF32 && (uint64_t)dv + e.y < adv.du[lo]) atomicMin(&adv.du[lo], dv + e.y);
+                }
+            }
+            __syncthreads();
+            const uint32_t k = lane_id();
+            if (deg && adv.du[k] < du) {
+                // Written with the entry's own stamp, not this round's: the
+                // round stamp would tell a later lowering of u in this round
+                // that u is already in the next frontier, and it is not (it is
+                // being pushed now), so that lowering must add it.
+                const uint32_t nd = adv.du[k];
+                const uint64_t old = atomicMin((unsigned long long *)(A.S + state_index(A.G, A.n, si, ent.y)),
+                                               ((uint64_t)nd << 32) | ent.z);
+                if (nd < (uint32_t)(old >> 32)) {
+                    const SearchDesc sd = A.sd[si];
+                    if (A.G == 2) {
+                        const uint32_t dp = (uint32_t)(A.S[state_index(2, A.n, si ^ 1u, ent.y)] >> 32);
+                        if (dp != INF32) mu_update(A, A.partners[sd.pbeg].pair, (uint64_t)nd + dp, ent.y);
+                    } else {
+                        meet_list(A, sd, nd, ent.y);
+                    }
+                } else {
+                    adv.du[k] = (uint32_t)(old >> 32) < du ? (uint32_t)(old >> 32) : du;
+                }
+            }
+            __syncthreads();
+        }
         for (uint32_t a0 = 0; a0 < T; a0 += WAVE) {
             const uint32_t a = a0 + lane_id();
             bool app = false;

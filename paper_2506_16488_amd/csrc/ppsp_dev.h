@@ -179,6 +179,12 @@ struct RoundArgs {
     // always qualifies, so every round makes progress.
     uint64_t *hlim;            // [nsearch]
     uint32_t hwin;             // window divisor for heavy vertices (1 = the whole window)
+    // Memoised heuristic (Section 5): per query slot, per vertex, the word
+    // (epoch << 32 | forward term h_t - h_s, or h_t for one-sided A*); a word
+    // from another epoch is a miss. Null: computed on every use.
+    uint64_t *memo;
+    uint32_t epoch;
+    uint32_t pull;             // 1: pull relaxation before pushing (Appendix B)
 };
 
 // Only the first ML_SAMPLE workgroups of the round kernels update the

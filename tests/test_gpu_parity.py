@@ -315,3 +315,48 @@ def test_autotune_changes_speed_not_results(P, tmp_path):
     assert r2["from_cache"] == 1 and r2["delta"] == r["delta"] and r2["theta_mode"] == r["theta_mode"]
     assert np.array_equal(G2.batch_query(pairs, algo="bidastar", sched="autotuned"), exp)
     G2.close()
+
+
+def test_memoised_heuristic_same_results(P):
+    """PPSP_MEMO_H (Section 5): the per-query memo of the heuristic changes
+    nothing in the results, across waves (the epoch tag) and batch modes."""
+    g = gen.lattice(150, 0.05, seed=61)
+    pairs = gen.pairs_uniform(g.n, 80, seed=62)
+    exp = _oracle(g, pairs)
+    G = _graph(P, g)
+    for algo in ["astar", "bidastar"]:
+        for batch in ["plainstar", "plain"]:
+            for _ in range(2):
+                got = G.batch_query(pairs, algo=algo, batch=batch, memo=True)
+                assert np.array_equal(got, exp), (algo, batch)
+        dist, (off, vtx) = G.batch_query(pairs[:20], algo=algo, memo=True, want_path=True)
+        _check_paths(g, pairs[:20], dist, off, vtx)
+    # several memory waves share the memo through the epoch tag
+    G.set_option("mem_budget_mb", 1)
+    assert np.array_equal(G.batch_query(pairs, algo="bidastar", memo=True), exp)
+    assert G.stats()["waves"] > 1
+    assert G.query(int(pairs[3, 0]), int(pairs[3, 1]), algo="bidastar", memo=True) == int(exp[3])
+    G.close()
+
+
+@pytest.mark.parametrize("graph", ["lattice", "rmat", "random"])
+def test_pull_relaxation_same_results(P, graph):
+    """PPSP_PULL (Appendix B): pulling before pushing changes nothing in the
+    results, in every mode and batch strategy, with hubs and unreachable pairs."""
+    if graph == "lattice":
+        g = gen.lattice(120, 0.1, seed=71)
+    elif graph == "rmat":
+        g = gen.rmat(12, 16, seed=72)
+    else:
+        g = gen.random_graph(2000, 3000, 300, seed=73)
+    pairs = gen.pairs_uniform(g.n, 60, seed=74)
+    exp = _oracle(g, pairs)
+    G = _graph(P, g)
+    algos = ALGOS_GEO if graph == "lattice" else ALGOS_PLAIN
+    for algo in algos:
+        assert np.array_equal(G.batch_query(pairs, algo=algo, pull=True), exp), algo
+    assert np.array_equal(G.batch_query(pairs, algo="bids", batch="multi", pull=True), exp)
+    assert np.array_equal(G.batch_query(pairs, algo="sssp", batch="vc", pull=True), exp)
+    dist, (off, vtx) = G.batch_query(pairs[:20], algo="bids", pull=True, want_path=True)
+    _check_paths(g, pairs[:20], dist, off, vtx)
+    G.close()
