@@ -82,7 +82,10 @@ enum ppsp_batch {
 enum ppsp_sched {
     PPSP_SCHED_FIXED = 0,      /* Delta*-stepping with opts.delta (0: graph default) */
     PPSP_SCHED_AUTOTUNED = 1,  /* the Delta and launch shape chosen by ppsp_tune (defaults until then) */
-    PPSP_SCHED_LEARNED = 2     /* per-round Delta multiplier chosen by the loaded MLP */
+    PPSP_SCHED_LEARNED = 2,    /* per-round Delta multiplier chosen by the loaded MLP */
+    PPSP_SCHED_RHO = 3         /* rho-stepping style (Section 2): each search's step is halved when its
+                                  next frontier holds more than 2 rho entries and doubled below rho / 2
+                                  (multipliers 2^-4 .. 2^3 of Delta; option "rho", default 4096) */
 };
 
 /* ppsp_graph_create flags. */
@@ -351,7 +354,9 @@ int ppsp_last_stats(ppsp_graph g, ppsp_stats *stats);
  *                     (raised to the smallest frontier key when a step would be
  *                     empty); 1: the threshold is the end of the Delta-wide bucket
  *                     holding the smallest frontier key (Delta-stepping buckets);
- *                     2 (default): the smallest frontier key + Delta - 1
+ *                     2 (default): the smallest frontier key + Delta - 1;
+ *                     3: infinite (every frontier entry is extracted each round: the
+ *                     Bellman-Ford instance of the stepping framework)
  *   "use_graph"       1: replay rounds through a captured hipGraph
  *   "timeout_ms"      host-side limit on one wave's round loop (0 = none)
  *   "queue_cap"       frontier queue capacity in entries (grows x4, with a rerun of
@@ -364,6 +369,7 @@ int ppsp_last_stats(ppsp_graph g, ppsp_stats *stats);
  *   "multi_group"     Multi-BiDS state layout: this many consecutive query-graph vertices
  *                     keep their words of a vertex side by side (a power of two up to 64;
  *                     default 32; 1 = search-major)
+ *   "rho"             target next-frontier size per search of PPSP_SCHED_RHO (default 4096)
  *   "ml_every"        rounds between evaluations of the learned schedule's network (default 4;
  *                     a search keeps its multiplier in between)
  * Returns PPSP_E_INVALID for an unknown name.

@@ -28,7 +28,7 @@ OK, E_INVALID, E_RANGE, E_OOM, E_OVERFLOW, E_NOCOORD, E_NOTSYM, E_DEVICE, E_BUSY
 
 ALGO = {"sssp": 0, "et": 1, "astar": 2, "bids": 3, "bidastar": 4}
 BATCH = {"plain": 0, "plainstar": 1, "multi": 2, "sssp": 3, "vc": 4, "auto": 5}
-SCHED = {"fixed": 0, "autotuned": 1, "learned": 2}
+SCHED = {"fixed": 0, "autotuned": 1, "learned": 2, "rho": 3}
 SYMMETRIC = 1
 WANT_PATH = 1
 MEMO_H = 2

@@ -157,7 +157,7 @@ struct ppsp_graph_s {
     // options
     int64_t opt_profile = 0, opt_rounds_per_sync = 16, opt_grid_blocks = 0, opt_mem_budget_mb = 0,
             opt_default_delta = 0, opt_use_graph = 0, opt_timeout_ms = 600000, opt_theta_mode = 2, opt_queue_cap = 0,
-            opt_ml_every = 4, opt_heavy_window = 64, opt_multi_group = 32;
+            opt_ml_every = 4, opt_heavy_window = 64, opt_multi_group = 32, opt_rho = 4096;
     uint64_t wmean = 1;             // mean arc weight (rounded up)
     uint64_t fingerprint = 0;       // hash of the CSR, keys the tuning cache
     struct Tuned {
@@ -271,6 +271,7 @@ void set_args(ppsp_graph g, RoundArgs &A, uint32_t nsearch, uint32_t npair, uint
         A.trace_n = g->trace_n.as<unsigned long long>();
         A.deg_feat = g->n ? (float)(std::log2(std::max(1.0, (double)g->m / g->n)) / 4.0) : 0.f;
         A.ml_every = (uint32_t)std::max<int64_t>(1, g->opt_ml_every);
+        A.rho = (uint32_t)g->opt_rho;
     }
     A.grid = g->opt_grid_blocks > 0 ? (uint32_t)g->opt_grid_blocks : (uint32_t)(24 * g->cu);
 }
@@ -543,6 +544,7 @@ void plan_single(ppsp_graph g, Plan &P, uint32_t s, uint32_t t, uint32_t algo, u
         const uint32_t kf = algo == PPSP_BIDS ? K_2DIST : K_BIDA_F;
         const uint32_t kb = algo == PPSP_BIDS ? K_2DIST : K_BIDA_B;
         SearchDesc f = make_sd(g, s, kf, s, t), b = make_sd(g, t, kb, s, t);
+        b.rev = g->symmetric ? 0u : 1u;      // on a directed graph the backward search walks the transpose
         f.pbeg = (uint32_t)P.partners.size();
         P.partners.push_back({a + 1, pair});
         f.pend = (uint32_t)P.partners.size();
@@ -569,9 +571,12 @@ void plan_single(ppsp_graph g, Plan &P, uint32_t s, uint32_t t, uint32_t algo, u
 
 int check_opts(ppsp_graph g, const ppsp_opts *o) {
     if (!o) return PPSP_E_INVALID;
-    if (o->algo > PPSP_BIDASTAR || o->batch > PPSP_BATCH_AUTO || o->sched > PPSP_SCHED_LEARNED) return PPSP_E_INVALID;
+    if (o->algo > PPSP_BIDASTAR || o->batch > PPSP_BATCH_AUTO || o->sched > PPSP_SCHED_RHO) return PPSP_E_INVALID;
     if (is_astar(o->algo) && !g->xy_ok) return PPSP_E_NOCOORD;
-    if (is_bidir(o->algo) && !g->symmetric) return PPSP_E_NOTSYM;
+    // directed graphs: bidirectional searches run their backward half on the
+    // transpose (Plain, Plain*, single queries); the query-graph strategies
+    // assume an undirected query graph
+    if (!g->symmetric && (o->batch == PPSP_BATCH_MULTI || o->batch == PPSP_BATCH_AUTO)) return PPSP_E_NOTSYM;
     if ((o->batch == PPSP_BATCH_MULTI || o->batch == PPSP_BATCH_AUTO) && o->algo != PPSP_BIDS) return PPSP_E_INVALID;
     if ((o->batch == PPSP_BATCH_SSSP || o->batch == PPSP_BATCH_VC) && o->algo != PPSP_SSSP) return PPSP_E_INVALID;
     if (o->batch == PPSP_BATCH_VC && !g->symmetric) return PPSP_E_NOTSYM;
@@ -922,8 +927,8 @@ int batch_impl(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp_opts 
         bool set;
         ~MlRestore() { if (set) g->ml = nullptr; }
     } mlrestore{g, false};
-    if (o->sched == PPSP_SCHED_LEARNED && !g->ml) {
-        learned.mode = 2;
+    if ((o->sched == PPSP_SCHED_LEARNED || o->sched == PPSP_SCHED_RHO) && !g->ml) {
+        learned.mode = o->sched == PPSP_SCHED_LEARNED ? 2 : 3;
         g->ml = &learned;
         mlrestore.set = true;
     }
@@ -1860,11 +1865,12 @@ int ppsp_set_option(ppsp_graph g, const char *name, int64_t v) {
     else if (k == "default_delta") { if (v < 0) return PPSP_E_INVALID; g->opt_default_delta = v; }
     else if (k == "use_graph") g->opt_use_graph = v;
     else if (k == "timeout_ms") { if (v < 0) return PPSP_E_INVALID; g->opt_timeout_ms = v; }
-    else if (k == "theta_mode") { if (v < 0 || v > 2) return PPSP_E_INVALID; g->opt_theta_mode = v; }
+    else if (k == "theta_mode") { if (v < 0 || v > 3) return PPSP_E_INVALID; g->opt_theta_mode = v; }
     else if (k == "queue_cap") { if (v < (int64_t)NSEG || v > (1ll << 31)) return PPSP_E_INVALID; g->qcap = (uint64_t)v; g->opt_queue_cap = v; }
     else if (k == "heavy_cap") { if (v < 1 || v > (1ll << 28)) return PPSP_E_INVALID; g->hcap = (uint32_t)v; }
     else if (k == "ml_every") { if (v < 1 || v > 1024) return PPSP_E_INVALID; g->opt_ml_every = v; }
     else if (k == "heavy_window") { if (v < 1 || v > 4096) return PPSP_E_INVALID; g->opt_heavy_window = v; }
+    else if (k == "rho") { if (v < 1 || v > (1ll << 31)) return PPSP_E_INVALID; g->opt_rho = v; }
     else if (k == "multi_group") {
         if (v < 1 || v > 64 || (v & (v - 1))) return PPSP_E_INVALID;
         g->opt_multi_group = v;
@@ -1890,6 +1896,7 @@ int ppsp_get_option(ppsp_graph g, const char *name, int64_t *v) {
     else if (k == "ml_every") *v = g->opt_ml_every;
     else if (k == "heavy_window") *v = g->opt_heavy_window;
     else if (k == "multi_group") *v = g->opt_multi_group;
+    else if (k == "rho") *v = g->opt_rho;
 
     else return PPSP_E_INVALID;
     return PPSP_OK;

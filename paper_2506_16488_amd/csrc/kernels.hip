@@ -196,7 +196,7 @@ __device__ __forceinline__ void wave_add_keyed(unsigned long long *ctr, uint32_t
 __device__ __forceinline__ bool relax_arc(const RoundArgs &A, const SearchDesc &sd, uint32_t i, uint32_t u,
                                           uint32_t du, uint64_t bnd, uint32_t e, uint32_t stamp, uint4 *out,
                                           uint64_t *lmin, unsigned long long *succ) {
-    const uint2 a = A.arcs[e];
+    const uint2 a = (sd.rev ? A.in_arcs : A.arcs)[e];
     const uint32_t v = a.x;
     const uint64_t cand = (uint64_t)du + a.y;
     if (cand >= INF32) { atomicOr(A.err, ERR_OVERFLOW); return false; }
@@ -368,9 +368,10 @@ __global__ __launch_bounds__(WAVE) void k_round(RoundArgs A) {
                         action = 1;                     // above the threshold: later round
                     } else {
                         bool wait = false;
+                        const uint32_t *rp = sd.rev ? A.in_row_ptr : A.row_ptr;
                         if (A.hcap && key < bnd && key > A.hlim[i]) {
-                            rb = A.row_ptr[u];
-                            re = A.row_ptr[u + 1];
+                            rb = rp[u];
+                            re = rp[u + 1];
                             wait = re - rb > HEAVY_DEG;   // a hub above the low end of the window
                         }
                         if (wait) {
@@ -383,8 +384,8 @@ __global__ __launch_bounds__(WAVE) void k_round(RoundArgs A) {
                             }
                             if (key < bnd) {
                                 action = 2;
-                                rb = A.row_ptr[u];
-                                re = A.row_ptr[u + 1];
+                                rb = rp[u];
+                                re = rp[u + 1];
                                 c_sv++;
                                 c_se += re - rb;
                             }
@@ -633,6 +634,7 @@ __device__ __forceinline__ int control_search(const RoundArgs &A, uint32_t i, ui
 // frontier and the step Delta d (key units).
 __device__ __forceinline__ uint64_t step_threshold(uint32_t mode, uint64_t th0, uint64_t mk, uint64_t d) {
     uint64_t th;
+    if (mode == 3) return INF64;     // Bellman-Ford: extract everything every round
     if (mode == 0 || mk == INF64) {
         // Delta*-stepping: the i-th threshold is i * Delta; steps that would
         // extract nothing are skipped by raising it to the smallest key.
@@ -791,6 +793,11 @@ __global__ __launch_bounds__(WAVE) void k_control_ml(RoundArgs A) {
             float z1, h1, z2, h2, lg[MLP_K];
             mlp_forward(L, f, z1, h1, z2, h2, lg);
             bin = mlp_argmax(lg);
+        } else if (A.ml_mode == 3) {
+            // rho-stepping style: steer the next frontier towards rho entries
+            const double nx = scale * (double)nxt;
+            if (nx > 2.0 * A.rho && bin > 0) bin--;
+            else if (nx < 0.5 * A.rho && bin < (uint32_t)MLP_K - 1) bin++;
         }
         if (w) {
             if (A.trace) {
@@ -885,11 +892,15 @@ __device__ __forceinline__ uint32_t dist_of(const RoundArgs &A, uint32_t i, uint
 
 // A predecessor of v on a shortest path from the root of search i: an
 // in-neighbour p with delta[p] + w(p,v) = delta[v] (exists for every exact
-// v != root; see ppsp_dev.h), or INF32.
+// v != root; see ppsp_dev.h), or INF32. A search over the reversed graph
+// takes its predecessors among the out-neighbours.
 __device__ uint32_t tight_pred(const RoundArgs &A, uint32_t i, uint32_t v) {
     const uint32_t dv = dist_of(A, i, v);
-    for (uint32_t e = A.in_row_ptr[v]; e < A.in_row_ptr[v + 1]; e++) {
-        const uint2 a = A.in_arcs[e];
+    const bool rev = A.sd[i].rev != 0;
+    const uint32_t *rp = rev ? A.row_ptr : A.in_row_ptr;
+    const uint2 *arcs = rev ? A.arcs : A.in_arcs;
+    for (uint32_t e = rp[v]; e < rp[v + 1]; e++) {
+        const uint2 a = arcs[e];
         const uint32_t dp = dist_of(A, i, a.x);
         if (dp != INF32 && (uint64_t)dp + a.y == dv) return a.x;
     }

@@ -84,7 +84,8 @@ struct SearchDesc {
     int32_t tx, ty;     // coordinates of the target t (h_t), A* kinds only
     int32_t sx, sy;     // coordinates of the source s (h_s), bidirectional A* only
     uint32_t noprune;   // 1: never prune (plain single-source search)
-    uint32_t pad;
+    uint32_t rev;       // 1: the search walks arcs backwards (the transpose), as the backward
+                        //    search of a bidirectional query on a directed graph does
 };
 
 // One query the search takes part in: the other endpoint (a search index, or
@@ -160,7 +161,9 @@ struct RoundArgs {
     // a round is its base Delta times 2^(bin[i] - 4).
     unsigned long long *sc;    // [2][nsearch][2] per-search counters of a round, by round parity:
                                //   (arcs of extracted vertices << 32) + extracted vertices; entries for the next frontier
-    uint32_t ml_mode;          // 1: bins fixed per search (tracing), 2: the network picks them
+    uint32_t ml_mode;          // 1: bins fixed per search (tracing), 2: the network picks them,
+                               // 3: a rule steers each search's next frontier towards rho entries
+    uint32_t rho;
     const uint16_t *mlp;       // network parameters in bf16 (layout in mlp_dev.h)
     uint8_t *bin;              // [nsearch] multiplier bin of the search's next round
     uint32_t *done_round;      // [nsearch] rounds the search ran

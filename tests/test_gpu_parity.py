@@ -201,8 +201,10 @@ def test_error_paths(P):
     d = gen.csr_from_edges(3, [0, 1], [1, 2], [1, 1], symmetric=False)
     D = P.Graph(d.n, d.row_ptr, d.col, d.w, symmetric=False)
     with pytest.raises(P.PPSPError) as e:
-        D.query(0, 2, algo="bids")
-    assert e.value.code == P.E_NOTSYM
+        D.batch_query(np.array([[0, 2]]), algo="bids", batch="multi")
+    assert e.value.code == P.E_NOTSYM                      # the query-graph strategies need symmetry
+    assert D.query(0, 2, algo="bids") == 2                  # the backward search walks the transpose
+    assert D.query(2, 0, algo="bids") == INF
     assert D.query(0, 2, algo="et") == 2
     assert D.query(2, 0, algo="et") == INF                 # directed: unreachable backwards
     D.close()
@@ -360,3 +362,86 @@ def test_pull_relaxation_same_results(P, graph):
     dist, (off, vtx) = G.batch_query(pairs[:20], algo="bids", pull=True, want_path=True)
     _check_paths(g, pairs[:20], dist, off, vtx)
     G.close()
+
+
+@pytest.mark.parametrize("graph", ["lattice", "rmat"])
+def test_bellman_ford_and_rho_schedules(P, graph):
+    """The Bellman-Ford threshold (theta = infinity) and the rho-stepping-style
+    schedule are stepping rules too: identical distances (Section 2)."""
+    g = gen.lattice(100, 0.1, seed=81) if graph == "lattice" else gen.rmat(12, 16, seed=82)
+    pairs = gen.pairs_uniform(g.n, 50, seed=83)
+    exp = _oracle(g, pairs)
+    G = _graph(P, g)
+    algos = ["bids", "et", "sssp", "bidastar", "astar"] if graph == "lattice" else ["bids", "et", "sssp"]
+    G.set_option("theta_mode", 3)
+    for algo in algos:
+        assert np.array_equal(G.batch_query(pairs, algo=algo), exp), ("bf", algo)
+    bf_rounds = G.stats()["rounds"]
+    G.set_option("theta_mode", 2)
+    for rho in (16, 4096):
+        G.set_option("rho", rho)
+        for algo in algos:
+            assert np.array_equal(G.batch_query(pairs, algo=algo, sched="rho"), exp), ("rho", rho, algo)
+    assert np.array_equal(G.batch_query(pairs, algo="bids", batch="multi", sched="rho"), exp)
+    assert bf_rounds > 0
+    G.close()
+
+
+def _directed_lattice(L, seed):
+    """A lattice whose two directions of every edge carry independent extra
+    weight (w >= 1000 * length still holds, so the heuristic stays consistent)."""
+    g = gen.lattice(L, 0.1, seed=seed)
+    rng = np.random.default_rng(seed + 1)
+    w = g.w.astype(np.int64) + rng.integers(0, 800, g.w.shape[0])
+    return g, w.astype(np.uint32)
+
+
+def test_directed_bidirectional_searches(P):
+    """Bidirectional search on directed graphs: the backward search runs on
+    the transpose; distances and paths against the oracle on the same arcs."""
+    g, w = _directed_lattice(90, 91)
+    pairs = gen.pairs_uniform(g.n, 60, seed=92)
+    exp = oracle.pp_batch(g.n, g.row_ptr, g.col, w, pairs)
+    rev = oracle.pp_batch(g.n, g.row_ptr, g.col, w, pairs[:, ::-1].copy())
+    assert not np.array_equal(exp, rev)                   # the graph really is directed
+    G = P.Graph(g.n, g.row_ptr, g.col, w, coords=g.coords, frac_bits=g.frac_bits, symmetric=False)
+    G.set_option("timeout_ms", 60000)
+    for algo in ["bids", "bidastar", "et", "astar", "sssp"]:
+        for batch in ["plainstar", "plain"]:
+            assert np.array_equal(G.batch_query(pairs, algo=algo, batch=batch), exp), (algo, batch)
+    assert np.array_equal(G.batch_query(pairs[:, ::-1].copy(), algo="bidastar"), rev)
+    for algo in ["bids", "bidastar"]:
+        dist, (off, vtx) = G.batch_query(pairs[:25], algo=algo, want_path=True)
+        for q in range(25):
+            s0, t0 = int(pairs[q, 0]), int(pairs[q, 1])
+            assert oracle.check_path(g.n, g.row_ptr, g.col, w, vtx[off[q]:off[q + 1]], s0, t0, int(dist[q])) == (0, 0)
+    G.close()
+    # random directed graph with unreachable pairs and (at this size) no hubs
+    d = gen.random_graph(3000, 9000, 200, seed=93, symmetric=False)
+    pairs = gen.pairs_uniform(d.n, 80, seed=94)
+    exp = oracle.pp_batch(d.n, d.row_ptr, d.col, d.w, pairs)
+    assert np.any(exp == INF)
+    D = P.Graph(d.n, d.row_ptr, d.col, d.w, symmetric=False)
+    for algo in ["bids", "et"]:
+        assert np.array_equal(D.batch_query(pairs, algo=algo), exp), algo
+    D.close()
+
+
+def test_directed_hubs_heavy_path(P):
+    """Directed graph with hubs (a random half of an R-MAT graph's arcs): the
+    heavy list of a backward search indexes the transpose."""
+    r = gen.rmat(12, 16, seed=95)
+    src = np.repeat(np.arange(r.n, dtype=np.int64), np.diff(r.row_ptr.astype(np.int64)))
+    keep = np.random.default_rng(96).random(src.shape[0]) < 0.5
+    d = gen.csr_from_edges(r.n, src[keep], r.col[keep].astype(np.int64), r.w[keep].astype(np.int64), symmetric=False)
+    assert np.max(np.diff(d.row_ptr.astype(np.int64))) > 512
+    pairs = gen.pairs_uniform(d.n, 60, seed=97)
+    exp = oracle.pp_batch(d.n, d.row_ptr, d.col, d.w, pairs)
+    D = P.Graph(d.n, d.row_ptr, d.col, d.w, symmetric=False)
+    D.set_option("timeout_ms", 60000)
+    for algo in ["bids", "et", "sssp"]:
+        assert np.array_equal(D.batch_query(pairs, algo=algo), exp), algo
+    dist, (off, vtx) = D.batch_query(pairs[:20], algo="bids", want_path=True)
+    assert np.array_equal(dist, exp[:20])
+    _check_paths(d, pairs[:20], dist, off, vtx)
+    D.close()
