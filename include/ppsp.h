@@ -258,11 +258,17 @@ int ppsp_tune(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp_opts *
  *                   the pair each row belongs to; *nrows = rows produced,
  *                   possibly more than cap) and per pair the rounds its
  *                   searches ran and the arcs they scanned.
- * ppsp_mlp_fit      the whole training recipe on sample pairs: labels by
- *                   timing every pair alone under each of the 8 fixed
- *                   multipliers (the fastest wins), feature rows traced along
- *                   the labelled and the default trajectories, training from
- *                   `init` (caller-drawn), then ppsp_mlp_load.
+ * ppsp_mlp_fit      the whole training recipe on sample pairs, then
+ *                   ppsp_mlp_load. Labels: label_mode 0 times every pair
+ *                   alone under each of the 8 fixed multipliers (the fastest
+ *                   wins); label_mode 1 runs the sample batch under each fixed
+ *                   multiplier, fits batch time = c0 + c_round * rounds +
+ *                   c_arc * arcs, and labels a pair with the bin minimising
+ *                   c_arc * its arcs + c_round * its rounds beyond the best
+ *                   fixed batch's (rounds that end before the batch does are
+ *                   free). Feature rows are traced along the labelled and the
+ *                   default trajectories; training starts from `init`
+ *                   (caller-drawn).
  * Errors: PPSP_E_INVALID (null pointers, label >= 8, a non-finite
  * parameter, a strategy other than Plain / Plain* for tracing or fitting),
  * the errors of ppsp_batch_query.
@@ -279,6 +285,9 @@ typedef struct {
     double train_acc;         /* fraction of rows whose argmax is the label */
     double label_ms;          /* time spent labelling */
     double train_ms;          /* time spent training */
+    double c_round_ms;        /* label_mode 1: fitted cost of a batch round (ms) */
+    double c_arc_ns;          /* label_mode 1: fitted cost of a scanned arc (ns) */
+    uint32_t best_fixed_bin;  /* label_mode 1: the fastest fixed multiplier bin for the sample batch */
 } ppsp_fit_report;
 
 int ppsp_mlp_forward(int device, const float *params, const float *x, uint32_t n, float *logits);
@@ -291,7 +300,7 @@ int ppsp_sched_trace(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp
                      float *feat, uint32_t *row_pair, uint64_t cap, uint64_t *nrows, uint32_t *pair_rounds,
                      uint64_t *pair_arcs);
 int ppsp_mlp_fit(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp_opts *opts, const float *init,
-                 uint32_t epochs, uint64_t seed, float *params_out, ppsp_fit_report *rep);
+                 uint32_t epochs, uint64_t seed, uint32_t label_mode, float *params_out, ppsp_fit_report *rep);
 
 /*
  * Serving (continuous batching). A server owns one or more resident graphs

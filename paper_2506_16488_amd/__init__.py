@@ -80,7 +80,8 @@ class ServerCounters(ctypes.Structure):
 class FitReport(ctypes.Structure):
     _fields_ = [("label_hist", ctypes.c_uint32 * 8), ("rows", ctypes.c_uint64), ("loss_first", ctypes.c_double),
                 ("loss_last", ctypes.c_double), ("train_acc", ctypes.c_double), ("label_ms", ctypes.c_double),
-                ("train_ms", ctypes.c_double)]
+                ("train_ms", ctypes.c_double), ("c_round_ms", ctypes.c_double), ("c_arc_ns", ctypes.c_double),
+                ("best_fixed_bin", ctypes.c_uint32)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}
@@ -155,7 +156,7 @@ def lib():
                                      ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
         L.ppsp_mlp_load.argtypes = [P, P]
         L.ppsp_sched_trace.argtypes = [P, P, u32, ctypes.POINTER(Opts), P, P, P, u64, ctypes.POINTER(u64), P, P]
-        L.ppsp_mlp_fit.argtypes = [P, P, u32, ctypes.POINTER(Opts), P, u32, u64, P, ctypes.POINTER(FitReport)]
+        L.ppsp_mlp_fit.argtypes = [P, P, u32, ctypes.POINTER(Opts), P, u32, u64, u32, P, ctypes.POINTER(FitReport)]
         for f in ("forward", "grad", "train", "load", "fit"):
             getattr(L, "ppsp_mlp_" + f).restype = ctypes.c_int
         L.ppsp_sched_trace.restype = ctypes.c_int
@@ -382,15 +383,17 @@ class Graph:
         kept = min(int(nrows.value), cap)
         return feat[:kept], rowp[:kept], int(nrows.value), pr, pa
 
-    def mlp_fit(self, pairs, init, algo="bids", batch="plainstar", epochs=20, seed=0, delta=0):
-        """Labels, traces, trains and loads the learned schedule; returns
-        (parameters, report dict)."""
+    def mlp_fit(self, pairs, init, algo="bids", batch="plainstar", epochs=20, seed=0, delta=0, labels="single"):
+        """Labels ("single": each pair timed alone; "batch": batch-aware),
+        traces, trains and loads the learned schedule; returns (parameters,
+        report dict)."""
         pairs = np.ascontiguousarray(pairs, np.uint32).reshape(-1, 2)
         p0 = _f32(init, (MLP_PARAMS,))
         out = np.empty(MLP_PARAMS, np.float32)
         rep = FitReport()
+        mode = {"single": 0, "batch": 1}[labels]
         _check(lib().ppsp_mlp_fit(self.h, _ptr(pairs), pairs.shape[0], ctypes.byref(make_opts(algo, batch, delta=delta)),
-                                  _ptr(p0), int(epochs), int(seed), _ptr(out), ctypes.byref(rep)), "ppsp_mlp_fit")
+                                  _ptr(p0), int(epochs), int(seed), mode, _ptr(out), ctypes.byref(rep)), "ppsp_mlp_fit")
         return out, rep.as_dict()
 
     def set_option(self, name, value):

@@ -2067,20 +2067,95 @@ int ppsp_sched_trace(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp
     return PPSP_OK;
 }
 
+// Batch-aware labels: the sample batch under each fixed multiplier gives its
+// wall time and, per pair, rounds and arcs. Batch time is fitted as
+// c0 + c_round * rounds + c_arc * arcs; a pair's label is the bin that
+// minimises c_arc * its arcs + c_round * its rounds beyond those of the best
+// fixed batch (rounds that end before the batch does cost nothing).
+int batch_labels(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp_opts *opts, std::vector<uint8_t> &y,
+                 ppsp_fit_report &R) {
+    std::vector<std::vector<uint32_t>> pr(MLP_K);
+    std::vector<std::vector<uint64_t>> pa(MLP_K);
+    double T[MLP_K], Rb[MLP_K], Ab[MLP_K];
+    for (uint8_t b = 0; b < MLP_K; b++) {
+        const std::vector<uint8_t> bins(k, b);
+        double best = 1e300;
+        for (int rep = 0; rep < 2; rep++) {
+            MlCtx c;
+            std::vector<uint32_t> rp;
+            const auto a = std::chrono::steady_clock::now();
+            CHK(trace_impl(g, pairs, k, opts, bins.data(), false, 0, c, rp, pr[b], pa[b]));
+            best = std::min(best, std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - a).count());
+        }
+        T[b] = best;
+        Rb[b] = *std::max_element(pr[b].begin(), pr[b].end());
+        Ab[b] = 0;
+        for (uint64_t v : pa[b]) Ab[b] += (double)v;
+    }
+    // least squares T = c0 + c1 R + c2 A (normal equations, 3 x 3), coefficients kept >= 0
+    auto fit = [&](bool use_r, bool use_a, double &c0, double &c1, double &c2) {
+        double M[3][4] = {{0}};
+        for (int b = 0; b < MLP_K; b++) {
+            const double x[3] = {1.0, use_r ? Rb[b] : 0.0, use_a ? Ab[b] : 0.0};
+            for (int r = 0; r < 3; r++) {
+                for (int c = 0; c < 3; c++) M[r][c] += x[r] * x[c];
+                M[r][3] += x[r] * T[b];
+            }
+        }
+        if (!use_r) { M[1][1] = 1; M[1][3] = 0; }
+        if (!use_a) { M[2][2] = 1; M[2][3] = 0; }
+        for (int c = 0; c < 3; c++) {
+            int piv = c;
+            for (int r = c + 1; r < 3; r++) if (std::fabs(M[r][c]) > std::fabs(M[piv][c])) piv = r;
+            for (int j = 0; j < 4; j++) std::swap(M[c][j], M[piv][j]);
+            if (std::fabs(M[c][c]) < 1e-30) continue;
+            for (int r = 0; r < 3; r++) {
+                if (r == c) continue;
+                const double f = M[r][c] / M[c][c];
+                for (int j = 0; j < 4; j++) M[r][j] -= f * M[c][j];
+            }
+        }
+        c0 = M[0][3] / M[0][0];
+        c1 = use_r ? M[1][3] / M[1][1] : 0.0;
+        c2 = use_a ? M[2][3] / M[2][2] : 0.0;
+    };
+    double c0, cr, ca;
+    fit(true, true, c0, cr, ca);
+    if (cr < 0) fit(false, true, c0, cr, ca);
+    if (ca < 0) fit(cr > 0, false, c0, cr, ca);
+    uint32_t bbest = 0;
+    for (uint32_t b = 1; b < (uint32_t)MLP_K; b++) if (T[b] < T[bbest]) bbest = b;
+    const double Rstar = Rb[bbest];
+    for (uint32_t i = 0; i < k; i++) {
+        double best = 1e300;
+        y[i] = (uint8_t)bbest;
+        for (uint32_t b = 0; b < (uint32_t)MLP_K; b++) {
+            const double cost = ca * (double)pa[b][i] + cr * std::max(0.0, (double)pr[b][i] - Rstar);
+            if (cost < best - 1e-12) { best = cost; y[i] = (uint8_t)b; }
+        }
+    }
+    R.c_round_ms = cr;
+    R.c_arc_ns = ca * 1e6;
+    R.best_fixed_bin = bbest;
+    return PPSP_OK;
+}
+
 int ppsp_mlp_fit(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp_opts *opts, const float *init,
-                 uint32_t epochs, uint64_t seed, float *params_out, ppsp_fit_report *rep) {
-    if (!g || !opts || !pairs || k == 0 || !init || !params_out) return PPSP_E_INVALID;
+                 uint32_t epochs, uint64_t seed, uint32_t label_mode, float *params_out, ppsp_fit_report *rep) {
+    if (!g || !opts || !pairs || k == 0 || !init || !params_out || label_mode > 1) return PPSP_E_INVALID;
     if (g->served) return PPSP_E_BUSY;
     if (opts->batch != PPSP_BATCH_PLAIN && opts->batch != PPSP_BATCH_PLAINSTAR) return PPSP_E_INVALID;
     CHK(check_opts(g, opts));
     ppsp_fit_report R{};
-    // 1. Labels: each pair alone under every fixed multiplier; the label is
-    //    the bin that finished it fastest (best of two runs).
     auto t0 = std::chrono::steady_clock::now();
     std::vector<uint8_t> y(k, (uint8_t)(MLP_K / 2));
     ppsp_opts one = *opts;
     one.batch = PPSP_BATCH_PLAIN;
-    for (uint32_t i = 0; i < k; i++) {
+    // 1. Labels. Mode 1: batch-aware (batch_labels). Mode 0: each pair alone
+    //    under every fixed multiplier; the label is the bin that finished it
+    //    fastest (best of two runs).
+    if (label_mode == 1) CHK(batch_labels(g, pairs, k, opts, y, R));
+    for (uint32_t i = 0; i < k && label_mode == 0; i++) {
         if (pairs[2 * i] == pairs[2 * i + 1]) continue;
         double best = 1e300;
         for (uint8_t b = 0; b < MLP_K; b++) {

@@ -165,4 +165,9 @@ def test_fit_recipe(P):
     exp = oracle.pp_batch(g.n, g.row_ptr, g.col, g.w, test)
     assert np.array_equal(G.batch_query(test, algo="bidastar", sched="learned"), exp)
     assert np.array_equal(G.batch_query(test, algo="bids", sched="learned"), exp)
+    # batch-aware labels: fitted costs are non-negative, the best fixed bin is reported
+    params, rep = G.mlp_fit(train, gen.mlp_init(85), algo="bidastar", epochs=5, seed=86, labels="batch")
+    assert sum(rep["label_hist"]) == 24 and 0 <= rep["best_fixed_bin"] < 8
+    assert rep["c_round_ms"] >= 0 and rep["c_arc_ns"] >= 0
+    assert np.array_equal(G.batch_query(test, algo="bidastar", sched="learned"), exp)
     G.close()
