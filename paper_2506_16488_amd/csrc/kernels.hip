@@ -193,10 +193,11 @@ __device__ __forceinline__ void wave_add_keyed(unsigned long long *ctr, uint32_t
 // whose stamp is `stamp`. Returns true if v^(i) must be added to the next
 // frontier; *out is that entry. *lmin takes the key of every unpruned
 // decrease (added now or by an earlier decrease of this round).
+template <bool MEMO, bool REV>
 __device__ __forceinline__ bool relax_arc(const RoundArgs &A, const SearchDesc &sd, uint32_t i, uint32_t u,
                                           uint32_t du, uint64_t bnd, uint32_t e, uint32_t stamp, uint4 *out,
                                           uint64_t *lmin, unsigned long long *succ) {
-    const uint2 a = (sd.rev ? A.in_arcs : A.arcs)[e];
+    const uint2 a = ((REV && sd.rev) ? A.in_arcs : A.arcs)[e];
     const uint32_t v = a.x;
     const uint64_t cand = (uint64_t)du + a.y;
     if (cand >= INF32) { atomicOr(A.err, ERR_OVERFLOW); return false; }
@@ -222,7 +223,7 @@ __device__ __forceinline__ bool relax_arc(const RoundArgs &A, const SearchDesc &
     } else {
         meet_list(A, sd, (uint32_t)cand, v);
     }
-    const int32_t hk = hterm_memo(A, sd, i, v);
+    const int32_t hk = MEMO ? hterm_memo(A, sd, i, v) : hterm(A, sd, v);
     const uint64_t kv = key_of(sd.kind, cand, hk);
     if (kv >= bnd) return false;        // Prune(v) before Add(v)
     if (kv < *lmin) *lmin = kv;
@@ -289,6 +290,7 @@ struct Advance {
 
 // One round. Workgroups are single waves that work independently (no
 // barriers between waves): each takes WAVE-entry chunks of its sub-queue.
+template <bool PULL, bool MEMO, bool REV>
 __global__ __launch_bounds__(WAVE) void k_round(RoundArgs A) {
     __shared__ WaveStage st;
     __shared__ Advance adv;
@@ -368,7 +370,7 @@ __global__ __launch_bounds__(WAVE) void k_round(RoundArgs A) {
                         action = 1;                     // above the threshold: later round
                     } else {
                         bool wait = false;
-                        const uint32_t *rp = sd.rev ? A.in_row_ptr : A.row_ptr;
+                        const uint32_t *rp = (REV && sd.rev) ? A.in_row_ptr : A.row_ptr;
                         if (A.hcap && key < bnd && key > A.hlim[i]) {
                             rb = rp[u];
                             re = rp[u + 1];
@@ -446,7 +448,7 @@ __global__ __launch_bounds__(WAVE) void k_round(RoundArgs A) {
         adv.rb[lane_id()] = rb;
         adv.bnd[lane_id()] = bnd;
         __syncthreads();
-        if (A.pull) {
+        if (PULL) {
             // Pull (Appendix B, undirected graphs): delta[u] <- min over the
             // arcs (v, u) of delta[v] + w before u pushes, as an LDS minimum
             // per extracted vertex; a lower value is written back (WriteMin)
@@ -502,7 +504,7 @@ __global__ __launch_bounds__(WAVE) void k_round(RoundArgs A) {
                 }
                 ai = adv.i[lo];
                 const SearchDesc sd = A.sd[ai];
-                app = relax_arc(A, sd, ai, adv.u[lo], adv.du[lo], adv.bnd[lo], adv.rb[lo] + (a - adv.off[lo]), stamp,
+                app = relax_arc<MEMO, REV>(A, sd, ai, adv.u[lo], adv.du[lo], adv.bnd[lo], adv.rb[lo] + (a - adv.off[lo]), stamp,
                                 &ne, &lmin, &c_succ);
             }
             wstage_push(st, scnt, app, ne, qout, qcout, A.qseg, A.err);
@@ -530,6 +532,7 @@ __global__ __launch_bounds__(WAVE) void k_round(RoundArgs A) {
 // The heavy list, relaxed by every wave of the grid: each wave takes whole
 // chunks (at most HEAVY_CHUNK arcs of one vertex), 64 arcs per step. Runs
 // after k_round in the same round.
+template <bool MEMO, bool REV>
 __global__ __launch_bounds__(WAVE) void k_heavy(RoundArgs A) {
     __shared__ WaveStage st;
     uint32_t scnt = 0;
@@ -553,7 +556,7 @@ __global__ __launch_bounds__(WAVE) void k_heavy(RoundArgs A) {
             bool app = false;
             uint4 ne = make_uint4(0, 0, 0, 0);
             uint64_t lmin = INF64;
-            if (e < ee) app = relax_arc(A, sd, ai, h1.y, h1.z, bnd, e, stamp, &ne, &lmin, &c_succ);
+            if (e < ee) app = relax_arc<MEMO, REV>(A, sd, ai, h1.y, h1.z, bnd, e, stamp, &ne, &lmin, &c_succ);
             wstage_push(st, scnt, app, ne, qout, qcout, A.qseg, A.err);
             search_stats(A, np, ai, app ? 1u : 0u, lmin, count);
         }
@@ -992,12 +995,35 @@ hipError_t launch_idle(const RoundArgs &A, hipStream_t st) {
 }
 
 hipError_t launch_round(const RoundArgs &A, uint32_t grid, hipStream_t st) {
-    k_round<<<grid, WAVE, 0, st>>>(A);
+    // The default path (symmetric graph, no pull pass, no heuristic memo) is
+    // compiled without those branches, which would otherwise cost it
+    // registers and occupancy. A directed graph has a separate transpose.
+    const bool rev = A.in_row_ptr != A.row_ptr;
+    if (rev) {
+        if (A.memo) k_round<false, true, true><<<grid, WAVE, 0, st>>>(A);
+        else k_round<false, false, true><<<grid, WAVE, 0, st>>>(A);
+    } else if (A.pull && A.memo) {
+        k_round<true, true, false><<<grid, WAVE, 0, st>>>(A);
+    } else if (A.pull) {
+        k_round<true, false, false><<<grid, WAVE, 0, st>>>(A);
+    } else if (A.memo) {
+        k_round<false, true, false><<<grid, WAVE, 0, st>>>(A);
+    } else {
+        k_round<false, false, false><<<grid, WAVE, 0, st>>>(A);
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_heavy(const RoundArgs &A, uint32_t grid, hipStream_t st) {
-    k_heavy<<<grid, WAVE, 0, st>>>(A);
+    const bool rev = A.in_row_ptr != A.row_ptr;
+    if (rev) {
+        if (A.memo) k_heavy<true, true><<<grid, WAVE, 0, st>>>(A);
+        else k_heavy<false, true><<<grid, WAVE, 0, st>>>(A);
+    } else if (A.memo) {
+        k_heavy<true, false><<<grid, WAVE, 0, st>>>(A);
+    } else {
+        k_heavy<false, false><<<grid, WAVE, 0, st>>>(A);
+    }
     return hipGetLastError();
 }
 
