@@ -445,3 +445,64 @@ def test_directed_hubs_heavy_path(P):
     assert np.array_equal(dist, exp[:20])
     _check_paths(d, pairs[:20], dist, off, vtx)
     D.close()
+
+
+def test_edge_cases(P):
+    """Empty and degenerate inputs, duplicates, distance overflow, a path
+    buffer that is too small, and the host-side time limit."""
+    g = gen.lattice(60, 0.1, seed=101)
+    G = _graph(P, g)
+    # empty batch
+    for batch in ["plainstar", "multi"]:
+        assert G.batch_query(np.zeros((0, 2), np.uint32), algo="bids", batch=batch).shape == (0,)
+    d, (off, vtx) = G.batch_query(np.zeros((0, 2), np.uint32), algo="bids", want_path=True)
+    assert d.shape == (0,) and off.tolist() == [0] and vtx.shape == (0,)
+    # duplicates, reversed duplicates and self pairs in one batch
+    base = gen.pairs_uniform(g.n, 20, seed=102)
+    pairs = np.concatenate([base, base[:7], base[3:12, ::-1], np.array([[5, 5], [5, 5]], np.uint32)])
+    exp = _oracle(g, pairs)
+    for algo, batch in [("bids", "plainstar"), ("bidastar", "plain"), ("bids", "multi"), ("sssp", "vc"),
+                        ("et", "plainstar")]:
+        assert np.array_equal(G.batch_query(pairs, algo=algo, batch=batch), exp), (algo, batch)
+    dist, (off, vtx) = G.batch_query(pairs, algo="bids", batch="multi", want_path=True)
+    _check_paths(g, pairs, dist, off, vtx)
+    # a path buffer that is too small reports PPSP_E_PATHCAP through the C ABI
+    import ctypes
+    pp = np.ascontiguousarray(base[:4])
+    dd = np.empty(4, np.uint64)
+    oo = np.empty(5, np.uint64)
+    vv = np.empty(1, np.uint32)
+    rc = P.lib().ppsp_batch_query(G.h, pp.ctypes.data, 4, ctypes.byref(P.make_opts("bids", "plainstar", want_path=True)),
+                                  None, dd.ctypes.data, oo.ctypes.data, vv.ctypes.data, 1)
+    assert rc == P.E_PATHCAP
+    # the host-side time limit ends a long wave with PPSP_E_TIMEOUT (or it finished in time)
+    G.set_option("timeout_ms", 1)
+    G.set_option("rounds_per_sync", 1)
+    try:
+        assert np.array_equal(G.batch_query(base, algo="bids", delta=1), _oracle(g, base))
+    except P.PPSPError as e:
+        assert e.code == P.E_TIMEOUT
+    G.set_option("timeout_ms", 60000)
+    assert np.array_equal(G.batch_query(base, algo="bids"), _oracle(g, base))   # usable again
+    G.close()
+    # one vertex, no arcs
+    one = gen.csr_from_edges(1, [], [], [])
+    O = P.Graph(one.n, one.row_ptr, one.col, one.w)
+    assert O.query(0, 0, algo="bids") == 0
+    assert O.batch_query(np.array([[0, 0]], np.uint32), algo="bids", batch="multi").tolist() == [0]
+    O.close()
+    # isolated vertices only: every pair unreachable
+    iso = gen.csr_from_edges(10, [0], [1], [3])
+    I = P.Graph(iso.n, iso.row_ptr, iso.col, iso.w)
+    q = np.array([[2, 7], [0, 1], [1, 0], [3, 9]], np.uint32)
+    for algo, batch in [("bids", "plainstar"), ("bids", "multi"), ("sssp", "vc"), ("et", "plain")]:
+        assert I.batch_query(q, algo=algo, batch=batch).tolist() == [INF, 3, 3, INF], (algo, batch)
+    I.close()
+    # distances past 2^32 - 2 report PPSP_E_OVERFLOW instead of a wrong value
+    big = gen.csr_from_edges(4, [0, 1, 2], [1, 2, 3], [2 ** 31, 2 ** 31 - 10, 2 ** 31])
+    B = P.Graph(big.n, big.row_ptr, big.col, big.w)
+    assert B.query(0, 1, algo="bids") == 2 ** 31
+    with pytest.raises(P.PPSPError) as e:
+        B.query(0, 3, algo="et")
+    assert e.value.code == P.E_OVERFLOW
+    B.close()
