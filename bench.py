@@ -5,7 +5,9 @@ Workload (one step): the road-like jittered 2048 x 2048 lattice (4,194,304
 vertices, ~17.2M arcs, weights ceil(1000 * Euclidean length), fixed-point
 coordinates) with its 1,000 seeded uniform s-t pairs, answered as one batch
 (Plain*: every query with its own forward and backward search in the same
-launches) with bidirectional A*. Inputs are resident on the GPU before timing.
+launches) with bidirectional A*. The graph is created with PPSP_REORDER (the
+device copy in Morton order of the coordinates; ids at the interface are the
+caller's). Inputs are resident on the GPU before timing.
 
 Printed: one JSON line with queries/s (whole job), GTEPS over the arcs the
 searches actually relaxed, the roofline of the dominant kernel (the round
@@ -99,7 +101,7 @@ def main():
     t0 = time.time()
     g = gen.config_graph(2)
     pairs = gen.config_pairs(2, g)
-    G = P.Graph.from_host(g, device=0)
+    G = P.Graph.from_host(g, device=0, reorder=True)
     G.set_option("timeout_ms", 300000)
     print("# graph n=%d m=%d built+uploaded in %.1fs" % (g.n, g.m, time.time() - t0), file=sys.stderr, flush=True)
     delta = args.delta
@@ -248,7 +250,7 @@ def workload_lattice4096hub(args):
     import paper_2506_16488_amd as P
     torch.cuda.set_device(0)
     g = gen.config_graph(3)
-    G = P.Graph.from_host(g, device=0)
+    G = P.Graph.from_host(g, device=0, reorder=True)
     G.set_option("timeout_ms", 600000)
     batches = [gen.config_pairs(3, g, batch=b) for b in range(args.steps + args.warmup)]
     it = iter(batches)
@@ -298,7 +300,7 @@ def workload_rmat24(args):
     g = gen.config_graph(4)
     lcc = gen.lcc(g)
     pairs = gen.config_pairs(4, g, cand=lcc)
-    G = P.Graph.from_host(g, device=0)
+    G = P.Graph.from_host(g, device=0, reorder=True)
     G.set_option("timeout_ms", 900000)
     print("# graph built: n=%d m=%d" % (g.n, g.m), file=sys.stderr, flush=True)
     res = {}
@@ -347,7 +349,7 @@ def workload_serve(args):
     hosts = [gen.config_graph(3), gen.config_graph(4)]
     lcc = gen.lcc(hosts[1])
     print("# graphs built", file=sys.stderr, flush=True)
-    Gs = [P.Graph.from_host(h, device=0) for h in hosts]
+    Gs = [P.Graph.from_host(h, device=0, reorder=True) for h in hosts]
     # the R-MAT graph runs with its autotuned Delta
     tr = Gs[1].tune(gen.config_pairs(4, hosts[1], cand=lcc)[:16], algo="bids", batch="plainstar")
     rng = np.random.default_rng(105)

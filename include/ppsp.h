@@ -90,6 +90,7 @@ enum ppsp_sched {
 
 /* ppsp_graph_create flags. */
 #define PPSP_SYMMETRIC 1u      /* every arc (u,v,w) has a reverse arc (v,u,w) */
+#define PPSP_REORDER 4u        /* graph_create: store vertices in a locality order (see ppsp_graph_create) */
 
 /* ppsp_opts.flags. */
 #define PPSP_WANT_PATH 1u      /* also return an s->t vertex path per query */
@@ -142,7 +143,14 @@ typedef struct ppsp_graph_s *ppsp_graph;
  *              here exactly in integers, and A* modes return PPSP_E_NOCOORD on a
  *              graph where it fails.
  *   flags      PPSP_SYMMETRIC if the graph is undirected (required by the
- *              bidirectional and batch modes, whose theorems assume it)
+ *              query-graph batch strategies; on directed graphs the backward
+ *              search of a bidirectional query walks the transpose).
+ *              PPSP_REORDER: the device copy numbers the vertices in a
+ *              locality order (Morton order of the coordinates when given,
+ *              else breadth-first from the highest-degree vertex), so that
+ *              vertices close in the graph share cache lines of the search
+ *              state. Vertex ids at the interface stay the caller's (pairs
+ *              and paths are translated); results are identical.
  *   out        receives the handle
  * Errors: PPSP_E_INVALID (bad CSR), PPSP_E_RANGE (col >= n, m too large,
  * coordinate span too large for exact 64-bit arithmetic), PPSP_E_OOM,

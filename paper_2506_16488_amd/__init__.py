@@ -214,8 +214,11 @@ def make_opts(algo="bids", batch="plainstar", sched="fixed", delta=0, want_path=
                 (WANT_PATH if want_path else 0) | (MEMO_H if memo else 0) | (PULL if pull else 0), int(delta))
 
 
+REORDER = 4
+
+
 def graph_create(n, row_ptr, col, w, coords=None, frac_bits=8, w_scale=1000, symmetric=True, device=0,
-                 stream=None):
+                 stream=None, reorder=False):
     """ppsp_graph_create: returns an opaque handle (c_void_p)."""
     rp = np.ascontiguousarray(row_ptr, np.uint64)
     col = np.ascontiguousarray(col, np.uint32)
@@ -223,7 +226,7 @@ def graph_create(n, row_ptr, col, w, coords=None, frac_bits=8, w_scale=1000, sym
     xy = None if coords is None else np.ascontiguousarray(coords, np.int32).reshape(-1)
     h = ctypes.c_void_p()
     rc = lib().ppsp_graph_create(device, int(n), int(col.shape[0]), _ptr(rp), _ptr(col), _ptr(w), _ptr(xy),
-                                 frac_bits, w_scale, SYMMETRIC if symmetric else 0,
+                                 frac_bits, w_scale, (SYMMETRIC if symmetric else 0) | (REORDER if reorder else 0),
                                  stream if stream is not None else current_stream(), ctypes.byref(h))
     _check(rc, "ppsp_graph_create")
     return h
@@ -337,15 +340,16 @@ def get_option(h, name: str) -> int:
 class Graph:
     """A graph resident on one GPU (owns a ppsp_graph handle)."""
 
-    def __init__(self, n, row_ptr, col, w, coords=None, frac_bits=8, w_scale=1000, symmetric=True, device=0):
+    def __init__(self, n, row_ptr, col, w, coords=None, frac_bits=8, w_scale=1000, symmetric=True, device=0,
+                 reorder=False):
         self.n = int(n)
-        self.h = graph_create(n, row_ptr, col, w, coords, frac_bits, w_scale, symmetric, device)
+        self.h = graph_create(n, row_ptr, col, w, coords, frac_bits, w_scale, symmetric, device, reorder=reorder)
 
     @classmethod
-    def from_host(cls, g, device=0, w_scale=1000):
+    def from_host(cls, g, device=0, w_scale=1000, reorder=False):
         """From any object with n, row_ptr, col, w, coords, frac_bits, symmetric."""
         return cls(g.n, g.row_ptr, g.col, g.w, getattr(g, "coords", None), getattr(g, "frac_bits", 8),
-                   w_scale, getattr(g, "symmetric", True), device)
+                   w_scale, getattr(g, "symmetric", True), device, reorder=reorder)
 
     def query(self, s, t, algo="bids", delta=0, want_path=False, memo=False, sched="fixed", pull=False):
         d, p = query(self.h, s, t, make_opts(algo, "plain", sched, delta, want_path, memo, pull), want_path=want_path)

@@ -141,7 +141,9 @@ struct ppsp_graph_s {
     bool symmetric = false, has_xy = false, xy_ok = false;
     uint32_t wmin = 0, wmax = 0, fb = 0, w_scale = 0;
     uint64_t ws2 = 0;
-    std::vector<int32_t> h_xy;      // host copy of coordinates (for descriptors)
+    std::vector<int32_t> h_xy;      // host copy of coordinates (device numbering, for descriptors)
+    std::vector<uint32_t> perm;     // PPSP_REORDER: device id of each caller id (empty: identity)
+    std::vector<uint32_t> iperm;    // caller id of each device id
     DevBuf row_ptr, arcs, xy, in_row_ptr, in_arcs;   // transpose only for a directed graph
     // workspace (grow only)
     DevBuf S, q0, q1, sd, partners, pairdesc, ctl, delta, done, exh, alive, minkey, mu, qcount, cpre, round, err,
@@ -889,6 +891,14 @@ int batch_impl(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp_opts 
     if (want_path && (!path_off || (!path_vtx && path_cap))) return PPSP_E_INVALID;
     for (uint64_t i = 0; i < 2ull * k; i++)
         if (pairs[i] >= g->n) return PPSP_E_RANGE;
+    // PPSP_REORDER: caller ids -> device ids (paths are translated back below)
+    std::vector<uint32_t> mapped;
+    const uint32_t *caller_pairs = pairs;
+    if (!g->perm.empty()) {
+        mapped.resize(2ull * k);
+        for (uint64_t i = 0; i < 2ull * k; i++) mapped[i] = g->perm[pairs[i]];
+        pairs = mapped.data();
+    }
     CHK(set_device(g));
     g->last = ppsp_stats{};
     // order the library stream after the caller's stream
@@ -991,18 +1001,19 @@ int batch_impl(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp_opts 
         return PPSP_E_PATHCAP;
     }
     uint64_t off = 0;
+    const bool re = !g->iperm.empty();
     for (uint32_t i = 0; i < k; i++) {
         if (self[i]) {
             dist[i] = 0;
-            if (want_path) { path_off[i] = off; path_vtx[off++] = pairs[2 * i]; }
+            if (want_path) { path_off[i] = off; path_vtx[off++] = caller_pairs[2 * i]; }
             continue;
         }
         const Answer &a = ans[qidx[i]];
         dist[i] = a.dist;
         if (want_path) {
             path_off[i] = off;
-            if (flip[i]) for (size_t j = a.path.size(); j-- > 0;) path_vtx[off++] = a.path[j];
-            else for (uint32_t v : a.path) path_vtx[off++] = v;
+            if (flip[i]) for (size_t j = a.path.size(); j-- > 0;) path_vtx[off++] = re ? g->iperm[a.path[j]] : a.path[j];
+            else for (uint32_t v : a.path) path_vtx[off++] = re ? g->iperm[v] : v;
         }
     }
     if (want_path) path_off[k] = off;
@@ -1602,6 +1613,81 @@ int ppsp_graph_create(int device, uint32_t n, uint64_t m, const uint64_t *row_pt
         ppsp_graph_destroy(g);
         return rc;
     };
+    // PPSP_REORDER: a locality order of the vertices, and the CSR (and
+    // coordinates) renumbered into it; everything below uses the renumbered
+    // arrays, the interface translates ids.
+    std::vector<uint64_t> rp_re;
+    std::vector<uint32_t> col_re, w_re;
+    std::vector<int32_t> xy_re;
+    if ((flags & PPSP_REORDER) && n > 1) {
+        std::vector<uint32_t> order(n);
+        if (coord_fx) {
+            // Morton (Z-order) key of the coordinates shifted to non-negative
+            int64_t x0 = INT64_MAX, y0 = INT64_MAX;
+            for (uint32_t v = 0; v < n; v++) {
+                x0 = std::min<int64_t>(x0, coord_fx[2 * (uint64_t)v]);
+                y0 = std::min<int64_t>(y0, coord_fx[2 * (uint64_t)v + 1]);
+            }
+            auto spread = [](uint64_t x) {   // the 32 bits of x to the even bit positions
+                x &= 0xFFFFFFFFull;
+                x = (x | (x << 16)) & 0x0000FFFF0000FFFFull;
+                x = (x | (x << 8)) & 0x00FF00FF00FF00FFull;
+                x = (x | (x << 4)) & 0x0F0F0F0F0F0F0F0Full;
+                x = (x | (x << 2)) & 0x3333333333333333ull;
+                x = (x | (x << 1)) & 0x5555555555555555ull;
+                return x;
+            };
+            std::vector<uint64_t> key(n);
+            for (uint32_t v = 0; v < n; v++)
+                key[v] = spread((uint64_t)(coord_fx[2 * (uint64_t)v] - x0)) |
+                         (spread((uint64_t)(coord_fx[2 * (uint64_t)v + 1] - y0)) << 1);
+            std::iota(order.begin(), order.end(), 0u);
+            std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return key[a] < key[b]; });
+        } else {
+            // breadth-first order from the highest-degree vertex, then from each unvisited vertex
+            std::vector<uint8_t> seen(n, 0);
+            uint32_t head = 0, tail = 0, root = 0;
+            for (uint32_t v = 1; v < n; v++)
+                if (row_ptr[v + 1] - row_ptr[v] > row_ptr[root + 1] - row_ptr[root]) root = v;
+            uint32_t next_root = 0;
+            while (tail < n) {
+                if (head == tail) {
+                    while (seen[root]) root = next_root++;
+                    seen[root] = 1;
+                    order[tail++] = root;
+                }
+                const uint32_t u = order[head++];
+                for (uint64_t e = row_ptr[u]; e < row_ptr[u + 1]; e++)
+                    if (!seen[col[e]]) { seen[col[e]] = 1; order[tail++] = col[e]; }
+            }
+        }
+        g->iperm = order;
+        g->perm.assign(n, 0);
+        for (uint32_t k = 0; k < n; k++) g->perm[order[k]] = k;
+        rp_re.assign(n + 1, 0);
+        col_re.resize(m);
+        w_re.resize(m);
+        for (uint32_t k = 0; k < n; k++) {
+            const uint32_t u = order[k];
+            uint64_t o = rp_re[k];
+            for (uint64_t e = row_ptr[u]; e < row_ptr[u + 1]; e++, o++) {
+                col_re[o] = g->perm[col[e]];
+                w_re[o] = w[e];
+            }
+            rp_re[k + 1] = o;
+        }
+        if (coord_fx) {
+            xy_re.resize(2 * (uint64_t)n);
+            for (uint32_t k = 0; k < n; k++) {
+                xy_re[2 * (uint64_t)k] = coord_fx[2 * (uint64_t)order[k]];
+                xy_re[2 * (uint64_t)k + 1] = coord_fx[2 * (uint64_t)order[k] + 1];
+            }
+            coord_fx = xy_re.data();
+        }
+        row_ptr = rp_re.data();
+        col = col_re.data();
+        w = w_re.data();
+    }
     if (coord_fx) {
         // exact 64-bit heuristic arithmetic needs w_scale^2 * (span_x^2 + span_y^2) < 2^63
         int64_t x0 = INT64_MAX, x1 = INT64_MIN, y0 = INT64_MAX, y1 = INT64_MIN;
@@ -1955,6 +2041,9 @@ int ppsp_server_submit(ppsp_server srv, uint32_t graph_id, const uint32_t *pairs
     SrvRequest &rq = srv->reqs[id];
     rq.graph = graph_id;
     rq.pairs.assign(pairs, pairs + 2ull * k);
+    const std::vector<uint32_t> &perm = srv->gs[graph_id].g->perm;   // PPSP_REORDER: device ids
+    if (!perm.empty())
+        for (auto &v : rq.pairs) v = perm[v];
     rq.dist.assign(k, PPSP_INF);
     rq.remaining = k;
     rq.t_submit = std::chrono::steady_clock::now();

@@ -506,3 +506,39 @@ def test_edge_cases(P):
         B.query(0, 3, algo="et")
     assert e.value.code == P.E_OVERFLOW
     B.close()
+
+
+@pytest.mark.parametrize("graph", ["lattice", "rmat", "directed"])
+def test_reordered_graph_same_results(P, graph):
+    """PPSP_REORDER renumbers the device copy (Morton order of the
+    coordinates, else breadth-first); ids at the interface, distances and
+    paths are the caller's."""
+    if graph == "lattice":
+        g = gen.lattice(110, 0.1, seed=111)
+        algos = ["bidastar", "astar", "bids", "et", "sssp"]
+    elif graph == "rmat":
+        g = gen.rmat(12, 16, seed=112)
+        algos = ["bids", "et", "sssp"]
+    else:
+        g = gen.random_graph(3000, 9000, 200, seed=113, symmetric=False)
+        algos = ["bids", "et"]
+    pairs = np.concatenate([gen.pairs_uniform(g.n, 50, seed=114), np.array([[7, 7]], np.uint32)])
+    exp = _oracle(g, pairs)
+    G = P.Graph.from_host(g, reorder=True)
+    G.set_option("timeout_ms", 60000)
+    for algo in algos:
+        assert np.array_equal(G.batch_query(pairs, algo=algo), exp), algo
+        assert G.query(int(pairs[1, 0]), int(pairs[1, 1]), algo=algo) == int(exp[1])
+    if g.symmetric:
+        for algo, batch in [("bids", "multi"), ("sssp", "vc")]:
+            assert np.array_equal(G.batch_query(pairs, algo=algo, batch=batch), exp), batch
+    dist, (off, vtx) = G.batch_query(pairs[:20], algo=algos[0], want_path=True)
+    _check_paths(g, pairs[:20], dist, off, vtx)
+    d1, p1 = G.query(int(pairs[2, 0]), int(pairs[2, 1]), algo=algos[0], want_path=True)
+    assert d1 == int(exp[2]) and (d1 == INF or (int(p1[0]), int(p1[-1])) == (int(pairs[2, 0]), int(pairs[2, 1])))
+    if g.symmetric:
+        S = P.Server([G], algo=algos[0], state_budget_bytes=24 * g.n * 4)
+        r = S.submit(0, pairs)
+        assert np.array_equal(S.wait(r, timeout_ms=60000)[0], exp)
+        S.close()
+    G.close()
