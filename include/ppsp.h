@@ -319,8 +319,8 @@ int ppsp_mlp_fit(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp_opt
  * in FIFO order and are admitted into free slots between rounds, so requests
  * that arrive while others run join them on the device; results are the same
  * distances ppsp_batch_query returns. A graph attached to a server is
- * reserved: ppsp_query / ppsp_batch_query on it return PPSP_E_BUSY until
- * ppsp_server_destroy.
+ * reserved: ppsp_query, ppsp_batch_query, ppsp_set_option and
+ * ppsp_graph_destroy on it return PPSP_E_BUSY until ppsp_server_destroy.
  *   opts          one per graph: opts[i].algo is PPSP_BIDS or PPSP_BIDASTAR
  *                 (one query = two searches), opts[i].delta its Delta (0 = the
  *                 graph's default); other fields are ignored

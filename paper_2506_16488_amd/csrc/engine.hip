@@ -1784,6 +1784,7 @@ int ppsp_graph_create(int device, uint32_t n, uint64_t m, const uint64_t *row_pt
 
 int ppsp_graph_destroy(ppsp_graph g) {
     if (!g) return PPSP_OK;
+    if (g->served) return PPSP_E_BUSY;   // the server's worker still uses it
     (void)hipSetDevice(g->device);
     if (g->st) (void)hipStreamSynchronize(g->st);
     DevBuf *bufs[] = {&g->row_ptr, &g->arcs, &g->xy, &g->in_row_ptr, &g->in_arcs, &g->S, &g->q0, &g->q1,
@@ -1943,6 +1944,7 @@ int ppsp_last_stats(ppsp_graph g, ppsp_stats *s) {
 
 int ppsp_set_option(ppsp_graph g, const char *name, int64_t v) {
     if (!g || !name) return PPSP_E_INVALID;
+    if (g->served) return PPSP_E_BUSY;   // the server's worker reads the options
     std::string k(name);
     if (k == "profile") g->opt_profile = v;
     else if (k == "rounds_per_sync") { if (v < 1) return PPSP_E_INVALID; g->opt_rounds_per_sync = v; }

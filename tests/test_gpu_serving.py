@@ -152,6 +152,10 @@ def test_server_errors_and_release(P):
         G.query(0, 1, algo="bids")                      # reserved while served
     assert e.value.code == P.E_BUSY
     with pytest.raises(P.PPSPError) as e:
+        G.set_option("rounds_per_sync", 4)
+    assert e.value.code == P.E_BUSY
+    assert P.lib().ppsp_graph_destroy(G.h) == P.E_BUSY
+    with pytest.raises(P.PPSPError) as e:
         S.submit(0, np.array([[0, g.n]], np.uint32))
     assert e.value.code == P.E_RANGE
     with pytest.raises(P.PPSPError):
