@@ -301,8 +301,14 @@ __global__ __launch_bounds__(WAVE) void k_round(RoundArgs A) {
     const uint4 *qin = par ? A.q1 : A.q0;
     uint4 *qout = (par ? A.q0 : A.q1) + (uint64_t)sego * A.qseg;
     uint32_t *qcout = &A.qcount[np * NSEG + sego];
-    const uint32_t *cpre = A.cpre + par * (NSEG + 1);
-    const uint32_t nchunks = cpre[NSEG];
+    // The chunk layout of the queue in registers: lane k holds the prefix of
+    // segments 0..k and the length of segment k, so a chunk's segment is a
+    // ballot and a popcount (the prefix is non-decreasing), with no memory
+    // access on the chunk's critical path.
+    static_assert(NSEG == WAVE, "one segment per lane");
+    const uint32_t my_cpre = A.cpre[par * (NSEG + 1) + lane_id() + 1];
+    const uint32_t my_qc = (uint32_t)min((uint64_t)A.qcount[par * NSEG + lane_id()], A.qseg);
+    const uint32_t nchunks = __shfl(my_cpre, NSEG - 1);
     if (blockIdx.x == 0 && lane_id() == 0) {
         A.round[1] = r;                                    // for k_control
         if (nchunks) atomicAdd(&A.stats[ST_ROUNDS], 1ull);
@@ -311,13 +317,10 @@ __global__ __launch_bounds__(WAVE) void k_round(RoundArgs A) {
     const bool count = A.sc && blockIdx.x < ML_SAMPLE;
 
     for (uint32_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
-        uint32_t lo = 0, hi = NSEG;                        // cpre[lo] <= ch < cpre[hi]
-        while (hi - lo > 1) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if (cpre[mid] <= ch) lo = mid; else hi = mid;
-        }
-        const uint64_t nseg = min((uint64_t)A.qcount[par * NSEG + lo], A.qseg);
-        const uint64_t base = (uint64_t)(ch - cpre[lo]) * WAVE;
+        const uint32_t lo = (uint32_t)__popcll(__ballot(my_cpre <= ch));   // cpre[lo] <= ch < cpre[lo + 1]
+        const uint32_t c0 = lo ? __shfl(my_cpre, lo - 1) : 0u;
+        const uint64_t nseg = __shfl(my_qc, lo);
+        const uint64_t base = (uint64_t)(ch - c0) * WAVE;
         const uint64_t pos = base + lane_id();
         const uint64_t idx = (uint64_t)lo * A.qseg + pos;
         const bool valid = pos < nseg;
