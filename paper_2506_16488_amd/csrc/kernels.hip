@@ -189,6 +189,33 @@ __device__ __forceinline__ void wave_add_keyed(unsigned long long *ctr, uint32_t
     if (active) atomicAdd(&ctr[(uint64_t)key * 2 + field], val);
 }
 
+// The part of a relaxation after its WriteMin returned `old`: on a strict
+// decrease the meeting check (with the partner copy `other` read before the
+// atomic), then Prune(v) and Add(v). Returns true if v^(i) must be added to
+// the next frontier; *out is that entry. *lmin takes the key of every
+// unpruned decrease (added now or by an earlier decrease of this round).
+template <bool MEMO>
+__device__ __forceinline__ bool relax_commit(const RoundArgs &A, const SearchDesc &sd, uint32_t i, uint32_t v,
+                                             uint64_t cand, uint64_t other, uint64_t old, uint64_t bnd,
+                                             uint32_t stamp, uint4 *out, uint64_t *lmin, unsigned long long *succ) {
+    if (cand >= (old >> 32)) return false;
+    (*succ)++;
+    if (A.G == 2) {
+        const uint32_t dp = (uint32_t)(other >> 32);
+        if (dp != INF32) mu_update(A, A.partners[sd.pbeg].pair, cand + dp, v);
+    } else {
+        meet_list(A, sd, (uint32_t)cand, v);
+    }
+    const int32_t hk = MEMO ? hterm_memo(A, sd, i, v) : hterm(A, sd, v);
+    const uint64_t kv = key_of(sd.kind, cand, hk);
+    if (kv >= bnd) return false;        // Prune(v) before Add(v)
+    if (kv < *lmin) *lmin = kv;
+    // Lowered before in this round: that lowering added v unless it was pruned.
+    if ((uint32_t)old == stamp && key_of(sd.kind, old >> 32, hk) < bnd) return false;
+    *out = make_uint4(i, v, stamp, (uint32_t)hk);
+    return true;
+}
+
 // Relaxation of arc e out of u^(i) (Algorithm 2, inner loop) in the round
 // whose stamp is `stamp`. Returns true if v^(i) must be added to the next
 // frontier; *out is that entry. *lmin takes the key of every unpruned
@@ -215,22 +242,7 @@ __device__ __forceinline__ bool relax_arc(const RoundArgs &A, const SearchDesc &
     }
     if (cand >= (own >> 32)) return false;
     const uint64_t old = atomicMin(p, (cand << 32) | stamp);
-    if (cand >= (old >> 32)) return false;
-    (*succ)++;
-    if (A.G == 2) {
-        const uint32_t dp = (uint32_t)(other >> 32);
-        if (dp != INF32) mu_update(A, A.partners[sd.pbeg].pair, cand + dp, v);
-    } else {
-        meet_list(A, sd, (uint32_t)cand, v);
-    }
-    const int32_t hk = MEMO ? hterm_memo(A, sd, i, v) : hterm(A, sd, v);
-    const uint64_t kv = key_of(sd.kind, cand, hk);
-    if (kv >= bnd) return false;        // Prune(v) before Add(v)
-    if (kv < *lmin) *lmin = kv;
-    // Lowered before in this round: that lowering added v unless it was pruned.
-    if ((uint32_t)old == stamp && key_of(sd.kind, old >> 32, hk) < bnd) return false;
-    *out = make_uint4(i, v, stamp, (uint32_t)hk);
-    return true;
+    return relax_commit<MEMO>(A, sd, i, v, cand, other, old, bnd, stamp, out, lmin, succ);
 }
 
 // LDS staging of one wave's frontier adds. The wave appends with a ballot
@@ -279,6 +291,10 @@ __device__ __forceinline__ uint32_t wave_exscan(uint32_t v, uint32_t *total) {
 
 #ifndef CARRY_CHECK
 #define CARRY_CHECK 2   // rounds between state checks of a carried entry (a power of two; 1 = every round)
+#endif
+
+#ifndef RELAX_WAYS
+#define RELAX_WAYS 1   // arcs per lane in flight in the round kernel's relaxation loop (1, 2 and 3 measured equal)
 #endif
 
 // Extracted vertices of one wave chunk, for the arc-parallel relaxation.
@@ -493,25 +509,73 @@ __global__ __launch_bounds__(WAVE) void k_round(RoundArgs A) {
             }
             __syncthreads();
         }
-        for (uint32_t a0 = 0; a0 < T; a0 += WAVE) {
-            const uint32_t a = a0 + lane_id();
-            bool app = false;
-            uint4 ne = make_uint4(0, 0, 0, 0);
-            uint64_t lmin = INF64;
-            uint32_t ai = 0;
-            if (a < T) {
-                uint32_t lo = 0, hi = WAVE;               // off[lo] <= a < off[hi]
-                while (hi - lo > 1) {
-                    const uint32_t mid = (lo + hi) >> 1;
-                    if (adv.off[mid] <= a) lo = mid; else hi = mid;
+        // RELAX_WAYS arcs per lane per step: their arc loads, then their state
+        // loads, then their WriteMins are all in flight before any result is
+        // used (the relaxation is a chain of dependent memory accesses).
+        for (uint32_t a0 = 0; a0 < T; a0 += RELAX_WAYS * WAVE) {
+            uint32_t lo[RELAX_WAYS], ai[RELAX_WAYS], v[RELAX_WAYS];
+            bool want[RELAX_WAYS];
+            uint2 arc[RELAX_WAYS];
+            uint64_t cand[RELAX_WAYS], own[RELAX_WAYS], other[RELAX_WAYS], old[RELAX_WAYS];
+            unsigned long long *wp[RELAX_WAYS];
+#pragma unroll
+            for (int h = 0; h < RELAX_WAYS; h++) {
+                const uint32_t a = a0 + h * WAVE + lane_id();
+                lo[h] = 0;
+                ai[h] = 0;
+                arc[h] = make_uint2(0, 0);
+                want[h] = a < T;
+                if (want[h]) {
+                    uint32_t l = 0, r = WAVE;               // off[l] <= a < off[r]
+                    while (r - l > 1) {
+                        const uint32_t mid = (l + r) >> 1;
+                        if (adv.off[mid] <= a) l = mid; else r = mid;
+                    }
+                    lo[h] = l;
+                    ai[h] = adv.i[l];
+                    const uint32_t e = adv.rb[l] + (a - adv.off[l]);
+                    arc[h] = REV ? ((A.sd[ai[h]].rev ? A.in_arcs : A.arcs)[e]) : A.arcs[e];
                 }
-                ai = adv.i[lo];
-                const SearchDesc sd = A.sd[ai];
-                app = relax_arc<MEMO, REV>(A, sd, ai, adv.u[lo], adv.du[lo], adv.bnd[lo], adv.rb[lo] + (a - adv.off[lo]), stamp,
-                                &ne, &lmin, &c_succ);
             }
-            wstage_push(st, scnt, app, ne, qout, qcout, A.qseg, A.err);
-            search_stats(A, np, ai, app ? 1u : 0u, lmin, count);
+#pragma unroll
+            for (int h = 0; h < RELAX_WAYS; h++) {
+                v[h] = arc[h].x;
+                own[h] = 0;
+                other[h] = INF64;
+                wp[h] = nullptr;
+                if (want[h]) {
+                    if (A.G == 2) {
+                        const uint64_t base = state_index(2, A.n, ai[h] & ~1u, v[h]);
+                        const ulonglong2 w = *(const ulonglong2 *)(A.S + base);   // possibly stale: never below the truth
+                        own[h] = (ai[h] & 1) ? w.y : w.x;
+                        other[h] = (ai[h] & 1) ? w.x : w.y;
+                        wp[h] = (unsigned long long *)(A.S + base + (ai[h] & 1));
+                    } else {
+                        wp[h] = (unsigned long long *)(A.S + state_index(A.G, A.n, ai[h], v[h]));
+                        own[h] = *wp[h];
+                    }
+                }
+            }
+#pragma unroll
+            for (int h = 0; h < RELAX_WAYS; h++) {
+                cand[h] = want[h] ? (uint64_t)adv.du[lo[h]] + arc[h].y : 0;
+                if (want[h] && cand[h] >= INF32) { atomicOr(A.err, ERR_OVERFLOW); want[h] = false; }
+                want[h] = want[h] && cand[h] < (own[h] >> 32);
+                old[h] = want[h] ? atomicMin(wp[h], (cand[h] << 32) | stamp) : 0ull;
+            }
+#pragma unroll
+            for (int h = 0; h < RELAX_WAYS; h++) {
+                bool app = false;
+                uint4 ne = make_uint4(0, 0, 0, 0);
+                uint64_t lmin = INF64;
+                if (want[h]) {
+                    const SearchDesc sd = A.sd[ai[h]];
+                    app = relax_commit<MEMO>(A, sd, ai[h], v[h], cand[h], other[h], old[h], adv.bnd[lo[h]], stamp,
+                                             &ne, &lmin, &c_succ);
+                }
+                wstage_push(st, scnt, app, ne, qout, qcout, A.qseg, A.err);
+                search_stats(A, np, ai[h], app ? 1u : 0u, lmin, count);
+            }
         }
         __syncthreads();                          // adv is rewritten by the next chunk
     }
