@@ -64,6 +64,37 @@ def copy_kernel():
 
 BYTES_PER_SCANNED_VERTEX = 24  # row_ptr 8 + own state 8 + frontier entry read/write 8
 BYTES_PER_SCANNED_ARC = 24     # arc (neighbour, weight) 8 + neighbour state read-modify-write 16
+# Scattered accesses of the round kernel: per scanned vertex its own state,
+# its row_ptr pair and the first line of its arcs; per scanned arc the head's
+# state pair; per successful relaxation one 64-bit atomic minimum.
+LOADS_PER_SCANNED_VERTEX = 3
+RANDBENCH_WORDS = 1 << 33      # 64 GiB table, about the size of the workload's search state
+RANDBENCH_OPS = 1 << 28
+
+
+def random_access_roofline(P, agg, launches, avg_launch_us):
+    """Second roofline for the round kernel: its scattered loads and atomics
+    per launch priced at the device's measured rates for such accesses
+    (ppsp_randbench, taken now on this GPU). frac = that floor / the launch
+    time; atomics are counted from successful relaxations, a lower bound."""
+    load_ms = P.randbench(RANDBENCH_WORDS, RANDBENCH_OPS, 0)
+    atom_ms = P.randbench(RANDBENCH_WORDS, RANDBENCH_OPS, 1)
+    load_rate = RANDBENCH_OPS / (load_ms * 1e-3)
+    atom_rate = RANDBENCH_OPS / (atom_ms * 1e-3)
+    loads = (LOADS_PER_SCANNED_VERTEX * agg["scanned_vertices"] + agg["scanned_arcs"]) / launches
+    atomics = agg["relax_success"] / launches
+    floor_us = 1e6 * (loads / load_rate + atomics / atom_rate)
+    return {
+        "bound": "scattered 16-byte loads + 64-bit atomics",
+        "loads_per_launch": int(loads),
+        "atomics_per_launch": int(atomics),
+        "load_rate_gops": round(load_rate / 1e9, 2),
+        "atomic_rate_gops": round(atom_rate / 1e9, 2),
+        "table_gib": RANDBENCH_WORDS * 8 >> 30,
+        "floor_us": round(floor_us, 2),
+        "avg_launch_us": avg_launch_us,
+        "frac": round(floor_us / avg_launch_us, 4) if avg_launch_us > 0 else None,
+    }
 
 
 def main():
@@ -204,6 +235,7 @@ def main():
                       "%d host threads, %.1f s wall" % (sample.shape[0], threads, cpu_s),
         }
     G.close()
+    out["random_access"] = random_access_roofline(P, agg, launches, out["roofline"]["avg_launch_us"])
     print(json.dumps(out), flush=True)
 
 

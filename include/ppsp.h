@@ -410,6 +410,19 @@ const char *ppsp_status_str(int status);
  * failing HIP call and its error name), or "" . Valid until the next call. */
 const char *ppsp_last_error(void);
 
+/*
+ * Measurement: the device's rate of scattered accesses, the resource the
+ * round kernel is bound by (each relaxation reads one vertex's state pair at
+ * a data-dependent address and, when it lowers it, performs one 64-bit
+ * atomic minimum). Times one kernel doing `accesses` operations at
+ * pseudo-random positions (a fixed counter hash) of a fresh device table of
+ * `words` 64-bit words: kind 0 = 16-byte loads, kind 1 = 64-bit atomicMin.
+ * *ms receives the kernel time of the second of two runs (HIP events).
+ * The search path never calls it. Errors: PPSP_E_INVALID (null ms,
+ * words < 2 or > 2^40, accesses == 0, kind not 0/1), PPSP_E_OOM, PPSP_E_DEVICE.
+ */
+int ppsp_randbench(int device, uint64_t words, uint64_t accesses, int kind, double *ms);
+
 /* Library version, e.g. "0.1.0". */
 const char *ppsp_version(void);
 

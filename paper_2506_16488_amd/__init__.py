@@ -95,7 +95,7 @@ EXPORTS = ["ppsp_graph_create", "ppsp_graph_destroy", "ppsp_query", "ppsp_batch_
            "ppsp_set_option", "ppsp_get_option", "ppsp_heuristic_fx", "ppsp_status_str", "ppsp_version",
            "ppsp_last_error", "ppsp_tune", "ppsp_server_create", "ppsp_server_submit", "ppsp_server_poll",
            "ppsp_server_wait", "ppsp_server_stats", "ppsp_server_destroy", "ppsp_mlp_forward", "ppsp_mlp_grad",
-           "ppsp_mlp_train", "ppsp_mlp_load", "ppsp_sched_trace", "ppsp_mlp_fit"]
+           "ppsp_mlp_train", "ppsp_mlp_load", "ppsp_sched_trace", "ppsp_mlp_fit", "ppsp_randbench"]
 
 _lib_handle = None
 
@@ -160,6 +160,8 @@ def lib():
         for f in ("forward", "grad", "train", "load", "fit"):
             getattr(L, "ppsp_mlp_" + f).restype = ctypes.c_int
         L.ppsp_sched_trace.restype = ctypes.c_int
+        L.ppsp_randbench.argtypes = [ctypes.c_int, u64, u64, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
+        L.ppsp_randbench.restype = ctypes.c_int
         _lib_handle = L
     return _lib_handle
 
@@ -319,6 +321,14 @@ def mlp_train(params, X, y, epochs, batch=512, lr=2e-3, seed=0, device=0):
     _check(lib().ppsp_mlp_train(device, _ptr(p), _ptr(X), _ptr(y), X.shape[0], int(epochs), int(batch), float(lr),
                                 int(seed), ctypes.byref(l0), ctypes.byref(l1)), "ppsp_mlp_train")
     return p, l0.value, l1.value
+
+
+def randbench(words, accesses, kind, device=0) -> float:
+    """Kernel milliseconds for `accesses` scattered 16-byte loads (kind 0) or
+    64-bit atomicMin (kind 1) over `words` 64-bit words (ppsp_randbench)."""
+    ms = ctypes.c_double(0)
+    _check(lib().ppsp_randbench(device, int(words), int(accesses), int(kind), ctypes.byref(ms)), "ppsp_randbench")
+    return ms.value
 
 
 def last_stats(h) -> dict:

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 SO = os.path.join(HERE, "libppsp.so")
-SOURCES = ["engine.hip", "kernels.hip", "mlp.hip"]
+SOURCES = ["engine.hip", "kernels.hip", "mlp.hip", "randbench.hip"]
 ARCH = "gfx950"
 
 

@@ -116,3 +116,11 @@ def test_no_cpu_fallback_in_binding():
     assert "oracle" not in src.replace("marshals", "")
     for f in os.listdir(os.path.join(ROOT, "paper_2506_16488_amd", "csrc")):
         assert "oracle" not in open(os.path.join(ROOT, "paper_2506_16488_amd", "csrc", f)).read()
+
+
+def test_randbench_rejects_bad_arguments_before_device():
+    P = _ppsp()
+    for words, acc, kind in ((1, 10, 0), (1 << 20, 0, 0), (1 << 20, 10, 2), ((1 << 40) + 2, 10, 0)):
+        with pytest.raises(P.PPSPError) as e:
+            P.randbench(words, acc, kind)
+        assert e.value.code == P.E_INVALID
