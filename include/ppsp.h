@@ -362,7 +362,8 @@ int ppsp_last_stats(ppsp_graph g, ppsp_stats *stats);
 /*
  * Tuning knobs of a graph handle (not part of the method; they only change
  * launch shapes and bookkeeping):
- *   "profile"         1: time every round-kernel launch with HIP events
+ *   "profile"         1: time every round-kernel launch with HIP events carried
+ *                     by the launch itself (hipExtLaunchKernel: no extra packets)
  *   "rounds_per_sync" rounds launched between host checks for termination
  *   "grid_blocks"     single-wave workgroups of the round kernel (0 = 16 per compute unit)
  *   "mem_budget_mb"   cap on the search-state memory of one wave (0 = auto)

@@ -37,7 +37,8 @@
 
 namespace ppsp {
 hipError_t launch_init(const RoundArgs &A, hipStream_t st);
-hipError_t launch_round(const RoundArgs &A, uint32_t grid, hipStream_t st);
+hipError_t launch_round(const RoundArgs &A, uint32_t grid, hipStream_t st, hipEvent_t e0 = nullptr,
+                        hipEvent_t e1 = nullptr);
 hipError_t launch_control(const RoundArgs &A, hipStream_t st);
 hipError_t launch_heavy(const RoundArgs &A, uint32_t grid, hipStream_t st);
 hipError_t launch_admit(const RoundArgs &A, const uint32_t *ids, uint32_t k, hipStream_t st);
@@ -426,10 +427,9 @@ int run_wave(ppsp_graph g, const Plan &P, bool want_path, WaveOut &out) {
                 r += kk;
             } else {
                 for (kk = 0; kk < K; kk++, r++) {
-                    if (prof) HIPCHK(hipEventRecord(g->ev[2 * kk], st));
-                    HIPCHK(launch_round(A, grid, st));
+                    if (prof) HIPCHK(launch_round(A, grid, st, g->ev[2 * kk], g->ev[2 * kk + 1]));
+                    else HIPCHK(launch_round(A, grid, st));
                     if (A.hcap) HIPCHK(launch_heavy(A, grid, st));
-                    if (prof) HIPCHK(hipEventRecord(g->ev[2 * kk + 1], st));
                     HIPCHK(launch_control(A, st));
                 }
             }

@@ -53,6 +53,8 @@
 // The round number lives in device memory (written by the kernel that does
 // not read it in the same launch), so a fixed sequence of launches can be
 // captured once in a hipGraph and replayed.
+#include <hip/hip_ext.h>
+
 #include "mlp_dev.h"
 #include "ppsp_dev.h"
 
@@ -1061,24 +1063,28 @@ hipError_t launch_idle(const RoundArgs &A, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_round(const RoundArgs &A, uint32_t grid, hipStream_t st) {
+// With events, the launch carries them in its own dispatch (start and end
+// of the kernel itself): no marker packets are queued between the rounds.
+template <bool PULL, bool MEMO, bool REV>
+static hipError_t launch_round_t(const RoundArgs &A, uint32_t grid, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+    if (e0)
+        hipExtLaunchKernelGGL(k_round<PULL, MEMO, REV>, dim3(grid), dim3(WAVE), 0, st, e0, e1, 0, A);
+    else
+        k_round<PULL, MEMO, REV><<<grid, WAVE, 0, st>>>(A);
+    return hipGetLastError();
+}
+
+hipError_t launch_round(const RoundArgs &A, uint32_t grid, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
     // The default path (symmetric graph, no pull pass, no heuristic memo) is
     // compiled without those branches, which would otherwise cost it
     // registers and occupancy. A directed graph has a separate transpose.
     const bool rev = A.in_row_ptr != A.row_ptr;
-    if (rev) {
-        if (A.memo) k_round<false, true, true><<<grid, WAVE, 0, st>>>(A);
-        else k_round<false, false, true><<<grid, WAVE, 0, st>>>(A);
-    } else if (A.pull && A.memo) {
-        k_round<true, true, false><<<grid, WAVE, 0, st>>>(A);
-    } else if (A.pull) {
-        k_round<true, false, false><<<grid, WAVE, 0, st>>>(A);
-    } else if (A.memo) {
-        k_round<false, true, false><<<grid, WAVE, 0, st>>>(A);
-    } else {
-        k_round<false, false, false><<<grid, WAVE, 0, st>>>(A);
-    }
-    return hipGetLastError();
+    if (rev) return A.memo ? launch_round_t<false, true, true>(A, grid, st, e0, e1)
+                           : launch_round_t<false, false, true>(A, grid, st, e0, e1);
+    if (A.pull) return A.memo ? launch_round_t<true, true, false>(A, grid, st, e0, e1)
+                              : launch_round_t<true, false, false>(A, grid, st, e0, e1);
+    return A.memo ? launch_round_t<false, true, false>(A, grid, st, e0, e1)
+                  : launch_round_t<false, false, false>(A, grid, st, e0, e1);
 }
 
 hipError_t launch_heavy(const RoundArgs &A, uint32_t grid, hipStream_t st) {

@@ -14,7 +14,7 @@
 
 #include "ppsp.h"
 
-namespace {
+namespace ppsp_randbench_kernels {
 
 __device__ __forceinline__ uint64_t mix64(uint64_t z) {
     z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
@@ -40,7 +40,9 @@ __global__ __launch_bounds__(256) void k_rand_atomic(unsigned long long *t, uint
     }
 }
 
-}  // namespace
+}  // namespace ppsp_randbench_kernels
+
+using namespace ppsp_randbench_kernels;
 
 extern "C" int ppsp_randbench(int device, uint64_t words, uint64_t accesses, int kind, double *ms) {
     if (!ms || words < 2 || accesses == 0 || kind < 0 || kind > 1 || words > (1ull << 40)) return PPSP_E_INVALID;
