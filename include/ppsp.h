@@ -383,13 +383,21 @@ int ppsp_last_stats(ppsp_graph g, ppsp_stats *stats);
  *   "heavy_window"    vertices of degree > 512 are extracted only from the low 1/heavy_window
  *                     of the step window (smallest key + Delta/heavy_window), where their
  *                     distance is close to final, so their long arc lists are pushed fewer
- *                     times (default 8; 1 = the whole window)
+ *                     times (default 64; 1 = the whole window)
  *   "multi_group"     Multi-BiDS state layout: this many consecutive query-graph vertices
  *                     keep their words of a vertex side by side (a power of two up to 64;
  *                     default 32; 1 = search-major)
  *   "rho"             target next-frontier size per search of PPSP_SCHED_RHO (default 4096)
  *   "ml_every"        rounds between evaluations of the learned schedule's network (default 4;
  *                     a search keeps its multiplier in between)
+ *   "local_chunks"    up to this many chunks of 64 entries per wave per round are taken
+ *                     from the wave's own additions whose key is within the round's
+ *                     threshold, in the same launch, for heuristic searches (A*, BiD-A*):
+ *                     a frontier advances several hops per round (default 4; 0 = off)
+ *   "local_chunks_plain" the same for the other searches (ET, SSSP, BiDS, Multi-BiDS;
+ *                     default 0: measured neutral to slower there)
+ *   "local_fill"      local chunks only in rounds whose frontier holds fewer entries than
+ *                     this (default 0 = every round)
  * Returns PPSP_E_INVALID for an unknown name.
  */
 int ppsp_set_option(ppsp_graph g, const char *name, int64_t value);

@@ -199,7 +199,8 @@ __device__ __forceinline__ void wave_add_keyed(unsigned long long *ctr, uint32_t
 template <bool MEMO>
 __device__ __forceinline__ bool relax_commit(const RoundArgs &A, const SearchDesc &sd, uint32_t i, uint32_t v,
                                              uint64_t cand, uint64_t other, uint64_t old, uint64_t bnd,
-                                             uint32_t stamp, uint4 *out, uint64_t *lmin, unsigned long long *succ) {
+                                             uint32_t stamp, uint4 *out, uint64_t *lmin, unsigned long long *succ,
+                                             uint64_t *kout) {
     if (cand >= (old >> 32)) return false;
     (*succ)++;
     if (A.G == 2) {
@@ -215,6 +216,7 @@ __device__ __forceinline__ bool relax_commit(const RoundArgs &A, const SearchDes
     // Lowered before in this round: that lowering added v unless it was pruned.
     if ((uint32_t)old == stamp && key_of(sd.kind, old >> 32, hk) < bnd) return false;
     *out = make_uint4(i, v, stamp, (uint32_t)hk);
+    *kout = kv;
     return true;
 }
 
@@ -244,7 +246,8 @@ __device__ __forceinline__ bool relax_arc(const RoundArgs &A, const SearchDesc &
     }
     if (cand >= (own >> 32)) return false;
     const uint64_t old = atomicMin(p, (cand << 32) | stamp);
-    return relax_commit<MEMO>(A, sd, i, v, cand, other, old, bnd, stamp, out, lmin, succ);
+    uint64_t kv;
+    return relax_commit<MEMO>(A, sd, i, v, cand, other, old, bnd, stamp, out, lmin, succ, &kv);
 }
 
 // LDS staging of one wave's frontier adds. The wave appends with a ballot
@@ -303,8 +306,23 @@ __device__ __forceinline__ uint32_t wave_exscan(uint32_t v, uint32_t *total) {
 struct Advance {
     uint32_t off[WAVE + 1];   // exclusive prefix of the extracted degrees (0 for other lanes)
     uint32_t i[WAVE], u[WAVE], du[WAVE], rb[WAVE];
-    uint64_t bnd[WAVE];
+    uint64_t bnd[WAVE], th[WAVE];
 };
+
+// Local chunks (RoundArgs::local): entries a wave adds whose key is within
+// the round's threshold are kept in its LDS list and extracted by the same
+// wave in the same round, so a frontier advances several hops per launch.
+// A local entry carries the current round's stamp in .z; extracting it
+// first clears the stamp of its state word to 0 with a compare-and-swap
+// (the distance unchanged), so a later lowering in the round adds the
+// vertex again. A wave only lists entries it has reserved local chunks for,
+// so every listed entry is extracted before the launch ends.
+constexpr uint32_t LCAP = 128;                 // LDS list slots per wave
+// Check-only entry (.z): the meeting check of a vertex that was extracted
+// locally in a search with partner copies, repeated in the next round.
+// Within one launch another XCD's write of a partner copy may not be
+// visible; the next launch sees it (the deferred check described above).
+constexpr uint32_t RECHECK_Z = 0xFFFFFFFEu;
 
 // One round. Workgroups are single waves that work independently (no
 // barriers between waves): each takes WAVE-entry chunks of its sub-queue.
@@ -334,14 +352,33 @@ __global__ __launch_bounds__(WAVE) void k_round(RoundArgs A) {
     unsigned long long c_ent = 0, c_sv = 0, c_se = 0, c_succ = 0, c_keep = 0;
     const bool count = A.sc && blockIdx.x < ML_SAMPLE;
 
-    for (uint32_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
-        const uint32_t lo = (uint32_t)__popcll(__ballot(my_cpre <= ch));   // cpre[lo] <= ch < cpre[lo + 1]
-        const uint32_t c0 = lo ? __shfl(my_cpre, lo - 1) : 0u;
-        const uint64_t nseg = __shfl(my_qc, lo);
-        const uint64_t base = (uint64_t)(ch - c0) * WAVE;
-        const uint64_t pos = base + lane_id();
-        const uint64_t idx = (uint64_t)lo * A.qseg + pos;
-        const bool valid = pos < nseg;
+    __shared__ uint4 lq[LCAP];
+    uint32_t lpend = 0;                                    // listed local entries not yet taken
+    const uint32_t lmax = A.local > A.local_plain ? A.local : A.local_plain;
+    uint32_t lbud = (!PULL && lmax && (A.local_fill == 0 || (uint64_t)nchunks * WAVE < A.local_fill)) ? lmax : 0u;
+    uint32_t ch = blockIdx.x;
+    for (;;) {
+        // The next chunk: this wave's own listed entries first, then the queue.
+        uint4 ent = make_uint4(0, 0, 0, 0);
+        bool valid;
+        if (lpend) {
+            const uint32_t take = lpend < (uint32_t)WAVE ? lpend : (uint32_t)WAVE;
+            valid = lane_id() < take;
+            if (valid) ent = lq[lpend - take + lane_id()];
+            lpend -= take;
+            lbud--;
+            __syncthreads();                                // read before this chunk lists more
+        } else if (ch < nchunks) {
+            const uint32_t lo = (uint32_t)__popcll(__ballot(my_cpre <= ch));   // cpre[lo] <= ch < cpre[lo + 1]
+            const uint32_t c0 = lo ? __shfl(my_cpre, lo - 1) : 0u;
+            const uint64_t nseg = __shfl(my_qc, lo);
+            const uint64_t pos = (uint64_t)(ch - c0) * WAVE + lane_id();
+            valid = pos < nseg;
+            if (valid) ent = qin[(uint64_t)lo * A.qseg + pos];
+            ch += gridDim.x;
+        } else {
+            break;
+        }
 
         // 1. One entry per lane: stale, kept for later, pruned or extracted.
         // A carried entry stores its exact key (CARRY_BIT set in .x, the key in
@@ -350,19 +387,31 @@ __global__ __launch_bounds__(WAVE) void k_round(RoundArgs A) {
         // state, except every CARRY_CHECK-th round (staggered by vertex),
         // which drops it if the vertex was lowered since (then a fresher
         // entry exists).
-        uint4 ent = make_uint4(0, 0, 0, 0);
         uint32_t si = 0, du = 0, rb = 0, re = 0;
-        uint64_t key = 0, bnd = 0;
+        uint64_t key = 0, bnd = 0, th = 0;
         int action = 0;  // 0 nothing, 1 keep for a later round, 2 relax
+        bool recheck = false;   // push a check-only entry for the next round
         if (valid) {
-            ent = qin[idx];
             const bool carried = (ent.x & CARRY_BIT) != 0;
             si = ent.x & ~CARRY_BIT;
             const uint32_t i = si, u = ent.y;
             c_ent++;
             const ulonglong2 c = A.ctl[i];
             bnd = c.y;
-            if (bnd != 0 && carried && ent.w != KEY_UNKNOWN && ent.w > c.x && ent.w < bnd &&
+            th = c.x;
+            if (bnd != 0 && ent.z == RECHECK_Z) {
+                // the deferred meeting check of a vertex extracted locally last round
+                const SearchDesc sd = A.sd[i];
+                if (A.G == 2) {
+                    const ulonglong2 w = *(const ulonglong2 *)(A.S + state_index(2, A.n, i & ~1u, u));
+                    const uint32_t d0 = (uint32_t)(((i & 1) ? w.y : w.x) >> 32);
+                    const uint32_t d1 = (uint32_t)(((i & 1) ? w.x : w.y) >> 32);
+                    if (d0 != INF32 && d1 != INF32) mu_update(A, A.partners[sd.pbeg].pair, (uint64_t)d0 + d1, u);
+                } else {
+                    const uint32_t d0 = (uint32_t)(A.S[state_index(A.G, A.n, i, u)] >> 32);
+                    if (d0 != INF32) meet_list(A, sd, d0, u);
+                }
+            } else if (bnd != 0 && carried && ent.w != KEY_UNKNOWN && ent.w > c.x && ent.w < bnd &&
                 ((r + u) & (CARRY_CHECK - 1)) != 0) {
                 key = ent.w;
                 action = 1;
@@ -370,12 +419,31 @@ __global__ __launch_bounds__(WAVE) void k_round(RoundArgs A) {
                 const SearchDesc sd = A.sd[i];
                 uint64_t word;
                 uint32_t dp = INF32;
+                unsigned long long *wp;
                 if (A.G == 2) {
-                    const ulonglong2 w = *(const ulonglong2 *)(A.S + state_index(2, A.n, i & ~1u, u));
+                    const uint64_t base = state_index(2, A.n, i & ~1u, u);
+                    const ulonglong2 w = *(const ulonglong2 *)(A.S + base);
                     word = (i & 1) ? w.y : w.x;
                     dp = (uint32_t)(((i & 1) ? w.x : w.y) >> 32);
+                    wp = (unsigned long long *)(A.S + base + (i & 1));
                 } else {
-                    word = A.S[state_index(A.G, A.n, i, u)];
+                    wp = (unsigned long long *)(A.S + state_index(A.G, A.n, i, u));
+                    word = *wp;
+                }
+                bool local = false;
+                if (ent.z == stamp && (uint32_t)word == stamp) {
+                    // A local entry: take it by clearing the stamp (a lowering
+                    // since it was listed keeps the stamp; retry with that).
+                    for (;;) {
+                        const uint64_t prev = atomicCAS(wp, (unsigned long long)word, word & ~0xFFFFFFFFull);
+                        if (prev == word || (uint32_t)prev != stamp) {
+                            local = prev == word;
+                            word = prev == word ? (word & ~0xFFFFFFFFull) : prev;
+                            break;
+                        }
+                        word = prev;
+                    }
+                    if (local) ent.z = 0;       // what the state word now holds
                 }
                 du = (uint32_t)(word >> 32);
                 if ((uint32_t)word != ent.z && (uint32_t)word != INF32) {
@@ -411,6 +479,8 @@ __global__ __launch_bounds__(WAVE) void k_round(RoundArgs A) {
                                 re = rp[u + 1];
                                 c_sv++;
                                 c_se += re - rb;
+                                recheck = local && (A.G == 2 || sd.pend > sd.pbeg + 1 ||
+                                                    (sd.pend > sd.pbeg && !(A.partners[sd.pbeg].other & TARGET_BIT)));
                             }
                         }
                     }
@@ -427,8 +497,10 @@ __global__ __launch_bounds__(WAVE) void k_round(RoundArgs A) {
         // stale).
         const bool keep = action == 1;
         c_keep += keep;
-        wstage_push(st, scnt, keep, ent, qout, qcout, A.qseg, A.err);
-        search_stats(A, np, si, keep ? 1u : 0u, keep ? key : INF64, count);
+        wstage_push(st, scnt, keep || recheck, keep ? ent : make_uint4(si, ent.y, RECHECK_Z, 0u), qout, qcout, A.qseg,
+                    A.err);
+        // a check-only entry keeps its search alive for one more round, at no key
+        search_stats(A, np, si, (keep || recheck) ? 1u : 0u, keep ? key : INF64, count);
 
         // High-degree vertices go to the heavy list as chunks of at most
         // HEAVY_CHUNK arcs, which all waves of k_heavy share; one atomic per
@@ -468,6 +540,7 @@ __global__ __launch_bounds__(WAVE) void k_round(RoundArgs A) {
         adv.du[lane_id()] = du;
         adv.rb[lane_id()] = rb;
         adv.bnd[lane_id()] = bnd;
+        adv.th[lane_id()] = th;
         __syncthreads();
         if (PULL) {
             // Pull (Appendix B, undirected graphs): delta[u] <- min over the
@@ -569,14 +642,30 @@ __global__ __launch_bounds__(WAVE) void k_round(RoundArgs A) {
             for (int h = 0; h < RELAX_WAYS; h++) {
                 bool app = false;
                 uint4 ne = make_uint4(0, 0, 0, 0);
-                uint64_t lmin = INF64;
+                uint64_t lmin = INF64, kv = INF64;
+                bool heur = false;
                 if (want[h]) {
                     const SearchDesc sd = A.sd[ai[h]];
+                    heur = sd.kind == K_ASTAR || sd.kind == K_BIDA_F || sd.kind == K_BIDA_B;
                     app = relax_commit<MEMO>(A, sd, ai[h], v[h], cand[h], other[h], old[h], adv.bnd[lo[h]], stamp,
-                                             &ne, &lmin, &c_succ);
+                                             &ne, &lmin, &c_succ, &kv);
                 }
-                wstage_push(st, scnt, app, ne, qout, qcout, A.qseg, A.err);
-                search_stats(A, np, ai[h], app ? 1u : 0u, lmin, count);
+                // Within the threshold: list it for this wave's next local
+                // chunk if its chunks fit the budget, else the next round.
+                bool loc = false;
+                if (lbud) {
+                    loc = app && kv <= adv.th[lo[h]] && (heur ? A.local : A.local_plain) != 0;
+                    const uint64_t lm = __ballot(loc);
+                    const uint32_t nl = (uint32_t)__popcll(lm);
+                    if (nl && lpend + nl <= LCAP && (lpend + nl + WAVE - 1) / WAVE <= lbud) {
+                        if (loc) lq[lpend + mbcnt64(lm)] = ne;
+                        lpend += nl;
+                    } else {
+                        loc = false;
+                    }
+                }
+                wstage_push(st, scnt, app && !loc, ne, qout, qcout, A.qseg, A.err);
+                search_stats(A, np, ai[h], (app && !loc) ? 1u : 0u, loc ? INF64 : lmin, count);
             }
         }
         __syncthreads();                          // adv is rewritten by the next chunk

@@ -188,6 +188,14 @@ struct RoundArgs {
     uint64_t *memo;
     uint32_t epoch;
     uint32_t pull;             // 1: pull relaxation before pushing (Appendix B)
+    // Local chunks of the round kernel: up to max(local, local_plain) chunks
+    // per wave per round taken from the wave's own additions: entries of
+    // heuristic searches (A*, BiD-A*) when local > 0, of the others when
+    // local_plain > 0; in rounds whose frontier holds fewer than local_fill
+    // entries (0: every round).
+    uint32_t local;
+    uint32_t local_plain;
+    uint32_t local_fill;
 };
 
 // Only the first ML_SAMPLE workgroups of the round kernels update the

@@ -59,4 +59,9 @@ def test_random_graphs_every_mode(P, seed):
                     assert path.shape[0] == 0
                 else:
                     assert oracle.check_path(g.n, g.row_ptr, g.col, g.w, path, s, t, int(dist[q])) == (0, 0), q
+        # local chunks (a wave extracts its own additions in the same round)
+        G.set_option("local_chunks", 8)
+        G.set_option("local_chunks_plain", 8)
+        for algo, batch in strategies[:4]:
+            assert np.array_equal(G.batch_query(pairs, algo=algo, batch=batch), exp), (seed, reorder, algo, batch, "local")
         G.close()
