@@ -19,6 +19,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -31,9 +32,14 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_2506_16488_amd", "csrc", f) for f in
 
 
 def kernel_source_hash():
+    """Hash of the round kernel's sources with comments and blank lines
+    removed (a comment edit does not invalidate the counters)."""
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        h.update(open(f, "rb").read())
+        src = open(f).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", "", src)
+        h.update("\n".join(l.rstrip() for l in src.splitlines() if l.strip()).encode())
     return h.hexdigest()[:16]
 
 

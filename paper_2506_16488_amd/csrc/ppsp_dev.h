@@ -17,6 +17,9 @@
 // than the entry's) is stale, because that later lowering added a fresh
 // entry (or pruned the vertex), and is dropped. So an entry kept for a later
 // round is simply added again, with no atomic and no duplicate work.
+// Stamp 0 also marks a word whose vertex a wave has taken from its own list
+// in the round that added it (local chunks, see the round kernel): a later
+// lowering in that round then adds the vertex again.
 // Parents are not stored: every vertex of an exact
 // path has a tight in-arc (delta[p] + w(p,v) = delta[v]) to an exact vertex,
 // so paths are recovered by walking tight arcs back to the root.
