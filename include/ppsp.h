@@ -365,7 +365,7 @@ int ppsp_last_stats(ppsp_graph g, ppsp_stats *stats);
  *   "profile"         1: time every round-kernel launch with HIP events carried
  *                     by the launch itself (hipExtLaunchKernel: no extra packets)
  *   "rounds_per_sync" rounds launched between host checks for termination
- *   "grid_blocks"     single-wave workgroups of the round kernel (0 = 16 per compute unit)
+ *   "grid_blocks"     single-wave workgroups of the round kernel (0 = 20 per compute unit)
  *   "mem_budget_mb"   cap on the search-state memory of one wave (0 = auto)
  *   "default_delta"   Delta (distance units) used when opts.delta = 0 (0 = 2 x mean arc weight)
  *   "theta_mode"      0: Delta*-stepping, the threshold grows by Delta every round

@@ -62,9 +62,20 @@ namespace {
 
 extern thread_local std::string g_last_error;
 
+// Device allocation owned by its holder (freed with it, movable, not copyable).
 struct DevBuf {
     void *p = nullptr;
     size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    DevBuf(DevBuf &&o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+    DevBuf &operator=(DevBuf &&o) noexcept {
+        std::swap(p, o.p);
+        std::swap(bytes, o.bytes);
+        return *this;
+    }
+    ~DevBuf() { if (p) (void)hipFree(p); }
     template <class T> T *as() const { return (T *)p; }
 };
 
@@ -187,11 +198,12 @@ int set_device(ppsp_graph g) {
     return PPSP_OK;
 }
 
-// Workgroups of the round kernel: the "grid_blocks" option, else 16 per
-// compute unit (measured best on the 2048^2 lattice batch: 12, 16, 20, 24
-// and 32 per unit gave 3,955, 3,980, 3,942, 3,892 and 3,695 queries/s).
+// Workgroups of the round kernel: the "grid_blocks" option, else 20 per
+// compute unit, the most that are resident at once (5 waves per SIMD by
+// registers, 7.4 KB of LDS each). On the 2048^2 lattice batch 16, 18 and 20
+// per unit gave 5,240, 5,320 and 5,360 queries/s.
 uint32_t round_grid(ppsp_graph g) {
-    return g->opt_grid_blocks > 0 ? (uint32_t)g->opt_grid_blocks : (uint32_t)(16 * g->cu);
+    return g->opt_grid_blocks > 0 ? (uint32_t)g->opt_grid_blocks : (uint32_t)(20 * g->cu);
 }
 
 uint64_t key_delta(uint32_t kind, uint64_t d) {
@@ -319,7 +331,8 @@ int run_wave(ppsp_graph g, const Plan &P, bool want_path, WaveOut &out) {
     const uint64_t n = g->n;
     const uint64_t ns_words = ((uint64_t)ns + P.G - 1) / P.G * P.G;   // whole groups of G searches
     hipStream_t st = g->st;
-    CHK(ensure(g->S, ns_words * n * 8));
+    const uint64_t sbytes = ns_words * n * 8;
+    CHK(ensure(g->S, sbytes));
     CHK(ensure(g->round, 16));
     CHK(ensure(g->hcount, 16));
     if (g->maxdeg > HEAVY_DEG) {
@@ -354,7 +367,7 @@ int run_wave(ppsp_graph g, const Plan &P, bool want_path, WaveOut &out) {
     for (;;) {
         CHK(ensure(g->q0, g->qcap * 16));
         CHK(ensure(g->q1, g->qcap * 16));
-        HIPCHK(hipMemsetAsync(g->S.p, 0xFF, ns_words * n * 8, st));
+        HIPCHK(hipMemsetAsync(g->S.p, 0xFF, sbytes, st));
         HIPCHK(hipMemcpyAsync(g->sd.p, P.sd.data(), ns * sizeof(SearchDesc), hipMemcpyHostToDevice, st));
         if (!P.partners.empty())
             HIPCHK(hipMemcpyAsync(g->partners.p, P.partners.data(), P.partners.size() * sizeof(Partner),
@@ -1805,7 +1818,7 @@ int ppsp_graph_destroy(ppsp_graph g) {
     for (hipEvent_t e : g->ev) (void)hipEventDestroy(e);
     if (g->h_poll) (void)hipHostFree(g->h_poll);
     if (g->st) (void)hipStreamDestroy(g->st);
-    delete g;
+    delete g;                          // frees every remaining buffer
     return PPSP_OK;
 }
 
@@ -1920,7 +1933,7 @@ int ppsp_tune(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp_opts *
         const double ms = trial(dd, best_mode, 0);
         if (ms < best_ms) { best_ms = ms; best_d = dd; }
     }
-    for (int64_t per_cu : {12, 24}) {
+    for (int64_t per_cu : {12, 16}) {
         const double ms = trial(best_d, best_mode, per_cu * g->cu);
         if (ms < best_ms) { best_ms = ms; best_grid = per_cu * g->cu; }
     }

@@ -317,7 +317,7 @@ struct Advance {
 // (the distance unchanged), so a later lowering in the round adds the
 // vertex again. A wave only lists entries it has reserved local chunks for,
 // so every listed entry is extracted before the launch ends.
-constexpr uint32_t LCAP = 128;                 // LDS list slots per wave
+constexpr uint32_t LCAP = 64;                  // LDS list slots per wave
 // Check-only entry (.z): the meeting check of a vertex that was extracted
 // locally in a search with partner copies, repeated in the next round.
 // Within one launch another XCD's write of a partner copy may not be
