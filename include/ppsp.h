@@ -51,7 +51,7 @@ enum {
     PPSP_E_OOM = -3,       /* device memory (or the search-state budget) is exhausted */
     PPSP_E_OVERFLOW = -4,  /* a tentative distance reached 2^32-1 */
     PPSP_E_NOCOORD = -5,   /* A* mode on a graph without consistent coordinates */
-    PPSP_E_NOTSYM = -6,    /* a bidirectional or batch mode on a graph not flagged symmetric */
+    PPSP_E_NOTSYM = -6,    /* reserved: no call returns it (every mode runs on directed graphs) */
     PPSP_E_DEVICE = -7,    /* a HIP runtime error */
     PPSP_E_BUSY = -8,      /* (serving) the request has not finished, or the graph belongs to a server */
     PPSP_E_PATHCAP = -9,   /* the caller's path buffer is too small; *path_len gets the need */
@@ -171,7 +171,9 @@ int ppsp_graph_destroy(ppsp_graph g);
  *   path      host buffer of path_cap vertex ids, or NULL; filled with an
  *             s->t shortest path (s first, t last) when opts->flags has
  *             PPSP_WANT_PATH; *path_len gets its length (0 if unreachable)
- * Errors: PPSP_E_RANGE (s or t >= n), PPSP_E_NOCOORD, PPSP_E_NOTSYM,
+ * On a graph not flagged PPSP_SYMMETRIC the backward search of BiDS and
+ * BiD-A* walks the transposed graph.
+ * Errors: PPSP_E_RANGE (s or t >= n), PPSP_E_NOCOORD,
  * PPSP_E_OVERFLOW, PPSP_E_PATHCAP (path_cap too small; *path_len = need),
  * PPSP_E_NOPATH, PPSP_E_OOM, PPSP_E_DEVICE.
  */
@@ -190,10 +192,14 @@ int ppsp_query(ppsp_graph g, uint32_t s, uint32_t t, const ppsp_opts *opts, void
  * The SSSP-based strategies of Section 4.2 run one search without pruning per
  * root and read every query's distance off its root's search: Plain-SSSP
  * (PPSP_BATCH_SSSP) roots one search at every distinct source; VC-SSSP
- * (PPSP_BATCH_VC, symmetric graphs) at the vertices of a vertex cover of the
- * query graph (exact minimum per component of at most 16 query-graph
- * vertices, greedy by uncovered degree above that), each query answered by a
- * cover endpoint. Both take algo = PPSP_SSSP. PPSP_BATCH_AUTO (algo =
+ * (PPSP_BATCH_VC) at the vertices of a vertex cover of the query graph
+ * (ppsp_query_cover: exact minimum per component of at most 16 query-graph
+ * vertices, greedy by uncovered degree above that; on a directed graph the
+ * query graph is bipartite and the cover an exact minimum, a covered target
+ * running a backward search on the transpose), each query answered by a
+ * cover endpoint. Both take algo = PPSP_SSSP. On a directed graph Multi-BiDS
+ * starts a forward search from every source and a backward search from every
+ * target (a vertex that is both gets both). PPSP_BATCH_AUTO (algo =
  * PPSP_BIDS) runs VC-SSSP when the cover has at most a quarter of the
  * query-graph vertices (star- and fork-like batches, where one search
  * answers many queries), else Multi-BiDS.
@@ -402,6 +408,24 @@ int ppsp_last_stats(ppsp_graph g, ppsp_stats *stats);
  */
 int ppsp_set_option(ppsp_graph g, const char *name, int64_t value);
 int ppsp_get_option(ppsp_graph g, const char *name, int64_t *value);
+
+/*
+ * The query-graph vertex cover that PPSP_BATCH_VC runs on (Section 4.2 and
+ * the adaptation to directed graphs): the k pairs (pairs[2q], pairs[2q+1])
+ * are the edges of the query graph. Undirected (directed = 0): (s, t) and
+ * (t, s) are one edge; the cover is an exact minimum in every connected
+ * component of at most 16 vertices and greedy by uncovered degree in larger
+ * ones. Directed: the query graph is bipartite (sources, targets) and the
+ * cover is an exact minimum (Hopcroft-Karp matching and Koenig's theorem).
+ * root[q] receives the endpoint whose single-source search answers pair q
+ * and from_target[q] 1 when that endpoint is the pair's target (on a
+ * directed graph: a backward search on the transpose). A pair with s = t
+ * needs no search: root[q] = s, not counted. *cover_size receives the number
+ * of searches (distinct roots, with their direction when directed). Host
+ * function; caller-owned arrays of k entries. Errors: PPSP_E_INVALID.
+ */
+int ppsp_query_cover(const uint32_t *pairs, uint32_t k, uint32_t directed, uint32_t *root, uint8_t *from_target,
+                     uint32_t *cover_size);
 
 /*
  * The heuristic of Sections 3.3 and 3.5 on fixed-point coordinates,

@@ -95,7 +95,8 @@ EXPORTS = ["ppsp_graph_create", "ppsp_graph_destroy", "ppsp_query", "ppsp_batch_
            "ppsp_set_option", "ppsp_get_option", "ppsp_heuristic_fx", "ppsp_status_str", "ppsp_version",
            "ppsp_last_error", "ppsp_tune", "ppsp_server_create", "ppsp_server_submit", "ppsp_server_poll",
            "ppsp_server_wait", "ppsp_server_stats", "ppsp_server_destroy", "ppsp_mlp_forward", "ppsp_mlp_grad",
-           "ppsp_mlp_train", "ppsp_mlp_load", "ppsp_sched_trace", "ppsp_mlp_fit", "ppsp_randbench"]
+           "ppsp_mlp_train", "ppsp_mlp_load", "ppsp_sched_trace", "ppsp_mlp_fit", "ppsp_randbench",
+           "ppsp_query_cover"]
 
 _lib_handle = None
 
@@ -162,6 +163,8 @@ def lib():
         L.ppsp_sched_trace.restype = ctypes.c_int
         L.ppsp_randbench.argtypes = [ctypes.c_int, u64, u64, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
         L.ppsp_randbench.restype = ctypes.c_int
+        L.ppsp_query_cover.argtypes = [P, u32, u32, P, P, ctypes.POINTER(u32)]
+        L.ppsp_query_cover.restype = ctypes.c_int
         _lib_handle = L
     return _lib_handle
 
@@ -321,6 +324,19 @@ def mlp_train(params, X, y, epochs, batch=512, lr=2e-3, seed=0, device=0):
     _check(lib().ppsp_mlp_train(device, _ptr(p), _ptr(X), _ptr(y), X.shape[0], int(epochs), int(batch), float(lr),
                                 int(seed), ctypes.byref(l0), ctypes.byref(l1)), "ppsp_mlp_train")
     return p, l0.value, l1.value
+
+
+def query_cover(pairs, directed=False):
+    """(root per pair, 1 where the root is the pair's target, searches) of the
+    query-graph vertex cover PPSP_BATCH_VC uses (ppsp_query_cover; host only)."""
+    pairs = np.ascontiguousarray(pairs, np.uint32).reshape(-1, 2)
+    k = pairs.shape[0]
+    root = np.empty(k, np.uint32)
+    ft = np.empty(k, np.uint8)
+    size = ctypes.c_uint32(0)
+    _check(lib().ppsp_query_cover(_ptr(pairs), k, 1 if directed else 0, _ptr(root), _ptr(ft), ctypes.byref(size)),
+           "ppsp_query_cover")
+    return root, ft, int(size.value)
 
 
 def randbench(words, accesses, kind, device=0) -> float:

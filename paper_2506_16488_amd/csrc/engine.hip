@@ -598,13 +598,10 @@ int check_opts(ppsp_graph g, const ppsp_opts *o) {
     if (!o) return PPSP_E_INVALID;
     if (o->algo > PPSP_BIDASTAR || o->batch > PPSP_BATCH_AUTO || o->sched > PPSP_SCHED_RHO) return PPSP_E_INVALID;
     if (is_astar(o->algo) && !g->xy_ok) return PPSP_E_NOCOORD;
-    // directed graphs: bidirectional searches run their backward half on the
-    // transpose (Plain, Plain*, single queries); the query-graph strategies
-    // assume an undirected query graph
-    if (!g->symmetric && (o->batch == PPSP_BATCH_MULTI || o->batch == PPSP_BATCH_AUTO)) return PPSP_E_NOTSYM;
+    // directed graphs: backward searches run on the transpose, and the query
+    // graph of the shared-search strategies is bipartite (sources, targets)
     if ((o->batch == PPSP_BATCH_MULTI || o->batch == PPSP_BATCH_AUTO) && o->algo != PPSP_BIDS) return PPSP_E_INVALID;
     if ((o->batch == PPSP_BATCH_SSSP || o->batch == PPSP_BATCH_VC) && o->algo != PPSP_SSSP) return PPSP_E_INVALID;
-    if (o->batch == PPSP_BATCH_VC && !g->symmetric) return PPSP_E_NOTSYM;
     if ((o->flags & PPSP_WANT_PATH) && g->wmin == 0 && g->m > 0) return PPSP_E_NOPATH;
     if (o->sched == PPSP_SCHED_LEARNED && !g->mlp_loaded) return PPSP_E_INVALID;
     return PPSP_OK;
@@ -689,23 +686,31 @@ int run_independent(ppsp_graph g, const std::vector<Query> &qs, const ppsp_opts 
 }
 
 // Multi-BiDS (Section 4.2): searches are the query-graph vertices, waves are
-// unions of whole query-graph components.
+// unions of whole query-graph components. On a directed graph the query
+// graph is bipartite (Appendix on directed graphs): a source gets a forward
+// search, a target a backward search on the transpose, and a vertex that is
+// both gets both.
 int run_multi(ppsp_graph g, const std::vector<Query> &qs, const ppsp_opts *o, uint64_t delta,
               std::vector<Answer> &ans) {
     const bool want_path = o->flags & PPSP_WANT_PATH;
-    // query graph G_q: vertex ids and adjacency (Section 4.1)
-    std::unordered_map<uint32_t, uint32_t> vid;
+    // query graph G_q: vertex ids and adjacency (Section 4.1); a vertex id
+    // carries its direction (always forward on a symmetric graph)
+    std::unordered_map<uint64_t, uint32_t> vid;
     std::vector<uint32_t> verts;
-    auto id_of = [&](uint32_t v) {
-        auto it = vid.find(v);
+    std::vector<uint8_t> vrev;
+    auto id_of = [&](uint32_t v, uint8_t rev) {
+        const uint64_t key = ((uint64_t)rev << 32) | v;
+        auto it = vid.find(key);
         if (it != vid.end()) return it->second;
         uint32_t k = (uint32_t)verts.size();
-        vid.emplace(v, k);
+        vid.emplace(key, k);
         verts.push_back(v);
+        vrev.push_back(rev);
         return k;
     };
+    const uint8_t trev = g->symmetric ? 0 : 1;
     std::vector<std::pair<uint32_t, uint32_t>> qe(qs.size());
-    for (size_t q = 0; q < qs.size(); q++) qe[q] = {id_of(qs[q].s), id_of(qs[q].t)};
+    for (size_t q = 0; q < qs.size(); q++) qe[q] = {id_of(qs[q].s, 0), id_of(qs[q].t, trev)};
     const uint32_t nv = (uint32_t)verts.size();
     // components (union-find)
     std::vector<uint32_t> par(nv);
@@ -733,6 +738,7 @@ int run_multi(ppsp_graph g, const std::vector<Query> &qs, const ppsp_opts *o, ui
             for (uint32_t v : comp_verts[c]) {
                 local[v] = (uint32_t)P.sd.size();
                 P.sd.push_back(make_sd(g, verts[v], K_2DIST, verts[v], verts[v]));
+                P.sd.back().rev = vrev[v];
                 P.delta.push_back(key_delta(K_2DIST, delta));
                 P.bin.push_back((uint8_t)(MLP_K / 2));
             }
@@ -784,11 +790,114 @@ int run_multi(ppsp_graph g, const std::vector<Query> &qs, const ppsp_opts *o, ui
     return flush();
 }
 
-// A vertex cover of the query graph (edges = queries): exact minimum per
-// connected component of at most 16 vertices (smallest mask among the
-// minimum ones), greedy by uncovered degree otherwise. Returns, per query,
-// the cover endpoint that answers it.
-std::vector<uint32_t> query_cover(const std::vector<Query> &qs) {
+// Minimum vertex cover of a bipartite graph (left: nl sources, right: nr
+// targets, one edge per query) by Koenig's theorem: a maximum matching
+// (Hopcroft-Karp: BFS layers from the free left vertices, then vertex-
+// disjoint shortest augmenting paths by DFS, repeated until none is left),
+// then Z = the vertices reachable from free left vertices by alternating
+// paths; the cover is (left \ Z) + (right in Z). Returns, per edge, 1 if its
+// left endpoint covers it (else its right endpoint does).
+std::vector<uint8_t> bipartite_cover(uint32_t nl, uint32_t nr, const std::vector<std::pair<uint32_t, uint32_t>> &e) {
+    const uint32_t NIL = UINT32_MAX, FAR = UINT32_MAX;
+    std::vector<std::vector<uint32_t>> adj(nl);
+    for (const auto &x : e) adj[x.first].push_back(x.second);
+    std::vector<uint32_t> ml(nl, NIL), mr(nr, NIL), lay(nl, FAR);
+    auto layers = [&]() {
+        std::deque<uint32_t> Q;
+        bool free_right = false;
+        for (uint32_t u = 0; u < nl; u++) {
+            lay[u] = ml[u] == NIL ? 0 : FAR;
+            if (ml[u] == NIL) Q.push_back(u);
+        }
+        while (!Q.empty()) {
+            const uint32_t u = Q.front();
+            Q.pop_front();
+            for (uint32_t v : adj[u]) {
+                const uint32_t w = mr[v];
+                if (w == NIL) free_right = true;
+                else if (lay[w] == FAR) { lay[w] = lay[u] + 1; Q.push_back(w); }
+            }
+        }
+        return free_right;
+    };
+    // One augmenting path from free left vertex r along the layers (iterative
+    // DFS: st holds (left vertex, next arc), via the right vertices taken).
+    auto augment = [&](uint32_t r) {
+        std::vector<std::pair<uint32_t, size_t>> st{{r, 0}};
+        std::vector<uint32_t> via;
+        while (!st.empty()) {
+            const uint32_t u = st.back().first;
+            const size_t k = st.back().second;
+            if (k == adj[u].size()) {
+                lay[u] = FAR;                  // dead end for this phase
+                st.pop_back();
+                if (!via.empty()) via.pop_back();
+                continue;
+            }
+            st.back().second = k + 1;
+            const uint32_t v = adj[u][k], w = mr[v];
+            if (w == NIL) {
+                via.push_back(v);
+                for (size_t j = 0; j < st.size(); j++) {
+                    ml[st[j].first] = via[j];
+                    mr[via[j]] = st[j].first;
+                }
+                return true;
+            }
+            if (lay[w] != FAR && lay[w] == lay[u] + 1) {
+                via.push_back(v);
+                st.push_back({w, 0});
+            }
+        }
+        return false;
+    };
+    while (layers())
+        for (uint32_t u = 0; u < nl; u++)
+            if (ml[u] == NIL) augment(u);
+    std::vector<uint8_t> zl(nl, 0), zr(nr, 0);
+    std::deque<uint32_t> Q;
+    for (uint32_t u = 0; u < nl; u++)
+        if (ml[u] == NIL) { zl[u] = 1; Q.push_back(u); }
+    while (!Q.empty()) {
+        const uint32_t u = Q.front();
+        Q.pop_front();
+        for (uint32_t v : adj[u]) {
+            if (ml[u] == v || zr[v]) continue;
+            zr[v] = 1;
+            const uint32_t w = mr[v];
+            if (w != NIL && !zl[w]) { zl[w] = 1; Q.push_back(w); }
+        }
+    }
+    std::vector<uint8_t> by_left(e.size());
+    for (size_t q = 0; q < e.size(); q++) by_left[q] = zl[e[q].first] ? 0 : 1;
+    return by_left;
+}
+
+// A vertex cover of the query graph (edges = queries). Undirected: exact
+// minimum per connected component of at most 16 vertices (smallest mask
+// among the minimum ones), greedy by uncovered degree otherwise. Directed:
+// the query graph is bipartite (sources, targets) and its minimum cover is
+// exact (bipartite_cover). Returns, per query, the cover endpoint that
+// answers it; rev[q] = 1 when that endpoint is the target of a directed
+// query (a backward search on the transpose).
+std::vector<uint32_t> query_cover(const std::vector<Query> &qs, bool directed, std::vector<uint8_t> &rev) {
+    rev.assign(qs.size(), 0);
+    if (directed) {
+        std::unordered_map<uint32_t, uint32_t> lid, rid;
+        std::vector<std::pair<uint32_t, uint32_t>> e(qs.size());
+        for (size_t q = 0; q < qs.size(); q++) {
+            const uint32_t a = lid.emplace(qs[q].s, (uint32_t)lid.size()).first->second;
+            const uint32_t b = rid.emplace(qs[q].t, (uint32_t)rid.size()).first->second;
+            e[q] = {a, b};
+        }
+        const std::vector<uint8_t> by_left = bipartite_cover((uint32_t)lid.size(), (uint32_t)rid.size(), e);
+        std::vector<uint32_t> by(qs.size());
+        for (size_t q = 0; q < qs.size(); q++) {
+            by[q] = by_left[q] ? qs[q].s : qs[q].t;
+            rev[q] = by_left[q] ? 0 : 1;
+        }
+        return by;
+    }
     std::unordered_map<uint32_t, uint32_t> vid;
     std::vector<uint32_t> verts;
     auto id_of = [&](uint32_t v) {
@@ -864,11 +973,13 @@ std::vector<uint32_t> query_cover(const std::vector<Query> &qs) {
 // Plain-SSSP and VC-SSSP (Section 4.2): one search without pruning per root,
 // each query read off its root's search (a gather after the rounds).
 int run_cover(ppsp_graph g, const std::vector<Query> &qs, const ppsp_opts *o, uint64_t delta,
-              std::vector<Answer> &ans, const std::vector<uint32_t> &root_of) {
+              std::vector<Answer> &ans, const std::vector<uint32_t> &root_of, const std::vector<uint8_t> &root_rev) {
     const bool want_path = o->flags & PPSP_WANT_PATH;
-    std::map<uint32_t, std::vector<uint32_t>> by_root;
-    for (size_t q = 0; q < qs.size(); q++) by_root[root_of[q]].push_back((uint32_t)q);
-    std::vector<uint32_t> roots;
+    // roots keyed by (direction, vertex): a backward root walks the transpose
+    std::map<uint64_t, std::vector<uint32_t>> by_root;
+    for (size_t q = 0; q < qs.size(); q++)
+        by_root[((uint64_t)root_rev[q] << 32) | root_of[q]].push_back((uint32_t)q);
+    std::vector<uint64_t> roots;
     for (auto &kv : by_root) roots.push_back(kv.first);
     const uint64_t lim = std::max<uint64_t>(1, search_limit(g));
     for (size_t r0 = 0; r0 < roots.size(); r0 += lim) {
@@ -878,15 +989,16 @@ int run_cover(ppsp_graph g, const std::vector<Query> &qs, const ppsp_opts *o, ui
         P.gather = true;
         std::vector<uint32_t> ans_of_pair;
         for (size_t r = r0; r < r1; r++) {
-            const uint32_t root = roots[r];
+            const uint32_t root = (uint32_t)roots[r];
             const uint32_t a = (uint32_t)P.sd.size();
             SearchDesc sd = make_sd(g, root, K_DIST, root, root);
+            sd.rev = (uint32_t)(roots[r] >> 32);
             sd.noprune = 1;
             sd.pbeg = sd.pend = 0;
             P.sd.push_back(sd);
             P.delta.push_back(key_delta(K_DIST, delta));
             P.bin.push_back((uint8_t)(MLP_K / 2));
-            for (uint32_t q : by_root[root]) {
+            for (uint32_t q : by_root[roots[r]]) {
                 const uint32_t other = qs[q].s == root ? qs[q].t : qs[q].s;
                 P.pairs.push_back({a, TARGET_BIT | other});
                 ans_of_pair.push_back(q);
@@ -989,19 +1101,22 @@ int batch_impl(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp_opts 
         if (o->batch == PPSP_BATCH_SSSP) {
             std::vector<uint32_t> root_of(qs.size());
             for (size_t q = 0; q < qs.size(); q++) root_of[q] = qs[q].s;
-            CHK(run_cover(g, qs, o, delta, ans, root_of));
+            CHK(run_cover(g, qs, o, delta, ans, root_of, std::vector<uint8_t>(qs.size(), 0)));
         } else if (o->batch == PPSP_BATCH_VC || o->batch == PPSP_BATCH_AUTO) {
-            const std::vector<uint32_t> root_of = query_cover(qs);
-            std::unordered_map<uint32_t, char> cover, vq;
+            std::vector<uint8_t> root_rev;
+            const std::vector<uint32_t> root_of = query_cover(qs, !g->symmetric, root_rev);
+            // query-graph vertices and cover vertices, with their direction on a directed graph
+            const uint64_t tdir = g->symmetric ? 0 : 1ull << 32;
+            std::unordered_map<uint64_t, char> cover, vq;
             for (size_t q = 0; q < qs.size(); q++) {
-                cover[root_of[q]] = 1;
+                cover[((uint64_t)root_rev[q] << 32) | root_of[q]] = 1;
                 vq[qs[q].s] = 1;
-                vq[qs[q].t] = 1;
+                vq[tdir | qs[q].t] = 1;
             }
             if (o->batch == PPSP_BATCH_VC || 4 * cover.size() <= vq.size()) {
                 ppsp_opts oo = *o;
                 oo.algo = PPSP_SSSP;
-                CHK(run_cover(g, qs, &oo, delta, ans, root_of));
+                CHK(run_cover(g, qs, &oo, delta, ans, root_of, root_rev));
             } else {
                 ppsp_opts oo = *o;
                 oo.batch = PPSP_BATCH_MULTI;
@@ -1433,6 +1548,7 @@ int srv_chunk(ppsp_server srv, bool &any_running) {
                 SearchDesc b = make_sd(G.g, t0, G.sd[2 * slot + 1].kind, s0, t0);
                 f.pbeg = G.sd[2 * slot].pbeg; f.pend = G.sd[2 * slot].pend;
                 b.pbeg = G.sd[2 * slot + 1].pbeg; b.pend = G.sd[2 * slot + 1].pend;
+                b.rev = G.g->symmetric ? 0u : 1u;    // directed: the backward half walks the transpose
                 G.sd[2 * slot] = f;
                 G.sd[2 * slot + 1] = b;
                 admit[gi].push_back(slot);
@@ -1575,6 +1691,39 @@ const char *ppsp_status_str(int s) {
         case PPSP_E_TIMEOUT: return "round loop exceeded its time limit";
         default: return "unknown status";
     }
+}
+
+int ppsp_query_cover(const uint32_t *pairs, uint32_t k, uint32_t directed, uint32_t *root, uint8_t *from_target,
+                     uint32_t *cover_size) {
+    if ((k && (!pairs || !root || !from_target)) || !cover_size) return PPSP_E_INVALID;
+    std::vector<Query> qs;
+    std::vector<uint32_t> qidx(k, UINT32_MAX);
+    std::vector<uint8_t> flip(k, 0);
+    std::unordered_map<uint64_t, uint32_t> seen;
+    for (uint32_t i = 0; i < k; i++) {
+        uint32_t s = pairs[2 * i], t = pairs[2 * i + 1];
+        if (s == t) continue;
+        if (!directed && s > t) { std::swap(s, t); flip[i] = 1; }
+        const uint64_t key = ((uint64_t)s << 32) | t;
+        auto it = seen.emplace(key, (uint32_t)qs.size()).first;
+        if (it->second == qs.size()) qs.push_back({s, t});
+        qidx[i] = it->second;
+    }
+    std::vector<uint8_t> rev;
+    const std::vector<uint32_t> by = query_cover(qs, directed != 0, rev);
+    std::unordered_map<uint64_t, char> roots;
+    for (size_t q = 0; q < qs.size(); q++) roots[((uint64_t)rev[q] << 32) | by[q]] = 1;
+    for (uint32_t i = 0; i < k; i++) {
+        if (qidx[i] == UINT32_MAX) {                       // s = t: no search
+            root[i] = pairs[2 * i];
+            from_target[i] = 0;
+            continue;
+        }
+        root[i] = by[qidx[i]];
+        from_target[i] = root[i] == pairs[2 * i + 1] ? 1 : 0;
+    }
+    *cover_size = (uint32_t)roots.size();
+    return PPSP_OK;
 }
 
 uint64_t ppsp_heuristic_fx(int32_t x0, int32_t y0, int32_t x1, int32_t y1, uint32_t w_scale, uint32_t frac_bits) {
@@ -2028,7 +2177,6 @@ int ppsp_server_create(const ppsp_graph *graphs, uint32_t ngraphs, const ppsp_op
         if (!graphs[i] || graphs[i]->served) return PPSP_E_INVALID;
         for (uint32_t j = 0; j < i; j++)
             if (graphs[j] == graphs[i]) return PPSP_E_INVALID;
-        if (!graphs[i]->symmetric) return PPSP_E_NOTSYM;
         if (opts[i].algo == PPSP_BIDASTAR && !graphs[i]->xy_ok) return PPSP_E_NOCOORD;
         if (graphs[i]->device != graphs[0]->device) return PPSP_E_INVALID;
     }

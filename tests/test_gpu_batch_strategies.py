@@ -85,15 +85,52 @@ def test_strategy_errors_and_directed(P):
             G.batch_query(pairs, algo=algo, batch=batch)
         assert e.value.code == P.E_INVALID
     G.close()
-    # directed graph: Plain-SSSP runs, VC-SSSP needs a symmetric graph
-    d = gen.random_graph(500, 3000, 100, seed=94, symmetric=False)
+
+
+
+def _directed_graph(kind):
+    if kind == "lattice":
+        g = gen.lattice(90, 0.1, seed=95)
+        rng = np.random.default_rng(96)
+        w = (g.w.astype(np.int64) + rng.integers(0, 800, g.w.shape[0])).astype(np.uint32)
+        return gen.csr_from_edges(g.n, np.repeat(np.arange(g.n), np.diff(g.row_ptr.astype(np.int64))),
+                                  g.col.astype(np.int64), w.astype(np.int64), symmetric=False)
+    if kind == "random":
+        return gen.random_graph(3000, 9000, 200, seed=97, symmetric=False)
+    r = gen.rmat(12, 16, seed=98)            # hubs: half of an R-MAT graph's arcs
+    src = np.repeat(np.arange(r.n, dtype=np.int64), np.diff(r.row_ptr.astype(np.int64)))
+    keep = np.random.default_rng(99).random(src.shape[0]) < 0.5
+    return gen.csr_from_edges(r.n, src[keep], r.col[keep].astype(np.int64), r.w[keep].astype(np.int64),
+                              symmetric=False)
+
+
+@pytest.mark.parametrize("kind", ["lattice", "random", "hubs"])
+def test_directed_patterns_all_strategies(P, kind):
+    """Directed graphs (the adaptation to directed graphs): Multi-BiDS starts
+    a forward search from every source and a backward one (on the transpose)
+    from every target; VC-SSSP covers the bipartite query graph exactly."""
+    d = _directed_graph(kind)
     D = P.Graph.from_host(d)
-    pairs = gen.batch_pattern("clique", d.n, seed=6)
-    exp = oracle.pp_batch(d.n, d.row_ptr, d.col, d.w, pairs)
-    assert np.array_equal(D.batch_query(pairs, algo="sssp", batch="sssp"), exp)
-    dist, (off, vtx) = D.batch_query(pairs, algo="sssp", batch="sssp", want_path=True)
-    _check_paths(d, pairs, dist, off, vtx)
-    with pytest.raises(P.PPSPError) as e:
+    D.set_option("timeout_ms", 60000)
+    for j, pat in enumerate(gen.PATTERNS):
+        pairs = gen.batch_pattern(pat, d.n, seed=600 + j)
+        exp = oracle.pp_batch(d.n, d.row_ptr, d.col, d.w, pairs)
+        for algo, batch in STRATS:
+            assert np.array_equal(D.batch_query(pairs, algo=algo, batch=batch), exp), (kind, pat, algo, batch)
+        real = pairs[pairs[:, 0] != pairs[:, 1]]
         D.batch_query(pairs, algo="sssp", batch="vc")
-    assert e.value.code == P.E_NOTSYM
+        assert D.stats()["searches"] == P.query_cover(real, directed=True)[2], pat
+        D.batch_query(pairs, algo="bids", batch="multi")
+        assert D.stats()["searches"] == len(set(real[:, 0].tolist())) + len(set(real[:, 1].tolist())), pat
+        if kind != "random" or pat in ("star", "chain"):
+            for algo, batch in [("sssp", "vc"), ("bids", "multi")]:
+                dist, (off, vtx) = D.batch_query(pairs, algo=algo, batch=batch, want_path=True)
+                assert np.array_equal(dist, exp)
+                _check_paths(d, pairs, dist, off, vtx)
+    # a reversed star: one backward search from the common target covers it
+    star = gen.batch_pattern("star", d.n, seed=650, m=20)[:, ::-1].copy()
+    exp = oracle.pp_batch(d.n, d.row_ptr, d.col, d.w, star)
+    assert np.array_equal(D.batch_query(star, algo="sssp", batch="vc"), exp)
+    assert D.stats()["searches"] == 1
+    assert np.array_equal(D.batch_query(star, algo="bids", batch="auto"), exp)
     D.close()

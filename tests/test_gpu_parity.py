@@ -200,9 +200,9 @@ def test_error_paths(P):
     G.close()
     d = gen.csr_from_edges(3, [0, 1], [1, 2], [1, 1], symmetric=False)
     D = P.Graph(d.n, d.row_ptr, d.col, d.w, symmetric=False)
-    with pytest.raises(P.PPSPError) as e:
-        D.batch_query(np.array([[0, 2]]), algo="bids", batch="multi")
-    assert e.value.code == P.E_NOTSYM                      # the query-graph strategies need symmetry
+    # the query graph of a directed batch is bipartite: sources forward, targets backward
+    assert D.batch_query(np.array([[0, 2], [2, 0]]), algo="bids", batch="multi").tolist() == [2, INF]
+    assert D.batch_query(np.array([[0, 2], [2, 0]]), algo="sssp", batch="vc").tolist() == [2, INF]
     assert D.query(0, 2, algo="bids") == 2                  # the backward search walks the transpose
     assert D.query(2, 0, algo="bids") == INF
     assert D.query(0, 2, algo="et") == 2

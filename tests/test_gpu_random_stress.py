@@ -44,8 +44,7 @@ def test_random_graphs_every_mode(P, seed):
         G.set_option("timeout_ms", 60000)
         strategies = [("sssp", "plainstar"), ("et", "plainstar"), ("bids", "plainstar"), ("bids", "plain"),
                       ("sssp", "sssp")]
-        if g.symmetric:
-            strategies += [("bids", "multi"), ("sssp", "vc"), ("bids", "auto")]
+        strategies += [("bids", "multi"), ("sssp", "vc"), ("bids", "auto")]   # bipartite query graph if directed
         for algo, batch in strategies:
             got = G.batch_query(pairs, algo=algo, batch=batch)
             assert np.array_equal(got, exp), (seed, reorder, algo, batch)

@@ -169,3 +169,25 @@ def test_server_errors_and_release(P):
     p = gen.pairs_uniform(g.n, 10, seed=1)
     assert np.array_equal(G.batch_query(p, algo="bids"), _oracle(g, p))  # usable again
     G.close()
+
+
+def test_server_directed_graph(P):
+    """A directed graph served with BiDS: the backward half of every admitted
+    query walks the transpose."""
+    g = gen.lattice(100, 0.1, seed=31)
+    rng = np.random.default_rng(32)
+    src = np.repeat(np.arange(g.n), np.diff(g.row_ptr.astype(np.int64)))
+    w = g.w.astype(np.int64) + rng.integers(0, 800, g.w.shape[0])
+    d = gen.csr_from_edges(g.n, src, g.col.astype(np.int64), w, symmetric=False)
+    reqs = _requests([d], [5, 17, 3, 30, 9], seed=33)
+    exp = [_oracle(d, p) for _, p in reqs]
+    rev = oracle.pp_batch(d.n, d.row_ptr, d.col, d.w, reqs[3][1][:, ::-1].copy())
+    assert not np.array_equal(rev, exp[3])                   # the graph really is directed
+    D = P.Graph.from_host(d)
+    S = P.Server([D], algo="bids", state_budget_bytes=24 * d.n * 4)
+    ids = [S.submit(0, p) for _, p in reqs]
+    for r, e in zip(ids, exp):
+        got, _ = S.wait(r, timeout_ms=120000)
+        assert np.array_equal(got, e)
+    S.close()
+    D.close()
