@@ -115,7 +115,7 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=64)
     ap.add_argument("--latency-sample", type=int, default=40)
     ap.add_argument("--copy-kernel", action="store_true", help="run the 1 GiB copy used to calibrate counters")
-    ap.add_argument("--workload", default="lattice2048", choices=["lattice2048", "lattice4096hub", "rmat24", "serve"],
+    ap.add_argument("--workload", default="lattice2048", choices=["lattice2048", "lattice4096hub", "rmat24", "serve", "ranks"],
                     help="lattice2048: the headline line; the others are the further measured workloads")
     args = ap.parse_args()
     if args.copy_kernel:
@@ -458,7 +458,61 @@ def workload_serve(args):
           out["load_80"]["queries_per_s"], out["load_80"]["p50_ms"], serving=out)
 
 
-OTHER_WORKLOADS = {"lattice4096hub": workload_lattice4096hub, "rmat24": workload_rmat24, "serve": workload_serve}
+def workload_ranks(args):
+    """The distance-rank study of Section 6 on the 2048 x 2048 lattice: from
+    4 seeded sources, targets at distance ranks 10, 20, 40, ... up to the
+    farthest vertex (ranks from the library's own single-source distances),
+    each query answered alone by ET, A*, BiDS and BiD-A*; per rank the median
+    milliseconds over the sources, and the single-source search for scale."""
+    import numpy as np
+    import torch
+    import gen
+    import paper_2506_16488_amd as P
+    torch.cuda.set_device(0)
+    g = gen.config_graph(2)
+    G = P.Graph.from_host(g, device=0, reorder=True)
+    G.set_option("timeout_ms", 300000)
+    sources = gen.pairs_uniform(g.n, 4, seed=2026)[:, 0]
+    algos = ["et", "astar", "bids", "bidastar"]
+    per_rank = {}
+    sssp_ms = []
+    ladder_pairs = []
+    G.query(int(sources[0]), int(sources[1]), algo="bidastar")          # warm-up
+    for s in sources.tolist():
+        a = time.perf_counter()
+        d = G.sssp(s)
+        sssp_ms.append(1000 * (time.perf_counter() - a))
+        reach = int(np.sum(d != P.INF)) - 1
+        ranks = gen.rank_ladder(reach)
+        targets = gen.targets_by_rank(d, s, ranks)
+        for r, t in zip(ranks, targets.tolist()):
+            ladder_pairs.append((s, t, int(d[t])))
+            for algo in algos:
+                a = time.perf_counter()
+                got = G.query(s, t, algo=algo)
+                ms = 1000 * (time.perf_counter() - a)
+                assert got == d[t], (s, t, algo)
+                per_rank.setdefault("farthest" if r == reach else r, {}).setdefault(algo, []).append(ms)
+        print("# source %d: %d ranks" % (s, len(ranks)), file=sys.stderr, flush=True)
+    by_rank = {str(r): {a: round(float(np.median(v)), 3) for a, v in m.items()} for r, m in per_rank.items()}
+    bida = [ms for m in per_rank.values() for ms in m["bidastar"]]
+    extra = {"by_rank_median_ms": by_rank, "sssp_median_ms": round(float(np.median(sssp_ms)), 2),
+             "queries": len(ladder_pairs) * len(algos)}
+    if not args.no_cpu:
+        first = [p for p in ladder_pairs if p[0] == int(sources[0])]
+        sample = np.array([[s, t] for s, t, _ in first], np.uint32)
+        exp, cb = _cpu_baseline(g, sample, "the first source's whole ladder (ranks 10 to the farthest vertex)")
+        assert exp.tolist() == [dd for _, _, dd in first]
+        extra["cpu_baseline"] = cb
+    G.close()
+    mean_ms = float(np.mean(bida))
+    _line(args, "distance-rank ladder on the jittered 2048x2048 lattice (4 sources, targets at ranks 10, 20, 40, ... "
+                "to the farthest vertex), single queries; value = BiD-A* queries/s over the ladder",
+          1000.0 / mean_ms, mean_ms, **extra)
+
+
+OTHER_WORKLOADS = {"lattice4096hub": workload_lattice4096hub, "rmat24": workload_rmat24, "serve": workload_serve,
+                   "ranks": workload_ranks}
 
 
 if __name__ == "__main__":

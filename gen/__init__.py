@@ -312,3 +312,38 @@ def batch_pattern(kind: str, n_or_cand, seed: int, m: int = 6, k: int = 0) -> np
         verts = np.asarray(n_or_cand)[rng.choice(len(n_or_cand), m, replace=False)]
     e = pattern_edges(kind, m, k, seed + 1)
     return np.array([[verts[a], verts[b]] for a, b in e], np.uint32).reshape(-1, 2)
+
+
+# ---- distance-rank targets (the fine-grained percentile study of Section 6) ----
+# Selection only: the distances from the source are an input (from the oracle
+# in tests, from the library under test in the benchmark).
+
+UNREACHABLE = (1 << 64) - 1
+
+
+def rank_ladder(reachable: int, first: int = 10) -> list:
+    """Distance ranks first, 2*first, 4*first, ... below `reachable`, then the
+    farthest vertex (rank `reachable`)."""
+    out = []
+    r = first
+    while r < reachable:
+        out.append(r)
+        r *= 2
+    if reachable > 0:
+        out.append(reachable)
+    return out
+
+
+def targets_by_rank(dist, s: int, ranks) -> np.ndarray:
+    """The vertices at the given 1-based distance ranks from s: the vertices
+    other than s that s reaches, ordered by distance, ties by vertex id."""
+    dist = np.asarray(dist, np.uint64)
+    cand = np.nonzero(dist != np.uint64(UNREACHABLE))[0]
+    cand = cand[cand != s]
+    order = cand[np.lexsort((cand, dist[cand]))]
+    return np.array([order[r - 1] for r in ranks], np.uint32)
+
+
+def percentile_rank(reachable: int, x: float) -> int:
+    """Rank of the x-th distance percentile target: the x% farthest vertex."""
+    return max(1, min(reachable, int(np.ceil(x / 100.0 * reachable))))

@@ -181,6 +181,17 @@ int ppsp_query(ppsp_graph g, uint32_t s, uint32_t t, const ppsp_opts *opts, void
                uint64_t *dist, uint32_t *path, uint32_t path_cap, uint32_t *path_len);
 
 /*
+ * Single-source shortest paths from s (the SSSP row of Table 2: one search
+ * without pruning, run until its frontier is empty), with the stepping
+ * schedule of opts (delta, sched other than PPSP_SCHED_LEARNED; algo,
+ * batch and flags are ignored).
+ *   dist      host, n entries: d(s, v), PPSP_INF where v is unreachable
+ * Errors: PPSP_E_RANGE (s >= n), PPSP_E_INVALID, PPSP_E_BUSY (served
+ * graph), PPSP_E_OVERFLOW, PPSP_E_OOM, PPSP_E_DEVICE.
+ */
+int ppsp_sssp(ppsp_graph g, uint32_t s, const ppsp_opts *opts, void *hip_stream, uint64_t *dist);
+
+/*
  * A batch of k queries (Section 4): pairs[2q] = s_q, pairs[2q+1] = t_q (host).
  * Duplicate pairs, (t,s) mirrors and s = t are allowed.
  *   dist      host, k entries, in input order

@@ -96,7 +96,7 @@ EXPORTS = ["ppsp_graph_create", "ppsp_graph_destroy", "ppsp_query", "ppsp_batch_
            "ppsp_last_error", "ppsp_tune", "ppsp_server_create", "ppsp_server_submit", "ppsp_server_poll",
            "ppsp_server_wait", "ppsp_server_stats", "ppsp_server_destroy", "ppsp_mlp_forward", "ppsp_mlp_grad",
            "ppsp_mlp_train", "ppsp_mlp_load", "ppsp_sched_trace", "ppsp_mlp_fit", "ppsp_randbench",
-           "ppsp_query_cover"]
+           "ppsp_query_cover", "ppsp_sssp"]
 
 _lib_handle = None
 
@@ -165,6 +165,8 @@ def lib():
         L.ppsp_randbench.restype = ctypes.c_int
         L.ppsp_query_cover.argtypes = [P, u32, u32, P, P, ctypes.POINTER(u32)]
         L.ppsp_query_cover.restype = ctypes.c_int
+        L.ppsp_sssp.argtypes = [P, u32, ctypes.POINTER(Opts), P, P]
+        L.ppsp_sssp.restype = ctypes.c_int
         _lib_handle = L
     return _lib_handle
 
@@ -385,6 +387,13 @@ class Graph:
                     sched="fixed", pull=False):
         return batch_query(self.h, pairs, make_opts(algo, batch, sched, delta, want_path, memo, pull),
                            want_path=want_path)
+
+    def sssp(self, s, delta=0, sched="fixed"):
+        """Distances from s to every vertex (ppsp_sssp; PPSP_INF where unreachable)."""
+        dist = np.empty(self.n, np.uint64)
+        o = make_opts("sssp", "plain", sched, delta)
+        _check(lib().ppsp_sssp(self.h, int(s), ctypes.byref(o), current_stream(), _ptr(dist)), "ppsp_sssp")
+        return dist
 
     def stats(self) -> dict:
         return last_stats(self.h)

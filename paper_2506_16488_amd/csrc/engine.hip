@@ -1995,6 +1995,45 @@ int ppsp_query(ppsp_graph g, uint32_t s, uint32_t t, const ppsp_opts *opts, void
     return PPSP_OK;
 }
 
+int ppsp_sssp(ppsp_graph g, uint32_t s, const ppsp_opts *opts, void *hip_stream, uint64_t *dist) {
+    const auto t0 = std::chrono::steady_clock::now();
+    if (!g || !opts || !dist) return PPSP_E_INVALID;
+    if (g->served) return PPSP_E_BUSY;
+    if (s >= g->n) return PPSP_E_RANGE;
+    if (opts->sched == PPSP_SCHED_LEARNED || opts->sched > PPSP_SCHED_RHO) return PPSP_E_INVALID;
+    CHK(set_device(g));
+    g->last = ppsp_stats{};
+    hipEvent_t ev;
+    HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    HIPCHK(hipEventRecord(ev, (hipStream_t)hip_stream));
+    HIPCHK(hipStreamWaitEvent(g->st, ev, 0));
+    (void)hipEventDestroy(ev);
+    const uint32_t root = g->perm.empty() ? s : g->perm[s];
+    const uint64_t delta = opts->delta ? opts->delta : graph_default_delta(g);
+    // one search without pruning and without queries: it runs until its frontier is empty
+    Plan P;
+    P.G = 1;
+    SearchDesc sd = make_sd(g, root, K_DIST, root, root);
+    sd.noprune = 1;
+    P.sd.push_back(sd);
+    P.delta.push_back(key_delta(K_DIST, delta));
+    P.bin.push_back((uint8_t)(MLP_K / 2));
+    g->last.searches = 1;
+    WaveOut w;
+    CHK(run_wave(g, P, false, w));
+    accumulate(g, w);
+    std::vector<uint64_t> words(g->n);
+    HIPCHK(hipMemcpyAsync(words.data(), g->S.p, (uint64_t)g->n * 8, hipMemcpyDeviceToHost, g->st));
+    HIPCHK(hipStreamSynchronize(g->st));
+    const bool re = !g->iperm.empty();
+    for (uint32_t v = 0; v < g->n; v++) {
+        const uint32_t d32 = (uint32_t)(words[v] >> 32);
+        dist[re ? g->iperm[v] : v] = d32 == INF32 ? PPSP_INF : d32;
+    }
+    g->last.wall_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return PPSP_OK;
+}
+
 int ppsp_tune(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp_opts *opts, const char *cache_path,
               ppsp_tune_result *out) {
     if (!g || !pairs || k == 0 || !opts || !out) return PPSP_E_INVALID;
