@@ -119,10 +119,11 @@ typedef struct {
     uint64_t searches;         /* searches (frontier copies) in the batch */
     uint64_t waves;            /* memory waves the batch was split into */
     double wall_ms;            /* host wall time of the call */
-    double relax_kernel_ms;    /* summed duration of the round kernel (profiling on), else 0 */
+    double relax_kernel_ms;    /* summed duration of the timed round-kernel launches ("profile"), else 0 */
     uint64_t relax_launches;   /* number of round-kernel launches */
     uint64_t carried;          /* entries kept for a later round (key above the threshold) */
     uint64_t retries;          /* waves rerun after growing an overflowed frontier queue */
+    uint64_t relax_timed;      /* round-kernel launches timed ("profile"): relax_kernel_ms covers these */
 } ppsp_stats;
 
 typedef struct ppsp_graph_s *ppsp_graph;
@@ -379,8 +380,9 @@ int ppsp_last_stats(ppsp_graph g, ppsp_stats *stats);
 /*
  * Tuning knobs of a graph handle (not part of the method; they only change
  * launch shapes and bookkeeping):
- *   "profile"         1: time every round-kernel launch with HIP events carried
- *                     by the launch itself (hipExtLaunchKernel: no extra packets)
+ *   "profile"         K >= 1: time every K-th round-kernel launch (1: all) with HIP
+ *                     events carried by the launch itself (hipExtLaunchKernel: no extra
+ *                     packets); 0: off
  *   "rounds_per_sync" rounds launched between host checks for termination
  *   "grid_blocks"     single-wave workgroups of the round kernel (0 = 20 per compute unit)
  *   "mem_budget_mb"   cap on the search-state memory of one wave (0 = auto)

@@ -54,7 +54,7 @@ class Stats(ctypes.Structure):
                 ("relax_success", ctypes.c_uint64), ("searches", ctypes.c_uint64),
                 ("waves", ctypes.c_uint64), ("wall_ms", ctypes.c_double),
                 ("relax_kernel_ms", ctypes.c_double), ("relax_launches", ctypes.c_uint64),
-                ("carried", ctypes.c_uint64), ("retries", ctypes.c_uint64)]
+                ("carried", ctypes.c_uint64), ("retries", ctypes.c_uint64), ("relax_timed", ctypes.c_uint64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

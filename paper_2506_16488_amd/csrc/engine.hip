@@ -316,7 +316,7 @@ struct WaveOut {
     std::vector<uint64_t> path_off; // npair + 1
     unsigned long long stats[ST_N] = {0};
     double relax_ms = 0;
-    uint64_t launches = 0;
+    uint64_t launches = 0, timed = 0;   // round-kernel launches, and those timed
     // learned / traced schedule: per search
     std::vector<uint32_t> done_round;
     std::vector<unsigned long long> tot_arcs;
@@ -415,10 +415,11 @@ int run_wave(ppsp_graph g, const Plan &P, bool want_path, WaveOut &out) {
         HIPCHK(launch_init(A, st));
         const int K = std::max<int64_t>(1, g->opt_rounds_per_sync);
         const bool prof = g->opt_profile != 0;
+        const uint64_t every = prof ? (uint64_t)g->opt_profile : 0;   // time every `every`-th launch
         if (prof) CHK(ensure_events(g, 2 * (size_t)K));
         uint64_t r = 0;
         double relax_ms = 0;
-        uint64_t launches = 0;
+        uint64_t launches = 0, timed = 0;
         const auto t_start = std::chrono::steady_clock::now();
         bool timed_out = false;
         hipGraphExec_t gexec = nullptr;
@@ -436,15 +437,19 @@ int run_wave(ppsp_graph g, const Plan &P, bool want_path, WaveOut &out) {
             HIPCHK(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
         }
         for (;;) {
-            int kk;
+            int kk, nt = 0;
             if (gexec) {
                 HIPCHK(hipGraphLaunch(gexec, st));
                 kk = K + (K & 1);
                 r += kk;
             } else {
                 for (kk = 0; kk < K; kk++, r++) {
-                    if (prof) HIPCHK(launch_round(A, grid, st, g->ev[2 * kk], g->ev[2 * kk + 1]));
-                    else HIPCHK(launch_round(A, grid, st));
+                    if (prof && r % every == 0) {
+                        HIPCHK(launch_round(A, grid, st, g->ev[2 * nt], g->ev[2 * nt + 1]));
+                        nt++;
+                    } else {
+                        HIPCHK(launch_round(A, grid, st));
+                    }
                     if (A.hcap) HIPCHK(launch_heavy(A, grid, st));
                     HIPCHK(launch_control(A, st));
                 }
@@ -454,13 +459,12 @@ int run_wave(ppsp_graph g, const Plan &P, bool want_path, WaveOut &out) {
             HIPCHK(hipMemcpyAsync(g->h_poll + 2 * NSEG, g->err.p, 4, hipMemcpyDeviceToHost, st));
             HIPCHK(hipMemcpyAsync(g->h_poll + 2 * NSEG + 1, g->round.p, 4, hipMemcpyDeviceToHost, st));
             HIPCHK(hipStreamSynchronize(st));
-            if (prof) {
-                for (int k = 0; k < kk; k++) {
-                    float ms = 0;
-                    HIPCHK(hipEventElapsedTime(&ms, g->ev[2 * k], g->ev[2 * k + 1]));
-                    relax_ms += ms;
-                }
+            for (int k = 0; k < nt; k++) {
+                float ms = 0;
+                HIPCHK(hipEventElapsedTime(&ms, g->ev[2 * k], g->ev[2 * k + 1]));
+                relax_ms += ms;
             }
+            timed += nt;
             uint64_t pending = 0;
             const uint32_t next = g->h_poll[2 * NSEG + 1];   // round to run next
             for (uint32_t x = 0; x < (uint32_t)NSEG; x++) pending += g->h_poll[(next & 1) * NSEG + x];
@@ -518,6 +522,7 @@ int run_wave(ppsp_graph g, const Plan &P, bool want_path, WaveOut &out) {
         }
         out.relax_ms = relax_ms;
         out.launches = launches;
+        out.timed = timed;
         if (want_path) {
             CHK(ensure(g->pathlen, npair * 4));
             CHK(ensure(g->pathoff, (npair + 1) * 8));
@@ -626,6 +631,7 @@ void accumulate(ppsp_graph g, const WaveOut &w) {
     g->last.carried += w.stats[ST_CARRY];
     g->last.relax_kernel_ms += w.relax_ms;
     g->last.relax_launches += w.launches;
+    g->last.relax_timed += w.timed;
     g->last.waves += 1;
 }
 
