@@ -412,9 +412,15 @@ int ppsp_last_stats(ppsp_graph g, ppsp_stats *stats);
  *   "local_chunks"    up to this many chunks of 64 entries per wave per round are taken
  *                     from the wave's own additions whose key is within the round's
  *                     threshold, in the same launch, for heuristic searches (A*, BiD-A*):
- *                     a frontier advances several hops per round (default 4; 0 = off)
+ *                     a frontier advances several hops per round (default 16; 0 = off)
  *   "local_chunks_plain" the same for the other searches (ET, SSSP, BiDS, Multi-BiDS;
  *                     default 0: measured neutral to slower there)
+ *   "local_chunks_small" the budget instead in rounds whose frontier is small enough for
+ *                     chunks below 64 entries (default 4: single queries; a long serial
+ *                     chain per wave would set the round's length)
+ *   "min_chunk"       entries per chunk of the round kernel while the frontier is too small
+ *                     to give every workgroup a 64-entry chunk: the smallest power of two
+ *                     from min_chunk up that covers it (default 16; 64 = always 64)
  *   "local_fill"      local chunks only in rounds whose frontier holds fewer entries than
  *                     this (default 0 = every round)
  * Returns PPSP_E_INVALID for an unknown name.

@@ -345,6 +345,7 @@ __global__ __launch_bounds__(WAVE) void k_round(RoundArgs A) {
     const uint32_t my_cpre = A.cpre[par * (NSEG + 1) + lane_id() + 1];
     const uint32_t my_qc = (uint32_t)min((uint64_t)A.qcount[par * NSEG + lane_id()], A.qseg);
     const uint32_t nchunks = __shfl(my_cpre, NSEG - 1);
+    const uint32_t csize = A.cpre[par * (NSEG + 1)];         // entries per chunk this round
     if (blockIdx.x == 0 && lane_id() == 0) {
         A.round[1] = r;                                    // for k_control
         if (nchunks) atomicAdd(&A.stats[ST_ROUNDS], 1ull);
@@ -354,8 +355,11 @@ __global__ __launch_bounds__(WAVE) void k_round(RoundArgs A) {
 
     __shared__ uint4 lq[LCAP];
     uint32_t lpend = 0;                                    // listed local entries not yet taken
-    const uint32_t lmax = A.local > A.local_plain ? A.local : A.local_plain;
-    uint32_t lbud = (!PULL && lmax && (A.local_fill == 0 || (uint64_t)nchunks * WAVE < A.local_fill)) ? lmax : 0u;
+    // budget: local_small in rounds of small chunks (a small frontier: short
+    // rounds matter), local / local_plain in rounds of full chunks
+    const uint32_t lmain = A.local > A.local_plain ? A.local : A.local_plain;
+    const uint32_t lmax = (csize < (uint32_t)WAVE && lmain) ? A.local_small : lmain;
+    uint32_t lbud = (!PULL && lmax && (A.local_fill == 0 || (uint64_t)nchunks * csize < A.local_fill)) ? lmax : 0u;
     uint32_t ch = blockIdx.x;
     for (;;) {
         // The next chunk: this wave's own listed entries first, then the queue.
@@ -372,8 +376,8 @@ __global__ __launch_bounds__(WAVE) void k_round(RoundArgs A) {
             const uint32_t lo = (uint32_t)__popcll(__ballot(my_cpre <= ch));   // cpre[lo] <= ch < cpre[lo + 1]
             const uint32_t c0 = lo ? __shfl(my_cpre, lo - 1) : 0u;
             const uint64_t nseg = __shfl(my_qc, lo);
-            const uint64_t pos = (uint64_t)(ch - c0) * WAVE + lane_id();
-            valid = pos < nseg;
+            const uint64_t pos = (uint64_t)(ch - c0) * csize + lane_id();
+            valid = lane_id() < csize && pos < nseg;
             if (valid) ent = qin[(uint64_t)lo * A.qseg + pos];
             ch += gridDim.x;
         } else {
@@ -725,18 +729,29 @@ __global__ __launch_bounds__(WAVE) void k_heavy(RoundArgs A) {
 }
 
 // Prefix sum of the chunk counts of the NSEG segments of queue `q` (one
-// wave of 64 = NSEG lanes).
+// wave of 64 = NSEG lanes). A chunk is WAVE entries, or fewer while the
+// whole queue is too small to give every workgroup of the round kernel a
+// full chunk: then min_chunk, 2 min_chunk, ... entries (the fewest that
+// still cover the queue in one chunk per workgroup), so a small frontier is
+// spread over more waves, each with a shorter chain of dependent accesses.
+// The chunk size is stored in cpre[q][0].
 __device__ __forceinline__ void chunk_prefix(const RoundArgs &A, uint32_t q) {
     const uint32_t k = lane_id();
     const uint32_t n = (uint32_t)min((uint64_t)A.qcount[q * NSEG + k], A.qseg);
-    const uint32_t c = (n + WAVE - 1) / WAVE;
+    const unsigned long long tot = wave_sum_u64(n);
+    uint32_t ch = WAVE;
+    if (A.min_chunk && A.min_chunk < (uint32_t)WAVE) {
+        ch = A.min_chunk;
+        while (ch < (uint32_t)WAVE && tot > (unsigned long long)ch * A.grid) ch <<= 1;
+    }
+    const uint32_t c = (n + ch - 1) / ch;
     uint32_t x = c;
     for (int o = 1; o < WAVE; o <<= 1) {
         const uint32_t y = __shfl_up(x, o);
         if (k >= (uint32_t)o) x += y;
     }
     A.cpre[q * (NSEG + 1) + k + 1] = x;
-    if (k == 0) A.cpre[q * (NSEG + 1)] = 0;
+    if (k == 0) A.cpre[q * (NSEG + 1)] = ch;
 }
 
 __global__ __launch_bounds__(WAVE) void k_seed_prefix(RoundArgs A) { chunk_prefix(A, 0); }

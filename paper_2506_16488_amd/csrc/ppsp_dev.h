@@ -149,7 +149,8 @@ struct RoundArgs {
     uint64_t *mu;              // [npair] packed (distance, meeting vertex)
     uint4 *q0, *q1;            // frontier queues by round parity, NSEG segments of qseg entries
     uint32_t *qcount;          // [2][NSEG] segment lengths
-    uint32_t *cpre;            // [2][NSEG + 1] prefix sums of the segments' WAVE-entry chunk counts
+    uint32_t *cpre;            // [2][NSEG + 1]: [0] entries per chunk, [k + 1] prefix sums of the
+                               // chunk counts of segments 0..k
     uint64_t qseg;             // capacity of one segment (entries)
     uint32_t *round;           // [0] round to run next (read by k_round), [1] round just run (k_control)
     uint4 *heavy;              // [hcap][2] arc chunks of this round's extracted high-degree vertices:
@@ -199,6 +200,8 @@ struct RoundArgs {
     uint32_t local;
     uint32_t local_plain;
     uint32_t local_fill;
+    uint32_t local_small;      // the budget in rounds whose chunks are below WAVE entries
+    uint32_t min_chunk;        // smallest chunk of a small queue (a power of two <= WAVE; WAVE or 0: fixed)
 };
 
 // Only the first ML_SAMPLE workgroups of the round kernels update the

@@ -28,6 +28,7 @@ def _graph(P, g, local, fill=0, **kw):
     G.set_option("timeout_ms", 60000)
     G.set_option("local_chunks", local)
     G.set_option("local_chunks_plain", local)
+    G.set_option("local_chunks_small", local)
     G.set_option("local_fill", fill)
     return G
 
@@ -124,10 +125,32 @@ def test_directed_memo_and_reordered(P):
 def test_options_checked(P):
     g = gen.lattice(20, 0.1, seed=341)
     G = P.Graph.from_host(g)
-    assert G.get_option("local_chunks") == 4 and G.get_option("local_chunks_plain") == 0   # defaults
+    assert G.get_option("local_chunks") == 16 and G.get_option("local_chunks_plain") == 0   # defaults
+    assert G.get_option("local_chunks_small") == 4 and G.get_option("min_chunk") == 16
+    for name, bad in [("min_chunk", 0), ("min_chunk", 24), ("min_chunk", 128), ("local_chunks_small", -1)]:
+        with pytest.raises(P.PPSPError):
+            G.set_option(name, bad)
     for name, bad in [("local_chunks", -1), ("local_chunks", 1025), ("local_chunks_plain", -1), ("local_fill", -1)]:
         with pytest.raises(P.PPSPError):
             G.set_option(name, bad)
     G.set_option("local_chunks", 12)
     assert G.get_option("local_chunks") == 12
+    G.close()
+
+
+@pytest.mark.parametrize("min_chunk", [1, 4, 64])
+def test_chunk_sizes(P, min_chunk):
+    """Small frontiers in chunks of min_chunk.. entries: same results for every
+    mode (1 = one entry per wave, 64 = fixed chunks)."""
+    g = gen.lattice(100, 0.1, seed=351)
+    pairs = gen.pairs_uniform(g.n, 50, seed=352)
+    exp = oracle.pp_batch(g.n, g.row_ptr, g.col, g.w, pairs)
+    G = _graph(P, g, 4)
+    G.set_option("min_chunk", min_chunk)
+    for algo, batch in [("bidastar", "plainstar"), ("bids", "plainstar"), ("bids", "multi"), ("et", "plain"),
+                        ("sssp", "vc"), ("astar", "plainstar")]:
+        assert np.array_equal(G.batch_query(pairs, algo=algo, batch=batch), exp), (algo, batch)
+    for q in range(5):
+        assert G.query(int(pairs[q, 0]), int(pairs[q, 1]), algo="bidastar") == exp[q]
+    assert np.array_equal(G.sssp(int(pairs[0, 0])), oracle.sssp(g.n, g.row_ptr, g.col, g.w, int(pairs[0, 0])))
     G.close()
