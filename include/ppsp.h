@@ -100,12 +100,15 @@ enum ppsp_sched {
 #define PPSP_MEMO_H 2u         /* memoise the heuristic per query and vertex (Section 5): A* and BiD-A*,
                                   Plain / Plain*; one 8-byte word per query and vertex, shared by the
                                   query's two searches. Results are identical with or without it. */
+#define PPSP_DEVICE_IO 8u      /* ppsp_batch_query: `pairs` and `dist` are device pointers (on the graph's
+                                  device), read and written in order on the caller's stream; paths stay
+                                  host arrays */
 
 typedef struct {
     uint32_t algo;     /* enum ppsp_algo */
     uint32_t batch;    /* enum ppsp_batch (ignored by ppsp_query) */
     uint32_t sched;    /* enum ppsp_sched */
-    uint32_t flags;    /* PPSP_WANT_PATH | PPSP_MEMO_H | PPSP_PULL */
+    uint32_t flags;    /* PPSP_WANT_PATH | PPSP_MEMO_H | PPSP_PULL | PPSP_DEVICE_IO */
     uint64_t delta;    /* Delta in distance units for PPSP_SCHED_FIXED; 0 = graph default */
 } ppsp_opts;
 
@@ -193,7 +196,8 @@ int ppsp_query(ppsp_graph g, uint32_t s, uint32_t t, const ppsp_opts *opts, void
 int ppsp_sssp(ppsp_graph g, uint32_t s, const ppsp_opts *opts, void *hip_stream, uint64_t *dist);
 
 /*
- * A batch of k queries (Section 4): pairs[2q] = s_q, pairs[2q+1] = t_q (host).
+ * A batch of k queries (Section 4): pairs[2q] = s_q, pairs[2q+1] = t_q (host, or
+ * device memory with PPSP_DEVICE_IO, as is dist).
  * Duplicate pairs, (t,s) mirrors and s = t are allowed.
  *   dist      host, k entries, in input order
  *   path_off  host, k+1 entries or NULL: with PPSP_WANT_PATH, the path of query

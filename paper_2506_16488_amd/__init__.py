@@ -33,6 +33,7 @@ SYMMETRIC = 1
 WANT_PATH = 1
 MEMO_H = 2
 PULL = 4
+DEVICE_IO = 8
 
 
 class PPSPError(RuntimeError):
@@ -387,6 +388,22 @@ class Graph:
                     sched="fixed", pull=False):
         return batch_query(self.h, pairs, make_opts(algo, batch, sched, delta, want_path, memo, pull),
                            want_path=want_path)
+
+    def batch_query_device(self, pairs, dist, algo="bids", batch="plainstar", delta=0, sched="fixed"):
+        """ppsp_batch_query with PPSP_DEVICE_IO: `pairs` (k x 2 int32/uint32) and `dist`
+        (k int64, receives the distances; PPSP_INF reads as -1) are torch tensors on the
+        graph's device, used in order on torch's current stream."""
+        import torch
+        assert pairs.is_cuda and dist.is_cuda and pairs.is_contiguous() and dist.is_contiguous()
+        assert pairs.dtype in (torch.int32,) and dist.dtype == torch.int64
+        k = pairs.shape[0]
+        assert pairs.shape == (k, 2) and dist.shape == (k,)
+        o = make_opts(algo, batch, sched, delta)
+        o.flags |= DEVICE_IO
+        _check(lib().ppsp_batch_query(self.h, ctypes.c_void_p(pairs.data_ptr()), k, ctypes.byref(o),
+                                      current_stream(), ctypes.c_void_p(dist.data_ptr()), None, None, 0),
+               "ppsp_batch_query")
+        return dist
 
     def sssp(self, s, delta=0, sched="fixed"):
         """Distances from s to every vertex (ppsp_sssp; PPSP_INF where unreachable)."""

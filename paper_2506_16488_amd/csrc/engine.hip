@@ -1982,6 +1982,27 @@ int ppsp_graph_destroy(ppsp_graph g) {
 
 int ppsp_batch_query(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp_opts *opts, void *hip_stream,
                      uint64_t *dist, uint64_t *path_off, uint32_t *path_vtx, uint64_t path_cap) {
+    if (opts && (opts->flags & PPSP_DEVICE_IO)) {
+        // device-resident pairs and distances: staged through the host, where
+        // the batch is planned, in order on the caller's stream
+        if (!g || (!pairs && k) || (!dist && k)) return PPSP_E_INVALID;
+        CHK(set_device(g));
+        hipStream_t cs = (hipStream_t)hip_stream;
+        std::vector<uint32_t> hp(2ull * k);
+        std::vector<uint64_t> hd(k);
+        if (k) {
+            HIPCHK(hipMemcpyAsync(hp.data(), pairs, 8ull * k, hipMemcpyDeviceToHost, cs));
+            HIPCHK(hipStreamSynchronize(cs));
+        }
+        ppsp_opts o = *opts;
+        o.flags &= ~PPSP_DEVICE_IO;
+        CHK(batch_impl(g, hp.data(), k, &o, hip_stream, hd.data(), path_off, path_vtx, path_cap, nullptr));
+        if (k) {
+            HIPCHK(hipMemcpyAsync(dist, hd.data(), 8ull * k, hipMemcpyHostToDevice, cs));
+            HIPCHK(hipStreamSynchronize(cs));
+        }
+        return PPSP_OK;
+    }
     return batch_impl(g, pairs, k, opts, hip_stream, dist, path_off, path_vtx, path_cap, nullptr);
 }
 

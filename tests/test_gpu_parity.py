@@ -542,3 +542,30 @@ def test_reordered_graph_same_results(P, graph):
         assert np.array_equal(S.wait(r, timeout_ms=60000)[0], exp)
         S.close()
     G.close()
+
+
+def test_device_resident_pairs_and_distances(P):
+    """PPSP_DEVICE_IO: pairs and distances in device memory (torch tensors on the
+    current stream), with duplicates, a self pair and unreachable pairs."""
+    import torch
+    g = gen.random_graph(3000, 2600, 100, seed=63)
+    pairs = gen.pairs_uniform(g.n, 90, seed=64)
+    pairs[3] = pairs[2]
+    pairs[4, 1] = pairs[4, 0]
+    exp = _oracle(g, pairs)
+    assert np.any(exp == INF)
+    G = _graph(P, g)
+    dp = torch.from_numpy(pairs.astype(np.int32)).cuda()
+    dd = torch.full((pairs.shape[0],), 7, dtype=torch.int64, device="cuda")
+    for algo, batch in [("bids", "plainstar"), ("bids", "multi"), ("et", "plain"), ("sssp", "vc")]:
+        dd.fill_(7)
+        G.batch_query_device(dp, dd, algo=algo, batch=batch)
+        assert np.array_equal(dd.cpu().numpy().view(np.uint64), exp), (algo, batch)
+    e = torch.empty((0, 2), dtype=torch.int32, device="cuda")
+    G.batch_query_device(e, torch.empty(0, dtype=torch.int64, device="cuda"))
+    bad = dp.clone()
+    bad[5, 1] = g.n
+    with pytest.raises(P.PPSPError) as err:
+        G.batch_query_device(bad, dd)
+    assert err.value.code == P.E_RANGE
+    G.close()
