@@ -12,7 +12,7 @@
 //                 - otherwise run UpdateDistance for u (the deferred meeting
 //                   check, see below) and Prune(u^(i)): key >= bound;
 //                 - relax every arc (u, v, w) with a 64-bit atomicMin on the
-//                   packed (distance, parent) word; on a strict decrease run
+//                   packed (distance, stamp) word; on a strict decrease run
 //                   UpdateDistance for v^(i) at once, then Prune(v^(i)) and
 //                   Add(v^(i)) to the next frontier.
 //   k_control   per search: the next threshold (Delta*-stepping of Section 2:
@@ -32,7 +32,16 @@
 // (Theorems bids-correctness and bdastar-correctness) one of its two copies
 // is unpruned when it becomes exact, so that copy is added to the frontier
 // and the later check covers the case where both copies became exact in the
-// same round.
+// same round. A copy that its own wave extracts in the launch that added it
+// (local chunks, below) leaves a check-only entry, so the later check still
+// runs in a later launch.
+//
+// Work distribution. The queue is walked in chunks of 64 entries (16 or 32
+// while the whole queue is too small to give every workgroup a full chunk)
+// with a static stride over the workgroups. A wave also keeps its own
+// additions whose key is within the round's threshold in an LDS list and
+// extracts them as local chunks in the same launch, up to a budget, so a
+// frontier advances several hops per round.
 //
 // Frontier building. The round kernel runs one wave per workgroup and the
 // waves never wait for each other. A wave appends with a ballot + mbcnt
