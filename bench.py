@@ -139,8 +139,8 @@ def main():
 
     torch.cuda.set_device(0)
     t0 = time.time()
-    g = gen.config_graph(2)
-    pairs = gen.config_pairs(2, g)
+    g = gen.workload_graph("lattice2048")
+    pairs = gen.workload_pairs("lattice2048", g)
     G = P.Graph.from_host(g, device=0, reorder=True)
     G.set_option("timeout_ms", 300000)
     print("# graph n=%d m=%d built+uploaded in %.1fs" % (g.n, g.m, time.time() - t0), file=sys.stderr, flush=True)
@@ -319,10 +319,10 @@ def workload_lattice4096hub(args):
     import gen
     import paper_2506_16488_amd as P
     torch.cuda.set_device(0)
-    g = gen.config_graph(3)
+    g = gen.workload_graph("lattice4096")
     G = P.Graph.from_host(g, device=0, reorder=True)
     G.set_option("timeout_ms", 600000)
-    batches = [gen.config_pairs(3, g, batch=b) for b in range(args.steps + args.warmup)]
+    batches = [gen.workload_pairs("lattice4096", g, batch=b) for b in range(args.steps + args.warmup)]
     it = iter(batches)
     res = {}
     dist = None
@@ -367,9 +367,9 @@ def workload_rmat24(args):
     import gen
     import paper_2506_16488_amd as P
     torch.cuda.set_device(0)
-    g = gen.config_graph(4)
+    g = gen.workload_graph("rmat24")
     lcc = gen.lcc(g)
-    pairs = gen.config_pairs(4, g, cand=lcc)
+    pairs = gen.workload_pairs("rmat24", g, cand=lcc)
     G = P.Graph.from_host(g, device=0, reorder=True)
     G.set_option("timeout_ms", 900000)
     print("# graph built: n=%d m=%d" % (g.n, g.m), file=sys.stderr, flush=True)
@@ -416,12 +416,12 @@ def workload_serve(args):
     import gen
     import paper_2506_16488_amd as P
     torch.cuda.set_device(0)
-    hosts = [gen.config_graph(3), gen.config_graph(4)]
+    hosts = [gen.workload_graph("lattice4096"), gen.workload_graph("rmat24")]
     lcc = gen.lcc(hosts[1])
     print("# graphs built", file=sys.stderr, flush=True)
     Gs = [P.Graph.from_host(h, device=0, reorder=True) for h in hosts]
     # the R-MAT graph runs with its autotuned Delta
-    tr = Gs[1].tune(gen.config_pairs(4, hosts[1], cand=lcc)[:16], algo="bids", batch="plainstar")
+    tr = Gs[1].tune(gen.workload_pairs("rmat24", hosts[1], cand=lcc)[:16], algo="bids", batch="plainstar")
     rng = np.random.default_rng(105)
 
     def make_requests(k, seed):
@@ -501,7 +501,7 @@ def workload_ranks(args):
     import gen
     import paper_2506_16488_amd as P
     torch.cuda.set_device(0)
-    g = gen.config_graph(2)
+    g = gen.workload_graph("lattice2048")
     G = P.Graph.from_host(g, device=0, reorder=True)
     G.set_option("timeout_ms", 300000)
     sources = gen.pairs_uniform(g.n, 4, seed=2026)[:, 0]

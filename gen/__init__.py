@@ -5,7 +5,7 @@ path. It holds input construction only (no relaxation, pruning or heuristic
 arithmetic). The heavy generators are C (``gen.c``, OpenMP) loaded through
 ctypes; tiny test graphs are built with numpy.
 
-The configurations mirror the synthetic stand-ins for the paper's datasets
+The workloads are synthetic stand-ins for the paper's datasets
 (Section 6, Table 3): a uniform-weight grid, road-like jittered lattices
 (weights = ceil(1000 * Euclidean length), coordinates in fixed point with 8
 fractional bits) and a power-law R-MAT graph with integer weights.
@@ -203,38 +203,40 @@ def random_graph(n: int, m_edges: int, wmax: int, seed: int, wmin: int = 1,
     return csr_from_edges(n, src, dst, w, symmetric=symmetric)
 
 
-# ---- the five workload configurations -----------------------------------------
+# ---- the benchmark workloads -----------------------------------------------------
 
-CONFIG_SEEDS = {1: 1, 2: 2, 3: 3, 4: 4}
-
-
-def config_graph(k: int) -> Graph:
-    """Graph of workload configuration k (1..4)."""
-    if k == 1:
-        return grid(256, 256, 1, 1000, seed=1)
-    if k == 2:
-        return lattice(2048, 0.05, seed=2)
-    if k == 3:
-        return lattice(4096, 0.05, seed=3)
-    if k == 4:
-        return rmat(24, 16, 0.57, 0.19, 0.19, 1, 65535, seed=4)
-    raise ValueError(k)
+# The benchmark workloads by name: graph seed and pair seed 100 + graph seed.
+WORKLOAD_SEEDS = {"grid256": 1, "lattice2048": 2, "lattice4096": 3, "rmat24": 4}
 
 
-def config_pairs(k: int, g: Graph, batch: int = 0, cand: Optional[np.ndarray] = None) -> np.ndarray:
-    """Query pairs of configuration k (pair seed = 100 + k)."""
-    seed = 100 + k
-    if k == 1:
+def workload_graph(name: str) -> Graph:
+    """grid256: 256 x 256 grid, weights U[1, 1000]; lattice2048 / lattice4096:
+    jittered lattices with 5% diagonals; rmat24: R-MAT scale 24, edge factor 16,
+    weights U[1, 65535]."""
+    seed = WORKLOAD_SEEDS[name]
+    if name == "grid256":
+        return grid(256, 256, 1, 1000, seed=seed)
+    if name == "lattice2048":
+        return lattice(2048, 0.05, seed=seed)
+    if name == "lattice4096":
+        return lattice(4096, 0.05, seed=seed)
+    return rmat(24, 16, 0.57, 0.19, 0.19, 1, 65535, seed=seed)
+
+
+def workload_pairs(name: str, g: Graph, batch: int = 0, cand: Optional[np.ndarray] = None) -> np.ndarray:
+    """grid256: 64 distinct uniform pairs; lattice2048: 1,000 uniform pairs;
+    lattice4096: batches of 1,024 (512 from 32 hubs, 512 uniform); rmat24: 256
+    uniform pairs from the largest component (or `cand`)."""
+    seed = 100 + WORKLOAD_SEEDS[name]
+    if name == "grid256":
         return pairs_uniform(g.n, 64, seed, distinct=True)
-    if k == 2:
+    if name == "lattice2048":
         return pairs_uniform(g.n, 1000, seed)
-    if k == 3:
+    if name == "lattice4096":
         return pairs_hub(g.n, 32, 512, 1024, seed, batch)
-    if k == 4:
-        if cand is None:
-            cand = lcc(g)
-        return pairs_uniform(cand, 256, seed, stream=batch * 16)
-    raise ValueError(k)
+    if cand is None:
+        cand = lcc(g)
+    return pairs_uniform(cand, 256, seed, stream=batch * 16)
 
 
 # ---- learned-schedule network: initial parameters and synthetic rows ----------

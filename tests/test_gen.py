@@ -34,8 +34,8 @@ def test_grid_shape_weights_symmetry():
         assert nb.tolist() == exp
 
 
-def test_grid_config1_counts():
-    g = gen.config_graph(1)
+def test_grid256_counts():
+    g = gen.workload_graph("grid256")
     assert g.n == 65536 and g.m == 261120
 
 

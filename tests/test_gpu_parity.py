@@ -50,9 +50,9 @@ def _check_paths(g, pairs, dist, off, vtx):
         assert rc == (0, 0), (q, s, t, rc)
 
 
-def test_config1_grid_all_modes(P):
-    g = gen.config_graph(1)
-    pairs = gen.config_pairs(1, g)
+def test_grid256_all_modes(P):
+    g = gen.workload_graph("grid256")
+    pairs = gen.workload_pairs("grid256", g)
     exp = _oracle(g, pairs)
     G = _graph(P, g)
     for algo in ALGOS_PLAIN:
@@ -69,9 +69,9 @@ def test_config1_grid_all_modes(P):
     G.close()
 
 
-def test_config1_paths(P):
-    g = gen.config_graph(1)
-    pairs = gen.config_pairs(1, g)
+def test_grid256_paths(P):
+    g = gen.workload_graph("grid256")
+    pairs = gen.workload_pairs("grid256", g)
     G = _graph(P, g)
     for algo in ["et", "bids"]:
         for batch in ["plainstar", "multi"] if algo == "bids" else ["plainstar"]:
@@ -148,7 +148,7 @@ def test_schedule_invariance(P):
 
 
 def test_batch_equals_alone_and_repeatable(P):
-    g = gen.config_graph(1)
+    g = gen.workload_graph("grid256")
     pairs = gen.pairs_uniform(g.n, 40, seed=9)
     G = _graph(P, g)
     batch = G.batch_query(pairs, algo="bids", batch="multi")
@@ -174,8 +174,8 @@ def test_hub_batch_multi(P):
 
 def test_memory_waves(P):
     """A state budget below the batch size forces several waves."""
-    g = gen.config_graph(1)
-    pairs = gen.config_pairs(1, g)
+    g = gen.workload_graph("grid256")
+    pairs = gen.workload_pairs("grid256", g)
     exp = _oracle(g, pairs)
     G = _graph(P, g)
     G.set_option("mem_budget_mb", 8)          # ~15 searches of 65,536 vertices per wave
@@ -218,11 +218,11 @@ def test_error_paths(P):
 
 
 @pytest.mark.slow
-def test_config2_full_size_sampled(P):
+def test_lattice2048_full_size_sampled(P):
     """The 2048^2 road-like lattice with all 1,000 pairs in one Plain* batch
     (the benchmark's launch configuration); 48 sampled pairs vs the oracle."""
-    g = gen.config_graph(2)
-    pairs = gen.config_pairs(2, g)
+    g = gen.workload_graph("lattice2048")
+    pairs = gen.workload_pairs("lattice2048", g)
     G = _graph(P, g)
     got = {a: G.batch_query(pairs, algo=a, batch="plainstar") for a in ["bidastar", "bids"]}
     idx = np.arange(0, 1000, 21)
@@ -268,12 +268,12 @@ def test_overflow_retries_keep_results_exact(P):
 
 
 @pytest.mark.slow
-def test_config3_hub_batch_sampled(P):
+def test_lattice4096_hub_batch_sampled(P):
     """The 4096^2 lattice with a 1,024-pair hub batch (512 pairs from 32 hub
     sources, 512 uniform) as one Multi-BiDS wave of ~1,568 searches, and as
     Plain* bidirectional A*; sampled pairs against the oracle."""
-    g = gen.config_graph(3)
-    pairs = gen.config_pairs(3, g)
+    g = gen.workload_graph("lattice4096")
+    pairs = gen.workload_pairs("lattice4096", g)
     idx = np.arange(0, 1024, 64)
     exp = _oracle(g, pairs[idx])
     G = _graph(P, g)
@@ -285,12 +285,12 @@ def test_config3_hub_batch_sampled(P):
 
 
 @pytest.mark.slow
-def test_config4_rmat_sampled(P):
+def test_rmat24_sampled(P):
     """R-MAT scale 24 (power law, hubs of degree ~400K) with 256 pairs from the
     largest component, Multi-BiDS; sampled pairs against the oracle."""
-    g = gen.config_graph(4)
+    g = gen.workload_graph("rmat24")
     lcc = gen.lcc(g)
-    pairs = gen.config_pairs(4, g, cand=lcc)
+    pairs = gen.workload_pairs("rmat24", g, cand=lcc)
     idx = np.arange(0, 256, 32)
     exp = _oracle(g, pairs[idx])
     G = _graph(P, g)

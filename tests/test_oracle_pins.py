@@ -108,9 +108,9 @@ def test_disconnected_and_isolated():
     assert oracle.pp(g.n, g.row_ptr, g.col, g.w, 3, 5) == 6
 
 
-def test_scipy_crosscheck_grid_config1():
+def test_scipy_crosscheck_grid256():
     import scipy.sparse.csgraph as csg
-    g = gen.config_graph(1)
+    g = gen.workload_graph("grid256")
     M = _min_weight_matrix(g)
     srcs = [0, 12345, 65535]
     ref = csg.dijkstra(M, directed=True, indices=srcs)
@@ -130,7 +130,7 @@ def test_scipy_crosscheck_random_multigraph():
 
 
 def test_certificate_accepts_oracle_and_rejects_planted_mistakes():
-    g = gen.config_graph(1)
+    g = gen.workload_graph("grid256")
     rng = np.random.default_rng(11)
     for s in rng.integers(0, g.n, 3).tolist():
         dist = oracle.sssp(g.n, g.row_ptr, g.col, g.w, s)
@@ -157,8 +157,8 @@ def test_certificate_reachability():
 
 
 @pytest.mark.slow
-def test_certificate_lattice_config2_sampled():
-    g = gen.config_graph(2)
+def test_certificate_lattice2048_sampled():
+    g = gen.workload_graph("lattice2048")
     for s in [0, 2048 * 1024 + 1024]:
         dist = oracle.sssp(g.n, g.row_ptr, g.col, g.w, s)
         assert oracle.check_sssp(g.n, g.row_ptr, g.col, g.w, s, dist) == (0, 0)
