@@ -422,6 +422,10 @@ int ppsp_last_stats(ppsp_graph g, ppsp_stats *stats);
  *   "local_chunks_small" the budget instead in rounds whose frontier is small enough for
  *                     chunks below 64 entries (default 4: single queries; a long serial
  *                     chain per wave would set the round's length)
+ *   "local_time_pct"  in rounds of full chunks a wave stops taking local chunks once it has run
+ *                     this percentage of the previous round's mean wave time, and its listed
+ *                     entries go to the next round, so one long chain does not hold the round
+ *                     open (default 80; 0 = no limit)
  *   "min_chunk"       entries per chunk of the round kernel while the frontier is too small
  *                     to give every workgroup a 64-entry chunk: the smallest power of two
  *                     from min_chunk up that covers it (default 16; 64 = always 64)

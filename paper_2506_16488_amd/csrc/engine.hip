@@ -158,6 +158,7 @@ struct ppsp_graph_s {
     std::vector<uint32_t> iperm;    // caller id of each device id
     DevBuf row_ptr, arcs, xy, in_row_ptr, in_arcs;   // transpose only for a directed graph
     // workspace (grow only)
+    DevBuf tsum;                    // local-chunk time limit: 4 sums, then 2 limits
     DevBuf S, q0, q1, sd, partners, pairdesc, ctl, delta, done, exh, alive, minkey, mu, qcount, cpre, round, err,
         stats, wstats, pathlen, pathoff, pathbuf, heavy, hcount, hlim, memo;
     uint32_t maxdeg = 0;
@@ -172,7 +173,7 @@ struct ppsp_graph_s {
     int64_t opt_profile = 0, opt_rounds_per_sync = 16, opt_grid_blocks = 0, opt_mem_budget_mb = 0,
             opt_default_delta = 0, opt_use_graph = 0, opt_timeout_ms = 600000, opt_theta_mode = 2, opt_queue_cap = 0,
             opt_ml_every = 4, opt_heavy_window = 64, opt_multi_group = 32, opt_rho = 4096, opt_local = 16, opt_local_plain = 0, opt_local_fill = 0,
-            opt_min_chunk = 16, opt_local_small = 4;
+            opt_min_chunk = 16, opt_local_small = 4, opt_local_pct = 80;
     uint64_t wmean = 1;             // mean arc weight (rounded up)
     uint64_t fingerprint = 0;       // hash of the CSR, keys the tuning cache
     struct Tuned {
@@ -278,6 +279,11 @@ void set_args(ppsp_graph g, RoundArgs &A, uint32_t nsearch, uint32_t npair, uint
     A.local_fill = (uint32_t)g->opt_local_fill;
     A.min_chunk = (uint32_t)g->opt_min_chunk;
     A.local_small = (uint32_t)g->opt_local_small;
+    if (g->opt_local_pct > 0 && (g->opt_local > 0 || g->opt_local_plain > 0)) {
+        A.tsum = g->tsum.as<unsigned long long>();
+        A.lcap = g->tsum.as<uint32_t>() + 8;             // after the 4 sums
+        A.local_pct = (uint32_t)g->opt_local_pct;
+    }
     A.pull = g->pull_call && g->symmetric ? 1u : 0u;
     if (g->memo_call && g->has_xy && (G == 2 || G == 1)) {
         A.memo = g->memo.as<uint64_t>();
@@ -357,6 +363,7 @@ int run_wave(ppsp_graph g, const Plan &P, bool want_path, WaveOut &out) {
     CHK(ensure(g->mu, npair * 8));
     CHK(ensure(g->qcount, 2 * NSEG * 4));
     CHK(ensure(g->cpre, 2 * (NSEG + 1) * 4));
+    CHK(ensure(g->tsum, 48));
     CHK(ensure(g->err, 16));
     CHK(ensure(g->stats, ST_N * 8));
     {
@@ -379,6 +386,7 @@ int run_wave(ppsp_graph g, const Plan &P, bool want_path, WaveOut &out) {
         HIPCHK(hipMemcpyAsync(g->delta.p, P.delta.data(), ns * 8, hipMemcpyHostToDevice, st));
         HIPCHK(hipMemsetAsync(g->mu.p, 0xFF, npair * 8, st));
         HIPCHK(hipMemsetAsync(g->qcount.p, 0, 2 * NSEG * 4, st));
+        HIPCHK(hipMemsetAsync(g->tsum.p, 0, 48, st));
         HIPCHK(hipMemsetAsync(g->wstats.p, 0, (uint64_t)grid * ST_N * 8, st));
         HIPCHK(hipMemsetAsync(g->round.p, 0, 16, st));
         HIPCHK(hipMemsetAsync(g->hcount.p, 0, 16, st));
@@ -1469,6 +1477,7 @@ int srv_setup_graph(ppsp_server srv, SrvGraph &G, const ppsp_opts &o, uint64_t b
     CHK(ensure(g->mu, (uint64_t)npair * 8));
     CHK(ensure(g->qcount, 2 * NSEG * 4));
     CHK(ensure(g->cpre, 2 * (NSEG + 1) * 4));
+    CHK(ensure(g->tsum, 48));
     CHK(ensure(g->err, 16));
     CHK(ensure(g->stats, ST_N * 8));
     G.grid = round_grid(g);
@@ -1486,6 +1495,7 @@ int srv_setup_graph(ppsp_server srv, SrvGraph &G, const ppsp_opts &o, uint64_t b
     HIPCHK(hipMemcpyAsync(g->delta.p, G.delta.data(), (uint64_t)ns * 8, hipMemcpyHostToDevice, st));
     HIPCHK(hipMemsetAsync(g->qcount.p, 0, 2 * NSEG * 4, st));
     HIPCHK(hipMemsetAsync(g->cpre.p, 0, 2 * (NSEG + 1) * 4, st));
+    HIPCHK(hipMemsetAsync(g->tsum.p, 0, 48, st));
     HIPCHK(hipMemsetAsync(g->round.p, 0, 16, st));
     HIPCHK(hipMemsetAsync(g->hcount.p, 0, 16, st));
     HIPCHK(hipMemsetAsync(g->err.p, 0, 16, st));
@@ -1527,6 +1537,7 @@ int srv_restart(ppsp_server srv, SrvGraph &G, uint32_t errbits) {
     const uint32_t ns = 2 * G.C;
     HIPCHK(hipMemsetAsync(g->qcount.p, 0, 2 * NSEG * 4, st));
     HIPCHK(hipMemsetAsync(g->cpre.p, 0, 2 * (NSEG + 1) * 4, st));
+    HIPCHK(hipMemsetAsync(g->tsum.p, 0, 48, st));
     HIPCHK(hipMemsetAsync(g->hcount.p, 0, 16, st));
     HIPCHK(hipMemsetAsync(g->err.p, 0, 16, st));
     set_args(g, G.A, ns, G.C, 2);
@@ -2204,6 +2215,7 @@ int ppsp_set_option(ppsp_graph g, const char *name, int64_t v) {
     else if (k == "local_chunks_plain") { if (v < 0 || v > 1024) return PPSP_E_INVALID; g->opt_local_plain = v; }
     else if (k == "local_fill") { if (v < 0 || v > (1ll << 31)) return PPSP_E_INVALID; g->opt_local_fill = v; }
     else if (k == "local_chunks_small") { if (v < 0 || v > 1024) return PPSP_E_INVALID; g->opt_local_small = v; }
+    else if (k == "local_time_pct") { if (v < 0 || v > 100000) return PPSP_E_INVALID; g->opt_local_pct = v; }
     else if (k == "min_chunk") {
         if (v < 1 || v > (int64_t)WAVE || (v & (v - 1))) return PPSP_E_INVALID;
         g->opt_min_chunk = v;
@@ -2239,6 +2251,7 @@ int ppsp_get_option(ppsp_graph g, const char *name, int64_t *v) {
     else if (k == "local_fill") *v = g->opt_local_fill;
     else if (k == "min_chunk") *v = g->opt_min_chunk;
     else if (k == "local_chunks_small") *v = g->opt_local_small;
+    else if (k == "local_time_pct") *v = g->opt_local_pct;
 
     else return PPSP_E_INVALID;
     return PPSP_OK;

@@ -370,10 +370,31 @@ __global__ __launch_bounds__(WAVE) void k_round(RoundArgs A) {
     const uint32_t lmax = (csize < (uint32_t)WAVE && lmain) ? A.local_small : lmain;
     uint32_t lbud = (!PULL && lmax && (A.local_fill == 0 || (uint64_t)nchunks * csize < A.local_fill)) ? lmax : 0u;
     uint32_t ch = blockIdx.x;
+    // Time limit for local chunks in rounds of full chunks: a percentage of
+    // the previous round's mean wave time (set with the chunk prefix; 0:
+    // none), so a wave with a long chain of local chunks does not hold a
+    // loaded round open for all others. Small rounds (a small frontier: the
+    // chain is the point) have none.
+    const uint32_t lcap = (A.lcap && csize == (uint32_t)WAVE) ? A.lcap[par] : 0u;
+    const unsigned long long t_begin = wall_clock64();
     for (;;) {
         // The next chunk: this wave's own listed entries first, then the queue.
         uint4 ent = make_uint4(0, 0, 0, 0);
         bool valid;
+        if (lpend && lcap && wall_clock64() - t_begin > lcap) {
+            // Out of time for local chunks: the listed entries go to the next
+            // round's queue (live, with no key: that only widens the next
+            // threshold), and this wave lists no more.
+            for (uint32_t j = 0; j < lpend; j += WAVE) {
+                const bool v = j + lane_id() < lpend;
+                const uint4 e = v ? lq[j + lane_id()] : make_uint4(0, 0, 0, 0);
+                wstage_push(st, scnt, v, e, qout, qcout, A.qseg, A.err);
+                search_stats(A, np, e.x, v ? 1u : 0u, INF64, false);
+            }
+            __syncthreads();
+            lpend = 0;
+            lbud = 0;
+        }
         if (lpend) {
             const uint32_t take = lpend < (uint32_t)WAVE ? lpend : (uint32_t)WAVE;
             valid = lane_id() < take;
@@ -698,6 +719,11 @@ __global__ __launch_bounds__(WAVE) void k_round(RoundArgs A) {
         ws[ST_SCANE] += c_se;
         ws[ST_SUCC] += c_succ;
     }
+    if (A.tsum && blockIdx.x < ML_SAMPLE && lane_id() == 0) {
+        // sampled wave times of this round, for the next round's limit
+        atomicAdd(&A.tsum[par * 2], (unsigned long long)(wall_clock64() - t_begin));
+        atomicAdd(&A.tsum[par * 2 + 1], 1ull);
+    }
 }
 
 // The heavy list, relaxed by every wave of the grid: each wave takes whole
@@ -761,6 +787,15 @@ __device__ __forceinline__ void chunk_prefix(const RoundArgs &A, uint32_t q) {
     }
     A.cpre[q * (NSEG + 1) + k + 1] = x;
     if (k == 0) A.cpre[q * (NSEG + 1)] = ch;
+    if (k == 0 && A.tsum) {
+        // the local-chunk time limit of the round that reads queue q, from
+        // the sampled wave times of the round before; its own sums start at 0
+        const unsigned long long sum = A.tsum[(q ^ 1) * 2], cnt = A.tsum[(q ^ 1) * 2 + 1];
+        const unsigned long long cap = cnt ? sum / cnt * A.local_pct / 100 : 0ull;
+        A.lcap[q] = (uint32_t)min(cap, 0xFFFFFFFFull);
+        A.tsum[q * 2] = 0;
+        A.tsum[q * 2 + 1] = 0;
+    }
 }
 
 __global__ __launch_bounds__(WAVE) void k_seed_prefix(RoundArgs A) { chunk_prefix(A, 0); }
