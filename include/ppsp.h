@@ -426,6 +426,10 @@ int ppsp_last_stats(ppsp_graph g, ppsp_stats *stats);
  *                     this percentage of the previous round's mean wave time, and its listed
  *                     entries go to the next round, so one long chain does not hold the round
  *                     open (default 80; 0 = no limit)
+ *   "defer_time_pct"  in rounds of full chunks a wave that has run this percentage of the
+ *                     previous round's mean wave time hands its remaining queue chunks to the
+ *                     next round unprocessed; its first chunk is always processed (default
+ *                     105; 0 = never; otherwise at least 100)
  *   "min_chunk"       entries per chunk of the round kernel while the frontier is too small
  *                     to give every workgroup a 64-entry chunk: the smallest power of two
  *                     from min_chunk up that covers it (default 16; 64 = always 64)

@@ -173,7 +173,7 @@ struct ppsp_graph_s {
     int64_t opt_profile = 0, opt_rounds_per_sync = 16, opt_grid_blocks = 0, opt_mem_budget_mb = 0,
             opt_default_delta = 0, opt_use_graph = 0, opt_timeout_ms = 600000, opt_theta_mode = 2, opt_queue_cap = 0,
             opt_ml_every = 4, opt_heavy_window = 64, opt_multi_group = 32, opt_rho = 4096, opt_local = 16, opt_local_plain = 0, opt_local_fill = 0,
-            opt_min_chunk = 16, opt_local_small = 4, opt_local_pct = 80;
+            opt_min_chunk = 16, opt_local_small = 4, opt_local_pct = 80, opt_defer_pct = 105;
     uint64_t wmean = 1;             // mean arc weight (rounded up)
     uint64_t fingerprint = 0;       // hash of the CSR, keys the tuning cache
     struct Tuned {
@@ -279,10 +279,11 @@ void set_args(ppsp_graph g, RoundArgs &A, uint32_t nsearch, uint32_t npair, uint
     A.local_fill = (uint32_t)g->opt_local_fill;
     A.min_chunk = (uint32_t)g->opt_min_chunk;
     A.local_small = (uint32_t)g->opt_local_small;
-    if (g->opt_local_pct > 0 && (g->opt_local > 0 || g->opt_local_plain > 0)) {
+    if ((g->opt_local_pct > 0 && (g->opt_local > 0 || g->opt_local_plain > 0)) || g->opt_defer_pct > 0) {
         A.tsum = g->tsum.as<unsigned long long>();
         A.lcap = g->tsum.as<uint32_t>() + 8;             // after the 4 sums
         A.local_pct = (uint32_t)g->opt_local_pct;
+        A.defer_pct = (uint32_t)g->opt_defer_pct;
     }
     A.pull = g->pull_call && g->symmetric ? 1u : 0u;
     if (g->memo_call && g->has_xy && (G == 2 || G == 1)) {
@@ -2216,6 +2217,11 @@ int ppsp_set_option(ppsp_graph g, const char *name, int64_t v) {
     else if (k == "local_fill") { if (v < 0 || v > (1ll << 31)) return PPSP_E_INVALID; g->opt_local_fill = v; }
     else if (k == "local_chunks_small") { if (v < 0 || v > 1024) return PPSP_E_INVALID; g->opt_local_small = v; }
     else if (k == "local_time_pct") { if (v < 0 || v > 100000) return PPSP_E_INVALID; g->opt_local_pct = v; }
+    else if (k == "defer_time_pct") {
+        // below 100 % a wave would defer before the average wave is done
+        if (v < 0 || (v > 0 && v < 100) || v > 100000) return PPSP_E_INVALID;
+        g->opt_defer_pct = v;
+    }
     else if (k == "min_chunk") {
         if (v < 1 || v > (int64_t)WAVE || (v & (v - 1))) return PPSP_E_INVALID;
         g->opt_min_chunk = v;
@@ -2252,6 +2258,7 @@ int ppsp_get_option(ppsp_graph g, const char *name, int64_t *v) {
     else if (k == "min_chunk") *v = g->opt_min_chunk;
     else if (k == "local_chunks_small") *v = g->opt_local_small;
     else if (k == "local_time_pct") *v = g->opt_local_pct;
+    else if (k == "defer_time_pct") *v = g->opt_defer_pct;
 
     else return PPSP_E_INVALID;
     return PPSP_OK;

@@ -375,7 +375,13 @@ __global__ __launch_bounds__(WAVE) void k_round(RoundArgs A) {
     // none), so a wave with a long chain of local chunks does not hold a
     // loaded round open for all others. Small rounds (a small frontier: the
     // chain is the point) have none.
-    const uint32_t lcap = (A.lcap && csize == (uint32_t)WAVE) ? A.lcap[par] : 0u;
+    const unsigned long long tmean = (A.lcap && csize == (uint32_t)WAVE) ? A.lcap[par] : 0ull;
+    const unsigned long long lcap = tmean * A.local_pct / 100;
+    // Past defer_pct % of that mean, a wave hands its remaining queue chunks to
+    // the next round unprocessed (0: never). Its first chunk is always
+    // processed, so every round makes progress whatever the setting.
+    const unsigned long long dcap = tmean * A.defer_pct / 100;
+    bool first_global = true;
     const unsigned long long t_begin = wall_clock64();
     for (;;) {
         // The next chunk: this wave's own listed entries first, then the queue.
@@ -410,6 +416,17 @@ __global__ __launch_bounds__(WAVE) void k_round(RoundArgs A) {
             valid = lane_id() < csize && pos < nseg;
             if (valid) ent = qin[(uint64_t)lo * A.qseg + pos];
             ch += gridDim.x;
+            const bool defer = !first_global && dcap && wall_clock64() - t_begin > dcap;
+            first_global = false;
+            if (defer) {
+                // deferred as it is: live in the next round; a carried entry
+                // keeps its key, any other counts with none
+                const bool carried = (ent.x & CARRY_BIT) != 0;
+                const uint64_t k = (valid && carried && ent.w != KEY_UNKNOWN) ? (uint64_t)ent.w : INF64;
+                wstage_push(st, scnt, valid, ent, qout, qcout, A.qseg, A.err);
+                search_stats(A, np, ent.x & ~CARRY_BIT, valid ? 1u : 0u, k, false);
+                continue;
+            }
         } else {
             break;
         }
@@ -791,8 +808,7 @@ __device__ __forceinline__ void chunk_prefix(const RoundArgs &A, uint32_t q) {
         // the local-chunk time limit of the round that reads queue q, from
         // the sampled wave times of the round before; its own sums start at 0
         const unsigned long long sum = A.tsum[(q ^ 1) * 2], cnt = A.tsum[(q ^ 1) * 2 + 1];
-        const unsigned long long cap = cnt ? sum / cnt * A.local_pct / 100 : 0ull;
-        A.lcap[q] = (uint32_t)min(cap, 0xFFFFFFFFull);
+        A.lcap[q] = (uint32_t)min(cnt ? sum / cnt : 0ull, 0xFFFFFFFFull);   // mean wave time, in ticks
         A.tsum[q * 2] = 0;
         A.tsum[q * 2 + 1] = 0;
     }

@@ -202,13 +202,16 @@ struct RoundArgs {
     uint32_t local_fill;
     uint32_t local_small;      // the budget in rounds whose chunks are below WAVE entries
     uint32_t min_chunk;        // smallest chunk of a small queue (a power of two <= WAVE; WAVE or 0: fixed)
-    // Local chunks stop in a wave once it has run local_pct % of the previous
-    // round's mean wave time (null tsum: no limit); its listed entries go to
-    // the next round. tsum[2][2]: sampled wave-time sums and counts by round
-    // parity; lcap[2]: the limit in wall-clock ticks of the round of each parity.
+    // In rounds of full chunks, local chunks stop in a wave once it has run
+    // local_pct % of the previous round's mean wave time (null tsum: no
+    // limit), its listed entries going to the next round; past defer_pct %
+    // (0: never) its remaining queue chunks go there too. tsum[2][2]: sampled
+    // wave-time sums and counts by round parity; lcap[2]: the mean wave time
+    // (wall-clock ticks) of the round before the round of each parity.
     unsigned long long *tsum;
     uint32_t *lcap;
     uint32_t local_pct;
+    uint32_t defer_pct;
 };
 
 // Only the first ML_SAMPLE workgroups of the round kernels update the

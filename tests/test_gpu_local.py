@@ -127,9 +127,9 @@ def test_options_checked(P):
     G = P.Graph.from_host(g)
     assert G.get_option("local_chunks") == 16 and G.get_option("local_chunks_plain") == 0   # defaults
     assert G.get_option("local_chunks_small") == 4 and G.get_option("min_chunk") == 16
-    assert G.get_option("local_time_pct") == 80
+    assert G.get_option("local_time_pct") == 80 and G.get_option("defer_time_pct") == 105
     for name, bad in [("min_chunk", 0), ("min_chunk", 24), ("min_chunk", 128), ("local_chunks_small", -1),
-                      ("local_time_pct", -1)]:
+                      ("local_time_pct", -1), ("defer_time_pct", -1), ("defer_time_pct", 50)]:
         with pytest.raises(P.PPSPError):
             G.set_option(name, bad)
     for name, bad in [("local_chunks", -1), ("local_chunks", 1025), ("local_chunks_plain", -1), ("local_fill", -1)]:
@@ -158,11 +158,12 @@ def test_chunk_sizes(P, min_chunk):
     G.close()
 
 
-@pytest.mark.parametrize("pct", [0, 1, 30])
-def test_local_time_limit(P, pct):
-    """The time limit on local chunks (1%: listed entries are handed to the next
-    round almost at once; 0: no limit): same results in every mode, on a batch
-    large enough for full chunks."""
+@pytest.mark.parametrize("pct,defer", [(0, 0), (1, 0), (30, 0), (80, 100), (0, 100), (1, 100), (80, 105)])
+def test_local_time_limit(P, pct, defer):
+    """The time limits on local chunks (1%: listed entries are handed to the
+    next round almost at once; 0: no limit) and on queue chunks (100%: every
+    wave slower than the mean hands on its remaining chunks): same results in
+    every mode, on a batch large enough for full chunks."""
     g = gen.lattice(300, 0.05, seed=361)
     pairs = gen.pairs_uniform(g.n, 400, seed=362)
     exp = oracle.pp_batch(g.n, g.row_ptr, g.col, g.w, pairs)
@@ -170,6 +171,7 @@ def test_local_time_limit(P, pct):
     G.set_option("timeout_ms", 60000)
     G.set_option("grid_blocks", 64)              # few workgroups: full chunks at this size
     G.set_option("local_time_pct", pct)
+    G.set_option("defer_time_pct", defer)
     G.set_option("local_chunks_plain", 8)
     for algo, batch in [("bidastar", "plainstar"), ("astar", "plainstar"), ("bids", "plainstar"),
                         ("bids", "multi"), ("et", "plain")]:
