@@ -41,7 +41,10 @@
 // with a static stride over the workgroups. A wave also keeps its own
 // additions whose key is within the round's threshold in an LDS list and
 // extracts them as local chunks in the same launch, up to a budget, so a
-// frontier advances several hops per round.
+// frontier advances several hops per round. In rounds of full chunks, a wave
+// that has run a set share of the previous round's mean wave time hands its
+// listed entries, and later its remaining queue chunks, to the next round,
+// so that no single wave holds the round open.
 //
 // Frontier building. The round kernel runs one wave per workgroup and the
 // waves never wait for each other. A wave appends with a ballot + mbcnt
