@@ -13,7 +13,11 @@
  *     (Section 3.5, Theorem bdastar-correctness);
  *   - Delta*-stepping thresholds (Section 2: the i-th threshold is i*Delta);
  *   - batch queries through the query graph (Section 4.1) and the Plain,
- *     Plain* and Multi-BiDS strategies (Section 4.2).
+ *     Plain*, Multi-BiDS, Plain-SSSP and VC-SSSP strategies (Section 4.2),
+ *     with the paper's adaptation to directed graphs (bipartite query graph,
+ *     backward searches on the transposed graph);
+ *   - single-source distances (ppsp_sssp), an autotuner, a learned step
+ *     schedule and a continuous-batching server around the same kernels.
  * Every mode computes exact distances; the threshold schedule only decides
  * the order of work.
  *
