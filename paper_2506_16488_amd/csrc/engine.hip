@@ -424,6 +424,17 @@ int run_wave(ppsp_graph g, const Plan &P, bool want_path, WaveOut &out) {
         }
         RoundArgs A;
         set_args(g, A, ns, npair, P.G);
+        // The time limits serve waves with local chunks: without heuristic
+        // searches (and without "local_chunks_plain") they only cost (Multi-BiDS
+        // on the hub lattice: 534 -> 508 queries/s), so they are off.
+        {
+            bool heur = false;
+            for (const SearchDesc &d : P.sd) heur = heur || d.kind == K_ASTAR || d.kind == K_BIDA_F || d.kind == K_BIDA_B;
+            if (!heur && g->opt_local_plain == 0) {
+                A.tsum = nullptr;
+                A.lcap = nullptr;
+            }
+        }
         HIPCHK(launch_init(A, st));
         const int K = std::max<int64_t>(1, g->opt_rounds_per_sync);
         const bool prof = g->opt_profile != 0;
