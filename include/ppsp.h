@@ -429,7 +429,7 @@ int ppsp_last_stats(ppsp_graph g, ppsp_stats *stats);
  *   "local_time_pct"  in rounds of full chunks a wave stops taking local chunks once it has run
  *                     this percentage of the previous round's mean wave time, and its listed
  *                     entries go to the next round, so one long chain does not hold the round
- *                     open (default 80; 0 = no limit)
+ *                     open (default 90; 0 = no limit)
  *   "defer_time_pct"  in rounds of full chunks a wave that has run this percentage of the
  *                     previous round's mean wave time hands its remaining queue chunks to the
  *                     next round unprocessed; its first chunk is always processed (default

@@ -173,7 +173,7 @@ struct ppsp_graph_s {
     int64_t opt_profile = 0, opt_rounds_per_sync = 16, opt_grid_blocks = 0, opt_mem_budget_mb = 0,
             opt_default_delta = 0, opt_use_graph = 0, opt_timeout_ms = 600000, opt_theta_mode = 2, opt_queue_cap = 0,
             opt_ml_every = 4, opt_heavy_window = 64, opt_multi_group = 32, opt_rho = 4096, opt_local = 16, opt_local_plain = 0, opt_local_fill = 0,
-            opt_min_chunk = 16, opt_local_small = 4, opt_local_pct = 80, opt_defer_pct = 105;
+            opt_min_chunk = 16, opt_local_small = 4, opt_local_pct = 90, opt_defer_pct = 105;
     uint64_t wmean = 1;             // mean arc weight (rounded up)
     uint64_t fingerprint = 0;       // hash of the CSR, keys the tuning cache
     struct Tuned {

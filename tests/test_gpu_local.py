@@ -127,7 +127,7 @@ def test_options_checked(P):
     G = P.Graph.from_host(g)
     assert G.get_option("local_chunks") == 16 and G.get_option("local_chunks_plain") == 0   # defaults
     assert G.get_option("local_chunks_small") == 4 and G.get_option("min_chunk") == 16
-    assert G.get_option("local_time_pct") == 80 and G.get_option("defer_time_pct") == 105
+    assert G.get_option("local_time_pct") == 90 and G.get_option("defer_time_pct") == 105
     for name, bad in [("min_chunk", 0), ("min_chunk", 24), ("min_chunk", 128), ("local_chunks_small", -1),
                       ("local_time_pct", -1), ("defer_time_pct", -1), ("defer_time_pct", 50)]:
         with pytest.raises(P.PPSPError):
