@@ -28,7 +28,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_round_traffic.json")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_2506_16488_amd", "csrc", f) for f in ("kernels.hip", "ppsp_dev.h")]
+# the round kernel and the engine whose defaults shape its launches
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2506_16488_amd", "csrc", f) for f in ("kernels.hip", "ppsp_dev.h", "engine.hip")]
 
 
 def kernel_source_hash():
