@@ -241,6 +241,7 @@ typedef struct {
     uint32_t trials;       /* configurations timed */
     uint32_t from_cache;   /* 1 if read from cache_path */
     uint32_t heavy_window; /* chosen "heavy_window" (graphs with vertices of degree > 512) */
+    uint32_t local_chunks; /* chosen "local_chunks" (A* and BiD-A*; else the graph's setting) */
 } ppsp_tune_result;
 
 /*
@@ -249,7 +250,8 @@ typedef struct {
  * first swept by doubling from a small start while the time improves (the
  * tuning procedure of Section 6.1), then the hub window ("heavy_window", on
  * graphs with vertices of degree > 512), the threshold rule, Delta between the
- * doublings and the number of round-kernel workgroups are refined. The choice
+ * doublings, the number of round-kernel workgroups and, for A* and BiD-A*, the
+ * local-chunk budget ("local_chunks") are refined. The choice
  * is kept in the handle and used by PPSP_SCHED_AUTOTUNED. With cache_path
  * (or NULL) the choice is read from / appended to a text file keyed by a hash
  * of the graph, so a later process can skip the timing. Results of queries are

@@ -179,7 +179,7 @@ struct ppsp_graph_s {
     struct Tuned {
         bool valid = false;
         uint64_t delta = 0;
-        int64_t theta_mode = 2, grid = 0, hwin = 64;
+        int64_t theta_mode = 2, grid = 0, hwin = 64, local = 16;
         double ms = 0;
     } tuned[5][6];                  // per (algo, batch strategy)
     uint64_t qcap = 0;
@@ -1076,15 +1076,21 @@ int batch_impl(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp_opts 
     // ppsp_tune chose for this algorithm and batch strategy.
     struct Restore {
         ppsp_graph g;
-        int64_t mode, grid, hwin;
-        ~Restore() { g->opt_theta_mode = mode; g->opt_grid_blocks = grid; g->opt_heavy_window = hwin; }
-    } restore{g, g->opt_theta_mode, g->opt_grid_blocks, g->opt_heavy_window};
+        int64_t mode, grid, hwin, local;
+        ~Restore() {
+            g->opt_theta_mode = mode;
+            g->opt_grid_blocks = grid;
+            g->opt_heavy_window = hwin;
+            g->opt_local = local;
+        }
+    } restore{g, g->opt_theta_mode, g->opt_grid_blocks, g->opt_heavy_window, g->opt_local};
     if (o->sched == PPSP_SCHED_AUTOTUNED && g->tuned[o->algo][o->batch].valid) {
         const auto &t = g->tuned[o->algo][o->batch];
         delta = t.delta;
         g->opt_theta_mode = t.theta_mode;
         g->opt_grid_blocks = t.grid;
         g->opt_heavy_window = t.hwin;
+        g->opt_local = t.local;
     }
     struct MemoRestore {
         ppsp_graph g;
@@ -2093,28 +2099,29 @@ int ppsp_tune(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp_opts *
     CHK(check_opts(g, opts));
     auto &slot = g->tuned[opts->algo][opts->batch];
     char key[128];
-    snprintf(key, sizeof key, "ppsp-tune-v2 %016llx %u %u", (unsigned long long)g->fingerprint, opts->algo, opts->batch);
+    snprintf(key, sizeof key, "ppsp-tune-v3 %016llx %u %u", (unsigned long long)g->fingerprint, opts->algo, opts->batch);
     if (cache_path) {
         if (FILE *f = fopen(cache_path, "r")) {
             char line[256];
             while (fgets(line, sizeof line, f)) {
                 unsigned long long d;
-                long long mode, grid, hw;
+                long long mode, grid, hw, lc;
                 double ms;
                 if (strncmp(line, key, strlen(key)) == 0 &&
-                    sscanf(line + strlen(key), " %llu %lld %lld %lld %lf", &d, &mode, &grid, &hw, &ms) == 5) {
+                    sscanf(line + strlen(key), " %llu %lld %lld %lld %lld %lf", &d, &mode, &grid, &hw, &lc, &ms) == 6) {
                     slot.valid = true;
                     slot.delta = d;
                     slot.theta_mode = mode;
                     slot.grid = grid;
                     slot.hwin = hw;
+                    slot.local = lc;
                     slot.ms = ms;
                 }
             }
             fclose(f);
             if (slot.valid) {
                 *out = ppsp_tune_result{slot.delta, (uint32_t)slot.theta_mode, (uint32_t)slot.grid, slot.ms, 0, 0, 1,
-                                        (uint32_t)slot.hwin};
+                                        (uint32_t)slot.hwin, (uint32_t)slot.local};
                 return PPSP_OK;
             }
         }
@@ -2123,14 +2130,16 @@ int ppsp_tune(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp_opts *
     ppsp_opts o = *opts;
     o.sched = PPSP_SCHED_FIXED;
     o.flags &= ~PPSP_WANT_PATH;
-    const int64_t mode0 = g->opt_theta_mode, grid0 = g->opt_grid_blocks, hwin0 = g->opt_heavy_window;
+    const int64_t mode0 = g->opt_theta_mode, grid0 = g->opt_grid_blocks, hwin0 = g->opt_heavy_window,
+                  local0 = g->opt_local;
     uint32_t trials = 0;
-    int64_t best_hw = hwin0;
+    int64_t best_hw = hwin0, best_local = local0;
     // wall time of one configuration (best of two runs; the first may allocate)
     auto trial = [&](uint64_t delta, int64_t mode, int64_t grid) -> double {
         g->opt_theta_mode = mode;
         g->opt_grid_blocks = grid;
         g->opt_heavy_window = best_hw;
+        g->opt_local = best_local;
         o.delta = delta;
         double best = 1e300;
         for (int rep = 0; rep < 2; rep++) {
@@ -2178,25 +2187,38 @@ int ppsp_tune(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp_opts *
         const double ms = trial(best_d, best_mode, per_cu * g->cu);
         if (ms < best_ms) { best_ms = ms; best_grid = per_cu * g->cu; }
     }
+    // 3. The local-chunk budget of heuristic searches (the only ones that use it by default).
+    if (is_astar(opts->algo)) {
+        const int64_t start = best_local;
+        for (int64_t lc : {8, 32}) {
+            if (lc == start) continue;
+            const int64_t keep = best_local;
+            best_local = lc;
+            const double ms = trial(best_d, best_mode, best_grid);
+            if (ms < best_ms) best_ms = ms; else best_local = keep;
+        }
+    }
     g->opt_theta_mode = mode0;
     g->opt_grid_blocks = grid0;
     g->opt_heavy_window = hwin0;
+    g->opt_local = local0;
     if (best_ms >= 1e300) return PPSP_E_DEVICE;
     slot.valid = true;
     slot.delta = best_d;
     slot.theta_mode = best_mode;
     slot.grid = best_grid;
     slot.hwin = best_hw;
+    slot.local = best_local;
     slot.ms = best_ms;
     if (cache_path) {
         if (FILE *f = fopen(cache_path, "a")) {
-            fprintf(f, "%s %llu %lld %lld %lld %.3f\n", key, (unsigned long long)best_d, (long long)best_mode,
-                    (long long)best_grid, (long long)best_hw, best_ms);
+            fprintf(f, "%s %llu %lld %lld %lld %lld %.3f\n", key, (unsigned long long)best_d, (long long)best_mode,
+                    (long long)best_grid, (long long)best_hw, (long long)best_local, best_ms);
             fclose(f);
         }
     }
     *out = ppsp_tune_result{best_d, (uint32_t)best_mode, (uint32_t)best_grid, best_ms, default_ms, trials, 0,
-                            (uint32_t)best_hw};
+                            (uint32_t)best_hw, (uint32_t)best_local};
     return PPSP_OK;
 }
 

@@ -314,7 +314,9 @@ def test_autotune_changes_speed_not_results(P, tmp_path):
     # a new handle on the same graph reads the choice back from the cache
     G2 = _graph(P, g)
     r2 = G2.tune(pairs[:32], algo="bidastar", batch="plainstar", cache_path=cache)
+    assert r["local_chunks"] in (8, 16, 32)
     assert r2["from_cache"] == 1 and r2["delta"] == r["delta"] and r2["theta_mode"] == r["theta_mode"]
+    assert r2["local_chunks"] == r["local_chunks"] and r2["heavy_window"] == r["heavy_window"]
     assert np.array_equal(G2.batch_query(pairs, algo="bidastar", sched="autotuned"), exp)
     G2.close()
 
