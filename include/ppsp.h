@@ -304,7 +304,12 @@ int ppsp_tune(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp_opts *
  *                   fixed batch's (rounds that end before the batch does are
  *                   free). Feature rows are traced along the labelled and the
  *                   default trajectories; training starts from `init`
- *                   (caller-drawn).
+ *                   (caller-drawn). Fixed-Delta stepping then judges the
+ *                   result: the sample batch is timed under the trained
+ *                   network and under constant networks that always pick the
+ *                   base multiplier (bin 4) or, in label_mode 1, the fastest
+ *                   fixed one; a faster constant network is installed and
+ *                   returned in params_out instead (rep->fallback_bin).
  * Errors: PPSP_E_INVALID (null pointers, label >= 8, a non-finite
  * parameter, a strategy other than Plain / Plain* for tracing or fitting),
  * the errors of ppsp_batch_query.
@@ -324,6 +329,10 @@ typedef struct {
     double c_round_ms;        /* label_mode 1: fitted cost of a batch round (ms) */
     double c_arc_ns;          /* label_mode 1: fitted cost of a scanned arc (ns) */
     uint32_t best_fixed_bin;  /* label_mode 1: the fastest fixed multiplier bin for the sample batch */
+    uint32_t fallback_bin;    /* PPSP_MLP_BINS: the trained network was installed; else the bin of the
+                                 constant network installed instead (fixed-Delta fallback) */
+    double learned_ms;        /* sample batch under the trained network (best of two runs) */
+    double fixed_ms;          /* sample batch under the fastest constant network tried (best of two) */
 } ppsp_fit_report;
 
 int ppsp_mlp_forward(int device, const float *params, const float *x, uint32_t n, float *logits);

@@ -82,7 +82,8 @@ class FitReport(ctypes.Structure):
     _fields_ = [("label_hist", ctypes.c_uint32 * 8), ("rows", ctypes.c_uint64), ("loss_first", ctypes.c_double),
                 ("loss_last", ctypes.c_double), ("train_acc", ctypes.c_double), ("label_ms", ctypes.c_double),
                 ("train_ms", ctypes.c_double), ("c_round_ms", ctypes.c_double), ("c_arc_ns", ctypes.c_double),
-                ("best_fixed_bin", ctypes.c_uint32)]
+                ("best_fixed_bin", ctypes.c_uint32), ("fallback_bin", ctypes.c_uint32),
+                ("learned_ms", ctypes.c_double), ("fixed_ms", ctypes.c_double)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}

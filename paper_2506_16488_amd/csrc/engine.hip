@@ -2602,6 +2602,47 @@ int ppsp_mlp_fit(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp_opt
         hit += best == Y[r];
     }
     R.train_acc = Y.empty() ? 0.0 : (double)hit / Y.size();
+    // 5. Fixed-Delta stepping judges the network. The sample batch runs under
+    //    the trained network and under constant networks that always pick the
+    //    base multiplier (bin 4) or, with batch labels, the fastest fixed one;
+    //    all through the same learned-schedule path. If a constant network is
+    //    faster, it is the one installed (and returned).
+    const std::vector<float> trained(params_out, params_out + MLP_NPARAM);
+    auto constant_net = [](uint32_t b) {
+        std::vector<float> p(MLP_NPARAM, 0.f);
+        p[MLP_NPARAM - MLP_K + b] = 1.f;   // output bias: the logits are constant, argmax b
+        return p;
+    };
+    ppsp_opts lo = *opts;
+    lo.sched = PPSP_SCHED_LEARNED;
+    lo.flags &= ~(uint32_t)PPSP_WANT_PATH;
+    std::vector<uint64_t> jd(k);
+    auto time_net = [&](const float *p, double &ms) -> int {
+        CHK(mlp_load_impl(g, p));
+        ms = 1e300;
+        for (int r = 0; r < 2; r++) {   // best of two (the first run may grow buffers)
+            const auto a = std::chrono::steady_clock::now();
+            CHK(batch_impl(g, pairs, k, &lo, nullptr, jd.data(), nullptr, nullptr, 0, nullptr));
+            ms = std::min(ms, std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - a).count());
+        }
+        return PPSP_OK;
+    };
+    CHK(time_net(trained.data(), R.learned_ms));
+    std::vector<uint32_t> cand{(uint32_t)(MLP_K / 2)};
+    if (label_mode == 1 && R.best_fixed_bin != (uint32_t)(MLP_K / 2)) cand.push_back(R.best_fixed_bin);
+    uint32_t fb = cand[0];
+    R.fixed_ms = 1e300;
+    for (uint32_t b : cand) {
+        double ms = 0;
+        CHK(time_net(constant_net(b).data(), ms));
+        if (ms < R.fixed_ms) { R.fixed_ms = ms; fb = b; }
+    }
+    R.fallback_bin = MLP_K;
+    if (R.fixed_ms < R.learned_ms) {
+        const std::vector<float> p = constant_net(fb);
+        memcpy(params_out, p.data(), MLP_NPARAM * 4);
+        R.fallback_bin = fb;
+    }
     CHK(mlp_load_impl(g, params_out));
     if (rep) *rep = R;
     return PPSP_OK;

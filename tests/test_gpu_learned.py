@@ -161,6 +161,7 @@ def test_fit_recipe(P):
     assert sum(rep["label_hist"]) == 24
     assert rep["rows"] > 0 and rep["loss_last"] <= rep["loss_first"]
     assert 0.0 <= rep["train_acc"] <= 1.0
+    _check_judge(rep, params)
     test = gen.pairs_uniform(g.n, 50, seed=84)
     exp = oracle.pp_batch(g.n, g.row_ptr, g.col, g.w, test)
     assert np.array_equal(G.batch_query(test, algo="bidastar", sched="learned"), exp)
@@ -170,4 +171,35 @@ def test_fit_recipe(P):
     assert sum(rep["label_hist"]) == 24 and 0 <= rep["best_fixed_bin"] < 8
     assert rep["c_round_ms"] >= 0 and rep["c_arc_ns"] >= 0
     assert np.array_equal(G.batch_query(test, algo="bidastar", sched="learned"), exp)
+    _check_judge(rep, params)
+    G.close()
+
+
+def _check_judge(rep, params):
+    """The fixed-Delta judge: either the trained network won on the sample
+    batch, or the installed (returned) network is the constant one for the
+    faster fixed multiplier."""
+    assert rep["learned_ms"] > 0 and rep["fixed_ms"] > 0
+    fb = rep["fallback_bin"]
+    assert 0 <= fb <= 8
+    if fb == 8:
+        assert rep["learned_ms"] <= rep["fixed_ms"]
+    else:
+        assert rep["fixed_ms"] < rep["learned_ms"]
+        assert np.count_nonzero(params) == 1 and params[-8 + fb] == 1.0
+
+
+def test_constant_network_is_exact(P):
+    """The fallback network (zero weights, one output bias) is a valid learned
+    schedule: every search keeps one multiplier and the distances are exact."""
+    g = gen.lattice(96, 0.05, seed=87)
+    test = gen.pairs_uniform(g.n, 40, seed=88)
+    exp = oracle.pp_batch(g.n, g.row_ptr, g.col, g.w, test)
+    G = P.Graph.from_host(g)
+    for b in (0, 4, 7):
+        p = np.zeros(P.MLP_PARAMS, np.float32)
+        p[-8 + b] = 1.0
+        G.mlp_load(p)
+        for algo in ("bidastar", "bids"):
+            assert np.array_equal(G.batch_query(test, algo=algo, sched="learned"), exp), (b, algo)
     G.close()
