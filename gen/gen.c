@@ -26,6 +26,7 @@
 #include <stdlib.h>
 #include <string.h>
 #include <math.h>
+#include <omp.h>
 
 typedef uint64_t u64;
 typedef uint32_t u32;
@@ -41,11 +42,12 @@ static inline u64 mix64(u64 z) {
     return z ^ (z >> 31);
 }
 
+/* Key of stream `stream` under `seed`, and word number `idx` of a keyed stream. */
+static inline u64 stream_key(u64 seed, u64 stream) { return mix64(seed ^ mix64(stream * 0xD1B54A32D192ED03ULL)); }
+static inline u64 keyed_rand(u64 key, u64 idx) { return mix64(key + idx * 0x9E3779B97F4A7C15ULL); }
+
 /* Random 64-bit word number `idx` of stream `stream` under `seed`. */
-u64 gen_rand(u64 seed, u64 stream, u64 idx) {
-    u64 key = mix64(seed ^ mix64(stream * 0xD1B54A32D192ED03ULL));
-    return mix64(key + idx * 0x9E3779B97F4A7C15ULL);
-}
+u64 gen_rand(u64 seed, u64 stream, u64 idx) { return keyed_rand(stream_key(seed, stream), idx); }
 
 /* Uniform integer in [0, range) from a 64-bit word (multiply-shift). */
 static inline u64 below(u64 r, u64 range) {
@@ -210,31 +212,55 @@ void gen_lattice_arcs(u32 L, double p_diag, u64 seed, const i32 *xy, u32 frac_bi
 
 /* ---- R-MAT ------------------------------------------------------------------ */
 
-static int cmp_u64(const void *a, const void *b) {
-    u64 x = *(const u64 *)a, y = *(const u64 *)b;
-    return (x > y) - (x < y);
-}
-
-/* LSD radix sort of u64 keys (16-bit digits), tmp has the same size. */
+/* Parallel LSD radix sort of u64 keys on their low key_bits bits (16-bit
+ * digits; stable: every thread scatters its own contiguous slice, in order,
+ * after the slices of lower threads). tmp has the same size as a. */
 static void radix_sort_u64(u64 *a, u64 *tmp, u64 n, int key_bits) {
+    const u64 NB = 65536;
+    const int passes = (key_bits + 15) / 16;
+    const int T = omp_get_max_threads();
+    u64 *cnt = (u64 *)malloc((u64)T * NB * sizeof(u64));
     u64 *src = a, *dst = tmp;
-    int passes = (key_bits + 15) / 16;
-    u64 *cnt = (u64 *)malloc(65536 * sizeof(u64));
     for (int p = 0; p < passes; p++) {
-        int sh = 16 * p;
-        memset(cnt, 0, 65536 * sizeof(u64));
-        for (u64 i = 0; i < n; i++) cnt[(src[i] >> sh) & 0xFFFF]++;
-        u64 s = 0;
-        for (int d = 0; d < 65536; d++) { u64 c = cnt[d]; cnt[d] = s; s += c; }
-        for (u64 i = 0; i < n; i++) dst[cnt[(src[i] >> sh) & 0xFFFF]++] = src[i];
+        const int sh = 16 * p;
+        #pragma omp parallel num_threads(T)
+        {
+            const int t = omp_get_thread_num(), nt = omp_get_num_threads();
+            const u64 lo = n * (u64)t / (u64)nt, hi = n * (u64)(t + 1) / (u64)nt;
+            u64 *c = cnt + (u64)t * NB;
+            memset(c, 0, NB * sizeof(u64));
+            for (u64 i = lo; i < hi; i++) c[(src[i] >> sh) & (NB - 1)]++;
+            #pragma omp barrier
+            #pragma omp single
+            {
+                u64 s = 0;
+                for (u64 d = 0; d < NB; d++)
+                    for (int tt = 0; tt < nt; tt++) {
+                        const u64 x = cnt[(u64)tt * NB + d];
+                        cnt[(u64)tt * NB + d] = s;
+                        s += x;
+                    }
+            }
+            for (u64 i = lo; i < hi; i++) dst[c[(src[i] >> sh) & (NB - 1)]++] = src[i];
+        }
         u64 *t = src; src = dst; dst = t;
     }
     if (src != a) memcpy(a, src, n * sizeof(u64));
     free(cnt);
 }
 
+/* First index i of the sorted a[0..n) with a[i] >= x. */
+static u64 lower_bound_u64(const u64 *a, u64 n, u64 x) {
+    u64 lo = 0, hi = n;
+    while (lo < hi) {
+        const u64 mid = lo + (hi - lo) / 2;
+        if (a[mid] < x) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
 /* Generates the R-MAT graph; returns a malloc'd array of unique canonical
- * undirected edges (key = min<<32 | max), count in *n_edges. */
+ * undirected edges (key = min << scale | max, ascending), count in *n_edges. */
 static u64 *rmat_edges(u32 scale, u32 edge_factor, double a, double b, double c,
                        u64 seed, u64 *n_edges) {
     u64 n = 1ULL << scale;
@@ -251,13 +277,16 @@ static u64 *rmat_edges(u32 scale, u32 edge_factor, double a, double b, double c,
         pk[v] = ((gen_rand(seed, ST_PERM, (u64)v) >> scale) << scale) | (u64)v;
     radix_sort_u64(pk, ptmp, n, 64);
     u32 *perm = (u32 *)malloc(n * sizeof(u32));
-    for (u64 r = 0; r < n; r++) perm[pk[r] & (n - 1)] = (u32)r;  /* vertex -> new id */
+    #pragma omp parallel for schedule(static)
+    for (long long r = 0; r < (long long)n; r++) perm[pk[r] & (n - 1)] = (u32)r;  /* vertex -> new id */
     free(pk); free(ptmp);
+    /* self-loops get the all-ones key, above every edge key in its low 2 * scale bits */
+    const u64 kr = stream_key(seed, ST_RMAT);
     #pragma omp parallel for schedule(static)
     for (long long ee = 0; ee < (long long)E; ee++) {
         u64 u = 0, v = 0;
         for (u32 lvl = 0; lvl < scale; lvl++) {
-            u64 r = gen_rand(seed, ST_RMAT, (u64)ee * scale + lvl) >> 11;
+            u64 r = keyed_rand(kr, (u64)ee * scale + lvl) >> 11;
             int q = (r < ta) ? 0 : (r < tb) ? 1 : (r < tc) ? 2 : 3;
             u = (u << 1) | (u64)(q >> 1);
             v = (v << 1) | (u64)(q & 1);
@@ -265,11 +294,11 @@ static u64 *rmat_edges(u32 scale, u32 edge_factor, double a, double b, double c,
         u32 pu = perm[u], pv = perm[v];
         if (pu == pv) { keys[ee] = ~0ULL; continue; }
         u64 lo = pu < pv ? pu : pv, hi = pu < pv ? pv : pu;
-        keys[ee] = (lo << 32) | hi;
+        keys[ee] = (lo << scale) | hi;
     }
     free(perm);
     u64 *tmp = (u64 *)malloc(E * sizeof(u64));
-    radix_sort_u64(keys, tmp, E, 64);
+    radix_sort_u64(keys, tmp, E, 2 * (int)scale);
     free(tmp);
     u64 k = 0;
     for (u64 i = 0; i < E; i++) {
@@ -292,30 +321,51 @@ void *gen_rmat_begin(u32 scale, u32 edge_factor, double a, double b, double c,
     return st;
 }
 
-/* Builds the symmetric CSR (neighbours ascending) and frees the state. */
+/* Builds the symmetric CSR and frees the state. Row v holds its neighbours
+ * below v (ascending), then those above v (ascending); the weight of edge
+ * {lo, hi} is drawn from the hash of (lo << 32 | hi). The neighbours above v
+ * are the edges keyed (v, hi), contiguous in the sorted edge list; those
+ * below v come from a copy of the list keyed (hi, lo) and sorted again. */
 void gen_rmat_finish(void *h, u64 *row_ptr, u32 *col, u32 *w) {
     rmat_state *st = (rmat_state *)h;
-    u64 n = 1ULL << st->scale;
-    u64 span = (u64)st->whi - st->wlo + 1;
-    memset(row_ptr, 0, (n + 1) * sizeof(u64));
-    for (u64 i = 0; i < st->ne; i++) {
-        row_ptr[(st->edges[i] >> 32) + 1]++;
-        row_ptr[(st->edges[i] & 0xFFFFFFFFULL) + 1]++;
+    const u32 s = st->scale;
+    const u64 n = 1ULL << s, ne = st->ne, mask = n - 1;
+    const u64 span = (u64)st->whi - st->wlo + 1;
+    const u64 *e1 = st->edges;
+    const u64 kw = stream_key(st->seed, ST_WEIGHT);
+    u64 *e2 = (u64 *)malloc((ne ? ne : 1) * sizeof(u64));
+    u64 *tmp = (u64 *)malloc((ne ? ne : 1) * sizeof(u64));
+    #pragma omp parallel for schedule(static)
+    for (long long i = 0; i < (long long)ne; i++) e2[i] = ((e1[i] & mask) << s) | (e1[i] >> s);
+    radix_sort_u64(e2, tmp, ne, 2 * (int)s);
+    free(tmp);
+    u64 *a1 = (u64 *)malloc((n + 1) * sizeof(u64));   /* first edge (v, .) in e1 */
+    u64 *a2 = (u64 *)malloc((n + 1) * sizeof(u64));   /* first edge (v, .) in e2 */
+    #pragma omp parallel for schedule(static)
+    for (long long v = 0; v < (long long)n; v++) {
+        a1[v] = lower_bound_u64(e1, ne, (u64)v << s);
+        a2[v] = lower_bound_u64(e2, ne, (u64)v << s);
     }
-    for (u64 v = 0; v < n; v++) row_ptr[v + 1] += row_ptr[v];
-    u64 *pos = (u64 *)malloc(n * sizeof(u64));
-    memcpy(pos, row_ptr, n * sizeof(u64));
-    /* edges are sorted by (lo, hi): scanning them in order appends
-     * neighbours of lo ascending; neighbours of hi (< hi) arrive ascending by lo */
-    for (u64 i = 0; i < st->ne; i++) {
-        u64 key = st->edges[i];
-        u32 lo = (u32)(key >> 32), hi = (u32)(key & 0xFFFFFFFFULL);
-        u32 wt = st->wlo + (u32)below(gen_rand(st->seed, ST_WEIGHT, key), span);
-        u64 p = pos[hi]++; col[p] = lo; w[p] = wt;
-        p = pos[lo]++; col[p] = hi; w[p] = wt;
+    a1[n] = ne;
+    a2[n] = ne;
+    row_ptr[0] = 0;
+    for (u64 v = 0; v < n; v++) row_ptr[v + 1] = row_ptr[v] + (a1[v + 1] - a1[v]) + (a2[v + 1] - a2[v]);
+    #pragma omp parallel for schedule(dynamic, 4096)
+    for (long long vv = 0; vv < (long long)n; vv++) {
+        const u64 v = (u64)vv;
+        u64 p = row_ptr[v];
+        for (u64 j = a2[v]; j < a2[v + 1]; j++, p++) {
+            const u64 lo = e2[j] & mask;
+            col[p] = (u32)lo;
+            w[p] = st->wlo + (u32)below(keyed_rand(kw, (lo << 32) | v), span);
+        }
+        for (u64 j = a1[v]; j < a1[v + 1]; j++, p++) {
+            const u64 hi = e1[j] & mask;
+            col[p] = (u32)hi;
+            w[p] = st->wlo + (u32)below(keyed_rand(kw, (v << 32) | hi), span);
+        }
     }
-    free(pos);
-    /* each row now holds neighbours < v (ascending) then > v (ascending) */
+    free(a1); free(a2); free(e2);
     free(st->edges);
     free(st);
 }
