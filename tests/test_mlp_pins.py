@@ -2,8 +2,9 @@
 
 The learned schedule is not in the paper, so these pins come from the
 network's own definition: finite differences of the loss check the
-chain-rule gradient, closed forms check the loss, and Adam's first step
-has a closed form.
+chain-rule gradient, closed forms check the loss, and Adam (Kingma and Ba,
+Algorithm 1) is pinned by the closed forms of its moment recurrences under a
+constant and a sign-alternating gradient over several steps.
 """
 import numpy as np
 
@@ -90,6 +91,46 @@ def test_adam_first_step_closed_form():
     p1, m, v = mlp.adam_step(p, np.zeros(100), np.zeros(100), g, 1, lr)
     assert np.allclose(p1, p - lr * g / (np.abs(g) + 1e-8))
     assert np.allclose(m, 0.1 * g) and np.allclose(v, 0.001 * g * g)
+
+
+def test_adam_constant_gradient_closed_form_t1_to_5():
+    """A constant gradient g from zero moments: m_t = (1 - b1^t) g and
+    v_t = (1 - b2^t) g^2, so the bias-corrected moments are exactly g and g^2
+    at every t and each step moves p by -lr g / (|g| + eps). A dropped or
+    mis-indexed bias correction changes the step size after t = 1."""
+    rng = np.random.default_rng(21)
+    p0 = rng.normal(size=64)
+    g = rng.normal(size=64) * 10.0 ** rng.integers(-3, 3, 64)
+    lr, b1, b2, eps = 2e-3, 0.9, 0.999, 1e-8
+    p, m, v = p0.copy(), np.zeros(64), np.zeros(64)
+    for t in range(1, 6):
+        p, m, v = mlp.adam_step(p, m, v, g, t, lr)
+        assert np.allclose(m, (1 - b1 ** t) * g, rtol=1e-12, atol=0)
+        assert np.allclose(v, (1 - b2 ** t) * g * g, rtol=1e-12, atol=0)
+        assert np.allclose(p, p0 - t * lr * g / (np.abs(g) + eps), rtol=1e-12, atol=1e-15)
+
+
+def test_adam_alternating_gradient_closed_form_t1_to_5():
+    """Gradients g, -g, g, -g, ...: m_t = (1 - b1) g (b1^t - (-1)^t) / (1 + b1)
+    (the geometric sum of the recurrence) and v_t = (1 - b2^t) g^2; the update
+    divides by the bias corrections 1 - b1^t and 1 - b2^t of step t."""
+    rng = np.random.default_rng(22)
+    p0 = rng.normal(size=32)
+    g = rng.normal(size=32)
+    lr, b1, b2, eps = 1e-2, 0.9, 0.999, 1e-8
+    p, m, v = p0.copy(), np.zeros(32), np.zeros(32)
+    expect = p0.copy()
+    for t in range(1, 6):
+        gt = g if t % 2 == 1 else -g
+        p, m, v = mlp.adam_step(p, m, v, gt, t, lr)
+        mt = (1 - b1) * g * (b1 ** t - (-1.0) ** t) / (1 + b1)
+        vt = (1 - b2 ** t) * g * g
+        assert np.allclose(m, mt, rtol=1e-12, atol=1e-15)
+        assert np.allclose(v, vt, rtol=1e-12, atol=0)
+        expect = expect - lr * (mt / (1 - b1 ** t)) / (np.sqrt(vt / (1 - b2 ** t)) + eps)
+        assert np.allclose(p, expect, rtol=1e-12, atol=1e-15)
+    # the step sizes differ from a no-bias-correction update after t = 1
+    assert not np.allclose(m / (1 - b1 ** 5), m)
 
 
 def test_gradient_descent_lowers_loss():

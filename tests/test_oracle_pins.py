@@ -55,6 +55,25 @@ def test_dijkstra_matches_floyd_warshall(seed):
             assert oracle.pp(g.n, g.row_ptr, g.col, g.w, s, t) == int(D[s, t])
 
 
+@pytest.mark.parametrize("nthreads", [1, 3, 7])
+def test_pp_batch_matches_floyd_warshall_and_single_queries(nthreads):
+    """The batch checker that most GPU tests use: every entry equals the
+    single-pair Dijkstra and the Floyd-Warshall matrix, whatever the thread
+    count (pairs in shuffled order, duplicates, s = t and unreachable pairs)."""
+    for seed in range(16):
+        rng = np.random.default_rng(300 + seed)
+        n = int(rng.integers(2, 36))
+        g = gen.random_graph(n, int(rng.integers(0, 3 * n + 1)), int(rng.choice([1, 7, 1000])), seed=300 + seed,
+                             wmin=seed % 2, symmetric=bool(seed % 3), allow_loops=True)
+        D = oracle.floyd_warshall(g.n, g.row_ptr, g.col, g.w)
+        allp = np.array([(s, t) for s in range(n) for t in range(n)], np.uint32)
+        pairs = np.concatenate([allp[rng.permutation(len(allp))], allp[rng.integers(0, len(allp), 7)]])
+        got = oracle.pp_batch(g.n, g.row_ptr, g.col, g.w, pairs, nthreads=nthreads)
+        assert np.array_equal(got, D[pairs[:, 0], pairs[:, 1]]), (seed, nthreads)
+        one = [oracle.pp(g.n, g.row_ptr, g.col, g.w, int(s), int(t)) for s, t in pairs[:40]]
+        assert got[:40].tolist() == one
+
+
 @pytest.mark.parametrize("seed", range(12))
 def test_dijkstra_matches_bellman_ford(seed):
     rng = np.random.default_rng(1000 + seed)
