@@ -85,10 +85,11 @@ RANDBENCH_OPS = 1 << 28
 def random_access_roofline(P, agg, launches, avg_launch_us):
     """Second roofline for the round kernel: its scattered loads and atomics
     per launch priced at the device's measured rates for such accesses
-    (ppsp_randbench, taken now on this GPU). frac = that floor / the launch
+    (the probe library's scattered-access kernel, taken now on this GPU). frac = that floor / the launch
     time; atomics are counted from successful relaxations, a lower bound."""
-    load_ms = P.randbench(RANDBENCH_WORDS, RANDBENCH_OPS, 0)
-    atom_ms = P.randbench(RANDBENCH_WORDS, RANDBENCH_OPS, 1)
+    from paper_2506_16488_amd import probe
+    load_ms = probe.randbench(RANDBENCH_WORDS, RANDBENCH_OPS, 0)
+    atom_ms = probe.randbench(RANDBENCH_WORDS, RANDBENCH_OPS, 1)
     load_rate = RANDBENCH_OPS / (load_ms * 1e-3)
     atom_rate = RANDBENCH_OPS / (atom_ms * 1e-3)
     loads = (LOADS_PER_SCANNED_VERTEX * agg["scanned_vertices"] + agg["scanned_arcs"]) / launches

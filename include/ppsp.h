@@ -13,7 +13,7 @@
  *     (Section 3.5, Theorem bdastar-correctness);
  *   - Delta*-stepping thresholds (Section 2: the i-th threshold is i*Delta);
  *   - batch queries through the query graph (Section 4.1) and the Plain,
- *     Plain*, Multi-BiDS, Plain-SSSP and VC-SSSP strategies (Section 4.2),
+ *     Plain*, Multi-BiDS (Section 4.2), Plain-SSSP and VC-SSSP (Section 4.3) strategies,
  *     with the paper's adaptation to directed graphs (bipartite query graph,
  *     backward searches on the transposed graph);
  *   - single-source distances (ppsp_sssp), an autotuner, a learned step
@@ -72,7 +72,7 @@ enum ppsp_algo {
     PPSP_BIDASTAR = 4   /* bidirectional A*: prune 2*delta +/- (h_t - h_s) >= mu (Section 3.5) */
 };
 
-/* Batch strategy (Section 4.2). */
+/* Batch strategy: the BiDS-based strategies of Section 4.2 and the SSSP-based ones of Section 4.3. */
 enum ppsp_batch {
     PPSP_BATCH_PLAIN = 0,      /* one query after another */
     PPSP_BATCH_PLAINSTAR = 1,  /* all queries at once, each with its own searches */
@@ -209,7 +209,7 @@ int ppsp_sssp(ppsp_graph g, uint32_t s, const ppsp_opts *opts, void *hip_stream,
  *   path_vtx  host buffer of path_cap vertex ids, or NULL
  * opts->batch selects Plain, Plain* or Multi-BiDS; Multi-BiDS requires
  * algo = PPSP_BIDS (the paper defines no batched heuristic search).
- * The SSSP-based strategies of Section 4.2 run one search without pruning per
+ * The SSSP-based strategies of Section 4.3 run one search without pruning per
  * root and read every query's distance off its root's search: Plain-SSSP
  * (PPSP_BATCH_SSSP) roots one search at every distinct source; VC-SSSP
  * (PPSP_BATCH_VC) at the vertices of a vertex cover of the query graph
@@ -456,7 +456,7 @@ int ppsp_set_option(ppsp_graph g, const char *name, int64_t value);
 int ppsp_get_option(ppsp_graph g, const char *name, int64_t *value);
 
 /*
- * The query-graph vertex cover that PPSP_BATCH_VC runs on (Section 4.2 and
+ * The query-graph vertex cover that PPSP_BATCH_VC runs on (Section 4.3 and
  * the adaptation to directed graphs): the k pairs (pairs[2q], pairs[2q+1])
  * are the edges of the query graph. Undirected (directed = 0): (s, t) and
  * (t, s) are one edge; the cover is an exact minimum in every connected
@@ -488,19 +488,6 @@ const char *ppsp_status_str(int status);
 /* Detail of the most recent PPSP_E_DEVICE / PPSP_E_OOM on this thread (the
  * failing HIP call and its error name), or "" . Valid until the next call. */
 const char *ppsp_last_error(void);
-
-/*
- * Measurement: the device's rate of scattered accesses, the resource the
- * round kernel is bound by (each relaxation reads one vertex's state pair at
- * a data-dependent address and, when it lowers it, performs one 64-bit
- * atomic minimum). Times one kernel doing `accesses` operations at
- * pseudo-random positions (a fixed counter hash) of a fresh device table of
- * `words` 64-bit words: kind 0 = 16-byte loads, kind 1 = 64-bit atomicMin.
- * *ms receives the kernel time of the second of two runs (HIP events).
- * The search path never calls it. Errors: PPSP_E_INVALID (null ms,
- * words < 2 or > 2^40, accesses == 0, kind not 0/1), PPSP_E_OOM, PPSP_E_DEVICE.
- */
-int ppsp_randbench(int device, uint64_t words, uint64_t accesses, int kind, double *ms);
 
 /* Library version, e.g. "0.1.0". */
 const char *ppsp_version(void);

@@ -97,7 +97,7 @@ EXPORTS = ["ppsp_graph_create", "ppsp_graph_destroy", "ppsp_query", "ppsp_batch_
            "ppsp_set_option", "ppsp_get_option", "ppsp_heuristic_fx", "ppsp_status_str", "ppsp_version",
            "ppsp_last_error", "ppsp_tune", "ppsp_server_create", "ppsp_server_submit", "ppsp_server_poll",
            "ppsp_server_wait", "ppsp_server_stats", "ppsp_server_destroy", "ppsp_mlp_forward", "ppsp_mlp_grad",
-           "ppsp_mlp_train", "ppsp_mlp_load", "ppsp_sched_trace", "ppsp_mlp_fit", "ppsp_randbench",
+           "ppsp_mlp_train", "ppsp_mlp_load", "ppsp_sched_trace", "ppsp_mlp_fit",
            "ppsp_query_cover", "ppsp_sssp"]
 
 _lib_handle = None
@@ -163,8 +163,6 @@ def lib():
         for f in ("forward", "grad", "train", "load", "fit"):
             getattr(L, "ppsp_mlp_" + f).restype = ctypes.c_int
         L.ppsp_sched_trace.restype = ctypes.c_int
-        L.ppsp_randbench.argtypes = [ctypes.c_int, u64, u64, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
-        L.ppsp_randbench.restype = ctypes.c_int
         L.ppsp_query_cover.argtypes = [P, u32, u32, P, P, ctypes.POINTER(u32)]
         L.ppsp_query_cover.restype = ctypes.c_int
         L.ppsp_sssp.argtypes = [P, u32, ctypes.POINTER(Opts), P, P]
@@ -341,14 +339,6 @@ def query_cover(pairs, directed=False):
     _check(lib().ppsp_query_cover(_ptr(pairs), k, 1 if directed else 0, _ptr(root), _ptr(ft), ctypes.byref(size)),
            "ppsp_query_cover")
     return root, ft, int(size.value)
-
-
-def randbench(words, accesses, kind, device=0) -> float:
-    """Kernel milliseconds for `accesses` scattered 16-byte loads (kind 0) or
-    64-bit atomicMin (kind 1) over `words` 64-bit words (ppsp_randbench)."""
-    ms = ctypes.c_double(0)
-    _check(lib().ppsp_randbench(device, int(words), int(accesses), int(kind), ctypes.byref(ms)), "ppsp_randbench")
-    return ms.value
 
 
 def last_stats(h) -> dict:

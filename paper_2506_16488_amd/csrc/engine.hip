@@ -999,7 +999,7 @@ std::vector<uint32_t> query_cover(const std::vector<Query> &qs, bool directed, s
     return by;
 }
 
-// Plain-SSSP and VC-SSSP (Section 4.2): one search without pruning per root,
+// Plain-SSSP and VC-SSSP (Section 4.3): one search without pruning per root,
 // each query read off its root's search (a gather after the rounds).
 int run_cover(ppsp_graph g, const std::vector<Query> &qs, const ppsp_opts *o, uint64_t delta,
               std::vector<Answer> &ans, const std::vector<uint32_t> &root_of, const std::vector<uint8_t> &root_rev) {

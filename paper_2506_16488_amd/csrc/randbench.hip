@@ -2,17 +2,20 @@
 // roofline: the round kernel is bound by scattered 8-16 byte accesses to
 // the search state, whose achievable rate is far below streaming bandwidth.
 //
-// ppsp_randbench times one kernel that performs `accesses` operations at
+// This is a measurement probe built into its own library (libppsp_probe.so),
+// outside the search library and its C interface. probe_randbench(device,
+// words, accesses, kind, ms) times one kernel that performs `accesses`
+// operations at
 // pseudo-random 16-byte-aligned positions of a table of `words` 64-bit words
 // (positions from a counter hash, so every run is the same):
 //   kind 0: 16-byte loads (the state pair of a vertex), summed per thread
 //   kind 1: 64-bit atomicMin at device scope (the WriteMin of a relaxation)
-// and returns the kernel time (HIP events) in *ms. Measurement tooling: the
-// search path does not use it.
+// and returns the kernel time (HIP events) of the second of two runs in *ms.
+// Returns 0, or -1 for bad arguments (null ms, words < 2 or > 2^40,
+// accesses == 0, kind not 0/1), -3 when the table cannot be allocated, -7 on
+// a HIP error.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
-
-#include "ppsp.h"
 
 namespace ppsp_randbench_kernels {
 
@@ -44,13 +47,14 @@ __global__ __launch_bounds__(256) void k_rand_atomic(unsigned long long *t, uint
 
 using namespace ppsp_randbench_kernels;
 
-extern "C" int ppsp_randbench(int device, uint64_t words, uint64_t accesses, int kind, double *ms) {
-    if (!ms || words < 2 || accesses == 0 || kind < 0 || kind > 1 || words > (1ull << 40)) return PPSP_E_INVALID;
-    if (hipSetDevice(device) != hipSuccess) return PPSP_E_DEVICE;
+extern "C" int probe_randbench(int device, uint64_t words, uint64_t accesses, int kind, double *ms) {
+    enum { E_INVALID = -1, E_OOM = -3, E_DEVICE = -7 };
+    if (!ms || words < 2 || accesses == 0 || kind < 0 || kind > 1 || words > (1ull << 40)) return E_INVALID;
+    if (hipSetDevice(device) != hipSuccess) return E_DEVICE;
     words &= ~1ull;
     void *t = nullptr, *sink = nullptr;
-    if (hipMalloc(&t, words * 8) != hipSuccess) return PPSP_E_OOM;
-    if (hipMalloc(&sink, 8) != hipSuccess) { (void)hipFree(t); return PPSP_E_OOM; }
+    if (hipMalloc(&t, words * 8) != hipSuccess) return E_OOM;
+    if (hipMalloc(&sink, 8) != hipSuccess) { (void)hipFree(t); return E_OOM; }
     int rc = 0;
     hipEvent_t a, b;
     (void)hipEventCreate(&a);
@@ -64,9 +68,9 @@ extern "C" int ppsp_randbench(int device, uint64_t words, uint64_t accesses, int
             k_rand_load<<<blocks, threads>>>((const ulonglong2 *)t, words / 2, per, (uint64_t *)sink);
         else
             k_rand_atomic<<<blocks, threads>>>((unsigned long long *)t, words, per);
-        if (hipGetLastError() != hipSuccess) { rc = PPSP_E_DEVICE; break; }
+        if (hipGetLastError() != hipSuccess) { rc = E_DEVICE; break; }
         (void)hipEventRecord(b, nullptr);
-        if (hipEventSynchronize(b) != hipSuccess) rc = PPSP_E_DEVICE;
+        if (hipEventSynchronize(b) != hipSuccess) rc = E_DEVICE;
         float f = 0;
         (void)hipEventElapsedTime(&f, a, b);
         *ms = f;

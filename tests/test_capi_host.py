@@ -118,9 +118,18 @@ def test_no_cpu_fallback_in_binding():
         assert "oracle" not in open(os.path.join(ROOT, "paper_2506_16488_amd", "csrc", f)).read()
 
 
-def test_randbench_rejects_bad_arguments_before_device():
+def test_randbench_probe_is_outside_the_search_library():
+    """The scattered-access probe lives in its own library; it rejects bad
+    arguments before touching a device."""
     P = _ppsp()
+    from paper_2506_16488_amd import probe
+    assert _not_exported(P.SO_PATH, "ppsp_randbench")
     for words, acc, kind in ((1, 10, 0), (1 << 20, 0, 0), (1 << 20, 10, 2), ((1 << 40) + 2, 10, 0)):
-        with pytest.raises(P.PPSPError) as e:
-            P.randbench(words, acc, kind)
-        assert e.value.code == P.E_INVALID
+        with pytest.raises(ValueError):
+            probe.randbench(words, acc, kind)
+
+
+def _not_exported(so, name):
+    import subprocess
+    out = subprocess.run(["nm", "-D", "--defined-only", so], capture_output=True, text=True).stdout
+    return all(l.split()[-1] != name for l in out.splitlines() if l.strip())

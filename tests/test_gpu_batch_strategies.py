@@ -1,4 +1,4 @@
-"""GPU parity of the batch strategies of Section 4.2 on the query-graph
+"""GPU parity of the batch strategies of Sections 4.2 and 4.3 on the query-graph
 patterns of the batch experiments (star, fork, chain, cycle, bipartite,
 clique, separate, random over six sources; and 30 sources with 200 random
 pairs), against the oracle."""
