@@ -161,8 +161,9 @@ typedef struct ppsp_graph_s *ppsp_graph;
  *              and paths are translated); results are identical.
  *   out        receives the handle
  * Errors: PPSP_E_INVALID (bad CSR), PPSP_E_RANGE (col >= n, m too large,
- * coordinate span too large for exact 64-bit arithmetic), PPSP_E_OOM,
- * PPSP_E_DEVICE.
+ * coordinate span too large for exact 64-bit arithmetic, or a heuristic
+ * value across the coordinates' bounding box of 2^31 or more: the kernels
+ * carry heuristic terms as signed 32-bit values), PPSP_E_OOM, PPSP_E_DEVICE.
  */
 int ppsp_graph_create(int device, uint32_t n, uint64_t m, const uint64_t *row_ptr,
                       const uint32_t *col, const uint32_t *w, const int32_t *coord_fx,
@@ -383,6 +384,9 @@ typedef struct {
     uint64_t pending;     /* requests with queries not yet admitted */
     uint64_t restarts;    /* frontier-buffer overflows: the queries on the device were restarted
                              with larger buffers (and count again in `admitted`) */
+    uint64_t renumbers;   /* the round loop was renumbered from round 0 before its round stamps
+                             reached the reserved values (about every 4.29e9 rounds); the queries
+                             then on the device were restarted (and count again in `admitted`) */
 } ppsp_server_counters;
 
 int ppsp_server_create(const ppsp_graph *graphs, uint32_t ngraphs, const ppsp_opts *opts, uint64_t state_budget,
@@ -450,6 +454,10 @@ int ppsp_last_stats(ppsp_graph g, ppsp_stats *stats);
  *                     from min_chunk up that covers it (default 16; 64 = always 64)
  *   "local_fill"      local chunks only in rounds whose frontier holds fewer entries than
  *                     this (default 0 = every round)
+ *   "server_round_base" the round number a server's round loop on this graph starts at
+ *                     (default 0; below 0xFFFFFF00). A server renumbers its rounds from 0
+ *                     before they reach 0xFFFFFF00, restarting the queries then running;
+ *                     a high base exercises that without billions of rounds
  * Returns PPSP_E_INVALID for an unknown name.
  */
 int ppsp_set_option(ppsp_graph g, const char *name, int64_t value);

@@ -72,7 +72,7 @@ class TuneResult(ctypes.Structure):
 
 class ServerCounters(ctypes.Structure):
     _fields_ = [(k, ctypes.c_uint64) for k in ("admitted", "completed", "chunks", "rounds", "running", "slots",
-                                               "pending", "restarts")]
+                                               "pending", "restarts", "renumbers")]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}

@@ -173,7 +173,8 @@ struct ppsp_graph_s {
     int64_t opt_profile = 0, opt_rounds_per_sync = 16, opt_grid_blocks = 0, opt_mem_budget_mb = 0,
             opt_default_delta = 0, opt_use_graph = 0, opt_timeout_ms = 600000, opt_theta_mode = 2, opt_queue_cap = 0,
             opt_ml_every = 4, opt_heavy_window = 64, opt_multi_group = 32, opt_rho = 4096, opt_local = 16, opt_local_plain = 0, opt_local_fill = 0,
-            opt_min_chunk = 16, opt_local_small = 4, opt_local_pct = 90, opt_defer_pct = 105;
+            opt_min_chunk = 16, opt_local_small = 4, opt_local_pct = 90, opt_defer_pct = 105,
+            opt_server_round_base = 0;
     uint64_t wmean = 1;             // mean arc weight (rounded up)
     uint64_t fingerprint = 0;       // hash of the CSR, keys the tuning cache
     struct Tuned {
@@ -445,24 +446,43 @@ int run_wave(ppsp_graph g, const Plan &P, bool want_path, WaveOut &out) {
         uint64_t launches = 0, timed = 0;
         const auto t_start = std::chrono::steady_clock::now();
         bool timed_out = false;
-        hipGraphExec_t gexec = nullptr;
-        hipGraph_t graph = nullptr;
+        // the captured round chunk of this wave, released on every way out
+        struct GraphHold {
+            hipGraphExec_t exec = nullptr;
+            hipGraph_t graph = nullptr;
+            ~GraphHold() {
+                if (exec) (void)hipGraphExecDestroy(exec);
+                if (graph) (void)hipGraphDestroy(graph);
+            }
+        } gh;
+        hipGraphExec_t &gexec = gh.exec;
+        hipGraph_t &graph = gh.graph;
         if (g->opt_use_graph && !prof) {
             // Capture K rounds (K even keeps the parity pattern) once per wave.
             const int Kg = K + (K & 1);
             HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-            for (int k = 0; k < Kg; k++) {
-                (void)launch_round(A, grid, st);
-                if (A.hcap) (void)launch_heavy(A, grid, st);
-                (void)launch_control(A, st);
+            hipError_t le = hipSuccess;
+            for (int k = 0; k < Kg && le == hipSuccess; k++) {
+                le = launch_round(A, grid, st);
+                if (le == hipSuccess && A.hcap) le = launch_heavy(A, grid, st);
+                if (le == hipSuccess) le = launch_control(A, st);
             }
-            HIPCHK(hipStreamEndCapture(st, &graph));
-            HIPCHK(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
+            const hipError_t ee = hipStreamEndCapture(st, &graph);
+            if (le != hipSuccess || ee != hipSuccess) {
+                // a launch that failed inside the capture: end it, report that launch's error
+                return device_error(le != hipSuccess ? "round launch during hipGraph capture" : "hipStreamEndCapture",
+                                    le != hipSuccess ? le : ee);
+            }
+            if (const hipError_t ie = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0); ie != hipSuccess) {
+                gexec = nullptr;
+                return device_error("hipGraphInstantiate", ie);
+            }
         }
         for (;;) {
             int kk, nt = 0;
             if (gexec) {
-                HIPCHK(hipGraphLaunch(gexec, st));
+                if (const hipError_t ge = hipGraphLaunch(gexec, st); ge != hipSuccess)
+                    return device_error("hipGraphLaunch", ge);
                 kk = K + (K & 1);
                 r += kk;
             } else {
@@ -495,7 +515,6 @@ int run_wave(ppsp_graph g, const Plan &P, bool want_path, WaveOut &out) {
             const double el = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
             if (g->opt_timeout_ms > 0 && el > (double)g->opt_timeout_ms) { timed_out = true; break; }
         }
-        if (gexec) { (void)hipGraphExecDestroy(gexec); (void)hipGraphDestroy(graph); }
         if (timed_out) return PPSP_E_TIMEOUT;
         const uint32_t errbits = g->h_poll[2 * NSEG];
         if (errbits & ERR_OVERFLOW) return PPSP_E_OVERFLOW;
@@ -1420,6 +1439,7 @@ struct SrvGraph {
     std::vector<uint32_t> h_ids;    // admitted search ids (kept until the chunk's sync)
     uint32_t running = 0;           // slots in state 1
     uint32_t draining = 0;          // slots in state 2
+    uint64_t round = 0;             // the device round counter, mirrored on the host
     std::deque<std::pair<uint64_t, uint32_t>> redo;   // (request, query) to admit first, after an overflow
 };
 
@@ -1436,7 +1456,7 @@ struct ppsp_server_s {
     std::thread worker;
     bool stop = false;
     int err = PPSP_OK;
-    uint64_t admitted = 0, completed = 0, chunks = 0, rounds = 0, restarts = 0;
+    uint64_t admitted = 0, completed = 0, chunks = 0, rounds = 0, restarts = 0, renumbers = 0;
     uint32_t rounds_per_chunk = 16;
 };
 
@@ -1515,6 +1535,13 @@ int srv_setup_graph(ppsp_server srv, SrvGraph &G, const ppsp_opts &o, uint64_t b
     HIPCHK(hipMemsetAsync(g->cpre.p, 0, 2 * (NSEG + 1) * 4, st));
     HIPCHK(hipMemsetAsync(g->tsum.p, 0, 48, st));
     HIPCHK(hipMemsetAsync(g->round.p, 0, 16, st));
+    if (g->opt_server_round_base > 0) {
+        // the round loop starts at this round (a test of the renumbering below)
+        const uint32_t rb[2] = {(uint32_t)g->opt_server_round_base, (uint32_t)g->opt_server_round_base};
+        HIPCHK(hipMemcpyAsync(g->round.p, rb, 8, hipMemcpyHostToDevice, st));
+        HIPCHK(hipStreamSynchronize(st));
+    }
+    G.round = (uint64_t)g->opt_server_round_base;
     HIPCHK(hipMemsetAsync(g->hcount.p, 0, 16, st));
     HIPCHK(hipMemsetAsync(g->err.p, 0, 16, st));
     HIPCHK(hipMemsetAsync(g->stats.p, 0, ST_N * 8, st));
@@ -1526,10 +1553,18 @@ int srv_setup_graph(ppsp_server srv, SrvGraph &G, const ppsp_opts &o, uint64_t b
     return PPSP_OK;
 }
 
-// Grows the buffer that overflowed, resets the graph's round loop to idle and
-// puts every running query back in front of the admission order. Called with
-// the lock held, after the stream is idle.
-int srv_restart(ppsp_server srv, SrvGraph &G, uint32_t errbits) {
+// A round's stamp (1 + its number, see ppsp_dev.h) must stay below the
+// reserved stamp values (0xFFFFFFFE marks a check-only entry, 0xFFFFFFFF a
+// cleared word), so a server renumbers its round loop from 0 before its
+// round counter reaches SRV_ROUND_LIMIT.
+constexpr uint64_t SRV_ROUND_LIMIT = 0xFFFFFF00ull;
+
+// Grows the buffer that overflowed (errbits), or with renumber resets the
+// round counter to 0; in both cases resets the graph's round loop to idle and
+// puts every running query back in front of the admission order (each
+// admitted query clears its own state slab, so no stamp of an earlier round
+// number survives). Called with the lock held, after the stream is idle.
+int srv_restart(ppsp_server srv, SrvGraph &G, uint32_t errbits, bool renumber = false) {
     ppsp_graph g = G.g;
     hipStream_t st = g->st;
     if (errbits & ERR_QUEUE) {
@@ -1558,10 +1593,14 @@ int srv_restart(ppsp_server srv, SrvGraph &G, uint32_t errbits) {
     HIPCHK(hipMemsetAsync(g->tsum.p, 0, 48, st));
     HIPCHK(hipMemsetAsync(g->hcount.p, 0, 16, st));
     HIPCHK(hipMemsetAsync(g->err.p, 0, 16, st));
+    if (renumber) {
+        HIPCHK(hipMemsetAsync(g->round.p, 0, 16, st));
+        G.round = 0;
+    }
     set_args(g, G.A, ns, G.C, 2);
     HIPCHK(launch_idle(G.A, st));
     HIPCHK(hipStreamSynchronize(st));
-    srv->restarts++;
+    if (renumber) srv->renumbers++; else srv->restarts++;
     return PPSP_OK;
 }
 
@@ -1653,6 +1692,7 @@ int srv_chunk(ppsp_server srv, bool &any_running) {
     for (auto &G : srv->gs) {
         if (G.running == 0 && G.draining == 0) continue;
         srv->rounds += srv->rounds_per_chunk;
+        G.round += srv->rounds_per_chunk;
         if (G.h_done[2 * G.C] & ERR_OVERFLOW) return PPSP_E_OVERFLOW;
         if (G.h_done[2 * G.C] & (ERR_QUEUE | ERR_HEAVY)) {
             // A queue or the heavy list overflowed in this chunk: frontier
@@ -1676,6 +1716,8 @@ int srv_chunk(ppsp_server srv, bool &any_running) {
                 srv->completed++;
             }
         }
+        // the next chunk would run rounds with stamps too close to the reserved ones
+        if (G.round + srv->rounds_per_chunk >= SRV_ROUND_LIMIT) CHK(srv_restart(srv, G, 0, true));
     }
     srv->cv_done.notify_all();
     return PPSP_OK;
@@ -1910,6 +1952,11 @@ int ppsp_graph_create(int device, uint32_t n, uint64_t m, const uint64_t *row_pt
         const __int128 sx = (__int128)x1 - x0, sy = (__int128)y1 - y0;
         const unsigned __int128 span = (unsigned __int128)(sx * sx) + (unsigned __int128)(sy * sy);
         if ((span * ((unsigned __int128)w_scale * w_scale)) >> 63) return fail(PPSP_E_RANGE);
+        // The kernels carry a vertex's heuristic term (h_t, or h_t - h_s) as a
+        // signed 32-bit value: every heuristic value is at most the one across
+        // the bounding box's diagonal, which must stay below 2^31.
+        if ((isqrt_floor((uint64_t)(span * ((unsigned __int128)w_scale * w_scale))) >> coord_frac_bits) >= (1ull << 31))
+            return fail(PPSP_E_RANGE);
         g->has_xy = true;
         g->fb = coord_frac_bits;
         g->w_scale = w_scale;
@@ -2263,6 +2310,10 @@ int ppsp_set_option(ppsp_graph g, const char *name, int64_t v) {
         if (v < 1 || v > 64 || (v & (v - 1))) return PPSP_E_INVALID;
         g->opt_multi_group = v;
     }
+    else if (k == "server_round_base") {
+        if (v < 0 || v >= (int64_t)SRV_ROUND_LIMIT) return PPSP_E_INVALID;
+        g->opt_server_round_base = v;
+    }
 
     else return PPSP_E_INVALID;
     return PPSP_OK;
@@ -2292,6 +2343,7 @@ int ppsp_get_option(ppsp_graph g, const char *name, int64_t *v) {
     else if (k == "local_chunks_small") *v = g->opt_local_small;
     else if (k == "local_time_pct") *v = g->opt_local_pct;
     else if (k == "defer_time_pct") *v = g->opt_defer_pct;
+    else if (k == "server_round_base") *v = g->opt_server_round_base;
 
     else return PPSP_E_INVALID;
     return PPSP_OK;
@@ -2401,6 +2453,7 @@ int ppsp_server_stats(ppsp_server srv, ppsp_server_counters *out) {
     for (auto &G : srv->gs) { out->running += G.running; out->slots += G.C; }
     out->pending = srv->pending.size();
     out->restarts = srv->restarts;
+    out->renumbers = srv->renumbers;
     return PPSP_OK;
 }
 

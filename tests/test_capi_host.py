@@ -108,6 +108,14 @@ def test_graph_create_rejects_bad_input_before_device():
     with pytest.raises(P.PPSPError) as e:
         P.graph_create(g.n, g.row_ptr, g.col, g.w, coords=big, w_scale=1000)
     assert e.value.code == P.E_RANGE
+    # exact in 64 bits, but the heuristic across the box, 2^16 * 2^23 * sqrt(2)
+    # / 2^8 = 2^31.5, would not fit the kernels' signed 32-bit heuristic terms
+    wide = np.zeros((g.n, 2), np.int32)
+    wide[-1] = (1 << 23, 1 << 23)          # diagonal 2^23 * sqrt(2) units, 8 fractional bits
+    with pytest.raises(P.PPSPError) as e:
+        P.graph_create(g.n, g.row_ptr, g.col, g.w, coords=wide, w_scale=1 << 16, frac_bits=8)
+    assert e.value.code == P.E_RANGE
+    assert P.heuristic_fx(0, 0, 1 << 23, 1 << 23, 1 << 16, 8) >= 1 << 31
 
 
 def test_no_cpu_fallback_in_binding():

@@ -191,3 +191,25 @@ def test_server_directed_graph(P):
         assert np.array_equal(got, e)
     S.close()
     D.close()
+
+
+def test_server_renumbers_rounds_before_stamp_limit(P):
+    """The round loop starts 40 rounds below the renumbering point (option
+    server_round_base): the server renumbers its rounds from 0 while
+    requests are on the device, restarts them, and every request still equals
+    the oracle."""
+    g = gen.lattice(160, 0.05, seed=31)
+    G = P.Graph.from_host(g)
+    G.set_option("rounds_per_sync", 16)
+    G.set_option("server_round_base", 0xFFFFFF00 - 40)
+    assert G.get_option("server_round_base") == 0xFFFFFF00 - 40
+    reqs = [gen.pairs_uniform(g.n, k, seed=700 + i) for i, k in enumerate([5, 12, 3, 20, 8, 1, 15])]
+    S = P.Server([G], algo="bidastar", state_budget_bytes=24 * g.n * 6)
+    ids = [S.submit(0, p) for p in reqs]
+    res = [S.wait(r, timeout_ms=120000) for r in ids]
+    st = S.stats()
+    S.close()
+    G.close()
+    assert st["renumbers"] >= 1, st
+    for p, (d, _) in zip(reqs, res):
+        assert np.array_equal(d, _oracle(g, p))
