@@ -232,6 +232,32 @@ int ppsp_batch_query(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp
                      void *hip_stream, uint64_t *dist, uint64_t *path_off, uint32_t *path_vtx,
                      uint64_t path_cap);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * ppsp_batch_query for Plain and Plain* batches without any allocation.
+ * Every workspace buffer of the call (search state, frontier queues, heavy
+ * list, control words) is carved from a fixed device array of
+ * PPSP_NOALLOC_SCRATCH_BYTES that each GPU holds from the first such call
+ * until the process ends; the graph's own workspace is left as it was.
+ * Batches whose state does not fit run in several waves of whole queries
+ * inside it. Work is ordered on hip_stream itself (NULL = the default
+ * stream), which is synchronised before returning. Calls on one GPU share
+ * the array: calls that overlap on one GPU race, and must not be issued
+ * concurrently (each call clears what it reads before use).
+ *   pairs, dist   as ppsp_batch_query (host, or device with PPSP_DEVICE_IO)
+ *   opts          batch PPSP_BATCH_PLAIN or PPSP_BATCH_PLAINSTAR, sched
+ *                 PPSP_SCHED_FIXED or PPSP_SCHED_AUTOTUNED; flags may hold
+ *                 PPSP_PULL and PPSP_DEVICE_IO (no paths, no memo)
+ * Errors: PPSP_E_INVALID (another strategy, schedule or flag), PPSP_E_OOM
+ * with ppsp_last_error() saying so when one query on the graph (two searches
+ * of 8 bytes per vertex each, plus its queues) does not fit the scratch, and
+ * the errors of ppsp_batch_query.
+ */
+#define PPSP_NOALLOC_SCRATCH_BYTES (128ull << 20)
+int ppsp_batch_query_noalloc(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp_opts *opts,
+                             void *hip_stream, uint64_t *dist);
+
 /* Result of ppsp_tune. */
 typedef struct {
     uint64_t delta;        /* chosen Delta (distance units) */
@@ -278,7 +304,8 @@ int ppsp_tune(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp_opts *
  *   0 log2(1+extracted)/16  1 log2(1+arcs scanned)/16  2 log2(1+next frontier)/16
  *   3 (log2(1+next) - log2(1+partner's next))/8   4 log2(1+(bound-minkey)/Delta)/16 (0 if bound infinite)
  *   5 bound infinite (1/0)  6 log2(1+(minkey-theta)/Delta)/8  7 log2(1+(theta-root key)/Delta)/16
- *   8 log2(1+heuristic s-t distance/Delta)/16  9 log2(1+round)/16  10 (previous bin-4)/4  11 log2(m/n)/4
+ *   8 log2(1+heuristic s-t distance/Delta)/16  9 log2(1+round)/16
+ *   10 progress (theta-root key)/(bound-root key) in [0,1] (0 if bound infinite)  11 log2(m/n)/4
  *
  * ppsp_mlp_forward  logits [n][8] of feature rows x [n][12] (device `device`).
  * ppsp_mlp_grad     mean cross-entropy loss of labels y (< 8) and its gradient
@@ -347,6 +374,47 @@ int ppsp_sched_trace(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp
                      uint64_t *pair_arcs);
 int ppsp_mlp_fit(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp_opts *opts, const float *init,
                  uint32_t epochs, uint64_t seed, uint32_t label_mode, float *params_out, ppsp_fit_report *rep);
+
+/*
+ * ppsp_sched_trace_ex: a traced Plain or Plain* batch (exact distances, like
+ * any other schedule) with the step schedule given per pair:
+ *   bins[k] (NULL: bin 4 = the base Delta) until the step for round
+ *   switch_round[k], bins_after[k] from that step on (both NULL: no switch;
+ *   the counterfactual replays behind the learned schedule's labels), or,
+ *   with network = 1, the bins the loaded network picks (bins ignored; the
+ *   rows then record its inputs and choices, for checking its inference).
+ *   distinct = 1 keeps equal pairs apart (each pair its own query).
+ * Outputs (caller-owned; NULL skips): cap feature rows feat [cap][12] with
+ * row_pair, row_round (the round after which the step was chosen), row_side
+ * (0: the pair's forward or only search, 1: its backward search), row_bin
+ * (the bin chosen); nrows = rows produced (may exceed cap); per pair the
+ * rounds its searches ran, the arcs they scanned, the entries they put in
+ * their next frontiers (carried entries included) and the distance.
+ * Errors: PPSP_E_INVALID (a bin >= 8, one of switch_round / bins_after
+ * without the other, network = 1 with no network loaded, another strategy),
+ * the errors of ppsp_batch_query.
+ */
+typedef struct {
+    const uint8_t *bins;
+    const uint8_t *bins_after;
+    const uint32_t *switch_round;
+    uint32_t network;
+    uint32_t distinct;
+    uint64_t cap;
+    float *feat;
+    uint32_t *row_pair;
+    uint32_t *row_round;
+    uint8_t *row_side;
+    uint8_t *row_bin;
+    uint64_t nrows;          /* out */
+    uint32_t *pair_rounds;
+    uint64_t *pair_arcs;
+    uint64_t *pair_entries;
+    uint64_t *dist;
+} ppsp_trace_spec;
+
+int ppsp_sched_trace_ex(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp_opts *opts,
+                        ppsp_trace_spec *spec);
 
 /*
  * Serving (continuous batching). A server owns one or more resident graphs

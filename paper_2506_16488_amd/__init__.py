@@ -91,6 +91,15 @@ class FitReport(ctypes.Structure):
         return d
 
 
+class TraceSpec(ctypes.Structure):
+    _fields_ = [("bins", ctypes.c_void_p), ("bins_after", ctypes.c_void_p), ("switch_round", ctypes.c_void_p),
+                ("network", ctypes.c_uint32), ("distinct", ctypes.c_uint32), ("cap", ctypes.c_uint64),
+                ("feat", ctypes.c_void_p), ("row_pair", ctypes.c_void_p), ("row_round", ctypes.c_void_p),
+                ("row_side", ctypes.c_void_p), ("row_bin", ctypes.c_void_p), ("nrows", ctypes.c_uint64),
+                ("pair_rounds", ctypes.c_void_p), ("pair_arcs", ctypes.c_void_p), ("pair_entries", ctypes.c_void_p),
+                ("dist", ctypes.c_void_p)]
+
+
 MLP_FEATURES, MLP_BINS, MLP_PARAMS = 12, 8, 5512
 
 EXPORTS = ["ppsp_graph_create", "ppsp_graph_destroy", "ppsp_query", "ppsp_batch_query", "ppsp_last_stats",
@@ -98,7 +107,7 @@ EXPORTS = ["ppsp_graph_create", "ppsp_graph_destroy", "ppsp_query", "ppsp_batch_
            "ppsp_last_error", "ppsp_tune", "ppsp_server_create", "ppsp_server_submit", "ppsp_server_poll",
            "ppsp_server_wait", "ppsp_server_stats", "ppsp_server_destroy", "ppsp_mlp_forward", "ppsp_mlp_grad",
            "ppsp_mlp_train", "ppsp_mlp_load", "ppsp_sched_trace", "ppsp_mlp_fit",
-           "ppsp_query_cover", "ppsp_sssp"]
+           "ppsp_query_cover", "ppsp_sssp", "ppsp_batch_query_noalloc", "ppsp_sched_trace_ex"]
 
 _lib_handle = None
 
@@ -129,6 +138,10 @@ def lib():
         L.ppsp_query.restype = ctypes.c_int
         L.ppsp_batch_query.argtypes = [P, P, u32, ctypes.POINTER(Opts), P, P, P, P, u64]
         L.ppsp_batch_query.restype = ctypes.c_int
+        L.ppsp_batch_query_noalloc.argtypes = [P, P, u32, ctypes.POINTER(Opts), P, P]
+        L.ppsp_batch_query_noalloc.restype = ctypes.c_int
+        L.ppsp_sched_trace_ex.argtypes = [P, P, u32, ctypes.POINTER(Opts), ctypes.POINTER(TraceSpec)]
+        L.ppsp_sched_trace_ex.restype = ctypes.c_int
         L.ppsp_last_stats.argtypes = [P, ctypes.POINTER(Stats)]
         L.ppsp_last_stats.restype = ctypes.c_int
         L.ppsp_set_option.argtypes = [P, ctypes.c_char_p, i64]
@@ -396,6 +409,30 @@ class Graph:
                "ppsp_batch_query")
         return dist
 
+    def batch_query_noalloc(self, pairs, algo="bids", batch="plainstar", delta=0, sched="fixed", pull=False):
+        """ppsp_batch_query_noalloc: the same distances, with every workspace
+        buffer carved from the library's fixed device scratch (no allocation)."""
+        pairs = np.ascontiguousarray(pairs, np.uint32).reshape(-1, 2)
+        k = pairs.shape[0]
+        dist = np.empty(k, np.uint64)
+        o = make_opts(algo, batch, sched, delta, pull=pull)
+        _check(lib().ppsp_batch_query_noalloc(self.h, _ptr(pairs), k, ctypes.byref(o), current_stream(), _ptr(dist)),
+               "ppsp_batch_query_noalloc")
+        return dist
+
+    def batch_query_noalloc_device(self, pairs, dist, algo="bids", batch="plainstar", delta=0):
+        """ppsp_batch_query_noalloc with PPSP_DEVICE_IO (torch tensors as in batch_query_device)."""
+        import torch
+        assert pairs.is_cuda and dist.is_cuda and pairs.dtype == torch.int32 and dist.dtype == torch.int64
+        k = pairs.shape[0]
+        assert pairs.shape == (k, 2) and dist.shape == (k,) and pairs.is_contiguous() and dist.is_contiguous()
+        o = make_opts(algo, batch, "fixed", delta)
+        o.flags |= DEVICE_IO
+        _check(lib().ppsp_batch_query_noalloc(self.h, ctypes.c_void_p(pairs.data_ptr()), k, ctypes.byref(o),
+                                              current_stream(), ctypes.c_void_p(dist.data_ptr())),
+               "ppsp_batch_query_noalloc")
+        return dist
+
     def sssp(self, s, delta=0, sched="fixed"):
         """Distances from s to every vertex (ppsp_sssp; PPSP_INF where unreachable)."""
         dist = np.empty(self.n, np.uint64)
@@ -429,6 +466,33 @@ class Graph:
                                       ctypes.byref(nrows), _ptr(pr), _ptr(pa)), "ppsp_sched_trace")
         kept = min(int(nrows.value), cap)
         return feat[:kept], rowp[:kept], int(nrows.value), pr, pa
+
+    def sched_trace_ex(self, pairs, algo="bids", batch="plainstar", delta=0, bins=None, bins_after=None,
+                       switch_round=None, network=False, distinct=False, cap=0):
+        """ppsp_sched_trace_ex; returns a dict with rows (feat, pair, round,
+        side, bin), nrows, and per pair rounds, arcs, entries and dist."""
+        pairs = np.ascontiguousarray(pairs, np.uint32).reshape(-1, 2)
+        k = pairs.shape[0]
+
+        def per_pair(x, dt):
+            return None if x is None else np.ascontiguousarray(np.broadcast_to(x, (k,)), dt)
+        b, ba, sw = per_pair(bins, np.uint8), per_pair(bins_after, np.uint8), per_pair(switch_round, np.uint32)
+        out = {"feat": np.empty((cap, MLP_FEATURES), np.float32), "pair": np.empty(cap, np.uint32),
+               "round": np.empty(cap, np.uint32), "side": np.empty(cap, np.uint8), "bin": np.empty(cap, np.uint8),
+               "pair_rounds": np.empty(k, np.uint32), "pair_arcs": np.empty(k, np.uint64),
+               "pair_entries": np.empty(k, np.uint64), "dist": np.empty(k, np.uint64)}
+        spec = TraceSpec(_ptr(b), _ptr(ba), _ptr(sw), 1 if network else 0, 1 if distinct else 0, int(cap),
+                         _ptr(out["feat"]) if cap else None, _ptr(out["pair"]) if cap else None,
+                         _ptr(out["round"]) if cap else None, _ptr(out["side"]) if cap else None,
+                         _ptr(out["bin"]) if cap else None, 0, _ptr(out["pair_rounds"]), _ptr(out["pair_arcs"]),
+                         _ptr(out["pair_entries"]), _ptr(out["dist"]))
+        _check(lib().ppsp_sched_trace_ex(self.h, _ptr(pairs), k, ctypes.byref(make_opts(algo, batch, delta=delta)),
+                                         ctypes.byref(spec)), "ppsp_sched_trace_ex")
+        kept = min(int(spec.nrows), cap)
+        for key in ("feat", "pair", "round", "side", "bin"):
+            out[key] = out[key][:kept]
+        out["nrows"] = int(spec.nrows)
+        return out
 
     def mlp_fit(self, pairs, init, algo="bids", batch="plainstar", epochs=20, seed=0, delta=0, labels="single"):
         """Labels ("single": each pair timed alone; "batch": batch-aware),

@@ -62,27 +62,69 @@ namespace {
 
 extern thread_local std::string g_last_error;
 
-// Device allocation owned by its holder (freed with it, movable, not copyable).
+// Device allocation owned by its holder (freed with it, movable, not
+// copyable), or a borrowed view into the no-allocation scratch (never freed).
 struct DevBuf {
     void *p = nullptr;
     size_t bytes = 0;
+    bool borrowed = false;
     DevBuf() = default;
     DevBuf(const DevBuf &) = delete;
     DevBuf &operator=(const DevBuf &) = delete;
-    DevBuf(DevBuf &&o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+    DevBuf(DevBuf &&o) noexcept : p(o.p), bytes(o.bytes), borrowed(o.borrowed) {
+        o.p = nullptr;
+        o.bytes = 0;
+        o.borrowed = false;
+    }
     DevBuf &operator=(DevBuf &&o) noexcept {
         std::swap(p, o.p);
         std::swap(bytes, o.bytes);
+        std::swap(borrowed, o.borrowed);
         return *this;
     }
-    ~DevBuf() { if (p) (void)hipFree(p); }
+    ~DevBuf() { if (p && !borrowed) (void)hipFree(p); }
     template <class T> T *as() const { return (T *)p; }
 };
+
+extern thread_local std::string g_last_error;
+
+// The no-allocation entry point (ppsp_batch_query_noalloc) serves every
+// workspace buffer of its call from one fixed device region: while t_arena is
+// set on the calling thread, ensure() carves 256-byte-aligned views from it
+// (bump allocation) and never calls hipMalloc.
+struct Arena {
+    char *base = nullptr;
+    uint64_t size = 0;
+    uint64_t off = 0;
+    uint64_t state_budget = 0;   // bytes of search state a wave may take
+};
+thread_local Arena *t_arena = nullptr;
+// run_wave asks its caller to retry with fewer queries per wave: a frontier
+// buffer overflowed and cannot grow inside the arena (internal, never returned)
+constexpr int E_ARENA_RETRY = -1000;
 
 int ensure(DevBuf &b, size_t bytes) {
     if (bytes == 0) bytes = 8;
     if (b.bytes >= bytes) return PPSP_OK;
-    if (b.p) { (void)hipFree(b.p); b.p = nullptr; b.bytes = 0; }
+    if (t_arena) {
+        const uint64_t o = (t_arena->off + 255) & ~255ull;
+        if (o + bytes > t_arena->size) {
+            // the caller retries with fewer queries per wave (or reports PPSP_E_OOM for one)
+            g_last_error = "no-allocation call: " + std::to_string(bytes) + " more bytes do not fit the " +
+                           std::to_string(t_arena->size) + "-byte scratch";
+            return E_ARENA_RETRY;
+        }
+        if (b.p && !b.borrowed) (void)hipFree(b.p);
+        b.p = t_arena->base + o;
+        b.bytes = bytes;
+        b.borrowed = true;
+        t_arena->off = o + bytes;
+        return PPSP_OK;
+    }
+    if (b.p && !b.borrowed) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+    b.borrowed = false;
     if (hipMalloc(&b.p, bytes) != hipSuccess) {
         (void)hipGetLastError();
         b.p = nullptr;
@@ -94,9 +136,10 @@ int ensure(DevBuf &b, size_t bytes) {
 }
 
 void release(DevBuf &b) {
-    if (b.p) (void)hipFree(b.p);
+    if (b.p && !b.borrowed) (void)hipFree(b.p);
     b.p = nullptr;
     b.bytes = 0;
+    b.borrowed = false;
 }
 
 thread_local std::string g_last_error;
@@ -127,20 +170,31 @@ struct Plan {
     std::vector<uint64_t> delta;    // per search, key units
     bool gather = false;            // read each query's distance off its root's search after the rounds
     std::vector<uint8_t> bin;       // per search: Delta-multiplier bin (learned / traced schedule)
+    std::vector<uint8_t> bin_after; // per search (traced switch, empty: none): bin from sw_round on
+    std::vector<uint32_t> sw_round; // per search: the round whose step first uses bin_after
     std::vector<uint32_t> qid;      // per search: index of its query among the call's distinct queries
+    std::vector<uint8_t> side;      // per search: its position among its query's searches (0 forward, 1 backward)
 };
 
 // Learned or traced step schedule of the current call.
 struct MlCtx {
-    int mode = 0;                        // 0 off, 1 trace with fixed bins, 2 learned
+    int mode = 0;                        // 0 off, 1 trace with fixed bins, 2 learned, 3 rho rule
     const std::vector<uint8_t> *qbin = nullptr;  // trace: bin per distinct query
+    const std::vector<uint8_t> *qbin_after = nullptr;   // trace with a switch: bin from qsw on
+    const std::vector<uint32_t> *qsw = nullptr;         // per distinct query: switch round
+    bool nodedup = false;                // every input pair is its own query (no merging of equal pairs)
     bool rows = false;                   // trace: record feature rows
+    bool collect = false;                // collect per-query rounds, arcs, entries (and rows)
     uint64_t cap = 0;                    // row capacity
     // outputs per distinct query / per row (trace)
     std::vector<uint32_t> q_rounds;
     std::vector<uint64_t> q_arcs;
+    std::vector<uint64_t> q_ent;
     std::vector<float> feat;
     std::vector<uint32_t> row_q;
+    std::vector<uint32_t> row_r;
+    std::vector<uint8_t> row_b;
+    std::vector<uint8_t> row_side;
     uint64_t rows_total = 0;             // rows produced (may exceed cap)
 };
 
@@ -189,7 +243,7 @@ struct ppsp_graph_s {
     bool memo_call = false;         // the current call memoises the heuristic (PPSP_MEMO_H)
     bool pull_call = false;         // the current call pulls before pushing (PPSP_PULL)
     // learned schedule
-    DevBuf sc, bin, done_round, tot_arcs, trace, trace_s, trace_n, mlpw;
+    DevBuf sc, bin, bin_after, sw_round, done_round, tot_arcs, tot_ent, trace, trace_s, trace_r, trace_b, trace_n, mlpw;
     bool mlp_loaded = false;
     MlCtx *ml = nullptr;            // set for the duration of a learned or traced call
 };
@@ -199,6 +253,20 @@ namespace {
 int set_device(ppsp_graph g) {
     HIPCHK(hipSetDevice(g->device));
     return PPSP_OK;
+}
+
+// The workspace buffers of a batch (everything run_wave sizes per wave);
+// a no-allocation call swaps them out for views into the scratch.
+std::vector<DevBuf *> wave_buffers(ppsp_graph g) {
+    return {&g->S, &g->q0, &g->q1, &g->sd, &g->partners, &g->pairdesc, &g->ctl, &g->delta, &g->done, &g->exh,
+            &g->alive, &g->minkey, &g->mu, &g->qcount, &g->cpre, &g->round, &g->err, &g->stats, &g->wstats,
+            &g->heavy, &g->hcount, &g->hlim, &g->tsum};
+}
+
+// Inside a no-allocation call: drop every view and start carving again.
+void arena_reset(ppsp_graph g) {
+    for (DevBuf *b : wave_buffers(g)) release(*b);
+    t_arena->off = 0;
 }
 
 // Workgroups of the round kernel: the "grid_blocks" option, else 20 per
@@ -222,6 +290,7 @@ uint64_t graph_default_delta(ppsp_graph g) {
 uint64_t state_bytes_per_search(ppsp_graph g) { return (uint64_t)g->n * 8; }
 
 uint64_t state_budget(ppsp_graph g) {
+    if (t_arena) return t_arena->state_budget;
     if (g->opt_mem_budget_mb > 0) return (uint64_t)g->opt_mem_budget_mb << 20;
     size_t fr = 0, tot = 0;
     if (hipMemGetInfo(&fr, &tot) != hipSuccess) { (void)hipGetLastError(); return 1ull << 30; }
@@ -299,9 +368,12 @@ void set_args(ppsp_graph g, RoundArgs &A, uint32_t nsearch, uint32_t npair, uint
         A.bin = g->bin.as<uint8_t>();
         A.done_round = g->done_round.as<uint32_t>();
         A.tot_arcs = g->tot_arcs.as<unsigned long long>();
+        A.tot_ent = g->tot_ent.as<unsigned long long>();
         if (g->ml->rows && g->ml->cap) {
             A.trace = g->trace.as<float>();
             A.trace_s = g->trace_s.as<uint32_t>();
+            A.trace_r = g->trace_r.as<uint32_t>();
+            A.trace_b = g->trace_b.as<uint8_t>();
             A.trace_cap = g->ml->cap;
         }
         A.trace_n = g->trace_n.as<unsigned long long>();
@@ -330,9 +402,10 @@ struct WaveOut {
     uint64_t launches = 0, timed = 0;   // round-kernel launches, and those timed
     // learned / traced schedule: per search
     std::vector<uint32_t> done_round;
-    std::vector<unsigned long long> tot_arcs;
+    std::vector<unsigned long long> tot_arcs, tot_ent;
     std::vector<float> feat;        // trace rows
-    std::vector<uint32_t> row_s;
+    std::vector<uint32_t> row_s, row_r;
+    std::vector<uint8_t> row_b;
     uint64_t rows_total = 0;
 };
 
@@ -348,8 +421,10 @@ int run_wave(ppsp_graph g, const Plan &P, bool want_path, WaveOut &out) {
     CHK(ensure(g->hcount, 16));
     if (g->maxdeg > HEAVY_DEG) {
         // a round can extract each hub once per search; a quarter of that at once is ample
-        const uint64_t want = std::min<uint64_t>(1u << 26, std::max<uint64_t>(1u << 20, (uint64_t)ns * g->hchunks / 4));
-        if (g->hcap < want) g->hcap = (uint32_t)want;
+        // (inside the no-allocation scratch: a quarter of the hub chunks, at least 4,096)
+        const uint64_t want = t_arena ? std::max<uint64_t>(4096, (uint64_t)ns * g->hchunks / 4)
+                                      : std::min<uint64_t>(1u << 26, std::max<uint64_t>(1u << 20, (uint64_t)ns * g->hchunks / 4));
+        if (g->hcap < want || t_arena) g->hcap = (uint32_t)std::min<uint64_t>(want, 1u << 28);
         CHK(ensure(g->heavy, (uint64_t)g->hcap * 32));
     }
     CHK(ensure(g->sd, ns * sizeof(SearchDesc)));
@@ -376,6 +451,17 @@ int run_wave(ppsp_graph g, const Plan &P, bool want_path, WaveOut &out) {
     }
     const uint32_t grid = round_grid(g);
     CHK(ensure(g->wstats, (uint64_t)grid * ST_N * 8));
+    if (t_arena) {
+        // the two frontier queues take what the scratch has left (up to the usual size)
+        const uint64_t used = ((t_arena->off + 255) & ~255ull) + 512;
+        const uint64_t left = t_arena->size > used ? t_arena->size - used : 0;
+        const uint64_t fit = (left / 32) / NSEG * NSEG;
+        if (fit < 4096) {
+            g_last_error = "no-allocation call: no room left in the scratch for the frontier queues";
+            return E_ARENA_RETRY;
+        }
+        g->qcap = std::min<uint64_t>(g->qcap, fit);
+    }
     for (;;) {
         CHK(ensure(g->q0, g->qcap * 16));
         CHK(ensure(g->q1, g->qcap * 16));
@@ -399,15 +485,25 @@ int run_wave(ppsp_graph g, const Plan &P, bool want_path, WaveOut &out) {
             CHK(ensure(g->bin, ns));
             CHK(ensure(g->done_round, (uint64_t)ns * 4));
             CHK(ensure(g->tot_arcs, (uint64_t)ns * 8));
+            CHK(ensure(g->tot_ent, (uint64_t)ns * 8));
             CHK(ensure(g->trace_n, 8));
             if (g->ml->rows && g->ml->cap) {
                 CHK(ensure(g->trace, g->ml->cap * MLP_F * 4));
                 CHK(ensure(g->trace_s, g->ml->cap * 4));
+                CHK(ensure(g->trace_r, g->ml->cap * 4));
+                CHK(ensure(g->trace_b, g->ml->cap));
+            }
+            if (!P.sw_round.empty()) {
+                CHK(ensure(g->bin_after, ns));
+                CHK(ensure(g->sw_round, (uint64_t)ns * 4));
+                HIPCHK(hipMemcpyAsync(g->bin_after.p, P.bin_after.data(), ns, hipMemcpyHostToDevice, st));
+                HIPCHK(hipMemcpyAsync(g->sw_round.p, P.sw_round.data(), (uint64_t)ns * 4, hipMemcpyHostToDevice, st));
             }
             HIPCHK(hipMemsetAsync(g->sc.p, 0, 2ull * ns * 16, st));
             HIPCHK(hipMemcpyAsync(g->bin.p, P.bin.data(), ns, hipMemcpyHostToDevice, st));
             HIPCHK(hipMemsetAsync(g->done_round.p, 0, (uint64_t)ns * 4, st));
             HIPCHK(hipMemsetAsync(g->tot_arcs.p, 0, (uint64_t)ns * 8, st));
+            HIPCHK(hipMemsetAsync(g->tot_ent.p, 0, (uint64_t)ns * 8, st));
             HIPCHK(hipMemsetAsync(g->trace_n.p, 0, 8, st));
         }
         if (g->memo_call) {
@@ -425,6 +521,10 @@ int run_wave(ppsp_graph g, const Plan &P, bool want_path, WaveOut &out) {
         }
         RoundArgs A;
         set_args(g, A, ns, npair, P.G);
+        if (A.sc && A.ml_mode == 1 && !P.sw_round.empty()) {
+            A.bin_after = g->bin_after.as<uint8_t>();
+            A.sw_round = g->sw_round.as<uint32_t>();
+        }
         // The time limits serve waves with local chunks: without heuristic
         // searches (and without "local_chunks_plain") they only cost (Multi-BiDS
         // on the hub lattice: 534 -> 508 queries/s), so they are off.
@@ -518,6 +618,11 @@ int run_wave(ppsp_graph g, const Plan &P, bool want_path, WaveOut &out) {
         if (timed_out) return PPSP_E_TIMEOUT;
         const uint32_t errbits = g->h_poll[2 * NSEG];
         if (errbits & ERR_OVERFLOW) return PPSP_E_OVERFLOW;
+        if ((errbits & (ERR_QUEUE | ERR_HEAVY)) && t_arena) {
+            // the buffers cannot grow inside the scratch: fewer queries per wave
+            g->last.retries++;
+            return E_ARENA_RETRY;
+        }
         if (errbits & (ERR_QUEUE | ERR_HEAVY)) {
             g->last.retries++;
             // Grow the frontier queues (or the heavy list) and rerun the wave from scratch.
@@ -542,11 +647,13 @@ int run_wave(ppsp_graph g, const Plan &P, bool want_path, WaveOut &out) {
         HIPCHK(hipStreamSynchronize(st));
         for (uint64_t b = 0; b < grid; b++)
             for (int k = 1; k < ST_N; k++) out.stats[k] += ws[b * ST_N + k];
-        if (g->ml && g->ml->mode == 1) {
+        if (g->ml && g->ml->collect) {
             out.done_round.resize(ns);
             out.tot_arcs.resize(ns);
+            out.tot_ent.resize(ns);
             HIPCHK(hipMemcpyAsync(out.done_round.data(), g->done_round.p, (uint64_t)ns * 4, hipMemcpyDeviceToHost, st));
             HIPCHK(hipMemcpyAsync(out.tot_arcs.data(), g->tot_arcs.p, (uint64_t)ns * 8, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipMemcpyAsync(out.tot_ent.data(), g->tot_ent.p, (uint64_t)ns * 8, hipMemcpyDeviceToHost, st));
             unsigned long long nrow = 0;
             HIPCHK(hipMemcpyAsync(&nrow, g->trace_n.p, 8, hipMemcpyDeviceToHost, st));
             HIPCHK(hipStreamSynchronize(st));
@@ -555,9 +662,13 @@ int run_wave(ppsp_graph g, const Plan &P, bool want_path, WaveOut &out) {
                 const uint64_t keep = std::min<uint64_t>(nrow, g->ml->cap);
                 out.feat.resize(keep * MLP_F);
                 out.row_s.resize(keep);
+                out.row_r.resize(keep);
+                out.row_b.resize(keep);
                 if (keep) {
                     HIPCHK(hipMemcpyAsync(out.feat.data(), g->trace.p, keep * MLP_F * 4, hipMemcpyDeviceToHost, st));
                     HIPCHK(hipMemcpyAsync(out.row_s.data(), g->trace_s.p, keep * 4, hipMemcpyDeviceToHost, st));
+                    HIPCHK(hipMemcpyAsync(out.row_r.data(), g->trace_r.p, keep * 4, hipMemcpyDeviceToHost, st));
+                    HIPCHK(hipMemcpyAsync(out.row_b.data(), g->trace_b.p, keep, hipMemcpyDeviceToHost, st));
                     HIPCHK(hipStreamSynchronize(st));
                 }
             }
@@ -698,6 +809,7 @@ int run_independent(ppsp_graph g, const std::vector<Query> &qs, const ppsp_opts 
                    : std::max<uint64_t>(1, search_limit(g) / (per + (g->memo_call ? 1 : 0)));
     for (size_t q0 = 0; q0 < qs.size(); q0 += lim) {
         const size_t q1 = std::min<size_t>(qs.size(), q0 + lim);
+        if (t_arena) arena_reset(g);
         Plan P;
         P.G = is_bidir(o->algo) ? 2 : 1;
         std::vector<uint32_t> ans_of_pair;
@@ -705,27 +817,49 @@ int run_independent(ppsp_graph g, const std::vector<Query> &qs, const ppsp_opts 
             const size_t a = P.sd.size();
             plan_single(g, P, qs[q].s, qs[q].t, o->algo, delta);
             ans_of_pair.push_back((uint32_t)q);
-            const uint8_t b = (g->ml && g->ml->mode == 1) ? (*g->ml->qbin)[q] : (uint8_t)(MLP_K / 2);
+            const bool traced = g->ml && g->ml->mode == 1;
+            const uint8_t b = traced ? (*g->ml->qbin)[q] : (uint8_t)(MLP_K / 2);
             for (size_t i = a; i < P.sd.size(); i++) {
                 P.bin.push_back(b);
                 P.qid.push_back((uint32_t)q);
+                P.side.push_back((uint8_t)(i - a));
+                if (traced && g->ml->qsw) {
+                    P.bin_after.push_back((*g->ml->qbin_after)[q]);
+                    P.sw_round.push_back((*g->ml->qsw)[q]);
+                }
             }
         }
         g->last.searches += P.sd.size();
         WaveOut w;
-        CHK(run_wave(g, P, want_path, w));
+        const int rc = run_wave(g, P, want_path, w);
+        if (rc == E_ARENA_RETRY) {
+            // inside the no-allocation scratch: the same queries again in smaller waves
+            if (q1 - q0 == 1) {
+                g_last_error = "no-allocation call: one query's frontier does not fit the scratch";
+                return PPSP_E_OOM;
+            }
+            g->last.searches -= P.sd.size();
+            lim = std::max<uint64_t>(1, (q1 - q0) / 2);
+            q0 -= lim;          // the loop adds lim back: the same first query
+            continue;
+        }
+        CHK(rc);
         accumulate(g, w);
         collect(w, ans_of_pair, ans, want_path);
-        if (g->ml && g->ml->mode == 1) {
+        if (g->ml && g->ml->collect) {
             MlCtx &c = *g->ml;
             for (size_t i = 0; i < P.sd.size(); i++) {
                 const uint32_t q = P.qid[i];
                 c.q_rounds[q] = std::max(c.q_rounds[q], w.done_round[i]);
                 c.q_arcs[q] += w.tot_arcs[i];
+                c.q_ent[q] += w.tot_ent[i];
             }
             c.rows_total += w.rows_total;
             for (size_t r = 0; r < w.row_s.size() && c.row_q.size() < c.cap; r++) {
                 c.row_q.push_back(P.qid[w.row_s[r]]);
+                c.row_r.push_back(w.row_r[r]);
+                c.row_b.push_back(w.row_b[r]);
+                c.row_side.push_back(P.side[w.row_s[r]]);
                 c.feat.insert(c.feat.end(), w.feat.begin() + r * MLP_F, w.feat.begin() + (r + 1) * MLP_F);
             }
         }
@@ -1084,12 +1218,15 @@ int batch_impl(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp_opts 
     }
     CHK(set_device(g));
     g->last = ppsp_stats{};
-    // order the library stream after the caller's stream
-    hipEvent_t ev;
-    HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
-    HIPCHK(hipEventRecord(ev, (hipStream_t)hip_stream));
-    HIPCHK(hipStreamWaitEvent(g->st, ev, 0));
-    (void)hipEventDestroy(ev);
+    // order the library stream after the caller's stream (a no-allocation
+    // call runs on the caller's stream itself)
+    if (!t_arena) {
+        hipEvent_t ev;
+        HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        HIPCHK(hipEventRecord(ev, (hipStream_t)hip_stream));
+        HIPCHK(hipStreamWaitEvent(g->st, ev, 0));
+        (void)hipEventDestroy(ev);
+    }
     uint64_t delta = o->delta ? o->delta : graph_default_delta(g);
     // PPSP_SCHED_AUTOTUNED: the threshold rule, Delta and launch shape that
     // ppsp_tune chose for this algorithm and batch strategy.
@@ -1141,6 +1278,11 @@ int batch_impl(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp_opts 
             uint32_t s = pairs[2 * i], t = pairs[2 * i + 1];
             if (s == t) { self[i] = 1; continue; }
             if (g->symmetric && s > t && o->algo != PPSP_SSSP) { std::swap(s, t); flip[i] = 1; }
+            if (g->ml && g->ml->nodedup) {            // every pair its own query (traced variants)
+                qidx[i] = (uint32_t)qs.size();
+                qs.push_back({s, t});
+                continue;
+            }
             const uint64_t key = ((uint64_t)s << 32) | t;
             auto it = seen.find(key);
             if (it == seen.end()) {
@@ -1217,56 +1359,116 @@ int batch_impl(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp_opts 
 
 // ---- learned schedule: tracing, training, fitting ------------------------------
 
-// Runs the batch with a fixed Delta-multiplier bin per pair (ml mode 1) and
-// collects, per pair, the rounds and arcs of its searches and, optionally,
-// the feature rows of its step decisions.
-int trace_impl(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp_opts *o, const uint8_t *bins,
-               bool rows, uint64_t cap, MlCtx &c, std::vector<uint32_t> &row_pair, std::vector<uint32_t> &pair_rounds,
-               std::vector<uint64_t> &pair_arcs) {
+// What a traced batch records (host arrays sized by the caller).
+struct TraceReq {
+    const uint8_t *bins = nullptr;         // per pair: bin (NULL: 4)
+    const uint8_t *bins_after = nullptr;   // per pair: bin from switch_round on
+    const uint32_t *switch_round = nullptr;
+    bool network = false;                  // the loaded network picks the bins
+    bool distinct = false;                 // every pair its own query
+    bool rows = false;
+    uint64_t cap = 0;
+};
+struct TraceOut {
+    std::vector<uint32_t> row_pair, row_round;
+    std::vector<uint8_t> row_bin, row_side;
+    std::vector<float> feat;
+    uint64_t rows_total = 0;
+    std::vector<uint32_t> pair_rounds;
+    std::vector<uint64_t> pair_arcs, pair_ent, dist;
+};
+
+// Runs a Plain / Plain* batch with the multiplier bin of every pair fixed
+// (ml mode 1; optionally switching to another bin from a given round on), or
+// chosen by the loaded network (ml mode 2), and collects per pair the rounds
+// its searches ran, the arcs they scanned and the entries they put in their
+// next frontiers, and optionally the feature rows of their step decisions.
+int trace_run(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp_opts *o, const TraceReq &rq, TraceOut &out) {
     if (o->batch != PPSP_BATCH_PLAIN && o->batch != PPSP_BATCH_PLAINSTAR) return PPSP_E_INVALID;
+    if (rq.network && !g->mlp_loaded) return PPSP_E_INVALID;
     for (uint32_t i = 0; i < k; i++)
-        if (bins && bins[i] >= MLP_K) return PPSP_E_INVALID;
+        if ((rq.bins && rq.bins[i] >= MLP_K) || (rq.switch_round && (!rq.bins_after || rq.bins_after[i] >= MLP_K)))
+            return PPSP_E_INVALID;
     // distinct queries in first-occurrence order, as batch_impl forms them
     std::unordered_map<uint64_t, uint32_t> seen;
     std::vector<uint32_t> first, qof(k, UINT32_MAX);
-    std::vector<uint8_t> qbin;
+    std::vector<uint8_t> qbin, qbin_after;
+    std::vector<uint32_t> qsw;
     for (uint32_t i = 0; i < k; i++) {
         uint32_t s = pairs[2 * i], t = pairs[2 * i + 1];
         if (s >= g->n || t >= g->n) return PPSP_E_RANGE;
         if (s == t) continue;
         if (g->symmetric && s > t && o->algo != PPSP_SSSP) std::swap(s, t);
-        auto it = seen.find(((uint64_t)s << 32) | t);
+        const uint64_t key = rq.distinct ? (uint64_t)i : (((uint64_t)s << 32) | t);
+        auto it = seen.find(key);
         if (it == seen.end()) {
-            it = seen.emplace(((uint64_t)s << 32) | t, (uint32_t)first.size()).first;
+            it = seen.emplace(key, (uint32_t)first.size()).first;
             first.push_back(i);
-            qbin.push_back(bins ? bins[i] : (uint8_t)(MLP_K / 2));
+            qbin.push_back(rq.bins ? rq.bins[i] : (uint8_t)(MLP_K / 2));
+            if (rq.switch_round) {
+                qbin_after.push_back(rq.bins_after[i]);
+                qsw.push_back(rq.switch_round[i]);
+            }
         }
         qof[i] = it->second;
     }
-    c = MlCtx{};
-    c.mode = 1;
+    MlCtx c;
+    c.mode = rq.network ? 2 : 1;
     c.qbin = &qbin;
-    c.rows = rows;
-    c.cap = rows ? cap : 0;
+    if (rq.switch_round) {
+        c.qbin_after = &qbin_after;
+        c.qsw = &qsw;
+    }
+    c.nodedup = rq.distinct;
+    c.collect = true;
+    c.rows = rq.rows;
+    c.cap = rq.rows ? rq.cap : 0;
     c.q_rounds.assign(first.size(), 0);
     c.q_arcs.assign(first.size(), 0);
+    c.q_ent.assign(first.size(), 0);
     g->ml = &c;
-    std::vector<uint64_t> dist(k);
+    out.dist.assign(k, 0);
     ppsp_opts oo = *o;
     oo.sched = PPSP_SCHED_FIXED;
-    oo.flags &= ~PPSP_WANT_PATH;
-    const int rc = batch_impl(g, pairs, k, &oo, nullptr, dist.data(), nullptr, nullptr, 0, nullptr);
+    oo.flags &= ~(uint32_t)(PPSP_WANT_PATH | PPSP_DEVICE_IO);
+    const int rc = batch_impl(g, pairs, k, &oo, nullptr, out.dist.data(), nullptr, nullptr, 0, nullptr);
     g->ml = nullptr;
     CHK(rc);
-    row_pair.resize(c.row_q.size());
-    for (size_t r = 0; r < c.row_q.size(); r++) row_pair[r] = first[c.row_q[r]];
-    pair_rounds.assign(k, 0);
-    pair_arcs.assign(k, 0);
+    out.row_pair.resize(c.row_q.size());
+    for (size_t r = 0; r < c.row_q.size(); r++) out.row_pair[r] = first[c.row_q[r]];
+    out.row_round = std::move(c.row_r);
+    out.row_bin = std::move(c.row_b);
+    out.row_side = std::move(c.row_side);
+    out.feat = std::move(c.feat);
+    out.rows_total = c.rows_total;
+    out.pair_rounds.assign(k, 0);
+    out.pair_arcs.assign(k, 0);
+    out.pair_ent.assign(k, 0);
     for (uint32_t i = 0; i < k; i++)
         if (qof[i] != UINT32_MAX) {
-            pair_rounds[i] = c.q_rounds[qof[i]];
-            pair_arcs[i] = c.q_arcs[qof[i]];
+            out.pair_rounds[i] = c.q_rounds[qof[i]];
+            out.pair_arcs[i] = c.q_arcs[qof[i]];
+            out.pair_ent[i] = c.q_ent[qof[i]];
         }
+    return PPSP_OK;
+}
+
+// The earlier interface: fixed bins (NULL: 4), rows, per-pair rounds and arcs.
+int trace_impl(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp_opts *o, const uint8_t *bins,
+               bool rows, uint64_t cap, MlCtx &c, std::vector<uint32_t> &row_pair, std::vector<uint32_t> &pair_rounds,
+               std::vector<uint64_t> &pair_arcs) {
+    TraceReq rq;
+    rq.bins = bins;
+    rq.rows = rows;
+    rq.cap = cap;
+    TraceOut out;
+    CHK(trace_run(g, pairs, k, o, rq, out));
+    c = MlCtx{};
+    c.feat = std::move(out.feat);
+    c.rows_total = out.rows_total;
+    row_pair = std::move(out.row_pair);
+    pair_rounds = std::move(out.pair_rounds);
+    pair_arcs = std::move(out.pair_arcs);
     return PPSP_OK;
 }
 
@@ -2082,6 +2284,122 @@ int ppsp_batch_query(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp
     return batch_impl(g, pairs, k, opts, hip_stream, dist, path_off, path_vtx, path_cap, nullptr);
 }
 
+}  // extern "C"
+
+// ---- the no-allocation entry point ---------------------------------------------
+//
+// ppsp_batch_query_noalloc runs Plain / Plain* batches with every workspace
+// buffer (search state, frontier queues, heavy list, control words) carved
+// from `scratch`, a fixed device array that each GPU holds from the first
+// call until the process ends. Its device address comes from
+// hipGetSymbolAddress, once per device with that device current; host code
+// never uses the array's name as an address. Calls on one GPU share it, so
+// calls that overlap on one GPU race; every call clears what it reads
+// before use (state words, queue counters, control words).
+
+namespace {
+
+constexpr uint64_t NOALLOC_SCRATCH_BYTES = 128ull << 20;
+static __device__ __align__(256) uint8_t scratch[NOALLOC_SCRATCH_BYTES];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[NOALLOC_MAX_DEVICES] = {nullptr};
+
+// The device address of `scratch` on `device` (the current device).
+int scratch_ptr(int device, char **out) {
+    if (device < 0 || device >= NOALLOC_MAX_DEVICES) return PPSP_E_INVALID;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return device_error("hipGetSymbolAddress(scratch)", e);
+        g_scratch_ptr[device] = p;
+    }
+    *out = (char *)g_scratch_ptr[device];
+    return PPSP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ppsp_batch_query_noalloc(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp_opts *opts,
+                             void *hip_stream, uint64_t *dist) {
+    if (!g || !opts || (k && (!pairs || !dist))) return PPSP_E_INVALID;
+    if (opts->batch != PPSP_BATCH_PLAIN && opts->batch != PPSP_BATCH_PLAINSTAR) return PPSP_E_INVALID;
+    if (opts->sched != PPSP_SCHED_FIXED && opts->sched != PPSP_SCHED_AUTOTUNED) return PPSP_E_INVALID;
+    if (opts->flags & (PPSP_WANT_PATH | PPSP_MEMO_H)) return PPSP_E_INVALID;
+    if (g->served) return PPSP_E_BUSY;
+    CHK(set_device(g));
+    // the smallest wave: one query's two searches, the queues and the per-workgroup counters
+    const uint64_t need = 2 * (uint64_t)g->n * 8 + 2 * 4096ull * 16 + (uint64_t)round_grid(g) * ST_N * 8 +
+                          (g->maxdeg > HEAVY_DEG ? 4096ull * 32 : 0) + (1ull << 20);
+    if (need > NOALLOC_SCRATCH_BYTES) {
+        g_last_error = "no-allocation call: one query on this graph needs " + std::to_string(need) +
+                       " bytes, the scratch holds " + std::to_string(NOALLOC_SCRATCH_BYTES);
+        return PPSP_E_OOM;
+    }
+    char *base = nullptr;
+    CHK(scratch_ptr(g->device, &base));
+    // the graph's own workspace is set aside (and kept) for the duration of the call
+    struct Swap {
+        ppsp_graph g;
+        std::vector<DevBuf> saved;
+        hipStream_t st;
+        uint64_t qcap;
+        uint32_t hcap;
+        int64_t profile, use_graph;
+        Arena arena;
+        Swap(ppsp_graph g_, hipStream_t cs) : g(g_), st(g_->st), qcap(g_->qcap), hcap(g_->hcap),
+                                             profile(g_->opt_profile), use_graph(g_->opt_use_graph) {
+            for (DevBuf *b : wave_buffers(g)) saved.push_back(std::move(*b));
+            g->st = cs;               // work is ordered on the caller's stream
+            g->opt_profile = 0;       // no events
+            g->opt_use_graph = 0;     // no captured graphs
+            if (g->opt_queue_cap == 0) g->qcap = 0;
+            g->hcap = 0;
+        }
+        ~Swap() {
+            t_arena = nullptr;
+            auto bufs = wave_buffers(g);
+            for (size_t i = 0; i < bufs.size(); i++) {
+                release(*bufs[i]);
+                *bufs[i] = std::move(saved[i]);
+            }
+            g->st = st;
+            g->qcap = qcap;
+            g->hcap = hcap;
+            g->opt_profile = profile;
+            g->opt_use_graph = use_graph;
+        }
+    } swap(g, (hipStream_t)hip_stream);
+    swap.arena.base = base;
+    swap.arena.size = NOALLOC_SCRATCH_BYTES;
+    // search state takes at most five eighths of the scratch; queues and the rest share what is left
+    swap.arena.state_budget = NOALLOC_SCRATCH_BYTES / 8 * 5;
+    t_arena = &swap.arena;
+    ppsp_opts o = *opts;
+    if (o.flags & PPSP_DEVICE_IO) {
+        // device-resident pairs and distances, staged through the host on the caller's stream
+        o.flags &= ~PPSP_DEVICE_IO;
+        hipStream_t cs = (hipStream_t)hip_stream;
+        std::vector<uint32_t> hp(2ull * k);
+        std::vector<uint64_t> hd(k);
+        if (k) {
+            HIPCHK(hipMemcpyAsync(hp.data(), pairs, 8ull * k, hipMemcpyDeviceToHost, cs));
+            HIPCHK(hipStreamSynchronize(cs));
+        }
+        CHK(batch_impl(g, hp.data(), k, &o, hip_stream, hd.data(), nullptr, nullptr, 0, nullptr));
+        if (k) {
+            HIPCHK(hipMemcpyAsync(dist, hd.data(), 8ull * k, hipMemcpyHostToDevice, cs));
+            HIPCHK(hipStreamSynchronize(cs));
+        }
+        return PPSP_OK;
+    }
+    return batch_impl(g, pairs, k, &o, hip_stream, dist, nullptr, nullptr, 0, nullptr);
+}
+
 int ppsp_query(ppsp_graph g, uint32_t s, uint32_t t, const ppsp_opts *opts, void *hip_stream, uint64_t *dist,
                uint32_t *path, uint32_t path_cap, uint32_t *path_len) {
     if (!g || !opts || !dist) return PPSP_E_INVALID;
@@ -2514,6 +2832,39 @@ int ppsp_sched_trace(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp
     if (nrows) *nrows = c.rows_total;
     if (pair_rounds) memcpy(pair_rounds, pr.data(), (uint64_t)k * 4);
     if (pair_arcs) memcpy(pair_arcs, pa.data(), (uint64_t)k * 8);
+    return PPSP_OK;
+}
+
+int ppsp_sched_trace_ex(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp_opts *opts,
+                        ppsp_trace_spec *spec) {
+    if (!g || !opts || !spec || (k && !pairs)) return PPSP_E_INVALID;
+    if (spec->cap && (!spec->feat || !spec->row_pair)) return PPSP_E_INVALID;
+    if ((spec->switch_round != nullptr) != (spec->bins_after != nullptr)) return PPSP_E_INVALID;
+    if (g->served) return PPSP_E_BUSY;
+    CHK(check_opts(g, opts));
+    TraceReq rq;
+    rq.bins = spec->bins;
+    rq.bins_after = spec->bins_after;
+    rq.switch_round = spec->switch_round;
+    rq.network = spec->network != 0;
+    rq.distinct = spec->distinct != 0;
+    rq.rows = spec->cap > 0;
+    rq.cap = spec->cap;
+    TraceOut out;
+    CHK(trace_run(g, pairs, k, opts, rq, out));
+    const uint64_t kept = out.row_pair.size();
+    if (spec->cap) {
+        memcpy(spec->feat, out.feat.data(), kept * MLP_F * 4);
+        memcpy(spec->row_pair, out.row_pair.data(), kept * 4);
+        if (spec->row_round) memcpy(spec->row_round, out.row_round.data(), kept * 4);
+        if (spec->row_side) memcpy(spec->row_side, out.row_side.data(), kept);
+        if (spec->row_bin) memcpy(spec->row_bin, out.row_bin.data(), kept);
+    }
+    spec->nrows = out.rows_total;
+    if (spec->pair_rounds) memcpy(spec->pair_rounds, out.pair_rounds.data(), (uint64_t)k * 4);
+    if (spec->pair_arcs) memcpy(spec->pair_arcs, out.pair_arcs.data(), (uint64_t)k * 8);
+    if (spec->pair_entries) memcpy(spec->pair_entries, out.pair_ent.data(), (uint64_t)k * 8);
+    if (spec->dist) memcpy(spec->dist, out.dist.data(), (uint64_t)k * 8);
     return PPSP_OK;
 }
 

@@ -938,9 +938,11 @@ __device__ __forceinline__ float lg2p(double x) { return log2f((float)(1.0 + x))
 //   7  log2(1 + (threshold - root key) / Delta) / 16   (progress)
 //   8  log2(1 + heuristic distance of the query / Delta) / 16; 0 without coordinates
 //   9  log2(1 + round) / 16
-//  10  (previous bin - 4) / 4
+//  10  progress towards the bound: (threshold - root key) / (bound - root key),
+//      clipped to [0, 1]; 0 while the bound is infinite
 //  11  log2(m / n) / 4
-// Delta is the search's base Delta in key units.
+// Delta is the search's base Delta in key units. No feature holds the bin the
+// search ran with, so the choice is a function of the search's state alone.
 __device__ __forceinline__ void ml_features(const RoundArgs &A, uint32_t i, const SearchDesc &sd, uint32_t r,
                                             uint32_t par, unsigned long long c0, unsigned long long nxt, double scale,
                                             uint64_t th0, uint64_t mk, uint64_t nb, uint64_t db, uint32_t bin,
@@ -974,8 +976,10 @@ __device__ __forceinline__ void ml_features(const RoundArgs &A, uint32_t i, cons
     }
     f[8] = lg2p(est / d) / 16.f;
     f[9] = lg2p((double)r) / 16.f;
-    f[10] = ((float)bin - 4.f) / 4.f;
+    f[10] = 0.f;
+    if (nb != INF64 && nb > key0) f[10] = (float)fmin(1.0, (double)(th0 > key0 ? th0 - key0 : 0) / (double)(nb - key0));
     f[11] = A.deg_feat;
+    (void)bin;
 }
 
 // Step control of the learned or traced schedule: one wave per search (the
@@ -1015,7 +1019,10 @@ __global__ __launch_bounds__(WAVE) void k_control_ml(RoundArgs A) {
             sn[1] = 0;
         }
         if (st == 0) continue;
-        if (w) A.tot_arcs[i] += (unsigned long long)(scale * (double)(c0 >> 32) + 0.5);
+        if (w) {
+            A.tot_arcs[i] += (unsigned long long)(scale * (double)(c0 >> 32) + 0.5);
+            A.tot_ent[i] += (unsigned long long)(scale * (double)nxt + 0.5);
+        }
         if (st == 1) {
             if (w) A.done_round[i] = r + 1;
             continue;
@@ -1037,6 +1044,8 @@ __global__ __launch_bounds__(WAVE) void k_control_ml(RoundArgs A) {
             const double nx = scale * (double)nxt;
             if (nx > 2.0 * A.rho && bin > 0) bin--;
             else if (nx < 0.5 * A.rho && bin < (uint32_t)MLP_K - 1) bin++;
+        } else if (A.ml_mode == 1 && A.sw_round && r + 1 >= A.sw_round[i]) {
+            bin = A.bin_after[i];           // a traced switch: this step and all later ones
         }
         if (w) {
             if (A.trace) {
@@ -1044,6 +1053,8 @@ __global__ __launch_bounds__(WAVE) void k_control_ml(RoundArgs A) {
                 if (row < A.trace_cap) {
                     for (int k = 0; k < MLP_F; k++) A.trace[row * MLP_F + k] = f[k];
                     A.trace_s[row] = i;
+                    if (A.trace_r) A.trace_r[row] = r;
+                    if (A.trace_b) A.trace_b[row] = (uint8_t)bin;
                 }
             }
             A.bin[i] = (uint8_t)bin;

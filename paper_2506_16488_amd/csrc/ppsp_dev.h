@@ -167,13 +167,20 @@ struct RoundArgs {
                                //   (arcs of extracted vertices << 32) + extracted vertices; entries for the next frontier
     uint32_t ml_mode;          // 1: bins fixed per search (tracing), 2: the network picks them,
                                // 3: a rule steers each search's next frontier towards rho entries
+    // Tracing (ml_mode 1) with a switch: search i runs bin[i] until its step
+    // for round sw_round[i], and bin_after[i] from then on (null: no switch).
+    const uint8_t *bin_after;
+    const uint32_t *sw_round;
     uint32_t rho;
     const uint16_t *mlp;       // network parameters in bf16 (layout in mlp_dev.h)
     uint8_t *bin;              // [nsearch] multiplier bin of the search's next round
     uint32_t *done_round;      // [nsearch] rounds the search ran
     unsigned long long *tot_arcs;  // [nsearch] arcs it scanned
+    unsigned long long *tot_ent;   // [nsearch] entries it put in its next frontiers (carried ones included)
     float *trace;              // [trace_cap][12] feature rows, or null
     uint32_t *trace_s;         // [trace_cap] search of each row
+    uint32_t *trace_r;         // [trace_cap] the round after which the row's step was chosen
+    uint8_t *trace_b;          // [trace_cap] the bin chosen (the network's, or the fixed one)
     unsigned long long *trace_n;
     uint64_t trace_cap;
     float deg_feat;            // log2(m / n) / 4

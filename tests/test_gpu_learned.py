@@ -203,3 +203,68 @@ def test_constant_network_is_exact(P):
         for algo in ("bidastar", "bids"):
             assert np.array_equal(G.batch_query(test, algo=algo, sched="learned"), exp), (b, algo)
     G.close()
+
+
+def _bf16(p):
+    """fp32 -> bf16 (round to nearest even) -> fp32, written out from the
+    format's definition: keep the top 16 bits after adding half an ulp."""
+    u = np.ascontiguousarray(p, np.float32).view(np.uint32).astype(np.uint64)
+    r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return (r & 0xFFFFFFFF).astype(np.uint32).view(np.float32)
+
+
+def test_in_round_inference_matches_reference(P):
+    """The network inside the control kernel (bf16 weights, fp32 arithmetic)
+    picks, on every traced row, the argmax of the FP64 reference evaluated on
+    the bf16-rounded parameters and the row's recorded features (rows whose
+    two best logits are within 1e-3 of each other are skipped: fp32 and fp64
+    may order them differently). The run is exact."""
+    g = gen.lattice(128, 0.05, seed=90)
+    pairs = gen.pairs_uniform(g.n, 40, seed=91)
+    exp = oracle.pp_batch(g.n, g.row_ptr, g.col, g.w, pairs)
+    G = P.Graph.from_host(g)
+    G.set_option("ml_every", 1)                 # the network decides after every round
+    seen = set()
+    for seed, noise in ((92, 0.3), (93, 1.0), (94, 2.0)):
+        p = _params(seed, noise)
+        G.mlp_load(p)
+        tr = G.sched_trace_ex(pairs, algo="bidastar", network=True, cap=400000)
+        assert np.array_equal(tr["dist"], exp)
+        n = len(tr["bin"])
+        assert tr["nrows"] == n > 100
+        z = mlp.forward(_bf16(p).astype(np.float64), tr["feat"].astype(np.float64))
+        top = np.sort(z, axis=1)
+        clear = top[:, -1] - top[:, -2] > 1e-3 * (1 + np.abs(top[:, -1]))
+        assert clear.mean() > 0.9, clear.mean()
+        assert np.array_equal(tr["bin"][clear].astype(np.int64), np.argmax(z, axis=1)[clear])
+        seen |= set(np.unique(tr["bin"]).tolist())
+        assert np.all(tr["side"] <= 1) and np.all(tr["pair"] < len(pairs))
+    assert len(seen) >= 2, seen                 # more than one output compared
+    G.close()
+
+
+def test_switched_schedule_rows_and_exactness(P):
+    """Traced switches (the counterfactual replays of the labels): a pair runs
+    bin 2 until the step for its switch round and bin 6 from then on; every
+    row records the bin its step used, the distances are exact, and with
+    distinct = 1 equal pairs with different schedules are traced apart."""
+    g = gen.lattice(128, 0.05, seed=95)
+    pairs = gen.pairs_uniform(g.n, 30, seed=96)
+    exp = oracle.pp_batch(g.n, g.row_ptr, g.col, g.w, pairs)
+    G = P.Graph.from_host(g)
+    sw = np.array([1 + 3 * (i % 5) for i in range(30)], np.uint32)
+    tr = G.sched_trace_ex(pairs, algo="bidastar", bins=2, bins_after=6, switch_round=sw, cap=300000)
+    assert np.array_equal(tr["dist"], exp)
+    want = np.where(tr["round"] + 1 >= sw[tr["pair"]], 6, 2)
+    assert np.array_equal(tr["bin"], want)
+    assert np.all(tr["pair_rounds"] > 0) and np.all(tr["pair_arcs"] > 0) and np.all(tr["pair_entries"] > 0)
+    # one pair three times: bins 0, 4 and 7 from round 1 on, kept apart
+    rep = np.repeat(pairs[:1], 3, axis=0)
+    tr = G.sched_trace_ex(rep, algo="bids", bins=4, bins_after=np.array([0, 4, 7], np.uint8),
+                          switch_round=1, distinct=True)
+    assert np.all(tr["dist"] == exp[0])
+    # a smaller step needs more rounds and scans fewer arcs (a stale entry
+    # checked every other round can add one round to a search)
+    assert tr["pair_rounds"][0] > tr["pair_rounds"][1] and tr["pair_rounds"][2] <= tr["pair_rounds"][1] + 1
+    assert tr["pair_arcs"][0] <= tr["pair_arcs"][2]
+    G.close()
