@@ -1,19 +1,32 @@
 #!/usr/bin/env python3
 """Throughput benchmark of the exact point-to-point shortest-path path on one MI355X.
 
-Workload (one step): the road-like jittered 2048 x 2048 lattice (4,194,304
-vertices, ~17.2M arcs, weights ceil(1000 * Euclidean length), fixed-point
-coordinates) with its 1,000 seeded uniform s-t pairs, answered as one batch
-(Plain*: every query with its own forward and backward search in the same
-launches) with bidirectional A*. The graph is created with PPSP_REORDER (the
-device copy in Morton order of the coordinates; ids at the interface are the
-caller's). Inputs are resident on the GPU before timing.
+Default workload (one step = one batch): the power-law graph R-MAT scale 24
+(16,777,216 vertices, edge factor 16, (a, b, c, d) = (0.57, 0.19, 0.19,
+0.05), symmetrised, deduplicated, weights uniform in [1, 65535]) with its
+256 seeded s-t pairs from the largest connected component, answered as one
+BiDS Plain* batch (every query with its own forward and backward search in
+the same launches). Three threshold schedules run on the same graph and
+pairs in the same run:
+  - fixed Delta*-stepping: the i-th threshold is i * Delta (Section 2), with
+    Delta chosen by the doubling sweep of the experiments (Section 6.1) on 32
+    held-out sample pairs;
+  - autotuned: ppsp_tune on the same sample (threshold rule, Delta, hub
+    window, launch shape); this is also the best fixed Delta under the
+    threshold rule the learned schedule uses;
+  - learned: the step network trained by ppsp_mlp_fit on counterfactual
+    replays of the sample pairs (held out from the 256), with the tuned
+    setting as its base; `value` is its queries/s over the timed steps.
+Inputs are resident on the GPU (graph in HBM, pairs handed over at the
+interface) before timing; every schedule gives the same distances, checked
+against each other and, on a sample, against the CPU oracle.
 
 Printed: one JSON line with queries/s (whole job), GTEPS over the arcs the
-searches actually relaxed, the roofline of the dominant kernel (the round
-kernel: every 4th launch of the timed steps carries HIP events, on the library stream), single-query
-p50/p99 latency, and the CPU oracle (binary-heap Dijkstra on the host cores)
-timed on a bounded sample of the same pairs.
+searches relaxed, the rooflines of the round kernel and of the hub-list
+kernel (every 4th round of the timed steps carries HIP events in both
+launches, on the library stream) with the dominant one as `roofline`, and
+the CPU oracle (binary-heap Dijkstra on the host cores) on a bounded sample.
+`--workload` selects the other measured workloads (one JSON line each).
 """
 import argparse
 import hashlib
@@ -27,14 +40,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_round_traffic.json")
-# the round kernel and the engine whose defaults shape its launches
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+# the kernels and the engine whose defaults shape their launches
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2506_16488_amd", "csrc", f) for f in ("kernels.hip", "ppsp_dev.h", "engine.hip")]
 
 
 def kernel_source_hash():
-    """Hash of the round kernel's sources with comments and blank lines
-    removed (a comment edit does not invalidate the counters)."""
+    """Hash of the kernels' sources with comments and blank lines removed
+    (a comment edit does not invalidate the counters)."""
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
         src = open(f).read()
@@ -44,16 +57,17 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per round-kernel launch from the committed rocprofv3 counter
-    summary, or None when the kernel source changed since it was taken."""
+def measured_traffic(workload, kernel):
+    """HBM bytes per launch of `kernel` on `workload` from the committed
+    rocprofv3 counter summary, or None when the kernels changed since."""
     try:
         t = json.load(open(TRAFFIC_FILE))
     except (OSError, ValueError):
         return None
-    if t.get("kernel_source_hash") != kernel_source_hash():
+    e = t.get(workload, {}).get(kernel)
+    if not e or e.get("kernel_source_hash") != kernel_source_hash():
         return None
-    return int(t["traffic_bytes_per_launch"])
+    return int(e["traffic_bytes_per_launch"])
 
 
 def copy_kernel():
@@ -69,31 +83,43 @@ def copy_kernel():
     print("copied 3 x 1 GiB", flush=True)
 
 
-# The round kernel's duration: every PROFILE_EVERY-th launch of the timed steps
-# carries HIP events (a uniform sample; timing every launch costs about 2%).
+# Kernel durations: every PROFILE_EVERY-th round of the timed steps carries
+# HIP events in its round-kernel and hub-list-kernel launches (a uniform
+# sample; timing every launch costs about 2%).
 PROFILE_EVERY = 4
 BYTES_PER_SCANNED_VERTEX = 24  # row_ptr 8 + own state 8 + frontier entry read/write 8
 BYTES_PER_SCANNED_ARC = 24     # arc (neighbour, weight) 8 + neighbour state read-modify-write 16
-# Scattered accesses of the round kernel: per scanned vertex its own state,
-# its row_ptr pair and the first line of its arcs; per scanned arc the head's
-# state pair; per successful relaxation one 64-bit atomic minimum.
+BYTES_PER_HEAVY_CHUNK = 64     # a hub-list record, written by the round kernel and read by the hub-list kernel
+# Scattered accesses: per scanned vertex its own state, its row_ptr pair and
+# the first line of its arcs; per relaxed arc the head's state pair; per
+# successful relaxation one 64-bit atomic minimum.
 LOADS_PER_SCANNED_VERTEX = 3
-RANDBENCH_WORDS = 1 << 33      # 64 GiB table, about the size of the workload's search state
+RANDBENCH_WORDS = 1 << 33      # 64 GiB table, the size of the workloads' search state
 RANDBENCH_OPS = 1 << 28
 
 
-def random_access_roofline(P, agg, launches, avg_launch_us):
-    """Second roofline for the round kernel: its scattered loads and atomics
-    per launch priced at the device's measured rates for such accesses
-    (the probe library's scattered-access kernel, taken now on this GPU). frac = that floor / the launch
-    time; atomics are counted from successful relaxations, a lower bound."""
+def cpu_threads():
+    """Host threads the oracle runs on: every CPU this process may use."""
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def random_access_rates():
+    """The device's measured rates of scattered 16-byte loads and 64-bit
+    atomics over a 64 GiB table (the probe library's kernel, run now)."""
     from paper_2506_16488_amd import probe
     load_ms = probe.randbench(RANDBENCH_WORDS, RANDBENCH_OPS, 0)
     atom_ms = probe.randbench(RANDBENCH_WORDS, RANDBENCH_OPS, 1)
-    load_rate = RANDBENCH_OPS / (load_ms * 1e-3)
-    atom_rate = RANDBENCH_OPS / (atom_ms * 1e-3)
-    loads = (LOADS_PER_SCANNED_VERTEX * agg["scanned_vertices"] + agg["scanned_arcs"]) / launches
-    atomics = agg["relax_success"] / launches
+    return RANDBENCH_OPS / (load_ms * 1e-3), RANDBENCH_OPS / (atom_ms * 1e-3)
+
+
+def random_access_roofline(rates, loads, atomics, avg_launch_us):
+    """Second roofline of a kernel: its scattered loads and atomics per launch
+    priced at the device's measured rates; frac = that floor / the launch
+    time (atomics counted from successful relaxations, a lower bound)."""
+    load_rate, atom_rate = rates
     floor_us = 1e6 * (loads / load_rate + atomics / atom_rate)
     return {
         "bound": "scattered 16-byte loads + 64-bit atomics",
@@ -103,170 +129,31 @@ def random_access_roofline(P, agg, launches, avg_launch_us):
         "atomic_rate_gops": round(atom_rate / 1e9, 2),
         "table_gib": RANDBENCH_WORDS * 8 >> 30,
         "floor_us": round(floor_us, 2),
-        "avg_launch_us": avg_launch_us,
+        "avg_launch_us": round(avg_launch_us, 3),
         "frac": round(floor_us / avg_launch_us, 4) if avg_launch_us > 0 else None,
     }
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--algo", default="bidastar")
-    ap.add_argument("--batch", default="plainstar")
-    ap.add_argument("--delta", type=int, default=0)
-    ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=64)
-    ap.add_argument("--latency-sample", type=int, default=40)
-    ap.add_argument("--copy-kernel", action="store_true", help="run the 1 GiB copy used to calibrate counters")
-    ap.add_argument("--workload", default="lattice2048", choices=["lattice2048", "lattice4096hub", "rmat24", "serve", "ranks"],
-                    help="lattice2048: the headline line; the others are the further measured workloads")
-    args = ap.parse_args()
-    if args.copy_kernel:
-        copy_kernel()
-        return
-    if args.gpus != 1:
-        print("bench.py: one GPU only (queries shard across GPUs with no exchange, so a multi-GPU run "
-              "is N independent copies of this one); run with --gpus 1", file=sys.stderr)
-        sys.exit(2)
-    if args.workload != "lattice2048":
-        OTHER_WORKLOADS[args.workload](args)
-        return
-
-    import numpy as np
-    import torch
-    import gen
-    import paper_2506_16488_amd as P
-
-    torch.cuda.set_device(0)
-    t0 = time.time()
-    g = gen.workload_graph("lattice2048")
-    pairs = gen.workload_pairs("lattice2048", g)
-    G = P.Graph.from_host(g, device=0, reorder=True)
-    G.set_option("timeout_ms", 300000)
-    print("# graph n=%d m=%d built+uploaded in %.1fs" % (g.n, g.m, time.time() - t0), file=sys.stderr, flush=True)
-    delta = args.delta
-    # pairs and results resident on the GPU (PPSP_DEVICE_IO), used on torch's current stream
-    pairs_dev = torch.from_numpy(pairs.astype(np.int32)).cuda()
-    dist_dev = torch.empty(pairs.shape[0], dtype=torch.int64, device="cuda")
-    torch.cuda.synchronize()
-
-    def step():
-        G.batch_query_device(pairs_dev, dist_dev, algo=args.algo, batch=args.batch, delta=delta)
-
-    for w in range(args.warmup):
-        step()
-        print("# warmup %d done" % w, file=sys.stderr, flush=True)
-
-    # timed region: K full steps with round-kernel timing on the library stream
-    G.set_option("profile", PROFILE_EVERY)
-    agg = {"scanned_vertices": 0, "scanned_arcs": 0, "relax_kernel_ms": 0.0, "relax_launches": 0, "relax_timed": 0,
-           "rounds": 0,
-           "relax_success": 0, "entries": 0}
-    step_ms = []
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    for k in range(args.steps):
-        a = time.perf_counter()
-        step()
-        step_ms.append(1000.0 * (time.perf_counter() - a))
-        st = G.stats()
-        for key in agg:
-            agg[key] += st[key]
-        print("# step %d: %.1f ms, rounds %d" % (k, step_ms[-1], st["rounds"]), file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t_start
-    G.set_option("profile", 0)
-    dist0 = dist_dev.cpu().numpy().view(np.uint64)
-
-    K = args.steps
-    q = pairs.shape[0]
-    ms_per_step = 1000.0 * elapsed / K
-    qps = q * K / elapsed
-    gteps = agg["scanned_arcs"] / elapsed / 1e9
-    alg_bytes = BYTES_PER_SCANNED_VERTEX * agg["scanned_vertices"] + BYTES_PER_SCANNED_ARC * agg["scanned_arcs"]
-    launches = max(1, agg["relax_launches"])
-    avg_launch_s = agg["relax_kernel_ms"] / 1000.0 / max(1, agg["relax_timed"])
-    achieved = alg_bytes / launches / avg_launch_s / 1e9 if avg_launch_s > 0 else 0.0
-
-    # single-query latency (each query alone through ppsp_query)
-    lat = []
-    for i in range(min(args.latency_sample, q)):
-        s, t = int(pairs[i, 0]), int(pairs[i, 1])
-        a = time.perf_counter()
-        dd = G.query(s, t, algo=args.algo, delta=delta)
-        lat.append(1000.0 * (time.perf_counter() - a))
-        assert dd == int(dist0[i]), "single query disagrees with the batch"
-    lat = np.array(lat) if lat else None
-
-    out = {
-        "metric": "exact s-t queries/sec",
-        "value": round(qps, 2),
-        "unit": "queries/s",
-        "n_gpus": 1,
-        "steps": K,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 3),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "u32",
-        "data": "synthetic",
-        "config": {
-            "workload": "road-like jittered lattice 2048x2048 (4,194,304 vertices, %d arcs, w=ceil(1000*len)), "
-                        "1,000 uniform s-t pairs per step, %s, %s batch" % (g.m, args.algo, args.batch),
-            "queries_per_step": int(q),
-            "delta": int(G.get_option("default_delta") if delta == 0 else delta),
-        },
-        "ms_per_step_median": round(float(np.median(step_ms)), 3),
-        "gteps": round(gteps, 4),
-        "sssp_equivalent_gteps": round(g.m * qps / 1e9, 3),
-        "scanned_arcs_per_query": int(agg["scanned_arcs"] / (K * q)),
-        "rounds_per_step": int(agg["rounds"] / K),
-        "single_query_p50_ms": None if lat is None else round(float(np.percentile(lat, 50)), 3),
-        "single_query_p99_ms": None if lat is None else round(float(np.percentile(lat, 99)), 3),
-        "roofline": {
-            "bound": "hbm",
-            "kernel": "k_round",
-            "achieved": round(achieved, 2),
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 5),
-            "traffic": measured_traffic(),
-            "traffic_gbs": None if measured_traffic() is None else round(measured_traffic() / avg_launch_s / 1e9, 1),
-            "avg_launch_us": round(1e6 * avg_launch_s, 3),
-            "alg_bytes_per_launch": int(alg_bytes / launches),
-            "launches": int(launches),
-            "timed_launches": int(agg["relax_timed"]),
-        },
+def hbm_roofline(kernel, alg_bytes_per_launch, avg_launch_s, launches, timed, traffic):
+    achieved = alg_bytes_per_launch / avg_launch_s / 1e9 if avg_launch_s > 0 else 0.0
+    return {
+        "bound": "hbm",
+        "kernel": kernel,
+        "achieved": round(achieved, 2),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 5),
+        "traffic": traffic,
+        "traffic_gbs": None if traffic is None or avg_launch_s <= 0 else round(traffic / avg_launch_s / 1e9, 1),
+        "avg_launch_us": round(1e6 * avg_launch_s, 3),
+        "alg_bytes_per_launch": int(alg_bytes_per_launch),
+        "launches": int(launches),
+        "timed_launches": int(timed),
     }
 
-    if not args.no_cpu:
-        import oracle
-        threads = min(16, os.cpu_count() or 1)
-        sample = pairs[: args.cpu_sample]
-        a = time.perf_counter()
-        exp = oracle.pp_batch(g.n, g.row_ptr, g.col, g.w, sample, nthreads=threads)
-        cpu_s = time.perf_counter() - a
-        assert np.array_equal(exp, dist0[: args.cpu_sample]), "GPU and oracle disagree on the CPU sample"
-        a = time.perf_counter()
-        one = oracle.pp_batch(g.n, g.row_ptr, g.col, g.w, pairs[:4], nthreads=1)
-        one_ms = 1000.0 * (time.perf_counter() - a) / 4
-        assert np.array_equal(one, dist0[:4])
-        out["cpu_baseline"] = {
-            "value": round(sample.shape[0] / cpu_s, 3),
-            "unit": "queries/s",
-            "cores": threads,
-            "kind": "oracle",
-            "sample": "first %d of the 1,000 pairs, one binary-heap Dijkstra per pair (stops at t), "
-                      "%d host threads, %.1f s wall" % (sample.shape[0], threads, cpu_s),
-            "single_thread_ms_per_query": round(one_ms, 2),
-            "host_cpu": _cpu_model(),
-        }
-    G.close()
-    out["random_access"] = random_access_roofline(P, agg, launches, out["roofline"]["avg_launch_us"])
-    print(json.dumps(out), flush=True)
+
+def _log(msg):
+    print("# " + msg, file=sys.stderr, flush=True)
 
 
 def _cpu_model():
@@ -277,6 +164,380 @@ def _cpu_model():
     except OSError:
         pass
     return None
+
+
+def _cpu_baseline(g, sample, label, threads=None):
+    """The oracle as it stands, one binary-heap Dijkstra per pair, timed on
+    the host threads."""
+    import oracle
+    threads = threads or cpu_threads()
+    a = time.perf_counter()
+    exp = oracle.pp_batch(g.n, g.row_ptr, g.col, g.w, sample, nthreads=threads)
+    cpu_s = time.perf_counter() - a
+    return exp, {"value": round(sample.shape[0] / cpu_s, 3), "unit": "queries/s", "cores": threads, "kind": "oracle",
+                 "sample": "%d pairs of %s, one binary-heap Dijkstra per pair (stops at t), %d host threads, %.1f s"
+                           % (sample.shape[0], label, threads, cpu_s), "host_cpu": _cpu_model()}
+
+
+def _line(args, workload, value, ms, dtype="u32", metric="exact s-t queries/sec", **extra):
+    out = {"metric": metric, "value": round(value, 2), "unit": "queries/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": dtype, "data": "synthetic",
+           "config": {"workload": workload}}
+    out.update(extra)
+    print(json.dumps(out), flush=True)
+
+
+def _agg_stats(G, agg, keys):
+    st = G.stats()
+    for k in keys:
+        agg[k] = agg.get(k, 0) + st[k]
+    return st
+
+
+STAT_KEYS = ("rounds", "entries", "scanned_vertices", "scanned_arcs", "relax_success", "carried", "relax_kernel_ms",
+             "relax_launches", "relax_timed", "heavy_kernel_ms", "heavy_arcs", "heavy_chunks", "heavy_success")
+
+
+def kernel_rooflines(agg, workload, rates=None):
+    """Rooflines of the round kernel and the hub-list kernel from the timed
+    steps' counters and sampled launch durations; the dominant one (more
+    measured time per launch x launches) first."""
+    launches = max(1, agg["relax_launches"])
+    timed = max(1, agg["relax_timed"])
+    k_round_s = agg["relax_kernel_ms"] / 1000.0 / timed
+    k_heavy_s = agg["heavy_kernel_ms"] / 1000.0 / timed
+    light_arcs = agg["scanned_arcs"] - agg["heavy_arcs"]
+    rb = (BYTES_PER_SCANNED_VERTEX * agg["scanned_vertices"] + BYTES_PER_SCANNED_ARC * light_arcs
+          + BYTES_PER_HEAVY_CHUNK / 2 * agg["heavy_chunks"]) / launches
+    hb = (BYTES_PER_SCANNED_ARC * agg["heavy_arcs"] + BYTES_PER_HEAVY_CHUNK / 2 * agg["heavy_chunks"]) / launches
+    out = {"k_round": hbm_roofline("k_round", rb, k_round_s, launches, agg["relax_timed"],
+                                   measured_traffic(workload, "k_round"))}
+    if agg["heavy_kernel_ms"] > 0:
+        out["k_heavy"] = hbm_roofline("k_heavy", hb, k_heavy_s, launches, agg["relax_timed"],
+                                      measured_traffic(workload, "k_heavy"))
+    if rates is not None:
+        heavy_succ = agg["heavy_success"]
+        out["k_round"]["random_access"] = random_access_roofline(
+            rates, (LOADS_PER_SCANNED_VERTEX * agg["scanned_vertices"] + light_arcs) / launches,
+            (agg["relax_success"] - heavy_succ) / launches, 1e6 * k_round_s)
+        if "k_heavy" in out:
+            out["k_heavy"]["random_access"] = random_access_roofline(
+                rates, agg["heavy_arcs"] / launches, heavy_succ / launches, 1e6 * k_heavy_s)
+    dom = "k_heavy" if "k_heavy" in out and k_heavy_s > k_round_s else "k_round"
+    return dom, out
+
+
+# ---- the headline: R-MAT scale 24, three schedules -----------------------------
+
+def workload_rmat24(args):
+    import numpy as np
+    import torch
+    import gen
+    import paper_2506_16488_amd as P
+
+    torch.cuda.set_device(0)
+    t0 = time.time()
+    g = gen.workload_graph("rmat24")
+    lcc = gen.lcc(g)
+    pairs = gen.workload_pairs("rmat24", g, cand=lcc)          # the 256 pairs of every step
+    sample = gen.pairs_uniform(lcc, 32, seed=1104)             # held-out tuning and training pairs
+    assert not (set(map(tuple, sample.tolist())) & set(map(tuple, pairs.tolist())))
+    G = P.Graph.from_host(g, device=0, reorder=True)
+    G.set_option("timeout_ms", 900000)
+    _log("graph n=%d m=%d (largest component %d) built+uploaded in %.1fs" % (g.n, g.m, lcc.size, time.time() - t0))
+    K = pairs.shape[0]
+    sched = {}
+
+    def time_batch(p, reps, **kw):
+        """Wall ms of each of `reps` batches of pairs p (after the caller's warm-up)."""
+        ms = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            d = G.batch_query(p, algo="bids", **kw)
+            ms.append(1000.0 * (time.perf_counter() - a))
+        return d, ms
+
+    def summary(name, ms, st, **extra):
+        m = float(np.median(ms))
+        sched[name] = dict({"queries_per_s": round(1000.0 * K / m, 2), "ms_per_batch_median": round(m, 1),
+                            "batches_timed": len(ms), "rounds": int(st["rounds"]),
+                            "scanned_arcs_per_query": int(st["scanned_arcs"] / K),
+                            "gteps": round(st["scanned_arcs"] / (m / 1000.0) / 1e9, 3)}, **extra)
+        _log("%s: %.2f q/s (%.0f ms per batch, %d rounds)" % (name, 1000.0 * K / m, m, st["rounds"]))
+
+    # 1. fixed Delta*-stepping (the i-th threshold is i * Delta, Section 2);
+    #    Delta by doubling while the sample batch gets faster (Section 6.1)
+    G.set_option("theta_mode", 0)
+    d0 = max(int(g.w.min()), 256)
+    G.batch_query(sample, algo="bids", delta=d0)               # warm-up: buffers
+    sweep, best = [], None
+    d = d0
+    while d <= (1 << 20):
+        _, ms = time_batch(sample, 1, delta=d)
+        sweep.append([d, round(ms[0], 1)])
+        if best is None or ms[0] < best[1]:
+            best = (d, ms[0])
+        else:
+            break
+        d *= 2
+    d_star = best[0]
+    G.batch_query(pairs, algo="bids", delta=d_star)
+    d_fixed, ms = time_batch(pairs, args.cmp_steps, delta=d_star)
+    summary("fixed_delta_star", ms, G.stats(), delta=d_star, theta_rule="i-th threshold = i * Delta",
+            doubling_sweep_on_sample_ms=sweep)
+    G.set_option("theta_mode", 2)
+
+    # 2. autotuned on the sample
+    tr = G.tune(sample, algo="bids", batch="plainstar")
+    _log("tuned: %s" % {k: (round(v, 2) if isinstance(v, float) else v) for k, v in tr.items()})
+    G.batch_query(pairs, algo="bids", sched="autotuned")
+    d_auto, ms = time_batch(pairs, args.cmp_steps, sched="autotuned")
+    rule = {0: "i * Delta", 1: "end of the smallest key's Delta bucket", 2: "smallest key + Delta - 1"}
+    summary("autotuned", ms, G.stats(), delta=int(tr["delta"]), theta_rule=rule.get(int(tr["theta_mode"])),
+            heavy_window=int(tr["heavy_window"]), grid_blocks=int(tr["grid_blocks"]), trials=int(tr["trials"]))
+    assert np.array_equal(d_auto, d_fixed), "schedules disagree"
+
+    # 3. learned: trained on the sample with the tuned setting as its base
+    #    (Delta, threshold rule, hub window and launch shape), so the tuned
+    #    fixed run above is the same-rule comparison
+    G.set_option("theta_mode", int(tr["theta_mode"]))
+    G.set_option("heavy_window", int(tr["heavy_window"]))
+    G.set_option("grid_blocks", int(tr["grid_blocks"]))
+    dl = int(tr["delta"])
+    a = time.perf_counter()
+    params, rep = G.mlp_fit(sample, gen.mlp_init(4), algo="bids", epochs=args.epochs, seed=4, delta=dl,
+                            labels="counterfactual")
+    fit_s = time.perf_counter() - a
+    _log("fit in %.1fs: %s" % (fit_s, {k: (round(v, 3) if isinstance(v, float) else v) for k, v in rep.items()}))
+
+    def step():
+        return G.batch_query(pairs, algo="bids", sched="learned", delta=dl)
+
+    for w in range(args.warmup):
+        step()
+        _log("warmup %d done" % w)
+    G.set_option("profile", PROFILE_EVERY)
+    agg = {}
+    step_ms = []
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for k in range(args.steps):
+        a = time.perf_counter()
+        d_learned = step()
+        step_ms.append(1000.0 * (time.perf_counter() - a))
+        st = _agg_stats(G, agg, STAT_KEYS)
+        _log("step %d: %.1f ms, rounds %d" % (k, step_ms[-1], st["rounds"]))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    G.set_option("profile", 0)
+    assert np.array_equal(d_learned, d_auto), "the learned schedule disagrees with the fixed ones"
+    steps = args.steps
+    qps = K * steps / elapsed
+    summary("learned", step_ms, {k: v / steps for k, v in agg.items()}, fit_seconds=round(fit_s, 1),
+            fit={k: (round(v, 4) if isinstance(v, float) else v) for k, v in rep.items()})
+
+    rates = None if args.no_randbench else random_access_rates()
+    dom, roofs = kernel_rooflines(agg, "rmat24", rates)
+    out = {
+        "metric": "exact s-t queries/sec, learned schedule (vs fixed Delta*-stepping and autotuned, same run)",
+        "value": round(qps, 2),
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1000.0 * elapsed / steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {
+            "workload": "R-MAT scale 24 (16,777,216 vertices, %d arcs after symmetrising and deduplication, "
+                        "weights U[1,65535]), 256 pairs from the largest component per step, BiDS Plain*, "
+                        "learned step schedule" % g.m,
+            "queries_per_step": int(K),
+        },
+        "gteps": round(agg["scanned_arcs"] / elapsed / 1e9, 4),
+        "sssp_equivalent_gteps": round(g.m * qps / 1e9, 3),
+        "learned_vs_fixed_delta_star": round(qps / sched["fixed_delta_star"]["queries_per_s"], 4),
+        "learned_vs_same_rule_fixed": round(qps / sched["autotuned"]["queries_per_s"], 4),
+        "batch_ms_p50": round(float(np.percentile(step_ms, 50)), 1),
+        "batch_ms_p99": round(float(np.percentile(step_ms, 99)), 1),
+        "schedules": sched,
+        "roofline": {k: v for k, v in roofs[dom].items() if k != "random_access"},
+        "rooflines": roofs,
+    }
+    if not args.no_cpu:
+        threads = cpu_threads()
+        n_cpu = min(K, max(args.cpu_sample, threads))
+        exp, cb = _cpu_baseline(g, pairs[:n_cpu], "the 256 (the first %d)" % n_cpu, threads)
+        assert np.array_equal(exp, d_learned[:n_cpu]), "GPU and oracle disagree on the CPU sample"
+        out["cpu_baseline"] = cb
+    G.close()
+    print(json.dumps(out), flush=True)
+
+
+# ---- the road-like lattice: 1,000 BiD-A* queries per batch -----------------------
+
+def workload_lattice2048(args):
+    """The jittered 2048 x 2048 lattice (4,194,304 vertices, ~17.2M arcs,
+    weights ceil(1000 * Euclidean length), fixed-point coordinates) with its
+    1,000 seeded uniform pairs as one Plain* BiD-A* batch per step; the graph
+    is stored in Morton order of the coordinates (PPSP_REORDER). Pairs and
+    distances sit in device memory at the interface (PPSP_DEVICE_IO; the
+    library plans the batch on the host, so it stages them through host
+    memory inside the timed call). All 1,000 distances of the last step are
+    checked against the oracle, and every pair is also answered alone for
+    the single-query p50/p99."""
+    import numpy as np
+    import torch
+    import gen
+    import oracle
+    import paper_2506_16488_amd as P
+
+    torch.cuda.set_device(0)
+    t0 = time.time()
+    g = gen.workload_graph("lattice2048")
+    pairs = gen.workload_pairs("lattice2048", g)
+    G = P.Graph.from_host(g, device=0, reorder=True)
+    G.set_option("timeout_ms", 300000)
+    _log("graph n=%d m=%d built+uploaded in %.1fs" % (g.n, g.m, time.time() - t0))
+    pairs_dev = torch.from_numpy(pairs.astype(np.int32)).cuda()
+    dist_dev = torch.empty(pairs.shape[0], dtype=torch.int64, device="cuda")
+    torch.cuda.synchronize()
+
+    def step():
+        G.batch_query_device(pairs_dev, dist_dev, algo=args.algo, batch=args.batch, delta=args.delta)
+
+    for w in range(args.warmup):
+        step()
+        _log("warmup %d done" % w)
+    G.set_option("profile", PROFILE_EVERY)
+    agg = {}
+    step_ms = []
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for k in range(args.steps):
+        a = time.perf_counter()
+        step()
+        step_ms.append(1000.0 * (time.perf_counter() - a))
+        st = _agg_stats(G, agg, STAT_KEYS)
+        _log("step %d: %.1f ms, rounds %d" % (k, step_ms[-1], st["rounds"]))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    G.set_option("profile", 0)
+    dist0 = dist_dev.cpu().numpy().view(np.uint64)
+    K, q = args.steps, pairs.shape[0]
+    qps = q * K / elapsed
+
+    # every distance of the last step against the oracle (not part of any timing)
+    exp = oracle.pp_batch(g.n, g.row_ptr, g.col, g.w, pairs, nthreads=cpu_threads())
+    assert np.array_equal(exp, dist0), "GPU and oracle disagree"
+    # single-query latency: every pair alone through ppsp_query
+    lat = []
+    n_lat = q if args.latency_sample < 0 else min(args.latency_sample, q)
+    for i in range(n_lat):
+        s, t = int(pairs[i, 0]), int(pairs[i, 1])
+        a = time.perf_counter()
+        dd = G.query(s, t, algo=args.algo, delta=args.delta)
+        lat.append(1000.0 * (time.perf_counter() - a))
+        assert dd == int(dist0[i]), "single query disagrees with the batch"
+    rates = None if args.no_randbench else random_access_rates()
+    dom, roofs = kernel_rooflines(agg, "lattice2048", rates)
+    out = {
+        "metric": "exact s-t queries/sec",
+        "value": round(qps, 2), "unit": "queries/s", "n_gpus": 1, "steps": K, "warmup": args.warmup,
+        "ms_per_step": round(1000.0 * elapsed / K, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {
+            "workload": "road-like jittered lattice 2048x2048 (4,194,304 vertices, %d arcs, w=ceil(1000*len)), "
+                        "1,000 uniform s-t pairs per step, %s, %s batch" % (g.m, args.algo, args.batch),
+            "queries_per_step": int(q),
+            "delta": int(G.get_option("default_delta") if args.delta == 0 else args.delta),
+        },
+        "ms_per_step_median": round(float(np.median(step_ms)), 3),
+        "gteps": round(agg["scanned_arcs"] / elapsed / 1e9, 4),
+        "sssp_equivalent_gteps": round(g.m * qps / 1e9, 3),
+        "scanned_arcs_per_query": int(agg["scanned_arcs"] / (K * q)),
+        "rounds_per_step": int(agg["rounds"] / K),
+        "all_distances_checked_against_oracle": int(q),
+        "single_query_count": len(lat),
+        "single_query_p50_ms": round(float(np.percentile(lat, 50)), 3) if lat else None,
+        "single_query_p99_ms": round(float(np.percentile(lat, 99)), 3) if lat else None,
+        "roofline": {k: v for k, v in roofs[dom].items() if k != "random_access"},
+        "rooflines": roofs,
+    }
+    if not args.no_cpu:
+        threads = cpu_threads()
+        n_cpu = min(q, max(args.cpu_sample, threads))
+        exp2, cb = _cpu_baseline(g, pairs[:n_cpu], "the 1,000 (the first %d)" % n_cpu, threads)
+        assert np.array_equal(exp2, dist0[:n_cpu])
+        a = time.perf_counter()
+        one = oracle.pp_batch(g.n, g.row_ptr, g.col, g.w, pairs[:4], nthreads=1)
+        cb["single_thread_ms_per_query"] = round(1000.0 * (time.perf_counter() - a) / 4, 2)
+        assert np.array_equal(one, dist0[:4])
+        out["cpu_baseline"] = cb
+    G.close()
+    print(json.dumps(out), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="rmat24",
+                    choices=["rmat24", "lattice2048", "lattice4096hub", "serve", "ranks", "profile"],
+                    help="rmat24: the headline (learned vs fixed schedules); the others are further measured "
+                         "workloads; profile: one batch of a fixed setting, for counter runs")
+    ap.add_argument("--algo", default="bidastar", help="lattice2048: the search algorithm")
+    ap.add_argument("--batch", default="plainstar", help="lattice2048: the batch strategy")
+    ap.add_argument("--delta", type=int, default=0, help="lattice2048: Delta (0 = the graph default)")
+    ap.add_argument("--cmp-steps", type=int, default=3, help="rmat24: timed batches of each comparison schedule")
+    ap.add_argument("--epochs", type=int, default=30, help="rmat24: training epochs of the learned schedule")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-randbench", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=16)
+    ap.add_argument("--latency-sample", type=int, default=-1, help="lattice2048: pairs answered alone (-1: all)")
+    ap.add_argument("--profile-graph", default="rmat24", help="profile: rmat24 or lattice2048")
+    ap.add_argument("--copy-kernel", action="store_true", help="run the 1 GiB copy used to calibrate counters")
+    args = ap.parse_args()
+    if args.copy_kernel:
+        copy_kernel()
+        return
+    if args.gpus != 1:
+        print("bench.py: one GPU only (queries shard across GPUs with no exchange, so a multi-GPU run "
+              "is N independent copies of this one); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    WORKLOADS[args.workload](args)
+
+
+def workload_profile(args):
+    """One batch of a fixed setting for rocprofv3 counter runs: R-MAT 24 with
+    the bucketed threshold rule at Delta 2048 (the tuned setting's
+    neighbourhood), or the 2048^2 lattice BiD-A* batch at the default Delta."""
+    import numpy as np
+    import torch
+    import gen
+    import paper_2506_16488_amd as P
+    torch.cuda.set_device(0)
+    g = gen.workload_graph(args.profile_graph)
+    if args.profile_graph == "rmat24":
+        pairs = gen.workload_pairs("rmat24", g, cand=gen.lcc(g))
+        algo, delta, rule = "bids", 2048, 1
+    else:
+        pairs = gen.workload_pairs("lattice2048", g)
+        algo, delta, rule = "bidastar", 0, 2
+    G = P.Graph.from_host(g, device=0, reorder=True)
+    G.set_option("theta_mode", rule)
+    for k in range(max(1, args.steps)):
+        G.batch_query(pairs, algo=algo, delta=delta)
+        st = G.stats()
+        print("profile batch %d: rounds %d, arcs %d, hub arcs %d" % (k, st["rounds"], st["scanned_arcs"],
+                                                                    st["heavy_arcs"]), flush=True)
+    G.close()
 
 
 # ---- further workloads (one JSON line each; not the headline) -----------------
@@ -291,26 +552,6 @@ def _timed(fn, steps, warmup):
         fn()
     torch.cuda.synchronize()
     return (time.perf_counter() - a) / steps
-
-
-def _cpu_baseline(g, sample, label):
-    import oracle
-    threads = min(16, os.cpu_count() or 1)
-    a = time.perf_counter()
-    exp = oracle.pp_batch(g.n, g.row_ptr, g.col, g.w, sample, nthreads=threads)
-    cpu_s = time.perf_counter() - a
-    return exp, {"value": round(sample.shape[0] / cpu_s, 3), "unit": "queries/s", "cores": threads, "kind": "oracle",
-                 "sample": "%d pairs of %s, one binary-heap Dijkstra per pair (stops at t), %d host threads, %.1f s"
-                           % (sample.shape[0], label, threads, cpu_s)}
-
-
-def _line(args, workload, value, ms, dtype="u32", **extra):
-    out = {"metric": "exact s-t queries/sec", "value": round(value, 2), "unit": "queries/s", "n_gpus": 1,
-           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3), "higher_is_better": True,
-           "scaling": "weak", "vs_baseline": None, "dtype": dtype, "data": "synthetic",
-           "config": {"workload": workload}}
-    out.update(extra)
-    print(json.dumps(out), flush=True)
 
 
 def workload_lattice4096hub(args):
@@ -358,55 +599,6 @@ def workload_lattice4096hub(args):
                 "(512 from 32 hubs, 512 uniform); value = the fastest of Multi-BiDS, Plain* BiD-A* and Plain* BiDS"
                 % g.m,
           main_["queries_per_s"], main_["ms_per_batch"], **extra)
-
-
-def workload_rmat24(args):
-    """R-MAT scale 24, edge factor 16, weights U[1, 65535]: 256 pairs from the
-    largest component, BiDS Plain*, with the graph's default Delta, the
-    autotuned setting and the learned schedule."""
-    import numpy as np
-    import torch
-    import gen
-    import paper_2506_16488_amd as P
-    torch.cuda.set_device(0)
-    g = gen.workload_graph("rmat24")
-    lcc = gen.lcc(g)
-    pairs = gen.workload_pairs("rmat24", g, cand=lcc)
-    G = P.Graph.from_host(g, device=0, reorder=True)
-    G.set_option("timeout_ms", 900000)
-    print("# graph built: n=%d m=%d" % (g.n, g.m), file=sys.stderr, flush=True)
-    res = {}
-    t = _timed(lambda: G.batch_query(pairs, algo="bids"), 1, 1)
-    res["fixed_default_delta"] = {"queries_per_s": round(len(pairs) / t, 2), "delta": G.get_option("default_delta"),
-                                  "scanned_arcs_per_query": int(G.stats()["scanned_arcs"] / len(pairs))}
-    print("# fixed: %.2f q/s" % (len(pairs) / t), file=sys.stderr, flush=True)
-    print("# tuning on 32 pairs", file=sys.stderr, flush=True)
-    tr = G.tune(pairs[:32], algo="bids", batch="plainstar")
-    print("# tuned: %s" % tr, file=sys.stderr, flush=True)
-    t = _timed(lambda: G.batch_query(pairs, algo="bids", sched="autotuned"), max(1, args.steps), 0)
-    res["autotuned"] = {"queries_per_s": round(len(pairs) / t, 2), "tune": {k: (round(v, 3) if isinstance(v, float) else v)
-                                                                              for k, v in tr.items()},
-                        "scanned_arcs_per_query": int(G.stats()["scanned_arcs"] / len(pairs))}
-    d_auto = G.batch_query(pairs, algo="bids", sched="autotuned")
-    print("# autotuned: %.2f q/s" % (len(pairs) / t), file=sys.stderr, flush=True)
-    train = gen.pairs_uniform(lcc, 16, seed=1104)
-    print("# fitting the learned schedule on 16 pairs", file=sys.stderr, flush=True)
-    params, rep = G.mlp_fit(train, gen.mlp_init(4), algo="bids", epochs=20, seed=4, delta=int(tr["delta"]))
-    t = _timed(lambda: G.batch_query(pairs, algo="bids", sched="learned", delta=int(tr["delta"])), 1, 0)
-    assert np.array_equal(G.batch_query(pairs[:32], algo="bids", sched="learned", delta=int(tr["delta"])), d_auto[:32])
-    res["learned"] = {"queries_per_s": round(len(pairs) / t, 2), "fit": {k: (round(v, 3) if isinstance(v, float) else v)
-                                                                          for k, v in rep.items()}}
-    print("# learned: %.2f q/s" % (len(pairs) / t), file=sys.stderr, flush=True)
-    extra = {"schedules": res}
-    if not args.no_cpu:
-        exp, cb = _cpu_baseline(g, pairs[:8], "the 256")
-        assert np.array_equal(exp, d_auto[:8])
-        extra["cpu_baseline"] = cb
-    G.close()
-    best = max(v["queries_per_s"] for v in res.values())
-    _line(args, "R-MAT scale 24 (16,777,216 vertices, %d arcs, weights U[1,65535]), 256 pairs from the largest "
-                "component, BiDS Plain*; value = best of default-Delta, autotuned and learned schedules" % g.m,
-          best, 1000.0 * len(pairs) / best, **extra)
 
 
 def workload_serve(args):
@@ -545,8 +737,8 @@ def workload_ranks(args):
           1000.0 / mean_ms, mean_ms, **extra)
 
 
-OTHER_WORKLOADS = {"lattice4096hub": workload_lattice4096hub, "rmat24": workload_rmat24, "serve": workload_serve,
-                   "ranks": workload_ranks}
+WORKLOADS = {"rmat24": workload_rmat24, "lattice2048": workload_lattice2048, "lattice4096hub": workload_lattice4096hub,
+             "serve": workload_serve, "ranks": workload_ranks, "profile": workload_profile}
 
 
 if __name__ == "__main__":

@@ -131,6 +131,12 @@ typedef struct {
     uint64_t carried;          /* entries kept for a later round (key above the threshold) */
     uint64_t retries;          /* waves rerun after growing an overflowed frontier queue */
     uint64_t relax_timed;      /* round-kernel launches timed ("profile"): relax_kernel_ms covers these */
+    double heavy_kernel_ms;    /* summed duration of the hub-list kernel launches of the same timed rounds
+                                  (graphs with vertices of degree > 512), else 0 */
+    uint64_t heavy_arcs;       /* arcs of extracted vertices of degree > 512, relaxed by the hub-list kernel
+                                  (included in scanned_arcs) */
+    uint64_t heavy_chunks;     /* hub-list chunk records (at most 2,048 arcs of one vertex each) */
+    uint64_t heavy_success;    /* successful write_min operations of the hub-list kernel (in relax_success) */
 } ppsp_stats;
 
 typedef struct ppsp_graph_s *ppsp_graph;
@@ -338,6 +344,25 @@ int ppsp_tune(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp_opts *
  *                   base multiplier (bin 4) or, in label_mode 1, the fastest
  *                   fixed one; a faster constant network is installed and
  *                   returned in params_out instead (rep->fallback_bin).
+ *                   label_mode 2 (counterfactual): the first three quarters
+ *                   of the pairs (all of them below 8 pairs) train, the rest
+ *                   judge. Every training pair runs under each fixed bin
+ *                   (batch time fitted as c0 + c_round * rounds + c_arc *
+ *                   arcs + c_entry * frontier entries, non-negative
+ *                   coefficients) and under replays that follow the base
+ *                   multiplier up to one of six decision rounds spread over
+ *                   its run and switch to each bin there; the label of a
+ *                   (pair, decision round) is the bin of lowest fitted cost
+ *                   (c_arc * arcs + c_entry * entries + c_round * rounds
+ *                   beyond the best fixed batch's), the base bin unless
+ *                   another is at least 1% cheaper, and it holds until the
+ *                   next switch point. The rows are the base trajectory's
+ *                   features at those decision rounds. The judge times the
+ *                   held-out pairs under the trained network and through
+ *                   the plain fixed-Delta path (base Delta, the graph's
+ *                   threshold rule); if the plain path is faster,
+ *                   PPSP_SCHED_LEARNED runs it on this graph until the next
+ *                   ppsp_mlp_load (rep->plain_fallback = 1).
  * Errors: PPSP_E_INVALID (null pointers, label >= 8, a non-finite
  * parameter, a strategy other than Plain / Plain* for tracing or fitting),
  * the errors of ppsp_batch_query.
@@ -361,6 +386,15 @@ typedef struct {
                                  constant network installed instead (fixed-Delta fallback) */
     double learned_ms;        /* sample batch under the trained network (best of two runs) */
     double fixed_ms;          /* sample batch under the fastest constant network tried (best of two) */
+    /* label_mode 2 (counterfactual replays; see ppsp_mlp_fit) */
+    double c_entry_ns;        /* fitted cost of a frontier entry (ns) */
+    uint32_t variants;        /* replays run (pair x switch round x bin) */
+    uint32_t heldout;         /* held-out pairs the judge timed */
+    double heldout_learned_ms;    /* held-out batch under the trained network (best of two) */
+    double heldout_fixed_ms;      /* held-out batch through the plain fixed-Delta path (best of two) */
+    double heldout_learned_cost;  /* fitted cost (ms) of the held-out run's rounds, arcs and entries, learned */
+    double heldout_fixed_cost;    /* the same for the base multiplier (bin 4) */
+    uint32_t plain_fallback;  /* 1: the plain fixed path won the judge: PPSP_SCHED_LEARNED then runs it */
 } ppsp_fit_report;
 
 int ppsp_mlp_forward(int device, const float *params, const float *x, uint32_t n, float *logits);
@@ -471,9 +505,9 @@ int ppsp_last_stats(ppsp_graph g, ppsp_stats *stats);
 /*
  * Tuning knobs of a graph handle (not part of the method; they only change
  * launch shapes and bookkeeping):
- *   "profile"         K >= 1: time every K-th round-kernel launch (1: all) with HIP
- *                     events carried by the launch itself (hipExtLaunchKernel: no extra
- *                     packets); 0: off
+ *   "profile"         K >= 1: time every K-th round-kernel launch (1: all), and the
+ *                     hub-list kernel of the same rounds, with HIP events carried by the
+ *                     launches themselves (hipExtLaunchKernel: no extra packets); 0: off
  *   "rounds_per_sync" rounds launched between host checks for termination
  *   "grid_blocks"     single-wave workgroups of the round kernel (0 = 20 per compute unit)
  *   "mem_budget_mb"   cap on the search-state memory of one wave (0 = auto)

@@ -55,7 +55,9 @@ class Stats(ctypes.Structure):
                 ("relax_success", ctypes.c_uint64), ("searches", ctypes.c_uint64),
                 ("waves", ctypes.c_uint64), ("wall_ms", ctypes.c_double),
                 ("relax_kernel_ms", ctypes.c_double), ("relax_launches", ctypes.c_uint64),
-                ("carried", ctypes.c_uint64), ("retries", ctypes.c_uint64), ("relax_timed", ctypes.c_uint64)]
+                ("carried", ctypes.c_uint64), ("retries", ctypes.c_uint64), ("relax_timed", ctypes.c_uint64),
+                ("heavy_kernel_ms", ctypes.c_double), ("heavy_arcs", ctypes.c_uint64), ("heavy_chunks", ctypes.c_uint64),
+                ("heavy_success", ctypes.c_uint64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -83,7 +85,10 @@ class FitReport(ctypes.Structure):
                 ("loss_last", ctypes.c_double), ("train_acc", ctypes.c_double), ("label_ms", ctypes.c_double),
                 ("train_ms", ctypes.c_double), ("c_round_ms", ctypes.c_double), ("c_arc_ns", ctypes.c_double),
                 ("best_fixed_bin", ctypes.c_uint32), ("fallback_bin", ctypes.c_uint32),
-                ("learned_ms", ctypes.c_double), ("fixed_ms", ctypes.c_double)]
+                ("learned_ms", ctypes.c_double), ("fixed_ms", ctypes.c_double), ("c_entry_ns", ctypes.c_double),
+                ("variants", ctypes.c_uint32), ("heldout", ctypes.c_uint32), ("heldout_learned_ms", ctypes.c_double),
+                ("heldout_fixed_ms", ctypes.c_double), ("heldout_learned_cost", ctypes.c_double),
+                ("heldout_fixed_cost", ctypes.c_double), ("plain_fallback", ctypes.c_uint32)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}
@@ -502,7 +507,7 @@ class Graph:
         p0 = _f32(init, (MLP_PARAMS,))
         out = np.empty(MLP_PARAMS, np.float32)
         rep = FitReport()
-        mode = {"single": 0, "batch": 1}[labels]
+        mode = {"single": 0, "batch": 1, "counterfactual": 2}[labels]
         _check(lib().ppsp_mlp_fit(self.h, _ptr(pairs), pairs.shape[0], ctypes.byref(make_opts(algo, batch, delta=delta)),
                                   _ptr(p0), int(epochs), int(seed), mode, _ptr(out), ctypes.byref(rep)), "ppsp_mlp_fit")
         return out, rep.as_dict()

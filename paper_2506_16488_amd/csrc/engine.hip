@@ -40,7 +40,8 @@ hipError_t launch_init(const RoundArgs &A, hipStream_t st);
 hipError_t launch_round(const RoundArgs &A, uint32_t grid, hipStream_t st, hipEvent_t e0 = nullptr,
                         hipEvent_t e1 = nullptr);
 hipError_t launch_control(const RoundArgs &A, hipStream_t st);
-hipError_t launch_heavy(const RoundArgs &A, uint32_t grid, hipStream_t st);
+hipError_t launch_heavy(const RoundArgs &A, uint32_t grid, hipStream_t st, hipEvent_t e0 = nullptr,
+                        hipEvent_t e1 = nullptr);
 hipError_t launch_admit(const RoundArgs &A, const uint32_t *ids, uint32_t k, hipStream_t st);
 hipError_t launch_idle(const RoundArgs &A, hipStream_t st);
 hipError_t launch_mlp_forward(const float *P, const float *X, uint32_t n, float *logits, hipStream_t st);
@@ -245,6 +246,7 @@ struct ppsp_graph_s {
     // learned schedule
     DevBuf sc, bin, bin_after, sw_round, done_round, tot_arcs, tot_ent, trace, trace_s, trace_r, trace_b, trace_n, mlpw;
     bool mlp_loaded = false;
+    bool ml_plain = false;          // the fit's judge preferred the plain fixed path: LEARNED runs it
     MlCtx *ml = nullptr;            // set for the duration of a learned or traced call
 };
 
@@ -398,7 +400,7 @@ struct WaveOut {
     std::vector<uint32_t> path;     // concatenated paths (if requested)
     std::vector<uint64_t> path_off; // npair + 1
     unsigned long long stats[ST_N] = {0};
-    double relax_ms = 0;
+    double relax_ms = 0, heavy_ms = 0;  // summed durations of the timed round / hub-list launches
     uint64_t launches = 0, timed = 0;   // round-kernel launches, and those timed
     // learned / traced schedule: per search
     std::vector<uint32_t> done_round;
@@ -540,9 +542,9 @@ int run_wave(ppsp_graph g, const Plan &P, bool want_path, WaveOut &out) {
         const int K = std::max<int64_t>(1, g->opt_rounds_per_sync);
         const bool prof = g->opt_profile != 0;
         const uint64_t every = prof ? (uint64_t)g->opt_profile : 0;   // time every `every`-th launch
-        if (prof) CHK(ensure_events(g, 2 * (size_t)K));
+        if (prof) CHK(ensure_events(g, 4 * (size_t)K));
         uint64_t r = 0;
-        double relax_ms = 0;
+        double relax_ms = 0, heavy_ms = 0;
         uint64_t launches = 0, timed = 0;
         const auto t_start = std::chrono::steady_clock::now();
         bool timed_out = false;
@@ -588,12 +590,14 @@ int run_wave(ppsp_graph g, const Plan &P, bool want_path, WaveOut &out) {
             } else {
                 for (kk = 0; kk < K; kk++, r++) {
                     if (prof && r % every == 0) {
-                        HIPCHK(launch_round(A, grid, st, g->ev[2 * nt], g->ev[2 * nt + 1]));
+                        // the round and hub-list kernels of this round carry their own events
+                        HIPCHK(launch_round(A, grid, st, g->ev[4 * nt], g->ev[4 * nt + 1]));
+                        if (A.hcap) HIPCHK(launch_heavy(A, grid, st, g->ev[4 * nt + 2], g->ev[4 * nt + 3]));
                         nt++;
                     } else {
                         HIPCHK(launch_round(A, grid, st));
+                        if (A.hcap) HIPCHK(launch_heavy(A, grid, st));
                     }
-                    if (A.hcap) HIPCHK(launch_heavy(A, grid, st));
                     HIPCHK(launch_control(A, st));
                 }
             }
@@ -604,8 +608,12 @@ int run_wave(ppsp_graph g, const Plan &P, bool want_path, WaveOut &out) {
             HIPCHK(hipStreamSynchronize(st));
             for (int k = 0; k < nt; k++) {
                 float ms = 0;
-                HIPCHK(hipEventElapsedTime(&ms, g->ev[2 * k], g->ev[2 * k + 1]));
+                HIPCHK(hipEventElapsedTime(&ms, g->ev[4 * k], g->ev[4 * k + 1]));
                 relax_ms += ms;
+                if (A.hcap) {
+                    HIPCHK(hipEventElapsedTime(&ms, g->ev[4 * k + 2], g->ev[4 * k + 3]));
+                    heavy_ms += ms;
+                }
             }
             timed += nt;
             uint64_t pending = 0;
@@ -674,6 +682,7 @@ int run_wave(ppsp_graph g, const Plan &P, bool want_path, WaveOut &out) {
             }
         }
         out.relax_ms = relax_ms;
+        out.heavy_ms = heavy_ms;
         out.launches = launches;
         out.timed = timed;
         if (want_path) {
@@ -780,11 +789,15 @@ void accumulate(ppsp_graph g, const WaveOut &w) {
     g->last.entries += w.stats[ST_ENTRIES];
     g->last.scanned_vertices += w.stats[ST_SCANV];
     g->last.scanned_arcs += w.stats[ST_SCANE];
-    g->last.relax_success += w.stats[ST_SUCC];
+    g->last.relax_success += w.stats[ST_SUCC] + w.stats[ST_HSUCC];
+    g->last.heavy_success += w.stats[ST_HSUCC];
     g->last.carried += w.stats[ST_CARRY];
     g->last.relax_kernel_ms += w.relax_ms;
     g->last.relax_launches += w.launches;
     g->last.relax_timed += w.timed;
+    g->last.heavy_kernel_ms += w.heavy_ms;
+    g->last.heavy_arcs += w.stats[ST_HEAVYE];
+    g->last.heavy_chunks += w.stats[ST_HCHUNK];
     g->last.waves += 1;
 }
 
@@ -1263,7 +1276,7 @@ int batch_impl(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp_opts 
         bool set;
         ~MlRestore() { if (set) g->ml = nullptr; }
     } mlrestore{g, false};
-    if ((o->sched == PPSP_SCHED_LEARNED || o->sched == PPSP_SCHED_RHO) && !g->ml) {
+    if ((o->sched == PPSP_SCHED_RHO || (o->sched == PPSP_SCHED_LEARNED && !g->ml_plain)) && !g->ml) {
         learned.mode = o->sched == PPSP_SCHED_LEARNED ? 2 : 3;
         g->ml = &learned;
         mlrestore.set = true;
@@ -1595,6 +1608,7 @@ int mlp_load_impl(ppsp_graph g, const float *params) {
     HIPCHK(hipMemcpyAsync(g->mlpw.p, h.data(), MLP_NPARAM * 2, hipMemcpyHostToDevice, g->st));
     HIPCHK(hipStreamSynchronize(g->st));
     g->mlp_loaded = true;
+    g->ml_plain = false;
     return PPSP_OK;
 }
 
@@ -2941,12 +2955,261 @@ int batch_labels(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp_opt
     return PPSP_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Batch time T = c0 + c_r R + c_a A + c_e E by least squares over the fixed
+// bins, with every coefficient non-negative: the best fit among the subsets of
+// (R, A, E) whose own least-squares coefficients are all non-negative.
+void fit_cost4(int nb, const double *T, const double *Rb, const double *Ab, const double *Eb, double &c0, double &cr,
+               double &ca, double &ce) {
+    double best_err = 1e300;
+    c0 = T[0];
+    cr = ca = ce = 0;
+    for (int mask = 0; mask < 8; mask++) {
+        const double *col[3] = {Rb, Ab, Eb};
+        int idx[3], m = 0;
+        for (int j = 0; j < 3; j++)
+            if (mask >> j & 1) idx[m++] = j;
+        // normal equations of [1, cols] (up to 4 x 4), Gauss-Jordan with pivoting
+        double M[4][5] = {{0}};
+        for (int b = 0; b < nb; b++) {
+            double x[4] = {1.0, 0, 0, 0};
+            for (int j = 0; j < m; j++) x[j + 1] = col[idx[j]][b];
+            for (int r = 0; r <= m; r++) {
+                for (int c = 0; c <= m; c++) M[r][c] += x[r] * x[c];
+                M[r][4] += x[r] * T[b];
+            }
+        }
+        bool ok = true;
+        for (int c = 0; c <= m && ok; c++) {
+            int piv = c;
+            for (int r = c + 1; r <= m; r++) if (std::fabs(M[r][c]) > std::fabs(M[piv][c])) piv = r;
+            for (int j = 0; j < 5; j++) std::swap(M[c][j], M[piv][j]);
+            if (std::fabs(M[c][c]) < 1e-300) { ok = false; break; }
+            for (int r = 0; r <= m; r++) {
+                if (r == c) continue;
+                const double f = M[r][c] / M[c][c];
+                for (int j = 0; j < 5; j++) M[r][j] -= f * M[c][j];
+            }
+        }
+        if (!ok) continue;
+        double coef[4];
+        for (int j = 0; j <= m; j++) coef[j] = M[j][4] / M[j][j];
+        bool nonneg = true;
+        for (int j = 1; j <= m; j++) nonneg = nonneg && coef[j] >= 0;
+        if (!nonneg) continue;
+        double err = 0;
+        for (int b = 0; b < nb; b++) {
+            double p = coef[0];
+            for (int j = 0; j < m; j++) p += coef[j + 1] * col[idx[j]][b];
+            err += (p - T[b]) * (p - T[b]);
+        }
+        if (err < best_err) {
+            best_err = err;
+            c0 = coef[0];
+            cr = ca = ce = 0;
+            for (int j = 0; j < m; j++) (idx[j] == 0 ? cr : idx[j] == 1 ? ca : ce) = coef[j + 1];
+        }
+    }
+}
+
+double wall_ms_since(std::chrono::steady_clock::time_point a) {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - a).count();
+}
+
+// label_mode 2 of ppsp_mlp_fit (see include/ppsp.h).
+int fit_counterfactual(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp_opts *opts, const float *init,
+                       uint32_t epochs, uint64_t seed, float *params_out, ppsp_fit_report &R) {
+    const auto t0 = std::chrono::steady_clock::now();
+    const uint32_t kt = k >= 8 ? (3 * k + 3) / 4 : k;             // training pairs
+    const uint32_t *hp = k >= 8 ? pairs + 2ull * kt : pairs;       // held-out pairs of the judge
+    const uint32_t hk = k >= 8 ? k - kt : k;
+    ppsp_opts o = *opts;
+    o.sched = PPSP_SCHED_FIXED;
+    o.flags &= ~(uint32_t)(PPSP_WANT_PATH | PPSP_DEVICE_IO);
+    const uint32_t every = (uint32_t)std::max<int64_t>(1, g->opt_ml_every);
+    // 1. Every fixed bin on the training pairs: batch time, and per pair rounds, arcs, entries.
+    double T[MLP_K], Rb[MLP_K], Ab[MLP_K], Eb[MLP_K];
+    {
+        TraceReq warm;
+        TraceOut w;
+        CHK(trace_run(g, pairs, kt, &o, warm, w));                 // buffers grown once, untimed
+    }
+    for (uint32_t b = 0; b < (uint32_t)MLP_K; b++) {
+        const std::vector<uint8_t> bins(kt, (uint8_t)b);
+        TraceReq rq;
+        rq.bins = bins.data();
+        TraceOut out;
+        const auto a = std::chrono::steady_clock::now();
+        CHK(trace_run(g, pairs, kt, &o, rq, out));
+        T[b] = wall_ms_since(a);
+        Rb[b] = *std::max_element(out.pair_rounds.begin(), out.pair_rounds.end());
+        Ab[b] = Eb[b] = 0;
+        for (uint32_t i = 0; i < kt; i++) { Ab[b] += (double)out.pair_arcs[i]; Eb[b] += (double)out.pair_ent[i]; }
+    }
+    double c0, cr, ca, ce;
+    fit_cost4(MLP_K, T, Rb, Ab, Eb, c0, cr, ca, ce);
+    uint32_t bbest = 0;
+    for (uint32_t b = 1; b < (uint32_t)MLP_K; b++) if (T[b] < T[bbest]) bbest = b;
+    const double Rstar = Rb[bbest];
+    R.c_round_ms = cr;
+    R.c_arc_ns = ca * 1e6;
+    R.c_entry_ns = ce * 1e6;
+    R.best_fixed_bin = bbest;
+    // 2. The base trajectory (bin 4) with its feature rows.
+    TraceReq dq;
+    dq.rows = true;
+    dq.cap = 1ull << 22;
+    TraceOut base;
+    CHK(trace_run(g, pairs, kt, &o, dq, base));
+    // 3. Replays: the base bin until a decision round, then each bin to the end.
+    constexpr int NPOINT = 6;
+    std::vector<uint32_t> vp, vsw, vq, vr;
+    std::vector<uint8_t> vb, v4;
+    std::vector<std::vector<uint32_t>> points(kt);
+    for (uint32_t q = 0; q < kt; q++) {
+        if (pairs[2 * q] == pairs[2 * q + 1] || base.pair_rounds[q] == 0) continue;
+        const uint32_t Rq = base.pair_rounds[q];
+        for (int j = 0; j < NPOINT; j++) {
+            const uint32_t r = (uint32_t)((uint64_t)j * Rq / NPOINT) / every * every;   // a decision round
+            if (r >= Rq || (!points[q].empty() && points[q].back() == r)) continue;
+            points[q].push_back(r);
+            for (uint32_t b = 0; b < (uint32_t)MLP_K; b++) {
+                vp.push_back(pairs[2 * q]);
+                vp.push_back(pairs[2 * q + 1]);
+                vsw.push_back(r + 1);            // the step chosen after round r runs bin b
+                vb.push_back((uint8_t)b);
+                v4.push_back((uint8_t)(MLP_K / 2));
+                vq.push_back(q);
+                vr.push_back(r);
+            }
+        }
+    }
+    const uint32_t nv = (uint32_t)vq.size();
+    R.variants = nv;
+    TraceOut rep;
+    if (nv) {
+        TraceReq vq_;
+        vq_.bins = v4.data();
+        vq_.bins_after = vb.data();
+        vq_.switch_round = vsw.data();
+        vq_.distinct = true;
+        CHK(trace_run(g, vp.data(), nv, &o, vq_, rep));
+    }
+    // 4. Labels per (pair, switch point): the bin of lowest fitted remaining cost.
+    std::map<std::pair<uint32_t, uint32_t>, uint8_t> label;
+    for (uint32_t v0 = 0; v0 < nv; v0 += MLP_K) {
+        double cost[MLP_K];
+        for (uint32_t b = 0; b < (uint32_t)MLP_K; b++) {
+            const uint32_t v = v0 + b;
+            cost[b] = ca * (double)rep.pair_arcs[v] + ce * (double)rep.pair_ent[v] +
+                      cr * std::max(0.0, (double)rep.pair_rounds[v] - Rstar);
+        }
+        uint32_t lb = MLP_K / 2;
+        for (uint32_t b = 0; b < (uint32_t)MLP_K; b++)
+            if (cost[b] < cost[lb] && cost[b] < cost[MLP_K / 2] * 0.99) lb = b;
+        label[{vq[v0], vr[v0]}] = (uint8_t)lb;
+        R.label_hist[lb]++;
+    }
+    // rows: the base trajectory's decision rounds, each labelled by the switch
+    // point at or before it
+    std::vector<float> X;
+    std::vector<uint32_t> Y;
+    for (size_t r = 0; r < base.row_pair.size(); r++) {
+        const uint32_t q = base.row_pair[r], rr = base.row_round[r];
+        if (q >= kt || rr % every != 0 || points[q].empty()) continue;
+        uint32_t pt = points[q][0];
+        for (uint32_t p : points[q]) if (p <= rr) pt = p;
+        if (pt > rr) continue;
+        X.insert(X.end(), base.feat.begin() + r * MLP_F, base.feat.begin() + (r + 1) * MLP_F);
+        Y.push_back(label[{q, pt}]);
+    }
+    R.rows = Y.size();
+    R.label_ms = wall_ms_since(t0);
+    // 5. Training on the GPU.
+    auto t1 = std::chrono::steady_clock::now();
+    memcpy(params_out, init, MLP_NPARAM * 4);
+    if (!Y.empty())
+        CHK(mlp_train_impl(g->device, params_out, X.data(), Y.data(), (uint32_t)Y.size(), epochs,
+                           std::min<uint32_t>(256, (uint32_t)Y.size()), 2e-3f, seed, &R.loss_first, &R.loss_last));
+    R.train_ms = wall_ms_since(t1);
+    if (!Y.empty()) {
+        std::vector<float> lg((uint64_t)Y.size() * MLP_K);
+        CHK(mlp_forward_impl(g->device, params_out, X.data(), (uint32_t)Y.size(), lg.data()));
+        uint64_t hit = 0;
+        for (size_t r = 0; r < Y.size(); r++) {
+            uint32_t bb = 0;
+            for (uint32_t b = 1; b < (uint32_t)MLP_K; b++) if (lg[r * MLP_K + b] > lg[r * MLP_K + bb]) bb = b;
+            hit += bb == Y[r];
+        }
+        R.train_acc = (double)hit / Y.size();
+    }
+    // 6. The judge, on held-out pairs: the trained network against the plain
+    //    fixed-Delta path (base Delta, the graph's threshold rule).
+    CHK(mlp_load_impl(g, params_out));
+    R.heldout = hk;
+    std::vector<uint64_t> dd(hk);
+    ppsp_opts lo = o;
+    lo.sched = PPSP_SCHED_LEARNED;
+    R.heldout_learned_ms = R.heldout_fixed_ms = 1e300;
+    for (int rep2 = 0; rep2 < 2; rep2++) {
+        auto a = std::chrono::steady_clock::now();
+        CHK(batch_impl(g, hp, hk, &lo, nullptr, dd.data(), nullptr, nullptr, 0, nullptr));
+        R.heldout_learned_ms = std::min(R.heldout_learned_ms, wall_ms_since(a));
+        a = std::chrono::steady_clock::now();
+        CHK(batch_impl(g, hp, hk, &o, nullptr, dd.data(), nullptr, nullptr, 0, nullptr));
+        R.heldout_fixed_ms = std::min(R.heldout_fixed_ms, wall_ms_since(a));
+    }
+    // fitted costs of the two held-out runs (traced: same schedules, counters kept)
+    {
+        TraceReq nq;
+        nq.network = true;
+        TraceOut nl, nf;
+        CHK(trace_run(g, hp, hk, &o, nq, nl));
+        TraceReq fq;
+        CHK(trace_run(g, hp, hk, &o, fq, nf));
+        auto cost = [&](const TraceOut &t) {
+            double a = 0, e = 0, rmax = 0;
+            for (uint32_t i = 0; i < hk; i++) {
+                a += (double)t.pair_arcs[i];
+                e += (double)t.pair_ent[i];
+                rmax = std::max(rmax, (double)t.pair_rounds[i]);
+            }
+            return c0 + cr * rmax + ca * a + ce * e;
+        };
+        R.heldout_learned_cost = cost(nl);
+        R.heldout_fixed_cost = cost(nf);
+    }
+    R.fallback_bin = MLP_K;
+    R.learned_ms = R.heldout_learned_ms;
+    R.fixed_ms = R.heldout_fixed_ms;
+    if (R.heldout_fixed_ms < R.heldout_learned_ms) {
+        g->ml_plain = true;            // LEARNED runs the plain fixed path on this graph
+        R.plain_fallback = 1;
+    }
+    return PPSP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 int ppsp_mlp_fit(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp_opts *opts, const float *init,
                  uint32_t epochs, uint64_t seed, uint32_t label_mode, float *params_out, ppsp_fit_report *rep) {
-    if (!g || !opts || !pairs || k == 0 || !init || !params_out || label_mode > 1) return PPSP_E_INVALID;
+    if (!g || !opts || !pairs || k == 0 || !init || !params_out || label_mode > 2) return PPSP_E_INVALID;
     if (g->served) return PPSP_E_BUSY;
     if (opts->batch != PPSP_BATCH_PLAIN && opts->batch != PPSP_BATCH_PLAINSTAR) return PPSP_E_INVALID;
     CHK(check_opts(g, opts));
+    for (uint64_t i = 0; i < 2ull * k; i++)
+        if (pairs[i] >= g->n) return PPSP_E_RANGE;
+    if (label_mode == 2) {
+        ppsp_fit_report R{};
+        CHK(fit_counterfactual(g, pairs, k, opts, init, epochs, seed, params_out, R));
+        if (rep) *rep = R;
+        return PPSP_OK;
+    }
     ppsp_fit_report R{};
     auto t0 = std::chrono::steady_clock::now();
     std::vector<uint8_t> y(k, (uint8_t)(MLP_K / 2));

@@ -362,7 +362,7 @@ __global__ __launch_bounds__(WAVE) void k_round(RoundArgs A) {
         A.round[1] = r;                                    // for k_control
         if (nchunks) atomicAdd(&A.stats[ST_ROUNDS], 1ull);
     }
-    unsigned long long c_ent = 0, c_sv = 0, c_se = 0, c_succ = 0, c_keep = 0;
+    unsigned long long c_ent = 0, c_sv = 0, c_se = 0, c_succ = 0, c_keep = 0, c_he = 0, c_hc = 0;
     const bool count = A.sc && blockIdx.x < ML_SAMPLE;
 
     __shared__ uint4 lq[LCAP];
@@ -562,6 +562,10 @@ __global__ __launch_bounds__(WAVE) void k_round(RoundArgs A) {
         const bool heavy = action == 2 && A.hcap && re - rb > HEAVY_DEG;
         if (__ballot(heavy)) {
             const uint32_t nck = heavy ? (re - rb + HEAVY_CHUNK - 1) / HEAVY_CHUNK : 0u;
+            if (heavy) {
+                c_he += re - rb;
+                c_hc += nck;
+            }
             uint32_t tot;
             const uint32_t pre = wave_exscan(nck, &tot);
             unsigned long long b0 = 0;
@@ -730,10 +734,14 @@ __global__ __launch_bounds__(WAVE) void k_round(RoundArgs A) {
     c_se = wave_sum_u64(c_se);
     c_succ = wave_sum_u64(c_succ);
     c_keep = wave_sum_u64(c_keep);
+    c_he = wave_sum_u64(c_he);
+    c_hc = wave_sum_u64(c_hc);
     if (lane_id() == 0 && c_ent) {
         // this workgroup's own slot: no atomics, summed by the host
         unsigned long long *ws = A.wstats + (uint64_t)blockIdx.x * ST_N;
         ws[ST_CARRY] += c_keep;
+        ws[ST_HEAVYE] += c_he;
+        ws[ST_HCHUNK] += c_hc;
         ws[ST_ENTRIES] += c_ent;
         ws[ST_SCANV] += c_sv;
         ws[ST_SCANE] += c_se;
@@ -780,7 +788,7 @@ __global__ __launch_bounds__(WAVE) void k_heavy(RoundArgs A) {
     }
     wstage_flush(st, scnt, qout, qcout, A.qseg, A.err);
     c_succ = wave_sum_u64(c_succ);
-    if (lane_id() == 0 && c_succ) A.wstats[(uint64_t)blockIdx.x * ST_N + ST_SUCC] += c_succ;
+    if (lane_id() == 0 && c_succ) A.wstats[(uint64_t)blockIdx.x * ST_N + ST_HSUCC] += c_succ;
 }
 
 // Prefix sum of the chunk counts of the NSEG segments of queue `q` (one
@@ -1265,17 +1273,19 @@ hipError_t launch_round(const RoundArgs &A, uint32_t grid, hipStream_t st, hipEv
                   : launch_round_t<false, false, false>(A, grid, st, e0, e1);
 }
 
-hipError_t launch_heavy(const RoundArgs &A, uint32_t grid, hipStream_t st) {
-    const bool rev = A.in_row_ptr != A.row_ptr;
-    if (rev) {
-        if (A.memo) k_heavy<true, true><<<grid, WAVE, 0, st>>>(A);
-        else k_heavy<false, true><<<grid, WAVE, 0, st>>>(A);
-    } else if (A.memo) {
-        k_heavy<true, false><<<grid, WAVE, 0, st>>>(A);
-    } else {
-        k_heavy<false, false><<<grid, WAVE, 0, st>>>(A);
-    }
+template <bool MEMO, bool REV>
+static hipError_t launch_heavy_t(const RoundArgs &A, uint32_t grid, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+    if (e0)
+        hipExtLaunchKernelGGL(k_heavy<MEMO, REV>, dim3(grid), dim3(WAVE), 0, st, e0, e1, 0, A);
+    else
+        k_heavy<MEMO, REV><<<grid, WAVE, 0, st>>>(A);
     return hipGetLastError();
+}
+
+hipError_t launch_heavy(const RoundArgs &A, uint32_t grid, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+    const bool rev = A.in_row_ptr != A.row_ptr;
+    if (rev) return A.memo ? launch_heavy_t<true, true>(A, grid, st, e0, e1) : launch_heavy_t<false, true>(A, grid, st, e0, e1);
+    return A.memo ? launch_heavy_t<true, false>(A, grid, st, e0, e1) : launch_heavy_t<false, false>(A, grid, st, e0, e1);
 }
 
 hipError_t launch_control(const RoundArgs &A, hipStream_t st) {

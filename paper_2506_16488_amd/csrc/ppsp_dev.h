@@ -234,6 +234,10 @@ __host__ __device__ inline uint64_t state_index(uint32_t G, uint32_t n, uint32_t
     return ((((uint64_t)(i >> s) * n) + v) << s) | (i & (G - 1u));
 }
 
-enum StatIdx { ST_ROUNDS = 0, ST_ENTRIES = 1, ST_SCANV = 2, ST_SCANE = 3, ST_SUCC = 4, ST_CARRY = 5, ST_N = 8 };
+// ST_HEAVYE / ST_HCHUNK: arcs and chunk records the round kernel handed to the
+// heavy list (relaxed by k_heavy; ST_SCANE counts every scanned arc);
+// ST_HSUCC: successful relaxations in k_heavy (ST_SUCC: in k_round).
+enum StatIdx { ST_ROUNDS = 0, ST_ENTRIES = 1, ST_SCANV = 2, ST_SCANE = 3, ST_SUCC = 4, ST_CARRY = 5, ST_HEAVYE = 6,
+               ST_HCHUNK = 7, ST_HSUCC = 8, ST_N = 16 };
 
 }  // namespace ppsp

@@ -38,12 +38,41 @@ def test_kernel_hash_ignores_comments_only(tmp_path):
 
 
 def test_traffic_profile_fields():
+    """Every committed counter summary (per workload and kernel) holds the
+    scaled FETCH_SIZE + WRITE_SIZE bytes it reports, and is reported only while
+    the kernel source matches the one it measured."""
+    if not os.path.exists(bench.TRAFFIC_FILE):
+        assert bench.measured_traffic("rmat24", "k_round") is None
+        return
     t = json.load(open(bench.TRAFFIC_FILE))
-    for key in ("kernel", "kernel_source_hash", "fetch_kib_per_launch", "write_kib_per_launch", "fetch_scale",
-                "write_scale", "traffic_bytes_per_launch"):
-        assert key in t
-    assert t["kernel"] == "k_round" and t["traffic_bytes_per_launch"] > 0
-    expect = (t["fetch_kib_per_launch"] * t["fetch_scale"] + t["write_kib_per_launch"] * t["write_scale"]) * 1024
-    assert abs(expect - t["traffic_bytes_per_launch"]) <= 1024
-    # reported only while the kernel source matches the one the counters measured
-    assert bench.measured_traffic() in (None, int(t["traffic_bytes_per_launch"]))
+    assert t
+    for workload, kernels in t.items():
+        for kernel, e in kernels.items():
+            for key in ("kernel_source_hash", "fetch_kib_per_launch", "write_kib_per_launch", "fetch_scale",
+                        "write_scale", "traffic_bytes_per_launch", "command"):
+                assert key in e, (workload, kernel, key)
+            assert e["traffic_bytes_per_launch"] > 0
+            expect = (e["fetch_kib_per_launch"] * e["fetch_scale"] + e["write_kib_per_launch"] * e["write_scale"]) * 1024
+            assert abs(expect - e["traffic_bytes_per_launch"]) <= 1024
+            assert bench.measured_traffic(workload, kernel) in (None, int(e["traffic_bytes_per_launch"]))
+    assert bench.measured_traffic("no-such-workload", "k_round") is None
+
+
+def test_rooflines_from_counters():
+    """The per-kernel rooflines: algorithmic bytes per launch from the
+    counters (24 B per scanned vertex and per arc, the hub arcs to the hub-list
+    kernel), achieved = bytes / sampled launch time, the dominant kernel is
+    the one with the longer launches."""
+    agg = {"relax_launches": 10, "relax_timed": 5, "relax_kernel_ms": 5.0, "heavy_kernel_ms": 10.0,
+           "scanned_vertices": 1000, "scanned_arcs": 10000, "heavy_arcs": 6000, "heavy_chunks": 10,
+           "relax_success": 500, "heavy_success": 200}
+    dom, r = bench.kernel_rooflines(agg, "none")
+    assert dom == "k_heavy"
+    kr, kh = r["k_round"], r["k_heavy"]
+    assert kr["alg_bytes_per_launch"] == int((24 * 1000 + 24 * 4000 + 32 * 10) / 10)
+    assert kh["alg_bytes_per_launch"] == int((24 * 6000 + 32 * 10) / 10)
+    assert abs(kr["avg_launch_us"] - 1000.0) < 1e-6 and abs(kh["avg_launch_us"] - 2000.0) < 1e-6
+    assert abs(kr["achieved"] - kr["alg_bytes_per_launch"] / 1e-3 / 1e9) < 0.01
+    assert kr["frac"] == round(kr["achieved"] / 8000.0, 5)
+    ra = bench.random_access_roofline((1e10, 1e9), 3000, 100, 10.0)
+    assert abs(ra["floor_us"] - 1e6 * (3000 / 1e10 + 100 / 1e9)) < 0.01
