@@ -311,6 +311,11 @@ def workload_rmat24(args):
                             labels="counterfactual")
     fit_s = time.perf_counter() - a
     _log("fit in %.1fs: %s" % (fit_s, {k: (round(v, 3) if isinstance(v, float) else v) for k, v in rep.items()}))
+    if args.save_schedule:
+        # the trained schedule and its base setting, for counter runs of the same batch (--workload profile)
+        np.savez(args.save_schedule, params=params, delta=dl, theta_mode=int(tr["theta_mode"]),
+                 heavy_window=int(tr["heavy_window"]), grid_blocks=int(tr["grid_blocks"]),
+                 plain_fallback=int(rep["plain_fallback"]))
 
     def step():
         return G.batch_query(pairs, algo="bids", sched="learned", delta=dl)
@@ -502,6 +507,11 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=16)
     ap.add_argument("--latency-sample", type=int, default=-1, help="lattice2048: pairs answered alone (-1: all)")
     ap.add_argument("--profile-graph", default="rmat24", help="profile: rmat24 or lattice2048")
+    ap.add_argument("--schedule", default=None, help="profile: the schedule file a headline run saved")
+    ap.add_argument("--save-schedule", default=None, help="rmat24: save the trained schedule (.npz) here")
+    ap.add_argument("--serve-sat", type=int, default=12, help="serve: requests of the saturation run")
+    ap.add_argument("--serve-requests", type=int, default=24, help="serve: requests per load level")
+    ap.add_argument("--serve-budget-gb", type=int, default=160, help="serve: search-state budget (GiB)")
     ap.add_argument("--copy-kernel", action="store_true", help="run the 1 GiB copy used to calibrate counters")
     args = ap.parse_args()
     if args.copy_kernel:
@@ -515,28 +525,36 @@ def main():
 
 
 def workload_profile(args):
-    """One batch of a fixed setting for rocprofv3 counter runs: R-MAT 24 with
-    the bucketed threshold rule at Delta 2048 (the tuned setting's
-    neighbourhood), or the 2048^2 lattice BiD-A* batch at the default Delta."""
+    """Batches of one workload's timed step alone, for rocprofv3 counter runs
+    (--steps batches): R-MAT 24 under the learned schedule that a headline
+    run saved with --save-schedule (--schedule FILE: its network, Delta,
+    threshold rule, hub window and launch shape), or the 2048^2 lattice
+    BiD-A* batch at the default Delta (--profile-graph lattice2048)."""
     import numpy as np
     import torch
     import gen
     import paper_2506_16488_amd as P
     torch.cuda.set_device(0)
     g = gen.workload_graph(args.profile_graph)
+    G = P.Graph.from_host(g, device=0, reorder=True)
+    G.set_option("timeout_ms", 900000)
     if args.profile_graph == "rmat24":
         pairs = gen.workload_pairs("rmat24", g, cand=gen.lcc(g))
-        algo, delta, rule = "bids", 2048, 1
+        s = np.load(args.schedule)
+        G.set_option("theta_mode", int(s["theta_mode"]))
+        G.set_option("heavy_window", int(s["heavy_window"]))
+        G.set_option("grid_blocks", int(s["grid_blocks"]))
+        G.mlp_load(s["params"])
+        sched = "fixed" if int(s["plain_fallback"]) else "learned"
+        run = lambda: G.batch_query(pairs, algo="bids", sched=sched, delta=int(s["delta"]))
     else:
         pairs = gen.workload_pairs("lattice2048", g)
-        algo, delta, rule = "bidastar", 0, 2
-    G = P.Graph.from_host(g, device=0, reorder=True)
-    G.set_option("theta_mode", rule)
+        run = lambda: G.batch_query(pairs, algo="bidastar")
     for k in range(max(1, args.steps)):
-        G.batch_query(pairs, algo=algo, delta=delta)
+        run()
         st = G.stats()
-        print("profile batch %d: rounds %d, arcs %d, hub arcs %d" % (k, st["rounds"], st["scanned_arcs"],
-                                                                    st["heavy_arcs"]), flush=True)
+        print("profile batch %d: rounds %d, launches %d, arcs %d, hub arcs %d" % (
+            k, st["rounds"], st["relax_launches"], st["scanned_arcs"], st["heavy_arcs"]), flush=True)
     G.close()
 
 
@@ -602,51 +620,72 @@ def workload_lattice4096hub(args):
 
 
 def workload_serve(args):
-    """Serving: the 4096^2 lattice (BiD-A*) and R-MAT 24 (BiDS) resident in one
-    server; requests of log-uniform size in [1, 64] pairs on either graph
-    (50/50), Poisson arrivals at 50% and 80% of the measured saturation rate."""
+    """Serving (continuous batching): the 4096 x 4096 lattice (BiD-A*) and
+    R-MAT 24 (BiDS, autotuned Delta and threshold rule) resident together in
+    one server, both under their learned step schedule (trained by
+    ppsp_mlp_fit on held-out sample pairs); requests of log-uniform size in
+    [1, 4096] pairs on either graph (50/50); saturation from requests
+    submitted at once, then Poisson arrivals at 50% and 80% of it. Every
+    request of the last level is checked against its own run alone."""
     import numpy as np
     import torch
     import gen
+    import oracle
     import paper_2506_16488_amd as P
     torch.cuda.set_device(0)
+    t0 = time.time()
     hosts = [gen.workload_graph("lattice4096"), gen.workload_graph("rmat24")]
     lcc = gen.lcc(hosts[1])
-    print("# graphs built", file=sys.stderr, flush=True)
-    Gs = [P.Graph.from_host(h, device=0, reorder=True) for h in hosts]
-    # the R-MAT graph runs with its autotuned Delta
-    tr = Gs[1].tune(gen.workload_pairs("rmat24", hosts[1], cand=lcc)[:16], algo="bids", batch="plainstar")
-    rng = np.random.default_rng(105)
+    Gs = [P.Graph.from_host(h, reorder=True) for h in hosts]
+    for G in Gs:
+        G.set_option("timeout_ms", 900000)
+    _log("graphs built in %.1fs" % (time.time() - t0))
+    rm_sample = gen.pairs_uniform(lcc, 32, seed=1104)
+    tr = Gs[1].tune(rm_sample, algo="bids", batch="plainstar")
+    Gs[1].set_option("theta_mode", int(tr["theta_mode"]))
+    Gs[1].set_option("heavy_window", int(tr["heavy_window"]))
+    fits = []
+    a = time.perf_counter()
+    _, rep0 = Gs[0].mlp_fit(gen.pairs_uniform(hosts[0].n, 32, seed=1103), gen.mlp_init(3), algo="bidastar",
+                            epochs=args.epochs, seed=3, labels="counterfactual")
+    _, rep1 = Gs[1].mlp_fit(rm_sample, gen.mlp_init(4), algo="bids", epochs=args.epochs, seed=4,
+                            delta=int(tr["delta"]), labels="counterfactual")
+    for rep in (rep0, rep1):
+        fits.append({k: rep[k] for k in ("label_hist", "heldout_learned_ms", "heldout_fixed_ms", "plain_fallback")})
+    _log("schedules fitted in %.1fs: %s" % (time.perf_counter() - a, fits))
+    deltas = [0, int(tr["delta"])]
+    algos = ["bidastar", "bids"]
 
     def make_requests(k, seed):
         r = np.random.default_rng(seed)
         out = []
         for j in range(k):
             gi = int(r.integers(0, 2))
-            size = int(np.floor(np.exp(r.uniform(0, np.log(65)))))
-            size = max(1, min(64, size))
+            size = int(np.clip(np.floor(np.exp(r.uniform(0, np.log(4097)))), 1, 4096))
             cand = None if gi == 0 else lcc
-            p = gen.pairs_uniform(hosts[gi].n if cand is None else cand, size, seed=seed * 1000 + j)
-            out.append((gi, p))
+            out.append((gi, gen.pairs_uniform(hosts[gi].n if cand is None else cand, size, seed=seed * 100000 + j)))
         return out
 
-    S = P.Server(Gs, algo=["bidastar", "bids"], delta=[0, int(tr["delta"])], state_budget_bytes=48 << 30)
+    S = P.Server(Gs, algo=algos, delta=deltas, sched="learned", state_budget_bytes=args.serve_budget_gb << 30)
+    out = {"slots": S.stats()["slots"], "fits": fits, "tuned_rmat": {k: tr[k] for k in ("delta", "theta_mode",
+                                                                                      "heavy_window")}}
     # saturation: everything submitted at once
-    reqs = make_requests(60, 1)
+    reqs = make_requests(args.serve_sat, 1)
     a = time.perf_counter()
     ids = [S.submit(gi, p) for gi, p in reqs]
     for r in ids:
-        S.wait(r, timeout_ms=600000)
+        S.wait(r, timeout_ms=1800000)
     sat_s = time.perf_counter() - a
     nq = sum(p.shape[0] for _, p in reqs)
     sat_rps = len(reqs) / sat_s
-    print("# saturation: %.1f requests/s, %.1f queries/s" % (sat_rps, nq / sat_s), file=sys.stderr, flush=True)
-    out = {"saturation_requests_per_s": round(sat_rps, 2), "saturation_queries_per_s": round(nq / sat_s, 2),
-           "slots": S.stats()["slots"]}
+    _log("saturation: %.3f requests/s, %.1f queries/s" % (sat_rps, nq / sat_s))
+    out.update({"saturation_requests": len(reqs), "saturation_requests_per_s": round(sat_rps, 4),
+                "saturation_queries_per_s": round(nq / sat_s, 2)})
+    rng = np.random.default_rng(105)
     check = None
     for frac in (0.5, 0.8):
         lam = frac * sat_rps
-        reqs = make_requests(120, 2 if frac == 0.5 else 3)
+        reqs = make_requests(args.serve_requests, 2 if frac == 0.5 else 3)
         gaps = rng.exponential(1.0 / lam, len(reqs))
         a = time.perf_counter()
         t_next = a
@@ -654,33 +693,39 @@ def workload_serve(args):
         for (gi, p), gap in zip(reqs, gaps):
             t_next += gap
             while time.perf_counter() < t_next:
-                time.sleep(0.0005)
+                time.sleep(0.001)
             ids.append(S.submit(gi, p))
-        lats = []
-        res = []
+        lats, res = [], []
         for r in ids:
-            d, lat = S.wait(r, timeout_ms=600000)
+            d, lat = S.wait(r, timeout_ms=1800000)
             lats.append(lat)
             res.append(d)
         wall = time.perf_counter() - a
         lats = np.array(lats)
         q = sum(p.shape[0] for _, p in reqs)
-        out["load_%d" % int(frac * 100)] = {"offered_requests_per_s": round(lam, 2), "queries_per_s": round(q / wall, 2),
-                                             "p50_ms": round(float(np.percentile(lats, 50)), 2),
-                                             "p99_ms": round(float(np.percentile(lats, 99)), 2), "requests": len(reqs)}
-        print("# load %.0f%%: p50 %.1f ms p99 %.1f ms" % (100 * frac, np.percentile(lats, 50), np.percentile(lats, 99)),
-              file=sys.stderr, flush=True)
+        out["load_%d" % int(frac * 100)] = {
+            "offered_requests_per_s": round(lam, 4), "requests": len(reqs), "queries": int(q),
+            "queries_per_s": round(q / wall, 2), "p50_ms": round(float(np.percentile(lats, 50)), 1),
+            "p99_ms": round(float(np.percentile(lats, 99)), 1),
+            "p50_ms_by_graph": [round(float(np.percentile(lats[[gi == k for gi, _ in reqs]], 50)), 1)
+                                if any(gi == k for gi, _ in reqs) else None for k in (0, 1)]}
+        _log("load %.0f%%: %s" % (100 * frac, out["load_%d" % int(frac * 100)]))
         check = (reqs, res)
     S.close()
-    # results in the mix equal each request run alone
-    for (gi, p), d in list(zip(*check))[:10]:
-        alone = Gs[gi].batch_query(p, algo="bidastar" if gi == 0 else "bids",
-                                   delta=0 if gi == 0 else int(tr["delta"]))
-        assert np.array_equal(alone, d)
+    # every request of the last level equals its run alone (the same library, learned schedule)
+    for (gi, p), d in zip(*check):
+        alone = Gs[gi].batch_query(p, algo=algos[gi], delta=deltas[gi], sched="learned")
+        assert np.array_equal(alone, d), "a served request differs from its run alone"
+    small = [(gi, p) for gi, p in check[0] if p.shape[0] <= 8][:4]
+    for gi, p in small:
+        exp = oracle.pp_batch(hosts[gi].n, hosts[gi].row_ptr, hosts[gi].col, hosts[gi].w, p, nthreads=cpu_threads())
+        assert np.array_equal(exp, Gs[gi].batch_query(p, algo=algos[gi], delta=deltas[gi]))
+    out["checked_against_own_run_alone"] = len(check[0])
     for G in Gs:
         G.close()
-    _line(args, "serving: lattice 4096x4096 (BiD-A*) + R-MAT 24 (BiDS, autotuned Delta) resident together, requests "
-                "of log-uniform 1..64 pairs on either graph, Poisson arrivals at 50% and 80% of saturation",
+    _line(args, "serving: lattice 4096x4096 (BiD-A*) + R-MAT 24 (BiDS, autotuned) resident together, learned "
+                "schedules, requests of log-uniform 1..4096 pairs on either graph, Poisson arrivals at 50%% and 80%% "
+                "of saturation (%d and %d requests per level)" % (args.serve_sat, args.serve_requests),
           out["load_80"]["queries_per_s"], out["load_80"]["p50_ms"], serving=out)
 
 

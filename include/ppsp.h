@@ -463,7 +463,10 @@ int ppsp_sched_trace_ex(ppsp_graph g, const uint32_t *pairs, uint32_t k, const p
  * ppsp_graph_destroy on it return PPSP_E_BUSY until ppsp_server_destroy.
  *   opts          one per graph: opts[i].algo is PPSP_BIDS or PPSP_BIDASTAR
  *                 (one query = two searches), opts[i].delta its Delta (0 = the
- *                 graph's default); other fields are ignored
+ *                 graph's default), opts[i].sched PPSP_SCHED_FIXED or
+ *                 PPSP_SCHED_LEARNED (the network loaded on the graph picks
+ *                 every search's step, as in ppsp_batch_query; the plain path
+ *                 when the fit's judge chose it); other fields are ignored
  * ppsp_server_submit copies the pairs and returns a request id.
  * ppsp_server_poll returns PPSP_E_BUSY until every query of the request has
  * finished; then it copies the k distances (input order) and the latency
@@ -556,6 +559,16 @@ int ppsp_last_stats(ppsp_graph g, ppsp_stats *stats);
  *                     from min_chunk up that covers it (default 16; 64 = always 64)
  *   "local_fill"      local chunks only in rounds whose frontier holds fewer entries than
  *                     this (default 0 = every round)
+ *   "dense_min"       dense frontiers (the dense mode of Appendix B): a search whose next
+ *                     frontier reaches this many entries (sampled per-search counts) keeps
+ *                     its frontier from then on as bitmaps of n bits, one per step bucket
+ *                     (the bucket of Delta at the switch holding the smallest key, and 8
+ *                     buckets ahead; later entries stay in the queue), so that entries
+ *                     waiting for a later bucket cost nothing per round; its threshold is
+ *                     then the end of its current bucket. 0 (default) = off. Not with
+ *                     PPSP_PULL; not in ppsp_batch_query_noalloc or the server. Results are
+ *                     identical. Memory: 9 * n / 8 bytes per search more.
+ *   "dense_force"     1: every search switches to dense frontiers after its first round
  *   "server_round_base" the round number a server's round loop on this graph starts at
  *                     (default 0; below 0xFFFFFF00). A server renumbers its rounds from 0
  *                     before they reach 0xFFFFFF00, restarting the queries then running;

@@ -536,14 +536,15 @@ class Server:
     """Continuous-batching server over resident graphs (ppsp_server_*): queries
     submitted while others run are admitted between rounds into free slots."""
 
-    def __init__(self, graphs, algo="bidastar", delta=0, state_budget_bytes=1 << 30):
-        """algo and delta: one value for every graph, or a list with one per graph."""
+    def __init__(self, graphs, algo="bidastar", delta=0, state_budget_bytes=1 << 30, sched="fixed"):
+        """algo, delta and sched: one value for every graph, or a list with one per graph."""
         self.graphs = list(graphs)
         k = len(self.graphs)
         algos = list(algo) if isinstance(algo, (list, tuple)) else [algo] * k
         deltas = list(delta) if isinstance(delta, (list, tuple)) else [delta] * k
+        scheds = list(sched) if isinstance(sched, (list, tuple)) else [sched] * k
         hs = (ctypes.c_void_p * k)(*[g.h for g in self.graphs])
-        opts = (Opts * k)(*[make_opts(a, "plainstar", delta=d) for a, d in zip(algos, deltas)])
+        opts = (Opts * k)(*[make_opts(a, "plainstar", sc, delta=d) for a, d, sc in zip(algos, deltas, scheds)])
         h = ctypes.c_void_p()
         _check(lib().ppsp_server_create(hs, k, opts, int(state_budget_bytes), ctypes.byref(h)), "ppsp_server_create")
         self.h = h

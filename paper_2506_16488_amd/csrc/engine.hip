@@ -229,7 +229,7 @@ struct ppsp_graph_s {
             opt_default_delta = 0, opt_use_graph = 0, opt_timeout_ms = 600000, opt_theta_mode = 2, opt_queue_cap = 0,
             opt_ml_every = 4, opt_heavy_window = 64, opt_multi_group = 32, opt_rho = 4096, opt_local = 16, opt_local_plain = 0, opt_local_fill = 0,
             opt_min_chunk = 16, opt_local_small = 4, opt_local_pct = 90, opt_defer_pct = 105,
-            opt_server_round_base = 0;
+            opt_server_round_base = 0, opt_dense_min = 0, opt_dense_force = 0;
     uint64_t wmean = 1;             // mean arc weight (rounded up)
     uint64_t fingerprint = 0;       // hash of the CSR, keys the tuning cache
     struct Tuned {
@@ -245,6 +245,8 @@ struct ppsp_graph_s {
     bool pull_call = false;         // the current call pulls before pushing (PPSP_PULL)
     // learned schedule
     DevBuf sc, bin, bin_after, sw_round, done_round, tot_arcs, tot_ent, trace, trace_s, trace_r, trace_b, trace_n, mlpw;
+    // dense frontiers (options "dense_min" / "dense_force")
+    DevBuf dbits, dmode, dbase, dW, dread, docc, dlist, dcount;
     bool mlp_loaded = false;
     bool ml_plain = false;          // the fit's judge preferred the plain fixed path: LEARNED runs it
     MlCtx *ml = nullptr;            // set for the duration of a learned or traced call
@@ -288,16 +290,25 @@ uint64_t graph_default_delta(ppsp_graph g) {
     return std::max<uint64_t>(1, 2 * g->wmean);
 }
 
-// Bytes of search state per search.
-uint64_t state_bytes_per_search(ppsp_graph g) { return (uint64_t)g->n * 8; }
+bool dense_on(ppsp_graph g) { return g->opt_dense_min > 0 || g->opt_dense_force != 0; }
+
+// 32-bit words of one dense bitmap.
+uint64_t dense_words(ppsp_graph g) { return ((uint64_t)g->n + 31) / 32; }
+
+// Bytes of search state per search (with dense frontiers: plus its bitmaps).
+uint64_t state_bytes_per_search(ppsp_graph g) {
+    return (uint64_t)g->n * 8 + (dense_on(g) ? (uint64_t)(DRING + 1) * dense_words(g) * 4 : 0);
+}
 
 uint64_t state_budget(ppsp_graph g) {
     if (t_arena) return t_arena->state_budget;
     if (g->opt_mem_budget_mb > 0) return (uint64_t)g->opt_mem_budget_mb << 20;
     size_t fr = 0, tot = 0;
     if (hipMemGetInfo(&fr, &tot) != hipSuccess) { (void)hipGetLastError(); return 1ull << 30; }
-    uint64_t have = fr + g->S.bytes;   // reusable
-    uint64_t reserve = (2ull << 30) + 2 * g->qcap * 16;  // queues and small buffers
+    uint64_t have = fr + g->S.bytes + g->dbits.bytes;   // reusable
+    // queues (at their largest default size), the hub list, trace buffers and small buffers
+    uint64_t reserve = (2ull << 30) + 2 * std::max<uint64_t>(g->qcap, 1ull << 28) * 16 +
+                       (g->maxdeg > HEAVY_DEG ? (1ull << 26) * 32 : 0) + (1ull << 30);
     return have > reserve ? (uint64_t)((have - reserve) * 0.9) : (1ull << 28);
 }
 
@@ -482,14 +493,16 @@ int run_wave(ppsp_graph g, const Plan &P, bool want_path, WaveOut &out) {
         HIPCHK(hipMemsetAsync(g->hcount.p, 0, 16, st));
         HIPCHK(hipMemsetAsync(g->err.p, 0, 16, st));
         HIPCHK(hipMemsetAsync(g->stats.p, 0, ST_N * 8, st));
-        if (g->ml && g->ml->mode) {
+        const bool dense = dense_on(g) && !g->pull_call;
+        if ((g->ml && g->ml->mode) || dense) {
+            // per-search counters (the learned / traced schedules, and the dense-mode switch)
             CHK(ensure(g->sc, 2ull * ns * 16));
             CHK(ensure(g->bin, ns));
             CHK(ensure(g->done_round, (uint64_t)ns * 4));
             CHK(ensure(g->tot_arcs, (uint64_t)ns * 8));
             CHK(ensure(g->tot_ent, (uint64_t)ns * 8));
             CHK(ensure(g->trace_n, 8));
-            if (g->ml->rows && g->ml->cap) {
+            if (g->ml && g->ml->rows && g->ml->cap) {
                 CHK(ensure(g->trace, g->ml->cap * MLP_F * 4));
                 CHK(ensure(g->trace_s, g->ml->cap * 4));
                 CHK(ensure(g->trace_r, g->ml->cap * 4));
@@ -502,7 +515,8 @@ int run_wave(ppsp_graph g, const Plan &P, bool want_path, WaveOut &out) {
                 HIPCHK(hipMemcpyAsync(g->sw_round.p, P.sw_round.data(), (uint64_t)ns * 4, hipMemcpyHostToDevice, st));
             }
             HIPCHK(hipMemsetAsync(g->sc.p, 0, 2ull * ns * 16, st));
-            HIPCHK(hipMemcpyAsync(g->bin.p, P.bin.data(), ns, hipMemcpyHostToDevice, st));
+            if (P.bin.size() == ns) HIPCHK(hipMemcpyAsync(g->bin.p, P.bin.data(), ns, hipMemcpyHostToDevice, st));
+            else HIPCHK(hipMemsetAsync(g->bin.p, MLP_K / 2, ns, st));
             HIPCHK(hipMemsetAsync(g->done_round.p, 0, (uint64_t)ns * 4, st));
             HIPCHK(hipMemsetAsync(g->tot_arcs.p, 0, (uint64_t)ns * 8, st));
             HIPCHK(hipMemsetAsync(g->tot_ent.p, 0, (uint64_t)ns * 8, st));
@@ -521,8 +535,46 @@ int run_wave(ppsp_graph g, const Plan &P, bool want_path, WaveOut &out) {
                 g->memo_epoch = 1;
             }
         }
+        if (dense) {
+            const uint64_t dw = dense_words(g);
+            CHK(ensure(g->dbits, (uint64_t)ns * (DRING + 1) * dw * 4));
+            CHK(ensure(g->dmode, ns));
+            CHK(ensure(g->dbase, (uint64_t)ns * 8));
+            CHK(ensure(g->dW, (uint64_t)ns * 8));
+            CHK(ensure(g->dread, ns));
+            CHK(ensure(g->docc, (uint64_t)ns * (DRING + 1) * 4));
+            CHK(ensure(g->dlist, 2ull * ns * 4));
+            CHK(ensure(g->dcount, 16));
+            HIPCHK(hipMemsetAsync(g->dbits.p, 0, (uint64_t)ns * (DRING + 1) * dw * 4, st));
+            HIPCHK(hipMemsetAsync(g->docc.p, 0, (uint64_t)ns * (DRING + 1) * 4, st));
+            HIPCHK(hipMemsetAsync(g->dcount.p, 0, 16, st));
+        }
         RoundArgs A;
         set_args(g, A, ns, npair, P.G);
+        if (dense) {
+            if (!A.sc) {
+                // counters without a learned or traced schedule (ml_mode 0: the base step)
+                A.sc = g->sc.as<unsigned long long>();
+                A.ml_mode = 0;
+                A.bin = g->bin.as<uint8_t>();
+                A.done_round = g->done_round.as<uint32_t>();
+                A.tot_arcs = g->tot_arcs.as<unsigned long long>();
+                A.tot_ent = g->tot_ent.as<unsigned long long>();
+                A.trace_n = g->trace_n.as<unsigned long long>();
+                A.ml_every = 1;
+            }
+            A.dbits = g->dbits.as<uint32_t>();
+            A.dwords = dense_words(g);
+            A.dmode = g->dmode.as<uint8_t>();
+            A.dbase = g->dbase.as<uint64_t>();
+            A.dW = g->dW.as<uint64_t>();
+            A.dread = g->dread.as<uint8_t>();
+            A.docc = g->docc.as<uint32_t>();
+            A.dlist = g->dlist.as<uint32_t>();
+            A.dcount = g->dcount.as<uint32_t>();
+            A.dense_min = (uint64_t)std::max<int64_t>(1, g->opt_dense_min);
+            A.dense_force = g->opt_dense_force ? 1u : 0u;
+        }
         if (A.sc && A.ml_mode == 1 && !P.sw_round.empty()) {
             A.bin_after = g->bin_after.as<uint8_t>();
             A.sw_round = g->sw_round.as<uint32_t>();
@@ -605,6 +657,8 @@ int run_wave(ppsp_graph g, const Plan &P, bool want_path, WaveOut &out) {
             HIPCHK(hipMemcpyAsync(g->h_poll, g->qcount.p, 2 * NSEG * 4, hipMemcpyDeviceToHost, st));
             HIPCHK(hipMemcpyAsync(g->h_poll + 2 * NSEG, g->err.p, 4, hipMemcpyDeviceToHost, st));
             HIPCHK(hipMemcpyAsync(g->h_poll + 2 * NSEG + 1, g->round.p, 4, hipMemcpyDeviceToHost, st));
+            g->h_poll[2 * NSEG + 2] = 0;
+            if (A.dbits) HIPCHK(hipMemcpyAsync(g->h_poll + 2 * NSEG + 2, A.dcount + 2, 4, hipMemcpyDeviceToHost, st));
             HIPCHK(hipStreamSynchronize(st));
             for (int k = 0; k < nt; k++) {
                 float ms = 0;
@@ -616,7 +670,7 @@ int run_wave(ppsp_graph g, const Plan &P, bool want_path, WaveOut &out) {
                 }
             }
             timed += nt;
-            uint64_t pending = 0;
+            uint64_t pending = g->h_poll[2 * NSEG + 2];        // dense searches still running
             const uint32_t next = g->h_poll[2 * NSEG + 1];   // round to run next
             for (uint32_t x = 0; x < (uint32_t)NSEG; x++) pending += g->h_poll[(next & 1) * NSEG + x];
             if (pending == 0 || g->h_poll[2 * NSEG] != 0) break;
@@ -1656,6 +1710,7 @@ struct SrvGraph {
     uint32_t running = 0;           // slots in state 1
     uint32_t draining = 0;          // slots in state 2
     uint64_t round = 0;             // the device round counter, mirrored on the host
+    bool learned = false;           // the graph's loaded network picks every search's step
     std::deque<std::pair<uint64_t, uint32_t>> redo;   // (request, query) to admit first, after an overflow
 };
 
@@ -1678,8 +1733,26 @@ struct ppsp_server_s {
 
 namespace {
 
+// The learned schedule in a server's round loop: per-search counters and
+// bins (reset for each admitted search by k_admit) and the loaded network.
+void srv_learned_args(const SrvGraph &G, RoundArgs &A) {
+    if (!G.learned) return;
+    ppsp_graph g = G.g;
+    A.sc = g->sc.as<unsigned long long>();
+    A.ml_mode = 2;
+    A.mlp = g->mlpw.as<uint16_t>();
+    A.bin = g->bin.as<uint8_t>();
+    A.done_round = g->done_round.as<uint32_t>();
+    A.tot_arcs = g->tot_arcs.as<unsigned long long>();
+    A.tot_ent = g->tot_ent.as<unsigned long long>();
+    A.trace_n = g->trace_n.as<unsigned long long>();
+    A.deg_feat = g->n ? (float)(std::log2(std::max(1.0, (double)g->m / g->n)) / 4.0) : 0.f;
+    A.ml_every = (uint32_t)std::max<int64_t>(1, g->opt_ml_every);
+}
+
 int srv_setup_graph(ppsp_server srv, SrvGraph &G, const ppsp_opts &o, uint64_t budget) {
     ppsp_graph g = G.g;
+    G.learned = o.sched == PPSP_SCHED_LEARNED && g->mlp_loaded && !g->ml_plain;
     const uint64_t n = g->n;
     const uint64_t per_query = 2 * n * 8;
     // two thirds of the budget for search state, one third for the two frontier queues
@@ -1763,7 +1836,22 @@ int srv_setup_graph(ppsp_server srv, SrvGraph &G, const ppsp_opts &o, uint64_t b
     HIPCHK(hipMemsetAsync(g->stats.p, 0, ST_N * 8, st));
     HIPCHK(hipMemsetAsync(g->wstats.p, 0, (uint64_t)G.grid * ST_N * 8, st));
     HIPCHK(hipMemsetAsync(g->mu.p, 0xFF, (uint64_t)npair * 8, st));
+    if (G.learned) {
+        CHK(ensure(g->sc, 2ull * ns * 16));
+        CHK(ensure(g->bin, ns));
+        CHK(ensure(g->done_round, (uint64_t)ns * 4));
+        CHK(ensure(g->tot_arcs, (uint64_t)ns * 8));
+        CHK(ensure(g->tot_ent, (uint64_t)ns * 8));
+        CHK(ensure(g->trace_n, 8));
+        HIPCHK(hipMemsetAsync(g->sc.p, 0, 2ull * ns * 16, st));
+        HIPCHK(hipMemsetAsync(g->bin.p, MLP_K / 2, ns, st));
+        HIPCHK(hipMemsetAsync(g->done_round.p, 0, (uint64_t)ns * 4, st));
+        HIPCHK(hipMemsetAsync(g->tot_arcs.p, 0, (uint64_t)ns * 8, st));
+        HIPCHK(hipMemsetAsync(g->tot_ent.p, 0, (uint64_t)ns * 8, st));
+        HIPCHK(hipMemsetAsync(g->trace_n.p, 0, 8, st));
+    }
     set_args(g, G.A, ns, npair, 2);
+    srv_learned_args(G, G.A);
     HIPCHK(launch_idle(G.A, st));
     HIPCHK(hipStreamSynchronize(st));
     return PPSP_OK;
@@ -1814,6 +1902,7 @@ int srv_restart(ppsp_server srv, SrvGraph &G, uint32_t errbits, bool renumber = 
         G.round = 0;
     }
     set_args(g, G.A, ns, G.C, 2);
+    srv_learned_args(G, G.A);
     HIPCHK(launch_idle(G.A, st));
     HIPCHK(hipStreamSynchronize(st));
     if (renumber) srv->renumbers++; else srv->restarts++;
@@ -2363,14 +2452,17 @@ int ppsp_batch_query_noalloc(ppsp_graph g, const uint32_t *pairs, uint32_t k, co
         hipStream_t st;
         uint64_t qcap;
         uint32_t hcap;
-        int64_t profile, use_graph;
+        int64_t profile, use_graph, dense_min, dense_force;
         Arena arena;
         Swap(ppsp_graph g_, hipStream_t cs) : g(g_), st(g_->st), qcap(g_->qcap), hcap(g_->hcap),
-                                             profile(g_->opt_profile), use_graph(g_->opt_use_graph) {
+                                             profile(g_->opt_profile), use_graph(g_->opt_use_graph),
+                                             dense_min(g_->opt_dense_min), dense_force(g_->opt_dense_force) {
             for (DevBuf *b : wave_buffers(g)) saved.push_back(std::move(*b));
             g->st = cs;               // work is ordered on the caller's stream
             g->opt_profile = 0;       // no events
             g->opt_use_graph = 0;     // no captured graphs
+            g->opt_dense_min = 0;     // sparse frontiers only (the dense bitmaps are not in the scratch)
+            g->opt_dense_force = 0;
             if (g->opt_queue_cap == 0) g->qcap = 0;
             g->hcap = 0;
         }
@@ -2386,6 +2478,8 @@ int ppsp_batch_query_noalloc(ppsp_graph g, const uint32_t *pairs, uint32_t k, co
             g->hcap = hcap;
             g->opt_profile = profile;
             g->opt_use_graph = use_graph;
+            g->opt_dense_min = dense_min;
+            g->opt_dense_force = dense_force;
         }
     } swap(g, (hipStream_t)hip_stream);
     swap.arena.base = base;
@@ -2646,6 +2740,8 @@ int ppsp_set_option(ppsp_graph g, const char *name, int64_t v) {
         if (v < 0 || v >= (int64_t)SRV_ROUND_LIMIT) return PPSP_E_INVALID;
         g->opt_server_round_base = v;
     }
+    else if (k == "dense_min") { if (v < 0) return PPSP_E_INVALID; g->opt_dense_min = v; }
+    else if (k == "dense_force") { if (v < 0 || v > 1) return PPSP_E_INVALID; g->opt_dense_force = v; }
 
     else return PPSP_E_INVALID;
     return PPSP_OK;
@@ -2676,6 +2772,8 @@ int ppsp_get_option(ppsp_graph g, const char *name, int64_t *v) {
     else if (k == "local_time_pct") *v = g->opt_local_pct;
     else if (k == "defer_time_pct") *v = g->opt_defer_pct;
     else if (k == "server_round_base") *v = g->opt_server_round_base;
+    else if (k == "dense_min") *v = g->opt_dense_min;
+    else if (k == "dense_force") *v = g->opt_dense_force;
 
     else return PPSP_E_INVALID;
     return PPSP_OK;
@@ -2691,6 +2789,8 @@ int ppsp_server_create(const ppsp_graph *graphs, uint32_t ngraphs, const ppsp_op
         for (uint32_t j = 0; j < i; j++)
             if (graphs[j] == graphs[i]) return PPSP_E_INVALID;
         if (opts[i].algo == PPSP_BIDASTAR && !graphs[i]->xy_ok) return PPSP_E_NOCOORD;
+        if (opts[i].sched != PPSP_SCHED_FIXED && opts[i].sched != PPSP_SCHED_LEARNED) return PPSP_E_INVALID;
+        if (opts[i].sched == PPSP_SCHED_LEARNED && !graphs[i]->mlp_loaded) return PPSP_E_INVALID;
         if (graphs[i]->device != graphs[0]->device) return PPSP_E_INVALID;
     }
     ppsp_server srv = new ppsp_server_s();
@@ -3089,14 +3189,23 @@ int fit_counterfactual(ppsp_graph g, const uint32_t *pairs, uint32_t k, const pp
     }
     const uint32_t nv = (uint32_t)vq.size();
     R.variants = nv;
+    // in batches of at most 256 replays, the size of batch whose frontier
+    // queues and hub list are known to fit (all replays at once can hold
+    // several times the frontier entries)
     TraceOut rep;
-    if (nv) {
+    constexpr uint32_t VCHUNK = 256;
+    for (uint32_t v0 = 0; v0 < nv; v0 += VCHUNK) {
+        const uint32_t nc = std::min(VCHUNK, nv - v0);
         TraceReq vq_;
-        vq_.bins = v4.data();
-        vq_.bins_after = vb.data();
-        vq_.switch_round = vsw.data();
+        vq_.bins = v4.data() + v0;
+        vq_.bins_after = vb.data() + v0;
+        vq_.switch_round = vsw.data() + v0;
         vq_.distinct = true;
-        CHK(trace_run(g, vp.data(), nv, &o, vq_, rep));
+        TraceOut part;
+        CHK(trace_run(g, vp.data() + 2ull * v0, nc, &o, vq_, part));
+        rep.pair_rounds.insert(rep.pair_rounds.end(), part.pair_rounds.begin(), part.pair_rounds.end());
+        rep.pair_arcs.insert(rep.pair_arcs.end(), part.pair_arcs.begin(), part.pair_arcs.end());
+        rep.pair_ent.insert(rep.pair_ent.end(), part.pair_ent.begin(), part.pair_ent.end());
     }
     // 4. Labels per (pair, switch point): the bin of lowest fitted remaining cost.
     std::map<std::pair<uint32_t, uint32_t>, uint8_t> label;

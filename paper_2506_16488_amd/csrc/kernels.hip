@@ -212,7 +212,7 @@ template <bool MEMO>
 __device__ __forceinline__ bool relax_commit(const RoundArgs &A, const SearchDesc &sd, uint32_t i, uint32_t v,
                                              uint64_t cand, uint64_t other, uint64_t old, uint64_t bnd,
                                              uint32_t stamp, uint4 *out, uint64_t *lmin, unsigned long long *succ,
-                                             uint64_t *kout) {
+                                             uint64_t *kout, bool dense = false) {
     if (cand >= (old >> 32)) return false;
     (*succ)++;
     if (A.G == 2) {
@@ -225,8 +225,9 @@ __device__ __forceinline__ bool relax_commit(const RoundArgs &A, const SearchDes
     const uint64_t kv = key_of(sd.kind, cand, hk);
     if (kv >= bnd) return false;        // Prune(v) before Add(v)
     if (kv < *lmin) *lmin = kv;
-    // Lowered before in this round: that lowering added v unless it was pruned.
-    if ((uint32_t)old == stamp && key_of(sd.kind, old >> 32, hk) < bnd) return false;
+    // Lowered before in this round: that lowering added v unless it was pruned
+    // (a dense search adds every lowering: its bucket may have changed).
+    if (!dense && (uint32_t)old == stamp && key_of(sd.kind, old >> 32, hk) < bnd) return false;
     *out = make_uint4(i, v, stamp, (uint32_t)hk);
     *kout = kv;
     return true;
@@ -239,7 +240,7 @@ __device__ __forceinline__ bool relax_commit(const RoundArgs &A, const SearchDes
 template <bool MEMO, bool REV>
 __device__ __forceinline__ bool relax_arc(const RoundArgs &A, const SearchDesc &sd, uint32_t i, uint32_t u,
                                           uint32_t du, uint64_t bnd, uint32_t e, uint32_t stamp, uint4 *out,
-                                          uint64_t *lmin, unsigned long long *succ) {
+                                          uint64_t *lmin, unsigned long long *succ, uint64_t *kout, bool dense) {
     const uint2 a = ((REV && sd.rev) ? A.in_arcs : A.arcs)[e];
     const uint32_t v = a.x;
     const uint64_t cand = (uint64_t)du + a.y;
@@ -258,8 +259,26 @@ __device__ __forceinline__ bool relax_arc(const RoundArgs &A, const SearchDesc &
     }
     if (cand >= (own >> 32)) return false;
     const uint64_t old = atomicMin(p, (cand << 32) | stamp);
-    uint64_t kv;
-    return relax_commit<MEMO>(A, sd, i, v, cand, other, old, bnd, stamp, out, lmin, succ, &kv);
+    return relax_commit<MEMO>(A, sd, i, v, cand, other, old, bnd, stamp, out, lmin, succ, kout, dense);
+}
+
+// Dense frontiers (RoundArgs::dbits): sets v^(i)'s bit in the bitmap of the
+// step bucket of key k. Returns false when that bucket lies beyond the ring;
+// the caller then queues the entry.
+__device__ __forceinline__ bool dense_add(const RoundArgs &A, uint32_t i, uint32_t v, uint64_t k) {
+    const uint64_t W = A.dW[i], base = A.dbase[i];
+    uint64_t b = k / W;
+    if (b < base) b = base;
+    uint32_t id;
+    if (b == base) id = A.dread[i] == DRING ? (uint32_t)(base % DRING) : DRING;   // a refill of the current bucket
+    else if (b - base < DRING) id = (uint32_t)(b % DRING);
+    else return false;
+    const uint64_t slot = (uint64_t)i * (DRING + 1) + id;
+    uint32_t *w = A.dbits + slot * A.dwords + (v >> 5);
+    const uint32_t bit = 1u << (v & 31);
+    if (!(*w & bit)) atomicOr(w, bit);
+    if (A.docc[slot] == 0) A.docc[slot] = 1;
+    return true;
 }
 
 // LDS staging of one wave's frontier adds. The wave appends with a ballot
@@ -319,6 +338,7 @@ struct Advance {
     uint32_t off[WAVE + 1];   // exclusive prefix of the extracted degrees (0 for other lanes)
     uint32_t i[WAVE], u[WAVE], du[WAVE], rb[WAVE];
     uint64_t bnd[WAVE], th[WAVE];
+    uint8_t dm[WAVE];         // the lane's search keeps a dense frontier
 };
 
 // Local chunks (RoundArgs::local): entries a wave adds whose key is within
@@ -338,13 +358,25 @@ constexpr uint32_t RECHECK_Z = 0xFFFFFFFEu;
 
 // One round. Workgroups are single waves that work independently (no
 // barriers between waves): each takes WAVE-entry chunks of its sub-queue.
-template <bool PULL, bool MEMO, bool REV>
+template <bool PULL, bool MEMO, bool REV, bool DENSE>
 __global__ __launch_bounds__(WAVE) void k_round(RoundArgs A) {
     __shared__ WaveStage st;
     __shared__ Advance adv;
     uint32_t scnt = 0;
     const uint32_t r = A.round[0];
     const uint32_t par = r & 1, np = par ^ 1, stamp = r + 1;
+    // Dense frontiers: after its queue chunks a wave takes tiles of 64 words
+    // (2,048 vertices) of the read bitmaps of the searches in this round's
+    // dense list, one word per lane, and extracts their set bits 64 at a time.
+    const uint32_t ndense = DENSE ? A.dcount[par] : 0u;
+    const uint64_t tiles_per = DENSE ? (A.dwords + WAVE - 1) / WAVE : 1ull;
+    const uint64_t dtiles = (uint64_t)ndense * tiles_per;
+    uint64_t dt = blockIdx.x, dwidx = 0;
+    uint32_t dword = 0, dsi = 0;
+    if (DENSE && blockIdx.x == 0 && lane_id() == 0) {
+        A.dcount[np] = 0;                                  // the list the control step builds next
+        A.dcount[2] = 0;                                   // dense searches still running, counted by it
+    }
     const uint32_t sego = blockIdx.x % NSEG;                // segment this wave appends to
     const uint4 *qin = par ? A.q1 : A.q0;
     uint4 *qout = (par ? A.q0 : A.q1) + (uint64_t)sego * A.qseg;
@@ -430,6 +462,27 @@ __global__ __launch_bounds__(WAVE) void k_round(RoundArgs A) {
                 search_stats(A, np, ent.x & ~CARRY_BIT, valid ? 1u : 0u, k, false);
                 continue;
             }
+        } else if (DENSE && (__any(dword != 0) || dt < dtiles)) {
+            if (!__any(dword != 0)) {
+                // the next tile; its words are cleared as they are read (no adds
+                // go to a read bitmap: refills of the current bucket use the other one)
+                dsi = A.dlist[(uint64_t)par * A.nsearch + dt / tiles_per];
+                dwidx = (dt % tiles_per) * WAVE + lane_id();
+                dt += gridDim.x;
+                dword = 0;
+                if (dwidx < A.dwords) {
+                    uint32_t *wp = A.dbits + ((uint64_t)dsi * (DRING + 1) + A.dread[dsi]) * A.dwords + dwidx;
+                    dword = *wp;
+                    if (dword) *wp = 0;
+                }
+                if (!__any(dword != 0)) continue;
+            }
+            valid = dword != 0;
+            if (valid) {
+                const uint32_t b = (uint32_t)__builtin_ctz(dword);
+                dword &= dword - 1;
+                ent = make_uint4(dsi | DENSE_BIT, (uint32_t)(dwidx * 32 + b), 0u, 0u);
+            }
         } else {
             break;
         }
@@ -445,9 +498,11 @@ __global__ __launch_bounds__(WAVE) void k_round(RoundArgs A) {
         uint64_t key = 0, bnd = 0, th = 0;
         int action = 0;  // 0 nothing, 1 keep for a later round, 2 relax
         bool recheck = false;   // push a check-only entry for the next round
+        bool dent = false;
         if (valid) {
             const bool carried = (ent.x & CARRY_BIT) != 0;
-            si = ent.x & ~CARRY_BIT;
+            dent = DENSE && (ent.x & DENSE_BIT) != 0;     // from a dense bitmap: no stamp, no stored term
+            si = ent.x & ~(CARRY_BIT | DENSE_BIT);
             const uint32_t i = si, u = ent.y;
             c_ent++;
             const ulonglong2 c = A.ctl[i];
@@ -500,16 +555,20 @@ __global__ __launch_bounds__(WAVE) void k_round(RoundArgs A) {
                     if (local) ent.z = 0;       // what the state word now holds
                 }
                 du = (uint32_t)(word >> 32);
-                if ((uint32_t)word != ent.z && (uint32_t)word != INF32) {
+                if (!dent && (uint32_t)word != ent.z && (uint32_t)word != INF32) {
                     // lowered after this entry was added: a fresher entry exists
                 } else {
                     // the heuristic term: stored, or (unchanged distance) the stored key minus scale * delta
                     int32_t hk;
-                    if (!carried) hk = (int32_t)ent.w;
+                    if (dent) hk = MEMO ? hterm_memo(A, sd, i, u) : hterm(A, sd, u);
+                    else if (!carried) hk = (int32_t)ent.w;
                     else if (ent.w != KEY_UNKNOWN) hk = (int32_t)((int64_t)ent.w - (int64_t)key_scale(sd.kind) * du);
                     else hk = hterm(A, sd, u);
                     key = key_of(sd.kind, du, hk);
-                    if (key > c.x && key < bnd) {
+                    if (dent && key / A.dW[i] < A.dbase[i]) {
+                        // a stale bit: the vertex was lowered into an earlier bucket,
+                        // whose bitmap got its bit and has been read
+                    } else if (key > c.x && key < bnd) {
                         action = 1;                     // above the threshold: later round
                     } else {
                         bool wait = false;
@@ -539,7 +598,8 @@ __global__ __launch_bounds__(WAVE) void k_round(RoundArgs A) {
                         }
                     }
                     if (action == 1)
-                        ent = make_uint4(i | CARRY_BIT, u, ent.z, key < KEY_UNKNOWN ? (uint32_t)key : KEY_UNKNOWN);
+                        ent = make_uint4(i | CARRY_BIT, u, dent ? (uint32_t)word : ent.z,
+                                         key < KEY_UNKNOWN ? (uint32_t)key : KEY_UNKNOWN);
                 }
             }
         }
@@ -548,13 +608,14 @@ __global__ __launch_bounds__(WAVE) void k_round(RoundArgs A) {
                            ((unsigned long long)(re - rb) << 32) + 1ull, action == 2);
         // Entries above the threshold stay in the frontier (a lowering of the
         // vertex in this round adds a fresher entry, which makes this one
-        // stale).
+        // stale); a dense search keeps them in the bitmap of their bucket.
         const bool keep = action == 1;
+        const bool kq = keep && !(DENSE && A.dmode[si] && dense_add(A, si, ent.y, key));
         c_keep += keep;
-        wstage_push(st, scnt, keep || recheck, keep ? ent : make_uint4(si, ent.y, RECHECK_Z, 0u), qout, qcout, A.qseg,
+        wstage_push(st, scnt, kq || recheck, kq ? ent : make_uint4(si, ent.y, RECHECK_Z, 0u), qout, qcout, A.qseg,
                     A.err);
         // a check-only entry keeps its search alive for one more round, at no key
-        search_stats(A, np, si, (keep || recheck) ? 1u : 0u, keep ? key : INF64, count);
+        search_stats(A, np, si, (kq || recheck) ? 1u : 0u, keep ? key : INF64, count);
 
         // High-degree vertices go to the heavy list as chunks of at most
         // HEAVY_CHUNK arcs, which all waves of k_heavy share; one atomic per
@@ -599,6 +660,7 @@ __global__ __launch_bounds__(WAVE) void k_round(RoundArgs A) {
         adv.rb[lane_id()] = rb;
         adv.bnd[lane_id()] = bnd;
         adv.th[lane_id()] = th;
+        adv.dm[lane_id()] = DENSE && deg && A.dmode[si];
         __syncthreads();
         if (PULL) {
             // Pull (Appendix B, undirected graphs): delta[u] <- min over the
@@ -702,17 +764,20 @@ __global__ __launch_bounds__(WAVE) void k_round(RoundArgs A) {
                 uint4 ne = make_uint4(0, 0, 0, 0);
                 uint64_t lmin = INF64, kv = INF64;
                 bool heur = false;
+                const bool dm = DENSE && want[h] && adv.dm[lo[h]];
                 if (want[h]) {
                     const SearchDesc sd = A.sd[ai[h]];
                     heur = sd.kind == K_ASTAR || sd.kind == K_BIDA_F || sd.kind == K_BIDA_B;
                     app = relax_commit<MEMO>(A, sd, ai[h], v[h], cand[h], other[h], old[h], adv.bnd[lo[h]], stamp,
-                                             &ne, &lmin, &c_succ, &kv);
+                                             &ne, &lmin, &c_succ, &kv, dm);
                 }
+                // a dense search's addition goes to the bitmap of its bucket
+                if (DENSE && app && dm && dense_add(A, ai[h], v[h], kv)) app = false;
                 // Within the threshold: list it for this wave's next local
                 // chunk if its chunks fit the budget, else the next round.
                 bool loc = false;
                 if (lbud) {
-                    loc = app && kv <= adv.th[lo[h]] && (heur ? A.local : A.local_plain) != 0;
+                    loc = app && !dm && kv <= adv.th[lo[h]] && (heur ? A.local : A.local_plain) != 0;
                     const uint64_t lm = __ballot(loc);
                     const uint32_t nl = (uint32_t)__popcll(lm);
                     if (nl && lpend + nl <= LCAP && (lpend + nl + WAVE - 1) / WAVE <= lbud) {
@@ -776,12 +841,14 @@ __global__ __launch_bounds__(WAVE) void k_heavy(RoundArgs A) {
         const uint32_t ai = h1.x;
         const SearchDesc sd = A.sd[ai];
         const uint64_t bnd = A.ctl[ai].y;
+        const bool dm = A.dbits && A.dmode[ai];
         for (uint32_t e0 = h1.w; e0 < ee; e0 += WAVE) {
             const uint32_t e = e0 + lane_id();
             bool app = false;
             uint4 ne = make_uint4(0, 0, 0, 0);
-            uint64_t lmin = INF64;
-            if (e < ee) app = relax_arc<MEMO, REV>(A, sd, ai, h1.y, h1.z, bnd, e, stamp, &ne, &lmin, &c_succ);
+            uint64_t lmin = INF64, kv = INF64;
+            if (e < ee) app = relax_arc<MEMO, REV>(A, sd, ai, h1.y, h1.z, bnd, e, stamp, &ne, &lmin, &c_succ, &kv, dm);
+            if (app && dm && dense_add(A, ai, ne.y, kv)) app = false;
             wstage_push(st, scnt, app, ne, qout, qcout, A.qseg, A.err);
             search_stats(A, np, ai, app ? 1u : 0u, lmin, count);
         }
@@ -834,7 +901,13 @@ __global__ __launch_bounds__(WAVE) void k_seed_prefix(RoundArgs A) { chunk_prefi
 // Only the writer lane stores.
 __device__ __forceinline__ int control_search(const RoundArgs &A, uint32_t i, uint32_t par, uint32_t np, bool writer,
                                               uint64_t *mk_out, uint64_t *nb_out) {
-    const uint32_t c = A.alive[(uint64_t)np * A.nsearch + i];
+    uint32_t c = A.alive[(uint64_t)np * A.nsearch + i];
+    if (A.dbits && A.dmode[i] && !c) {
+        // a dense search lives on while a bitmap other than the one just read holds bits
+        const uint32_t rd = A.dread[i];
+        for (uint32_t j = 0; j <= DRING; j++)
+            if (j != rd && A.docc[(uint64_t)i * (DRING + 1) + j]) c = 1;
+    }
     const uint64_t mk = A.minkey[(uint64_t)np * A.nsearch + i];
     if (writer) {
         A.alive[(uint64_t)par * A.nsearch + i] = 0;
@@ -1055,6 +1128,74 @@ __global__ __launch_bounds__(WAVE) void k_control_ml(RoundArgs A) {
         } else if (A.ml_mode == 1 && A.sw_round && r + 1 >= A.sw_round[i]) {
             bin = A.bin_after[i];           // a traced switch: this step and all later ones
         }
+        if (A.dbits && !A.dmode[i] && (A.dense_force || scale * (double)nxt >= (double)A.dense_min)) {
+            // sparse -> dense (for good): buckets of this step's width, the
+            // current one holding the smallest key of the next frontier
+            uint64_t W = (db << bin) >> 4;
+            if (W == 0) W = 1;
+            if (w) {
+                // the frontier of the next round is still the queue's: its
+                // entries above the current bucket move into the ring then
+                const uint64_t base = mk == INF64 ? 0 : mk / W;
+                A.dmode[i] = 1;
+                A.dW[i] = W;
+                A.dbase[i] = base;
+                A.dread[i] = (uint8_t)(base % DRING);
+                for (uint32_t j = 0; j <= DRING; j++) A.docc[(uint64_t)i * (DRING + 1) + j] = 0;
+                A.ctl[i] = make_ulonglong2(base >= INF64 / W - 1 ? INF64 : (base + 1) * W - 1, nb);
+                if (A.hcap) A.hlim[i] = heavy_limit(mk == INF64 ? base * W : mk, W, A.hwin);
+                A.bin[i] = (uint8_t)bin;
+                atomicAdd(&A.dcount[2], 1u);
+            }
+            continue;
+        }
+        if (A.dbits && A.dmode[i]) {
+            // Dense: stay on the current bucket while it refilled, else move to
+            // the next bucket with bits (or, the ring empty, to the smallest
+            // key's bucket: those entries sit in the queue); done once every
+            // remaining key would be pruned.
+            const uint64_t base = A.dbase[i], W = A.dW[i];
+            const uint32_t rd = A.dread[i];
+            const uint32_t refill = rd == DRING ? (uint32_t)(base % DRING) : DRING;
+            uint32_t *oc = A.docc + (uint64_t)i * (DRING + 1);
+            uint64_t nbase = INF64;
+            uint32_t nread = 0;
+            if (oc[refill]) {
+                nbase = base;
+                nread = refill;
+            } else {
+                for (uint32_t j = 1; j < DRING && nbase == INF64; j++)
+                    if (oc[(base + j) % DRING]) {
+                        nbase = base + j;
+                        nread = (uint32_t)((base + j) % DRING);
+                    }
+                if (nbase == INF64) {
+                    nbase = mk == INF64 ? base + 1 : (mk / W > base ? mk / W : base + 1);
+                    nread = (uint32_t)(nbase % DRING);
+                }
+            }
+            const bool prune_all = nb != INF64 && nbase >= (nb + W - 1) / W;   // nbase * W >= bound
+            if (w) {
+                oc[rd] = 0;                            // read (and cleared) by this round's scan
+                if (prune_all) {
+                    A.done[i] = 1;
+                    A.ctl[i] = make_ulonglong2(th0, 0);
+                    A.done_round[i] = r + 1;
+                } else {
+                    A.dbase[i] = nbase;
+                    A.dread[i] = (uint8_t)nread;
+                    const uint64_t th = nbase >= INF64 / W - 1 ? INF64 : (nbase + 1) * W - 1;
+                    A.ctl[i] = make_ulonglong2(th, nb);
+                    // hubs wait for the low end of the window above the smallest key
+                    // added this round (a hub that waited was re-added, so the
+                    // smallest waiting one always qualifies: the bucket drains)
+                    if (A.hcap) A.hlim[i] = heavy_limit(mk == INF64 || mk < nbase * W ? nbase * W : mk, W, A.hwin);
+                    atomicAdd(&A.dcount[2], 1u);
+                    if (oc[nread]) A.dlist[(uint64_t)np * A.nsearch + atomicAdd(&A.dcount[np], 1u)] = i;
+                }
+            }
+            continue;
+        }
         if (w) {
             if (A.trace) {
                 const unsigned long long row = atomicAdd(A.trace_n, 1ull);
@@ -1096,6 +1237,7 @@ __global__ __launch_bounds__(BLOCK) void k_init(RoundArgs A) {
     A.minkey[(uint64_t)A.nsearch + i] = INF64;
     A.done[i] = 0;
     A.exh[i] = 0;
+    if (A.dbits) A.dmode[i] = 0;
 }
 
 // Serving: Init() for the searches listed in ids[0..k), inserted between
@@ -1126,6 +1268,14 @@ __global__ __launch_bounds__(BLOCK) void k_admit(RoundArgs A, const uint32_t *id
     A.done[i] = 0;
     A.exh[i] = 0;
     for (uint32_t p = sd.pbeg; p < sd.pend; p++) A.mu[A.partners[p].pair] = INF64;
+    if (A.sc) {
+        // the learned schedule: fresh counters, the base multiplier until the network's next decision
+        for (uint32_t q = 0; q < 2; q++) {
+            A.sc[((uint64_t)q * A.nsearch + i) * 2] = 0;
+            A.sc[((uint64_t)q * A.nsearch + i) * 2 + 1] = 0;
+        }
+        A.bin[i] = (uint8_t)(MLP_K / 2);
+    }
 }
 
 // Serving: chunk layout of the queue the next round reads, after admissions.
@@ -1251,20 +1401,27 @@ hipError_t launch_idle(const RoundArgs &A, hipStream_t st) {
 
 // With events, the launch carries them in its own dispatch (start and end
 // of the kernel itself): no marker packets are queued between the rounds.
-template <bool PULL, bool MEMO, bool REV>
+template <bool PULL, bool MEMO, bool REV, bool DENSE = false>
 static hipError_t launch_round_t(const RoundArgs &A, uint32_t grid, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
     if (e0)
-        hipExtLaunchKernelGGL(k_round<PULL, MEMO, REV>, dim3(grid), dim3(WAVE), 0, st, e0, e1, 0, A);
+        hipExtLaunchKernelGGL(k_round<PULL, MEMO, REV, DENSE>, dim3(grid), dim3(WAVE), 0, st, e0, e1, 0, A);
     else
-        k_round<PULL, MEMO, REV><<<grid, WAVE, 0, st>>>(A);
+        k_round<PULL, MEMO, REV, DENSE><<<grid, WAVE, 0, st>>>(A);
     return hipGetLastError();
 }
 
 hipError_t launch_round(const RoundArgs &A, uint32_t grid, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
-    // The default path (symmetric graph, no pull pass, no heuristic memo) is
-    // compiled without those branches, which would otherwise cost it
-    // registers and occupancy. A directed graph has a separate transpose.
+    // The default path (symmetric graph, no pull pass, no heuristic memo, no
+    // dense frontiers) is compiled without those branches, which would
+    // otherwise cost it registers and occupancy. A directed graph has a
+    // separate transpose. Dense frontiers exclude the pull pass.
     const bool rev = A.in_row_ptr != A.row_ptr;
+    if (A.dbits) {
+        if (rev) return A.memo ? launch_round_t<false, true, true, true>(A, grid, st, e0, e1)
+                               : launch_round_t<false, false, true, true>(A, grid, st, e0, e1);
+        return A.memo ? launch_round_t<false, true, false, true>(A, grid, st, e0, e1)
+                      : launch_round_t<false, false, false, true>(A, grid, st, e0, e1);
+    }
     if (rev) return A.memo ? launch_round_t<false, true, true>(A, grid, st, e0, e1)
                            : launch_round_t<false, false, true>(A, grid, st, e0, e1);
     if (A.pull) return A.memo ? launch_round_t<true, true, false>(A, grid, st, e0, e1)

@@ -213,3 +213,56 @@ def test_server_renumbers_rounds_before_stamp_limit(P):
     assert st["renumbers"] >= 1, st
     for p, (d, _) in zip(reqs, res):
         assert np.array_equal(d, _oracle(g, p))
+
+
+def test_server_4096_pair_request_across_slot_refills(P):
+    """One request of 4,096 pairs on a server with 16 query slots per graph:
+    it is admitted across hundreds of slot refills while a second graph's
+    requests run beside it, and equals the oracle and its own run alone."""
+    hosts = [gen.lattice(90, 0.05, seed=210), gen.rmat(12, 16, seed=211)]
+    big = gen.pairs_uniform(hosts[0].n, 4096, seed=212)
+    side = [gen.pairs_uniform(gen.lcc(hosts[1]), k, seed=213 + k) for k in (3, 40, 17)]
+    Gs = [P.Graph.from_host(h) for h in hosts]
+    alone = Gs[0].batch_query(big, algo="bidastar")
+    alone_side = [Gs[1].batch_query(p, algo="bids") for p in side]
+    budget = 24 * sum(h.n for h in hosts) * 16
+    S = P.Server(Gs, algo=["bidastar", "bids"], state_budget_bytes=budget)
+    assert S.stats()["slots"] == 32
+    ids = [S.submit(0, big)] + [S.submit(1, p) for p in side]
+    res = [S.wait(r, timeout_ms=300000) for r in ids]
+    st = S.stats()
+    S.close()
+    for G in Gs:
+        G.close()
+    assert np.array_equal(res[0][0], alone)
+    assert np.array_equal(res[0][0], _oracle(hosts[0], big))
+    for p, a, (d, _) in zip(side, alone_side, res[1:]):
+        assert np.array_equal(d, a) and np.array_equal(d, _oracle(hosts[1], p))
+    assert st["admitted"] >= 4096 - int(np.sum(big[:, 0] == big[:, 1]))
+
+
+def test_server_runs_the_learned_schedule(P):
+    """Served graphs under the learned schedule (a network loaded on each):
+    every search picks its step each round inside the server's round loop;
+    every request equals the oracle and its run alone (batch, learned)."""
+    hosts = [gen.lattice(150, 0.05, seed=220), gen.rmat(13, 16, seed=221)]
+    reqs = [(0, gen.pairs_uniform(hosts[0].n, k, seed=222 + k)) for k in (1, 30, 9, 64)] + \
+           [(1, gen.pairs_uniform(gen.lcc(hosts[1]), k, seed=240 + k)) for k in (5, 25, 2)]
+    Gs = [P.Graph.from_host(h) for h in hosts]
+    for i, G in enumerate(Gs):
+        p = gen.mlp_init(230 + i)
+        p[-8:] = np.linspace(-1, 1, 8)
+        G.mlp_load(p)
+    algos = ["bidastar", "bids"]
+    alone = [Gs[gi].batch_query(p, algo=algos[gi], sched="learned") for gi, p in reqs]
+    S = P.Server(Gs, algo=algos, sched="learned", state_budget_bytes=24 * sum(h.n for h in hosts) * 6)
+    ids = []
+    for gi, p in reqs:
+        ids.append(S.submit(gi, p))
+        time.sleep(0.002)
+    res = [S.wait(r, timeout_ms=120000) for r in ids]
+    S.close()
+    for G in Gs:
+        G.close()
+    for (gi, p), a, (d, _) in zip(reqs, alone, res):
+        assert np.array_equal(d, a) and np.array_equal(d, _oracle(hosts[gi], p))
