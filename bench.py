@@ -296,7 +296,8 @@ def workload_rmat24(args):
     d_auto, ms = time_batch(pairs, args.cmp_steps, sched="autotuned")
     rule = {0: "i * Delta", 1: "end of the smallest key's Delta bucket", 2: "smallest key + Delta - 1"}
     summary("autotuned", ms, G.stats(), delta=int(tr["delta"]), theta_rule=rule.get(int(tr["theta_mode"])),
-            heavy_window=int(tr["heavy_window"]), grid_blocks=int(tr["grid_blocks"]), trials=int(tr["trials"]))
+            heavy_window=int(tr["heavy_window"]), grid_blocks=int(tr["grid_blocks"]), dense_min=int(tr["dense_min"]),
+            dense_ring=int(tr["dense_ring"]), trials=int(tr["trials"]))
     assert np.array_equal(d_auto, d_fixed), "schedules disagree"
 
     # 3. learned: trained on the sample with the tuned setting as its base
@@ -305,6 +306,8 @@ def workload_rmat24(args):
     G.set_option("theta_mode", int(tr["theta_mode"]))
     G.set_option("heavy_window", int(tr["heavy_window"]))
     G.set_option("grid_blocks", int(tr["grid_blocks"]))
+    G.set_option("dense_min", int(tr["dense_min"]))
+    G.set_option("dense_ring", int(tr["dense_ring"]))
     dl = int(tr["delta"])
     a = time.perf_counter()
     params, rep = G.mlp_fit(sample, gen.mlp_init(4), algo="bids", epochs=args.epochs, seed=4, delta=dl,
@@ -315,6 +318,7 @@ def workload_rmat24(args):
         # the trained schedule and its base setting, for counter runs of the same batch (--workload profile)
         np.savez(args.save_schedule, params=params, delta=dl, theta_mode=int(tr["theta_mode"]),
                  heavy_window=int(tr["heavy_window"]), grid_blocks=int(tr["grid_blocks"]),
+                 dense_min=int(tr["dense_min"]), dense_ring=int(tr["dense_ring"]),
                  plain_fallback=int(rep["plain_fallback"]))
 
     def step():
@@ -544,6 +548,8 @@ def workload_profile(args):
         G.set_option("theta_mode", int(s["theta_mode"]))
         G.set_option("heavy_window", int(s["heavy_window"]))
         G.set_option("grid_blocks", int(s["grid_blocks"]))
+        G.set_option("dense_min", int(s["dense_min"]))
+        G.set_option("dense_ring", int(s["dense_ring"]))
         G.mlp_load(s["params"])
         sched = "fixed" if int(s["plain_fallback"]) else "learned"
         run = lambda: G.batch_query(pairs, algo="bids", sched=sched, delta=int(s["delta"]))

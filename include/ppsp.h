@@ -275,6 +275,8 @@ typedef struct {
     uint32_t from_cache;   /* 1 if read from cache_path */
     uint32_t heavy_window; /* chosen "heavy_window" (graphs with vertices of degree > 512) */
     uint32_t local_chunks; /* chosen "local_chunks" (A* and BiD-A*; else the graph's setting) */
+    uint64_t dense_min;    /* chosen "dense_min" (0: sparse frontiers only) */
+    uint32_t dense_ring;   /* chosen "dense_ring" */
 } ppsp_tune_result;
 
 /*
@@ -283,8 +285,9 @@ typedef struct {
  * first swept by doubling from a small start while the time improves (the
  * tuning procedure of Section 6.1), then the hub window ("heavy_window", on
  * graphs with vertices of degree > 512), the threshold rule, Delta between the
- * doublings, the number of round-kernel workgroups and, for A* and BiD-A*, the
- * local-chunk budget ("local_chunks") are refined. The choice
+ * doublings, the number of round-kernel workgroups, dense frontiers ("dense_min"
+ * 2^16 or 2^18, then "dense_ring" 32 and half the step) and, for A* and BiD-A*,
+ * the local-chunk budget ("local_chunks") are refined. The choice
  * is kept in the handle and used by PPSP_SCHED_AUTOTUNED. With cache_path
  * (or NULL) the choice is read from / appended to a text file keyed by a hash
  * of the graph, so a later process can skip the timing. Results of queries are
@@ -562,13 +565,15 @@ int ppsp_last_stats(ppsp_graph g, ppsp_stats *stats);
  *   "dense_min"       dense frontiers (the dense mode of Appendix B): a search whose next
  *                     frontier reaches this many entries (sampled per-search counts) keeps
  *                     its frontier from then on as bitmaps of n bits, one per step bucket
- *                     (the bucket of Delta at the switch holding the smallest key, and 8
- *                     buckets ahead; later entries stay in the queue), so that entries
+ *                     (the bucket of Delta at the switch holding the smallest key, and
+ *                     "dense_ring" buckets ahead; later entries stay in the queue), so that entries
  *                     waiting for a later bucket cost nothing per round; its threshold is
  *                     then the end of its current bucket. 0 (default) = off. Not with
  *                     PPSP_PULL; not in ppsp_batch_query_noalloc or the server. Results are
- *                     identical. Memory: 9 * n / 8 bytes per search more.
+ *                     identical. Memory: (dense_ring + 1) * n / 8 bytes per search more.
  *   "dense_force"     1: every search switches to dense frontiers after its first round
+ *   "dense_ring"      step buckets a dense frontier keeps ahead of its current one (a power
+ *                     of two from 2 to 64, default 16)
  *   "server_round_base" the round number a server's round loop on this graph starts at
  *                     (default 0; below 0xFFFFFF00). A server renumbers its rounds from 0
  *                     before they reach 0xFFFFFF00, restarting the queries then running;

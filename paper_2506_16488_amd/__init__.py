@@ -66,7 +66,8 @@ class Stats(ctypes.Structure):
 class TuneResult(ctypes.Structure):
     _fields_ = [("delta", ctypes.c_uint64), ("theta_mode", ctypes.c_uint32), ("grid_blocks", ctypes.c_uint32),
                 ("ms", ctypes.c_double), ("default_ms", ctypes.c_double), ("trials", ctypes.c_uint32),
-                ("from_cache", ctypes.c_uint32), ("heavy_window", ctypes.c_uint32), ("local_chunks", ctypes.c_uint32)]
+                ("from_cache", ctypes.c_uint32), ("heavy_window", ctypes.c_uint32), ("local_chunks", ctypes.c_uint32),
+                ("dense_min", ctypes.c_uint64), ("dense_ring", ctypes.c_uint32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -229,13 +229,13 @@ struct ppsp_graph_s {
             opt_default_delta = 0, opt_use_graph = 0, opt_timeout_ms = 600000, opt_theta_mode = 2, opt_queue_cap = 0,
             opt_ml_every = 4, opt_heavy_window = 64, opt_multi_group = 32, opt_rho = 4096, opt_local = 16, opt_local_plain = 0, opt_local_fill = 0,
             opt_min_chunk = 16, opt_local_small = 4, opt_local_pct = 90, opt_defer_pct = 105,
-            opt_server_round_base = 0, opt_dense_min = 0, opt_dense_force = 0;
+            opt_server_round_base = 0, opt_dense_min = 0, opt_dense_force = 0, opt_dense_ring = 16;
     uint64_t wmean = 1;             // mean arc weight (rounded up)
     uint64_t fingerprint = 0;       // hash of the CSR, keys the tuning cache
     struct Tuned {
         bool valid = false;
         uint64_t delta = 0;
-        int64_t theta_mode = 2, grid = 0, hwin = 64, local = 16;
+        int64_t theta_mode = 2, grid = 0, hwin = 64, local = 16, dense_min = 0, dense_ring = 16;
         double ms = 0;
     } tuned[5][6];                  // per (algo, batch strategy)
     uint64_t qcap = 0;
@@ -292,12 +292,15 @@ uint64_t graph_default_delta(ppsp_graph g) {
 
 bool dense_on(ppsp_graph g) { return g->opt_dense_min > 0 || g->opt_dense_force != 0; }
 
+// Step buckets of a dense frontier's ring ahead of its current one.
+uint32_t dense_ring(ppsp_graph g) { return (uint32_t)g->opt_dense_ring; }
+
 // 32-bit words of one dense bitmap.
 uint64_t dense_words(ppsp_graph g) { return ((uint64_t)g->n + 31) / 32; }
 
 // Bytes of search state per search (with dense frontiers: plus its bitmaps).
 uint64_t state_bytes_per_search(ppsp_graph g) {
-    return (uint64_t)g->n * 8 + (dense_on(g) ? (uint64_t)(DRING + 1) * dense_words(g) * 4 : 0);
+    return (uint64_t)g->n * 8 + (dense_on(g) ? (uint64_t)(dense_ring(g) + 1) * dense_words(g) * 4 : 0);
 }
 
 uint64_t state_budget(ppsp_graph g) {
@@ -537,16 +540,16 @@ int run_wave(ppsp_graph g, const Plan &P, bool want_path, WaveOut &out) {
         }
         if (dense) {
             const uint64_t dw = dense_words(g);
-            CHK(ensure(g->dbits, (uint64_t)ns * (DRING + 1) * dw * 4));
+            CHK(ensure(g->dbits, (uint64_t)ns * (dense_ring(g) + 1) * dw * 4));
             CHK(ensure(g->dmode, ns));
             CHK(ensure(g->dbase, (uint64_t)ns * 8));
             CHK(ensure(g->dW, (uint64_t)ns * 8));
             CHK(ensure(g->dread, ns));
-            CHK(ensure(g->docc, (uint64_t)ns * (DRING + 1) * 4));
+            CHK(ensure(g->docc, (uint64_t)ns * (dense_ring(g) + 1) * 4));
             CHK(ensure(g->dlist, 2ull * ns * 4));
             CHK(ensure(g->dcount, 16));
-            HIPCHK(hipMemsetAsync(g->dbits.p, 0, (uint64_t)ns * (DRING + 1) * dw * 4, st));
-            HIPCHK(hipMemsetAsync(g->docc.p, 0, (uint64_t)ns * (DRING + 1) * 4, st));
+            HIPCHK(hipMemsetAsync(g->dbits.p, 0, (uint64_t)ns * (dense_ring(g) + 1) * dw * 4, st));
+            HIPCHK(hipMemsetAsync(g->docc.p, 0, (uint64_t)ns * (dense_ring(g) + 1) * 4, st));
             HIPCHK(hipMemsetAsync(g->dcount.p, 0, 16, st));
         }
         RoundArgs A;
@@ -573,6 +576,7 @@ int run_wave(ppsp_graph g, const Plan &P, bool want_path, WaveOut &out) {
             A.dlist = g->dlist.as<uint32_t>();
             A.dcount = g->dcount.as<uint32_t>();
             A.dense_min = (uint64_t)std::max<int64_t>(1, g->opt_dense_min);
+            A.dring = dense_ring(g);
             A.dense_force = g->opt_dense_force ? 1u : 0u;
         }
         if (A.sc && A.ml_mode == 1 && !P.sw_round.empty()) {
@@ -1299,14 +1303,17 @@ int batch_impl(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp_opts 
     // ppsp_tune chose for this algorithm and batch strategy.
     struct Restore {
         ppsp_graph g;
-        int64_t mode, grid, hwin, local;
+        int64_t mode, grid, hwin, local, dmin, dring;
         ~Restore() {
             g->opt_theta_mode = mode;
             g->opt_grid_blocks = grid;
             g->opt_heavy_window = hwin;
             g->opt_local = local;
+            g->opt_dense_min = dmin;
+            g->opt_dense_ring = dring;
         }
-    } restore{g, g->opt_theta_mode, g->opt_grid_blocks, g->opt_heavy_window, g->opt_local};
+    } restore{g, g->opt_theta_mode, g->opt_grid_blocks, g->opt_heavy_window, g->opt_local, g->opt_dense_min,
+              g->opt_dense_ring};
     if (o->sched == PPSP_SCHED_AUTOTUNED && g->tuned[o->algo][o->batch].valid) {
         const auto &t = g->tuned[o->algo][o->batch];
         delta = t.delta;
@@ -1314,6 +1321,8 @@ int batch_impl(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp_opts 
         g->opt_grid_blocks = t.grid;
         g->opt_heavy_window = t.hwin;
         g->opt_local = t.local;
+        g->opt_dense_min = t.dense_min;
+        g->opt_dense_ring = t.dense_ring;
     }
     struct MemoRestore {
         ppsp_graph g;
@@ -2572,29 +2581,33 @@ int ppsp_tune(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp_opts *
     CHK(check_opts(g, opts));
     auto &slot = g->tuned[opts->algo][opts->batch];
     char key[128];
-    snprintf(key, sizeof key, "ppsp-tune-v3 %016llx %u %u", (unsigned long long)g->fingerprint, opts->algo, opts->batch);
+    snprintf(key, sizeof key, "ppsp-tune-v4 %016llx %u %u", (unsigned long long)g->fingerprint, opts->algo, opts->batch);
     if (cache_path) {
         if (FILE *f = fopen(cache_path, "r")) {
             char line[256];
             while (fgets(line, sizeof line, f)) {
                 unsigned long long d;
-                long long mode, grid, hw, lc;
+                long long mode, grid, hw, lc, dm, dr;
                 double ms;
                 if (strncmp(line, key, strlen(key)) == 0 &&
-                    sscanf(line + strlen(key), " %llu %lld %lld %lld %lld %lf", &d, &mode, &grid, &hw, &lc, &ms) == 6) {
+                    sscanf(line + strlen(key), " %llu %lld %lld %lld %lld %lld %lld %lf", &d, &mode, &grid, &hw, &lc, &dm,
+                           &dr, &ms) == 8) {
                     slot.valid = true;
                     slot.delta = d;
                     slot.theta_mode = mode;
                     slot.grid = grid;
                     slot.hwin = hw;
                     slot.local = lc;
+                    slot.dense_min = dm;
+                    slot.dense_ring = dr;
                     slot.ms = ms;
                 }
             }
             fclose(f);
             if (slot.valid) {
                 *out = ppsp_tune_result{slot.delta, (uint32_t)slot.theta_mode, (uint32_t)slot.grid, slot.ms, 0, 0, 1,
-                                        (uint32_t)slot.hwin, (uint32_t)slot.local};
+                                        (uint32_t)slot.hwin, (uint32_t)slot.local, (uint64_t)slot.dense_min,
+                                        (uint32_t)slot.dense_ring};
                 return PPSP_OK;
             }
         }
@@ -2604,15 +2617,17 @@ int ppsp_tune(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp_opts *
     o.sched = PPSP_SCHED_FIXED;
     o.flags &= ~PPSP_WANT_PATH;
     const int64_t mode0 = g->opt_theta_mode, grid0 = g->opt_grid_blocks, hwin0 = g->opt_heavy_window,
-                  local0 = g->opt_local;
+                  local0 = g->opt_local, dmin0 = g->opt_dense_min, dring0 = g->opt_dense_ring;
     uint32_t trials = 0;
-    int64_t best_hw = hwin0, best_local = local0;
+    int64_t best_hw = hwin0, best_local = local0, best_dmin = 0, best_dring = dring0;
     // wall time of one configuration (best of two runs; the first may allocate)
     auto trial = [&](uint64_t delta, int64_t mode, int64_t grid) -> double {
         g->opt_theta_mode = mode;
         g->opt_grid_blocks = grid;
         g->opt_heavy_window = best_hw;
         g->opt_local = best_local;
+        g->opt_dense_min = best_dmin;
+        g->opt_dense_ring = best_dring;
         o.delta = delta;
         double best = 1e300;
         for (int rep = 0; rep < 2; rep++) {
@@ -2660,7 +2675,27 @@ int ppsp_tune(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp_opts *
         const double ms = trial(best_d, best_mode, per_cu * g->cu);
         if (ms < best_ms) { best_ms = ms; best_grid = per_cu * g->cu; }
     }
-    // 3. The local-chunk budget of heuristic searches (the only ones that use it by default).
+    // 3. Dense frontiers (Appendix B): the switch size, then the ring and a
+    //    half-width step, which dense frontiers make cheaper (entries waiting
+    //    for later buckets cost nothing per round)
+    if (!(opts->flags & PPSP_PULL)) {
+        for (int64_t dm : {1ll << 16, 1ll << 18}) {
+            const int64_t keep = best_dmin;
+            best_dmin = dm;
+            const double ms = trial(best_d, best_mode, best_grid);
+            if (ms < best_ms) best_ms = ms; else best_dmin = keep;
+        }
+        if (best_dmin) {
+            const int64_t keep = best_dring;
+            best_dring = 32;
+            double ms = trial(best_d, best_mode, best_grid);
+            if (ms < best_ms) best_ms = ms; else best_dring = keep;
+            const uint64_t dd = std::max<uint64_t>(1, best_d / 2);
+            ms = trial(dd, best_mode, best_grid);
+            if (ms < best_ms) { best_ms = ms; best_d = dd; }
+        }
+    }
+    // 4. The local-chunk budget of heuristic searches (the only ones that use it by default).
     if (is_astar(opts->algo)) {
         const int64_t start = best_local;
         for (int64_t lc : {8, 32}) {
@@ -2675,6 +2710,8 @@ int ppsp_tune(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp_opts *
     g->opt_grid_blocks = grid0;
     g->opt_heavy_window = hwin0;
     g->opt_local = local0;
+    g->opt_dense_min = dmin0;
+    g->opt_dense_ring = dring0;
     if (best_ms >= 1e300) return PPSP_E_DEVICE;
     slot.valid = true;
     slot.delta = best_d;
@@ -2682,16 +2719,19 @@ int ppsp_tune(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp_opts *
     slot.grid = best_grid;
     slot.hwin = best_hw;
     slot.local = best_local;
+    slot.dense_min = best_dmin;
+    slot.dense_ring = best_dring;
     slot.ms = best_ms;
     if (cache_path) {
         if (FILE *f = fopen(cache_path, "a")) {
-            fprintf(f, "%s %llu %lld %lld %lld %lld %.3f\n", key, (unsigned long long)best_d, (long long)best_mode,
-                    (long long)best_grid, (long long)best_hw, (long long)best_local, best_ms);
+            fprintf(f, "%s %llu %lld %lld %lld %lld %lld %lld %.3f\n", key, (unsigned long long)best_d,
+                    (long long)best_mode, (long long)best_grid, (long long)best_hw, (long long)best_local,
+                    (long long)best_dmin, (long long)best_dring, best_ms);
             fclose(f);
         }
     }
     *out = ppsp_tune_result{best_d, (uint32_t)best_mode, (uint32_t)best_grid, best_ms, default_ms, trials, 0,
-                            (uint32_t)best_hw, (uint32_t)best_local};
+                            (uint32_t)best_hw, (uint32_t)best_local, (uint64_t)best_dmin, (uint32_t)best_dring};
     return PPSP_OK;
 }
 
@@ -2742,6 +2782,10 @@ int ppsp_set_option(ppsp_graph g, const char *name, int64_t v) {
     }
     else if (k == "dense_min") { if (v < 0) return PPSP_E_INVALID; g->opt_dense_min = v; }
     else if (k == "dense_force") { if (v < 0 || v > 1) return PPSP_E_INVALID; g->opt_dense_force = v; }
+    else if (k == "dense_ring") {
+        if (v < 2 || v > 64 || (v & (v - 1))) return PPSP_E_INVALID;   // a power of two
+        g->opt_dense_ring = v;
+    }
 
     else return PPSP_E_INVALID;
     return PPSP_OK;
@@ -2774,6 +2818,7 @@ int ppsp_get_option(ppsp_graph g, const char *name, int64_t *v) {
     else if (k == "server_round_base") *v = g->opt_server_round_base;
     else if (k == "dense_min") *v = g->opt_dense_min;
     else if (k == "dense_force") *v = g->opt_dense_force;
+    else if (k == "dense_ring") *v = g->opt_dense_ring;
 
     else return PPSP_E_INVALID;
     return PPSP_OK;

@@ -270,10 +270,10 @@ __device__ __forceinline__ bool dense_add(const RoundArgs &A, uint32_t i, uint32
     uint64_t b = k / W;
     if (b < base) b = base;
     uint32_t id;
-    if (b == base) id = A.dread[i] == DRING ? (uint32_t)(base % DRING) : DRING;   // a refill of the current bucket
-    else if (b - base < DRING) id = (uint32_t)(b % DRING);
+    if (b == base) id = A.dread[i] == A.dring ? (uint32_t)(base & (A.dring - 1)) : A.dring;   // a refill of the current bucket
+    else if (b - base < A.dring) id = (uint32_t)(b & (A.dring - 1));
     else return false;
-    const uint64_t slot = (uint64_t)i * (DRING + 1) + id;
+    const uint64_t slot = (uint64_t)i * (A.dring + 1) + id;
     uint32_t *w = A.dbits + slot * A.dwords + (v >> 5);
     const uint32_t bit = 1u << (v & 31);
     if (!(*w & bit)) atomicOr(w, bit);
@@ -471,7 +471,7 @@ __global__ __launch_bounds__(WAVE) void k_round(RoundArgs A) {
                 dt += gridDim.x;
                 dword = 0;
                 if (dwidx < A.dwords) {
-                    uint32_t *wp = A.dbits + ((uint64_t)dsi * (DRING + 1) + A.dread[dsi]) * A.dwords + dwidx;
+                    uint32_t *wp = A.dbits + ((uint64_t)dsi * (A.dring + 1) + A.dread[dsi]) * A.dwords + dwidx;
                     dword = *wp;
                     if (dword) *wp = 0;
                 }
@@ -905,8 +905,8 @@ __device__ __forceinline__ int control_search(const RoundArgs &A, uint32_t i, ui
     if (A.dbits && A.dmode[i] && !c) {
         // a dense search lives on while a bitmap other than the one just read holds bits
         const uint32_t rd = A.dread[i];
-        for (uint32_t j = 0; j <= DRING; j++)
-            if (j != rd && A.docc[(uint64_t)i * (DRING + 1) + j]) c = 1;
+        for (uint32_t j = 0; j <= A.dring; j++)
+            if (j != rd && A.docc[(uint64_t)i * (A.dring + 1) + j]) c = 1;
     }
     const uint64_t mk = A.minkey[(uint64_t)np * A.nsearch + i];
     if (writer) {
@@ -1140,8 +1140,8 @@ __global__ __launch_bounds__(WAVE) void k_control_ml(RoundArgs A) {
                 A.dmode[i] = 1;
                 A.dW[i] = W;
                 A.dbase[i] = base;
-                A.dread[i] = (uint8_t)(base % DRING);
-                for (uint32_t j = 0; j <= DRING; j++) A.docc[(uint64_t)i * (DRING + 1) + j] = 0;
+                A.dread[i] = (uint8_t)(base & (A.dring - 1));
+                for (uint32_t j = 0; j <= A.dring; j++) A.docc[(uint64_t)i * (A.dring + 1) + j] = 0;
                 A.ctl[i] = make_ulonglong2(base >= INF64 / W - 1 ? INF64 : (base + 1) * W - 1, nb);
                 if (A.hcap) A.hlim[i] = heavy_limit(mk == INF64 ? base * W : mk, W, A.hwin);
                 A.bin[i] = (uint8_t)bin;
@@ -1156,22 +1156,22 @@ __global__ __launch_bounds__(WAVE) void k_control_ml(RoundArgs A) {
             // remaining key would be pruned.
             const uint64_t base = A.dbase[i], W = A.dW[i];
             const uint32_t rd = A.dread[i];
-            const uint32_t refill = rd == DRING ? (uint32_t)(base % DRING) : DRING;
-            uint32_t *oc = A.docc + (uint64_t)i * (DRING + 1);
+            const uint32_t refill = rd == A.dring ? (uint32_t)(base & (A.dring - 1)) : A.dring;
+            uint32_t *oc = A.docc + (uint64_t)i * (A.dring + 1);
             uint64_t nbase = INF64;
             uint32_t nread = 0;
             if (oc[refill]) {
                 nbase = base;
                 nread = refill;
             } else {
-                for (uint32_t j = 1; j < DRING && nbase == INF64; j++)
-                    if (oc[(base + j) % DRING]) {
+                for (uint32_t j = 1; j < A.dring && nbase == INF64; j++)
+                    if (oc[(base + j) & (A.dring - 1)]) {
                         nbase = base + j;
-                        nread = (uint32_t)((base + j) % DRING);
+                        nread = (uint32_t)((base + j) & (A.dring - 1));
                     }
                 if (nbase == INF64) {
                     nbase = mk == INF64 ? base + 1 : (mk / W > base ? mk / W : base + 1);
-                    nread = (uint32_t)(nbase % DRING);
+                    nread = (uint32_t)(nbase & (A.dring - 1));
                 }
             }
             const bool prune_all = nb != INF64 && nbase >= (nb + W - 1) / W;   // nbase * W >= bound

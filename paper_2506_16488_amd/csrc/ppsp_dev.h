@@ -64,7 +64,6 @@ constexpr uint64_t INF64 = ~0ull;
 constexpr uint32_t TARGET_BIT = 0x80000000u;  // Partner.other: a target vertex, not a search
 constexpr uint32_t CARRY_BIT = 0x80000000u;   // frontier entry .x: carried entry, .w holds its key
 constexpr uint32_t DENSE_BIT = 0x40000000u;   // entry .x inside the round kernel: taken from a dense bitmap
-constexpr uint32_t DRING = 8;                  // dense frontier: step buckets ahead of the current one
 constexpr uint32_t KEY_UNKNOWN = 0xFFFFFFFFu; // carried key too large for 32 bits
 constexpr int BLOCK = 256;                     // threads per block (four wave64s)
 constexpr int WAVE = 64;
@@ -226,16 +225,17 @@ struct RoundArgs {
     // from its first step with dense_force), its frontier is kept as bitmaps
     // of n bits, one per step bucket of width dW (key / dW): the current
     // bucket dbase is read from bitmap dread, its refills go to the other of
-    // {dbase % DRING, DRING}, and bucket b < dbase + DRING lives in bitmap
-    // b % DRING. Entries beyond the ring stay in the queue. A search stays
+    // {dbase mod dring, dring}, and bucket b < dbase + dring lives in bitmap
+    // b mod dring (dring a power of two). Entries beyond the ring stay in the queue. A search stays
     // dense until it finishes; its threshold is the end of its current bucket.
-    uint32_t *dbits;           // [nsearch][DRING + 1][dwords]
+    uint32_t *dbits;           // [nsearch][dring + 1][dwords]
+    uint32_t dring;            // step buckets of the ring ahead of the current one
     uint64_t dwords;           // 32-bit words per bitmap
     uint8_t *dmode;            // [nsearch] 1: dense
     uint64_t *dbase;           // [nsearch] current bucket (absolute index)
     uint64_t *dW;              // [nsearch] bucket width (key units)
     uint8_t *dread;            // [nsearch] the bitmap read this round
-    uint32_t *docc;            // [nsearch][DRING + 1] 1: the bitmap may have bits set
+    uint32_t *docc;            // [nsearch][dring + 1] 1: the bitmap may have bits set
     uint32_t *dlist;           // [2][nsearch] by round parity: dense searches whose read bitmap the round scans
     uint32_t *dcount;          // [0], [1] entries of dlist by parity; [2] dense searches still running (host poll)
     uint64_t dense_min;
