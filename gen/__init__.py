@@ -241,11 +241,11 @@ def workload_pairs(name: str, g: Graph, batch: int = 0, cand: Optional[np.ndarra
 
 # ---- learned-schedule network: initial parameters and synthetic rows ----------
 
-MLP_SHAPES = [(64, 12), (64,), (64, 64), (64,), (8, 64), (8,)]
+MLP_SHAPES = [(64, 12), (64,), (64, 64), (64,), (9, 64), (9,)]
 
 
 def mlp_init(seed: int) -> np.ndarray:
-    """Initial parameters of the 12-64-64-8 network (flat float32, W1 b1 W2 b2
+    """Initial parameters of the 12-64-64-9 network (flat float32, W1 b1 W2 b2
     W3 b3): weights uniform in +-sqrt(6 / fan_in), biases 0."""
     rng = np.random.default_rng(seed)
     out = []
@@ -258,15 +258,21 @@ def mlp_init(seed: int) -> np.ndarray:
     return np.concatenate(out).astype(np.float32)
 
 
-def mlp_rows(n: int, seed: int, learnable: bool = True):
-    """n synthetic feature rows in [-1, 1) and labels in 0..7; with
-    learnable=True the label is a fixed function of the first two features."""
+def mlp_rows(n: int, seed: int, learnable: bool = True, modes: bool = False):
+    """n synthetic feature rows in [-1, 1) and labels: a bin in 0..7, plus 8 x
+    a mode label (1 sparse, 2 dense) when modes=True (else 0: none). With
+    learnable=True the bin is a fixed function of the first two features and
+    the mode of the third."""
     rng = np.random.default_rng(seed)
     X = rng.uniform(-1.0, 1.0, (n, 12)).astype(np.float32)
     if learnable:
         y = np.clip(np.floor(4.0 + 2.0 * X[:, 0] + 1.5 * X[:, 1]), 0, 7).astype(np.uint32)
+        m = np.where(X[:, 2] > 0.2, 2, 1)
     else:
         y = rng.integers(0, 8, n).astype(np.uint32)
+        m = rng.integers(1, 3, n)
+    if modes:
+        y = (y + 8 * m).astype(np.uint32)
     return X, y
 
 

@@ -302,23 +302,29 @@ int ppsp_tune(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp_opts *
  * and bdastar-correctness hold for every stepping rule), and the best Delta
  * depends on the query (Section 2's discussion of Delta and rho). With a
  * network loaded on the graph, every search picks its own step each round:
- * a 12 -> 64 -> 64 -> 8 perceptron (ReLU; parameters in bf16 on the device,
+ * a 12 -> 64 -> 64 -> 9 perceptron (ReLU; parameters in bf16 on the device,
  * fp32 arithmetic) maps 12 features of the search's state to one of 8
- * multipliers 2^(b-4) of the base Delta; the threshold rule stays the
- * graph's "theta_mode". Distances are exact whatever the network says.
+ * multipliers 2^(b-4) of the base Delta (the argmax of outputs 0..7); the
+ * threshold rule stays the graph's "theta_mode". Output 8 > 0 switches the
+ * search's frontier to dense bitmaps (the dense mode of Appendix B, option
+ * "dense_learned"). Distances are exact whatever the network says.
  *
  * Parameters: PPSP_MLP_PARAMS floats, row-major, in this order:
- *   W1 [64][12], b1 [64], W2 [64][64], b2 [64], W3 [8][64], b3 [8].
+ *   W1 [64][12], b1 [64], W2 [64][64], b2 [64], W3 [9][64], b3 [9].
  * Features (per search after each round; Delta = its base Delta, in key units):
  *   0 log2(1+extracted)/16  1 log2(1+arcs scanned)/16  2 log2(1+next frontier)/16
  *   3 (log2(1+next) - log2(1+partner's next))/8   4 log2(1+(bound-minkey)/Delta)/16 (0 if bound infinite)
  *   5 bound infinite (1/0)  6 log2(1+(minkey-theta)/Delta)/8  7 log2(1+(theta-root key)/Delta)/16
  *   8 log2(1+heuristic s-t distance/Delta)/16  9 log2(1+round)/16
  *   10 progress (theta-root key)/(bound-root key) in [0,1] (0 if bound infinite)  11 log2(m/n)/4
+ * Labels y (< PPSP_MLP_LABELS): y = bin + 8 * m, bin the best multiplier,
+ * m = 0 (no mode label), 1 (sparse frontier best) or 2 (dense frontier best).
+ * Loss per row: softmax cross-entropy of outputs 0..7 against bin, plus for
+ * m > 0 the logistic loss log(1 + e^z8) - [m = 2] z8.
  *
- * ppsp_mlp_forward  logits [n][8] of feature rows x [n][12] (device `device`).
- * ppsp_mlp_grad     mean cross-entropy loss of labels y (< 8) and its gradient
- *                   with respect to the parameters (grad: PPSP_MLP_PARAMS).
+ * ppsp_mlp_forward  outputs [n][9] of feature rows x [n][12] (device `device`).
+ * ppsp_mlp_grad     mean loss of labels y and its gradient with respect to
+ *                   the parameters (grad: PPSP_MLP_PARAMS).
  * ppsp_mlp_train    Adam (lr, beta 0.9/0.999) on mini-batches of `batch` rows,
  *                   reshuffled every epoch from `seed`; params is the initial
  *                   value on entry and the result on return; losses are the
@@ -354,25 +360,28 @@ int ppsp_tune(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp_opts *
  *                   arcs + c_entry * frontier entries, non-negative
  *                   coefficients) and under replays that follow the base
  *                   multiplier up to one of six decision rounds spread over
- *                   its run and switch to each bin there; the label of a
- *                   (pair, decision round) is the bin of lowest fitted cost
- *                   (c_arc * arcs + c_entry * entries + c_round * rounds
- *                   beyond the best fixed batch's), the base bin unless
- *                   another is at least 1% cheaper, and it holds until the
- *                   next switch point. The rows are the base trajectory's
+ *                   its run and switch there to each bin, with a sparse or a
+ *                   dense frontier; the label of a (pair, decision round) is
+ *                   the bin and mode of lowest fitted cost (c_arc * arcs +
+ *                   c_entry * entries + c_round * rounds beyond the best fixed
+ *                   batch's), the base (bin 4, sparse) unless another is at
+ *                   least 1% cheaper, and it holds until the next switch
+ *                   point. "dense_learned" is set when some label chose dense. The rows are the base trajectory's
  *                   features at those decision rounds. The judge times the
  *                   held-out pairs under the trained network and through
  *                   the plain fixed-Delta path (base Delta, the graph's
  *                   threshold rule); if the plain path is faster,
  *                   PPSP_SCHED_LEARNED runs it on this graph until the next
  *                   ppsp_mlp_load (rep->plain_fallback = 1).
- * Errors: PPSP_E_INVALID (null pointers, label >= 8, a non-finite
+ * Errors: PPSP_E_INVALID (null pointers, label >= PPSP_MLP_LABELS, a non-finite
  * parameter, a strategy other than Plain / Plain* for tracing or fitting),
  * the errors of ppsp_batch_query.
  */
 #define PPSP_MLP_FEATURES 12
 #define PPSP_MLP_BINS 8
-#define PPSP_MLP_PARAMS 5512
+#define PPSP_MLP_OUTPUTS 9
+#define PPSP_MLP_LABELS 24
+#define PPSP_MLP_PARAMS 5577
 
 typedef struct {
     uint32_t label_hist[8];   /* pairs per label bin */
@@ -391,13 +400,14 @@ typedef struct {
     double fixed_ms;          /* sample batch under the fastest constant network tried (best of two) */
     /* label_mode 2 (counterfactual replays; see ppsp_mlp_fit) */
     double c_entry_ns;        /* fitted cost of a frontier entry (ns) */
-    uint32_t variants;        /* replays run (pair x switch round x bin) */
+    uint32_t variants;        /* replays run (pair x switch round x bin x frontier mode) */
     uint32_t heldout;         /* held-out pairs the judge timed */
     double heldout_learned_ms;    /* held-out batch under the trained network (best of two) */
     double heldout_fixed_ms;      /* held-out batch through the plain fixed-Delta path (best of two) */
     double heldout_learned_cost;  /* fitted cost (ms) of the held-out run's rounds, arcs and entries, learned */
     double heldout_fixed_cost;    /* the same for the base multiplier (bin 4) */
     uint32_t plain_fallback;  /* 1: the plain fixed path won the judge: PPSP_SCHED_LEARNED then runs it */
+    uint32_t dense_labels;    /* label_mode 2: (pair, decision round) labels that chose a dense frontier */
 } ppsp_fit_report;
 
 int ppsp_mlp_forward(int device, const float *params, const float *x, uint32_t n, float *logits);
@@ -416,8 +426,9 @@ int ppsp_mlp_fit(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp_opt
  * ppsp_sched_trace_ex: a traced Plain or Plain* batch (exact distances, like
  * any other schedule) with the step schedule given per pair:
  *   bins[k] (NULL: bin 4 = the base Delta) until the step for round
- *   switch_round[k], bins_after[k] from that step on (both NULL: no switch;
- *   the counterfactual replays behind the learned schedule's labels), or,
+ *   switch_round[k], bins_after[k] from that step on (8..15: bin - 8 with the
+ *   frontier switched to dense there; both NULL: no switch; the
+ *   counterfactual replays behind the learned schedule's labels), or,
  *   with network = 1, the bins the loaded network picks (bins ignored; the
  *   rows then record its inputs and choices, for checking its inference).
  *   distinct = 1 keeps equal pairs apart (each pair its own query).
@@ -574,6 +585,8 @@ int ppsp_last_stats(ppsp_graph g, ppsp_stats *stats);
  *   "dense_force"     1: every search switches to dense frontiers after its first round
  *   "dense_ring"      step buckets a dense frontier keeps ahead of its current one (a power
  *                     of two from 2 to 64, default 16)
+ *   "dense_learned"   1: under PPSP_SCHED_LEARNED the network's mode output may switch a
+ *                     search to dense frontiers (set by ppsp_mlp_fit label_mode 2; default 0)
  *   "server_round_base" the round number a server's round loop on this graph starts at
  *                     (default 0; below 0xFFFFFF00). A server renumbers its rounds from 0
  *                     before they reach 0xFFFFFF00, restarting the queries then running;

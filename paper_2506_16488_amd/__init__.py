@@ -89,7 +89,8 @@ class FitReport(ctypes.Structure):
                 ("learned_ms", ctypes.c_double), ("fixed_ms", ctypes.c_double), ("c_entry_ns", ctypes.c_double),
                 ("variants", ctypes.c_uint32), ("heldout", ctypes.c_uint32), ("heldout_learned_ms", ctypes.c_double),
                 ("heldout_fixed_ms", ctypes.c_double), ("heldout_learned_cost", ctypes.c_double),
-                ("heldout_fixed_cost", ctypes.c_double), ("plain_fallback", ctypes.c_uint32)]
+                ("heldout_fixed_cost", ctypes.c_double), ("plain_fallback", ctypes.c_uint32),
+                ("dense_labels", ctypes.c_uint32)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}
@@ -106,7 +107,7 @@ class TraceSpec(ctypes.Structure):
                 ("dist", ctypes.c_void_p)]
 
 
-MLP_FEATURES, MLP_BINS, MLP_PARAMS = 12, 8, 5512
+MLP_FEATURES, MLP_BINS, MLP_OUTPUTS, MLP_PARAMS = 12, 8, 9, 5577
 
 EXPORTS = ["ppsp_graph_create", "ppsp_graph_destroy", "ppsp_query", "ppsp_batch_query", "ppsp_last_stats",
            "ppsp_set_option", "ppsp_get_option", "ppsp_heuristic_fx", "ppsp_status_str", "ppsp_version",
@@ -319,7 +320,7 @@ def mlp_forward(params, X, device=0) -> np.ndarray:
     """Logits [n][8] of feature rows X [n][12] (ppsp_mlp_forward)."""
     p = _f32(params, (MLP_PARAMS,))
     X = _f32(X, (-1, MLP_FEATURES))
-    out = np.empty((X.shape[0], MLP_BINS), np.float32)
+    out = np.empty((X.shape[0], MLP_OUTPUTS), np.float32)
     _check(lib().ppsp_mlp_forward(device, _ptr(p), _ptr(X), X.shape[0], _ptr(out)), "ppsp_mlp_forward")
     return out
 

@@ -184,6 +184,7 @@ struct MlCtx {
     const std::vector<uint8_t> *qbin_after = nullptr;   // trace with a switch: bin from qsw on
     const std::vector<uint32_t> *qsw = nullptr;         // per distinct query: switch round
     bool nodedup = false;                // every input pair is its own query (no merging of equal pairs)
+    bool dense = false;                  // dense frontiers available (switched by traced bins >= 8 or the network)
     bool rows = false;                   // trace: record feature rows
     bool collect = false;                // collect per-query rounds, arcs, entries (and rows)
     uint64_t cap = 0;                    // row capacity
@@ -229,7 +230,8 @@ struct ppsp_graph_s {
             opt_default_delta = 0, opt_use_graph = 0, opt_timeout_ms = 600000, opt_theta_mode = 2, opt_queue_cap = 0,
             opt_ml_every = 4, opt_heavy_window = 64, opt_multi_group = 32, opt_rho = 4096, opt_local = 16, opt_local_plain = 0, opt_local_fill = 0,
             opt_min_chunk = 16, opt_local_small = 4, opt_local_pct = 90, opt_defer_pct = 105,
-            opt_server_round_base = 0, opt_dense_min = 0, opt_dense_force = 0, opt_dense_ring = 16;
+            opt_server_round_base = 0, opt_dense_min = 0, opt_dense_force = 0, opt_dense_ring = 16,
+            opt_dense_learned = 0;
     uint64_t wmean = 1;             // mean arc weight (rounded up)
     uint64_t fingerprint = 0;       // hash of the CSR, keys the tuning cache
     struct Tuned {
@@ -496,7 +498,10 @@ int run_wave(ppsp_graph g, const Plan &P, bool want_path, WaveOut &out) {
         HIPCHK(hipMemsetAsync(g->hcount.p, 0, 16, st));
         HIPCHK(hipMemsetAsync(g->err.p, 0, 16, st));
         HIPCHK(hipMemsetAsync(g->stats.p, 0, ST_N * 8, st));
-        const bool dense = dense_on(g) && !g->pull_call;
+        // dense frontiers: by size (options), or by the learned schedule's mode
+        // output ("dense_learned"), or by traced switches
+        const bool dense = (dense_on(g) || (g->ml && (g->ml->dense || (g->ml->mode == 2 && g->opt_dense_learned)))) &&
+                           !g->pull_call;
         if ((g->ml && g->ml->mode) || dense) {
             // per-search counters (the learned / traced schedules, and the dense-mode switch)
             CHK(ensure(g->sc, 2ull * ns * 16));
@@ -575,7 +580,7 @@ int run_wave(ppsp_graph g, const Plan &P, bool want_path, WaveOut &out) {
             A.docc = g->docc.as<uint32_t>();
             A.dlist = g->dlist.as<uint32_t>();
             A.dcount = g->dcount.as<uint32_t>();
-            A.dense_min = (uint64_t)std::max<int64_t>(1, g->opt_dense_min);
+            A.dense_min = g->opt_dense_min > 0 ? (uint64_t)g->opt_dense_min : ~0ull;
             A.dring = dense_ring(g);
             A.dense_force = g->opt_dense_force ? 1u : 0u;
         }
@@ -1463,7 +1468,7 @@ int trace_run(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp_opts *
     if (o->batch != PPSP_BATCH_PLAIN && o->batch != PPSP_BATCH_PLAINSTAR) return PPSP_E_INVALID;
     if (rq.network && !g->mlp_loaded) return PPSP_E_INVALID;
     for (uint32_t i = 0; i < k; i++)
-        if ((rq.bins && rq.bins[i] >= MLP_K) || (rq.switch_round && (!rq.bins_after || rq.bins_after[i] >= MLP_K)))
+        if ((rq.bins && rq.bins[i] >= MLP_K) || (rq.switch_round && (!rq.bins_after || rq.bins_after[i] >= 2 * MLP_K)))
             return PPSP_E_INVALID;
     // distinct queries in first-occurrence order, as batch_impl forms them
     std::unordered_map<uint64_t, uint32_t> seen;
@@ -1497,6 +1502,7 @@ int trace_run(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp_opts *
     }
     c.nodedup = rq.distinct;
     c.collect = true;
+    for (uint32_t i = 0; i < k && rq.switch_round; i++) c.dense = c.dense || rq.bins_after[i] >= MLP_K;
     c.rows = rq.rows;
     c.cap = rq.rows ? rq.cap : 0;
     c.q_rounds.assign(first.size(), 0);
@@ -1604,7 +1610,7 @@ int mlp_train_impl(int device, float *params, const float *x, const uint32_t *y,
                    uint32_t batch, float lr, uint64_t seed, double *loss_first, double *loss_last) {
     if (!params || (n && (!x || !y)) || batch == 0 || !(lr > 0.f)) return PPSP_E_INVALID;
     for (uint32_t i = 0; i < n; i++)
-        if (y[i] >= (uint32_t)MLP_K) return PPSP_E_INVALID;
+        if (y[i] >= (uint32_t)MLP_Y) return PPSP_E_INVALID;
     MlpDev d;
     CHK(mlp_setup(device, d, params, x, y, n));
     if (loss_first) CHK(mlp_full_grad(d, n, nullptr, loss_first));
@@ -1645,9 +1651,9 @@ int mlp_forward_impl(int device, const float *params, const float *x, uint32_t n
     MlpDev d;
     CHK(mlp_setup(device, d, params, x, nullptr, n));
     if (n == 0) return PPSP_OK;
-    CHK(ensure(d.logits, (uint64_t)n * MLP_K * 4));
+    CHK(ensure(d.logits, (uint64_t)n * MLP_O * 4));
     HIPCHK(launch_mlp_forward(d.P.as<float>(), d.X.as<float>(), n, d.logits.as<float>(), d.st));
-    HIPCHK(hipMemcpyAsync(logits, d.logits.p, (uint64_t)n * MLP_K * 4, hipMemcpyDeviceToHost, d.st));
+    HIPCHK(hipMemcpyAsync(logits, d.logits.p, (uint64_t)n * MLP_O * 4, hipMemcpyDeviceToHost, d.st));
     HIPCHK(hipStreamSynchronize(d.st));
     return PPSP_OK;
 }
@@ -2782,6 +2788,7 @@ int ppsp_set_option(ppsp_graph g, const char *name, int64_t v) {
     }
     else if (k == "dense_min") { if (v < 0) return PPSP_E_INVALID; g->opt_dense_min = v; }
     else if (k == "dense_force") { if (v < 0 || v > 1) return PPSP_E_INVALID; g->opt_dense_force = v; }
+    else if (k == "dense_learned") { if (v < 0 || v > 1) return PPSP_E_INVALID; g->opt_dense_learned = v; }
     else if (k == "dense_ring") {
         if (v < 2 || v > 64 || (v & (v - 1))) return PPSP_E_INVALID;   // a power of two
         g->opt_dense_ring = v;
@@ -2818,6 +2825,7 @@ int ppsp_get_option(ppsp_graph g, const char *name, int64_t *v) {
     else if (k == "server_round_base") *v = g->opt_server_round_base;
     else if (k == "dense_min") *v = g->opt_dense_min;
     else if (k == "dense_force") *v = g->opt_dense_force;
+    else if (k == "dense_learned") *v = g->opt_dense_learned;
     else if (k == "dense_ring") *v = g->opt_dense_ring;
 
     else return PPSP_E_INVALID;
@@ -2962,7 +2970,7 @@ int ppsp_mlp_grad(int device, const float *params, const float *x, const uint32_
                   double *loss) {
     if (!params || (n && (!x || !y)) || !grad) return PPSP_E_INVALID;
     for (uint32_t i = 0; i < n; i++)
-        if (y[i] >= (uint32_t)MLP_K) return PPSP_E_INVALID;
+        if (y[i] >= (uint32_t)MLP_Y) return PPSP_E_INVALID;
     MlpDev d;
     CHK(mlp_setup(device, d, params, x, y, n));
     return mlp_full_grad(d, n, grad, loss);
@@ -3209,8 +3217,10 @@ int fit_counterfactual(ppsp_graph g, const uint32_t *pairs, uint32_t k, const pp
     dq.cap = 1ull << 22;
     TraceOut base;
     CHK(trace_run(g, pairs, kt, &o, dq, base));
-    // 3. Replays: the base bin until a decision round, then each bin to the end.
+    // 3. Replays: the base bin until a decision round, then each bin to the
+    //    end, with a sparse frontier and (bins 8..15) switched to dense there.
     constexpr int NPOINT = 6;
+    constexpr uint32_t NVAR = 2 * MLP_K;
     std::vector<uint32_t> vp, vsw, vq, vr;
     std::vector<uint8_t> vb, v4;
     std::vector<std::vector<uint32_t>> points(kt);
@@ -3221,7 +3231,7 @@ int fit_counterfactual(ppsp_graph g, const uint32_t *pairs, uint32_t k, const pp
             const uint32_t r = (uint32_t)((uint64_t)j * Rq / NPOINT) / every * every;   // a decision round
             if (r >= Rq || (!points[q].empty() && points[q].back() == r)) continue;
             points[q].push_back(r);
-            for (uint32_t b = 0; b < (uint32_t)MLP_K; b++) {
+            for (uint32_t b = 0; b < NVAR; b++) {
                 vp.push_back(pairs[2 * q]);
                 vp.push_back(pairs[2 * q + 1]);
                 vsw.push_back(r + 1);            // the step chosen after round r runs bin b
@@ -3252,21 +3262,27 @@ int fit_counterfactual(ppsp_graph g, const uint32_t *pairs, uint32_t k, const pp
         rep.pair_arcs.insert(rep.pair_arcs.end(), part.pair_arcs.begin(), part.pair_arcs.end());
         rep.pair_ent.insert(rep.pair_ent.end(), part.pair_ent.begin(), part.pair_ent.end());
     }
-    // 4. Labels per (pair, switch point): the bin of lowest fitted remaining cost.
+    // 4. Labels per (pair, switch point): the bin and frontier mode of lowest
+    //    fitted remaining cost (the base, sparse bin 4, unless another is at
+    //    least 1% cheaper), as y = bin + 8 * (1 sparse | 2 dense).
     std::map<std::pair<uint32_t, uint32_t>, uint8_t> label;
-    for (uint32_t v0 = 0; v0 < nv; v0 += MLP_K) {
-        double cost[MLP_K];
-        for (uint32_t b = 0; b < (uint32_t)MLP_K; b++) {
+    uint32_t dense_labels = 0;
+    for (uint32_t v0 = 0; v0 < nv; v0 += NVAR) {
+        double cost[NVAR];
+        for (uint32_t b = 0; b < NVAR; b++) {
             const uint32_t v = v0 + b;
             cost[b] = ca * (double)rep.pair_arcs[v] + ce * (double)rep.pair_ent[v] +
                       cr * std::max(0.0, (double)rep.pair_rounds[v] - Rstar);
         }
         uint32_t lb = MLP_K / 2;
-        for (uint32_t b = 0; b < (uint32_t)MLP_K; b++)
+        for (uint32_t b = 0; b < NVAR; b++)
             if (cost[b] < cost[lb] && cost[b] < cost[MLP_K / 2] * 0.99) lb = b;
-        label[{vq[v0], vr[v0]}] = (uint8_t)lb;
-        R.label_hist[lb]++;
+        const bool dn = lb >= (uint32_t)MLP_K;
+        label[{vq[v0], vr[v0]}] = (uint8_t)((lb & (MLP_K - 1)) + MLP_K * (dn ? 2 : 1));
+        R.label_hist[lb & (MLP_K - 1)]++;
+        dense_labels += dn;
     }
+    R.dense_labels = dense_labels;
     // rows: the base trajectory's decision rounds, each labelled by the switch
     // point at or before it
     std::vector<float> X;
@@ -3290,19 +3306,24 @@ int fit_counterfactual(ppsp_graph g, const uint32_t *pairs, uint32_t k, const pp
                            std::min<uint32_t>(256, (uint32_t)Y.size()), 2e-3f, seed, &R.loss_first, &R.loss_last));
     R.train_ms = wall_ms_since(t1);
     if (!Y.empty()) {
-        std::vector<float> lg((uint64_t)Y.size() * MLP_K);
+        // a row is right when its bin and (where labelled) its mode are
+        std::vector<float> lg((uint64_t)Y.size() * MLP_O);
         CHK(mlp_forward_impl(g->device, params_out, X.data(), (uint32_t)Y.size(), lg.data()));
         uint64_t hit = 0;
         for (size_t r = 0; r < Y.size(); r++) {
             uint32_t bb = 0;
-            for (uint32_t b = 1; b < (uint32_t)MLP_K; b++) if (lg[r * MLP_K + b] > lg[r * MLP_K + bb]) bb = b;
-            hit += bb == Y[r];
+            for (uint32_t b = 1; b < (uint32_t)MLP_K; b++) if (lg[r * MLP_O + b] > lg[r * MLP_O + bb]) bb = b;
+            const uint32_t m = Y[r] / MLP_K;
+            const bool mode_ok = m == 0 || ((lg[r * MLP_O + MLP_K] > 0.f) == (m == 2));
+            hit += bb == Y[r] % MLP_K && mode_ok;
         }
         R.train_acc = (double)hit / Y.size();
     }
     // 6. The judge, on held-out pairs: the trained network against the plain
-    //    fixed-Delta path (base Delta, the graph's threshold rule).
+    //    fixed-Delta path (base Delta, the graph's threshold rule). The
+    //    network's mode output is used when some label asked for a dense frontier.
     CHK(mlp_load_impl(g, params_out));
+    g->opt_dense_learned = dense_labels > 0 ? 1 : 0;
     R.heldout = hk;
     std::vector<uint64_t> dd(hk);
     ppsp_opts lo = o;
@@ -3413,13 +3434,13 @@ int ppsp_mlp_fit(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp_opt
                        &R.loss_first, &R.loss_last));
     R.train_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     // 4. Training accuracy and loading.
-    std::vector<float> lg((uint64_t)Y.size() * MLP_K);
+    std::vector<float> lg((uint64_t)Y.size() * MLP_O);
     CHK(mlp_forward_impl(g->device, params_out, X.data(), (uint32_t)Y.size(), lg.data()));
     uint64_t hit = 0;
     for (size_t r = 0; r < Y.size(); r++) {
         uint32_t best = 0;
         for (uint32_t b = 1; b < (uint32_t)MLP_K; b++)
-            if (lg[r * MLP_K + b] > lg[r * MLP_K + best]) best = b;
+            if (lg[r * MLP_O + b] > lg[r * MLP_O + best]) best = b;
         hit += best == Y[r];
     }
     R.train_acc = Y.empty() ? 0.0 : (double)hit / Y.size();
@@ -3431,7 +3452,7 @@ int ppsp_mlp_fit(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp_opt
     const std::vector<float> trained(params_out, params_out + MLP_NPARAM);
     auto constant_net = [](uint32_t b) {
         std::vector<float> p(MLP_NPARAM, 0.f);
-        p[MLP_NPARAM - MLP_K + b] = 1.f;   // output bias: the logits are constant, argmax b
+        p[MLP_B3 + b] = 1.f;   // output bias: the logits are constant, argmax b (mode logit 0: sparse)
         return p;
     };
     ppsp_opts lo = *opts;

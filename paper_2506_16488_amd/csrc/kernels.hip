@@ -1116,19 +1116,23 @@ __global__ __launch_bounds__(WAVE) void k_control_ml(RoundArgs A) {
             const SearchDesc sd = A.sd[i];
             ml_features(A, i, sd, r, par, c0, nxt, scale, th0, mk, nb, db, bin, f);
         }
+        bool want_dense = false;
         if (net) {
-            float z1, h1, z2, h2, lg[MLP_K];
+            float z1, h1, z2, h2, lg[MLP_O];
             mlp_forward(L, f, z1, h1, z2, h2, lg);
             bin = mlp_argmax(lg);
+            want_dense = lg[MLP_K] > 0.f;        // the mode output: make this search's frontier dense
         } else if (A.ml_mode == 3) {
             // rho-stepping style: steer the next frontier towards rho entries
             const double nx = scale * (double)nxt;
             if (nx > 2.0 * A.rho && bin > 0) bin--;
             else if (nx < 0.5 * A.rho && bin < (uint32_t)MLP_K - 1) bin++;
         } else if (A.ml_mode == 1 && A.sw_round && r + 1 >= A.sw_round[i]) {
-            bin = A.bin_after[i];           // a traced switch: this step and all later ones
+            // a traced switch: this step and all later ones; bins 8..15 also make the frontier dense
+            bin = A.bin_after[i] & (MLP_K - 1);
+            want_dense = A.bin_after[i] >= MLP_K;
         }
-        if (A.dbits && !A.dmode[i] && (A.dense_force || scale * (double)nxt >= (double)A.dense_min)) {
+        if (A.dbits && !A.dmode[i] && (A.dense_force || want_dense || scale * (double)nxt >= (double)A.dense_min)) {
             // sparse -> dense (for good): buckets of this step's width, the
             // current one holding the smallest key of the next frontier
             uint64_t W = (db << bin) >> 4;

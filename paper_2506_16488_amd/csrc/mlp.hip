@@ -1,5 +1,5 @@
 // Training kernels of the learned step schedule (forward, backward and Adam
-// for the 12 -> 64 -> 64 -> 8 network of mlp_dev.h), and batched inference
+// for the 12 -> 64 -> 64 -> 9 network of mlp_dev.h), and batched inference
 // for tests.
 //
 // k_mlp_grad: one wave per workgroup; each wave takes a contiguous slice of
@@ -20,18 +20,18 @@ __global__ __launch_bounds__(MLP_H) void k_mlp_forward(const float *P, const flo
         float x[MLP_F];
 #pragma unroll
         for (int i = 0; i < MLP_F; i++) x[i] = X[(uint64_t)s * MLP_F + i];
-        float z1, h1, z2, h2, lg[MLP_K];
+        float z1, h1, z2, h2, lg[MLP_O];
         mlp_forward(L, x, z1, h1, z2, h2, lg);
-        if (__lane_id() < (uint32_t)MLP_K) {
+        if (__lane_id() < (uint32_t)MLP_O) {
             float v = lg[0];
 #pragma unroll
-            for (int b = 1; b < MLP_K; b++) if (__lane_id() == (uint32_t)b) v = lg[b];
-            logits[(uint64_t)s * MLP_K + __lane_id()] = v;
+            for (int b = 1; b < MLP_O; b++) if (__lane_id() == (uint32_t)b) v = lg[b];
+            logits[(uint64_t)s * MLP_O + __lane_id()] = v;
         }
     }
 }
 
-// Gradient of scale * sum of cross-entropy losses over samples
+// Gradient of scale * sum of the row losses (mlp_dev.h) over samples
 // idx[beg + w*per .. beg + (w+1)*per) (clipped to end) for wave w.
 __global__ __launch_bounds__(MLP_H) void k_mlp_grad(const float *P, const float *X, const uint32_t *Y,
                                                     const uint32_t *idx, uint32_t beg, uint32_t end, uint32_t per,
@@ -42,13 +42,13 @@ __global__ __launch_bounds__(MLP_H) void k_mlp_grad(const float *P, const float 
     __syncthreads();
     MlpLane L;
     mlp_load_lane(P, L);
-    float g1[MLP_F], gb1 = 0.f, g2[MLP_H], gb2 = 0.f, g3[MLP_K], gb3[MLP_K];
+    float g1[MLP_F], gb1 = 0.f, g2[MLP_H], gb2 = 0.f, g3[MLP_O], gb3[MLP_O];
 #pragma unroll
     for (int i = 0; i < MLP_F; i++) g1[i] = 0.f;
 #pragma unroll
     for (int k = 0; k < MLP_H; k++) g2[k] = 0.f;
 #pragma unroll
-    for (int b = 0; b < MLP_K; b++) { g3[b] = 0.f; gb3[b] = 0.f; }
+    for (int b = 0; b < MLP_O; b++) { g3[b] = 0.f; gb3[b] = 0.f; }
     double lsum = 0.0;
     const uint64_t s0 = (uint64_t)beg + (uint64_t)blockIdx.x * per;
     const uint64_t s1 = s0 + per < end ? s0 + per : end;
@@ -57,8 +57,9 @@ __global__ __launch_bounds__(MLP_H) void k_mlp_grad(const float *P, const float 
         float x[MLP_F];
 #pragma unroll
         for (int i = 0; i < MLP_F; i++) x[i] = X[(uint64_t)s * MLP_F + i];
-        const uint32_t y = Y[s];
-        float z1, h1, z2, h2, lg[MLP_K];
+        const uint32_t yy = Y[s];
+        const uint32_t y = yy % MLP_K, m = yy / MLP_K;   // bin label, mode label (0: none, 1 sparse, 2 dense)
+        float z1, h1, z2, h2, lg[MLP_O];
         mlp_forward(L, x, z1, h1, z2, h2, lg);
         // softmax cross-entropy
         float mx = lg[0];
@@ -71,13 +72,21 @@ __global__ __launch_bounds__(MLP_H) void k_mlp_grad(const float *P, const float 
             if ((uint32_t)b == y) ly = lg[b];
         }
         lsum += (double)(logf(den) + mx - ly);
-        float dl[MLP_K];
+        float dl[MLP_O];
 #pragma unroll
         for (int b = 0; b < MLP_K; b++) dl[b] = scale * (expf(lg[b] - mx) / den - ((uint32_t)b == y ? 1.f : 0.f));
+        dl[MLP_K] = 0.f;
+        if (m) {
+            // logistic loss of the mode logit z against t = (m == 2):
+            // log(1 + e^z) - t z, computed without overflow; its derivative is sigmoid(z) - t
+            const float z = lg[MLP_K], t = m == 2 ? 1.f : 0.f;
+            lsum += (double)(fmaxf(z, 0.f) + log1pf(expf(-fabsf(z))) - t * z);
+            dl[MLP_K] = scale * (1.f / (1.f + expf(-z)) - t);
+        }
         // layer 3
         float dh2 = 0.f;
 #pragma unroll
-        for (int b = 0; b < MLP_K; b++) {
+        for (int b = 0; b < MLP_O; b++) {
             g3[b] = fmaf(dl[b], h2, g3[b]);
             gb3[b] += dl[b];
             dh2 = fmaf(L.w3[b], dl[b], dh2);
@@ -104,11 +113,11 @@ __global__ __launch_bounds__(MLP_H) void k_mlp_grad(const float *P, const float 
     for (int k = 0; k < MLP_H; k++) out[MLP_W2 + j * MLP_H + k] = g2[k];
     out[MLP_B2 + j] = gb2;
 #pragma unroll
-    for (int b = 0; b < MLP_K; b++) out[MLP_W3 + b * MLP_H + j] = g3[b];
-    if (j < (uint32_t)MLP_K) {
+    for (int b = 0; b < MLP_O; b++) out[MLP_W3 + b * MLP_H + j] = g3[b];
+    if (j < (uint32_t)MLP_O) {
         float v = gb3[0];
 #pragma unroll
-        for (int b = 1; b < MLP_K; b++) if (j == (uint32_t)b) v = gb3[b];
+        for (int b = 1; b < MLP_O; b++) if (j == (uint32_t)b) v = gb3[b];
         out[MLP_B3 + j] = v;
     }
     if (j == 0) loss[blockIdx.x] = lsum;

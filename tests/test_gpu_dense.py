@@ -117,7 +117,7 @@ def test_dense_with_learned_schedule(P):
     exp = _exp(g, pairs)
     G = P.Graph.from_host(g)
     p = gen.mlp_init(182)
-    p[-8:] = np.linspace(-1, 1, 8)
+    p[-9:-1] = np.linspace(-1, 1, 8)
     G.mlp_load(p)
     G.set_option("timeout_ms", 60000)
     G.set_option("dense_min", 32)

@@ -30,7 +30,7 @@ def test_graph_replay_lattice(P, rps):
     G = P.Graph.from_host(g)
     G.set_option("rounds_per_sync", rps)
     p = gen.mlp_init(122)
-    p[-8:] = np.linspace(-1, 1, 8)
+    p[-9:-1] = np.linspace(-1, 1, 8)
     G.mlp_load(p)
     for use in (0, 1):
         G.set_option("use_graph", use)

@@ -33,13 +33,14 @@ def test_forward_matches_fp64_reference(P):
         got = P.mlp_forward(p, X)
         exp = mlp.forward(p.astype(np.float64), X)
         assert np.max(np.abs(got - exp)) <= 1e-5 * (1 + np.max(np.abs(exp))), seed
-    assert P.mlp_forward(_params(3), np.zeros((0, 12), np.float32)).shape == (0, 8)
+    assert P.mlp_forward(_params(3), np.zeros((0, 12), np.float32)).shape == (0, 9)
 
 
 @pytest.mark.parametrize("n", [1, 37, 5000])
 def test_gradient_matches_fp64_reference(P, n):
     p = _params(4)
-    X, y = gen.mlp_rows(n, 20 + n, learnable=False)
+    X, y = gen.mlp_rows(n, 20 + n, learnable=False, modes=True)
+    y[::3] %= 8                                              # some rows without a mode label
     L, g = P.mlp_grad(p, X, y)
     Le, ge = mlp.grad(p.astype(np.float64), X, y)
     assert abs(L - Le) <= 1e-5 * (1 + abs(Le))
@@ -65,27 +66,31 @@ def test_adam_step_matches_reference(P):
 
 
 def test_training_learns_a_rule(P):
-    X, y = gen.mlp_rows(20000, 40, learnable=True)
+    X, y = gen.mlp_rows(20000, 40, learnable=True, modes=True)
     p, l0, l1 = P.mlp_train(gen.mlp_init(41), X, y, epochs=15, batch=256, lr=3e-3, seed=42)
     assert l1 < 0.5 * l0, (l0, l1)
-    acc = np.mean(np.argmax(P.mlp_forward(p, X), axis=1) == y)
+    z = P.mlp_forward(p, X)
+    acc = np.mean(np.argmax(z[:, :8], axis=1) == y % 8)
     assert acc > 0.85, acc
-    Xt, yt = gen.mlp_rows(4000, 43, learnable=True)
-    assert np.mean(np.argmax(mlp.forward(p.astype(np.float64), Xt), axis=1) == yt) > 0.8
+    assert np.mean((z[:, 8] > 0) == (y // 8 == 2)) > 0.9                  # the mode output learned too
+    Xt, yt = gen.mlp_rows(4000, 43, learnable=True, modes=True)
+    zt = mlp.forward(p.astype(np.float64), Xt)
+    assert np.mean(np.argmax(zt[:, :8], axis=1) == yt % 8) > 0.8
     # same seed, same result
     p2, _, _ = P.mlp_train(gen.mlp_init(41), X, y, epochs=15, batch=256, lr=3e-3, seed=42)
     assert np.array_equal(p, p2)
 
 
-def _bias_only(b):
-    """A network that always picks bin b."""
+def _bias_only(b, dense=False):
+    """A network that always picks bin b (and a dense frontier if asked)."""
     p = np.zeros(P_PARAMS, np.float32)
-    p[-8:] = -5.0
-    p[-8 + b] = 5.0
+    p[-9:-1] = -5.0
+    p[-9 + b] = 5.0
+    p[-1] = 5.0 if dense else -5.0
     return p
 
 
-P_PARAMS = 5512
+P_PARAMS = 5577
 
 
 def test_learned_schedule_is_exact(P):
@@ -186,7 +191,7 @@ def _check_judge(rep, params):
         assert rep["learned_ms"] <= rep["fixed_ms"]
     else:
         assert rep["fixed_ms"] < rep["learned_ms"]
-        assert np.count_nonzero(params) == 1 and params[-8 + fb] == 1.0
+        assert np.count_nonzero(params) == 1 and params[-9 + fb] == 1.0
 
 
 def test_constant_network_is_exact(P):
@@ -198,7 +203,7 @@ def test_constant_network_is_exact(P):
     G = P.Graph.from_host(g)
     for b in (0, 4, 7):
         p = np.zeros(P.MLP_PARAMS, np.float32)
-        p[-8 + b] = 1.0
+        p[-9 + b] = 1.0
         G.mlp_load(p)
         for algo in ("bidastar", "bids"):
             assert np.array_equal(G.batch_query(test, algo=algo, sched="learned"), exp), (b, algo)
@@ -232,7 +237,7 @@ def test_in_round_inference_matches_reference(P):
         assert np.array_equal(tr["dist"], exp)
         n = len(tr["bin"])
         assert tr["nrows"] == n > 100
-        z = mlp.forward(_bf16(p).astype(np.float64), tr["feat"].astype(np.float64))
+        z = mlp.forward(_bf16(p).astype(np.float64), tr["feat"].astype(np.float64))[:, :8]
         top = np.sort(z, axis=1)
         clear = top[:, -1] - top[:, -2] > 1e-3 * (1 + np.abs(top[:, -1]))
         assert clear.mean() > 0.9, clear.mean()
@@ -288,8 +293,9 @@ def test_counterfactual_fit_on_rmat_gains(P):
     params, rep = G.mlp_fit(sample, gen.mlp_init(133), algo="bids", epochs=30, seed=134, delta=delta,
                             labels="counterfactual")
     print({k: v for k, v in rep.items()}, flush=True)
-    assert rep["heldout"] == 12 and rep["variants"] > 0 and rep["variants"] % 8 == 0
-    assert sum(rep["label_hist"]) == rep["variants"] // 8
+    assert rep["heldout"] == 12 and rep["variants"] > 0 and rep["variants"] % 16 == 0
+    assert sum(rep["label_hist"]) == rep["variants"] // 16
+    assert 0 <= rep["dense_labels"] <= rep["variants"] // 16
     assert rep["rows"] > 0 and rep["loss_last"] <= rep["loss_first"]
     assert rep["c_round_ms"] >= 0 and rep["c_arc_ns"] >= 0 and rep["c_entry_ns"] >= 0
     assert rep["plain_fallback"] == (1 if rep["heldout_fixed_ms"] < rep["heldout_learned_ms"] else 0)

@@ -251,7 +251,7 @@ def test_server_runs_the_learned_schedule(P):
     Gs = [P.Graph.from_host(h) for h in hosts]
     for i, G in enumerate(Gs):
         p = gen.mlp_init(230 + i)
-        p[-8:] = np.linspace(-1, 1, 8)
+        p[-9:-1] = np.linspace(-1, 1, 8)
         G.mlp_load(p)
     algos = ["bidastar", "bids"]
     alone = [Gs[gi].batch_query(p, algo=algos[gi], sched="learned") for gi, p in reqs]

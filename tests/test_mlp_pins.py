@@ -17,31 +17,41 @@ def _rows(n, seed):
 
 
 def test_param_count_and_layout():
-    assert mlp.NPARAM == 5512
+    assert mlp.NPARAM == 5577 == 64 * 12 + 64 + 64 * 64 + 64 + 9 * 64 + 9
     p = np.arange(mlp.NPARAM, dtype=np.float64)
     w = mlp.unpack(p)
     assert w["W1"][0, 1] == 1 and w["b1"][0] == 768 and w["W2"][0, 0] == 832
-    assert w["b2"][0] == 4928 and w["W3"][0, 0] == 4992 and w["b3"][7] == 5511
+    assert w["b2"][0] == 4928 and w["W3"][0, 0] == 4992 and w["W3"][8, 63] == 5567
+    assert w["b3"][0] == 5568 and w["b3"][8] == 5576
     assert np.array_equal(mlp.pack(w), p)
 
 
 def test_zero_weights_give_bias_logits_and_closed_form_loss():
     p = np.zeros(mlp.NPARAM)
     w = mlp.unpack(p.copy())
-    b3 = np.array([0.5, -1.0, 2.0, 0.0, 0.25, -0.5, 1.0, 3.0])
-    p[-8:] = b3
+    b3 = np.array([0.5, -1.0, 2.0, 0.0, 0.25, -0.5, 1.0, 3.0, -0.7])
+    p[-9:] = b3
     X, y = _rows(50, 1)
     z = mlp.forward(p, X)
-    assert np.allclose(z, b3[None, :])
-    lse = np.log(np.exp(b3).sum())
-    assert np.isclose(mlp.loss(p, X, y), np.mean(lse - b3[y]))
+    assert z.shape == (50, 9) and np.allclose(z, b3[None, :])
+    lse = np.log(np.exp(b3[:8]).sum())
+    assert np.isclose(mlp.loss(p, X, y), np.mean(lse - b3[y]))          # no mode labels
+    # with mode labels: + log(1 + e^z8) for sparse rows, + log(1 + e^z8) - z8 for dense ones
+    Xm, ym = gen.mlp_rows(60, 2, learnable=False, modes=True)
+    b, m = ym % 8, ym // 8
+    assert set(m.tolist()) == {1, 2}
+    expect = np.mean(lse - b3[b] + np.log1p(np.exp(-0.7)) - (m == 2) * (-0.7))
+    assert np.isclose(mlp.loss(p, Xm, ym), expect)
     assert w["W1"].shape == (64, 12)
 
 
 def test_uniform_logits_loss_is_log8():
+    """All outputs 0: the bin term is log 8 and a labelled mode adds log 2."""
     p = np.zeros(mlp.NPARAM)
     X, y = _rows(30, 2)
     assert np.isclose(mlp.loss(p, X, y), np.log(8.0))
+    Xm, ym = gen.mlp_rows(30, 3, learnable=False, modes=True)
+    assert np.isclose(mlp.loss(p, Xm, ym), np.log(8.0) + np.log(2.0))
 
 
 def test_single_path_network_closed_form():
@@ -55,24 +65,27 @@ def test_single_path_network_closed_form():
     w["b2"][0] = -0.2
     w["W3"][3, 0] = 2.0
     w["b3"][3] = 0.3
+    w["W3"][8, 0] = -1.0                     # the mode output through the same path
     X, _ = _rows(20, 3)
     a = np.maximum(X.astype(np.float64) @ np.linspace(-1, 1, 12) + 0.1, 0)
     expect = 2.0 * np.maximum(1.5 * a - 0.2, 0) + 0.3
     z = mlp.forward(p, X)
     assert np.allclose(z[:, 3], expect)
-    assert np.allclose(np.delete(z, 3, axis=1), 0)
+    assert np.allclose(z[:, 8], -np.maximum(1.5 * a - 0.2, 0))
+    assert np.allclose(np.delete(z, [3, 8], axis=1), 0)
 
 
 def test_gradient_matches_finite_differences():
     p = gen.mlp_init(7).astype(np.float64)
     p += np.random.default_rng(8).normal(0, 0.05, p.shape)      # nonzero biases too
-    X, y = _rows(40, 9)
+    X, y = gen.mlp_rows(40, 9, learnable=False, modes=True)
+    y[::3] %= 8                                                  # a third of the rows without a mode label
     L, g = mlp.grad(p, X, y)
     assert np.isclose(L, mlp.loss(p, X, y))
     rng = np.random.default_rng(10)
     # every parameter block, a few coordinates each
     idx = np.concatenate([rng.choice(np.arange(a, b), min(12, b - a), replace=False)
-                          for a, b in [(0, 768), (768, 832), (832, 4928), (4928, 4992), (4992, 5504), (5504, 5512)]])
+                          for a, b in [(0, 768), (768, 832), (832, 4928), (4928, 4992), (4992, 5568), (5568, 5577)]])
     h = 1e-6
     for i in idx:
         e = np.zeros_like(p)
