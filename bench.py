@@ -9,14 +9,14 @@ BiDS Plain* batch (every query with its own forward and backward search in
 the same launches). Three threshold schedules run on the same graph and
 pairs in the same run:
   - fixed Delta*-stepping: the i-th threshold is i * Delta (Section 2), with
-    Delta chosen by the doubling sweep of the experiments (Section 6.1) on 32
-    held-out sample pairs;
+    Delta chosen by the doubling sweep of the experiments (Section 6.1) on
+    128 held-out sample pairs;
   - autotuned: ppsp_tune on the same sample (threshold rule, Delta, hub
-    window, launch shape); this is also the best fixed Delta under the
-    threshold rule the learned schedule uses;
+    window, launch shape, dense frontiers); this is also the best fixed
+    Delta under the threshold rule the learned schedule uses;
   - learned: the step network trained by ppsp_mlp_fit on counterfactual
-    replays of the sample pairs (held out from the 256), with the tuned
-    setting as its base; `value` is its queries/s over the timed steps.
+    replays of 32 of the sample pairs (held out from the 256), with the
+    tuned setting as its base; `value` is its queries/s over the timed steps.
 Inputs are resident on the GPU (graph in HBM, pairs handed over at the
 interface) before timing; every schedule gives the same distances, checked
 against each other and, on a sample, against the CPU oracle.
@@ -241,8 +241,9 @@ def workload_rmat24(args):
     g = gen.workload_graph("rmat24")
     lcc = gen.lcc(g)
     pairs = gen.workload_pairs("rmat24", g, cand=lcc)          # the 256 pairs of every step
-    sample = gen.pairs_uniform(lcc, 32, seed=1104)             # held-out tuning and training pairs
-    assert not (set(map(tuple, sample.tolist())) & set(map(tuple, pairs.tolist())))
+    tsample = gen.pairs_uniform(lcc, 128, seed=1104)           # held-out pairs: Delta sweep and autotuner
+    sample = tsample[:32]                                      # held-out pairs: training the schedule
+    assert not (set(map(tuple, tsample.tolist())) & set(map(tuple, pairs.tolist())))
     G = P.Graph.from_host(g, device=0, reorder=True)
     G.set_option("timeout_ms", 900000)
     _log("graph n=%d m=%d (largest component %d) built+uploaded in %.1fs" % (g.n, g.m, lcc.size, time.time() - t0))
@@ -271,11 +272,11 @@ def workload_rmat24(args):
     #    Delta by doubling while the sample batch gets faster (Section 6.1)
     G.set_option("theta_mode", 0)
     d0 = max(int(g.w.min()), 256)
-    G.batch_query(sample, algo="bids", delta=d0)               # warm-up: buffers
+    G.batch_query(tsample, algo="bids", delta=d0)              # warm-up: buffers
     sweep, best = [], None
     d = d0
     while d <= (1 << 20):
-        _, ms = time_batch(sample, 1, delta=d)
+        _, ms = time_batch(tsample, 1, delta=d)
         sweep.append([d, round(ms[0], 1)])
         if best is None or ms[0] < best[1]:
             best = (d, ms[0])
@@ -289,8 +290,8 @@ def workload_rmat24(args):
             doubling_sweep_on_sample_ms=sweep)
     G.set_option("theta_mode", 2)
 
-    # 2. autotuned on the sample
-    tr = G.tune(sample, algo="bids", batch="plainstar")
+    # 2. autotuned on the same sample
+    tr = G.tune(tsample, algo="bids", batch="plainstar")
     _log("tuned: %s" % {k: (round(v, 2) if isinstance(v, float) else v) for k, v in tr.items()})
     G.batch_query(pairs, algo="bids", sched="autotuned")
     d_auto, ms = time_batch(pairs, args.cmp_steps, sched="autotuned")

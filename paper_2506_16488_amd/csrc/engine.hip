@@ -2587,7 +2587,7 @@ int ppsp_tune(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp_opts *
     CHK(check_opts(g, opts));
     auto &slot = g->tuned[opts->algo][opts->batch];
     char key[128];
-    snprintf(key, sizeof key, "ppsp-tune-v4 %016llx %u %u", (unsigned long long)g->fingerprint, opts->algo, opts->batch);
+    snprintf(key, sizeof key, "ppsp-tune-v5 %016llx %u %u", (unsigned long long)g->fingerprint, opts->algo, opts->batch);
     if (cache_path) {
         if (FILE *f = fopen(cache_path, "r")) {
             char line[256];
@@ -2692,13 +2692,19 @@ int ppsp_tune(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp_opts *
             if (ms < best_ms) best_ms = ms; else best_dmin = keep;
         }
         if (best_dmin) {
-            const int64_t keep = best_dring;
-            best_dring = 32;
-            double ms = trial(best_d, best_mode, best_grid);
-            if (ms < best_ms) best_ms = ms; else best_dring = keep;
-            const uint64_t dd = std::max<uint64_t>(1, best_d / 2);
-            ms = trial(dd, best_mode, best_grid);
-            if (ms < best_ms) { best_ms = ms; best_d = dd; }
+            // ring and step width together: a narrower step needs more buckets ahead
+            const uint64_t d_dense = best_d;
+            const int64_t ring0 = best_dring;
+            const struct { int64_t ring; uint64_t div; } combo[] = {{ring0, 2}, {32, 1}, {32, 2}, {64, 2}, {64, 4}};
+            int64_t win_ring = ring0;
+            for (const auto &c : combo) {
+                if (c.ring == ring0 && c.div == 1) continue;
+                const uint64_t dd = std::max<uint64_t>(1, d_dense / c.div);
+                best_dring = c.ring;
+                const double ms = trial(dd, best_mode, best_grid);
+                if (ms < best_ms) { best_ms = ms; best_d = dd; win_ring = c.ring; }
+            }
+            best_dring = win_ring;
         }
     }
     // 4. The local-chunk budget of heuristic searches (the only ones that use it by default).
