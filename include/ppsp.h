@@ -106,7 +106,9 @@ enum ppsp_sched {
                                   query's two searches. Results are identical with or without it. */
 #define PPSP_DEVICE_IO 8u      /* ppsp_batch_query: `pairs` and `dist` are device pointers (on the graph's
                                   device), read and written in order on the caller's stream; paths stay
-                                  host arrays */
+                                  host arrays. The batch is planned on the host, so the call copies the
+                                  pairs to host memory and the distances back (8 B each per query) and
+                                  synchronises with the caller's stream to do so */
 
 typedef struct {
     uint32_t algo;     /* enum ppsp_algo */
@@ -137,6 +139,8 @@ typedef struct {
                                   (included in scanned_arcs) */
     uint64_t heavy_chunks;     /* hub-list chunk records (at most 2,048 arcs of one vertex each) */
     uint64_t heavy_success;    /* successful write_min operations of the hub-list kernel (in relax_success) */
+    uint64_t dense_searches;   /* searches whose frontier switched to dense bitmaps (options "dense_min",
+                                  "dense_force", "dense_learned") */
 } ppsp_stats;
 
 typedef struct ppsp_graph_s *ppsp_graph;
@@ -286,7 +290,8 @@ typedef struct {
  * tuning procedure of Section 6.1), then the hub window ("heavy_window", on
  * graphs with vertices of degree > 512), the threshold rule, Delta between the
  * doublings, the number of round-kernel workgroups, dense frontiers ("dense_min"
- * 2^16 or 2^18, then "dense_ring" 32 and half the step) and, for A* and BiD-A*,
+ * 2^16 or 2^18, then "dense_ring" 16, 32 or 64 together with the step, a half
+ * or a quarter of it) and, for A* and BiD-A*,
  * the local-chunk budget ("local_chunks") are refined. The choice
  * is kept in the handle and used by PPSP_SCHED_AUTOTUNED. With cache_path
  * (or NULL) the choice is read from / appended to a text file keyed by a hash
@@ -438,8 +443,8 @@ int ppsp_mlp_fit(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp_opt
  * (the bin chosen); nrows = rows produced (may exceed cap); per pair the
  * rounds its searches ran, the arcs they scanned, the entries they put in
  * their next frontiers (carried entries included) and the distance.
- * Errors: PPSP_E_INVALID (a bin >= 8, one of switch_round / bins_after
- * without the other, network = 1 with no network loaded, another strategy),
+ * Errors: PPSP_E_INVALID (a bin >= 8, a bins_after entry >= 16, one of
+ * switch_round / bins_after without the other, network = 1 with no network loaded, another strategy),
  * the errors of ppsp_batch_query.
  */
 typedef struct {

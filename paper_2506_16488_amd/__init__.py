@@ -57,7 +57,7 @@ class Stats(ctypes.Structure):
                 ("relax_kernel_ms", ctypes.c_double), ("relax_launches", ctypes.c_uint64),
                 ("carried", ctypes.c_uint64), ("retries", ctypes.c_uint64), ("relax_timed", ctypes.c_uint64),
                 ("heavy_kernel_ms", ctypes.c_double), ("heavy_arcs", ctypes.c_uint64), ("heavy_chunks", ctypes.c_uint64),
-                ("heavy_success", ctypes.c_uint64)]
+                ("heavy_success", ctypes.c_uint64), ("dense_searches", ctypes.c_uint64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -317,7 +317,7 @@ def _f32(a, shape=None):
 
 
 def mlp_forward(params, X, device=0) -> np.ndarray:
-    """Logits [n][8] of feature rows X [n][12] (ppsp_mlp_forward)."""
+    """Outputs [n][9] of feature rows X [n][12] (ppsp_mlp_forward): 8 bin logits, then the dense-mode logit."""
     p = _f32(params, (MLP_PARAMS,))
     X = _f32(X, (-1, MLP_FEATURES))
     out = np.empty((X.shape[0], MLP_OUTPUTS), np.float32)

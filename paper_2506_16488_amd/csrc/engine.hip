@@ -300,9 +300,12 @@ uint32_t dense_ring(ppsp_graph g) { return (uint32_t)g->opt_dense_ring; }
 // 32-bit words of one dense bitmap.
 uint64_t dense_words(ppsp_graph g) { return ((uint64_t)g->n + 31) / 32; }
 
-// Bytes of search state per search (with dense frontiers: plus its bitmaps).
+// Bytes of search state per search (where dense frontiers may be used: by
+// size, by the learned schedule's mode output or by traced switches, plus
+// its bitmaps).
 uint64_t state_bytes_per_search(ppsp_graph g) {
-    return (uint64_t)g->n * 8 + (dense_on(g) ? (uint64_t)(dense_ring(g) + 1) * dense_words(g) * 4 : 0);
+    const bool dense = dense_on(g) || g->opt_dense_learned || (g->ml && g->ml->dense);
+    return (uint64_t)g->n * 8 + (dense ? (uint64_t)(dense_ring(g) + 1) * dense_words(g) * 4 : 0);
 }
 
 uint64_t state_budget(ppsp_graph g) {
@@ -861,6 +864,7 @@ void accumulate(ppsp_graph g, const WaveOut &w) {
     g->last.heavy_kernel_ms += w.heavy_ms;
     g->last.heavy_arcs += w.stats[ST_HEAVYE];
     g->last.heavy_chunks += w.stats[ST_HCHUNK];
+    g->last.dense_searches += w.stats[ST_DENSE];
     g->last.waves += 1;
 }
 

@@ -1150,6 +1150,7 @@ __global__ __launch_bounds__(WAVE) void k_control_ml(RoundArgs A) {
                 if (A.hcap) A.hlim[i] = heavy_limit(mk == INF64 ? base * W : mk, W, A.hwin);
                 A.bin[i] = (uint8_t)bin;
                 atomicAdd(&A.dcount[2], 1u);
+                atomicAdd(&A.stats[ST_DENSE], 1ull);
             }
             continue;
         }

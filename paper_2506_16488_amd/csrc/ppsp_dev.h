@@ -257,8 +257,9 @@ __host__ __device__ inline uint64_t state_index(uint32_t G, uint32_t n, uint32_t
 
 // ST_HEAVYE / ST_HCHUNK: arcs and chunk records the round kernel handed to the
 // heavy list (relaxed by k_heavy; ST_SCANE counts every scanned arc);
-// ST_HSUCC: successful relaxations in k_heavy (ST_SUCC: in k_round).
+// ST_HSUCC: successful relaxations in k_heavy (ST_SUCC: in k_round);
+// ST_DENSE: searches switched to dense frontiers (counted by the control step).
 enum StatIdx { ST_ROUNDS = 0, ST_ENTRIES = 1, ST_SCANV = 2, ST_SCANE = 3, ST_SUCC = 4, ST_CARRY = 5, ST_HEAVYE = 6,
-               ST_HCHUNK = 7, ST_HSUCC = 8, ST_N = 16 };
+               ST_HCHUNK = 7, ST_HSUCC = 8, ST_DENSE = 9, ST_N = 16 };
 
 }  // namespace ppsp

@@ -141,3 +141,34 @@ def _not_exported(so, name):
     import subprocess
     out = subprocess.run(["nm", "-D", "--defined-only", so], capture_output=True, text=True).stdout
     return all(l.split()[-1] != name for l in out.splitlines() if l.strip())
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    """Every struct the binding passes through the C ABI has the size and
+    field offsets the header gives it (a C program built against
+    include/ppsp.h prints them)."""
+    import ctypes
+    import shutil
+    import subprocess
+    import paper_2506_16488_amd as P
+    if shutil.which("gcc") is None:
+        pytest.skip("no host C compiler")
+    pairs = [("ppsp_opts", P.Opts), ("ppsp_stats", P.Stats), ("ppsp_tune_result", P.TuneResult),
+             ("ppsp_fit_report", P.FitReport), ("ppsp_trace_spec", P.TraceSpec),
+             ("ppsp_server_counters", P.ServerCounters)]
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "ppsp.h"', "int main(void) {"]
+    for cname, cls in pairs:
+        lines.append('printf("%s %%zu\\n", sizeof(%s));' % (cname, cname))
+        for f, _ in cls._fields_:
+            lines.append('printf("%s.%s %%zu\\n", offsetof(%s, %s));' % (cname, f, cname, f))
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    inc = os.path.join(ROOT, "include")
+    subprocess.run(["gcc", "-std=c11", "-I", inc, str(src), "-o", str(exe)], check=True)
+    got = dict(l.split() for l in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n") if l)
+    for cname, cls in pairs:
+        assert int(got[cname]) == ctypes.sizeof(cls), cname
+        for f, _ in cls._fields_:
+            assert int(got["%s.%s" % (cname, f)]) == getattr(cls, f).offset, (cname, f)

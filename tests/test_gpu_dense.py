@@ -41,10 +41,18 @@ def test_dense_lattice_all_modes(P, mode):
     G = P.Graph.from_host(g)
     _modes(G, mode)
     print("dense lattice", mode, flush=True)
+    switched = {}
     for algo in ["sssp", "et", "astar", "bids", "bidastar"]:
         for batch in ["plainstar", "plain"]:
             assert np.array_equal(G.batch_query(pairs[:12] if batch == "plain" else pairs, algo=algo, batch=batch),
                                   exp[:12] if batch == "plain" else exp), (algo, batch)
+            switched[algo, batch] = G.stats()["dense_searches"]
+    if mode == "off":
+        assert not any(switched.values()), switched
+    elif mode == "forced":
+        assert all(switched.values()), switched
+    else:
+        assert switched["sssp", "plainstar"] > 0, switched
     assert np.array_equal(G.batch_query(pairs, algo="bids", batch="multi"), exp)
     assert np.array_equal(G.batch_query(pairs, algo="sssp", batch="vc"), exp)
     d, (off, vtx) = G.batch_query(pairs[:10], algo="bidastar", want_path=True)
@@ -123,4 +131,63 @@ def test_dense_with_learned_schedule(P):
     G.set_option("dense_min", 32)
     assert np.array_equal(G.batch_query(pairs, algo="bidastar", sched="learned"), exp)
     assert np.array_equal(G.batch_query(pairs, algo="bids", sched="learned"), exp)
+    G.close()
+
+
+def _mode_net(dense):
+    """Constant network: bin 4 (the base step) and a fixed frontier mode."""
+    p = np.zeros(P_PARAMS, np.float32)
+    p[-9 + 4] = 1.0
+    p[-1] = 4.0 if dense else -4.0
+    return p
+
+
+P_PARAMS = 5577
+
+
+@pytest.mark.parametrize("graph", ["lattice", "rmat"])
+def test_dense_chosen_by_network(P, graph):
+    """Option dense_learned: the network's mode output switches searches to
+    dense frontiers (and a negative output never does); without the option
+    the output is ignored. Distances are the oracle's in every case."""
+    if graph == "lattice":
+        g = gen.lattice(120, 0.05, seed=184)
+        pairs = gen.pairs_uniform(g.n, 40, seed=185)
+        algos = ["bidastar", "bids", "astar"]
+    else:
+        g = gen.rmat(14, 16, seed=186)
+        pairs = np.concatenate([gen.pairs_uniform(gen.lcc(g), 30, seed=187), gen.pairs_uniform(g.n, 10, seed=188)])
+        algos = ["bids", "et"]
+    exp = _exp(g, pairs)
+    G = P.Graph.from_host(g, reorder=graph == "rmat")
+    G.set_option("timeout_ms", 60000)
+    assert P.MLP_PARAMS == P_PARAMS
+    for opt in (0, 1):
+        G.set_option("dense_learned", opt)
+        for dense in (False, True):
+            G.mlp_load(_mode_net(dense))
+            for algo in algos:
+                print("dense by network", graph, opt, dense, algo, flush=True)
+                assert np.array_equal(G.batch_query(pairs, algo=algo, sched="learned"), exp), (opt, dense, algo)
+                n_dense = G.stats()["dense_searches"]
+                if opt and dense:
+                    assert n_dense > 0, algo
+                else:
+                    assert n_dense == 0, (opt, dense, algo, n_dense)
+    G.close()
+
+
+def test_dense_autotuned_setting_is_exact(P):
+    """The autotuner's dense trials (switch size, ring, narrower steps) on an
+    R-MAT graph with hubs: whatever it keeps, the autotuned batch is exact."""
+    g = gen.rmat(14, 16, seed=189)
+    lcc = gen.lcc(g)
+    sample = gen.pairs_uniform(lcc, 24, seed=190)
+    pairs = gen.pairs_uniform(lcc, 40, seed=191)
+    exp = _exp(g, pairs)
+    G = P.Graph.from_host(g, reorder=True)
+    G.set_option("timeout_ms", 60000)
+    tr = G.tune(sample, algo="bids", batch="plainstar")
+    assert tr["dense_ring"] in (16, 32, 64) and tr["dense_min"] in (0, 1 << 16, 1 << 18), tr
+    assert np.array_equal(G.batch_query(pairs, algo="bids", sched="autotuned"), exp)
     G.close()
