@@ -553,6 +553,9 @@ int ppsp_last_stats(ppsp_graph g, ppsp_stats *stats);
  *   "multi_group"     Multi-BiDS state layout: this many consecutive query-graph vertices
  *                     keep their words of a vertex side by side (a power of two up to 64;
  *                     default 32; 1 = search-major)
+ *   "plain_group"     bidirectional Plain* state layout: the words of a vertex for this many
+ *                     searches (half as many queries) side by side (a power of two, 2 to 64;
+ *                     default 2: one query's forward and backward copies)
  *   "rho"             target next-frontier size per search of PPSP_SCHED_RHO (default 4096)
  *   "ml_every"        rounds between evaluations of the learned schedule's network (default 4;
  *                     a search keeps its multiplier in between)

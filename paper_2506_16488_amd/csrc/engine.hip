@@ -165,6 +165,7 @@ int device_error(const char *what, hipError_t e) {
 // A query slot of one wave: which searches meet in it and where the answer goes.
 struct Plan {
     uint32_t G = 1;                 // searches per interleaved state group
+    bool pair2 = false;             // searches 2q, 2q + 1 are query q's forward and backward copies
     std::vector<SearchDesc> sd;
     std::vector<Partner> partners;
     std::vector<PairDesc> pairs;
@@ -231,7 +232,7 @@ struct ppsp_graph_s {
             opt_ml_every = 4, opt_heavy_window = 64, opt_multi_group = 32, opt_rho = 4096, opt_local = 16, opt_local_plain = 0, opt_local_fill = 0,
             opt_min_chunk = 16, opt_local_small = 4, opt_local_pct = 90, opt_defer_pct = 105,
             opt_server_round_base = 0, opt_dense_min = 0, opt_dense_force = 0, opt_dense_ring = 16,
-            opt_dense_learned = 0;
+            opt_dense_learned = 0, opt_plain_group = 2;
     uint64_t wmean = 1;             // mean arc weight (rounded up)
     uint64_t fingerprint = 0;       // hash of the CSR, keys the tuning cache
     struct Tuned {
@@ -328,7 +329,7 @@ uint64_t search_limit(ppsp_graph g) {
     return std::min<uint64_t>(std::max<uint64_t>(lim, 1), 1ull << 30);
 }
 
-void set_args(ppsp_graph g, RoundArgs &A, uint32_t nsearch, uint32_t npair, uint32_t G) {
+void set_args(ppsp_graph g, RoundArgs &A, uint32_t nsearch, uint32_t npair, uint32_t G, bool pair2) {
     memset(&A, 0, sizeof(A));
     A.row_ptr = g->row_ptr.as<uint32_t>();
     A.arcs = g->arcs.as<uint2>();
@@ -343,6 +344,7 @@ void set_args(ppsp_graph g, RoundArgs &A, uint32_t nsearch, uint32_t npair, uint
     A.nsearch = nsearch;
     A.npair = npair;
     A.G = G;
+    A.pair2 = pair2 ? 1u : 0u;
     A.S = g->S.as<uint64_t>();
     A.ctl = g->ctl.as<ulonglong2>();
     A.delta = g->delta.as<uint64_t>();
@@ -377,7 +379,7 @@ void set_args(ppsp_graph g, RoundArgs &A, uint32_t nsearch, uint32_t npair, uint
         A.defer_pct = (uint32_t)g->opt_defer_pct;
     }
     A.pull = g->pull_call && g->symmetric ? 1u : 0u;
-    if (g->memo_call && g->has_xy && (G == 2 || G == 1)) {
+    if (g->memo_call && g->has_xy && (pair2 || G == 1)) {
         A.memo = g->memo.as<uint64_t>();
         A.epoch = g->memo_epoch;
     }
@@ -535,7 +537,7 @@ int run_wave(ppsp_graph g, const Plan &P, bool want_path, WaveOut &out) {
         }
         if (g->memo_call) {
             // one word per query slot and vertex; a new epoch per wave invalidates the old words
-            const uint64_t slots = P.G == 2 ? (ns + 1) / 2 : ns;
+            const uint64_t slots = P.pair2 ? (ns + 1) / 2 : ns;
             if (g->memo.bytes < slots * n * 8) {
                 CHK(ensure(g->memo, slots * n * 8));
                 HIPCHK(hipMemsetAsync(g->memo.p, 0, g->memo.bytes, st));
@@ -561,7 +563,7 @@ int run_wave(ppsp_graph g, const Plan &P, bool want_path, WaveOut &out) {
             HIPCHK(hipMemsetAsync(g->dcount.p, 0, 16, st));
         }
         RoundArgs A;
-        set_args(g, A, ns, npair, P.G);
+        set_args(g, A, ns, npair, P.G, P.pair2);
         if (dense) {
             if (!A.sc) {
                 // counters without a learned or traced schedule (ml_mode 0: the base step)
@@ -887,11 +889,22 @@ int run_independent(ppsp_graph g, const std::vector<Query> &qs, const ppsp_opts 
     // queries per wave; the heuristic memo adds one 8-byte word per query and vertex (one search's worth)
     uint64_t lim = o->batch == PPSP_BATCH_PLAIN ? 1
                    : std::max<uint64_t>(1, search_limit(g) / (per + (g->memo_call ? 1 : 0)));
+    // bidirectional: G / 2 queries per state group (option "plain_group"); a
+    // wave holds whole groups, and one too small for a group uses groups of one query
+    uint32_t grp = 2;
+    if (per == 2 && o->batch != PPSP_BATCH_PLAIN) {
+        const uint64_t qpg = (uint64_t)g->opt_plain_group / 2;
+        if (lim >= qpg) {
+            grp = (uint32_t)g->opt_plain_group;
+            lim = lim / qpg * qpg;
+        }
+    }
     for (size_t q0 = 0; q0 < qs.size(); q0 += lim) {
         const size_t q1 = std::min<size_t>(qs.size(), q0 + lim);
         if (t_arena) arena_reset(g);
         Plan P;
-        P.G = is_bidir(o->algo) ? 2 : 1;
+        P.G = per == 2 ? grp : 1;
+        P.pair2 = per == 2;
         std::vector<uint32_t> ans_of_pair;
         for (size_t q = q0; q < q1; q++) {
             const size_t a = P.sd.size();
@@ -1869,7 +1882,7 @@ int srv_setup_graph(ppsp_server srv, SrvGraph &G, const ppsp_opts &o, uint64_t b
         HIPCHK(hipMemsetAsync(g->tot_ent.p, 0, (uint64_t)ns * 8, st));
         HIPCHK(hipMemsetAsync(g->trace_n.p, 0, 8, st));
     }
-    set_args(g, G.A, ns, npair, 2);
+    set_args(g, G.A, ns, npair, 2, true);
     srv_learned_args(G, G.A);
     HIPCHK(launch_idle(G.A, st));
     HIPCHK(hipStreamSynchronize(st));
@@ -1920,7 +1933,7 @@ int srv_restart(ppsp_server srv, SrvGraph &G, uint32_t errbits, bool renumber = 
         HIPCHK(hipMemsetAsync(g->round.p, 0, 16, st));
         G.round = 0;
     }
-    set_args(g, G.A, ns, G.C, 2);
+    set_args(g, G.A, ns, G.C, 2, true);
     srv_learned_args(G, G.A);
     HIPCHK(launch_idle(G.A, st));
     HIPCHK(hipStreamSynchronize(st));
@@ -2792,6 +2805,10 @@ int ppsp_set_option(ppsp_graph g, const char *name, int64_t v) {
         if (v < 1 || v > 64 || (v & (v - 1))) return PPSP_E_INVALID;
         g->opt_multi_group = v;
     }
+    else if (k == "plain_group") {
+        if (v < 2 || v > 64 || (v & (v - 1))) return PPSP_E_INVALID;
+        g->opt_plain_group = v;
+    }
     else if (k == "server_round_base") {
         if (v < 0 || v >= (int64_t)SRV_ROUND_LIMIT) return PPSP_E_INVALID;
         g->opt_server_round_base = v;
@@ -2824,6 +2841,7 @@ int ppsp_get_option(ppsp_graph g, const char *name, int64_t *v) {
     else if (k == "ml_every") *v = g->opt_ml_every;
     else if (k == "heavy_window") *v = g->opt_heavy_window;
     else if (k == "multi_group") *v = g->opt_multi_group;
+    else if (k == "plain_group") *v = g->opt_plain_group;
     else if (k == "rho") *v = g->opt_rho;
     else if (k == "local_chunks") *v = g->opt_local;
     else if (k == "local_chunks_plain") *v = g->opt_local_plain;

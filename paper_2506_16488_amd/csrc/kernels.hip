@@ -121,7 +121,7 @@ __device__ __forceinline__ int32_t hterm(const RoundArgs &A, const SearchDesc &s
 __device__ __forceinline__ int32_t hterm_memo(const RoundArgs &A, const SearchDesc &sd, uint32_t i, uint32_t v) {
     if (sd.kind == K_DIST || sd.kind == K_2DIST) return 0;
     if (!A.memo) return hterm(A, sd, v);
-    uint64_t *m = A.memo + (uint64_t)(A.G == 2 ? (i >> 1) : i) * A.n + v;
+    uint64_t *m = A.memo + (uint64_t)(A.pair2 ? (i >> 1) : i) * A.n + v;
     const uint64_t w = *m;
     int32_t h;
     if ((uint32_t)(w >> 32) == A.epoch) {
@@ -215,7 +215,7 @@ __device__ __forceinline__ bool relax_commit(const RoundArgs &A, const SearchDes
                                              uint64_t *kout, bool dense = false) {
     if (cand >= (old >> 32)) return false;
     (*succ)++;
-    if (A.G == 2) {
+    if (A.pair2) {
         const uint32_t dp = (uint32_t)(other >> 32);
         if (dp != INF32) mu_update(A, A.partners[sd.pbeg].pair, cand + dp, v);
     } else {
@@ -247,8 +247,8 @@ __device__ __forceinline__ bool relax_arc(const RoundArgs &A, const SearchDesc &
     if (cand >= INF32) { atomicOr(A.err, ERR_OVERFLOW); return false; }
     unsigned long long *p;
     uint64_t own, other = INF64;
-    if (A.G == 2) {
-        const uint64_t base = state_index(2, A.n, i & ~1u, v);
+    if (A.pair2) {
+        const uint64_t base = state_index(A.G, A.n, i & ~1u, v);
         const ulonglong2 w = *(const ulonglong2 *)(A.S + base);   // possibly stale: never below the truth
         own = (i & 1) ? w.y : w.x;
         other = (i & 1) ? w.x : w.y;
@@ -511,8 +511,8 @@ __global__ __launch_bounds__(WAVE) void k_round(RoundArgs A) {
             if (bnd != 0 && ent.z == RECHECK_Z) {
                 // the deferred meeting check of a vertex extracted locally last round
                 const SearchDesc sd = A.sd[i];
-                if (A.G == 2) {
-                    const ulonglong2 w = *(const ulonglong2 *)(A.S + state_index(2, A.n, i & ~1u, u));
+                if (A.pair2) {
+                    const ulonglong2 w = *(const ulonglong2 *)(A.S + state_index(A.G, A.n, i & ~1u, u));
                     const uint32_t d0 = (uint32_t)(((i & 1) ? w.y : w.x) >> 32);
                     const uint32_t d1 = (uint32_t)(((i & 1) ? w.x : w.y) >> 32);
                     if (d0 != INF32 && d1 != INF32) mu_update(A, A.partners[sd.pbeg].pair, (uint64_t)d0 + d1, u);
@@ -529,8 +529,8 @@ __global__ __launch_bounds__(WAVE) void k_round(RoundArgs A) {
                 uint64_t word;
                 uint32_t dp = INF32;
                 unsigned long long *wp;
-                if (A.G == 2) {
-                    const uint64_t base = state_index(2, A.n, i & ~1u, u);
+                if (A.pair2) {
+                    const uint64_t base = state_index(A.G, A.n, i & ~1u, u);
                     const ulonglong2 w = *(const ulonglong2 *)(A.S + base);
                     word = (i & 1) ? w.y : w.x;
                     dp = (uint32_t)(((i & 1) ? w.x : w.y) >> 32);
@@ -581,7 +581,7 @@ __global__ __launch_bounds__(WAVE) void k_round(RoundArgs A) {
                         if (wait) {
                             action = 1;
                         } else {
-                            if (A.G == 2) {
+                            if (A.pair2) {
                                 if (dp != INF32) mu_update(A, A.partners[sd.pbeg].pair, (uint64_t)du + dp, u);
                             } else {
                                 meet_list(A, sd, du, u);
@@ -592,7 +592,7 @@ __global__ __launch_bounds__(WAVE) void k_round(RoundArgs A) {
                                 re = rp[u + 1];
                                 c_sv++;
                                 c_se += re - rb;
-                                recheck = local && (A.G == 2 || sd.pend > sd.pbeg + 1 ||
+                                recheck = local && (A.pair2 || sd.pend > sd.pbeg + 1 ||
                                                     (sd.pend > sd.pbeg && !(A.partners[sd.pbeg].other & TARGET_BIT)));
                             }
                         }
@@ -692,8 +692,8 @@ __global__ __launch_bounds__(WAVE) void k_round(RoundArgs A) {
                                                ((uint64_t)nd << 32) | ent.z);
                 if (nd < (uint32_t)(old >> 32)) {
                     const SearchDesc sd = A.sd[si];
-                    if (A.G == 2) {
-                        const uint32_t dp = (uint32_t)(A.S[state_index(2, A.n, si ^ 1u, ent.y)] >> 32);
+                    if (A.pair2) {
+                        const uint32_t dp = (uint32_t)(A.S[state_index(A.G, A.n, si ^ 1u, ent.y)] >> 32);
                         if (dp != INF32) mu_update(A, A.partners[sd.pbeg].pair, (uint64_t)nd + dp, ent.y);
                     } else {
                         meet_list(A, sd, nd, ent.y);
@@ -739,8 +739,8 @@ __global__ __launch_bounds__(WAVE) void k_round(RoundArgs A) {
                 other[h] = INF64;
                 wp[h] = nullptr;
                 if (want[h]) {
-                    if (A.G == 2) {
-                        const uint64_t base = state_index(2, A.n, ai[h] & ~1u, v[h]);
+                    if (A.pair2) {
+                        const uint64_t base = state_index(A.G, A.n, ai[h] & ~1u, v[h]);
                         const ulonglong2 w = *(const ulonglong2 *)(A.S + base);   // possibly stale: never below the truth
                         own[h] = (ai[h] & 1) ? w.y : w.x;
                         other[h] = (ai[h] & 1) ? w.x : w.y;
@@ -1034,7 +1034,7 @@ __device__ __forceinline__ void ml_features(const RoundArgs &A, uint32_t i, cons
     f[1] = lg2p(arcs) / 16.f;
     f[2] = lg2p(scale * (double)nxt) / 16.f;
     uint32_t pj = INF32;
-    if (A.G == 2) {
+    if (A.pair2) {
         pj = i ^ 1u;
     } else if (sd.pend > sd.pbeg) {
         const uint32_t o = A.partners[sd.pbeg].other;

@@ -25,9 +25,12 @@
 // so paths are recovered by walking tight arcs back to the root.
 // Words are grouped G searches at a time, vertex-major inside a group:
 //     S[((i / G) * n + v) * G + i % G]
-// G = 2 puts the forward and backward copies of a bidirectional query side by
-// side, so one 16-byte load returns both delta[v+] and delta[v-] (the two
-// terms of UpdateDistance); G = 1 is plain search-major. Multi-BiDS groups
+// Bidirectional Plain and Plain* batches ("pair2") number a query's forward
+// and backward copies 2q and 2q + 1, so with any even G they sit side by side
+// and one 16-byte load returns both delta[v+] and delta[v-] (the two terms of
+// UpdateDistance). G = 2 is one query per group; a larger G also puts the
+// words of G / 2 queries for one vertex in the same lines (option
+// "plain_group"). G = 1 is plain search-major. Multi-BiDS groups
 // G consecutive query-graph vertices (by default 32: the copies of v for the
 // searches of one component share a few cache lines, the vertex-major layout
 // of Section 4.2), so its UpdateDistance over the neighbours in the query
@@ -139,7 +142,8 @@ struct RoundArgs {
     const Partner *partners;
     uint32_t nsearch;
     uint32_t npair;
-    uint32_t G;                // searches per interleaved group (1 or 2)
+    uint32_t G;                // searches per interleaved group (a power of two)
+    uint32_t pair2;            // 1: searches 2q and 2q + 1 are one query's forward and backward copies
     uint64_t *S;               // packed (distance, stamp) words, layout above
     ulonglong2 *ctl;           // [nsearch] (theta, bound) in key units; bound 0 = finished
     const uint64_t *delta;     // [nsearch] threshold increment (key units)
