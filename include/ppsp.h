@@ -556,6 +556,12 @@ int ppsp_last_stats(ppsp_graph g, ppsp_stats *stats);
  *   "plain_group"     bidirectional Plain* state layout: the words of a vertex for this many
  *                     searches (half as many queries) side by side (a power of two, 2 to 64;
  *                     default 2: one query's forward and backward copies)
+ *   "heavy_grouped"   1 (default): on a symmetric graph with vertices of degree > 512 and a
+ *                     state layout of 4 or more searches per group ("plain_group",
+ *                     "multi_group"), the hub-list kernel relaxes each chunk of a hub's
+ *                     arcs once for all searches of a group that extracted it in the round
+ *                     (arcs read once, the group's words of a head in shared lines); 0: one
+ *                     pass per search
  *   "rho"             target next-frontier size per search of PPSP_SCHED_RHO (default 4096)
  *   "ml_every"        rounds between evaluations of the learned schedule's network (default 4;
  *                     a search keeps its multiplier in between)

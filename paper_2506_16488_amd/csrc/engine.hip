@@ -214,6 +214,9 @@ struct ppsp_graph_s {
     std::vector<uint32_t> perm;     // PPSP_REORDER: device id of each caller id (empty: identity)
     std::vector<uint32_t> iperm;    // caller id of each device id
     DevBuf row_ptr, arcs, xy, in_row_ptr, in_arcs;   // transpose only for a directed graph
+    DevBuf hub_id, hub_vert;        // symmetric graphs with hubs: index of each vertex among them, their vertices
+    uint32_t nhub = 0;
+    DevBuf hmask, hrec, hgcount;    // the hub list grouped by vertex (workspace)
     // workspace (grow only)
     DevBuf tsum;                    // local-chunk time limit: 4 sums, then 2 limits
     DevBuf S, q0, q1, sd, partners, pairdesc, ctl, delta, done, exh, alive, minkey, mu, qcount, cpre, round, err,
@@ -232,7 +235,7 @@ struct ppsp_graph_s {
             opt_ml_every = 4, opt_heavy_window = 64, opt_multi_group = 32, opt_rho = 4096, opt_local = 16, opt_local_plain = 0, opt_local_fill = 0,
             opt_min_chunk = 16, opt_local_small = 4, opt_local_pct = 90, opt_defer_pct = 105,
             opt_server_round_base = 0, opt_dense_min = 0, opt_dense_force = 0, opt_dense_ring = 16,
-            opt_dense_learned = 0, opt_plain_group = 2;
+            opt_dense_learned = 0, opt_plain_group = 2, opt_heavy_grouped = 1;
     uint64_t wmean = 1;             // mean arc weight (rounded up)
     uint64_t fingerprint = 0;       // hash of the CSR, keys the tuning cache
     struct Tuned {
@@ -450,6 +453,14 @@ int run_wave(ppsp_graph g, const Plan &P, bool want_path, WaveOut &out) {
         if (g->hcap < want || t_arena) g->hcap = (uint32_t)std::min<uint64_t>(want, 1u << 28);
         CHK(ensure(g->heavy, (uint64_t)g->hcap * 32));
     }
+    // the hub list grouped by vertex: symmetric graphs with hubs, state groups of 4 or more searches
+    const bool hgrouped = g->nhub && g->opt_heavy_grouped && P.G >= 4 && !t_arena;
+    const uint64_t ngroups = ns_words / P.G;
+    if (hgrouped) {
+        CHK(ensure(g->hmask, 2ull * g->nhub * ngroups * 8));
+        CHK(ensure(g->hrec, 2ull * g->hcap * 16));
+        CHK(ensure(g->hgcount, 16));
+    }
     CHK(ensure(g->sd, ns * sizeof(SearchDesc)));
     CHK(ensure(g->partners, P.partners.size() * sizeof(Partner)));
     CHK(ensure(g->pairdesc, npair * sizeof(PairDesc)));
@@ -489,6 +500,10 @@ int run_wave(ppsp_graph g, const Plan &P, bool want_path, WaveOut &out) {
         CHK(ensure(g->q0, g->qcap * 16));
         CHK(ensure(g->q1, g->qcap * 16));
         HIPCHK(hipMemsetAsync(g->S.p, 0xFF, sbytes, st));
+        if (hgrouped) {
+            HIPCHK(hipMemsetAsync(g->hmask.p, 0, 2ull * g->nhub * ngroups * 8, st));
+            HIPCHK(hipMemsetAsync(g->hgcount.p, 0, 16, st));
+        }
         HIPCHK(hipMemcpyAsync(g->sd.p, P.sd.data(), ns * sizeof(SearchDesc), hipMemcpyHostToDevice, st));
         if (!P.partners.empty())
             HIPCHK(hipMemcpyAsync(g->partners.p, P.partners.data(), P.partners.size() * sizeof(Partner),
@@ -564,6 +579,16 @@ int run_wave(ppsp_graph g, const Plan &P, bool want_path, WaveOut &out) {
         }
         RoundArgs A;
         set_args(g, A, ns, npair, P.G, P.pair2);
+        if (hgrouped) {
+            A.hgrouped = 1;
+            A.hub_id = g->hub_id.as<uint32_t>();
+            A.hub_vert = g->hub_vert.as<uint32_t>();
+            A.hmask = g->hmask.as<unsigned long long>();
+            A.hrec = g->hrec.as<uint4>();
+            A.hgcount = g->hgcount.as<unsigned long long>();
+            A.nhub = g->nhub;
+            A.ngroups = (uint32_t)ngroups;
+        }
         if (dense) {
             if (!A.sc) {
                 // counters without a learned or traced schedule (ml_mode 0: the base step)
@@ -711,6 +736,7 @@ int run_wave(ppsp_graph g, const Plan &P, bool want_path, WaveOut &out) {
                 if (g->hcap >= (1u << 28)) return PPSP_E_OOM;
                 g->hcap *= 4;
                 CHK(ensure(g->heavy, (uint64_t)g->hcap * 32));
+                if (hgrouped) CHK(ensure(g->hrec, 2ull * g->hcap * 16));
             }
             continue;
         }
@@ -2348,6 +2374,24 @@ int ppsp_graph_create(int device, uint32_t n, uint64_t m, const uint64_t *row_pt
         return fail(device_error("upload row_ptr", he));
     if (m && (he = hipMemcpyAsync(g->arcs.p, arcs.data(), m * 8, hipMemcpyHostToDevice, st)) != hipSuccess)
         return fail(device_error("upload arcs", he));
+    // hubs of a symmetric graph, for the hub list grouped by vertex
+    std::vector<uint32_t> hid, hvert;
+    if (g->symmetric && maxdeg > HEAVY_DEG) {
+        hid.assign(n, INF32);
+        for (uint32_t v = 0; v < n; v++)
+            if (row_ptr[v + 1] - row_ptr[v] > HEAVY_DEG) {
+                hid[v] = (uint32_t)hvert.size();
+                hvert.push_back(v);
+            }
+        g->nhub = (uint32_t)hvert.size();
+        if ((rc = ensure(g->hub_id, n * 4ull)) != PPSP_OK) return fail(rc);
+        if ((rc = ensure(g->hub_vert, hvert.size() * 4ull)) != PPSP_OK) return fail(rc);
+        if ((he = hipMemcpyAsync(g->hub_id.p, hid.data(), n * 4ull, hipMemcpyHostToDevice, st)) != hipSuccess)
+            return fail(device_error("upload hub index", he));
+        if ((he = hipMemcpyAsync(g->hub_vert.p, hvert.data(), hvert.size() * 4ull, hipMemcpyHostToDevice, st)) !=
+            hipSuccess)
+            return fail(device_error("upload hub index", he));
+    }
     std::vector<uint32_t> trp;
     std::vector<uint2> tarcs;
     if (!g->symmetric) {
@@ -2722,6 +2766,11 @@ int ppsp_tune(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp_opts *
                 if (ms < best_ms) { best_ms = ms; best_d = dd; win_ring = c.ring; }
             }
             best_dring = win_ring;
+            // dense rounds run the round kernel at a lower occupancy: 16 workgroups per CU
+            if (best_grid == 0) {
+                const double ms = trial(best_d, best_mode, 16 * g->cu);
+                if (ms < best_ms) { best_ms = ms; best_grid = 16 * g->cu; }
+            }
         }
     }
     // 4. The local-chunk budget of heuristic searches (the only ones that use it by default).
@@ -2809,6 +2858,10 @@ int ppsp_set_option(ppsp_graph g, const char *name, int64_t v) {
         if (v < 2 || v > 64 || (v & (v - 1))) return PPSP_E_INVALID;
         g->opt_plain_group = v;
     }
+    else if (k == "heavy_grouped") {
+        if (v < 0 || v > 1) return PPSP_E_INVALID;
+        g->opt_heavy_grouped = v;
+    }
     else if (k == "server_round_base") {
         if (v < 0 || v >= (int64_t)SRV_ROUND_LIMIT) return PPSP_E_INVALID;
         g->opt_server_round_base = v;
@@ -2842,6 +2895,7 @@ int ppsp_get_option(ppsp_graph g, const char *name, int64_t *v) {
     else if (k == "heavy_window") *v = g->opt_heavy_window;
     else if (k == "multi_group") *v = g->opt_multi_group;
     else if (k == "plain_group") *v = g->opt_plain_group;
+    else if (k == "heavy_grouped") *v = g->opt_heavy_grouped;
     else if (k == "rho") *v = g->opt_rho;
     else if (k == "local_chunks") *v = g->opt_local;
     else if (k == "local_chunks_plain") *v = g->opt_local_plain;

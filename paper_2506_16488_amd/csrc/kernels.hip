@@ -237,11 +237,10 @@ __device__ __forceinline__ bool relax_commit(const RoundArgs &A, const SearchDes
 // whose stamp is `stamp`. Returns true if v^(i) must be added to the next
 // frontier; *out is that entry. *lmin takes the key of every unpruned
 // decrease (added now or by an earlier decrease of this round).
-template <bool MEMO, bool REV>
-__device__ __forceinline__ bool relax_arc(const RoundArgs &A, const SearchDesc &sd, uint32_t i, uint32_t u,
-                                          uint32_t du, uint64_t bnd, uint32_t e, uint32_t stamp, uint4 *out,
-                                          uint64_t *lmin, unsigned long long *succ, uint64_t *kout, bool dense) {
-    const uint2 a = ((REV && sd.rev) ? A.in_arcs : A.arcs)[e];
+template <bool MEMO>
+__device__ __forceinline__ bool relax_to(const RoundArgs &A, const SearchDesc &sd, uint32_t i, uint2 a, uint32_t du,
+                                         uint64_t bnd, uint32_t stamp, uint4 *out, uint64_t *lmin,
+                                         unsigned long long *succ, uint64_t *kout, bool dense) {
     const uint32_t v = a.x;
     const uint64_t cand = (uint64_t)du + a.y;
     if (cand >= INF32) { atomicOr(A.err, ERR_OVERFLOW); return false; }
@@ -260,6 +259,17 @@ __device__ __forceinline__ bool relax_arc(const RoundArgs &A, const SearchDesc &
     if (cand >= (own >> 32)) return false;
     const uint64_t old = atomicMin(p, (cand << 32) | stamp);
     return relax_commit<MEMO>(A, sd, i, v, cand, other, old, bnd, stamp, out, lmin, succ, kout, dense);
+}
+
+// The same for arc e of the search's CSR (the transpose for a backward
+// search on a directed graph).
+template <bool MEMO, bool REV>
+__device__ __forceinline__ bool relax_arc(const RoundArgs &A, const SearchDesc &sd, uint32_t i, uint32_t u,
+                                          uint32_t du, uint64_t bnd, uint32_t e, uint32_t stamp, uint4 *out,
+                                          uint64_t *lmin, unsigned long long *succ, uint64_t *kout, bool dense) {
+    (void)u;
+    const uint2 a = ((REV && sd.rev) ? A.in_arcs : A.arcs)[e];
+    return relax_to<MEMO>(A, sd, i, a, du, bnd, stamp, out, lmin, succ, kout, dense);
 }
 
 // Dense frontiers (RoundArgs::dbits): sets v^(i)'s bit in the bitmap of the
@@ -392,7 +402,7 @@ __global__ __launch_bounds__(WAVE) void k_round(RoundArgs A) {
     const uint32_t csize = A.cpre[par * (NSEG + 1)];         // entries per chunk this round
     if (blockIdx.x == 0 && lane_id() == 0) {
         A.round[1] = r;                                    // for k_control
-        if (nchunks) atomicAdd(&A.stats[ST_ROUNDS], 1ull);
+        if (nchunks || ndense) atomicAdd(&A.stats[ST_ROUNDS], 1ull);
     }
     unsigned long long c_ent = 0, c_sv = 0, c_se = 0, c_succ = 0, c_keep = 0, c_he = 0, c_hc = 0;
     const bool count = A.sc && blockIdx.x < ML_SAMPLE;
@@ -622,25 +632,36 @@ __global__ __launch_bounds__(WAVE) void k_round(RoundArgs A) {
         // wave reserves the wave's chunks.
         const bool heavy = action == 2 && A.hcap && re - rb > HEAVY_DEG;
         if (__ballot(heavy)) {
-            const uint32_t nck = heavy ? (re - rb + HEAVY_CHUNK - 1) / HEAVY_CHUNK : 0u;
+            uint32_t nck = heavy ? (re - rb + HEAVY_CHUNK - 1) / HEAVY_CHUNK : 0u;
             if (heavy) {
                 c_he += re - rb;
                 c_hc += nck;
             }
+            uint32_t hid = 0, grp = 0;
+            if (A.hgrouped && heavy) {
+                // grouped by vertex: only the group's first search to extract the hub lists its chunks
+                hid = A.hub_id[ent.y];
+                grp = si / A.G;
+                const unsigned long long old =
+                    atomicOr(A.hmask + ((uint64_t)par * A.nhub + hid) * A.ngroups + grp, 1ull << (si & (A.G - 1)));
+                if (old != 0) nck = 0;
+            }
             uint32_t tot;
             const uint32_t pre = wave_exscan(nck, &tot);
             unsigned long long b0 = 0;
-            if (lane_id() == 0) b0 = atomicAdd(A.hcount, (unsigned long long)tot);
+            if (lane_id() == 0 && tot) b0 = atomicAdd(A.hgrouped ? A.hgcount + par : A.hcount, (unsigned long long)tot);
             b0 = __shfl(b0, 0);
             for (uint32_t k = 0; k < nck; k++) {
                 const uint64_t slot = b0 + pre + k;
                 const uint32_t eb = rb + k * HEAVY_CHUNK;
                 const uint32_t ee = min(re, eb + HEAVY_CHUNK);
-                if (slot < A.hcap) {
+                if (slot >= A.hcap) {
+                    atomicOr(A.err, ERR_HEAVY);
+                } else if (A.hgrouped) {
+                    A.hrec[(uint64_t)par * A.hcap + slot] = make_uint4(hid, grp, eb, ee);
+                } else {
                     A.heavy[2 * slot] = make_uint4(si, ent.y, du, eb);
                     A.heavy[2 * slot + 1] = make_uint4(ee, 0u, 0u, 0u);
-                } else {
-                    atomicOr(A.err, ERR_HEAVY);
                 }
             }
         }
@@ -858,6 +879,71 @@ __global__ __launch_bounds__(WAVE) void k_heavy(RoundArgs A) {
     if (lane_id() == 0 && c_succ) A.wstats[(uint64_t)blockIdx.x * ST_N + ST_HSUCC] += c_succ;
 }
 
+// The hub list grouped by vertex (RoundArgs::hgrouped; symmetric graphs): a
+// wave takes one listed chunk of hub u and relaxes its arcs, 64 at a time,
+// for every search of the group whose bit is set, one search after the
+// other, so each arc is read once and the group's words of its head are in
+// the lines the first search brought in. The relaxation starts from each
+// search's current distance of u (never above the one it extracted: an exact
+// upper bound either way). First it clears the bits of the previous round's
+// list, which that round's kernel has finished reading.
+template <bool MEMO>
+__global__ __launch_bounds__(WAVE) void k_heavy_grouped(RoundArgs A) {
+    __shared__ WaveStage st;
+    __shared__ uint32_t s_du[WAVE];
+    __shared__ uint64_t s_bnd[WAVE];
+    uint32_t scnt = 0;
+    const uint32_t r = A.round[1];                          // set by this round's k_round
+    const uint32_t par = r & 1, np = par ^ 1, stamp = r + 1;
+    {
+        const uint64_t nprev = min((uint64_t)A.hgcount[np], (uint64_t)A.hcap);
+        for (uint64_t s = (uint64_t)blockIdx.x * WAVE + lane_id(); s < nprev; s += (uint64_t)gridDim.x * WAVE) {
+            const uint4 rc = A.hrec[(uint64_t)np * A.hcap + s];
+            A.hmask[((uint64_t)np * A.nhub + rc.x) * A.ngroups + rc.y] = 0;
+        }
+    }
+    const uint64_t nh = min((uint64_t)A.hgcount[par], (uint64_t)A.hcap);
+    if (nh == 0) return;
+    const bool count = A.sc && blockIdx.x < ML_SAMPLE;
+    const uint32_t sego = blockIdx.x % NSEG;
+    uint4 *qout = (par ? A.q0 : A.q1) + (uint64_t)sego * A.qseg;
+    uint32_t *qcout = &A.qcount[np * NSEG + sego];
+    unsigned long long c_succ = 0;
+    for (uint64_t slot = blockIdx.x; slot < nh; slot += gridDim.x) {
+        const uint4 rc = A.hrec[(uint64_t)par * A.hcap + slot];
+        const uint32_t u = A.hub_vert[rc.x], grp = rc.y;
+        const unsigned long long M = A.hmask[((uint64_t)par * A.nhub + rc.x) * A.ngroups + grp];
+        const uint32_t j = lane_id();
+        __syncthreads();                                    // the previous chunk's reads of s_du / s_bnd are done
+        if (j < A.G && ((M >> j) & 1ull)) {
+            const uint32_t si = grp * A.G + j;
+            s_du[j] = (uint32_t)(A.S[state_index(A.G, A.n, si, u)] >> 32);
+            s_bnd[j] = A.ctl[si].y;
+        }
+        __syncthreads();
+        for (uint32_t e0 = rc.z; e0 < rc.w; e0 += WAVE) {
+            const uint32_t e = e0 + lane_id();
+            const uint2 a = e < rc.w ? A.arcs[e] : make_uint2(0u, 0u);
+            for (unsigned long long mm = M; mm; mm &= mm - 1) {
+                const uint32_t jj = (uint32_t)__builtin_ctzll(mm);
+                const uint32_t ai = grp * A.G + jj;
+                const SearchDesc sd = A.sd[ai];
+                const bool dm = A.dbits && A.dmode[ai];
+                bool app = false;
+                uint4 ne = make_uint4(0, 0, 0, 0);
+                uint64_t lmin = INF64, kv = INF64;
+                if (e < rc.w) app = relax_to<MEMO>(A, sd, ai, a, s_du[jj], s_bnd[jj], stamp, &ne, &lmin, &c_succ, &kv, dm);
+                if (app && dm && dense_add(A, ai, ne.y, kv)) app = false;
+                wstage_push(st, scnt, app, ne, qout, qcout, A.qseg, A.err);
+                search_stats(A, np, ai, app ? 1u : 0u, lmin, count);
+            }
+        }
+    }
+    wstage_flush(st, scnt, qout, qcout, A.qseg, A.err);
+    c_succ = wave_sum_u64(c_succ);
+    if (lane_id() == 0 && c_succ) A.wstats[(uint64_t)blockIdx.x * ST_N + ST_HSUCC] += c_succ;
+}
+
 // Prefix sum of the chunk counts of the NSEG segments of queue `q` (one
 // wave of 64 = NSEG lanes). A chunk is WAVE entries, or fewer while the
 // whole queue is too small to give every workgroup of the round kernel a
@@ -997,6 +1083,7 @@ __global__ __launch_bounds__(BLOCK) void k_control(RoundArgs A) {
     if (i == 0) {
         A.round[0] = r + 1;
         *A.hcount = 0;
+        if (A.hgrouped) A.hgcount[np] = 0;       // the list whose bits the hub-list kernel just cleared
     }
     if (i >= A.nsearch) return;
     uint64_t mk = 0, nb = 0;
@@ -1079,6 +1166,7 @@ __global__ __launch_bounds__(WAVE) void k_control_ml(RoundArgs A) {
         if (w) {
             A.round[0] = r + 1;
             *A.hcount = 0;
+            if (A.hgrouped) A.hgcount[np] = 0;   // the list whose bits the hub-list kernel just cleared
         }
     }
     // share of this round's chunks that the counting workgroups processed
@@ -1444,7 +1532,19 @@ static hipError_t launch_heavy_t(const RoundArgs &A, uint32_t grid, hipStream_t 
     return hipGetLastError();
 }
 
+template <bool MEMO>
+static hipError_t launch_heavy_grouped_t(const RoundArgs &A, uint32_t grid, hipStream_t st, hipEvent_t e0,
+                                         hipEvent_t e1) {
+    if (e0)
+        hipExtLaunchKernelGGL(k_heavy_grouped<MEMO>, dim3(grid), dim3(WAVE), 0, st, e0, e1, 0, A);
+    else
+        k_heavy_grouped<MEMO><<<grid, WAVE, 0, st>>>(A);
+    return hipGetLastError();
+}
+
 hipError_t launch_heavy(const RoundArgs &A, uint32_t grid, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+    if (A.hgrouped)
+        return A.memo ? launch_heavy_grouped_t<true>(A, grid, st, e0, e1) : launch_heavy_grouped_t<false>(A, grid, st, e0, e1);
     const bool rev = A.in_row_ptr != A.row_ptr;
     if (rev) return A.memo ? launch_heavy_t<true, true>(A, grid, st, e0, e1) : launch_heavy_t<false, true>(A, grid, st, e0, e1);
     return A.memo ? launch_heavy_t<true, false>(A, grid, st, e0, e1) : launch_heavy_t<false, false>(A, grid, st, e0, e1);

@@ -162,6 +162,19 @@ struct RoundArgs {
                                //   (search, vertex, distance, first arc), (end arc, 0, 0, 0)
     unsigned long long *hcount;  // chunks written this round
     uint32_t hcap;             // heavy list capacity (chunks); 0 = no heavy path
+    // The hub list grouped by vertex (hgrouped = 1: a symmetric graph with
+    // state groups of G >= 4 searches). The searches of one group that
+    // extract hub h in a round set their bits in hmask[round parity][index of
+    // h][group]; the first of them lists h's chunks once for the group in
+    // hrec[round parity], and the hub-list kernel relaxes each listed chunk
+    // for all of the group's searches with bits set, reading the arcs once
+    // and their heads' words for the group from the same lines.
+    const uint32_t *hub_id;    // [n] index of each vertex among the hubs (degree > HEAVY_DEG), else INF32
+    const uint32_t *hub_vert;  // [nhub] vertex of each hub
+    unsigned long long *hmask; // [2][nhub][ngroups] bits of the searches of a group that extracted the hub
+    uint4 *hrec;               // [2][hcap] (hub index, group, first arc, end arc)
+    unsigned long long *hgcount;  // [2] records listed per round parity
+    uint32_t nhub, ngroups, hgrouped;
     uint32_t *err;             // ERR_* bits
     unsigned long long *stats; // [ST_ROUNDS] rounds run
     unsigned long long *wstats; // [grid][ST_N] per-workgroup counters of the round kernel
