@@ -369,7 +369,7 @@ constexpr uint32_t RECHECK_Z = 0xFFFFFFFEu;
 // One round. Workgroups are single waves that work independently (no
 // barriers between waves): each takes WAVE-entry chunks of its sub-queue.
 template <bool PULL, bool MEMO, bool REV, bool DENSE>
-__global__ __launch_bounds__(WAVE) void k_round(RoundArgs A) {
+__device__ __forceinline__ void round_body(const RoundArgs &A) {
     __shared__ WaveStage st;
     __shared__ Advance adv;
     uint32_t scnt = 0;
@@ -838,6 +838,17 @@ __global__ __launch_bounds__(WAVE) void k_round(RoundArgs A) {
         atomicAdd(&A.tsum[par * 2], (unsigned long long)(wall_clock64() - t_begin));
         atomicAdd(&A.tsum[par * 2 + 1], 1ull);
     }
+}
+
+template <bool PULL, bool MEMO, bool REV, bool DENSE>
+__global__ __launch_bounds__(WAVE) void k_round(RoundArgs A) {
+    round_body<PULL, MEMO, REV, DENSE>(A);
+}
+
+// The dense instantiation held to 96 registers (5 waves per SIMD, the
+// occupancy of the sparse one) at the cost of a few spills ("dense_waves5").
+__global__ __launch_bounds__(WAVE, 5) void k_round_dense5(RoundArgs A) {
+    round_body<false, false, false, true>(A);
 }
 
 // The heavy list, relaxed by every wave of the grid: each wave takes whole
@@ -1504,6 +1515,13 @@ static hipError_t launch_round_t(const RoundArgs &A, uint32_t grid, hipStream_t 
 }
 
 hipError_t launch_round(const RoundArgs &A, uint32_t grid, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+    if (A.dbits && A.dense_waves5 && A.in_row_ptr == A.row_ptr && !A.memo) {
+        if (e0)
+            hipExtLaunchKernelGGL(k_round_dense5, dim3(grid), dim3(WAVE), 0, st, e0, e1, 0, A);
+        else
+            k_round_dense5<<<grid, WAVE, 0, st>>>(A);
+        return hipGetLastError();
+    }
     // The default path (symmetric graph, no pull pass, no heuristic memo, no
     // dense frontiers) is compiled without those branches, which would
     // otherwise cost it registers and occupancy. A directed graph has a
