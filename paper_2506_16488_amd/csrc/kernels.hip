@@ -368,8 +368,13 @@ constexpr uint32_t RECHECK_Z = 0xFFFFFFFEu;
 
 // One round. Workgroups are single waves that work independently (no
 // barriers between waves): each takes WAVE-entry chunks of its sub-queue.
+// Held to 96 registers, i.e. 5 waves per SIMD: the default grid of 20
+// single-wave workgroups per CU is then resident at once (at 4 waves per
+// SIMD a fifth of the workgroups would start only when others finish, and
+// the static chunk stride would leave them a tail: 1.5x the launch time on
+// the 2048^2 lattice).
 template <bool PULL, bool MEMO, bool REV, bool DENSE>
-__device__ __forceinline__ void round_body(const RoundArgs &A) {
+__global__ __launch_bounds__(WAVE, 5) void k_round(RoundArgs A) {
     __shared__ WaveStage st;
     __shared__ Advance adv;
     uint32_t scnt = 0;
@@ -840,16 +845,6 @@ __device__ __forceinline__ void round_body(const RoundArgs &A) {
     }
 }
 
-template <bool PULL, bool MEMO, bool REV, bool DENSE>
-__global__ __launch_bounds__(WAVE) void k_round(RoundArgs A) {
-    round_body<PULL, MEMO, REV, DENSE>(A);
-}
-
-// The dense instantiation held to 96 registers (5 waves per SIMD, the
-// occupancy of the sparse one) at the cost of a few spills ("dense_waves5").
-__global__ __launch_bounds__(WAVE, 5) void k_round_dense5(RoundArgs A) {
-    round_body<false, false, false, true>(A);
-}
 
 // The heavy list, relaxed by every wave of the grid: each wave takes whole
 // chunks (at most HEAVY_CHUNK arcs of one vertex), 64 arcs per step. Runs
@@ -1515,13 +1510,6 @@ static hipError_t launch_round_t(const RoundArgs &A, uint32_t grid, hipStream_t 
 }
 
 hipError_t launch_round(const RoundArgs &A, uint32_t grid, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
-    if (A.dbits && A.dense_waves5 && A.in_row_ptr == A.row_ptr && !A.memo) {
-        if (e0)
-            hipExtLaunchKernelGGL(k_round_dense5, dim3(grid), dim3(WAVE), 0, st, e0, e1, 0, A);
-        else
-            k_round_dense5<<<grid, WAVE, 0, st>>>(A);
-        return hipGetLastError();
-    }
     // The default path (symmetric graph, no pull pass, no heuristic memo, no
     // dense frontiers) is compiled without those branches, which would
     // otherwise cost it registers and occupancy. A directed graph has a

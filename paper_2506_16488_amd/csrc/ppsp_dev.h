@@ -175,7 +175,6 @@ struct RoundArgs {
     uint4 *hrec;               // [2][hcap] (hub index, group, first arc, end arc)
     unsigned long long *hgcount;  // [2] records listed per round parity
     uint32_t nhub, ngroups, hgrouped;
-    uint32_t dense_waves5;     // dense rounds: the round kernel compiled for 5 waves per SIMD
     uint32_t *err;             // ERR_* bits
     unsigned long long *stats; // [ST_ROUNDS] rounds run
     unsigned long long *wstats; // [grid][ST_N] per-workgroup counters of the round kernel
