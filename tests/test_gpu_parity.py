@@ -286,17 +286,33 @@ def test_lattice4096_hub_batch_sampled(P):
 
 @pytest.mark.slow
 def test_rmat24_sampled(P):
-    """R-MAT scale 24 (power law, hubs of degree ~400K) with 256 pairs from the
-    largest component, Multi-BiDS; sampled pairs against the oracle."""
+    """R-MAT scale 24 (power law, hubs of degree ~400K) with the benchmark's
+    256 pairs from the largest component: Multi-BiDS, then Plain* BiDS in the
+    benchmark's setting (bucketed threshold, Delta 1433, dense frontiers with
+    a ring of 64) under the fixed and the learned schedule (a network that may
+    switch searches to dense frontiers); sampled pairs against the oracle,
+    all 256 against each other."""
     g = gen.workload_graph("rmat24")
     lcc = gen.lcc(g)
     pairs = gen.workload_pairs("rmat24", g, cand=lcc)
     idx = np.arange(0, 256, 32)
     exp = _oracle(g, pairs[idx])
-    G = _graph(P, g)
+    G = _graph(P, g, reorder=True)
     G.set_option("timeout_ms", 240000)
     got = G.batch_query(pairs, algo="bids", batch="multi")
     assert np.array_equal(got[idx], exp)
+    G.set_option("theta_mode", 1)
+    G.set_option("dense_min", 1 << 18)
+    G.set_option("dense_ring", 64)
+    print("rmat24 plain* tuned setting", flush=True)
+    assert np.array_equal(G.batch_query(pairs, algo="bids", batch="plainstar", delta=1433), got)
+    assert G.stats()["dense_searches"] > 0
+    p = gen.mlp_init(5)
+    p[-9:-1] = np.linspace(-0.5, 0.5, 8)
+    G.mlp_load(p)
+    G.set_option("dense_learned", 1)
+    print("rmat24 learned", flush=True)
+    assert np.array_equal(G.batch_query(pairs, algo="bids", batch="plainstar", delta=1433, sched="learned"), got)
     G.close()
 
 
