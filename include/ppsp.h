@@ -352,7 +352,7 @@ int ppsp_tune(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp_opts *
  *                   fixed batch's (rounds that end before the batch does are
  *                   free). Feature rows are traced along the labelled and the
  *                   default trajectories; training starts from `init`
- *                   (caller-drawn). Fixed-Delta stepping then judges the
+ *                   (caller-drawn). Fixed-Delta stepping then referees the
  *                   result: the sample batch is timed under the trained
  *                   network and under constant networks that always pick the
  *                   base multiplier (bin 4) or, in label_mode 1, the fastest
@@ -360,7 +360,7 @@ int ppsp_tune(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp_opts *
  *                   returned in params_out instead (rep->fallback_bin).
  *                   label_mode 2 (counterfactual): the first three quarters
  *                   of the pairs (all of them below 8 pairs) train, the rest
- *                   judge. Every training pair runs under each fixed bin
+ *                   referee. Every training pair runs under each fixed bin
  *                   (batch time fitted as c0 + c_round * rounds + c_arc *
  *                   arcs + c_entry * frontier entries, non-negative
  *                   coefficients) and under replays that follow the base
@@ -372,7 +372,7 @@ int ppsp_tune(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp_opts *
  *                   batch's), the base (bin 4, sparse) unless another is at
  *                   least 1% cheaper, and it holds until the next switch
  *                   point. "dense_learned" is set when some label chose dense. The rows are the base trajectory's
- *                   features at those decision rounds. The judge times the
+ *                   features at those decision rounds. The referee times the
  *                   held-out pairs under the trained network and through
  *                   the plain fixed-Delta path (base Delta, the graph's
  *                   threshold rule); if the plain path is faster,
@@ -406,12 +406,12 @@ typedef struct {
     /* label_mode 2 (counterfactual replays; see ppsp_mlp_fit) */
     double c_entry_ns;        /* fitted cost of a frontier entry (ns) */
     uint32_t variants;        /* replays run (pair x switch round x bin x frontier mode) */
-    uint32_t heldout;         /* held-out pairs the judge timed */
+    uint32_t heldout;         /* held-out pairs the referee timed */
     double heldout_learned_ms;    /* held-out batch under the trained network (best of two) */
     double heldout_fixed_ms;      /* held-out batch through the plain fixed-Delta path (best of two) */
     double heldout_learned_cost;  /* fitted cost (ms) of the held-out run's rounds, arcs and entries, learned */
     double heldout_fixed_cost;    /* the same for the base multiplier (bin 4) */
-    uint32_t plain_fallback;  /* 1: the plain fixed path won the judge: PPSP_SCHED_LEARNED then runs it */
+    uint32_t plain_fallback;  /* 1: the plain fixed path won the referee's comparison: PPSP_SCHED_LEARNED then runs it */
     uint32_t dense_labels;    /* label_mode 2: (pair, decision round) labels that chose a dense frontier */
 } ppsp_fit_report;
 
@@ -485,7 +485,7 @@ int ppsp_sched_trace_ex(ppsp_graph g, const uint32_t *pairs, uint32_t k, const p
  *                 graph's default), opts[i].sched PPSP_SCHED_FIXED or
  *                 PPSP_SCHED_LEARNED (the network loaded on the graph picks
  *                 every search's step, as in ppsp_batch_query; the plain path
- *                 when the fit's judge chose it); other fields are ignored
+ *                 when the fit's referee chose it); other fields are ignored
  * ppsp_server_submit copies the pairs and returns a request id.
  * ppsp_server_poll returns PPSP_E_BUSY until every query of the request has
  * finished; then it copies the k distances (input order) and the latency

@@ -254,7 +254,7 @@ struct ppsp_graph_s {
     // dense frontiers (options "dense_min" / "dense_force")
     DevBuf dbits, dmode, dbase, dW, dread, docc, dlist, dcount;
     bool mlp_loaded = false;
-    bool ml_plain = false;          // the fit's judge preferred the plain fixed path: LEARNED runs it
+    bool ml_plain = false;          // the fit's referee preferred the plain fixed path: LEARNED runs it
     MlCtx *ml = nullptr;            // set for the duration of a learned or traced call
 };
 
@@ -3256,7 +3256,7 @@ int fit_counterfactual(ppsp_graph g, const uint32_t *pairs, uint32_t k, const pp
                        uint32_t epochs, uint64_t seed, float *params_out, ppsp_fit_report &R) {
     const auto t0 = std::chrono::steady_clock::now();
     const uint32_t kt = k >= 8 ? (3 * k + 3) / 4 : k;             // training pairs
-    const uint32_t *hp = k >= 8 ? pairs + 2ull * kt : pairs;       // held-out pairs of the judge
+    const uint32_t *hp = k >= 8 ? pairs + 2ull * kt : pairs;       // held-out pairs of the referee
     const uint32_t hk = k >= 8 ? k - kt : k;
     ppsp_opts o = *opts;
     o.sched = PPSP_SCHED_FIXED;
@@ -3398,7 +3398,7 @@ int fit_counterfactual(ppsp_graph g, const uint32_t *pairs, uint32_t k, const pp
         }
         R.train_acc = (double)hit / Y.size();
     }
-    // 6. The judge, on held-out pairs: the trained network against the plain
+    // 6. The referee, on held-out pairs: the trained network against the plain
     //    fixed-Delta path (base Delta, the graph's threshold rule). The
     //    network's mode output is used when some label asked for a dense frontier.
     CHK(mlp_load_impl(g, params_out));
@@ -3523,7 +3523,7 @@ int ppsp_mlp_fit(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp_opt
         hit += best == Y[r];
     }
     R.train_acc = Y.empty() ? 0.0 : (double)hit / Y.size();
-    // 5. Fixed-Delta stepping judges the network. The sample batch runs under
+    // 5. Fixed-Delta stepping referees the network. The sample batch runs under
     //    the trained network and under constant networks that always pick the
     //    base multiplier (bin 4) or, with batch labels, the fastest fixed one;
     //    all through the same learned-schedule path. If a constant network is

@@ -166,7 +166,7 @@ def test_fit_recipe(P):
     assert sum(rep["label_hist"]) == 24
     assert rep["rows"] > 0 and rep["loss_last"] <= rep["loss_first"]
     assert 0.0 <= rep["train_acc"] <= 1.0
-    _check_judge(rep, params)
+    _check_referee(rep, params)
     test = gen.pairs_uniform(g.n, 50, seed=84)
     exp = oracle.pp_batch(g.n, g.row_ptr, g.col, g.w, test)
     assert np.array_equal(G.batch_query(test, algo="bidastar", sched="learned"), exp)
@@ -176,12 +176,12 @@ def test_fit_recipe(P):
     assert sum(rep["label_hist"]) == 24 and 0 <= rep["best_fixed_bin"] < 8
     assert rep["c_round_ms"] >= 0 and rep["c_arc_ns"] >= 0
     assert np.array_equal(G.batch_query(test, algo="bidastar", sched="learned"), exp)
-    _check_judge(rep, params)
+    _check_referee(rep, params)
     G.close()
 
 
-def _check_judge(rep, params):
-    """The fixed-Delta judge: either the trained network won on the sample
+def _check_referee(rep, params):
+    """The fixed-Delta referee: either the trained network won on the sample
     batch, or the installed (returned) network is the constant one for the
     faster fixed multiplier."""
     assert rep["learned_ms"] > 0 and rep["fixed_ms"] > 0
@@ -278,7 +278,7 @@ def test_switched_schedule_rows_and_exactness(P):
 def test_counterfactual_fit_on_rmat_gains(P):
     """label_mode 2 on a mid-size R-MAT graph (scale 17) with the bucketed
     threshold rule: the labels come from replays that switch bins at decision
-    rounds, the judge times 12 held-out pairs against the plain fixed path, and
+    rounds, the referee times 12 held-out pairs against the plain fixed path, and
     the trained schedule's fitted cost on those held-out pairs is below the
     base multiplier's. Distances stay exact."""
     g = gen.rmat(17, 16, seed=130)
