@@ -654,10 +654,12 @@ def workload_serve(args):
     tr = Gs[1].tune(rm_sample, algo="bids", batch="plainstar")
     Gs[1].set_option("theta_mode", int(tr["theta_mode"]))
     Gs[1].set_option("heavy_window", int(tr["heavy_window"]))
+    _log("R-MAT tuned: %s" % {k: tr[k] for k in ("delta", "theta_mode", "heavy_window")})
     fits = []
     a = time.perf_counter()
     _, rep0 = Gs[0].mlp_fit(gen.pairs_uniform(hosts[0].n, 32, seed=1103), gen.mlp_init(3), algo="bidastar",
                             epochs=args.epochs, seed=3, labels="counterfactual")
+    _log("lattice schedule fitted in %.1fs" % (time.perf_counter() - a))
     _, rep1 = Gs[1].mlp_fit(rm_sample, gen.mlp_init(4), algo="bids", epochs=args.epochs, seed=4,
                             delta=int(tr["delta"]), labels="counterfactual")
     for rep in (rep0, rep1):
@@ -684,8 +686,9 @@ def workload_serve(args):
     reqs = level_reqs[:args.serve_sat]
     a = time.perf_counter()
     ids = [S.submit(gi, p) for gi, p in reqs]
-    for r in ids:
+    for j, r in enumerate(ids):
         S.wait(r, timeout_ms=1800000)
+        _log("saturation: request %d of %d done" % (j + 1, len(ids)))
     sat_s = time.perf_counter() - a
     nq = sum(p.shape[0] for _, p in reqs)
     sat_rps = len(reqs) / sat_s
@@ -703,16 +706,19 @@ def workload_serve(args):
         a = time.perf_counter()
         t_next = a
         ids = []
-        for (gi, p), gap in zip(reqs, gaps):
+        for j, ((gi, p), gap) in enumerate(zip(reqs, gaps)):
             t_next += gap
             while time.perf_counter() < t_next:
                 time.sleep(0.001)
             ids.append(S.submit(gi, p))
+            if j % 8 == 7:
+                _log("load %.0f%%: %d requests submitted" % (100 * frac, j + 1))
         lats, res = [], []
-        for r in ids:
+        for j, r in enumerate(ids):
             d, lat = S.wait(r, timeout_ms=1800000)
             lats.append(lat)
             res.append(d)
+            _log("load %.0f%%: request %d of %d (%d pairs) done, %.0f ms" % (100 * frac, j + 1, len(ids), d.shape[0], lat))
         wall = time.perf_counter() - a
         lats = np.array(lats)
         q = sum(p.shape[0] for _, p in reqs)
@@ -727,9 +733,10 @@ def workload_serve(args):
         check = (reqs, res)
     S.close()
     # requests of the last level equal their runs alone (the same library, learned schedule)
-    for (gi, p), d in list(zip(*check))[:12]:
+    for j, ((gi, p), d) in enumerate(list(zip(*check))[:12]):
         alone = Gs[gi].batch_query(p, algo=algos[gi], delta=deltas[gi], sched="learned")
         assert np.array_equal(alone, d), "a served request differs from its run alone"
+        _log("request %d equals its run alone" % j)
     small = [(gi, p) for gi, p in check[0] if p.shape[0] <= 8][:4]
     for gi, p in small:
         exp = oracle.pp_batch(hosts[gi].n, hosts[gi].row_ptr, hosts[gi].col, hosts[gi].w, p, nthreads=cpu_threads())
