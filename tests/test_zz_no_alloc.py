@@ -103,3 +103,25 @@ def test_noalloc_rejects_graph_beyond_scratch(P):
     assert e.value.code == P.E_OOM
     assert "scratch" in str(e.value)
     G.close()
+
+
+def test_noalloc_with_graph_options(P):
+    """Options on the graph whose buffers live outside the scratch (dense
+    frontiers, the hub list grouped by vertex) are off inside the call, a
+    grouped state layout runs in the scratch, and the graph's own calls keep
+    the options afterwards; two calls in a row, the second smaller."""
+    g = gen.rmat(13, 16, seed=46)
+    lcc = gen.lcc(g)
+    pairs = gen.pairs_uniform(lcc, 40, seed=47)
+    exp = _exp(g, pairs)
+    G = P.Graph.from_host(g, reorder=True)
+    G.set_option("dense_min", 64)
+    G.set_option("plain_group", 8)
+    for k in (40, 13):
+        print("noalloc options", k, flush=True)
+        assert np.array_equal(G.batch_query_noalloc(pairs[:k], algo="bids"), exp[:k])
+        assert G.stats()["dense_searches"] == 0
+    assert G.get_option("dense_min") == 64 and G.get_option("plain_group") == 8
+    assert np.array_equal(G.batch_query(pairs, algo="bids"), exp)
+    assert G.stats()["dense_searches"] > 0
+    G.close()
