@@ -514,8 +514,8 @@ def main():
     ap.add_argument("--profile-graph", default="rmat24", help="profile: rmat24 or lattice2048")
     ap.add_argument("--schedule", default=None, help="profile: the schedule file a headline run saved")
     ap.add_argument("--save-schedule", default=None, help="rmat24: save the trained schedule (.npz) here")
-    ap.add_argument("--serve-sat", type=int, default=12, help="serve: requests of the saturation run")
-    ap.add_argument("--serve-requests", type=int, default=40, help="serve: requests per load level")
+    ap.add_argument("--serve-requests", type=int, default=24, help="serve: requests per load level (and of the "
+                    "saturation run)")
     ap.add_argument("--serve-budget-gb", type=int, default=160, help="serve: search-state budget (GiB)")
     ap.add_argument("--copy-kernel", action="store_true", help="run the 1 GiB copy used to calibrate counters")
     args = ap.parse_args()
@@ -632,9 +632,9 @@ def workload_serve(args):
     one server, both under their learned step schedule (trained by
     ppsp_mlp_fit on held-out sample pairs); requests of log-uniform size in
     [1, 4096] pairs on either graph (50/50); saturation from requests
-    submitted at once (the first requests of the sequence below), then
-    Poisson arrivals offering 50% and 80% of its query rate, both levels
-    with the same request sequence (so their latencies compare). The
+    submitted at once (the request sequence below), then Poisson arrivals
+    offering 50% and 80% of its query rate, both levels with the same
+    request sequence (so their latencies compare). The
     first 12 requests of the last level are checked against their own runs
     alone."""
     import numpy as np
@@ -683,7 +683,7 @@ def workload_serve(args):
                                                                                       "heavy_window")}}
     # saturation: everything submitted at once
     level_reqs = make_requests(args.serve_requests, 2)
-    reqs = level_reqs[:args.serve_sat]
+    reqs = level_reqs
     a = time.perf_counter()
     ids = [S.submit(gi, p) for gi, p in reqs]
     for j, r in enumerate(ids):
@@ -746,7 +746,7 @@ def workload_serve(args):
         G.close()
     _line(args, "serving: lattice 4096x4096 (BiD-A*) + R-MAT 24 (BiDS, autotuned) resident together, learned "
                 "schedules, requests of log-uniform 1..4096 pairs on either graph, Poisson arrivals at 50%% and 80%% "
-                "of saturation (%d and %d requests per level)" % (args.serve_sat, args.serve_requests),
+                "of the saturation query rate (%d requests per level)" % args.serve_requests,
           out["load_80"]["queries_per_s"], out["load_80"]["p50_ms"], serving=out)
 
 
