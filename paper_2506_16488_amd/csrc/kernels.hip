@@ -848,9 +848,10 @@ __global__ __launch_bounds__(WAVE, 5) void k_round(RoundArgs A) {
 
 // The heavy list, relaxed by every wave of the grid: each wave takes whole
 // chunks (at most HEAVY_CHUNK arcs of one vertex), 64 arcs per step. Runs
-// after k_round in the same round.
+// after k_round in the same round, on the same grid, so it too must keep 5
+// waves per SIMD resident.
 template <bool MEMO, bool REV>
-__global__ __launch_bounds__(WAVE) void k_heavy(RoundArgs A) {
+__global__ __launch_bounds__(WAVE, 5) void k_heavy(RoundArgs A) {
     __shared__ WaveStage st;
     uint32_t scnt = 0;
     const uint32_t r = A.round[1];                          // set by this round's k_round
@@ -862,22 +863,32 @@ __global__ __launch_bounds__(WAVE) void k_heavy(RoundArgs A) {
     uint4 *qout = ((r & 1) ? A.q0 : A.q1) + (uint64_t)sego * A.qseg;
     uint32_t *qcout = &A.qcount[np * NSEG + sego];
     unsigned long long c_succ = 0;
-    for (uint64_t slot = blockIdx.x; slot < nh; slot += gridDim.x) {
-        const uint4 h1 = A.heavy[2 * slot];
-        const uint32_t ee = A.heavy[2 * slot + 1].x;
-        const uint32_t ai = h1.x;
-        const SearchDesc sd = A.sd[ai];
-        const uint64_t bnd = A.ctl[ai].y;
-        const bool dm = A.dbits && A.dmode[ai];
-        for (uint32_t e0 = h1.w; e0 < ee; e0 += WAVE) {
-            const uint32_t e = e0 + lane_id();
-            bool app = false;
-            uint4 ne = make_uint4(0, 0, 0, 0);
-            uint64_t lmin = INF64, kv = INF64;
-            if (e < ee) app = relax_arc<MEMO, REV>(A, sd, ai, h1.y, h1.z, bnd, e, stamp, &ne, &lmin, &c_succ, &kv, dm);
-            if (app && dm && dense_add(A, ai, ne.y, kv)) app = false;
-            wstage_push(st, scnt, app, ne, qout, qcout, A.qseg, A.err);
-            search_stats(A, np, ai, app ? 1u : 0u, lmin, count);
+    // Records are claimed hclaim at a time from a counter (hcount[1], cleared
+    // with the list by the control step), so a wave that drew short records
+    // takes more; every wave leaves once the counter has passed the list.
+    for (;;) {
+        unsigned long long base = 0;
+        if (lane_id() == 0) base = atomicAdd(A.hcount + 1, (unsigned long long)A.hclaim);
+        base = __shfl(base, 0);
+        if (base >= nh) break;
+        const uint64_t end = min((uint64_t)base + A.hclaim, nh);
+        for (uint64_t slot = base; slot < end; slot++) {
+            const uint4 h1 = A.heavy[2 * slot];
+            const uint32_t ee = A.heavy[2 * slot + 1].x;
+            const uint32_t ai = h1.x;
+            const SearchDesc sd = A.sd[ai];
+            const uint64_t bnd = A.ctl[ai].y;
+            const bool dm = A.dbits && A.dmode[ai];
+            for (uint32_t e0 = h1.w; e0 < ee; e0 += WAVE) {
+                const uint32_t e = e0 + lane_id();
+                bool app = false;
+                uint4 ne = make_uint4(0, 0, 0, 0);
+                uint64_t lmin = INF64, kv = INF64;
+                if (e < ee) app = relax_arc<MEMO, REV>(A, sd, ai, h1.y, h1.z, bnd, e, stamp, &ne, &lmin, &c_succ, &kv, dm);
+                if (app && dm && dense_add(A, ai, ne.y, kv)) app = false;
+                wstage_push(st, scnt, app, ne, qout, qcout, A.qseg, A.err);
+                search_stats(A, np, ai, app ? 1u : 0u, lmin, count);
+            }
         }
     }
     wstage_flush(st, scnt, qout, qcout, A.qseg, A.err);
@@ -1088,7 +1099,8 @@ __global__ __launch_bounds__(BLOCK) void k_control(RoundArgs A) {
     }
     if (i == 0) {
         A.round[0] = r + 1;
-        *A.hcount = 0;
+        A.hcount[0] = 0;
+        A.hcount[1] = 0;
         if (A.hgrouped) A.hgcount[np] = 0;       // the list whose bits the hub-list kernel just cleared
     }
     if (i >= A.nsearch) return;
@@ -1171,7 +1183,8 @@ __global__ __launch_bounds__(WAVE) void k_control_ml(RoundArgs A) {
         A.qcount[par * NSEG + lane] = 0;
         if (w) {
             A.round[0] = r + 1;
-            *A.hcount = 0;
+            A.hcount[0] = 0;
+            A.hcount[1] = 0;
             if (A.hgrouped) A.hgcount[np] = 0;   // the list whose bits the hub-list kernel just cleared
         }
     }
