@@ -363,13 +363,16 @@ int ppsp_tune(ppsp_graph g, const uint32_t *pairs, uint32_t k, const ppsp_opts *
  *                   referee. Every training pair runs under each fixed bin
  *                   (batch time fitted as c0 + c_round * rounds + c_arc *
  *                   arcs + c_entry * frontier entries, non-negative
- *                   coefficients) and under replays that follow the base
+ *                   coefficients, with the rounds term whenever a fit with it
+ *                   exists) and under replays that follow the base
  *                   multiplier up to one of six decision rounds spread over
  *                   its run and switch there to each bin, with a sparse or a
  *                   dense frontier; the label of a (pair, decision round) is
  *                   the bin and mode of lowest fitted cost (c_arc * arcs +
  *                   c_entry * entries + c_round * rounds beyond the best fixed
- *                   batch's), the base (bin 4, sparse) unless another is at
+ *                   batch's, plus for a dense frontier the bitmap each of its
+ *                   searches reads every round from the switch on, n / 8
+ *                   bytes at 4 TB/s), the base (bin 4, sparse) unless another is at
  *                   least 1% cheaper, and it holds until the next switch
  *                   point. "dense_learned" is set when some label chose dense. The rows are the base trajectory's
  *                   features at those decision rounds. The referee times the

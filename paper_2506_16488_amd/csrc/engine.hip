@@ -3199,13 +3199,18 @@ namespace {
 
 // Batch time T = c0 + c_r R + c_a A + c_e E by least squares over the fixed
 // bins, with every coefficient non-negative: the best fit among the subsets of
-// (R, A, E) whose own least-squares coefficients are all non-negative.
+// (R, A, E) whose own least-squares coefficients are all non-negative, taken
+// among the subsets with the rounds term whenever one of those qualifies
+// (every round has a cost; rounds and entries both fall as the step grows,
+// and a fit that credits the entries alone labels steps that add rounds).
 void fit_cost4(int nb, const double *T, const double *Rb, const double *Ab, const double *Eb, double &c0, double &cr,
                double &ca, double &ce) {
     double best_err = 1e300;
     c0 = T[0];
     cr = ca = ce = 0;
+    for (int pass = 0; pass < 2 && best_err == 1e300; pass++)
     for (int mask = 0; mask < 8; mask++) {
+        if (pass == 0 && !(mask & 1)) continue;     // first the subsets with the rounds term
         const double *col[3] = {Rb, Ab, Eb};
         int idx[3], m = 0;
         for (int j = 0; j < 3; j++)
@@ -3358,6 +3363,11 @@ int fit_counterfactual(ppsp_graph g, const uint32_t *pairs, uint32_t k, const pp
             const uint32_t v = v0 + b;
             cost[b] = ca * (double)rep.pair_arcs[v] + ce * (double)rep.pair_ent[v] +
                       cr * std::max(0.0, (double)rep.pair_rounds[v] - Rstar);
+            // a dense frontier reads its search's bitmap of n bits every round
+            // from the switch on (two searches), priced at 4 TB/s: a cost the
+            // fixed-bin fit cannot see
+            if (b >= (uint32_t)MLP_K)
+                cost[b] += 2.0 * ((double)g->n / 8.0) / 4e9 * std::max(0.0, (double)rep.pair_rounds[v] - vr[v]);
         }
         uint32_t lb = MLP_K / 2;
         for (uint32_t b = 0; b < NVAR; b++)
