@@ -235,7 +235,7 @@ struct ppsp_graph_s {
             opt_ml_every = 4, opt_heavy_window = 64, opt_multi_group = 32, opt_rho = 4096, opt_local = 16, opt_local_plain = 0, opt_local_fill = 0,
             opt_min_chunk = 16, opt_local_small = 4, opt_local_pct = 90, opt_defer_pct = 105,
             opt_server_round_base = 0, opt_dense_min = 0, opt_dense_force = 0, opt_dense_ring = 16,
-            opt_dense_learned = 0, opt_plain_group = 2, opt_heavy_grouped = 1, opt_heavy_claim = 2, opt_dense_claim = 0;
+            opt_dense_learned = 0, opt_plain_group = 2, opt_heavy_grouped = 1, opt_heavy_claim = 2;
     uint64_t wmean = 1;             // mean arc weight (rounded up)
     uint64_t fingerprint = 0;       // hash of the CSR, keys the tuning cache
     struct Tuned {
@@ -614,7 +614,6 @@ int run_wave(ppsp_graph g, const Plan &P, bool want_path, WaveOut &out) {
             A.dense_min = g->opt_dense_min > 0 ? (uint64_t)g->opt_dense_min : ~0ull;
             A.dring = dense_ring(g);
             A.dense_force = g->opt_dense_force ? 1u : 0u;
-            A.dclaim = (uint32_t)g->opt_dense_claim;
         }
         if (A.sc && A.ml_mode == 1 && !P.sw_round.empty()) {
             A.bin_after = g->bin_after.as<uint8_t>();
@@ -2863,10 +2862,6 @@ int ppsp_set_option(ppsp_graph g, const char *name, int64_t v) {
         if (v < 1 || v > 64) return PPSP_E_INVALID;
         g->opt_heavy_claim = v;
     }
-    else if (k == "dense_claim") {
-        if (v < 0 || v > 4096) return PPSP_E_INVALID;
-        g->opt_dense_claim = v;
-    }
 
     else if (k == "server_round_base") {
         if (v < 0 || v >= (int64_t)SRV_ROUND_LIMIT) return PPSP_E_INVALID;
@@ -2903,7 +2898,6 @@ int ppsp_get_option(ppsp_graph g, const char *name, int64_t *v) {
     else if (k == "plain_group") *v = g->opt_plain_group;
     else if (k == "heavy_grouped") *v = g->opt_heavy_grouped;
     else if (k == "heavy_claim") *v = g->opt_heavy_claim;
-    else if (k == "dense_claim") *v = g->opt_dense_claim;
 
     else if (k == "rho") *v = g->opt_rho;
     else if (k == "local_chunks") *v = g->opt_local;

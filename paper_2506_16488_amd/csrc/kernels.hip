@@ -386,11 +386,7 @@ __global__ __launch_bounds__(WAVE, 5) void k_round(RoundArgs A) {
     const uint32_t ndense = DENSE ? A.dcount[par] : 0u;
     const uint64_t tiles_per = DENSE ? (A.dwords + WAVE - 1) / WAVE : 1ull;
     const uint64_t dtiles = (uint64_t)ndense * tiles_per;
-    // Tiles go to waves by a static stride over the grid, or (dclaim > 0)
-    // dclaim at a time from the round's counter dcount[3], cleared by the
-    // control step.
-    const uint32_t dclaim = DENSE ? A.dclaim : 0u;
-    uint64_t dt = dclaim ? 0 : blockIdx.x, dend = 0, dwidx = 0;
+    uint64_t dt = blockIdx.x, dwidx = 0;
     uint32_t dword = 0, dsi = 0;
     if (DENSE && blockIdx.x == 0 && lane_id() == 0) {
         A.dcount[np] = 0;                                  // the list the control step builds next
@@ -483,22 +479,11 @@ __global__ __launch_bounds__(WAVE, 5) void k_round(RoundArgs A) {
             }
         } else if (DENSE && (__any(dword != 0) || dt < dtiles)) {
             if (!__any(dword != 0)) {
-                if (dclaim && dt >= dend) {
-                    uint32_t base = 0;
-                    if (lane_id() == 0) base = atomicAdd(&A.dcount[3], dclaim);
-                    base = __shfl(base, 0);
-                    dt = base;
-                    dend = min((uint64_t)base + dclaim, dtiles);
-                    if (dt >= dtiles) {
-                        dt = dtiles;                       // the list is taken: this wave is done
-                        continue;
-                    }
-                }
                 // the next tile; its words are cleared as they are read (no adds
                 // go to a read bitmap: refills of the current bucket use the other one)
                 dsi = A.dlist[(uint64_t)par * A.nsearch + dt / tiles_per];
                 dwidx = (dt % tiles_per) * WAVE + lane_id();
-                dt += dclaim ? 1 : gridDim.x;
+                dt += gridDim.x;
                 dword = 0;
                 if (dwidx < A.dwords) {
                     uint32_t *wp = A.dbits + ((uint64_t)dsi * (A.dring + 1) + A.dread[dsi]) * A.dwords + dwidx;
@@ -1200,7 +1185,6 @@ __global__ __launch_bounds__(WAVE) void k_control_ml(RoundArgs A) {
             A.round[0] = r + 1;
             A.hcount[0] = 0;
             A.hcount[1] = 0;
-            if (A.dbits) A.dcount[3] = 0;            // the dense tiles' claim counter
             if (A.hgrouped) A.hgcount[np] = 0;   // the list whose bits the hub-list kernel just cleared
         }
     }

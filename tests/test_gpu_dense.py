@@ -191,30 +191,3 @@ def test_dense_autotuned_setting_is_exact(P):
     assert tr["dense_ring"] in (16, 32, 64) and tr["dense_min"] in (0, 1 << 16, 1 << 18), tr
     assert np.array_equal(G.batch_query(pairs, algo="bids", sched="autotuned"), exp)
     G.close()
-
-
-@pytest.mark.parametrize("claim", [1, 7, 64])
-def test_dense_tile_claims(P, claim):
-    """Dense bitmap tiles claimed from a counter (option dense_claim) instead
-    of a static stride: exact on a lattice and on R-MAT with hubs."""
-    g = gen.lattice(110, 0.05, seed=192)
-    pairs = gen.pairs_uniform(g.n, 30, seed=193)
-    G = P.Graph.from_host(g)
-    G.set_option("timeout_ms", 60000)
-    G.set_option("dense_force", 1)
-    G.set_option("dense_claim", claim)
-    assert G.get_option("dense_claim") == claim
-    print("dense claims lattice", claim, flush=True)
-    assert np.array_equal(G.batch_query(pairs, algo="bidastar"), _exp(g, pairs))
-    G.close()
-    r = gen.rmat(14, 16, seed=194)
-    rp = np.concatenate([gen.pairs_uniform(gen.lcc(r), 30, seed=195), gen.pairs_uniform(r.n, 8, seed=196)])
-    G = P.Graph.from_host(r, reorder=True)
-    G.set_option("timeout_ms", 60000)
-    G.set_option("dense_min", 64)
-    G.set_option("dense_claim", claim)
-    G.set_option("theta_mode", 1)
-    print("dense claims rmat", claim, flush=True)
-    assert np.array_equal(G.batch_query(rp, algo="bids", delta=2000), _exp(r, rp))
-    assert G.stats()["dense_searches"] > 0
-    G.close()
