@@ -655,17 +655,27 @@ def workload_serve(args):
     Gs[1].set_option("theta_mode", int(tr["theta_mode"]))
     Gs[1].set_option("heavy_window", int(tr["heavy_window"]))
     _log("R-MAT tuned: %s" % {k: tr[k] for k in ("delta", "theta_mode", "heavy_window")})
+    # served graphs run sparse frontiers; the tuned step may have been chosen with dense ones,
+    # so it and two wider steps are timed again on the sample without them
+    sparse_check = []
+    for d in (int(tr["delta"]), 2 * int(tr["delta"]), 4 * int(tr["delta"])):
+        Gs[1].batch_query(rm_sample, algo="bids", delta=d)
+        a = time.perf_counter()
+        Gs[1].batch_query(rm_sample, algo="bids", delta=d)
+        sparse_check.append([d, round(1000.0 * (time.perf_counter() - a), 1)])
+    d_srv = min(sparse_check, key=lambda x: x[1])[0]
+    _log("served R-MAT step (sparse frontiers): %d from %s" % (d_srv, sparse_check))
     fits = []
     a = time.perf_counter()
     _, rep0 = Gs[0].mlp_fit(gen.pairs_uniform(hosts[0].n, 32, seed=1103), gen.mlp_init(3), algo="bidastar",
                             epochs=args.epochs, seed=3, labels="counterfactual")
     _log("lattice schedule fitted in %.1fs" % (time.perf_counter() - a))
     _, rep1 = Gs[1].mlp_fit(rm_sample, gen.mlp_init(4), algo="bids", epochs=args.epochs, seed=4,
-                            delta=int(tr["delta"]), labels="counterfactual")
+                            delta=d_srv, labels="counterfactual")
     for rep in (rep0, rep1):
         fits.append({k: rep[k] for k in ("label_hist", "heldout_learned_ms", "heldout_fixed_ms", "plain_fallback")})
     _log("schedules fitted in %.1fs: %s" % (time.perf_counter() - a, fits))
-    deltas = [0, int(tr["delta"])]
+    deltas = [0, d_srv]
     algos = ["bidastar", "bids"]
 
     def make_requests(k, seed):
@@ -679,8 +689,9 @@ def workload_serve(args):
         return out
 
     S = P.Server(Gs, algo=algos, delta=deltas, sched="learned", state_budget_bytes=args.serve_budget_gb << 30)
-    out = {"slots": S.stats()["slots"], "fits": fits, "tuned_rmat": {k: tr[k] for k in ("delta", "theta_mode",
-                                                                                      "heavy_window")}}
+    out = {"slots": S.stats()["slots"], "fits": fits,
+           "tuned_rmat": {k: tr[k] for k in ("delta", "theta_mode", "heavy_window", "dense_min")},
+           "served_rmat_delta": d_srv, "sparse_step_check_ms": sparse_check}
     # saturation: everything submitted at once
     level_reqs = make_requests(args.serve_requests, 2)
     reqs = level_reqs
