@@ -559,10 +559,6 @@ int ppsp_last_stats(ppsp_graph g, ppsp_stats *stats);
  *   "plain_group"     bidirectional Plain* state layout: the words of a vertex for this many
  *                     searches (half as many queries) side by side (a power of two, 2 to 64;
  *                     default 2: one query's forward and backward copies)
- *   "live_bound"      1 (default): a search with one query (Plain, Plain*, one-sided) prunes
- *                     with that query's meeting distance as it stands when the vertex is
- *                     extracted and when a hub's arcs are relaxed, not only with the bound
- *                     of the round's start; 0: the round's bound
  *   "heavy_claim"     hub-list records (chunks of at most 2,048 arcs) a wave of the hub-list
  *                     kernel claims at a time from a shared counter (1 to 64; default 2)
  *   "heavy_grouped"   1 (default): on a symmetric graph with vertices of degree > 512 and a

@@ -208,17 +208,6 @@ __device__ __forceinline__ void wave_add_keyed(unsigned long long *ctr, uint32_t
 // atomic), then Prune(v) and Add(v). Returns true if v^(i) must be added to
 // the next frontier; *out is that entry. *lmin takes the key of every
 // unpruned decrease (added now or by an earlier decrease of this round).
-// The pruning bound of a search with one query (Plain, Plain*, one-sided
-// searches) from that query's meeting distance as it stands now, never above
-// the round's bound: every meeting value is the length of a path, so any of
-// them bounds the distance, and the sequential algorithm of the paper prunes
-// with mu as updated during the round. Off (live_bound = 0): the round's bound.
-__device__ __forceinline__ uint64_t live_bound(const RoundArgs &A, const SearchDesc &sd, uint64_t bnd) {
-    if (!A.live_bound || sd.noprune || sd.pend != sd.pbeg + 1) return bnd;
-    const uint32_t m = (uint32_t)(A.mu[A.partners[sd.pbeg].pair] >> 32);
-    return (m != INF32 && (uint64_t)m < bnd) ? (uint64_t)m : bnd;
-}
-
 template <bool MEMO>
 __device__ __forceinline__ bool relax_commit(const RoundArgs &A, const SearchDesc &sd, uint32_t i, uint32_t v,
                                              uint64_t cand, uint64_t other, uint64_t old, uint64_t bnd,
@@ -552,7 +541,6 @@ __global__ __launch_bounds__(WAVE, 5) void k_round(RoundArgs A) {
                 action = 1;
             } else if (bnd != 0) {
                 const SearchDesc sd = A.sd[i];
-                bnd = live_bound(A, sd, bnd);
                 uint64_t word;
                 uint32_t dp = INF32;
                 unsigned long long *wp;
@@ -678,7 +666,7 @@ __global__ __launch_bounds__(WAVE, 5) void k_round(RoundArgs A) {
                     A.hrec[(uint64_t)par * A.hcap + slot] = make_uint4(hid, grp, eb, ee);
                 } else {
                     A.heavy[2 * slot] = make_uint4(si, ent.y, du, eb);
-                    A.heavy[2 * slot + 1] = make_uint4(ee, (uint32_t)key, (uint32_t)(key >> 32), 0u);
+                    A.heavy[2 * slot + 1] = make_uint4(ee, 0u, 0u, 0u);
                 }
             }
         }
@@ -886,14 +874,10 @@ __global__ __launch_bounds__(WAVE, 5) void k_heavy(RoundArgs A) {
         const uint64_t end = min((uint64_t)base + A.hclaim, nh);
         for (uint64_t slot = base; slot < end; slot++) {
             const uint4 h1 = A.heavy[2 * slot];
-            const uint4 h2 = A.heavy[2 * slot + 1];
-            const uint32_t ee = h2.x;
+            const uint32_t ee = A.heavy[2 * slot + 1].x;
             const uint32_t ai = h1.x;
             const SearchDesc sd = A.sd[ai];
-            const uint64_t bnd = live_bound(A, sd, A.ctl[ai].y);
-            // the hub's key against the bound as it stands now: a meeting found
-            // since the hub was extracted may prune it (Prune(u)), arcs and all
-            if (((uint64_t)h2.z << 32 | h2.y) >= bnd) continue;
+            const uint64_t bnd = A.ctl[ai].y;
             const bool dm = A.dbits && A.dmode[ai];
             for (uint32_t e0 = h1.w; e0 < ee; e0 += WAVE) {
                 const uint32_t e = e0 + lane_id();

@@ -159,10 +159,9 @@ struct RoundArgs {
     uint64_t qseg;             // capacity of one segment (entries)
     uint32_t *round;           // [0] round to run next (read by k_round), [1] round just run (k_control)
     uint4 *heavy;              // [hcap][2] arc chunks of this round's extracted high-degree vertices:
-                               //   (search, vertex, distance, first arc), (end arc, key low, key high, 0)
+                               //   (search, vertex, distance, first arc), (end arc, 0, 0, 0)
     unsigned long long *hcount;  // [0] chunks written this round, [1] claim counter of the hub-list kernel
     uint32_t hclaim;           // hub-list records a wave claims at a time
-    uint32_t live_bound;       // 1: single-query searches prune with their query's current mu
     uint32_t hcap;             // heavy list capacity (chunks); 0 = no heavy path
     // The hub list grouped by vertex (hgrouped = 1: a symmetric graph with
     // state groups of G >= 4 searches). The searches of one group that
