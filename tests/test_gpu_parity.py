@@ -270,8 +270,8 @@ def test_overflow_retries_keep_results_exact(P):
 @pytest.mark.parametrize("claim", [1, 3, 64])
 def test_heavy_claim_sizes(P, claim):
     """The hub-list kernel's records claimed 1, 3 or 64 at a time (option
-    heavy_claim), with and without dense frontiers and with a hub list too
-    small for a round (overflow reruns): the oracle's distances."""
+    heavy_claim), with and without dense frontiers and with frontier queues
+    too small for a round (overflow reruns): the oracle's distances."""
     g = gen.rmat(14, 16, seed=79)
     lcc = gen.lcc(g)
     pairs = np.concatenate([gen.pairs_uniform(lcc, 60, seed=80), gen.pairs_uniform(g.n, 10, seed=81)])
@@ -284,7 +284,7 @@ def test_heavy_claim_sizes(P, claim):
     G.set_option("dense_min", 64)
     G.set_option("theta_mode", 1)
     assert np.array_equal(G.batch_query(pairs, algo="bids", delta=1500), exp)
-    G.set_option("heavy_cap", 4)
+    G.set_option("queue_cap", 4096)
     assert np.array_equal(G.batch_query(pairs, algo="bids", delta=1500), exp)
     assert G.stats()["retries"] > 0
     for bad in (0, 65):
