@@ -235,7 +235,7 @@ struct ppsp_graph_s {
             opt_ml_every = 4, opt_heavy_window = 64, opt_multi_group = 32, opt_rho = 4096, opt_local = 16, opt_local_plain = 0, opt_local_fill = 0,
             opt_min_chunk = 16, opt_local_small = 4, opt_local_pct = 90, opt_defer_pct = 105,
             opt_server_round_base = 0, opt_dense_min = 0, opt_dense_force = 0, opt_dense_ring = 16,
-            opt_dense_learned = 0, opt_plain_group = 2, opt_heavy_grouped = 1, opt_heavy_claim = 2;
+            opt_dense_learned = 0, opt_plain_group = 2, opt_heavy_grouped = 1, opt_heavy_claim = 2, opt_list_deg = HEAVY_DEG;
     uint64_t wmean = 1;             // mean arc weight (rounded up)
     uint64_t fingerprint = 0;       // hash of the CSR, keys the tuning cache
     struct Tuned {
@@ -369,6 +369,7 @@ void set_args(ppsp_graph g, RoundArgs &A, uint32_t nsearch, uint32_t npair, uint
     A.hcount = g->hcount.as<unsigned long long>();
     A.hcap = g->maxdeg > HEAVY_DEG ? g->hcap : 0;
     A.hclaim = (uint32_t)g->opt_heavy_claim;
+    A.list_deg = t_arena ? HEAVY_DEG : (uint32_t)g->opt_list_deg;
     A.hlim = g->hlim.as<uint64_t>();
     A.hwin = (uint32_t)g->opt_heavy_window;
     A.local = (uint32_t)g->opt_local;
@@ -582,6 +583,7 @@ int run_wave(ppsp_graph g, const Plan &P, bool want_path, WaveOut &out) {
         set_args(g, A, ns, npair, P.G, P.pair2);
         if (hgrouped) {
             A.hgrouped = 1;
+            A.list_deg = HEAVY_DEG;              // grouped records index the hubs
             A.hub_id = g->hub_id.as<uint32_t>();
             A.hub_vert = g->hub_vert.as<uint32_t>();
             A.hmask = g->hmask.as<unsigned long long>();
@@ -2862,6 +2864,10 @@ int ppsp_set_option(ppsp_graph g, const char *name, int64_t v) {
         if (v < 1 || v > 64) return PPSP_E_INVALID;
         g->opt_heavy_claim = v;
     }
+    else if (k == "list_deg") {
+        if (v < 16 || v > (int64_t)HEAVY_DEG) return PPSP_E_INVALID;
+        g->opt_list_deg = v;
+    }
 
     else if (k == "server_round_base") {
         if (v < 0 || v >= (int64_t)SRV_ROUND_LIMIT) return PPSP_E_INVALID;
@@ -2898,6 +2904,7 @@ int ppsp_get_option(ppsp_graph g, const char *name, int64_t *v) {
     else if (k == "plain_group") *v = g->opt_plain_group;
     else if (k == "heavy_grouped") *v = g->opt_heavy_grouped;
     else if (k == "heavy_claim") *v = g->opt_heavy_claim;
+    else if (k == "list_deg") *v = g->opt_list_deg;
 
     else if (k == "rho") *v = g->opt_rho;
     else if (k == "local_chunks") *v = g->opt_local;

@@ -635,7 +635,7 @@ __global__ __launch_bounds__(WAVE, 5) void k_round(RoundArgs A) {
         // High-degree vertices go to the heavy list as chunks of at most
         // HEAVY_CHUNK arcs, which all waves of k_heavy share; one atomic per
         // wave reserves the wave's chunks.
-        const bool heavy = action == 2 && A.hcap && re - rb > HEAVY_DEG;
+        const bool heavy = action == 2 && A.hcap && re - rb > A.list_deg;
         if (__ballot(heavy)) {
             uint32_t nck = heavy ? (re - rb + HEAVY_CHUNK - 1) / HEAVY_CHUNK : 0u;
             if (heavy) {

@@ -162,6 +162,7 @@ struct RoundArgs {
                                //   (search, vertex, distance, first arc), (end arc, 0, 0, 0)
     unsigned long long *hcount;  // [0] chunks written this round, [1] claim counter of the hub-list kernel
     uint32_t hclaim;           // hub-list records a wave claims at a time
+    uint32_t list_deg;         // extracted vertices of higher degree go to the hub list (at most HEAVY_DEG)
     uint32_t hcap;             // heavy list capacity (chunks); 0 = no heavy path
     // The hub list grouped by vertex (hgrouped = 1: a symmetric graph with
     // state groups of G >= 4 searches). The searches of one group that
