@@ -559,8 +559,13 @@ int ppsp_last_stats(ppsp_graph g, ppsp_stats *stats);
  *   "plain_group"     bidirectional Plain* state layout: the words of a vertex for this many
  *                     searches (half as many queries) side by side (a power of two, 2 to 64;
  *                     default 2: one query's forward and backward copies)
+ *   "list_deg"        extracted vertices of higher degree have their arcs relaxed by the
+ *                     hub-list kernel, in chunks of at most 2,048 arcs shared by all waves (16 to
+ *                     512; default 128; vertices above 512 also wait for the low end of the
+ *                     step window, "heavy_window"); graphs without a vertex above 512 have no
+ *                     hub list
  *   "heavy_claim"     hub-list records (chunks of at most 2,048 arcs) a wave of the hub-list
- *                     kernel claims at a time from a shared counter (1 to 64; default 2)
+ *                     kernel claims at a time from a shared counter (1 to 64; default 4)
  *   "heavy_grouped"   1 (default): on a symmetric graph with vertices of degree > 512 and a
  *                     state layout of 4 or more searches per group ("plain_group",
  *                     "multi_group"), the hub-list kernel relaxes each chunk of a hub's

@@ -223,6 +223,7 @@ struct ppsp_graph_s {
         stats, wstats, pathlen, pathoff, pathbuf, heavy, hcount, hlim, memo;
     uint32_t maxdeg = 0;
     uint64_t hchunks = 0;           // heavy-list chunks of all vertices of degree > HEAVY_DEG
+    uint64_t hchunks_at[6] = {};    // the same for degree > 16 << k (k = 0..5), for the "list_deg" option
     uint32_t hcap = 0;              // heavy list capacity (0 while no vertex exceeds HEAVY_DEG)
     hipStream_t st = nullptr;
     uint32_t *h_poll = nullptr;     // pinned
@@ -235,7 +236,7 @@ struct ppsp_graph_s {
             opt_ml_every = 4, opt_heavy_window = 64, opt_multi_group = 32, opt_rho = 4096, opt_local = 16, opt_local_plain = 0, opt_local_fill = 0,
             opt_min_chunk = 16, opt_local_small = 4, opt_local_pct = 90, opt_defer_pct = 105,
             opt_server_round_base = 0, opt_dense_min = 0, opt_dense_force = 0, opt_dense_ring = 16,
-            opt_dense_learned = 0, opt_plain_group = 2, opt_heavy_grouped = 1, opt_heavy_claim = 2, opt_list_deg = HEAVY_DEG;
+            opt_dense_learned = 0, opt_plain_group = 2, opt_heavy_grouped = 1, opt_heavy_claim = 4, opt_list_deg = 128;
     uint64_t wmean = 1;             // mean arc weight (rounded up)
     uint64_t fingerprint = 0;       // hash of the CSR, keys the tuning cache
     struct Tuned {
@@ -303,6 +304,14 @@ uint32_t dense_ring(ppsp_graph g) { return (uint32_t)g->opt_dense_ring; }
 
 // 32-bit words of one dense bitmap.
 uint64_t dense_words(ppsp_graph g) { return ((uint64_t)g->n + 31) / 32; }
+
+// Hub-list chunks of the vertices that go to the list (degree above
+// "list_deg", rounded down to 16 << k: never fewer than the list can hold).
+uint64_t list_chunks(ppsp_graph g) {
+    int k = 0;
+    while (k < 5 && (16ll << (k + 1)) <= g->opt_list_deg) k++;
+    return g->hchunks_at[k];
+}
 
 // Bytes of search state per search (where dense frontiers may be used: by
 // size, by the learned schedule's mode output or by traced switches, plus
@@ -450,8 +459,9 @@ int run_wave(ppsp_graph g, const Plan &P, bool want_path, WaveOut &out) {
     if (g->maxdeg > HEAVY_DEG) {
         // a round can extract each hub once per search; a quarter of that at once is ample
         // (inside the no-allocation scratch: a quarter of the hub chunks, at least 4,096)
-        const uint64_t want = t_arena ? std::max<uint64_t>(4096, (uint64_t)ns * g->hchunks / 4)
-                                      : std::min<uint64_t>(1u << 26, std::max<uint64_t>(1u << 20, (uint64_t)ns * g->hchunks / 4));
+        const uint64_t chunks = t_arena ? g->hchunks : list_chunks(g);
+        const uint64_t want = t_arena ? std::max<uint64_t>(4096, (uint64_t)ns * chunks / 4)
+                                      : std::min<uint64_t>(1u << 26, std::max<uint64_t>(1u << 20, (uint64_t)ns * chunks / 4));
         if (g->hcap < want || t_arena) g->hcap = (uint32_t)std::min<uint64_t>(want, 1u << 28);
         CHK(ensure(g->heavy, (uint64_t)g->hcap * 32));
     }
@@ -1848,7 +1858,7 @@ int srv_setup_graph(ppsp_server srv, SrvGraph &G, const ppsp_opts &o, uint64_t b
     CHK(ensure(g->round, 16));
     CHK(ensure(g->hcount, 16));
     if (g->maxdeg > HEAVY_DEG) {
-        const uint64_t want = std::min<uint64_t>(1u << 26, std::max<uint64_t>(1u << 20, (uint64_t)ns * g->hchunks / 4));
+        const uint64_t want = std::min<uint64_t>(1u << 26, std::max<uint64_t>(1u << 20, (uint64_t)ns * list_chunks(g) / 4));
         if (g->hcap < want) g->hcap = (uint32_t)want;
         CHK(ensure(g->heavy, (uint64_t)g->hcap * 32));
     }
@@ -2199,11 +2209,13 @@ int ppsp_graph_create(int device, uint32_t n, uint64_t m, const uint64_t *row_pt
     }
     if (m == 0) wmin = wmax = 1;
     uint32_t maxdeg = 0;
-    uint64_t hchunks = 0;
+    uint64_t hchunks = 0, hchunks_at[6] = {};
     for (uint32_t v = 0; v < n; v++) {
         const uint64_t d = row_ptr[v + 1] - row_ptr[v];
         maxdeg = std::max<uint32_t>(maxdeg, (uint32_t)d);
         if (d > HEAVY_DEG) hchunks += (d + HEAVY_CHUNK - 1) / HEAVY_CHUNK;
+        for (int k = 0; k < 6; k++)
+            if (d > (16ull << k)) hchunks_at[k] += (d + HEAVY_CHUNK - 1) / HEAVY_CHUNK;
     }
     if (coord_fx && coord_frac_bits > 30) return PPSP_E_RANGE;
     ppsp_graph g = new ppsp_graph_s();
@@ -2227,6 +2239,7 @@ int ppsp_graph_create(int device, uint32_t n, uint64_t m, const uint64_t *row_pt
     }
     g->maxdeg = maxdeg;
     g->hchunks = hchunks;
+    for (int k = 0; k < 6; k++) g->hchunks_at[k] = hchunks_at[k];
     auto fail = [&](int rc) {
         ppsp_graph_destroy(g);
         return rc;

@@ -267,6 +267,31 @@ def test_overflow_retries_keep_results_exact(P):
     G.close()
 
 
+@pytest.mark.parametrize("list_deg", [16, 100, 512])
+def test_hub_list_degree_threshold(P, list_deg):
+    """Vertices above list_deg degree relax their arcs through the hub-list
+    kernel (16: nearly all of them; 512: only the hubs): the oracle's
+    distances in every strategy that uses the list, paths included."""
+    g = gen.rmat(13, 16, seed=82)
+    lcc = gen.lcc(g)
+    pairs = np.concatenate([gen.pairs_uniform(lcc, 50, seed=83), gen.pairs_uniform(g.n, 8, seed=84)])
+    exp = _oracle(g, pairs)
+    G = _graph(P, g, reorder=True)
+    G.set_option("list_deg", list_deg)
+    assert G.get_option("list_deg") == list_deg
+    print("list_deg", list_deg, flush=True)
+    for algo in ["bids", "et", "sssp"]:
+        assert np.array_equal(G.batch_query(pairs, algo=algo), exp), algo
+    assert G.stats()["heavy_arcs"] > 0
+    assert np.array_equal(G.batch_query(pairs, algo="bids", batch="multi"), exp)
+    dist, (off, vtx) = G.batch_query(pairs[:20], algo="bids", want_path=True)
+    _check_paths(g, pairs[:20], dist, off, vtx)
+    for bad in (15, 513):
+        with pytest.raises(P.PPSPError):
+            G.set_option("list_deg", bad)
+    G.close()
+
+
 @pytest.mark.parametrize("claim", [1, 3, 64])
 def test_heavy_claim_sizes(P, claim):
     """The hub-list kernel's records claimed 1, 3 or 64 at a time (option
