@@ -236,7 +236,7 @@ struct ppsp_graph_s {
             opt_ml_every = 4, opt_heavy_window = 64, opt_multi_group = 32, opt_rho = 4096, opt_local = 16, opt_local_plain = 0, opt_local_fill = 0,
             opt_min_chunk = 16, opt_local_small = 4, opt_local_pct = 90, opt_defer_pct = 105,
             opt_server_round_base = 0, opt_dense_min = 0, opt_dense_force = 0, opt_dense_ring = 16,
-            opt_dense_learned = 0, opt_plain_group = 2, opt_heavy_grouped = 1, opt_heavy_claim = 4, opt_list_deg = 128;
+            opt_dense_learned = 0, opt_plain_group = 2, opt_heavy_grouped = 1, opt_heavy_claim = 4, opt_list_deg = 128, opt_heavy_waves = 0;
     uint64_t wmean = 1;             // mean arc weight (rounded up)
     uint64_t fingerprint = 0;       // hash of the CSR, keys the tuning cache
     struct Tuned {
@@ -286,6 +286,12 @@ void arena_reset(ppsp_graph g) {
 // per unit gave 5,240, 5,320 and 5,360 queries/s.
 uint32_t round_grid(ppsp_graph g) {
     return g->opt_grid_blocks > 0 ? (uint32_t)g->opt_grid_blocks : (uint32_t)(20 * g->cu);
+}
+
+// The hub-list kernel takes its records from a counter, so its grid is free
+// of the round kernel's (option "heavy_waves": single-wave workgroups per CU).
+uint32_t heavy_grid(ppsp_graph g) {
+    return g->opt_heavy_waves > 0 ? (uint32_t)(g->opt_heavy_waves * g->cu) : round_grid(g);
 }
 
 uint64_t key_delta(uint32_t kind, uint64_t d) {
@@ -496,7 +502,9 @@ int run_wave(ppsp_graph g, const Plan &P, bool want_path, WaveOut &out) {
         if (g->qcap < want && g->opt_queue_cap == 0) g->qcap = want;
     }
     const uint32_t grid = round_grid(g);
-    CHK(ensure(g->wstats, (uint64_t)grid * ST_N * 8));
+    // per-workgroup counters of both relaxing kernels (the hub-list kernel's grid may be larger)
+    const uint32_t wgrid = std::max(grid, heavy_grid(g));
+    CHK(ensure(g->wstats, (uint64_t)wgrid * ST_N * 8));
     if (t_arena) {
         // the two frontier queues take what the scratch has left (up to the usual size)
         const uint64_t used = ((t_arena->off + 255) & ~255ull) + 512;
@@ -525,7 +533,7 @@ int run_wave(ppsp_graph g, const Plan &P, bool want_path, WaveOut &out) {
         HIPCHK(hipMemsetAsync(g->mu.p, 0xFF, npair * 8, st));
         HIPCHK(hipMemsetAsync(g->qcount.p, 0, 2 * NSEG * 4, st));
         HIPCHK(hipMemsetAsync(g->tsum.p, 0, 48, st));
-        HIPCHK(hipMemsetAsync(g->wstats.p, 0, (uint64_t)grid * ST_N * 8, st));
+        HIPCHK(hipMemsetAsync(g->wstats.p, 0, (uint64_t)wgrid * ST_N * 8, st));
         HIPCHK(hipMemsetAsync(g->round.p, 0, 16, st));
         HIPCHK(hipMemsetAsync(g->hcount.p, 0, 16, st));
         HIPCHK(hipMemsetAsync(g->err.p, 0, 16, st));
@@ -670,7 +678,7 @@ int run_wave(ppsp_graph g, const Plan &P, bool want_path, WaveOut &out) {
             hipError_t le = hipSuccess;
             for (int k = 0; k < Kg && le == hipSuccess; k++) {
                 le = launch_round(A, grid, st);
-                if (le == hipSuccess && A.hcap) le = launch_heavy(A, grid, st);
+                if (le == hipSuccess && A.hcap) le = launch_heavy(A, heavy_grid(g), st);
                 if (le == hipSuccess) le = launch_control(A, st);
             }
             const hipError_t ee = hipStreamEndCapture(st, &graph);
@@ -696,11 +704,11 @@ int run_wave(ppsp_graph g, const Plan &P, bool want_path, WaveOut &out) {
                     if (prof && r % every == 0) {
                         // the round and hub-list kernels of this round carry their own events
                         HIPCHK(launch_round(A, grid, st, g->ev[4 * nt], g->ev[4 * nt + 1]));
-                        if (A.hcap) HIPCHK(launch_heavy(A, grid, st, g->ev[4 * nt + 2], g->ev[4 * nt + 3]));
+                        if (A.hcap) HIPCHK(launch_heavy(A, heavy_grid(g), st, g->ev[4 * nt + 2], g->ev[4 * nt + 3]));
                         nt++;
                     } else {
                         HIPCHK(launch_round(A, grid, st));
-                        if (A.hcap) HIPCHK(launch_heavy(A, grid, st));
+                        if (A.hcap) HIPCHK(launch_heavy(A, heavy_grid(g), st));
                     }
                     HIPCHK(launch_control(A, st));
                 }
@@ -757,10 +765,10 @@ int run_wave(ppsp_graph g, const Plan &P, bool want_path, WaveOut &out) {
         out.mu.resize(npair);
         HIPCHK(hipMemcpyAsync(out.mu.data(), g->mu.p, npair * 8, hipMemcpyDeviceToHost, st));
         HIPCHK(hipMemcpyAsync(out.stats, g->stats.p, ST_N * 8, hipMemcpyDeviceToHost, st));
-        std::vector<unsigned long long> ws((uint64_t)grid * ST_N);
+        std::vector<unsigned long long> ws((uint64_t)wgrid * ST_N);
         HIPCHK(hipMemcpyAsync(ws.data(), g->wstats.p, ws.size() * 8, hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
-        for (uint64_t b = 0; b < grid; b++)
+        for (uint64_t b = 0; b < wgrid; b++)
             for (int k = 1; k < ST_N; k++) out.stats[k] += ws[b * ST_N + k];
         if (g->ml && g->ml->collect) {
             out.done_round.resize(ns);
@@ -2544,17 +2552,19 @@ int ppsp_batch_query_noalloc(ppsp_graph g, const uint32_t *pairs, uint32_t k, co
         hipStream_t st;
         uint64_t qcap;
         uint32_t hcap;
-        int64_t profile, use_graph, dense_min, dense_force;
+        int64_t profile, use_graph, dense_min, dense_force, heavy_waves;
         Arena arena;
         Swap(ppsp_graph g_, hipStream_t cs) : g(g_), st(g_->st), qcap(g_->qcap), hcap(g_->hcap),
                                              profile(g_->opt_profile), use_graph(g_->opt_use_graph),
-                                             dense_min(g_->opt_dense_min), dense_force(g_->opt_dense_force) {
+                                             dense_min(g_->opt_dense_min), dense_force(g_->opt_dense_force),
+                                             heavy_waves(g_->opt_heavy_waves) {
             for (DevBuf *b : wave_buffers(g)) saved.push_back(std::move(*b));
             g->st = cs;               // work is ordered on the caller's stream
             g->opt_profile = 0;       // no events
             g->opt_use_graph = 0;     // no captured graphs
             g->opt_dense_min = 0;     // sparse frontiers only (the dense bitmaps are not in the scratch)
             g->opt_dense_force = 0;
+            g->opt_heavy_waves = 0;   // the per-workgroup counters in the scratch are sized for the round grid
             if (g->opt_queue_cap == 0) g->qcap = 0;
             g->hcap = 0;
         }
@@ -2572,6 +2582,7 @@ int ppsp_batch_query_noalloc(ppsp_graph g, const uint32_t *pairs, uint32_t k, co
             g->opt_use_graph = use_graph;
             g->opt_dense_min = dense_min;
             g->opt_dense_force = dense_force;
+            g->opt_heavy_waves = heavy_waves;
         }
     } swap(g, (hipStream_t)hip_stream);
     swap.arena.base = base;
@@ -2881,6 +2892,10 @@ int ppsp_set_option(ppsp_graph g, const char *name, int64_t v) {
         if (v < 16 || v > (int64_t)HEAVY_DEG) return PPSP_E_INVALID;
         g->opt_list_deg = v;
     }
+    else if (k == "heavy_waves") {
+        if (v < 0 || v > 32) return PPSP_E_INVALID;
+        g->opt_heavy_waves = v;
+    }
 
     else if (k == "server_round_base") {
         if (v < 0 || v >= (int64_t)SRV_ROUND_LIMIT) return PPSP_E_INVALID;
@@ -2918,6 +2933,7 @@ int ppsp_get_option(ppsp_graph g, const char *name, int64_t *v) {
     else if (k == "heavy_grouped") *v = g->opt_heavy_grouped;
     else if (k == "heavy_claim") *v = g->opt_heavy_claim;
     else if (k == "list_deg") *v = g->opt_list_deg;
+    else if (k == "heavy_waves") *v = g->opt_heavy_waves;
 
     else if (k == "rho") *v = g->opt_rho;
     else if (k == "local_chunks") *v = g->opt_local;

@@ -867,12 +867,13 @@ __global__ __launch_bounds__(WAVE, 5) void k_heavy(RoundArgs A) {
     // with the list by the control step), so a wave that drew short records
     // takes more; every wave leaves once the counter has passed the list.
     for (;;) {
-        unsigned long long base = 0;
-        if (lane_id() == 0) base = atomicAdd(A.hcount + 1, (unsigned long long)A.hclaim);
-        base = __shfl(base, 0);
+        unsigned long long got = 0;
+        if (lane_id() == 0) got = atomicAdd(A.hcount + 1, (unsigned long long)A.hclaim);
+        // wave-uniform in a scalar register, so the records load through the scalar cache
+        const uint32_t base = __builtin_amdgcn_readfirstlane((uint32_t)min(got, (unsigned long long)nh));
         if (base >= nh) break;
-        const uint64_t end = min((uint64_t)base + A.hclaim, nh);
-        for (uint64_t slot = base; slot < end; slot++) {
+        const uint32_t end = (uint32_t)min((uint64_t)base + A.hclaim, nh);
+        for (uint32_t slot = base; slot < end; slot++) {
             const uint4 h1 = A.heavy[2 * slot];
             const uint32_t ee = A.heavy[2 * slot + 1].x;
             const uint32_t ai = h1.x;
