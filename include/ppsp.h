@@ -566,6 +566,8 @@ int ppsp_last_stats(ppsp_graph g, ppsp_stats *stats);
  *                     hub list
  *   "heavy_claim"     hub-list records (chunks of at most 2,048 arcs) a wave of the hub-list
  *                     kernel claims at a time from a shared counter (1 to 64; default 4)
+ *   "heavy_waves"     single-wave workgroups per CU of the hub-list kernel (1 to 32; default
+ *                     24; 0: the round kernel's grid)
  *   "heavy_grouped"   1 (default): on a symmetric graph with vertices of degree > 512 and a
  *                     state layout of 4 or more searches per group ("plain_group",
  *                     "multi_group"), the hub-list kernel relaxes each chunk of a hub's

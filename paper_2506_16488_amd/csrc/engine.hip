@@ -236,7 +236,7 @@ struct ppsp_graph_s {
             opt_ml_every = 4, opt_heavy_window = 64, opt_multi_group = 32, opt_rho = 4096, opt_local = 16, opt_local_plain = 0, opt_local_fill = 0,
             opt_min_chunk = 16, opt_local_small = 4, opt_local_pct = 90, opt_defer_pct = 105,
             opt_server_round_base = 0, opt_dense_min = 0, opt_dense_force = 0, opt_dense_ring = 16,
-            opt_dense_learned = 0, opt_plain_group = 2, opt_heavy_grouped = 1, opt_heavy_claim = 4, opt_list_deg = 128, opt_heavy_waves = 0;
+            opt_dense_learned = 0, opt_plain_group = 2, opt_heavy_grouped = 1, opt_heavy_claim = 4, opt_list_deg = 128, opt_heavy_waves = 24;
     uint64_t wmean = 1;             // mean arc weight (rounded up)
     uint64_t fingerprint = 0;       // hash of the CSR, keys the tuning cache
     struct Tuned {
