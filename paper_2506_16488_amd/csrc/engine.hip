@@ -2315,6 +2315,30 @@ int ppsp_graph_create(int device, uint32_t n, uint64_t m, const uint64_t *row_pt
             }
             rp_re[k + 1] = o;
         }
+        // Each row's arcs by new head id: the heads a wave relaxes in one step
+        // then share state lines wherever the new order put a vertex's
+        // neighbours near each other (the breadth-first order numbers the
+        // unvisited neighbours of a vertex consecutively). Rows in parallel.
+        {
+            const uint32_t nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+            std::vector<std::thread> th;
+            for (uint32_t t = 0; t < nt; t++)
+                th.emplace_back([&, t]() {
+                    std::vector<std::pair<uint32_t, uint32_t>> tmp;
+                    for (uint64_t k = t; k < n; k += nt) {
+                        const uint64_t a = rp_re[k], b = rp_re[k + 1];
+                        if (b - a < 2) continue;
+                        tmp.resize(b - a);
+                        for (uint64_t e = a; e < b; e++) tmp[e - a] = {col_re[e], w_re[e]};
+                        std::sort(tmp.begin(), tmp.end());
+                        for (uint64_t e = a; e < b; e++) {
+                            col_re[e] = tmp[e - a].first;
+                            w_re[e] = tmp[e - a].second;
+                        }
+                    }
+                });
+            for (auto &x : th) x.join();
+        }
         if (coord_fx) {
             xy_re.resize(2 * (uint64_t)n);
             for (uint32_t k = 0; k < n; k++) {
