@@ -165,10 +165,13 @@ typedef struct ppsp_graph_s *ppsp_graph;
  *              search of a bidirectional query walks the transpose).
  *              PPSP_REORDER: the device copy numbers the vertices in a
  *              locality order (Morton order of the coordinates when given,
- *              else breadth-first from the highest-degree vertex), so that
- *              vertices close in the graph share cache lines of the search
- *              state. Vertex ids at the interface stay the caller's (pairs
- *              and paths are translated); results are identical.
+ *              else the vertices of degree above 128 first, in descending
+ *              degree, then the rest breadth-first from the highest-degree
+ *              vertex), so that vertices close in the graph, and the hubs
+ *              that most arcs lead to, share cache lines of the search
+ *              state; each row's arcs are then sorted by new head id.
+ *              Vertex ids at the interface stay the caller's (pairs and
+ *              paths are translated); results are identical.
  *   out        receives the handle
  * Errors: PPSP_E_INVALID (bad CSR), PPSP_E_RANGE (col >= n, m too large,
  * coordinate span too large for exact 64-bit arithmetic, or a heuristic
