@@ -165,11 +165,12 @@ typedef struct ppsp_graph_s *ppsp_graph;
  *              search of a bidirectional query walks the transpose).
  *              PPSP_REORDER: the device copy numbers the vertices in a
  *              locality order (Morton order of the coordinates when given,
- *              else the vertices of degree above 128 first, in descending
- *              degree, then the rest breadth-first from the highest-degree
- *              vertex), so that vertices close in the graph, and the hubs
- *              that most arcs lead to, share cache lines of the search
- *              state; each row's arcs are then sorted by new head id.
+ *              else the vertices of degree above 128 first, ranked by
+ *              descending degree with runs of 8 interleaved by quarter of
+ *              that ranking, then the rest breadth-first from the
+ *              highest-degree vertex), so that vertices close in the graph,
+ *              and the hubs that most arcs lead to, share cache lines of the
+ *              search state; each row's arcs are then sorted by new head id.
  *              Vertex ids at the interface stay the caller's (pairs and
  *              paths are translated); results are identical.
  *   out        receives the handle
